@@ -1,0 +1,166 @@
+/*
+ * lqt.h - C ABI of the MI355X (gfx950) parallel-in-time solver for the continuous-time linear
+ * quadratic tracker (LQT) of Sarkka & Garcia-Fernandez, "Temporal parallelisation of the HJB
+ * equation and continuous-time linear quadratic control".
+ *
+ * The solver works in three stages, each one entry point:
+ *   lqt_build_elements  per-block conditional value function parameters (A, b, C, eta, J) by RK4
+ *                       integration of the backward conditional LQT ODEs (Theorem 8, Sec. IV-B);
+ *                       every block is independent.
+ *   lqt_scan_value      the value function V(., t_k) = a_k (x) ... (x) a_T (Theorem 6, Sec. III-D)
+ *                       with the LQT combination rule (Lemma 7, Sec. IV-A) and the terminal
+ *                       element (Sec. IV-D); outputs S_k = J, v_k = eta at every block boundary.
+ *   lqt_forward_traj    the optimal trajectory by composing the per-block closed-loop maps
+ *                       x_{k+1} = Psi_k x_k + alpha_k (Method 1, Sec. IV-E; the per-block map is
+ *                       the Method 2 formula applied to one block) and the control law of Sec.
+ *                       II-B, u_k = -R^{-1} L(t_k)^T (S_k x_k - v_k).
+ * plus lqt_solve (the three stages in one call, with fused kernels) and lqt_backward (the adjoint:
+ * gradients of a loss on the trajectory with respect to Q, R, r, x0, Qf and rf).
+ *
+ * Problem (Sec. II-B with H = I, so Q = H^T X H and the reference r is in state space):
+ *     dx/dt = F(t) x + L(t) u + c(t),
+ *     cost  = 1/2 (x(t_T) - rf)^T Qf (x(t_T) - rf) + int 1/2 (x-r)^T Q (x-r) + 1/2 u^T R u dt.
+ * The horizon is split into T blocks [t_k, t_{k+1}], each integrated with n_steps classical RK4
+ * steps of h_k = (t_{k+1} - t_k) / n_steps.  Time-varying inputs are sampled on the half-step grid:
+ * sample j of block k is at t_k + j h_k / 2 (j = 0..2 n_steps) and has global index
+ * 2 n_steps k + j, so there are NS = 2 n_steps T + 1 samples (block ends shared).
+ *
+ * Conventions for every entry point:
+ *  - All array pointers are DEVICE pointers owned by the caller; the library never allocates,
+ *    frees or retains user memory.  Scratch memory is a caller buffer of at least
+ *    lqt_workspace_size() bytes, 256-byte aligned.
+ *  - Arrays are dense, row-major, all of the dtype named in lqt_dims (double or float), and hold
+ *    `batch` independent problems back to back (leading batch dimension), except F and L when
+ *    they are constant, which are shared by the whole batch.
+ *  - Calls are stream-ordered and non-blocking: they enqueue kernels on `stream` and return.
+ *  - Arguments are validated on the host before anything is launched; on error nothing is
+ *    launched and the status names the problem (lqt_last_error() gives a message).  Faults of the
+ *    device itself surface at the caller's next synchronisation as HIP errors.
+ *  - Q, R, Qf must be symmetric; R must be positive definite (its Cholesky factor is taken; a
+ *    non-positive-definite R yields NaN outputs, not an error code).
+ *  - Supported sizes: 1 <= nu <= nx <= 16; T >= 1; 1 <= n_steps <= 4096; batch >= 1.
+ */
+#ifndef LQT_H
+#define LQT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lqt_status {
+  LQT_OK = 0,
+  LQT_EINVAL = -1,       /* an argument is invalid (null pointer, size out of range, ...)        */
+  LQT_EUNSUPPORTED = -2, /* a valid request outside what this build implements                   */
+  LQT_EWORKSPACE = -3,   /* workspace pointer missing, misaligned or smaller than required       */
+  LQT_EHIP = -4          /* a HIP runtime call (kernel launch) failed                            */
+} lqt_status;
+
+typedef enum lqt_dtype { LQT_F64 = 0, LQT_F32 = 1 } lqt_dtype;
+
+/* Which entry point a workspace is sized for. */
+typedef enum lqt_call {
+  LQT_CALL_BUILD = 0,
+  LQT_CALL_SCAN_VALUE = 1,
+  LQT_CALL_FORWARD_TRAJ = 2,
+  LQT_CALL_SOLVE = 3,
+  LQT_CALL_BACKWARD = 4
+} lqt_call;
+
+typedef struct lqt_dims {
+  int32_t nx;        /* state dimension                                                         */
+  int32_t nu;        /* control dimension                                                       */
+  int32_t T;         /* number of blocks (sub-intervals)                                        */
+  int32_t n_steps;   /* RK4 steps per block                                                     */
+  int32_t batch;     /* independent problems of identical sizes in one call                     */
+  int32_t dtype;     /* lqt_dtype                                                               */
+  int32_t F_sampled; /* 0: F constant [nx*nx] shared by the batch; 1: F [batch][NS][nx*nx]      */
+  int32_t L_sampled; /* 0: L constant [nx*nu] shared by the batch; 1: L [batch][NS][nx*nu]      */
+  int32_t has_c;     /* 0: c = 0 (c may be NULL); 1: c [batch][NS][nx]                          */
+} lqt_dims;
+
+typedef struct lqt_problem {
+  const void *t;  /* [batch][T+1] block boundaries, strictly increasing                          */
+  const void *F;  /* see lqt_dims.F_sampled                                                      */
+  const void *L;  /* see lqt_dims.L_sampled                                                      */
+  const void *c;  /* see lqt_dims.has_c                                                          */
+  const void *Q;  /* [batch][nx*nx] running state weight, symmetric positive semi-definite      */
+  const void *R;  /* [batch][nu*nu] control weight, symmetric positive definite                  */
+  const void *r;  /* [batch][NS][nx] reference on the half-step grid                             */
+  const void *Qf; /* [batch][nx*nx] terminal weight, symmetric positive semi-definite           */
+  const void *rf; /* [batch][nx] terminal reference                                              */
+  const void *x0; /* [batch][nx] initial state                                                   */
+} lqt_problem;
+
+/* Number of values per element: NE = 2 nx^2 + 3 nx.  Element storage is structure-of-arrays,
+ * elts[batch][NE][T]: value q of block k of problem p is elts[(p * NE + q) * T + k].  Values q:
+ *   [0, nx^2)                A - I, row-major (the deviation from the identity is stored so that
+ *                            short blocks keep full relative precision in FP32)
+ *   [nx^2, nx^2+nx)          b
+ *   next nx(nx+1)/2          C, upper triangle, row by row ((0,0),(0,1),..,(0,nx-1),(1,1),..)
+ *   next nx                  eta
+ *   next nx(nx+1)/2          J, upper triangle, row by row                                   */
+size_t lqt_element_count(int32_t nx);
+
+/* Bytes of scratch memory entry point `call` needs for these dims (0 if dims are invalid). */
+size_t lqt_workspace_size(const lqt_dims *dims, lqt_call call);
+
+/* Elements a_0..a_{T-1} (Theorem 8, Sec. IV-B): for each block independently, integrate
+ * dA/ds = A G J - A F, db/ds = -A G eta - A c, dC/ds = -A G A^T,
+ * deta/ds = -Q r - F^T eta + J c + J G eta, dJ/ds = -Q - J F - F^T J + J G J  (G = L R^{-1} L^T)
+ * in s from s = t_{k+1}, where (A, b, C, eta, J) = (I, 0, 0, 0, 0), down to s = t_k with n_steps
+ * classical RK4 steps.  elts: [batch][NE][T] output (layout above).  ws: LQT_CALL_BUILD bytes. */
+lqt_status lqt_build_elements(const lqt_dims *dims, const lqt_problem *prob, void *elts, void *ws,
+                              size_t ws_bytes, hipStream_t stream);
+
+/* Value functions (Theorem 6 with the terminal element A = b = C = 0, eta = Qf rf, J = Qf):
+ * S [batch][T+1][nx*nx] (full symmetric) and v [batch][T+1][nx], V(x, t_k) = 1/2 x^T S_k x -
+ * v_k^T x + const.  elts: as written by lqt_build_elements (any producer of the same layout). */
+lqt_status lqt_scan_value(const lqt_dims *dims, const void *elts, const void *Qf, const void *rf,
+                          void *S, void *v, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Trajectory and control at the block boundaries: x [batch][T+1][nx], u [batch][T+1][nu], with
+ * x_{k+1} = (I + C_k S_{k+1})^{-1} (A_k x_k + b_k + C_k v_{k+1}) composed by a parallel scan
+ * from x_0 = x0, and u_k = -R^{-1} L(t_k)^T (S_k x_k - v_k).  Reads prob->{L, R, x0} (L at sample
+ * 2 n_steps k if sampled), elts, S, v.  u may be NULL. */
+lqt_status lqt_forward_traj(const lqt_dims *dims, const lqt_problem *prob, const void *elts,
+                            const void *S, const void *v, void *x, void *u, void *ws,
+                            size_t ws_bytes, hipStream_t stream);
+
+/* All three stages in one call (fused kernels; same results as the stage calls up to rounding).
+ * elts may be NULL (then the elements live in the workspace); S, v, x must be non-NULL; u may be
+ * NULL. */
+lqt_status lqt_solve(const lqt_dims *dims, const lqt_problem *prob, void *elts, void *S, void *v,
+                     void *x, void *u, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Adjoint of lqt_solve for a loss whose gradient with respect to the trajectory is dLdx
+ * [batch][T+1][nx]: accumulates nothing, overwrites the outputs with
+ *   dQ [batch][nx*nx], dR [batch][nu*nu], dr [batch][NS][nx], dx0 [batch][nx],
+ *   dQf [batch][nx*nx], drf [batch][nx]   (dQf, drf may be NULL).
+ * Gradients are entrywise with respect to the arrays as the forward pass reads them (Q enters
+ * through Q r with all entries and through the upper triangle of the J equation; R through its
+ * inverse).  S, v, x are the outputs of the forward solve of the same problem; elements are
+ * recomputed, not read.  Requires F, L constant and c = 0 (LQT_EUNSUPPORTED otherwise). */
+lqt_status lqt_backward(const lqt_dims *dims, const lqt_problem *prob, const void *S,
+                        const void *v, const void *x, const void *dLdx, void *dQ, void *dR,
+                        void *dr, void *dx0, void *dQf, void *drf, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
+/* Short description of a status code. */
+const char *lqt_status_string(lqt_status status);
+
+/* Detail message of the last error returned on the calling thread ("" if none). */
+const char *lqt_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int32_t lqt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LQT_H */

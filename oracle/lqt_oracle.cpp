@@ -7,7 +7,7 @@
 // links, includes or calls it, and it shares no code with it.
 //
 // Everything here is written for a reader checking it against the paper by eye: dense matrices of
-// runtime size (at most 16 x 16), straight loops, Gaussian elimination with partial pivoting, no
+// runtime size, straight loops, Gaussian elimination with partial pivoting, no
 // blocking, no fusion and no reordering beyond what the paper's formulas state.
 //
 // Problem (Sec. II-B, the LQT problem, with H = I so that Q = H^T X H and the reference r lives in
@@ -43,8 +43,6 @@
 #include <vector>
 
 namespace oracle {
-
-constexpr int NMAX = 16;
 
 // ------------------------------------------------------------------------------------------
 // Scalar types: double, forward-mode dual numbers, reverse-mode tape variables.
@@ -112,14 +110,11 @@ inline double value(const Var& x) { return x.v; }
 template <class S>
 struct Mat {
   int r = 0, c = 0;
-  S a[NMAX][NMAX];
+  std::vector<S> a;  // row-major, r * c entries
   Mat() {}
-  Mat(int rows, int cols) : r(rows), c(cols) {
-    for (int i = 0; i < r; ++i)
-      for (int j = 0; j < c; ++j) a[i][j] = S(0.0);
-  }
-  S& operator()(int i, int j) { return a[i][j]; }
-  const S& operator()(int i, int j) const { return a[i][j]; }
+  Mat(int rows, int cols) : r(rows), c(cols), a((size_t)rows * cols, S(0.0)) {}
+  S& operator()(int i, int j) { return a[(size_t)i * c + j]; }
+  const S& operator()(int i, int j) const { return a[(size_t)i * c + j]; }
 };
 
 template <class S>

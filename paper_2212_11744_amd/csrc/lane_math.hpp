@@ -1,0 +1,483 @@
+// Register-resident small-matrix algebra of the LQT solver, one problem block (or one tuple) per
+// lane, for state sizes N <= 4.  Everything is fully unrolled at compile time so that matrices
+// live in VGPRs and every product exposes N*N independent FMA chains.
+//
+// Representation (shared with the global structure-of-arrays layout of the C ABI):
+//   A is held as its deviation from the identity, Ad = A - I.  Blocks are short (A = I + O(h)),
+//   so storing A itself would round the O(h) part to the precision of 1 and, in FP32, lose most
+//   of it; every formula below is rearranged around Ad so that no small quantity is ever formed
+//   as the difference of two numbers close to one.
+//   C, J (and the value matrix S) are symmetric and kept as packed upper triangles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#define LQT_DEV __device__ __forceinline__
+
+namespace lqt {
+
+template <int N>
+struct Sym {
+  static constexpr int size = N * (N + 1) / 2;
+  // Packed index of (i, j), upper triangle stored row by row.
+  static constexpr int at(int i, int j) {
+    return i <= j ? i * N - (i * (i - 1)) / 2 + (j - i) : j * N - (j * (j - 1)) / 2 + (i - j);
+  }
+};
+
+// Offsets of the element components inside one structure-of-arrays record of NE values.
+template <int N>
+struct Lay {
+  static constexpr int NS = Sym<N>::size;
+  static constexpr int A = 0;
+  static constexpr int B = N * N;
+  static constexpr int C = N * N + N;
+  static constexpr int E = N * N + N + NS;
+  static constexpr int J = N * N + 2 * N + NS;
+  static constexpr int NE = 2 * N * N + 3 * N;
+  static constexpr int NV = NS + N;     // value record: packed S, then v
+  static constexpr int NM = N * N + N;  // affine map record: Psi - I, then alpha
+};
+
+// Conditional value function parameters (A - I, b, C, eta, J) of one interval.
+template <int N, class R>
+struct Tup {
+  R A[N][N];
+  R b[N];
+  R C[Sym<N>::size];
+  R e[N];
+  R J[Sym<N>::size];
+};
+
+// Affine map x -> (I + P) x + q (closed-loop state transition over an interval).
+template <int N, class R>
+struct Aff {
+  R P[N][N];
+  R q[N];
+};
+
+template <int N, class R>
+LQT_DEV void tup_identity(Tup<N, R>& x) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) x.A[i][j] = R(0);
+    x.b[i] = R(0);
+    x.e[i] = R(0);
+  }
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) {
+    x.C[i] = R(0);
+    x.J[i] = R(0);
+  }
+}
+
+template <int N, class R>
+LQT_DEV void tup_load(Tup<N, R>& x, const R* __restrict__ base, long stride, long k) {
+  using L = Lay<N>;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) x.A[i][j] = base[(L::A + i * N + j) * stride + k];
+#pragma unroll
+  for (int i = 0; i < N; ++i) x.b[i] = base[(L::B + i) * stride + k];
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) x.C[i] = base[(L::C + i) * stride + k];
+#pragma unroll
+  for (int i = 0; i < N; ++i) x.e[i] = base[(L::E + i) * stride + k];
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) x.J[i] = base[(L::J + i) * stride + k];
+}
+
+template <int N, class R>
+LQT_DEV void tup_store(const Tup<N, R>& x, R* __restrict__ base, long stride, long k) {
+  using L = Lay<N>;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) base[(L::A + i * N + j) * stride + k] = x.A[i][j];
+#pragma unroll
+  for (int i = 0; i < N; ++i) base[(L::B + i) * stride + k] = x.b[i];
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) base[(L::C + i) * stride + k] = x.C[i];
+#pragma unroll
+  for (int i = 0; i < N; ++i) base[(L::E + i) * stride + k] = x.e[i];
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) base[(L::J + i) * stride + k] = x.J[i];
+}
+
+// Solve M X = B in place (B <- M^{-1} B) by Gauss-Jordan elimination with partial pivoting.
+// The pivot search keeps the first row of largest magnitude.  Row exchanges sit behind a
+// data-dependent branch: for the near-identity matrices of short blocks no lane takes it and the
+// whole wave skips the exchange.
+template <int N, int NB, class R>
+LQT_DEV void gj_solve(R (&M)[N][N], R (&B)[N][NB]) {
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+#pragma unroll
+    for (int i = c + 1; i < N; ++i) {
+      if (fabs(M[i][c]) > fabs(M[c][c])) {
+#pragma unroll
+        for (int j = c; j < N; ++j) {
+          R t = M[i][j];
+          M[i][j] = M[c][j];
+          M[c][j] = t;
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          R t = B[i][j];
+          B[i][j] = B[c][j];
+          B[c][j] = t;
+        }
+      }
+    }
+    const R inv = R(1) / M[c][c];
+#pragma unroll
+    for (int j = c + 1; j < N; ++j) M[c][j] *= inv;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) B[c][j] *= inv;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      if (i == c) continue;
+      const R f = M[i][c];
+#pragma unroll
+      for (int j = c + 1; j < N; ++j) M[i][j] = fma(-f, M[c][j], M[i][j]);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) B[i][j] = fma(-f, B[c][j], B[i][j]);
+    }
+  }
+}
+
+// Lemma 7 (Sec. IV-A): o = x1 (x) x2 with x1 on [s, tau] (earlier) and x2 on [tau, t] (later).
+// With M = I + C1 J2 (invertible by Lemma 10, Appendix B):
+//   A = A2 M^{-1} A1,  b = A2 M^{-1} (b1 + C1 eta2) + b2,  C = A2 M^{-1} C1 A2^T + C2,
+//   eta = A1^T M^{-T} (eta2 - J2 b1) + eta1,  J = A1^T M^{-T} J2 A1 + J1,
+// using (I + J2 C1)^{-1} = M^{-T}.  One factorisation serves all: Y = M^{-1} A1 = I + Yd with
+// Yd = M^{-1} (Ad1 - C1 J2), D = M^{-1} C1 and g = M^{-1} (b1 + C1 eta2); then
+//   Ad = Ad2 + Yd + Ad2 Yd,  b = g + Ad2 g + b2,  C = (I + Ad2) D (I + Ad2)^T + C2,
+//   eta = w + Yd^T w + eta1 (w = eta2 - J2 b1),  J = (I + Yd)^T J2 (I + Ad1) + J1.
+template <int N, class R>
+LQT_DEV void combine(const Tup<N, R>& x1, const Tup<N, R>& x2, Tup<N, R>& o) {
+  using Y = Sym<N>;
+  R CJ[N][N], M[N][N], B[N][2 * N + 1];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(x1.C[Y::at(i, k)], x2.J[Y::at(k, j)], s);
+      CJ[i][j] = s;
+      M[i][j] = (i == j) ? R(1) + s : s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R g = x1.b[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      B[i][j] = x1.A[i][j] - CJ[i][j];
+      B[i][N + j] = x1.C[Y::at(i, j)];
+      g = fma(x1.C[Y::at(i, j)], x2.e[j], g);
+    }
+    B[i][2 * N] = g;
+  }
+  gj_solve<N, 2 * N + 1>(M, B);
+  // Outputs are produced in an order that consumes each input component before the matching
+  // output is written, so `o` may alias x2 (the running product of a reduction).
+  // C: W = (I + Ad2) D, C = W (I + Ad2)^T + C2 (upper triangle)
+  {
+    R Wm[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        R s = B[i][N + j];
+#pragma unroll
+        for (int k = 0; k < N; ++k) s = fma(x2.A[i][k], B[k][N + j], s);
+        Wm[i][j] = s;
+      }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        R s = Wm[i][j];
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(Wm[i][l], x2.A[j][l], s);
+        o.C[Y::at(i, j)] = x2.C[Y::at(i, j)] + s;
+      }
+  }
+  // b = g + Ad2 g + b2
+  {
+    R bn[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(x2.A[i][k], B[k][2 * N], s);
+      bn[i] = x2.b[i] + B[i][2 * N] + s;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) o.b[i] = bn[i];
+  }
+  // eta = w + Yd^T w + eta1, w = eta2 - J2 b1
+  {
+    R w[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      R s = x2.e[i];
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(-x2.J[Y::at(i, k)], x1.b[k], s);
+      w[i] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(B[k][i], w[k], s);
+      o.e[i] = x1.e[i] + (w[i] + s);
+    }
+  }
+  // J: P = J2 (I + Ad1), J = (I + Yd)^T P + J1 (upper triangle)
+  {
+    R P[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        R s = x2.J[Y::at(i, j)];
+#pragma unroll
+        for (int k = 0; k < N; ++k) s = fma(x2.J[Y::at(i, k)], x1.A[k][j], s);
+        P[i][j] = s;
+      }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) {
+        R s = P[i][j];
+#pragma unroll
+        for (int k = 0; k < N; ++k) s = fma(B[k][i], P[k][j], s);
+        o.J[Y::at(i, j)] = x1.J[Y::at(i, j)] + s;
+      }
+  }
+  // Ad = Ad2 + Yd + Ad2 Yd (row by row: row i of the result needs only row i of Ad2)
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R row[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(x2.A[i][k], B[k][j], s);
+      row[j] = x2.A[i][j] + B[i][j] + s;
+    }
+#pragma unroll
+    for (int j = 0; j < N; ++j) o.A[i][j] = row[j];
+  }
+}
+
+// One step of the value recursion: the Lemma with a right operand of the terminal form
+// (A = b = C = 0, eta = v, J = S), i.e. V(., t_k) from a_k and V(., t_{k+1}) (Sec. IV-D):
+//   Psi = (I + C S)^{-1} A = I + Pd,  Pd = (I + C S)^{-1} (Ad - C S),
+//   alpha = (I + C S)^{-1} (b + C v),
+//   S' = Psi^T S A + J,  v' = Psi^T (v - S b) + eta.
+// (Psi, alpha) is also the closed-loop map x_{k+1} = Psi x_k + alpha of the block (Sec. IV-E), so
+// it is returned for the trajectory.  S, v are updated in place.
+template <int N, class R>
+LQT_DEV void fold(const Tup<N, R>& a, R (&S)[Sym<N>::size], R (&v)[N], Aff<N, R>& m) {
+  using Y = Sym<N>;
+  R CS[N][N], M[N][N], B[N][N + 1];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(a.C[Y::at(i, k)], S[Y::at(k, j)], s);
+      CS[i][j] = s;
+      M[i][j] = (i == j) ? R(1) + s : s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R g = a.b[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      B[i][j] = a.A[i][j] - CS[i][j];
+      g = fma(a.C[Y::at(i, j)], v[j], g);
+    }
+    B[i][N] = g;
+  }
+  gj_solve<N, N + 1>(M, B);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) m.P[i][j] = B[i][j];
+    m.q[i] = B[i][N];
+  }
+  // w = v - S b
+  R w[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = v[i];
+#pragma unroll
+    for (int k = 0; k < N; ++k) s = fma(-S[Y::at(i, k)], a.b[k], s);
+    w[i] = s;
+  }
+  // X = S (I + Ad);  S' = J + X + Pd^T X (upper);  v' = eta + w + Pd^T w
+  R X[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(S[Y::at(i, k)], a.A[k][j], s);
+      X[i][j] = S[Y::at(i, j)] + s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(B[k][i], X[k][j], s);
+      S[Y::at(i, j)] = a.J[Y::at(i, j)] + (X[i][j] + s);
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = R(0);
+#pragma unroll
+    for (int k = 0; k < N; ++k) s = fma(B[k][i], w[k], s);
+    v[i] = a.e[i] + (w[i] + s);
+  }
+}
+
+// Closed-loop block map only (no value update): Psi, alpha from a_k and S_{k+1}, v_{k+1}.
+template <int N, class R>
+LQT_DEV void block_map(const R (&Ad)[N][N], const R (&b)[N], const R (&C)[Sym<N>::size],
+                       const R (&S)[Sym<N>::size], const R (&v)[N], Aff<N, R>& m) {
+  using Y = Sym<N>;
+  R M[N][N], B[N][N + 1];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(C[Y::at(i, k)], S[Y::at(k, j)], s);
+      M[i][j] = (i == j) ? R(1) + s : s;
+      B[i][j] = Ad[i][j] - s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R g = b[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j) g = fma(C[Y::at(i, j)], v[j], g);
+    B[i][N] = g;
+  }
+  gj_solve<N, N + 1>(M, B);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) m.P[i][j] = B[i][j];
+    m.q[i] = B[i][N];
+  }
+}
+
+template <int N, class R>
+LQT_DEV void aff_identity(Aff<N, R>& m) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) m.P[i][j] = R(0);
+    m.q[i] = R(0);
+  }
+}
+
+// acc <- later o acc  (apply acc first, then `later`):  P = Pa + Pl + Pl Pa,  q = ql + qa + Pl qa.
+template <int N, class R>
+LQT_DEV void aff_then(Aff<N, R>& acc, const Aff<N, R>& later) {
+  R P[N][N], q[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(later.P[i][k], acc.P[k][j], s);
+      P[i][j] = acc.P[i][j] + later.P[i][j] + s;
+    }
+    R s = R(0);
+#pragma unroll
+    for (int k = 0; k < N; ++k) s = fma(later.P[i][k], acc.q[k], s);
+    q[i] = later.q[i] + acc.q[i] + s;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc.P[i][j] = P[i][j];
+    acc.q[i] = q[i];
+  }
+}
+
+// acc <- acc o earlier  (apply `earlier` first, then acc).
+template <int N, class R>
+LQT_DEV void aff_after(Aff<N, R>& acc, const Aff<N, R>& earlier) {
+  R P[N][N], q[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(acc.P[i][k], earlier.P[k][j], s);
+      P[i][j] = earlier.P[i][j] + acc.P[i][j] + s;
+    }
+    R s = R(0);
+#pragma unroll
+    for (int k = 0; k < N; ++k) s = fma(acc.P[i][k], earlier.q[k], s);
+    q[i] = acc.q[i] + earlier.q[i] + s;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) acc.P[i][j] = P[i][j];
+    acc.q[i] = q[i];
+  }
+}
+
+// x <- (I + P) x + q
+template <int N, class R>
+LQT_DEV void aff_apply(const Aff<N, R>& m, R (&x)[N]) {
+  R y[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = R(0);
+#pragma unroll
+    for (int k = 0; k < N; ++k) s = fma(m.P[i][k], x[k], s);
+    y[i] = x[i] + (s + m.q[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) x[i] = y[i];
+}
+
+template <int N, class R>
+LQT_DEV void aff_load(Aff<N, R>& m, const R* __restrict__ base, long stride, long k) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) m.P[i][j] = base[(i * N + j) * stride + k];
+    m.q[i] = base[(N * N + i) * stride + k];
+  }
+}
+
+template <int N, class R>
+LQT_DEV void aff_store(const Aff<N, R>& m, R* __restrict__ base, long stride, long k) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) base[(i * N + j) * stride + k] = m.P[i][j];
+    base[(N * N + i) * stride + k] = m.q[i];
+  }
+}
+
+}  // namespace lqt

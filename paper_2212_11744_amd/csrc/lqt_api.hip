@@ -1,0 +1,352 @@
+// Host side of the C ABI declared in include/lqt.h: argument validation, workspace planning,
+// dispatch to the kernel instantiation of (nx, nu, dtype) and the launch sequence of every stage.
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "../../include/lqt.h"
+#include "lqt_internal.hpp"
+
+namespace lqt {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lqt_status fail(lqt_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+lqt_status ok() {
+  g_last_error.clear();
+  return LQT_OK;
+}
+
+int env_int(const char* name, int dflt, int lo, int hi) {
+  const char* s = getenv(name);
+  if (!s || !*s) return dflt;
+  int v = atoi(s);
+  return (v < lo || v > hi) ? dflt : v;
+}
+
+size_t dsize(int dtype) { return dtype == LQT_F64 ? 8 : 4; }
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+long ne_of(int nx) { return 2L * nx * nx + 3L * nx; }
+long nv_of(int nx) { return (long)nx * (nx + 1) / 2 + nx; }
+long nm_of(int nx) { return (long)nx * nx + nx; }
+
+}  // namespace
+
+Tree plan_tree(long T, int c0, int c) {
+  Tree t;
+  t.c0 = c0;
+  t.c = c;
+  t.n[0] = T;
+  t.n[1] = (T + c0 - 1) / c0;
+  t.levels = 1;
+  while (t.n[t.levels] > c && t.levels < kMaxLevels) {
+    t.n[t.levels + 1] = (t.n[t.levels] + c - 1) / c;
+    ++t.levels;
+  }
+  return t;
+}
+
+namespace {
+
+Tree tree_for(const lqt_dims* d) {
+  return plan_tree(d->T, env_int("LQT_CHUNK0", 4, 1, 4096), env_int("LQT_CHUNK", 8, 2, 4096));
+}
+
+// Byte layout of the workspace of one call.  Returns the total; fills w when base != nullptr.
+size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w) {
+  const size_t es = dsize(d->dtype);
+  const long B = d->batch;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    void* p = base ? base + off : nullptr;
+    off += align256(bytes);
+    return p;
+  };
+  void* consts = take(es * B * consts_count(d->nx, d->nu));
+  if (w) w->consts = consts;
+  const Tree t = tree_for(d);
+  const bool want_v = call == LQT_CALL_SCAN_VALUE || call == LQT_CALL_SOLVE;
+  const bool want_t = call == LQT_CALL_FORWARD_TRAJ || call == LQT_CALL_SOLVE;
+  for (int l = 1; l <= t.levels; ++l) {
+    if (want_v) {
+      void* a = take(es * B * ne_of(d->nx) * t.n[l]);
+      void* b = take(es * B * nv_of(d->nx) * t.n[l]);
+      if (w) {
+        w->vtup[l] = a;
+        w->vval[l] = b;
+      }
+    }
+    if (want_t) {
+      void* a = take(es * B * nm_of(d->nx) * t.n[l]);
+      void* b = take(es * B * d->nx * t.n[l]);
+      if (w) {
+        w->tmap[l] = a;
+        w->tx[l] = b;
+      }
+    }
+  }
+  if (call == LQT_CALL_SOLVE) {
+    void* e = take(es * B * ne_of(d->nx) * (size_t)d->T);
+    if (w) w->elts = e;
+  }
+  return off;
+}
+
+lqt_status check_dims_valid(const lqt_dims* d) {
+  if (!d) return fail(LQT_EINVAL, "dims is NULL");
+  if (d->dtype != LQT_F64 && d->dtype != LQT_F32)
+    return fail(LQT_EINVAL, "dtype %d is neither LQT_F64 nor LQT_F32", d->dtype);
+  if (d->nx < 1 || d->nx > 16) return fail(LQT_EINVAL, "nx = %d outside [1, 16]", d->nx);
+  if (d->nu < 1 || d->nu > d->nx) return fail(LQT_EINVAL, "nu = %d outside [1, nx]", d->nu);
+  if (d->T < 1) return fail(LQT_EINVAL, "T = %d: the horizon needs at least one block", d->T);
+  if (d->n_steps < 1 || d->n_steps > 4096)
+    return fail(LQT_EINVAL, "n_steps = %d outside [1, 4096]", d->n_steps);
+  if (d->batch < 1 || d->batch > 65535)
+    return fail(LQT_EINVAL, "batch = %d outside [1, 65535]", d->batch);
+  const long double ns = 2.0L * d->n_steps * d->T + 1;
+  if (ns * d->nx * d->nx > 9.0e18L) return fail(LQT_EINVAL, "sample arrays too large");
+  return LQT_OK;
+}
+
+lqt_status check_supported(const lqt_dims* d) {
+  lqt_status st = check_dims_valid(d);
+  if (st != LQT_OK) return st;
+  if (!lane_ops(d->nx, d->nu, d->dtype))
+    return fail(LQT_EUNSUPPORTED, "nx = %d, nu = %d: no kernel instantiation in this build",
+                d->nx, d->nu);
+  return LQT_OK;
+}
+
+lqt_status check_ptr(const void* p, const char* name, size_t es) {
+  if (!p) return fail(LQT_EINVAL, "%s is NULL", name);
+  if (((uintptr_t)p) % es) return fail(LQT_EINVAL, "%s is not aligned to its element size", name);
+  return LQT_OK;
+}
+
+lqt_status check_ws(const lqt_dims* d, lqt_call call, void* ws, size_t ws_bytes, Work* w) {
+  const size_t need = layout(d, call, nullptr, nullptr);
+  if (need > 0 && !ws) return fail(LQT_EWORKSPACE, "workspace is NULL (%zu bytes needed)", need);
+  if (((uintptr_t)ws) % 256) return fail(LQT_EWORKSPACE, "workspace is not 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(LQT_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
+  layout(d, call, (char*)ws, w);
+  return LQT_OK;
+}
+
+#define LQT_TRY(x)                       \
+  do {                                   \
+    lqt_status _s = (x);                 \
+    if (_s != LQT_OK) return _s;         \
+  } while (0)
+
+#define LQT_HIP(x)                                                                  \
+  do {                                                                              \
+    hipError_t _e = (x);                                                            \
+    if (_e != hipSuccess)                                                           \
+      return fail(LQT_EHIP, "%s failed: %s", #x, hipGetErrorString(_e));            \
+  } while (0)
+
+lqt_status check_problem(const lqt_dims* d, const lqt_problem* p, bool need_r, bool need_x0) {
+  const size_t es = dsize(d->dtype);
+  if (!p) return fail(LQT_EINVAL, "problem is NULL");
+  LQT_TRY(check_ptr(p->t, "t", es));
+  LQT_TRY(check_ptr(p->F, "F", es));
+  LQT_TRY(check_ptr(p->L, "L", es));
+  LQT_TRY(check_ptr(p->Q, "Q", es));
+  LQT_TRY(check_ptr(p->R, "R", es));
+  LQT_TRY(check_ptr(p->Qf, "Qf", es));
+  LQT_TRY(check_ptr(p->rf, "rf", es));
+  if (need_r) LQT_TRY(check_ptr(p->r, "r", es));
+  if (need_x0) LQT_TRY(check_ptr(p->x0, "x0", es));
+  if (d->has_c) LQT_TRY(check_ptr(p->c, "c", es));
+  return LQT_OK;
+}
+
+KProb make_kprob(const lqt_dims* d, const lqt_problem* p, const void* consts) {
+  KProb k;
+  k.nx = d->nx;
+  k.nu = d->nu;
+  k.T = d->T;
+  k.n = d->n_steps;
+  k.batch = d->batch;
+  k.F_sampled = d->F_sampled;
+  k.L_sampled = d->L_sampled;
+  k.has_c = d->has_c;
+  k.t = p ? p->t : nullptr;
+  k.F = p ? p->F : nullptr;
+  k.L = p ? p->L : nullptr;
+  k.c = p ? p->c : nullptr;
+  k.Q = p ? p->Q : nullptr;
+  k.R = p ? p->R : nullptr;
+  k.r = p ? p->r : nullptr;
+  k.Qf = p ? p->Qf : nullptr;
+  k.rf = p ? p->rf : nullptr;
+  k.x0 = p ? p->x0 : nullptr;
+  k.consts = consts;
+  return k;
+}
+
+// Value tree over elements: upward products, top fold, downward values, then the values of every
+// block (and, when maps1 != nullptr, level 1 of the trajectory tree).
+lqt_status run_value(const Ops* o, const KProb& kp, const Tree& t, const Work& w, const void* elts,
+                     void* S, void* v, void* maps1, hipStream_t s) {
+  LQT_HIP(o->vreduce(kp, elts, t.n[0], w.vtup[1], t.n[1], t.c0, s));
+  for (int l = 1; l < t.levels; ++l)
+    LQT_HIP(o->vreduce(kp, w.vtup[l], t.n[l], w.vtup[l + 1], t.n[l + 1], t.c, s));
+  LQT_HIP(o->vtop(kp, w.vtup[t.levels], t.n[t.levels], w.vval[t.levels], s));
+  for (int l = t.levels; l > 1; --l)
+    LQT_HIP(o->vdown(kp, w.vtup[l - 1], t.n[l - 1], w.vval[l], t.n[l], w.vval[l - 1], t.c, s));
+  LQT_HIP(o->vbottom(kp, elts, w.vval[1], t.n[1], S, v, maps1, t.c0, s));
+  return LQT_OK;
+}
+
+// Trajectory tree from level-1 maps: upward compositions, top sweep from x0, downward left-end
+// states, then x_k, u_k of every block.
+lqt_status run_traj(const Ops* o, const KProb& kp, const Tree& t, const Work& w, const void* elts,
+                    const void* S, const void* v, void* x, void* u, hipStream_t s) {
+  for (int l = 1; l < t.levels; ++l)
+    LQT_HIP(o->treduce(kp, w.tmap[l], t.n[l], w.tmap[l + 1], t.n[l + 1], t.c, s));
+  LQT_HIP(o->ttop(kp, w.tmap[t.levels], t.n[t.levels], w.tx[t.levels], s));
+  for (int l = t.levels; l > 1; --l)
+    LQT_HIP(o->tdown(kp, w.tmap[l - 1], t.n[l - 1], w.tx[l], t.n[l], w.tx[l - 1], t.c, s));
+  LQT_HIP(o->tbottom(kp, elts, S, v, w.tx[1], t.n[1], x, u, t.c0, s));
+  return LQT_OK;
+}
+
+}  // namespace
+}  // namespace lqt
+
+using namespace lqt;
+
+extern "C" {
+
+size_t lqt_element_count(int32_t nx) { return nx < 1 ? 0 : (size_t)ne_of(nx); }
+
+size_t lqt_workspace_size(const lqt_dims* dims, lqt_call call) {
+  if (check_dims_valid(dims) != LQT_OK) return 0;
+  if (call < LQT_CALL_BUILD || call > LQT_CALL_BACKWARD) return 0;
+  return layout(dims, call, nullptr, nullptr);
+}
+
+lqt_status lqt_build_elements(const lqt_dims* dims, const lqt_problem* prob, void* elts, void* ws,
+                              size_t ws_bytes, hipStream_t stream) {
+  LQT_TRY(check_supported(dims));
+  LQT_TRY(check_problem(dims, prob, true, false));
+  LQT_TRY(check_ptr(elts, "elts", dsize(dims->dtype)));
+  Work w;
+  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w));
+  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
+  KProb kp = make_kprob(dims, prob, w.consts);
+  LQT_HIP(o->prep(kp, w.consts, stream));
+  LQT_HIP(o->build(kp, elts, stream));
+  return ok();
+}
+
+lqt_status lqt_scan_value(const lqt_dims* dims, const void* elts, const void* Qf, const void* rf,
+                          void* S, void* v, void* ws, size_t ws_bytes, hipStream_t stream) {
+  LQT_TRY(check_supported(dims));
+  const size_t es = dsize(dims->dtype);
+  LQT_TRY(check_ptr(elts, "elts", es));
+  LQT_TRY(check_ptr(Qf, "Qf", es));
+  LQT_TRY(check_ptr(rf, "rf", es));
+  LQT_TRY(check_ptr(S, "S", es));
+  LQT_TRY(check_ptr(v, "v", es));
+  Work w;
+  LQT_TRY(check_ws(dims, LQT_CALL_SCAN_VALUE, ws, ws_bytes, &w));
+  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
+  lqt_problem p;
+  memset(&p, 0, sizeof(p));
+  p.Qf = Qf;
+  p.rf = rf;
+  KProb kp = make_kprob(dims, &p, w.consts);
+  LQT_TRY(run_value(o, kp, tree_for(dims), w, elts, S, v, nullptr, stream));
+  return ok();
+}
+
+lqt_status lqt_forward_traj(const lqt_dims* dims, const lqt_problem* prob, const void* elts,
+                            const void* S, const void* v, void* x, void* u, void* ws,
+                            size_t ws_bytes, hipStream_t stream) {
+  LQT_TRY(check_supported(dims));
+  const size_t es = dsize(dims->dtype);
+  if (!prob) return fail(LQT_EINVAL, "problem is NULL");
+  LQT_TRY(check_ptr(prob->L, "L", es));
+  LQT_TRY(check_ptr(prob->R, "R", es));
+  LQT_TRY(check_ptr(prob->x0, "x0", es));
+  LQT_TRY(check_ptr(elts, "elts", es));
+  LQT_TRY(check_ptr(S, "S", es));
+  LQT_TRY(check_ptr(v, "v", es));
+  LQT_TRY(check_ptr(x, "x", es));
+  if (u) LQT_TRY(check_ptr(u, "u", es));
+  Work w;
+  LQT_TRY(check_ws(dims, LQT_CALL_FORWARD_TRAJ, ws, ws_bytes, &w));
+  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
+  KProb kp = make_kprob(dims, prob, w.consts);
+  const Tree t = tree_for(dims);
+  LQT_HIP(o->prep(kp, w.consts, stream));
+  LQT_HIP(o->tbottom_reduce(kp, elts, S, v, w.tmap[1], t.n[1], t.c0, stream));
+  LQT_TRY(run_traj(o, kp, t, w, elts, S, v, x, u, stream));
+  return ok();
+}
+
+lqt_status lqt_solve(const lqt_dims* dims, const lqt_problem* prob, void* elts, void* S, void* v,
+                     void* x, void* u, void* ws, size_t ws_bytes, hipStream_t stream) {
+  LQT_TRY(check_supported(dims));
+  LQT_TRY(check_problem(dims, prob, true, true));
+  const size_t es = dsize(dims->dtype);
+  if (elts) LQT_TRY(check_ptr(elts, "elts", es));
+  LQT_TRY(check_ptr(S, "S", es));
+  LQT_TRY(check_ptr(v, "v", es));
+  LQT_TRY(check_ptr(x, "x", es));
+  if (u) LQT_TRY(check_ptr(u, "u", es));
+  Work w;
+  LQT_TRY(check_ws(dims, LQT_CALL_SOLVE, ws, ws_bytes, &w));
+  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
+  KProb kp = make_kprob(dims, prob, w.consts);
+  const Tree t = tree_for(dims);
+  void* e = elts ? elts : w.elts;
+  LQT_HIP(o->prep(kp, w.consts, stream));
+  LQT_HIP(o->build(kp, e, stream));
+  LQT_TRY(run_value(o, kp, t, w, e, S, v, w.tmap[1], stream));
+  LQT_TRY(run_traj(o, kp, t, w, e, S, v, x, u, stream));
+  return ok();
+}
+
+lqt_status lqt_backward(const lqt_dims* dims, const lqt_problem* prob, const void* S,
+                        const void* v, const void* x, const void* dLdx, void* dQ, void* dR,
+                        void* dr, void* dx0, void* dQf, void* drf, void* ws, size_t ws_bytes,
+                        hipStream_t stream) {
+  (void)prob; (void)S; (void)v; (void)x; (void)dLdx; (void)dQ; (void)dR; (void)dr; (void)dx0;
+  (void)dQf; (void)drf; (void)ws; (void)ws_bytes; (void)stream;
+  LQT_TRY(check_supported(dims));
+  return fail(LQT_EUNSUPPORTED, "lqt_backward is not available in this build");
+}
+
+const char* lqt_status_string(lqt_status s) {
+  switch (s) {
+    case LQT_OK: return "ok";
+    case LQT_EINVAL: return "invalid argument";
+    case LQT_EUNSUPPORTED: return "unsupported";
+    case LQT_EWORKSPACE: return "workspace missing or too small";
+    case LQT_EHIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+const char* lqt_last_error(void) { return g_last_error.c_str(); }
+
+int32_t lqt_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal interfaces between the host API (validation, workspace planning, dispatch) and the
+// kernel translation units.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lqt {
+
+constexpr int kMaxLevels = 40;
+constexpr int kThreads = 64;  // one wavefront per workgroup: spreads small grids over all CUs
+
+// Problem arrays of one call, type-erased (element type given by the dtype of the call).
+struct KProb {
+  int nx, nu, T, n, batch;
+  int F_sampled, L_sampled, has_c;
+  const void *t, *F, *L, *c, *Q, *R, *r, *Qf, *rf, *x0;
+  const void* consts;  // per-problem prepared constants (see consts_count)
+};
+
+// Per-problem constants prepared once per call by the prep kernel (values of the call dtype):
+//   G = L R^{-1} L^T [nx*nx], Lc = L W [nx*nu] with W = chol(R)^{-T} (so G = Lc Lc^T),
+//   Kc = R^{-1} L^T [nu*nx], W [nu*nu], Rinv [nu*nu].  G, Lc, Kc only when L is constant.
+__host__ __device__ inline int consts_off_G(int, int) { return 0; }
+__host__ __device__ inline int consts_off_Lc(int nx, int) { return nx * nx; }
+__host__ __device__ inline int consts_off_Kc(int nx, int nu) { return nx * nx + nx * nu; }
+__host__ __device__ inline int consts_off_W(int nx, int nu) { return nx * nx + 2 * nx * nu; }
+__host__ __device__ inline int consts_off_Rinv(int nx, int nu) { return nx * nx + 2 * nx * nu + nu * nu; }
+__host__ __device__ inline int consts_count(int nx, int nu) { return nx * nx + 2 * nx * nu + 2 * nu * nu; }
+
+// Level sizes of the reduce-then-fold trees: n[0] = T (blocks), n[1] = ceil(T / c0),
+// n[l+1] = ceil(n[l] / c) while n[l] > c; level `levels` is the top, swept by one thread.
+struct Tree {
+  int c0 = 4, c = 8;
+  int levels = 0;
+  long n[kMaxLevels + 1] = {};
+};
+
+Tree plan_tree(long T, int c0, int c);
+
+// Workspace pointers of one call (all per-level arrays hold `batch` problems back to back).
+struct Work {
+  void* consts = nullptr;
+  void* vtup[kMaxLevels + 1] = {};  // value tree: tuples at level l >= 1 [batch][NE][n_l]
+  void* vval[kMaxLevels + 1] = {};  // value tree: (packed S, v) at right ends [batch][NV][n_l]
+  void* tmap[kMaxLevels + 1] = {};  // trajectory tree: affine maps [batch][NM][n_l]
+  void* tx[kMaxLevels + 1] = {};    // trajectory tree: x at left ends [batch][nx][n_l]
+  void* elts = nullptr;             // elements when the caller gives none (lqt_solve)
+};
+
+// Kernel launchers of one (nx, nu, dtype) instantiation.  Each returns hipGetLastError().
+struct Ops {
+  hipError_t (*prep)(const KProb&, void* consts, hipStream_t);
+  hipError_t (*build)(const KProb&, void* elts, hipStream_t);
+  // value tree
+  hipError_t (*vreduce)(const KProb&, const void* src, long n_src, void* dst, long n_dst, int c,
+                        hipStream_t);
+  hipError_t (*vtop)(const KProb&, const void* tup, long n, void* val, hipStream_t);
+  hipError_t (*vdown)(const KProb&, const void* tup, long n_child, const void* val_in, long n_par,
+                      void* val_out, int c, hipStream_t);
+  hipError_t (*vbottom)(const KProb&, const void* elts, const void* val1, long n1, void* S,
+                        void* v, void* maps1, int c0, hipStream_t);
+  // trajectory tree
+  hipError_t (*tbottom_reduce)(const KProb&, const void* elts, const void* S, const void* v,
+                               void* maps1, long n1, int c0, hipStream_t);
+  hipError_t (*treduce)(const KProb&, const void* src, long n_src, void* dst, long n_dst, int c,
+                        hipStream_t);
+  hipError_t (*ttop)(const KProb&, const void* maps, long n, void* xs, hipStream_t);
+  hipError_t (*tdown)(const KProb&, const void* maps, long n_child, const void* x_in, long n_par,
+                      void* x_out, int c, hipStream_t);
+  hipError_t (*tbottom)(const KProb&, const void* elts, const void* S, const void* v,
+                        const void* x1, long n1, void* x, void* u, int c0, hipStream_t);
+};
+
+// Instantiations for 1 <= nu <= nx <= 4 (one tuple per lane); nullptr if not available.
+const Ops* lane_ops(int nx, int nu, int dtype);
+
+// Prep kernel (any nx, nu <= 16).
+hipError_t launch_prep(const KProb& kp, int dtype, void* consts, hipStream_t stream);
+
+}  // namespace lqt

@@ -1,0 +1,751 @@
+// Kernels of the per-lane path (1 <= nu <= nx <= 4): each lane owns one block of the horizon (or
+// one node of a scan tree) and keeps its tuple in registers.  Global arrays are structure-of-
+// arrays, so lane k of a wavefront touching value q of consecutive blocks issues one coalesced
+// access per value.
+//
+// Stages:
+//   k_build        element build: Theorem 8 (Sec. IV-B) integrated with classical RK4.
+//   k_vreduce      value tree, upward: chunk products a_j (x) ... (x) a_{j+c-1} (Lemma 7).
+//   k_vtop         value tree, top: fold of the top nodes from the terminal element (Sec. IV-D).
+//   k_vdown        value tree, downward: value at the right end of every child.
+//   k_vbottom      values S_k, v_k of every block (Theorem 6), optionally with the level-1
+//                  products of the closed-loop block maps for the trajectory.
+//   k_tbottom_reduce / k_treduce / k_ttop / k_tdown / k_tbottom
+//                  trajectory: composition scan of the block maps x_{k+1} = Psi_k x_k + alpha_k
+//                  (Method 1, Sec. IV-E), and the control law u_k (Sec. II-B).
+#include "lane_math.hpp"
+#include "lqt_internal.hpp"
+
+namespace lqt {
+namespace {
+
+template <int N, int NU>
+struct CS {
+  static constexpr int G = 0, Lc = N * N, Kc = N * N + N * NU, W = N * N + 2 * N * NU,
+                       Rinv = N * N + 2 * N * NU + NU * NU, size = N * N + 2 * N * NU + 2 * NU * NU;
+};
+
+__device__ inline long gid() { return (long)blockIdx.x * blockDim.x + threadIdx.x; }
+
+// ------------------------------------------------------------------------------------------
+// Element build (Theorem 8):
+//   dA/ds = A (G J - F),  db/ds = -A (G eta + c),  dC/ds = -A G A^T,
+//   deta/ds = (G J - F)^T eta + J c - Q r,  dJ/ds = -Q + J (G J - F) - F^T J,
+// i.e. the theorem's right-hand sides with K = G J - F factored out (K^T = J G - F^T as G, J are
+// symmetric).  With A = I + Ad: dAd/ds = K + Ad K and A G A^T = (A Lc)(A Lc)^T.  b and C never
+// enter a right-hand side, so their RK4 increments are accumulated directly.  CONST_COEF: F, L
+// constant and c = 0 (their values are then wave-uniform and stay in scalar registers).
+// ------------------------------------------------------------------------------------------
+template <int N, int NU, class R, bool CONST_COEF>
+__global__ __launch_bounds__(kThreads) void k_build(const KProb kp, R* __restrict__ elts) {
+  using Y = Sym<N>;
+  constexpr int NS = Y::size;
+  const int p = blockIdx.y;
+  const long T = kp.T;
+  const long k = gid();
+  if (k >= T) return;
+  const int n = kp.n;
+  const long nsamp = 2L * n * T + 1;
+  const R* __restrict__ t = (const R*)kp.t + p * (T + 1);
+  const R* __restrict__ r = (const R*)kp.r + p * nsamp * N;
+  const R* __restrict__ Fb = (const R*)kp.F + (kp.F_sampled ? p * nsamp * N * N : 0);
+  const R* __restrict__ Lb = (const R*)kp.L + (kp.L_sampled ? p * nsamp * N * NU : 0);
+  const R* __restrict__ cb = kp.has_c ? (const R*)kp.c + p * nsamp * N : nullptr;
+  const R* __restrict__ Qp = (const R*)kp.Q + p * N * N;
+  const R* __restrict__ cs = (const R*)kp.consts + p * CS<N, NU>::size;
+
+  R Q[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) Q[i][j] = Qp[i * N + j];
+  R F[N][N], G[N][N], Lc[N][NU], cv[N];
+  if (CONST_COEF) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        F[i][j] = Fb[i * N + j];
+        G[i][j] = cs[CS<N, NU>::G + i * N + j];
+      }
+#pragma unroll
+      for (int l = 0; l < NU; ++l) Lc[i][l] = cs[CS<N, NU>::Lc + i * NU + l];
+      cv[i] = R(0);
+    }
+  }
+  R Wr[NU][NU];
+  if (!CONST_COEF) {
+#pragma unroll
+    for (int i = 0; i < NU; ++i)
+#pragma unroll
+      for (int j = 0; j < NU; ++j) Wr[i][j] = cs[CS<N, NU>::W + i * NU + j];
+  }
+
+  const R h = (t[k + 1] - t[k]) / R(n);
+  R yA[N][N], yb[N], yC[NS], ye[N], yJ[NS];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) yA[i][j] = R(0);
+    yb[i] = R(0);
+    ye[i] = R(0);
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    yC[i] = R(0);
+    yJ[i] = R(0);
+  }
+
+  for (int m = 0; m < n; ++m) {
+    const long j1 = 2L * n * k + 2L * (n - m);  // sample at s = t_{k+1} - m h
+    R sA[N][N], se[N], sJ[NS], aA[N][N], ae[N], aJ[NS];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) sA[i][j] = yA[i][j];
+      se[i] = ye[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) sJ[i] = yJ[i];
+
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const long j = st == 0 ? j1 : (st == 3 ? j1 - 2 : j1 - 1);
+      const R wk = (st == 0 || st == 3) ? -h / R(6) : -h / R(3);
+      const R cn = st == 2 ? -h : -h / R(2);
+      R rv[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) rv[i] = r[j * N + i];
+      if (!CONST_COEF) {
+        const R* Fj = kp.F_sampled ? Fb + j * N * N : Fb;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int q = 0; q < N; ++q) F[i][q] = Fj[i * N + q];
+        if (kp.L_sampled) {
+          const R* Lj = Lb + j * N * NU;
+#pragma unroll
+          for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int l = 0; l < NU; ++l) {
+              R s = R(0);
+#pragma unroll
+              for (int q = 0; q < NU; ++q) s = fma(Lj[i * NU + q], Wr[q][l], s);
+              Lc[i][l] = s;
+            }
+#pragma unroll
+          for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+              R s = R(0);
+#pragma unroll
+              for (int l = 0; l < NU; ++l) s = fma(Lc[i][l], Lc[q][l], s);
+              G[i][q] = s;
+            }
+        } else {
+#pragma unroll
+          for (int i = 0; i < N; ++i) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) G[i][q] = cs[CS<N, NU>::G + i * N + q];
+#pragma unroll
+            for (int l = 0; l < NU; ++l) Lc[i][l] = cs[CS<N, NU>::Lc + i * NU + l];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) cv[i] = cb ? cb[j * N + i] : R(0);
+      }
+      // K = G J - F
+      R K[N][N];
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          R s = -F[i][q];
+#pragma unroll
+          for (int l = 0; l < N; ++l) s = fma(G[i][l], sJ[Y::at(l, q)], s);
+          K[i][q] = s;
+        }
+      // b: += wk * ( -(I + Ad)(G eta + c) )
+      {
+        R wv[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          R s = cv[i];
+#pragma unroll
+          for (int l = 0; l < N; ++l) s = fma(G[i][l], se[l], s);
+          wv[i] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          R s = wv[i];
+#pragma unroll
+          for (int l = 0; l < N; ++l) s = fma(sA[i][l], wv[l], s);
+          yb[i] = fma(-wk, s, yb[i]);
+        }
+      }
+      // C: += wk * ( -(A Lc)(A Lc)^T ),  A Lc = Lc + Ad Lc
+      {
+        R AL[N][NU];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int l = 0; l < NU; ++l) {
+            R s = Lc[i][l];
+#pragma unroll
+            for (int q = 0; q < N; ++q) s = fma(sA[i][q], Lc[q][l], s);
+            AL[i][l] = s;
+          }
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int q = i; q < N; ++q) {
+            R s = R(0);
+#pragma unroll
+            for (int l = 0; l < NU; ++l) s = fma(AL[i][l], AL[q][l], s);
+            yC[Y::at(i, q)] = fma(-wk, s, yC[Y::at(i, q)]);
+          }
+      }
+      // eta and J derivatives from the stage values
+      R ke[N], kJ[NS];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        R s = R(0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+          s = fma(K[l][i], se[l], s);
+          s = fma(sJ[Y::at(i, l)], cv[l], s);
+          s = fma(-Q[i][l], rv[l], s);
+        }
+        ke[i] = s;
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int q = i; q < N; ++q) {
+          R s = -Q[i][q];
+#pragma unroll
+          for (int l = 0; l < N; ++l) {
+            s = fma(sJ[Y::at(i, l)], K[l][q], s);
+            s = fma(-F[l][i], sJ[Y::at(l, q)], s);
+          }
+          kJ[Y::at(i, q)] = s;
+        }
+      // Ad rows: k = K + Ad K (row i needs only row i of Ad)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        R kr[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          R s = K[i][q];
+#pragma unroll
+          for (int l = 0; l < N; ++l) s = fma(sA[i][l], K[l][q], s);
+          kr[q] = s;
+        }
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          aA[i][q] = st == 0 ? fma(wk, kr[q], yA[i][q]) : fma(wk, kr[q], aA[i][q]);
+          if (st < 3) sA[i][q] = fma(cn, kr[q], yA[i][q]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        ae[i] = st == 0 ? fma(wk, ke[i], ye[i]) : fma(wk, ke[i], ae[i]);
+        if (st < 3) se[i] = fma(cn, ke[i], ye[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        aJ[i] = st == 0 ? fma(wk, kJ[i], yJ[i]) : fma(wk, kJ[i], aJ[i]);
+        if (st < 3) sJ[i] = fma(cn, kJ[i], yJ[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) yA[i][j] = aA[i][j];
+      ye[i] = ae[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) yJ[i] = aJ[i];
+  }
+
+  Tup<N, R> out;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) out.A[i][j] = yA[i][j];
+    out.b[i] = yb[i];
+    out.e[i] = ye[i];
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    out.C[i] = yC[i];
+    out.J[i] = yJ[i];
+  }
+  tup_store(out, elts + (long)p * Lay<N>::NE * T, T, k);
+}
+
+// ------------------------------------------------------------------------------------------
+// Value tree.
+// ------------------------------------------------------------------------------------------
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_vreduce(const R* __restrict__ src, long n_src,
+                                                       R* __restrict__ dst, long n_dst, int c) {
+  const int p = blockIdx.y;
+  const long i = gid();
+  if (i >= n_dst) return;
+  const R* s = src + (long)p * Lay<N>::NE * n_src;
+  const long j0 = i * c;
+  const long j1 = min(j0 + c, n_src);
+  Tup<N, R> acc;
+  tup_load(acc, s, n_src, j1 - 1);
+  for (long j = j1 - 2; j >= j0; --j) {
+    Tup<N, R> x;
+    tup_load(x, s, n_src, j);
+    combine(x, acc, acc);
+  }
+  tup_store(acc, dst + (long)p * Lay<N>::NE * n_dst, n_dst, i);
+}
+
+template <int N, class R>
+LQT_DEV void val_store(const R (&S)[Sym<N>::size], const R (&v)[N], R* base, long stride, long i) {
+#pragma unroll
+  for (int q = 0; q < Sym<N>::size; ++q) base[q * stride + i] = S[q];
+#pragma unroll
+  for (int q = 0; q < N; ++q) base[(Sym<N>::size + q) * stride + i] = v[q];
+}
+
+template <int N, class R>
+LQT_DEV void val_load(R (&S)[Sym<N>::size], R (&v)[N], const R* base, long stride, long i) {
+#pragma unroll
+  for (int q = 0; q < Sym<N>::size; ++q) S[q] = base[q * stride + i];
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = base[(Sym<N>::size + q) * stride + i];
+}
+
+// Terminal value (S, v) = (Qf, Qf rf) of the terminal element (Sec. IV-D).
+template <int N, class R>
+LQT_DEV void terminal_value(const KProb& kp, int p, R (&S)[Sym<N>::size], R (&v)[N]) {
+  const R* Qf = (const R*)kp.Qf + (long)p * N * N;
+  const R* rf = (const R*)kp.rf + (long)p * N;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = i; j < N; ++j) S[Sym<N>::at(i, j)] = Qf[i * N + j];
+    R s = R(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) s = fma(Qf[i * N + j], rf[j], s);
+    v[i] = s;
+  }
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_vtop(const KProb kp, const R* __restrict__ tup,
+                                                    long n, R* __restrict__ val) {
+  const int p = blockIdx.y;
+  if (threadIdx.x != 0) return;
+  const R* tp = tup + (long)p * Lay<N>::NE * n;
+  R* vp = val + (long)p * Lay<N>::NV * n;
+  R S[Sym<N>::size], v[N];
+  terminal_value<N, R>(kp, p, S, v);
+  for (long j = n - 1; j >= 0; --j) {
+    val_store<N, R>(S, v, vp, n, j);
+    if (j == 0) break;
+    Tup<N, R> a;
+    tup_load(a, tp, n, j);
+    Aff<N, R> m;
+    fold(a, S, v, m);
+  }
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_vdown(const R* __restrict__ tup, long n_child,
+                                                     const R* __restrict__ val_in, long n_par,
+                                                     R* __restrict__ val_out, int c) {
+  const int p = blockIdx.y;
+  const long i = gid();
+  if (i >= n_par) return;
+  const R* tp = tup + (long)p * Lay<N>::NE * n_child;
+  R* vo = val_out + (long)p * Lay<N>::NV * n_child;
+  R S[Sym<N>::size], v[N];
+  val_load<N, R>(S, v, val_in + (long)p * Lay<N>::NV * n_par, n_par, i);
+  const long j0 = i * c;
+  const long j1 = min(j0 + c, n_child);
+  for (long j = j1 - 1; j >= j0; --j) {
+    val_store<N, R>(S, v, vo, n_child, j);
+    if (j == j0) break;
+    Tup<N, R> a;
+    tup_load(a, tp, n_child, j);
+    Aff<N, R> m;
+    fold(a, S, v, m);
+  }
+}
+
+template <int N, class R>
+LQT_DEV void S_store_full(const R (&S)[Sym<N>::size], R* dst) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) dst[i * N + j] = S[Sym<N>::at(i, j)];
+}
+
+template <int N, class R>
+LQT_DEV void S_load_upper(R (&S)[Sym<N>::size], const R* src) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) S[Sym<N>::at(i, j)] = src[i * N + j];
+}
+
+// Values of every block: S_k, v_k for k in chunk i, folded from the value at the chunk's right end.
+// maps1 (optional): the product of the chunk's closed-loop block maps, level 1 of the trajectory
+// tree (the maps come out of the fold for free).
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_vbottom(const KProb kp, const R* __restrict__ elts,
+                                                       const R* __restrict__ val1, long n1,
+                                                       R* __restrict__ Sout, R* __restrict__ vout,
+                                                       R* __restrict__ maps1, int c0) {
+  const int p = blockIdx.y;
+  const long i = gid();
+  if (i >= n1) return;
+  const long T = kp.T;
+  const R* ep = elts + (long)p * Lay<N>::NE * T;
+  R* Sp = Sout + (long)p * (T + 1) * N * N;
+  R* vp = vout + (long)p * (T + 1) * N;
+  R S[Sym<N>::size], v[N];
+  val_load<N, R>(S, v, val1 + (long)p * Lay<N>::NV * n1, n1, i);
+  const long j0 = i * c0;
+  const long j1 = min(j0 + c0, T);
+  if (j1 == T) {
+    S_store_full<N, R>(S, Sp + T * N * N);
+#pragma unroll
+    for (int q = 0; q < N; ++q) vp[T * N + q] = v[q];
+  }
+  Aff<N, R> acc;
+  aff_identity(acc);
+  for (long k = j1 - 1; k >= j0; --k) {
+    Tup<N, R> a;
+    tup_load(a, ep, T, k);
+    Aff<N, R> m;
+    fold(a, S, v, m);
+    S_store_full<N, R>(S, Sp + k * N * N);
+#pragma unroll
+    for (int q = 0; q < N; ++q) vp[k * N + q] = v[q];
+    if (maps1) aff_after(acc, m);
+  }
+  if (maps1) aff_store(acc, maps1 + (long)p * Lay<N>::NM * n1, n1, i);
+}
+
+// ------------------------------------------------------------------------------------------
+// Trajectory tree.
+// ------------------------------------------------------------------------------------------
+template <int N, class R>
+LQT_DEV void elt_map_part(const R* ep, long T, long k, R (&Ad)[N][N], R (&b)[N],
+                          R (&C)[Sym<N>::size]) {
+  using L = Lay<N>;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) Ad[i][j] = ep[(L::A + i * N + j) * T + k];
+    b[i] = ep[(L::B + i) * T + k];
+  }
+#pragma unroll
+  for (int q = 0; q < Sym<N>::size; ++q) C[q] = ep[(L::C + q) * T + k];
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_tbottom_reduce(const KProb kp,
+                                                              const R* __restrict__ elts,
+                                                              const R* __restrict__ Sg,
+                                                              const R* __restrict__ vg,
+                                                              R* __restrict__ maps1, long n1,
+                                                              int c0) {
+  const int p = blockIdx.y;
+  const long i = gid();
+  if (i >= n1) return;
+  const long T = kp.T;
+  const R* ep = elts + (long)p * Lay<N>::NE * T;
+  const R* Sp = Sg + (long)p * (T + 1) * N * N;
+  const R* vp = vg + (long)p * (T + 1) * N;
+  const long j0 = i * c0;
+  const long j1 = min(j0 + c0, T);
+  Aff<N, R> acc;
+  aff_identity(acc);
+  for (long k = j0; k < j1; ++k) {
+    R Ad[N][N], b[N], C[Sym<N>::size], S[Sym<N>::size], v[N];
+    elt_map_part<N, R>(ep, T, k, Ad, b, C);
+    S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = vp[(k + 1) * N + q];
+    Aff<N, R> m;
+    block_map<N, R>(Ad, b, C, S, v, m);
+    aff_then(acc, m);
+  }
+  aff_store(acc, maps1 + (long)p * Lay<N>::NM * n1, n1, i);
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_treduce(const R* __restrict__ src, long n_src,
+                                                       R* __restrict__ dst, long n_dst, int c) {
+  const int p = blockIdx.y;
+  const long i = gid();
+  if (i >= n_dst) return;
+  const R* s = src + (long)p * Lay<N>::NM * n_src;
+  const long j0 = i * c;
+  const long j1 = min(j0 + c, n_src);
+  Aff<N, R> acc;
+  aff_load(acc, s, n_src, j0);
+  for (long j = j0 + 1; j < j1; ++j) {
+    Aff<N, R> m;
+    aff_load(m, s, n_src, j);
+    aff_then(acc, m);
+  }
+  aff_store(acc, dst + (long)p * Lay<N>::NM * n_dst, n_dst, i);
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_ttop(const KProb kp, const R* __restrict__ maps,
+                                                    long n, R* __restrict__ xs) {
+  const int p = blockIdx.y;
+  if (threadIdx.x != 0) return;
+  const R* mp = maps + (long)p * Lay<N>::NM * n;
+  R* xp = xs + (long)p * N * n;
+  R x[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) x[q] = ((const R*)kp.x0)[(long)p * N + q];
+  for (long j = 0; j < n; ++j) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) xp[q * n + j] = x[q];
+    if (j == n - 1) break;
+    Aff<N, R> m;
+    aff_load(m, mp, n, j);
+    aff_apply(m, x);
+  }
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_tdown(const R* __restrict__ maps, long n_child,
+                                                     const R* __restrict__ x_in, long n_par,
+                                                     R* __restrict__ x_out, int c) {
+  const int p = blockIdx.y;
+  const long i = gid();
+  if (i >= n_par) return;
+  const R* mp = maps + (long)p * Lay<N>::NM * n_child;
+  R* xo = x_out + (long)p * N * n_child;
+  R x[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) x[q] = x_in[(long)p * N * n_par + q * n_par + i];
+  const long j0 = i * c;
+  const long j1 = min(j0 + c, n_child);
+  for (long j = j0; j < j1; ++j) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) xo[q * n_child + j] = x[q];
+    if (j == j1 - 1) break;
+    Aff<N, R> m;
+    aff_load(m, mp, n_child, j);
+    aff_apply(m, x);
+  }
+}
+
+// u = -Kc (S x - v) with Kc = R^{-1} L(t_k)^T.
+template <int N, int NU, class R>
+LQT_DEV void control(const R (&Kc)[NU][N], const R (&S)[Sym<N>::size], const R (&v)[N],
+                     const R (&x)[N], R* u) {
+  R g[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = -v[i];
+#pragma unroll
+    for (int j = 0; j < N; ++j) s = fma(S[Sym<N>::at(i, j)], x[j], s);
+    g[i] = s;
+  }
+#pragma unroll
+  for (int l = 0; l < NU; ++l) {
+    R s = R(0);
+#pragma unroll
+    for (int j = 0; j < N; ++j) s = fma(-Kc[l][j], g[j], s);
+    u[l] = s;
+  }
+}
+
+template <int N, int NU, class R>
+LQT_DEV void gain_at(const KProb& kp, int p, long k, R (&Kc)[NU][N]) {
+  const R* cs = (const R*)kp.consts + (long)p * CS<N, NU>::size;
+  if (!kp.L_sampled) {
+#pragma unroll
+    for (int l = 0; l < NU; ++l)
+#pragma unroll
+      for (int j = 0; j < N; ++j) Kc[l][j] = cs[CS<N, NU>::Kc + l * N + j];
+  } else {
+    const long nsamp = 2L * kp.n * kp.T + 1;
+    const R* Lk = (const R*)kp.L + ((long)p * nsamp + 2L * kp.n * k) * N * NU;
+#pragma unroll
+    for (int l = 0; l < NU; ++l)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        R s = R(0);
+#pragma unroll
+        for (int q = 0; q < NU; ++q) s = fma(cs[CS<N, NU>::Rinv + l * NU + q], Lk[j * NU + q], s);
+        Kc[l][j] = s;
+      }
+  }
+}
+
+template <int N, int NU, class R>
+__global__ __launch_bounds__(kThreads) void k_tbottom(const KProb kp, const R* __restrict__ elts,
+                                                       const R* __restrict__ Sg,
+                                                       const R* __restrict__ vg,
+                                                       const R* __restrict__ x1, long n1,
+                                                       R* __restrict__ xout, R* __restrict__ uout,
+                                                       int c0) {
+  const int p = blockIdx.y;
+  const long i = gid();
+  if (i >= n1) return;
+  const long T = kp.T;
+  const R* ep = elts + (long)p * Lay<N>::NE * T;
+  const R* Sp = Sg + (long)p * (T + 1) * N * N;
+  const R* vp = vg + (long)p * (T + 1) * N;
+  R* xp = xout + (long)p * (T + 1) * N;
+  R* up = uout ? uout + (long)p * (T + 1) * NU : nullptr;
+  R x[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) x[q] = x1[(long)p * N * n1 + q * n1 + i];
+  const long j0 = i * c0;
+  const long j1 = min(j0 + c0, T);
+  R S[Sym<N>::size], v[N];
+  S_load_upper<N, R>(S, Sp + j0 * N * N);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = vp[j0 * N + q];
+  R Kc[NU][N];
+  if (!kp.L_sampled) gain_at<N, NU, R>(kp, p, 0, Kc);
+  for (long k = j0; k < j1; ++k) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) xp[k * N + q] = x[q];
+    if (up) {
+      if (kp.L_sampled) gain_at<N, NU, R>(kp, p, k, Kc);
+      control<N, NU, R>(Kc, S, v, x, up + k * NU);
+    }
+    R Ad[N][N], b[N], C[Sym<N>::size];
+    elt_map_part<N, R>(ep, T, k, Ad, b, C);
+    S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = vp[(k + 1) * N + q];
+    Aff<N, R> m;
+    block_map<N, R>(Ad, b, C, S, v, m);
+    aff_apply(m, x);
+  }
+  if (j1 == T) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) xp[T * N + q] = x[q];
+    if (up) {
+      if (kp.L_sampled) gain_at<N, NU, R>(kp, p, T, Kc);
+      control<N, NU, R>(Kc, S, v, x, up + T * NU);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers.
+// ------------------------------------------------------------------------------------------
+inline dim3 grid_for(long n, int batch) {
+  return dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)batch, 1);
+}
+
+template <int N, int NU, class R>
+struct L {
+  static hipError_t build(const KProb& kp, void* elts, hipStream_t s) {
+    const bool cc = !kp.F_sampled && !kp.L_sampled && !kp.has_c;
+    if (cc)
+      hipLaunchKernelGGL((k_build<N, NU, R, true>), grid_for(kp.T, kp.batch), dim3(kThreads), 0,
+                         s, kp, (R*)elts);
+    else
+      hipLaunchKernelGGL((k_build<N, NU, R, false>), grid_for(kp.T, kp.batch), dim3(kThreads), 0,
+                         s, kp, (R*)elts);
+    return hipGetLastError();
+  }
+  static hipError_t vreduce(const KProb& kp, const void* src, long n_src, void* dst, long n_dst,
+                            int c, hipStream_t s) {
+    hipLaunchKernelGGL((k_vreduce<N, R>), grid_for(n_dst, kp.batch), dim3(kThreads), 0, s,
+                       (const R*)src, n_src, (R*)dst, n_dst, c);
+    return hipGetLastError();
+  }
+  static hipError_t vtop(const KProb& kp, const void* tup, long n, void* val, hipStream_t s) {
+    hipLaunchKernelGGL((k_vtop<N, R>), dim3(1, kp.batch, 1), dim3(kThreads), 0, s, kp,
+                       (const R*)tup, n, (R*)val);
+    return hipGetLastError();
+  }
+  static hipError_t vdown(const KProb& kp, const void* tup, long n_child, const void* val_in,
+                          long n_par, void* val_out, int c, hipStream_t s) {
+    hipLaunchKernelGGL((k_vdown<N, R>), grid_for(n_par, kp.batch), dim3(kThreads), 0, s,
+                       (const R*)tup, n_child, (const R*)val_in, n_par, (R*)val_out, c);
+    return hipGetLastError();
+  }
+  static hipError_t vbottom(const KProb& kp, const void* elts, const void* val1, long n1, void* S,
+                            void* v, void* maps1, int c0, hipStream_t s) {
+    hipLaunchKernelGGL((k_vbottom<N, R>), grid_for(n1, kp.batch), dim3(kThreads), 0, s, kp,
+                       (const R*)elts, (const R*)val1, n1, (R*)S, (R*)v, (R*)maps1, c0);
+    return hipGetLastError();
+  }
+  static hipError_t tbottom_reduce(const KProb& kp, const void* elts, const void* S,
+                                   const void* v, void* maps1, long n1, int c0, hipStream_t s) {
+    hipLaunchKernelGGL((k_tbottom_reduce<N, R>), grid_for(n1, kp.batch), dim3(kThreads), 0, s,
+                       kp, (const R*)elts, (const R*)S, (const R*)v, (R*)maps1, n1, c0);
+    return hipGetLastError();
+  }
+  static hipError_t treduce(const KProb& kp, const void* src, long n_src, void* dst, long n_dst,
+                            int c, hipStream_t s) {
+    hipLaunchKernelGGL((k_treduce<N, R>), grid_for(n_dst, kp.batch), dim3(kThreads), 0, s,
+                       (const R*)src, n_src, (R*)dst, n_dst, c);
+    return hipGetLastError();
+  }
+  static hipError_t ttop(const KProb& kp, const void* maps, long n, void* xs, hipStream_t s) {
+    hipLaunchKernelGGL((k_ttop<N, R>), dim3(1, kp.batch, 1), dim3(kThreads), 0, s, kp,
+                       (const R*)maps, n, (R*)xs);
+    return hipGetLastError();
+  }
+  static hipError_t tdown(const KProb& kp, const void* maps, long n_child, const void* x_in,
+                          long n_par, void* x_out, int c, hipStream_t s) {
+    hipLaunchKernelGGL((k_tdown<N, R>), grid_for(n_par, kp.batch), dim3(kThreads), 0, s,
+                       (const R*)maps, n_child, (const R*)x_in, n_par, (R*)x_out, c);
+    return hipGetLastError();
+  }
+  static hipError_t tbottom(const KProb& kp, const void* elts, const void* S, const void* v,
+                            const void* x1, long n1, void* x, void* u, int c0, hipStream_t s) {
+    hipLaunchKernelGGL((k_tbottom<N, NU, R>), grid_for(n1, kp.batch), dim3(kThreads), 0, s, kp,
+                       (const R*)elts, (const R*)S, (const R*)v, (const R*)x1, n1, (R*)x, (R*)u,
+                       c0);
+    return hipGetLastError();
+  }
+  static hipError_t prep(const KProb& kp, void* consts, hipStream_t s) {
+    return launch_prep(kp, sizeof(R) == 8 ? 0 : 1, consts, s);
+  }
+  static const Ops* ops() {
+    static const Ops o = {prep,    build,          vreduce, vtop, vdown, vbottom,
+                          tbottom_reduce, treduce, ttop,    tdown, tbottom};
+    return &o;
+  }
+};
+
+template <class R>
+const Ops* ops_for(int nx, int nu) {
+  switch (nx * 8 + nu) {
+    case 1 * 8 + 1: return L<1, 1, R>::ops();
+    case 2 * 8 + 1: return L<2, 1, R>::ops();
+    case 2 * 8 + 2: return L<2, 2, R>::ops();
+    case 3 * 8 + 1: return L<3, 1, R>::ops();
+    case 3 * 8 + 2: return L<3, 2, R>::ops();
+    case 3 * 8 + 3: return L<3, 3, R>::ops();
+    case 4 * 8 + 1: return L<4, 1, R>::ops();
+    case 4 * 8 + 2: return L<4, 2, R>::ops();
+    case 4 * 8 + 3: return L<4, 3, R>::ops();
+    case 4 * 8 + 4: return L<4, 4, R>::ops();
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+const Ops* lane_ops(int nx, int nu, int dtype) {
+  return dtype == 0 ? ops_for<double>(nx, nu) : ops_for<float>(nx, nu);
+}
+
+}  // namespace lqt

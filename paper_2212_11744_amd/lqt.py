@@ -1,0 +1,250 @@
+"""Python binding of the C ABI in include/lqt.h (argument marshalling only).
+
+Every stage runs in the gfx950 HIP library `liblqt.so`; this module turns torch tensors into
+device pointers, allocates outputs and workspaces with torch, passes the current HIP stream and
+raises on error.  There is no fallback: if the library is missing or does not load, every entry
+point raises.  Functions mirror the C entry points:
+
+    build_elements(prob) -> elts
+    scan_value(prob, elts) -> S, v
+    forward_traj(prob, elts, S, v) -> x, u
+    solve(prob) -> dict(elts?, S, v, x, u)
+    backward(prob, S, v, x, dLdx) -> dict of gradients
+
+`prob` is a `DeviceProblem`: the arrays of one or more equally sized problems resident on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblqt.so")
+
+LQT_OK, LQT_EINVAL, LQT_EUNSUPPORTED, LQT_EWORKSPACE, LQT_EHIP = 0, -1, -2, -3, -4
+LQT_F64, LQT_F32 = 0, 1
+CALL_BUILD, CALL_SCAN_VALUE, CALL_FORWARD_TRAJ, CALL_SOLVE, CALL_BACKWARD = range(5)
+
+
+class LQTError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"lqt status {status}: {message}")
+        self.status = status
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("nx", "nu", "T", "n_steps", "batch", "dtype", "F_sampled", "L_sampled", "has_c")]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("t", "F", "L", "c", "Q", "R", "r", "Qf", "rf", "x0")]
+
+
+_lib = None
+
+
+def lib():
+    """Load liblqt.so (raises if it is missing: there is no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with `python -m paper_2212_11744_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp, sz, st = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p
+        L.lqt_element_count.argtypes = [ctypes.c_int32]
+        L.lqt_element_count.restype = sz
+        L.lqt_workspace_size.argtypes = [P(Dims), ctypes.c_int]
+        L.lqt_workspace_size.restype = sz
+        L.lqt_build_elements.argtypes = [P(Dims), P(Problem), vp, vp, sz, st]
+        L.lqt_scan_value.argtypes = [P(Dims), vp, vp, vp, vp, vp, vp, sz, st]
+        L.lqt_forward_traj.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
+        L.lqt_solve.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
+        L.lqt_backward.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, st]
+        for f in ("lqt_build_elements", "lqt_scan_value", "lqt_forward_traj", "lqt_solve", "lqt_backward"):
+            getattr(L, f).restype = ctypes.c_int
+        L.lqt_status_string.argtypes = [ctypes.c_int]
+        L.lqt_status_string.restype = ctypes.c_char_p
+        L.lqt_last_error.restype = ctypes.c_char_p
+        L.lqt_version.restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != LQT_OK:
+        raise LQTError(status, lib().lqt_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class DeviceProblem:
+    """Arrays of `batch` equally sized LQT problems on the GPU (layouts of include/lqt.h)."""
+
+    nx: int
+    nu: int
+    T: int
+    n: int
+    batch: int
+    dtype: torch.dtype
+    t: torch.Tensor
+    F: torch.Tensor
+    L: torch.Tensor
+    Q: torch.Tensor
+    R: torch.Tensor
+    r: torch.Tensor
+    Qf: torch.Tensor
+    rf: torch.Tensor
+    x0: torch.Tensor
+    c: Optional[torch.Tensor] = None
+    F_sampled: bool = False
+    L_sampled: bool = False
+
+    @property
+    def nsamp(self) -> int:
+        return 2 * self.n * self.T + 1
+
+    def dims(self) -> Dims:
+        return Dims(self.nx, self.nu, self.T, self.n, self.batch,
+                    LQT_F64 if self.dtype == torch.float64 else LQT_F32,
+                    int(self.F_sampled), int(self.L_sampled), int(self.c is not None))
+
+    def ptrs(self) -> Problem:
+        return Problem(*[None if getattr(self, k) is None else getattr(self, k).data_ptr()
+                         for k in ("t", "F", "L", "c", "Q", "R", "r", "Qf", "rf", "x0")])
+
+    @classmethod
+    def from_problems(cls, problems: Sequence, dtype=torch.float64, device="cuda") -> "DeviceProblem":
+        """Stack host problems (objects with the fields of `workloads.Problem`) onto the device.
+        All members must share nx, nu, T, n and, when constant, F and L."""
+        p0 = problems[0]
+        for p in problems:
+            if (p.nx, p.nu, p.T, p.n) != (p0.nx, p0.nu, p0.T, p0.n):
+                raise ValueError("batched problems must share nx, nu, T and n")
+        F_s, L_s = np.ndim(p0.F) == 3, np.ndim(p0.L) == 3
+        to = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+        stack = lambda name: to(np.stack([np.asarray(getattr(p, name)) for p in problems]))
+        has_c = getattr(p0, "c", None) is not None
+        return cls(p0.nx, p0.nu, p0.T, p0.n, len(problems), dtype,
+                   stack("t"), stack("F") if F_s else to(p0.F), stack("L") if L_s else to(p0.L),
+                   stack("Q"), stack("R"), stack("r"), stack("Qf"), stack("rf"), stack("x0"),
+                   stack("c") if has_c else None, F_s, L_s)
+
+
+def element_count(nx: int) -> int:
+    return int(lib().lqt_element_count(nx))
+
+
+def workspace_size(prob: DeviceProblem, call: int) -> int:
+    d = prob.dims()
+    n = int(lib().lqt_workspace_size(ctypes.byref(d), call))
+    if n == 0:
+        raise LQTError(LQT_EINVAL, "invalid dims for workspace query")
+    return n
+
+
+def workspace(prob: DeviceProblem, call: int) -> torch.Tensor:
+    n = workspace_size(prob, call)
+    ws = torch.empty(n + 256, dtype=torch.uint8, device=prob.t.device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + n]
+
+
+def _empty(prob, *shape):
+    return torch.empty(*shape, dtype=prob.dtype, device=prob.t.device)
+
+
+def build_elements(prob: DeviceProblem, elts: Optional[torch.Tensor] = None,
+                   ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Elements [batch][NE][T] (structure of arrays, A stored as A - I)."""
+    elts = _empty(prob, prob.batch, element_count(prob.nx), prob.T) if elts is None else elts
+    ws = workspace(prob, CALL_BUILD) if ws is None else ws
+    d, p = prob.dims(), prob.ptrs()
+    _check(lib().lqt_build_elements(ctypes.byref(d), ctypes.byref(p), _ptr(elts), _ptr(ws),
+                                    ws.numel(), _stream()))
+    return elts
+
+
+def scan_value(prob: DeviceProblem, elts: torch.Tensor, S=None, v=None, ws=None):
+    """Value function S [batch][T+1][nx][nx], v [batch][T+1][nx]."""
+    S = _empty(prob, prob.batch, prob.T + 1, prob.nx, prob.nx) if S is None else S
+    v = _empty(prob, prob.batch, prob.T + 1, prob.nx) if v is None else v
+    ws = workspace(prob, CALL_SCAN_VALUE) if ws is None else ws
+    d = prob.dims()
+    _check(lib().lqt_scan_value(ctypes.byref(d), _ptr(elts), _ptr(prob.Qf), _ptr(prob.rf), _ptr(S),
+                                _ptr(v), _ptr(ws), ws.numel(), _stream()))
+    return S, v
+
+
+def forward_traj(prob: DeviceProblem, elts, S, v, x=None, u=None, ws=None, want_u=True):
+    """Trajectory x [batch][T+1][nx] and control u [batch][T+1][nu]."""
+    x = _empty(prob, prob.batch, prob.T + 1, prob.nx) if x is None else x
+    if want_u and u is None:
+        u = _empty(prob, prob.batch, prob.T + 1, prob.nu)
+    ws = workspace(prob, CALL_FORWARD_TRAJ) if ws is None else ws
+    d, p = prob.dims(), prob.ptrs()
+    _check(lib().lqt_forward_traj(ctypes.byref(d), ctypes.byref(p), _ptr(elts), _ptr(S), _ptr(v),
+                                  _ptr(x), _ptr(u), _ptr(ws), ws.numel(), _stream()))
+    return x, u
+
+
+def solve(prob: DeviceProblem, out: Optional[dict] = None, ws=None, keep_elements=False):
+    """All stages in one call.  Returns dict with S, v, x, u (and elts if keep_elements)."""
+    if out is None:
+        out = {"S": _empty(prob, prob.batch, prob.T + 1, prob.nx, prob.nx),
+               "v": _empty(prob, prob.batch, prob.T + 1, prob.nx),
+               "x": _empty(prob, prob.batch, prob.T + 1, prob.nx),
+               "u": _empty(prob, prob.batch, prob.T + 1, prob.nu)}
+        if keep_elements:
+            out["elts"] = _empty(prob, prob.batch, element_count(prob.nx), prob.T)
+    ws = workspace(prob, CALL_SOLVE) if ws is None else ws
+    d, p = prob.dims(), prob.ptrs()
+    _check(lib().lqt_solve(ctypes.byref(d), ctypes.byref(p), _ptr(out.get("elts")), _ptr(out["S"]),
+                           _ptr(out["v"]), _ptr(out["x"]), _ptr(out.get("u")), _ptr(ws), ws.numel(),
+                           _stream()))
+    return out
+
+
+def backward(prob: DeviceProblem, S, v, x, dLdx, ws=None, want_terminal=True):
+    """Gradients of a trajectory loss (dLdx [batch][T+1][nx]) w.r.t. Q, R, r, x0, Qf, rf."""
+    g = {"Q": _empty(prob, prob.batch, prob.nx, prob.nx), "R": _empty(prob, prob.batch, prob.nu, prob.nu),
+         "r": _empty(prob, prob.batch, prob.nsamp, prob.nx), "x0": _empty(prob, prob.batch, prob.nx)}
+    if want_terminal:
+        g["Qf"] = _empty(prob, prob.batch, prob.nx, prob.nx)
+        g["rf"] = _empty(prob, prob.batch, prob.nx)
+    ws = workspace(prob, CALL_BACKWARD) if ws is None else ws
+    d, p = prob.dims(), prob.ptrs()
+    _check(lib().lqt_backward(ctypes.byref(d), ctypes.byref(p), _ptr(S), _ptr(v), _ptr(x), _ptr(dLdx),
+                              _ptr(g["Q"]), _ptr(g["R"]), _ptr(g["r"]), _ptr(g["x0"]), _ptr(g.get("Qf")),
+                              _ptr(g.get("rf")), _ptr(ws), ws.numel(), _stream()))
+    return g
+
+
+# --------------------------------------------------------------------------------------------
+# Element layout helpers (structure of arrays, see include/lqt.h).
+# --------------------------------------------------------------------------------------------
+def element_slices(nx: int):
+    ns = nx * (nx + 1) // 2
+    o = 0
+    out = {}
+    for name, size in (("A", nx * nx), ("b", nx), ("C", ns), ("eta", nx), ("J", ns)):
+        out[name] = slice(o, o + size)
+        o += size
+    return out
+
+
+def upper_indices(nx: int):
+    return np.triu_indices(nx)

@@ -1,0 +1,87 @@
+"""The C-ABI library loads and exports every entry point include/lqt.h declares; host-side
+argument validation rejects bad calls before anything is launched (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2212_11744_amd import lqt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "lqt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lqt_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 10
+    L = lqt.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_element_count_and_version():
+    assert lqt.element_count(4) == 44
+    assert lqt.element_count(16) == 2 * 256 + 48
+    assert lqt.lib().lqt_version() >= 100
+    assert lqt.lib().lqt_status_string(lqt.LQT_EWORKSPACE).decode().startswith("workspace")
+
+
+def _dims(**kw):
+    base = dict(nx=4, nu=2, T=1024, n_steps=4, batch=1, dtype=lqt.LQT_F64, F_sampled=0, L_sampled=0,
+                has_c=0)
+    base.update(kw)
+    return lqt.Dims(**base)
+
+
+def test_workspace_sizes_grow_with_T_and_reject_invalid_dims():
+    L = lqt.lib()
+    s1 = L.lqt_workspace_size(ctypes.byref(_dims(T=1024)), lqt.CALL_SOLVE)
+    s2 = L.lqt_workspace_size(ctypes.byref(_dims(T=4096)), lqt.CALL_SOLVE)
+    assert 0 < s1 < s2
+    assert L.lqt_workspace_size(ctypes.byref(_dims(T=1024, dtype=lqt.LQT_F32)), lqt.CALL_SOLVE) < s1
+    for bad in (dict(T=0), dict(nx=0), dict(nu=5), dict(nx=17, nu=2), dict(n_steps=0), dict(batch=0),
+                dict(dtype=7)):
+        assert L.lqt_workspace_size(ctypes.byref(_dims(**bad)), lqt.CALL_SOLVE) == 0, bad
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(T=0), lqt.LQT_EINVAL),
+    (dict(nx=0), lqt.LQT_EINVAL),
+    (dict(nu=3, nx=2), lqt.LQT_EINVAL),
+    (dict(n_steps=0), lqt.LQT_EINVAL),
+    (dict(dtype=3), lqt.LQT_EINVAL),
+])
+def test_invalid_dims_rejected_before_launch(bad, status):
+    L = lqt.lib()
+    d = _dims(**bad)
+    p = lqt.Problem()
+    st = L.lqt_build_elements(ctypes.byref(d), ctypes.byref(p), None, None, 0, None)
+    assert st == status
+    assert L.lqt_last_error()
+
+
+def test_null_pointers_rejected_before_launch():
+    L = lqt.lib()
+    d = _dims()
+    p = lqt.Problem()
+    assert L.lqt_build_elements(ctypes.byref(d), ctypes.byref(p), None, None, 0, None) == lqt.LQT_EINVAL
+    assert b"is NULL" in L.lqt_last_error()
+    assert L.lqt_build_elements(ctypes.byref(d), None, None, None, 0, None) == lqt.LQT_EINVAL
+    assert L.lqt_scan_value(ctypes.byref(d), None, None, None, None, None, None, 0, None) == lqt.LQT_EINVAL
+    assert L.lqt_solve(None, None, None, None, None, None, None, None, 0, None) == lqt.LQT_EINVAL
+
+
+def test_workspace_too_small_rejected_before_launch():
+    L = lqt.lib()
+    d = _dims()
+    fake = 1 << 20  # never dereferenced: validation fails first
+    st = L.lqt_scan_value(ctypes.byref(d), fake, fake, fake, fake, fake, fake, 16, None)
+    assert st == lqt.LQT_EWORKSPACE
+    st = L.lqt_scan_value(ctypes.byref(d), fake, fake, fake, fake, fake, fake + 8, 1 << 40, None)
+    assert st == lqt.LQT_EWORKSPACE  # misaligned workspace
