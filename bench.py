@@ -1,0 +1,189 @@
+"""Benchmark: full parallel-in-time LQT solve (elements + value scan + trajectory scan) on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--T 1048576] [--dtype f64|f32]
+
+Workload: the point-mass tracking problem (nx = 4, nu = 2) on [0, 10] with T = 2^20 blocks of
+4 RK4 steps each, FP64, seeded synthetic reference (sum of sinusoids), inputs resident in HBM.
+A step is one call of lqt_solve: per-block elements, the value scan (S_k, v_k) and the
+trajectory scan (x_k, u_k) at all T + 1 block boundaries.  Prints one JSON line.
+
+The dominant kernel (the element build, bound by FP64 vector arithmetic) is timed on its own with
+HIP events on the stream it is launched on; its algorithmic flop count is the FMA count of the
+kernel's formulation (see build_flops_per_block), the same figure the design notes derive.
+The CPU baseline is the oracle (single-threaded, unmodified) on a bounded sample of the same
+workload: the first M blocks of the grid (same block length and reference) solved as a horizon
+of their own.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK = {"hbm_GBps": 8000.0, "f64_TFLOPs": 78.6, "f32_TFLOPs": 157.3}
+
+
+def build_flops_per_block(nx: int, nu: int, n: int, has_c: bool = False) -> int:
+    """FP64/FP32 flops (FMA = 2) of one block of the element build as the kernel computes it.
+
+    Per RK4 stage: K = G J - F (nx^3), G eta (nx^2), b increment (nx^2 + nx), A Lc (nx^2 nu),
+    C increment (ns nu + ns), eta derivative (2 nx^2, + nx^2 with a drift c), J derivative
+    (nx^2 (nx + 1)), A-row derivative (nx^3) and the RK4 accumulations (2 nx^2 + 2 nx + 2 ns,
+    minus the stage-input updates in the last stage).  ns = nx (nx + 1) / 2.
+    """
+    ns = nx * (nx + 1) // 2
+    per_stage = (nx ** 3 + nx ** 2 + nx ** 2 + nx + nx * nx * nu + ns * nu + ns + 2 * nx ** 2
+                 + (nx ** 2 if has_c else 0) + nx ** 2 * (nx + 1) + nx ** 3
+                 + 2 * nx ** 2 + 2 * nx + 2 * ns)
+    last_stage = per_stage - (nx ** 2 + nx + ns)
+    return 2 * n * (3 * per_stage + last_stage)
+
+
+def build_bytes_per_block(nx: int, n: int, es: int) -> int:
+    """HBM bytes per block of the element build: 2n new reference samples read, one element
+    (2 nx^2 + 3 nx values) written."""
+    return es * (2 * n * nx + 2 * nx * nx + 3 * nx)
+
+
+def _events_time(fn, reps, torch):
+    s = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(s)
+    for _ in range(reps):
+        fn()
+    b.record(s)
+    b.synchronize()
+    return a.elapsed_time(b) / reps  # ms
+
+
+def cpu_baseline(T: int, target_s: float):
+    """The oracle on the first M blocks of the workload grid (M sized for ~target_s seconds)."""
+    import oracle as O
+    from paper_2212_11744_amd import workloads as W
+
+    def run(M):
+        p = W.point_mass(2, M, 4, 0.0, 10.0 * M / T)
+        t0 = time.perf_counter()
+        O.solve(p)
+        return time.perf_counter() - t0
+
+    M = 2048
+    dt = run(M)
+    M = int(min(T, max(2048, M * target_s / max(dt, 1e-3))))
+    dt = run(M)
+    return {"value": M / dt, "unit": "sub-intervals/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {M} of the {T} blocks (same block length, reference and weights) "
+                      f"solved as their own horizon by the sequential FP64 oracle: elements, value "
+                      f"fold and trajectory; {dt:.1f} s on one host thread"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--T", type=int, default=2 ** 20)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_build_f64_T2p20.json"))
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for "
+              f"--gpus {args.gpus}); the design notes describe how the solve would shard.",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2212_11744_amd import lqt
+    from paper_2212_11744_amd import workloads as W
+
+    dtype = torch.float64 if args.dtype == "f64" else torch.float32
+    es = 8 if args.dtype == "f64" else 4
+    T, n = args.T, 4
+    p = W.point_mass(2, T, n)
+    dp = lqt.DeviceProblem.from_problems([p], dtype=dtype)
+    out = {"S": torch.empty(1, T + 1, 4, 4, dtype=dtype, device="cuda"),
+           "v": torch.empty(1, T + 1, 4, dtype=dtype, device="cuda"),
+           "x": torch.empty(1, T + 1, 4, dtype=dtype, device="cuda"),
+           "u": torch.empty(1, T + 1, 2, dtype=dtype, device="cuda"),
+           "elts": None}
+    out["elts"] = lqt.empty_elements(dp)
+    ws = lqt.workspace(dp, lqt.CALL_SOLVE)
+    ws_b = lqt.workspace(dp, lqt.CALL_BUILD)
+    step = lambda: lqt.solve(dp, out, ws)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ms = _events_time(step, args.steps, torch)
+    torch.cuda.synchronize()
+
+    # Dominant kernel on its own: lqt_build_elements = per-problem constants (one tiny launch) +
+    # the element build.
+    build = lambda: lqt.build_elements(dp, out["elts"], ws_b)
+    build()
+    ms_build = _events_time(build, args.steps, torch)
+    flops = build_flops_per_block(4, 2, n) * T
+    achieved = flops / (ms_build * 1e-3) / 1e12
+    peak = PEAK["f64_TFLOPs" if es == 8 else "f32_TFLOPs"]
+    traffic = None
+    if os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            tr = json.load(f)
+        if tr.get("T") == T and tr.get("dtype") == args.dtype and tr.get("kernel_source_sha") == _kernel_sha():
+            traffic = tr.get("bytes_per_launch")
+    # Stage breakdown (each stage call timed on its own).
+    S, v = out["S"], out["v"]
+    ws_v = lqt.workspace(dp, lqt.CALL_SCAN_VALUE)
+    ws_t = lqt.workspace(dp, lqt.CALL_FORWARD_TRAJ)
+    ms_scan = _events_time(lambda: lqt.scan_value(dp, out["elts"], S, v, ws_v), max(3, args.steps // 2), torch)
+    ms_traj = _events_time(lambda: lqt.forward_traj(dp, out["elts"], S, v, out["x"], out["u"], ws_t),
+                           max(3, args.steps // 2), torch)
+
+    rec = {
+        "metric": "sub-intervals/s for full LQT solve (value+trajectory) at nx=4",
+        "value": T / (ms * 1e-3),
+        "unit": "sub-intervals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"point-mass LQT tracking, nx=4 nu=2, T={T} blocks x {n} RK4 steps on [0,10], "
+                               f"single problem, elements + value scan + trajectory scan",
+                   "T": T, "nx": 4, "nu": 2, "n_steps": n, "batch": 1, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": "k_build (element build)", "achieved": achieved,
+                     "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+                     "flops_per_launch": flops, "launch_ms": ms_build,
+                     "algorithmic_bytes_per_launch": build_bytes_per_block(4, n, es) * T},
+        "stages_ms": {"build_elements": ms_build, "scan_value": ms_scan, "forward_traj": ms_traj},
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(T, args.cpu_seconds)
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+def _kernel_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("lane_math.hpp", "lqt_lane.hip"):
+        with open(os.path.join(ROOT, "paper_2212_11744_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    sys.exit(main())

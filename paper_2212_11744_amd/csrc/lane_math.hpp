@@ -39,6 +39,21 @@ struct Lay {
   static constexpr int NM = N * N + N;  // affine map record: Psi - I, then alpha
 };
 
+// Tiled structure-of-arrays: records of NQ values for items k = 0..n-1 are stored in tiles of
+// kTile = 256 items.  Lane l of the wave that owns a tile handles the kChunk = 4 consecutive
+// items 4 l + j (j = 0..3), so inside a tile value q of item k sits at row q, column
+// 64 j + l:  index = (k / 256) * NQ * 256 + q * 256 + 64 (k % 4) + (k % 256) / 4.
+// A wave access to "item j of every lane" is then one contiguous 512-byte row (FP64), whether
+// lanes own one item each (build) or four (serial sweeps).
+constexpr int kTile = 256;
+constexpr int kChunk = 4;  // items per lane in every serial sweep (kTile = 64 * kChunk)
+
+template <int NQ>
+LQT_DEV long tix(int q, long k) {
+  return (k >> 8) * (NQ * (long)kTile) + (long)q * kTile + ((k & 3) << 6) + ((k & 255) >> 2);
+}
+
+
 // Conditional value function parameters (A - I, b, C, eta, J) of one interval.
 template <int N, class R>
 struct Tup {
@@ -73,37 +88,37 @@ LQT_DEV void tup_identity(Tup<N, R>& x) {
 }
 
 template <int N, class R>
-LQT_DEV void tup_load(Tup<N, R>& x, const R* __restrict__ base, long stride, long k) {
+LQT_DEV void tup_load(Tup<N, R>& x, const R* __restrict__ base, long k) {
   using L = Lay<N>;
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < N; ++j) x.A[i][j] = base[(L::A + i * N + j) * stride + k];
+    for (int j = 0; j < N; ++j) x.A[i][j] = base[tix<L::NE>(L::A + i * N + j, k)];
 #pragma unroll
-  for (int i = 0; i < N; ++i) x.b[i] = base[(L::B + i) * stride + k];
+  for (int i = 0; i < N; ++i) x.b[i] = base[tix<L::NE>(L::B + i, k)];
 #pragma unroll
-  for (int i = 0; i < Sym<N>::size; ++i) x.C[i] = base[(L::C + i) * stride + k];
+  for (int i = 0; i < Sym<N>::size; ++i) x.C[i] = base[tix<L::NE>(L::C + i, k)];
 #pragma unroll
-  for (int i = 0; i < N; ++i) x.e[i] = base[(L::E + i) * stride + k];
+  for (int i = 0; i < N; ++i) x.e[i] = base[tix<L::NE>(L::E + i, k)];
 #pragma unroll
-  for (int i = 0; i < Sym<N>::size; ++i) x.J[i] = base[(L::J + i) * stride + k];
+  for (int i = 0; i < Sym<N>::size; ++i) x.J[i] = base[tix<L::NE>(L::J + i, k)];
 }
 
 template <int N, class R>
-LQT_DEV void tup_store(const Tup<N, R>& x, R* __restrict__ base, long stride, long k) {
+LQT_DEV void tup_store(const Tup<N, R>& x, R* __restrict__ base, long k) {
   using L = Lay<N>;
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < N; ++j) base[(L::A + i * N + j) * stride + k] = x.A[i][j];
+    for (int j = 0; j < N; ++j) base[tix<L::NE>(L::A + i * N + j, k)] = x.A[i][j];
 #pragma unroll
-  for (int i = 0; i < N; ++i) base[(L::B + i) * stride + k] = x.b[i];
+  for (int i = 0; i < N; ++i) base[tix<L::NE>(L::B + i, k)] = x.b[i];
 #pragma unroll
-  for (int i = 0; i < Sym<N>::size; ++i) base[(L::C + i) * stride + k] = x.C[i];
+  for (int i = 0; i < Sym<N>::size; ++i) base[tix<L::NE>(L::C + i, k)] = x.C[i];
 #pragma unroll
-  for (int i = 0; i < N; ++i) base[(L::E + i) * stride + k] = x.e[i];
+  for (int i = 0; i < N; ++i) base[tix<L::NE>(L::E + i, k)] = x.e[i];
 #pragma unroll
-  for (int i = 0; i < Sym<N>::size; ++i) base[(L::J + i) * stride + k] = x.J[i];
+  for (int i = 0; i < Sym<N>::size; ++i) base[tix<L::NE>(L::J + i, k)] = x.J[i];
 }
 
 // Solve M X = B in place (B <- M^{-1} B) by Gauss-Jordan elimination with partial pivoting.
@@ -461,22 +476,22 @@ LQT_DEV void aff_apply(const Aff<N, R>& m, R (&x)[N]) {
 }
 
 template <int N, class R>
-LQT_DEV void aff_load(Aff<N, R>& m, const R* __restrict__ base, long stride, long k) {
+LQT_DEV void aff_load(Aff<N, R>& m, const R* __restrict__ base, long k) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) m.P[i][j] = base[(i * N + j) * stride + k];
-    m.q[i] = base[(N * N + i) * stride + k];
+    for (int j = 0; j < N; ++j) m.P[i][j] = base[tix<Lay<N>::NM>(i * N + j, k)];
+    m.q[i] = base[tix<Lay<N>::NM>(N * N + i, k)];
   }
 }
 
 template <int N, class R>
-LQT_DEV void aff_store(const Aff<N, R>& m, R* __restrict__ base, long stride, long k) {
+LQT_DEV void aff_store(const Aff<N, R>& m, R* __restrict__ base, long k) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) base[(i * N + j) * stride + k] = m.P[i][j];
-    base[(N * N + i) * stride + k] = m.q[i];
+    for (int j = 0; j < N; ++j) base[tix<Lay<N>::NM>(i * N + j, k)] = m.P[i][j];
+    base[tix<Lay<N>::NM>(N * N + i, k)] = m.q[i];
   }
 }
 

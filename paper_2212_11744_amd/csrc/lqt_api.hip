@@ -30,30 +30,22 @@ lqt_status ok() {
   return LQT_OK;
 }
 
-int env_int(const char* name, int dflt, int lo, int hi) {
-  const char* s = getenv(name);
-  if (!s || !*s) return dflt;
-  int v = atoi(s);
-  return (v < lo || v > hi) ? dflt : v;
-}
-
 size_t dsize(int dtype) { return dtype == LQT_F64 ? 8 : 4; }
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 long ne_of(int nx) { return 2L * nx * nx + 3L * nx; }
 long nv_of(int nx) { return (long)nx * (nx + 1) / 2 + nx; }
 long nm_of(int nx) { return (long)nx * nx + nx; }
+long padt(long n) { return (n + 255) / 256 * 256; }
 
 }  // namespace
 
-Tree plan_tree(long T, int c0, int c) {
+Tree plan_tree(long T) {
   Tree t;
-  t.c0 = c0;
-  t.c = c;
   t.n[0] = T;
-  t.n[1] = (T + c0 - 1) / c0;
+  t.n[1] = (T + kLaneChunk - 1) / kLaneChunk;
   t.levels = 1;
-  while (t.n[t.levels] > c && t.levels < kMaxLevels) {
-    t.n[t.levels + 1] = (t.n[t.levels] + c - 1) / c;
+  while (t.n[t.levels] > kWaveSpan && t.levels < kMaxLevels) {
+    t.n[t.levels + 1] = (t.n[t.levels] + kWaveSpan - 1) / kWaveSpan;
     ++t.levels;
   }
   return t;
@@ -61,9 +53,7 @@ Tree plan_tree(long T, int c0, int c) {
 
 namespace {
 
-Tree tree_for(const lqt_dims* d) {
-  return plan_tree(d->T, env_int("LQT_CHUNK0", 4, 1, 4096), env_int("LQT_CHUNK", 8, 2, 4096));
-}
+Tree tree_for(const lqt_dims* d) { return plan_tree(d->T); }
 
 // Byte layout of the workspace of one call.  Returns the total; fills w when base != nullptr.
 size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w) {
@@ -81,25 +71,30 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w) {
   const bool want_v = call == LQT_CALL_SCAN_VALUE || call == LQT_CALL_SOLVE;
   const bool want_t = call == LQT_CALL_FORWARD_TRAJ || call == LQT_CALL_SOLVE;
   for (int l = 1; l <= t.levels; ++l) {
+    const long lanes_above = l < t.levels ? t.n[l + 1] * 64 : 0;
     if (want_v) {
-      void* a = take(es * B * ne_of(d->nx) * t.n[l]);
-      void* b = take(es * B * nv_of(d->nx) * t.n[l]);
+      void* a = take(es * B * ne_of(d->nx) * padt(t.n[l]));
+      void* b = take(es * B * nv_of(d->nx) * padt(t.n[l]));
+      void* c = lanes_above ? take(es * B * ne_of(d->nx) * padt(lanes_above)) : nullptr;
       if (w) {
         w->vtup[l] = a;
         w->vval[l] = b;
+        w->vpart[l] = c;
       }
     }
     if (want_t) {
-      void* a = take(es * B * nm_of(d->nx) * t.n[l]);
-      void* b = take(es * B * d->nx * t.n[l]);
+      void* a = take(es * B * nm_of(d->nx) * padt(t.n[l]));
+      void* b = take(es * B * d->nx * padt(t.n[l]));
+      void* c = lanes_above ? take(es * B * nm_of(d->nx) * padt(lanes_above)) : nullptr;
       if (w) {
         w->tmap[l] = a;
         w->tx[l] = b;
+        w->tpart[l] = c;
       }
     }
   }
   if (call == LQT_CALL_SOLVE) {
-    void* e = take(es * B * ne_of(d->nx) * (size_t)d->T);
+    void* e = take(es * B * ne_of(d->nx) * (size_t)padt(d->T));
     if (w) w->elts = e;
   }
   return off;
@@ -199,17 +194,19 @@ KProb make_kprob(const lqt_dims* d, const lqt_problem* p, const void* consts) {
   return k;
 }
 
-// Value tree over elements: upward products, top fold, downward values, then the values of every
-// block (and, when maps1 != nullptr, level 1 of the trajectory tree).
+// Value tree over elements: upward products, top sweep from the terminal element, downward
+// values, then the values of every block (and, when maps1 != nullptr, level 1 of the trajectory
+// tree).
+// level1_ready: level 1 was produced together with the elements (fused build).
 lqt_status run_value(const Ops* o, const KProb& kp, const Tree& t, const Work& w, const void* elts,
-                     void* S, void* v, void* maps1, hipStream_t s) {
-  LQT_HIP(o->vreduce(kp, elts, t.n[0], w.vtup[1], t.n[1], t.c0, s));
+                     void* S, void* v, void* maps1, bool level1_ready, hipStream_t s) {
+  if (!level1_ready) LQT_HIP(o->vreduce0(kp, elts, w.vtup[1], t.n[1], s));
   for (int l = 1; l < t.levels; ++l)
-    LQT_HIP(o->vreduce(kp, w.vtup[l], t.n[l], w.vtup[l + 1], t.n[l + 1], t.c, s));
+    LQT_HIP(o->vup(kp, w.vtup[l], t.n[l], w.vpart[l], w.vtup[l + 1], t.n[l + 1], s));
   LQT_HIP(o->vtop(kp, w.vtup[t.levels], t.n[t.levels], w.vval[t.levels], s));
-  for (int l = t.levels; l > 1; --l)
-    LQT_HIP(o->vdown(kp, w.vtup[l - 1], t.n[l - 1], w.vval[l], t.n[l], w.vval[l - 1], t.c, s));
-  LQT_HIP(o->vbottom(kp, elts, w.vval[1], t.n[1], S, v, maps1, t.c0, s));
+  for (int l = t.levels - 1; l >= 1; --l)
+    LQT_HIP(o->vdown(kp, w.vtup[l], t.n[l], w.vpart[l], w.vval[l + 1], t.n[l + 1], w.vval[l], s));
+  LQT_HIP(o->vbottom(kp, elts, w.vval[1], t.n[1], S, v, maps1, s));
   return LQT_OK;
 }
 
@@ -218,11 +215,11 @@ lqt_status run_value(const Ops* o, const KProb& kp, const Tree& t, const Work& w
 lqt_status run_traj(const Ops* o, const KProb& kp, const Tree& t, const Work& w, const void* elts,
                     const void* S, const void* v, void* x, void* u, hipStream_t s) {
   for (int l = 1; l < t.levels; ++l)
-    LQT_HIP(o->treduce(kp, w.tmap[l], t.n[l], w.tmap[l + 1], t.n[l + 1], t.c, s));
+    LQT_HIP(o->tup(kp, w.tmap[l], t.n[l], w.tpart[l], w.tmap[l + 1], t.n[l + 1], s));
   LQT_HIP(o->ttop(kp, w.tmap[t.levels], t.n[t.levels], w.tx[t.levels], s));
-  for (int l = t.levels; l > 1; --l)
-    LQT_HIP(o->tdown(kp, w.tmap[l - 1], t.n[l - 1], w.tx[l], t.n[l], w.tx[l - 1], t.c, s));
-  LQT_HIP(o->tbottom(kp, elts, S, v, w.tx[1], t.n[1], x, u, t.c0, s));
+  for (int l = t.levels - 1; l >= 1; --l)
+    LQT_HIP(o->tdown(kp, w.tmap[l], t.n[l], w.tpart[l], w.tx[l + 1], t.n[l + 1], w.tx[l], s));
+  LQT_HIP(o->tbottom(kp, elts, S, v, w.tx[1], t.n[1], x, u, s));
   return LQT_OK;
 }
 
@@ -272,7 +269,7 @@ lqt_status lqt_scan_value(const lqt_dims* dims, const void* elts, const void* Qf
   p.Qf = Qf;
   p.rf = rf;
   KProb kp = make_kprob(dims, &p, w.consts);
-  LQT_TRY(run_value(o, kp, tree_for(dims), w, elts, S, v, nullptr, stream));
+  LQT_TRY(run_value(o, kp, tree_for(dims), w, elts, S, v, nullptr, false, stream));
   return ok();
 }
 
@@ -296,7 +293,7 @@ lqt_status lqt_forward_traj(const lqt_dims* dims, const lqt_problem* prob, const
   KProb kp = make_kprob(dims, prob, w.consts);
   const Tree t = tree_for(dims);
   LQT_HIP(o->prep(kp, w.consts, stream));
-  LQT_HIP(o->tbottom_reduce(kp, elts, S, v, w.tmap[1], t.n[1], t.c0, stream));
+  LQT_HIP(o->tbottom_reduce(kp, elts, S, v, w.tmap[1], t.n[1], stream));
   LQT_TRY(run_traj(o, kp, t, w, elts, S, v, x, u, stream));
   return ok();
 }
@@ -318,8 +315,14 @@ lqt_status lqt_solve(const lqt_dims* dims, const lqt_problem* prob, void* elts, 
   const Tree t = tree_for(dims);
   void* e = elts ? elts : w.elts;
   LQT_HIP(o->prep(kp, w.consts, stream));
-  LQT_HIP(o->build(kp, e, stream));
-  LQT_TRY(run_value(o, kp, t, w, e, S, v, w.tmap[1], stream));
+  // FP32 builds its elements and level 1 of the value tree in one kernel; in FP64 the fused
+  // kernel exceeds the register file, so the build and the level-1 products run separately.
+  const bool fused = dims->dtype == LQT_F32;
+  if (fused)
+    LQT_HIP(o->build_reduce(kp, e, w.vtup[1], t.n[1], stream));
+  else
+    LQT_HIP(o->build(kp, e, stream));
+  LQT_TRY(run_value(o, kp, t, w, e, S, v, w.tmap[1], fused, stream));
   LQT_TRY(run_traj(o, kp, t, w, e, S, v, x, u, stream));
   return ok();
 }

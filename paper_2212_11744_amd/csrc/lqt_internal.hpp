@@ -30,48 +30,56 @@ __host__ __device__ inline int consts_off_W(int nx, int nu) { return nx * nx + 2
 __host__ __device__ inline int consts_off_Rinv(int nx, int nu) { return nx * nx + 2 * nx * nu + nu * nu; }
 __host__ __device__ inline int consts_count(int nx, int nu) { return nx * nx + 2 * nx * nu + 2 * nu * nu; }
 
-// Level sizes of the reduce-then-fold trees: n[0] = T (blocks), n[1] = ceil(T / c0),
-// n[l+1] = ceil(n[l] / c) while n[l] > c; level `levels` is the top, swept by one thread.
+// Tree shape of the scans: n[0] = T blocks; level 1 has ceil(T / 4) nodes (4 blocks per lane);
+// level l + 1 has ceil(n[l] / 256) nodes (4 nodes per lane, 64 lanes per wave) while n[l] > 256;
+// level `levels` (<= 256 nodes) is swept by one wavefront.
+constexpr int kLaneChunk = 4;
+constexpr int kWaveSpan = 256;
+
 struct Tree {
-  int c0 = 4, c = 8;
   int levels = 0;
   long n[kMaxLevels + 1] = {};
 };
 
-Tree plan_tree(long T, int c0, int c);
+Tree plan_tree(long T);
 
-// Workspace pointers of one call (all per-level arrays hold `batch` problems back to back).
+// Workspace pointers of one call (all per-level arrays hold `batch` problems back to back, each in
+// tiles of 256 items).
 struct Work {
   void* consts = nullptr;
-  void* vtup[kMaxLevels + 1] = {};  // value tree: tuples at level l >= 1 [batch][NE][n_l]
-  void* vval[kMaxLevels + 1] = {};  // value tree: (packed S, v) at right ends [batch][NV][n_l]
-  void* tmap[kMaxLevels + 1] = {};  // trajectory tree: affine maps [batch][NM][n_l]
-  void* tx[kMaxLevels + 1] = {};    // trajectory tree: x at left ends [batch][nx][n_l]
-  void* elts = nullptr;             // elements when the caller gives none (lqt_solve)
+  void* vtup[kMaxLevels + 1] = {};   // value tree: tuples at level l >= 1
+  void* vval[kMaxLevels + 1] = {};   // value tree: (packed S, v) at right ends of level-l nodes
+  void* vpart[kMaxLevels + 1] = {};  // value tree: lane partials of the wave trees above level l
+  void* tmap[kMaxLevels + 1] = {};   // trajectory tree: affine maps at level l
+  void* tx[kMaxLevels + 1] = {};     // trajectory tree: x at left ends of level-l nodes
+  void* tpart[kMaxLevels + 1] = {};  // trajectory tree: lane partials above level l
+  void* elts = nullptr;              // elements when the caller gives none (lqt_solve)
 };
 
 // Kernel launchers of one (nx, nu, dtype) instantiation.  Each returns hipGetLastError().
 struct Ops {
   hipError_t (*prep)(const KProb&, void* consts, hipStream_t);
   hipError_t (*build)(const KProb&, void* elts, hipStream_t);
+  hipError_t (*build_reduce)(const KProb&, void* elts, void* lvl1, long n1, hipStream_t);
   // value tree
-  hipError_t (*vreduce)(const KProb&, const void* src, long n_src, void* dst, long n_dst, int c,
-                        hipStream_t);
+  hipError_t (*vreduce0)(const KProb&, const void* elts, void* lvl1, long n1, hipStream_t);
+  hipError_t (*vup)(const KProb&, const void* src, long n_src, void* part, void* dst, long n_dst,
+                    hipStream_t);
   hipError_t (*vtop)(const KProb&, const void* tup, long n, void* val, hipStream_t);
-  hipError_t (*vdown)(const KProb&, const void* tup, long n_child, const void* val_in, long n_par,
-                      void* val_out, int c, hipStream_t);
+  hipError_t (*vdown)(const KProb&, const void* tup, long n_child, const void* part,
+                      const void* val_par, long n_par, void* val_child, hipStream_t);
   hipError_t (*vbottom)(const KProb&, const void* elts, const void* val1, long n1, void* S,
-                        void* v, void* maps1, int c0, hipStream_t);
+                        void* v, void* maps1, hipStream_t);
   // trajectory tree
   hipError_t (*tbottom_reduce)(const KProb&, const void* elts, const void* S, const void* v,
-                               void* maps1, long n1, int c0, hipStream_t);
-  hipError_t (*treduce)(const KProb&, const void* src, long n_src, void* dst, long n_dst, int c,
-                        hipStream_t);
+                               void* maps1, long n1, hipStream_t);
+  hipError_t (*tup)(const KProb&, const void* src, long n_src, void* part, void* dst, long n_dst,
+                    hipStream_t);
   hipError_t (*ttop)(const KProb&, const void* maps, long n, void* xs, hipStream_t);
-  hipError_t (*tdown)(const KProb&, const void* maps, long n_child, const void* x_in, long n_par,
-                      void* x_out, int c, hipStream_t);
+  hipError_t (*tdown)(const KProb&, const void* maps, long n_child, const void* part,
+                      const void* x_par, long n_par, void* x_child, hipStream_t);
   hipError_t (*tbottom)(const KProb&, const void* elts, const void* S, const void* v,
-                        const void* x1, long n1, void* x, void* u, int c0, hipStream_t);
+                        const void* x1, long n1, void* x, void* u, hipStream_t);
 };
 
 // Instantiations for 1 <= nu <= nx <= 4 (one tuple per lane); nullptr if not available.

@@ -5,16 +5,24 @@
 //
 // Stages:
 //   k_build        element build: Theorem 8 (Sec. IV-B) integrated with classical RK4.
-//   k_vreduce      value tree, upward: chunk products a_j (x) ... (x) a_{j+c-1} (Lemma 7).
-//   k_vtop         value tree, top: fold of the top nodes from the terminal element (Sec. IV-D).
-//   k_vdown        value tree, downward: value at the right end of every child.
+//   k_vreduce0     value tree, level 1: products a_j (x) ... (x) a_{j+3} of 4 blocks per lane
+//                  (Lemma 7).
+//   k_vup          value tree, upper levels: 4 nodes per lane, then a wavefront tree (256 nodes
+//                  per wave); lane partials are kept for the downward pass.
+//   k_vtop         value tree, top (<= 256 nodes, one wave): up-sweep, then the downward pass
+//                  from the terminal element (Sec. IV-D).
+//   k_vdown        value tree, downward: value at the right end of every child node.
 //   k_vbottom      values S_k, v_k of every block (Theorem 6), optionally with the level-1
 //                  products of the closed-loop block maps for the trajectory.
-//   k_tbottom_reduce / k_treduce / k_ttop / k_tdown / k_tbottom
+//   k_tbottom_reduce / k_tup / k_ttop / k_tdown / k_tbottom
 //                  trajectory: composition scan of the block maps x_{k+1} = Psi_k x_k + alpha_k
-//                  (Method 1, Sec. IV-E), and the control law u_k (Sec. II-B).
+//                  (Method 1, Sec. IV-E) with the same tree shape, and the control law u_k
+//                  (Sec. II-B).
+// Tree shape: level 1 has ceil(T / 4) nodes (4 blocks per lane); level l + 1 has
+// ceil(n_l / 256) nodes while n_l > 256; the top level (<= 256 nodes) is one wave.
 #include "lane_math.hpp"
 #include "lqt_internal.hpp"
+#include "wave_tree.hpp"
 
 namespace lqt {
 namespace {
@@ -26,6 +34,7 @@ struct CS {
 };
 
 __device__ inline long gid() { return (long)blockIdx.x * blockDim.x + threadIdx.x; }
+__host__ __device__ inline long padt(long n) { return (n + kTile - 1) / kTile * kTile; }
 
 // ------------------------------------------------------------------------------------------
 // Element build (Theorem 8):
@@ -37,13 +46,10 @@ __device__ inline long gid() { return (long)blockIdx.x * blockDim.x + threadIdx.
 // constant and c = 0 (their values are then wave-uniform and stay in scalar registers).
 // ------------------------------------------------------------------------------------------
 template <int N, int NU, class R, bool CONST_COEF>
-__global__ __launch_bounds__(kThreads) void k_build(const KProb kp, R* __restrict__ elts) {
+LQT_DEV void build_block(const KProb& kp, int p, long k, Tup<N, R>& out) {
   using Y = Sym<N>;
   constexpr int NS = Y::size;
-  const int p = blockIdx.y;
   const long T = kp.T;
-  const long k = gid();
-  if (k >= T) return;
   const int n = kp.n;
   const long nsamp = 2L * n * T + 1;
   const R* __restrict__ t = (const R*)kp.t + p * (T + 1);
@@ -213,7 +219,7 @@ __global__ __launch_bounds__(kThreads) void k_build(const KProb kp, R* __restric
 #pragma unroll
         for (int l = 0; l < N; ++l) {
           s = fma(K[l][i], se[l], s);
-          s = fma(sJ[Y::at(i, l)], cv[l], s);
+          if (!CONST_COEF) s = fma(sJ[Y::at(i, l)], cv[l], s);
           s = fma(-Q[i][l], rv[l], s);
         }
         ke[i] = s;
@@ -268,7 +274,6 @@ __global__ __launch_bounds__(kThreads) void k_build(const KProb kp, R* __restric
     for (int i = 0; i < NS; ++i) yJ[i] = aJ[i];
   }
 
-  Tup<N, R> out;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
 #pragma unroll
@@ -281,45 +286,89 @@ __global__ __launch_bounds__(kThreads) void k_build(const KProb kp, R* __restric
     out.C[i] = yC[i];
     out.J[i] = yJ[i];
   }
-  tup_store(out, elts + (long)p * Lay<N>::NE * T, T, k);
+}
+
+template <int N, int NU, class R, bool CONST_COEF>
+__global__ __launch_bounds__(kThreads) void k_build(const KProb kp, R* __restrict__ elts) {
+  const int p = blockIdx.y;
+  const long k = gid();
+  if (k >= kp.T) return;
+  Tup<N, R> out;
+  build_block<N, NU, R, CONST_COEF>(kp, p, k, out);
+  tup_store(out, elts + (long)p * Lay<N>::NE * padt(kp.T), k);
+}
+
+// Element build fused with level 1 of the value tree: lane i builds its 4 blocks from the last to
+// the first, stores each element and folds it into the running product a_k (x) ... (x) a_{4i+3}.
+template <int N, int NU, class R, bool CONST_COEF>
+__global__ __launch_bounds__(kThreads) void k_build_reduce(const KProb kp, R* __restrict__ elts,
+                                                            R* __restrict__ lvl1, long n1) {
+  const int p = blockIdx.y;
+  const long i = gid();
+  if (i >= n1) return;
+  const long T = kp.T;
+  R* ep = elts + (long)p * Lay<N>::NE * padt(T);
+  const long j0 = i * kChunk, j1 = min(j0 + kChunk, T);
+  Tup<N, R> acc;
+  build_block<N, NU, R, CONST_COEF>(kp, p, j1 - 1, acc);
+  tup_store(acc, ep, j1 - 1);
+  for (long k = j1 - 2; k >= j0; --k) {
+    Tup<N, R> a;
+    build_block<N, NU, R, CONST_COEF>(kp, p, k, a);
+    tup_store(a, ep, k);
+    combine(a, acc, acc);
+  }
+  tup_store(acc, lvl1 + (long)p * Lay<N>::NE * padt(n1), i);
 }
 
 // ------------------------------------------------------------------------------------------
 // Value tree.
 // ------------------------------------------------------------------------------------------
+// Serial product of the <= 4 nodes [j0, j1) of src (right to left), the next tuple's loads issued
+// before the current combination so that memory latency overlaps arithmetic.
 template <int N, class R>
-__global__ __launch_bounds__(kThreads) void k_vreduce(const R* __restrict__ src, long n_src,
-                                                       R* __restrict__ dst, long n_dst, int c) {
-  const int p = blockIdx.y;
-  const long i = gid();
-  if (i >= n_dst) return;
-  const R* s = src + (long)p * Lay<N>::NE * n_src;
-  const long j0 = i * c;
-  const long j1 = min(j0 + c, n_src);
-  Tup<N, R> acc;
-  tup_load(acc, s, n_src, j1 - 1);
+LQT_DEV void serial_product(const R* __restrict__ s, long j0, long j1, Tup<N, R>& acc) {
+  if (j0 >= j1) {
+    tup_identity(acc);
+    return;
+  }
+  tup_load(acc, s, j1 - 1);
+  if (j1 - 2 < j0) return;
+  Tup<N, R> nxt;
+  tup_load(nxt, s, j1 - 2);
   for (long j = j1 - 2; j >= j0; --j) {
-    Tup<N, R> x;
-    tup_load(x, s, n_src, j);
+    Tup<N, R> x = nxt;
+    if (j - 1 >= j0) tup_load(nxt, s, j - 1);
     combine(x, acc, acc);
   }
-  tup_store(acc, dst + (long)p * Lay<N>::NE * n_dst, n_dst, i);
 }
 
 template <int N, class R>
-LQT_DEV void val_store(const R (&S)[Sym<N>::size], const R (&v)[N], R* base, long stride, long i) {
-#pragma unroll
-  for (int q = 0; q < Sym<N>::size; ++q) base[q * stride + i] = S[q];
-#pragma unroll
-  for (int q = 0; q < N; ++q) base[(Sym<N>::size + q) * stride + i] = v[q];
+__global__ __launch_bounds__(kThreads) void k_vreduce0(const R* __restrict__ elts, long T,
+                                                        R* __restrict__ dst, long n1) {
+  const int p = blockIdx.y;
+  const long i = gid();
+  if (i >= n1) return;
+  Tup<N, R> acc;
+  serial_product(elts + (long)p * Lay<N>::NE * padt(T), i * kChunk, min(i * kChunk + kChunk, T),
+                 acc);
+  tup_store(acc, dst + (long)p * Lay<N>::NE * padt(n1), i);
 }
 
 template <int N, class R>
-LQT_DEV void val_load(R (&S)[Sym<N>::size], R (&v)[N], const R* base, long stride, long i) {
+LQT_DEV void val_store(const R (&S)[Sym<N>::size], const R (&v)[N], R* base, long i) {
 #pragma unroll
-  for (int q = 0; q < Sym<N>::size; ++q) S[q] = base[q * stride + i];
+  for (int q = 0; q < Sym<N>::size; ++q) base[tix<Lay<N>::NV>(q, i)] = S[q];
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] = base[(Sym<N>::size + q) * stride + i];
+  for (int q = 0; q < N; ++q) base[tix<Lay<N>::NV>(Sym<N>::size + q, i)] = v[q];
+}
+
+template <int N, class R>
+LQT_DEV void val_load(R (&S)[Sym<N>::size], R (&v)[N], const R* base, long i) {
+#pragma unroll
+  for (int q = 0; q < Sym<N>::size; ++q) S[q] = base[tix<Lay<N>::NV>(q, i)];
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = base[tix<Lay<N>::NV>(Sym<N>::size + q, i)];
 }
 
 // Terminal value (S, v) = (Qf, Qf rf) of the terminal element (Sec. IV-D).
@@ -338,46 +387,74 @@ LQT_DEV void terminal_value(const KProb& kp, int p, R (&S)[Sym<N>::size], R (&v)
   }
 }
 
+// Serial downward sweep over the <= 4 nodes [j0, j1): node j receives the value at its right end,
+// then the value is folded through node j (right to left).
 template <int N, class R>
-__global__ __launch_bounds__(kThreads) void k_vtop(const KProb kp, const R* __restrict__ tup,
-                                                    long n, R* __restrict__ val) {
-  const int p = blockIdx.y;
-  if (threadIdx.x != 0) return;
-  const R* tp = tup + (long)p * Lay<N>::NE * n;
-  R* vp = val + (long)p * Lay<N>::NV * n;
-  R S[Sym<N>::size], v[N];
-  terminal_value<N, R>(kp, p, S, v);
-  for (long j = n - 1; j >= 0; --j) {
-    val_store<N, R>(S, v, vp, n, j);
-    if (j == 0) break;
+LQT_DEV void serial_values(const R* __restrict__ tp, long j0, long j1, R (&S)[Sym<N>::size],
+                           R (&v)[N], R* __restrict__ vo) {
+  for (long j = j1 - 1; j >= j0; --j) {
+    val_store<N, R>(S, v, vo, j);
+    if (j == j0) break;
     Tup<N, R> a;
-    tup_load(a, tp, n, j);
+    tup_load(a, tp, j);
     Aff<N, R> m;
     fold(a, S, v, m);
   }
 }
 
+// Upper level: lanes own 4 consecutive nodes, a wave 256; one output node per wave.
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_vup(const R* __restrict__ src, long n_src,
+                                                   R* __restrict__ part, R* __restrict__ dst,
+                                                   long n_dst) {
+  const int p = blockIdx.y;
+  const long gl = gid();
+  const int lane = threadIdx.x & 63;
+  const long w = gl >> 6;
+  if (w >= n_dst) return;
+  const long j0 = gl * kChunk, j1 = min(j0 + kChunk, n_src);
+  Tup<N, R> P;
+  serial_product(src + (long)p * Lay<N>::NE * padt(n_src), j0, j1, P);
+  wave_up_value(P, lane);
+  tup_store(P, part + (long)p * Lay<N>::NE * padt(n_dst * 64), gl);
+  if (lane == 0) tup_store(P, dst + (long)p * Lay<N>::NE * padt(n_dst), w);
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_vtop(const KProb kp, const R* __restrict__ tup,
+                                                    long n, R* __restrict__ val) {
+  const int p = blockIdx.y;
+  const int lane = threadIdx.x;
+  const R* tp = tup + (long)p * Lay<N>::NE * padt(n);
+  const long j0 = (long)lane * kChunk, j1 = min(j0 + kChunk, n);
+  const int levels = tree_levels((n + kChunk - 1) / kChunk);
+  Tup<N, R> P;
+  serial_product(tp, j0, j1, P);
+  wave_up_value(P, lane, levels);
+  R S[Sym<N>::size], v[N];
+  terminal_value<N, R>(kp, p, S, v);
+  wave_down_value(P, S, v, lane, levels);
+  serial_values<N, R>(tp, j0, j1, S, v, val + (long)p * Lay<N>::NV * padt(n));
+}
+
 template <int N, class R>
 __global__ __launch_bounds__(kThreads) void k_vdown(const R* __restrict__ tup, long n_child,
-                                                     const R* __restrict__ val_in, long n_par,
-                                                     R* __restrict__ val_out, int c) {
+                                                     const R* __restrict__ part,
+                                                     const R* __restrict__ val_par, long n_par,
+                                                     R* __restrict__ val_child) {
   const int p = blockIdx.y;
-  const long i = gid();
-  if (i >= n_par) return;
-  const R* tp = tup + (long)p * Lay<N>::NE * n_child;
-  R* vo = val_out + (long)p * Lay<N>::NV * n_child;
+  const long gl = gid();
+  const int lane = threadIdx.x & 63;
+  const long w = gl >> 6;
+  if (w >= n_par) return;
   R S[Sym<N>::size], v[N];
-  val_load<N, R>(S, v, val_in + (long)p * Lay<N>::NV * n_par, n_par, i);
-  const long j0 = i * c;
-  const long j1 = min(j0 + c, n_child);
-  for (long j = j1 - 1; j >= j0; --j) {
-    val_store<N, R>(S, v, vo, n_child, j);
-    if (j == j0) break;
-    Tup<N, R> a;
-    tup_load(a, tp, n_child, j);
-    Aff<N, R> m;
-    fold(a, S, v, m);
-  }
+  val_load<N, R>(S, v, val_par + (long)p * Lay<N>::NV * padt(n_par), w);
+  Tup<N, R> P;
+  tup_load(P, part + (long)p * Lay<N>::NE * padt(n_par * 64), gl);
+  wave_down_value(P, S, v, lane);
+  const long j0 = gl * kChunk, j1 = min(j0 + kChunk, n_child);
+  serial_values<N, R>(tup + (long)p * Lay<N>::NE * padt(n_child), j0, j1, S, v,
+                      val_child + (long)p * Lay<N>::NV * padt(n_child));
 }
 
 template <int N, class R>
@@ -396,25 +473,25 @@ LQT_DEV void S_load_upper(R (&S)[Sym<N>::size], const R* src) {
     for (int j = i; j < N; ++j) S[Sym<N>::at(i, j)] = src[i * N + j];
 }
 
-// Values of every block: S_k, v_k for k in chunk i, folded from the value at the chunk's right end.
-// maps1 (optional): the product of the chunk's closed-loop block maps, level 1 of the trajectory
-// tree (the maps come out of the fold for free).
+// Values of every block: S_k, v_k for the 4 blocks of lane i, folded from the value at the right
+// end of its level-1 node.  maps1 (optional): the composition of the lane's closed-loop block maps,
+// level 1 of the trajectory tree (the maps come out of the fold for free).
 template <int N, class R>
 __global__ __launch_bounds__(kThreads) void k_vbottom(const KProb kp, const R* __restrict__ elts,
                                                        const R* __restrict__ val1, long n1,
                                                        R* __restrict__ Sout, R* __restrict__ vout,
-                                                       R* __restrict__ maps1, int c0) {
+                                                       R* __restrict__ maps1) {
   const int p = blockIdx.y;
   const long i = gid();
   if (i >= n1) return;
   const long T = kp.T;
-  const R* ep = elts + (long)p * Lay<N>::NE * T;
+  const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
   R* Sp = Sout + (long)p * (T + 1) * N * N;
   R* vp = vout + (long)p * (T + 1) * N;
   R S[Sym<N>::size], v[N];
-  val_load<N, R>(S, v, val1 + (long)p * Lay<N>::NV * n1, n1, i);
-  const long j0 = i * c0;
-  const long j1 = min(j0 + c0, T);
+  val_load<N, R>(S, v, val1 + (long)p * Lay<N>::NV * padt(n1), i);
+  const long j0 = i * kChunk;
+  const long j1 = min(j0 + kChunk, T);
   if (j1 == T) {
     S_store_full<N, R>(S, Sp + T * N * N);
 #pragma unroll
@@ -422,9 +499,11 @@ __global__ __launch_bounds__(kThreads) void k_vbottom(const KProb kp, const R* _
   }
   Aff<N, R> acc;
   aff_identity(acc);
+  Tup<N, R> nxt;
+  tup_load(nxt, ep, j1 - 1);
   for (long k = j1 - 1; k >= j0; --k) {
-    Tup<N, R> a;
-    tup_load(a, ep, T, k);
+    Tup<N, R> a = nxt;
+    if (k - 1 >= j0) tup_load(nxt, ep, k - 1);
     Aff<N, R> m;
     fold(a, S, v, m);
     S_store_full<N, R>(S, Sp + k * N * N);
@@ -432,24 +511,23 @@ __global__ __launch_bounds__(kThreads) void k_vbottom(const KProb kp, const R* _
     for (int q = 0; q < N; ++q) vp[k * N + q] = v[q];
     if (maps1) aff_after(acc, m);
   }
-  if (maps1) aff_store(acc, maps1 + (long)p * Lay<N>::NM * n1, n1, i);
+  if (maps1) aff_store(acc, maps1 + (long)p * Lay<N>::NM * padt(n1), i);
 }
 
 // ------------------------------------------------------------------------------------------
 // Trajectory tree.
 // ------------------------------------------------------------------------------------------
 template <int N, class R>
-LQT_DEV void elt_map_part(const R* ep, long T, long k, R (&Ad)[N][N], R (&b)[N],
-                          R (&C)[Sym<N>::size]) {
+LQT_DEV void elt_map_part(const R* ep, long k, R (&Ad)[N][N], R (&b)[N], R (&C)[Sym<N>::size]) {
   using L = Lay<N>;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) Ad[i][j] = ep[(L::A + i * N + j) * T + k];
-    b[i] = ep[(L::B + i) * T + k];
+    for (int j = 0; j < N; ++j) Ad[i][j] = ep[tix<L::NE>(L::A + i * N + j, k)];
+    b[i] = ep[tix<L::NE>(L::B + i, k)];
   }
 #pragma unroll
-  for (int q = 0; q < Sym<N>::size; ++q) C[q] = ep[(L::C + q) * T + k];
+  for (int q = 0; q < Sym<N>::size; ++q) C[q] = ep[tix<L::NE>(L::C + q, k)];
 }
 
 template <int N, class R>
@@ -457,22 +535,21 @@ __global__ __launch_bounds__(kThreads) void k_tbottom_reduce(const KProb kp,
                                                               const R* __restrict__ elts,
                                                               const R* __restrict__ Sg,
                                                               const R* __restrict__ vg,
-                                                              R* __restrict__ maps1, long n1,
-                                                              int c0) {
+                                                              R* __restrict__ maps1, long n1) {
   const int p = blockIdx.y;
   const long i = gid();
   if (i >= n1) return;
   const long T = kp.T;
-  const R* ep = elts + (long)p * Lay<N>::NE * T;
+  const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
   const R* Sp = Sg + (long)p * (T + 1) * N * N;
   const R* vp = vg + (long)p * (T + 1) * N;
-  const long j0 = i * c0;
-  const long j1 = min(j0 + c0, T);
+  const long j0 = i * kChunk;
+  const long j1 = min(j0 + kChunk, T);
   Aff<N, R> acc;
   aff_identity(acc);
   for (long k = j0; k < j1; ++k) {
     R Ad[N][N], b[N], C[Sym<N>::size], S[Sym<N>::size], v[N];
-    elt_map_part<N, R>(ep, T, k, Ad, b, C);
+    elt_map_part<N, R>(ep, k, Ad, b, C);
     S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
 #pragma unroll
     for (int q = 0; q < N; ++q) v[q] = vp[(k + 1) * N + q];
@@ -480,70 +557,92 @@ __global__ __launch_bounds__(kThreads) void k_tbottom_reduce(const KProb kp,
     block_map<N, R>(Ad, b, C, S, v, m);
     aff_then(acc, m);
   }
-  aff_store(acc, maps1 + (long)p * Lay<N>::NM * n1, n1, i);
+  aff_store(acc, maps1 + (long)p * Lay<N>::NM * padt(n1), i);
 }
 
 template <int N, class R>
-__global__ __launch_bounds__(kThreads) void k_treduce(const R* __restrict__ src, long n_src,
-                                                       R* __restrict__ dst, long n_dst, int c) {
-  const int p = blockIdx.y;
-  const long i = gid();
-  if (i >= n_dst) return;
-  const R* s = src + (long)p * Lay<N>::NM * n_src;
-  const long j0 = i * c;
-  const long j1 = min(j0 + c, n_src);
-  Aff<N, R> acc;
-  aff_load(acc, s, n_src, j0);
+LQT_DEV void serial_compose(const R* __restrict__ s, long j0, long j1, Aff<N, R>& acc) {
+  if (j0 >= j1) {
+    aff_identity(acc);
+    return;
+  }
+  aff_load(acc, s, j0);
   for (long j = j0 + 1; j < j1; ++j) {
     Aff<N, R> m;
-    aff_load(m, s, n_src, j);
+    aff_load(m, s, j);
     aff_then(acc, m);
   }
-  aff_store(acc, dst + (long)p * Lay<N>::NM * n_dst, n_dst, i);
+}
+
+// Serial forward sweep over the <= 4 nodes [j0, j1): node j receives the state at its left end,
+// then the state is carried through node j's map.
+template <int N, class R>
+LQT_DEV void serial_states(const R* __restrict__ mp, long j0, long j1, R (&x)[N],
+                           R* __restrict__ xo) {
+  for (long j = j0; j < j1; ++j) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) xo[tix<N>(q, j)] = x[q];
+    if (j == j1 - 1) break;
+    Aff<N, R> m;
+    aff_load(m, mp, j);
+    aff_apply(m, x);
+  }
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_tup(const R* __restrict__ src, long n_src,
+                                                   R* __restrict__ part, R* __restrict__ dst,
+                                                   long n_dst) {
+  const int p = blockIdx.y;
+  const long gl = gid();
+  const int lane = threadIdx.x & 63;
+  const long w = gl >> 6;
+  if (w >= n_dst) return;
+  const long j0 = gl * kChunk, j1 = min(j0 + kChunk, n_src);
+  Aff<N, R> P;
+  serial_compose(src + (long)p * Lay<N>::NM * padt(n_src), j0, j1, P);
+  wave_up_traj(P, lane);
+  aff_store(P, part + (long)p * Lay<N>::NM * padt(n_dst * 64), gl);
+  if (lane == 63) aff_store(P, dst + (long)p * Lay<N>::NM * padt(n_dst), w);
 }
 
 template <int N, class R>
 __global__ __launch_bounds__(kThreads) void k_ttop(const KProb kp, const R* __restrict__ maps,
                                                     long n, R* __restrict__ xs) {
   const int p = blockIdx.y;
-  if (threadIdx.x != 0) return;
-  const R* mp = maps + (long)p * Lay<N>::NM * n;
-  R* xp = xs + (long)p * N * n;
+  const int lane = threadIdx.x;
+  const R* mp = maps + (long)p * Lay<N>::NM * padt(n);
+  const long j0 = (long)lane * kChunk, j1 = min(j0 + kChunk, n);
+  const int levels = tree_levels((n + kChunk - 1) / kChunk);
+  Aff<N, R> P;
+  serial_compose(mp, j0, j1, P);
+  wave_up_traj(P, lane, levels);
   R x[N];
 #pragma unroll
   for (int q = 0; q < N; ++q) x[q] = ((const R*)kp.x0)[(long)p * N + q];
-  for (long j = 0; j < n; ++j) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) xp[q * n + j] = x[q];
-    if (j == n - 1) break;
-    Aff<N, R> m;
-    aff_load(m, mp, n, j);
-    aff_apply(m, x);
-  }
+  wave_down_traj(P, x, lane, levels);
+  serial_states<N, R>(mp, j0, j1, x, xs + (long)p * N * padt(n));
 }
 
 template <int N, class R>
 __global__ __launch_bounds__(kThreads) void k_tdown(const R* __restrict__ maps, long n_child,
-                                                     const R* __restrict__ x_in, long n_par,
-                                                     R* __restrict__ x_out, int c) {
+                                                     const R* __restrict__ part,
+                                                     const R* __restrict__ x_par, long n_par,
+                                                     R* __restrict__ x_child) {
   const int p = blockIdx.y;
-  const long i = gid();
-  if (i >= n_par) return;
-  const R* mp = maps + (long)p * Lay<N>::NM * n_child;
-  R* xo = x_out + (long)p * N * n_child;
+  const long gl = gid();
+  const int lane = threadIdx.x & 63;
+  const long w = gl >> 6;
+  if (w >= n_par) return;
   R x[N];
 #pragma unroll
-  for (int q = 0; q < N; ++q) x[q] = x_in[(long)p * N * n_par + q * n_par + i];
-  const long j0 = i * c;
-  const long j1 = min(j0 + c, n_child);
-  for (long j = j0; j < j1; ++j) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) xo[q * n_child + j] = x[q];
-    if (j == j1 - 1) break;
-    Aff<N, R> m;
-    aff_load(m, mp, n_child, j);
-    aff_apply(m, x);
-  }
+  for (int q = 0; q < N; ++q) x[q] = x_par[(long)p * N * padt(n_par) + tix<N>(q, w)];
+  Aff<N, R> P;
+  aff_load(P, part + (long)p * Lay<N>::NM * padt(n_par * 64), gl);
+  wave_down_traj(P, x, lane);
+  const long j0 = gl * kChunk, j1 = min(j0 + kChunk, n_child);
+  serial_states<N, R>(maps + (long)p * Lay<N>::NM * padt(n_child), j0, j1, x,
+                      x_child + (long)p * N * padt(n_child));
 }
 
 // u = -Kc (S x - v) with Kc = R^{-1} L(t_k)^T.
@@ -595,22 +694,21 @@ __global__ __launch_bounds__(kThreads) void k_tbottom(const KProb kp, const R* _
                                                        const R* __restrict__ Sg,
                                                        const R* __restrict__ vg,
                                                        const R* __restrict__ x1, long n1,
-                                                       R* __restrict__ xout, R* __restrict__ uout,
-                                                       int c0) {
+                                                       R* __restrict__ xout, R* __restrict__ uout) {
   const int p = blockIdx.y;
   const long i = gid();
   if (i >= n1) return;
   const long T = kp.T;
-  const R* ep = elts + (long)p * Lay<N>::NE * T;
+  const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
   const R* Sp = Sg + (long)p * (T + 1) * N * N;
   const R* vp = vg + (long)p * (T + 1) * N;
   R* xp = xout + (long)p * (T + 1) * N;
   R* up = uout ? uout + (long)p * (T + 1) * NU : nullptr;
   R x[N];
 #pragma unroll
-  for (int q = 0; q < N; ++q) x[q] = x1[(long)p * N * n1 + q * n1 + i];
-  const long j0 = i * c0;
-  const long j1 = min(j0 + c0, T);
+  for (int q = 0; q < N; ++q) x[q] = x1[(long)p * N * padt(n1) + tix<N>(q, i)];
+  const long j0 = i * kChunk;
+  const long j1 = min(j0 + kChunk, T);
   R S[Sym<N>::size], v[N];
   S_load_upper<N, R>(S, Sp + j0 * N * N);
 #pragma unroll
@@ -625,7 +723,7 @@ __global__ __launch_bounds__(kThreads) void k_tbottom(const KProb kp, const R* _
       control<N, NU, R>(Kc, S, v, x, up + k * NU);
     }
     R Ad[N][N], b[N], C[Sym<N>::size];
-    elt_map_part<N, R>(ep, T, k, Ad, b, C);
+    elt_map_part<N, R>(ep, k, Ad, b, C);
     S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
 #pragma unroll
     for (int q = 0; q < N; ++q) v[q] = vp[(k + 1) * N + q];
@@ -644,28 +742,135 @@ __global__ __launch_bounds__(kThreads) void k_tbottom(const KProb kp, const R* _
 }
 
 // ------------------------------------------------------------------------------------------
+// Per-problem constants (see lqt_internal.hpp), fully unrolled for the sizes of this path:
+// R = Lr Lr^T (Cholesky), W = Lr^{-T}, Rinv = W W^T, Lc = L W, G = Lc Lc^T, Kc = Rinv L^T.
+// ------------------------------------------------------------------------------------------
+template <int N, int NU, class R>
+__global__ __launch_bounds__(kThreads) void k_prep_lane(const KProb kp, R* __restrict__ consts) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kp.batch) return;
+  using C = CS<N, NU>;
+  const R* Rm = (const R*)kp.R + (long)p * NU * NU;
+  R* cs = consts + (long)p * C::size;
+  R Lr[NU][NU], W[NU][NU];
+#pragma unroll
+  for (int i = 0; i < NU; ++i)
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      Lr[i][j] = R(0);
+      W[i][j] = R(0);
+    }
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    R d = Rm[j * NU + j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) d -= Lr[j][k] * Lr[j][k];
+    const R ljj = sqrt(d);
+    Lr[j][j] = ljj;
+#pragma unroll
+    for (int i = j + 1; i < NU; ++i) {
+      R s = Rm[i * NU + j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) s -= Lr[i][k] * Lr[j][k];
+      Lr[i][j] = s / ljj;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NU; ++c)
+#pragma unroll
+    for (int i = c; i < NU; ++i) {
+      R s = (i == c) ? R(1) : R(0);
+#pragma unroll
+      for (int k = c; k < i; ++k) s -= Lr[i][k] * W[c][k];
+      W[c][i] = s / Lr[i][i];
+    }
+  R Ri[NU][NU];
+#pragma unroll
+  for (int i = 0; i < NU; ++i)
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      cs[C::W + i * NU + j] = W[i][j];
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < NU; ++k) s += W[i][k] * W[j][k];
+      Ri[i][j] = s;
+      cs[C::Rinv + i * NU + j] = s;
+    }
+  if (!kp.L_sampled) {
+    const R* L = (const R*)kp.L;
+    R Lc[N][NU];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int l = 0; l < NU; ++l) {
+        R s = R(0);
+#pragma unroll
+        for (int q = 0; q < NU; ++q) s += L[i * NU + q] * W[q][l];
+        Lc[i][l] = s;
+        cs[C::Lc + i * NU + l] = s;
+      }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        R s = R(0);
+#pragma unroll
+        for (int l = 0; l < NU; ++l) s += Lc[i][l] * Lc[j][l];
+        cs[C::G + i * N + j] = s;
+      }
+#pragma unroll
+    for (int l = 0; l < NU; ++l)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        R s = R(0);
+#pragma unroll
+        for (int q = 0; q < NU; ++q) s += Ri[l][q] * L[j * NU + q];
+        cs[C::Kc + l * N + j] = s;
+      }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Launchers.
 // ------------------------------------------------------------------------------------------
-inline dim3 grid_for(long n, int batch) {
+inline dim3 grid_lanes(long n, int batch) {
   return dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)batch, 1);
 }
+inline dim3 grid_waves(long waves, int batch) { return dim3((unsigned)waves, (unsigned)batch, 1); }
 
 template <int N, int NU, class R>
 struct L {
   static hipError_t build(const KProb& kp, void* elts, hipStream_t s) {
     const bool cc = !kp.F_sampled && !kp.L_sampled && !kp.has_c;
     if (cc)
-      hipLaunchKernelGGL((k_build<N, NU, R, true>), grid_for(kp.T, kp.batch), dim3(kThreads), 0,
-                         s, kp, (R*)elts);
+      hipLaunchKernelGGL((k_build<N, NU, R, true>), grid_lanes(kp.T, kp.batch), dim3(kThreads),
+                         0, s, kp, (R*)elts);
     else
-      hipLaunchKernelGGL((k_build<N, NU, R, false>), grid_for(kp.T, kp.batch), dim3(kThreads), 0,
-                         s, kp, (R*)elts);
+      hipLaunchKernelGGL((k_build<N, NU, R, false>), grid_lanes(kp.T, kp.batch), dim3(kThreads),
+                         0, s, kp, (R*)elts);
     return hipGetLastError();
   }
-  static hipError_t vreduce(const KProb& kp, const void* src, long n_src, void* dst, long n_dst,
-                            int c, hipStream_t s) {
-    hipLaunchKernelGGL((k_vreduce<N, R>), grid_for(n_dst, kp.batch), dim3(kThreads), 0, s,
-                       (const R*)src, n_src, (R*)dst, n_dst, c);
+  static hipError_t build_reduce(const KProb& kp, void* elts, void* lvl1, long n1,
+                                 hipStream_t s) {
+    const bool cc = !kp.F_sampled && !kp.L_sampled && !kp.has_c;
+    if (cc)
+      hipLaunchKernelGGL((k_build_reduce<N, NU, R, true>), grid_lanes(n1, kp.batch),
+                         dim3(kThreads), 0, s, kp, (R*)elts, (R*)lvl1, n1);
+    else
+      hipLaunchKernelGGL((k_build_reduce<N, NU, R, false>), grid_lanes(n1, kp.batch),
+                         dim3(kThreads), 0, s, kp, (R*)elts, (R*)lvl1, n1);
+    return hipGetLastError();
+  }
+  static hipError_t vreduce0(const KProb& kp, const void* elts, void* dst, long n1,
+                             hipStream_t s) {
+    hipLaunchKernelGGL((k_vreduce0<N, R>), grid_lanes(n1, kp.batch), dim3(kThreads), 0, s,
+                       (const R*)elts, (long)kp.T, (R*)dst, n1);
+    return hipGetLastError();
+  }
+  static hipError_t vup(const KProb& kp, const void* src, long n_src, void* part, void* dst,
+                        long n_dst, hipStream_t s) {
+    hipLaunchKernelGGL((k_vup<N, R>), grid_waves(n_dst, kp.batch), dim3(kThreads), 0, s,
+                       (const R*)src, n_src, (R*)part, (R*)dst, n_dst);
     return hipGetLastError();
   }
   static hipError_t vtop(const KProb& kp, const void* tup, long n, void* val, hipStream_t s) {
@@ -673,28 +878,29 @@ struct L {
                        (const R*)tup, n, (R*)val);
     return hipGetLastError();
   }
-  static hipError_t vdown(const KProb& kp, const void* tup, long n_child, const void* val_in,
-                          long n_par, void* val_out, int c, hipStream_t s) {
-    hipLaunchKernelGGL((k_vdown<N, R>), grid_for(n_par, kp.batch), dim3(kThreads), 0, s,
-                       (const R*)tup, n_child, (const R*)val_in, n_par, (R*)val_out, c);
+  static hipError_t vdown(const KProb& kp, const void* tup, long n_child, const void* part,
+                          const void* val_par, long n_par, void* val_child, hipStream_t s) {
+    hipLaunchKernelGGL((k_vdown<N, R>), grid_waves(n_par, kp.batch), dim3(kThreads), 0, s,
+                       (const R*)tup, n_child, (const R*)part, (const R*)val_par, n_par,
+                       (R*)val_child);
     return hipGetLastError();
   }
   static hipError_t vbottom(const KProb& kp, const void* elts, const void* val1, long n1, void* S,
-                            void* v, void* maps1, int c0, hipStream_t s) {
-    hipLaunchKernelGGL((k_vbottom<N, R>), grid_for(n1, kp.batch), dim3(kThreads), 0, s, kp,
-                       (const R*)elts, (const R*)val1, n1, (R*)S, (R*)v, (R*)maps1, c0);
+                            void* v, void* maps1, hipStream_t s) {
+    hipLaunchKernelGGL((k_vbottom<N, R>), grid_lanes(n1, kp.batch), dim3(kThreads), 0, s, kp,
+                       (const R*)elts, (const R*)val1, n1, (R*)S, (R*)v, (R*)maps1);
     return hipGetLastError();
   }
   static hipError_t tbottom_reduce(const KProb& kp, const void* elts, const void* S,
-                                   const void* v, void* maps1, long n1, int c0, hipStream_t s) {
-    hipLaunchKernelGGL((k_tbottom_reduce<N, R>), grid_for(n1, kp.batch), dim3(kThreads), 0, s,
-                       kp, (const R*)elts, (const R*)S, (const R*)v, (R*)maps1, n1, c0);
+                                   const void* v, void* maps1, long n1, hipStream_t s) {
+    hipLaunchKernelGGL((k_tbottom_reduce<N, R>), grid_lanes(n1, kp.batch), dim3(kThreads), 0, s,
+                       kp, (const R*)elts, (const R*)S, (const R*)v, (R*)maps1, n1);
     return hipGetLastError();
   }
-  static hipError_t treduce(const KProb& kp, const void* src, long n_src, void* dst, long n_dst,
-                            int c, hipStream_t s) {
-    hipLaunchKernelGGL((k_treduce<N, R>), grid_for(n_dst, kp.batch), dim3(kThreads), 0, s,
-                       (const R*)src, n_src, (R*)dst, n_dst, c);
+  static hipError_t tup(const KProb& kp, const void* src, long n_src, void* part, void* dst,
+                        long n_dst, hipStream_t s) {
+    hipLaunchKernelGGL((k_tup<N, R>), grid_waves(n_dst, kp.batch), dim3(kThreads), 0, s,
+                       (const R*)src, n_src, (R*)part, (R*)dst, n_dst);
     return hipGetLastError();
   }
   static hipError_t ttop(const KProb& kp, const void* maps, long n, void* xs, hipStream_t s) {
@@ -702,25 +908,27 @@ struct L {
                        (const R*)maps, n, (R*)xs);
     return hipGetLastError();
   }
-  static hipError_t tdown(const KProb& kp, const void* maps, long n_child, const void* x_in,
-                          long n_par, void* x_out, int c, hipStream_t s) {
-    hipLaunchKernelGGL((k_tdown<N, R>), grid_for(n_par, kp.batch), dim3(kThreads), 0, s,
-                       (const R*)maps, n_child, (const R*)x_in, n_par, (R*)x_out, c);
+  static hipError_t tdown(const KProb& kp, const void* maps, long n_child, const void* part,
+                          const void* x_par, long n_par, void* x_child, hipStream_t s) {
+    hipLaunchKernelGGL((k_tdown<N, R>), grid_waves(n_par, kp.batch), dim3(kThreads), 0, s,
+                       (const R*)maps, n_child, (const R*)part, (const R*)x_par, n_par,
+                       (R*)x_child);
     return hipGetLastError();
   }
   static hipError_t tbottom(const KProb& kp, const void* elts, const void* S, const void* v,
-                            const void* x1, long n1, void* x, void* u, int c0, hipStream_t s) {
-    hipLaunchKernelGGL((k_tbottom<N, NU, R>), grid_for(n1, kp.batch), dim3(kThreads), 0, s, kp,
-                       (const R*)elts, (const R*)S, (const R*)v, (const R*)x1, n1, (R*)x, (R*)u,
-                       c0);
+                            const void* x1, long n1, void* x, void* u, hipStream_t s) {
+    hipLaunchKernelGGL((k_tbottom<N, NU, R>), grid_lanes(n1, kp.batch), dim3(kThreads), 0, s, kp,
+                       (const R*)elts, (const R*)S, (const R*)v, (const R*)x1, n1, (R*)x, (R*)u);
     return hipGetLastError();
   }
   static hipError_t prep(const KProb& kp, void* consts, hipStream_t s) {
-    return launch_prep(kp, sizeof(R) == 8 ? 0 : 1, consts, s);
+    hipLaunchKernelGGL((k_prep_lane<N, NU, R>), dim3((kp.batch + kThreads - 1) / kThreads),
+                       dim3(kThreads), 0, s, kp, (R*)consts);
+    return hipGetLastError();
   }
   static const Ops* ops() {
-    static const Ops o = {prep,    build,          vreduce, vtop, vdown, vbottom,
-                          tbottom_reduce, treduce, ttop,    tdown, tbottom};
+    static const Ops o = {prep, build, build_reduce, vreduce0, vup,   vtop, vdown,
+                          vbottom, tbottom_reduce, tup, ttop, tdown, tbottom};
     return &o;
   }
 };

@@ -148,6 +148,20 @@ def element_count(nx: int) -> int:
     return int(lib().lqt_element_count(nx))
 
 
+ELEMENT_TILE = 256
+
+
+def element_tiles(T: int) -> int:
+    """Number of 256-block tiles of the element layout."""
+    return (T + ELEMENT_TILE - 1) // ELEMENT_TILE
+
+
+def empty_elements(prob: "DeviceProblem") -> torch.Tensor:
+    """Element array [batch][ceil(T/256)][NE][256] (tiled structure of arrays, include/lqt.h)."""
+    return torch.empty(prob.batch, element_tiles(prob.T), element_count(prob.nx), ELEMENT_TILE,
+                       dtype=prob.dtype, device=prob.t.device)
+
+
 def workspace_size(prob: DeviceProblem, call: int) -> int:
     d = prob.dims()
     n = int(lib().lqt_workspace_size(ctypes.byref(d), call))
@@ -169,8 +183,8 @@ def _empty(prob, *shape):
 
 def build_elements(prob: DeviceProblem, elts: Optional[torch.Tensor] = None,
                    ws: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Elements [batch][NE][T] (structure of arrays, A stored as A - I)."""
-    elts = _empty(prob, prob.batch, element_count(prob.nx), prob.T) if elts is None else elts
+    """Elements [batch][ceil(T/256)][NE][256] (tiled structure of arrays, A stored as A - I)."""
+    elts = empty_elements(prob) if elts is None else elts
     ws = workspace(prob, CALL_BUILD) if ws is None else ws
     d, p = prob.dims(), prob.ptrs()
     _check(lib().lqt_build_elements(ctypes.byref(d), ctypes.byref(p), _ptr(elts), _ptr(ws),
@@ -209,7 +223,7 @@ def solve(prob: DeviceProblem, out: Optional[dict] = None, ws=None, keep_element
                "x": _empty(prob, prob.batch, prob.T + 1, prob.nx),
                "u": _empty(prob, prob.batch, prob.T + 1, prob.nu)}
         if keep_elements:
-            out["elts"] = _empty(prob, prob.batch, element_count(prob.nx), prob.T)
+            out["elts"] = empty_elements(prob)
     ws = workspace(prob, CALL_SOLVE) if ws is None else ws
     d, p = prob.dims(), prob.ptrs()
     _check(lib().lqt_solve(ctypes.byref(d), ctypes.byref(p), _ptr(out.get("elts")), _ptr(out["S"]),

@@ -5,10 +5,35 @@ import numpy as np
 from paper_2212_11744_amd import lqt
 
 
-def soa_to_dense(elts, nx):
-    """[NE][T] array (one problem) -> dict of A, b, C, eta, J with A the full matrix."""
+TILE = 256
+
+
+def tile_position(k):
+    """(tile, column) of item k: tiles of 256 items, column 64 (k % 4) + (k % 256) // 4."""
+    k = np.asarray(k)
+    return k // TILE, 64 * (k % 4) + (k % TILE) // 4
+
+
+def untile(elts, T):
+    """[ntile][NE][256] -> [NE][T]."""
     e = np.asarray(elts, dtype=np.float64)
-    T = e.shape[1]
+    g, c = tile_position(np.arange(T))
+    return e[g, :, c].T
+
+
+def tile(e):
+    """[NE][T] -> [ntile][NE][256] (padding zero)."""
+    NE, T = e.shape
+    nt = (T + TILE - 1) // TILE
+    out = np.zeros((nt, NE, TILE))
+    g, c = tile_position(np.arange(T))
+    out[g, :, c] = np.asarray(e).T
+    return out
+
+
+def soa_to_dense(elts, nx, T):
+    """[ntile][NE][256] array (one problem) -> dict of A, b, C, eta, J with A the full matrix."""
+    e = untile(elts, T)
     sl = lqt.element_slices(nx)
     iu = np.triu_indices(nx)
     out = {"A": e[sl["A"]].T.reshape(T, nx, nx) + np.eye(nx)[None],
@@ -23,10 +48,10 @@ def soa_to_dense(elts, nx):
 
 
 def dense_to_soa(el, nx, Ad=None):
-    """dict of A, b, C, eta, J (T leading) -> [NE][T] (A - I, packed upper triangles)."""
+    """dict of A, b, C, eta, J (T leading) -> [ntile][NE][256] (A - I, packed upper triangles)."""
     T = el["A"].shape[0]
     iu = np.triu_indices(nx)
     Ad = el["A"] - np.eye(nx)[None] if Ad is None else Ad
     parts = [Ad.reshape(T, nx * nx).T, el["b"].T, el["C"][:, iu[0], iu[1]].T, el["eta"].T,
              el["J"][:, iu[0], iu[1]].T]
-    return np.ascontiguousarray(np.concatenate(parts, axis=0))
+    return tile(np.concatenate(parts, axis=0))

@@ -51,7 +51,7 @@ def _device():
 def test_elements_config1():
     p = W.point_mass(1, 64, 10)
     dp = lqt.DeviceProblem.from_problems([p])
-    el = soa_to_dense(_np(lqt.build_elements(dp)[0]), p.nx)
+    el = soa_to_dense(_np(lqt.build_elements(dp)[0]), p.nx, p.T)
     ref = O.elements(p)
     _check_elements(el, ref, 1e-9, "config1")
     assert relerr(el["Ad"], ref["A"] - np.eye(p.nx)) < 1e-9
@@ -84,7 +84,7 @@ def test_ragged_horizons_fp64(T):
     dp = lqt.DeviceProblem.from_problems([p])
     out = lqt.solve(dp, keep_elements=True)
     _check_solution(p, out, ref, torch.float64, label=f"T={T} nx={nx}")
-    _check_elements(soa_to_dense(_np(out["elts"][0]), nx), O.elements(p), 1e-9, f"T={T}")
+    _check_elements(soa_to_dense(_np(out["elts"][0]), nx, T), O.elements(p), 1e-9, f"T={T}")
 
 
 @pytest.mark.parametrize("nx,nu", [(1, 1), (2, 1), (2, 2), (3, 1), (3, 2), (3, 3), (4, 1), (4, 2), (4, 3), (4, 4)])
@@ -136,27 +136,19 @@ def test_scan_example_exact():
     dp.nx, dp.nu = 1, 1
     dp.Qf = torch.zeros(1, 1, 1, dtype=torch.float64, device="cuda")
     dp.rf = torch.zeros(1, 1, dtype=torch.float64, device="cuda")
-    for c0, c in ((1, 2), (2, 2), (3, 5), (8, 8)):
-        os.environ["LQT_CHUNK0"], os.environ["LQT_CHUNK"] = str(c0), str(c)
-        try:
-            S, v = lqt.scan_value(dp, torch.as_tensor(dense_to_soa(el, 1)[None], device="cuda"))
-        finally:
-            del os.environ["LQT_CHUNK0"], os.environ["LQT_CHUNK"]
-        assert np.array_equal(_np(v[0, :T, 0]), np.array(g["suffix"], dtype=float)), (c0, c)
-        assert not _np(S).any()
+    S, v = lqt.scan_value(dp, torch.as_tensor(dense_to_soa(el, 1)[None], device="cuda"))
+    assert np.array_equal(_np(v[0, :T, 0]), np.array(g["suffix"], dtype=float))
+    assert not _np(S).any()
 
 
-@pytest.mark.parametrize("c0,c", [(1, 2), (2, 3), (4, 8), (16, 16), (5, 64)])
-def test_tree_shapes_agree(c0, c):
-    p = W.point_mass(3, 3001, 4, tf=10.0)
+@pytest.mark.parametrize("T", [1023, 1024, 1025, 4 * 256 * 256 + 3])
+def test_tree_shapes(T):
+    """Horizons that give one, two and three scan-tree levels (4 blocks per lane, 256 nodes per
+    wave above level 1), with ragged last nodes."""
+    p = W.point_mass(3, T, 2, tf=10.0 * T / 2 ** 16)
     ref = O.solve(p)
-    os.environ["LQT_CHUNK0"], os.environ["LQT_CHUNK"] = str(c0), str(c)
-    try:
-        out = lqt.solve(lqt.DeviceProblem.from_problems([p]))
-        torch.cuda.synchronize()
-    finally:
-        del os.environ["LQT_CHUNK0"], os.environ["LQT_CHUNK"]
-    _check_solution(p, out, ref, torch.float64, label=f"c0={c0} c={c}")
+    out = lqt.solve(lqt.DeviceProblem.from_problems([p]))
+    _check_solution(p, out, ref, torch.float64, label=f"T={T}")
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
