@@ -143,13 +143,17 @@ lqt_status lqt_solve(const lqt_dims *dims, const lqt_problem *prob, void *elts, 
                      void *x, void *u, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* Adjoint of lqt_solve for a loss whose gradient with respect to the trajectory is dLdx
- * [batch][T+1][nx]: accumulates nothing, overwrites the outputs with
+ * [batch][T+1][nx] (the exact adjoint of the discrete scheme, not of the continuous problem).
+ * Overwrites (accumulates nothing):
  *   dQ [batch][nx*nx], dR [batch][nu*nu], dr [batch][NS][nx], dx0 [batch][nx],
  *   dQf [batch][nx*nx], drf [batch][nx]   (dQf, drf may be NULL).
- * Gradients are entrywise with respect to the arrays as the forward pass reads them (Q enters
- * through Q r with all entries and through the upper triangle of the J equation; R through its
- * inverse).  S, v, x are the outputs of the forward solve of the same problem; elements are
- * recomputed, not read.  Requires F, L constant and c = 0 (LQT_EUNSUPPORTED otherwise). */
+ * dQ, dR, dQf are symmetric gradients: dL = <dQ, E> for every symmetric perturbation E of Q.
+ * S, v, x are the outputs of lqt_solve for the same problem; the elements are rebuilt in the
+ * workspace, not read.  Structure: a reverse affine scan for the state adjoint
+ * lambda_k = dLdx_k + Psi_k^T lambda_{k+1}, a forward scan for the value adjoints (the linear
+ * parts compose like the trajectory maps), per-block gradients of the combination rule
+ * (Lemma 7) and the discrete adjoint of each block's RK4 steps.  FP64 only, nx <= 4, F and L
+ * constant, c = 0 (LQT_EUNSUPPORTED otherwise). */
 lqt_status lqt_backward(const lqt_dims *dims, const lqt_problem *prob, const void *S,
                         const void *v, const void *x, const void *dLdx, void *dQ, void *dR,
                         void *dr, void *dx0, void *dQf, void *drf, void *ws, size_t ws_bytes,

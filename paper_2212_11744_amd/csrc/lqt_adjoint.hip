@@ -1,0 +1,1265 @@
+// Adjoint of lqt_solve (1 <= nu <= nx <= 4): gradients of a loss L(x_0, ..., x_T) with
+// respect to Q, R, the reference samples r, x0, Qf and rf, for F, L constant and c = 0.
+//
+// The forward scheme is: elements a_k from RK4 on Theorem 8 (Sec. IV-B); values
+// (S_k, v_k) = a_k (x) (S_{k+1}, v_{k+1}) from the terminal value (Qf, Qf rf) (Theorem 6,
+// Sec. IV-D); states x_{k+1} = Psi_k x_k + alpha_k with Psi_k = M_k^{-1} A_k,
+// alpha_k = M_k^{-1} (b_k + C_k v_{k+1}), M_k = I + C_k S_{k+1} (Sec. IV-E).  Its exact discrete
+// adjoint, with xbar_k = dL/dx_k given:
+//   lambda_T = xbar_T,  lambda_k = xbar_k + Psi_k^T lambda_{k+1}            (reverse affine scan)
+//   mu_k = M_k^{-T} lambda_{k+1}
+//   (Sbar_0, vbar_0) = 0,
+//   Sbar_{k+1} = Psi Sbar_k Psi^T - sym(Psi vbar_k alpha^T) - sym(C mu x_{k+1}^T),
+//   vbar_{k+1} = Psi vbar_k + C mu                                         (forward scan)
+// where Sbar_k, vbar_k are the total gradients with respect to S_k, v_k (the linear parts compose
+// like the trajectory maps, so this recursion is itself an associative scan).  Per block, the
+// gradient with respect to the element, with S = S_{k+1}, v = v_{k+1}, y = M^{-T} (v - S b),
+// p = S x_{k+1} - v:
+//   Jbar = Sbar_k, etabar = vbar_k,
+//   Abar = 2 S Psi Sbar_k + y vbar_k^T + mu x_k^T,   bbar = -S Psi vbar_k + mu,
+//   Cbar = -(S Psi) Sbar_k (S Psi)^T - sym(S Psi vbar_k y^T) - sym(mu p^T),
+// and the element gradient is carried back through the RK4 steps of the block (discrete adjoint,
+// the forward steps recomputed from the block's boundary values) to Q, G = L R^{-1} L^T and the
+// reference samples; R gets -R^{-1} L^T Gbar L R^{-1}.  Matrix gradients are symmetric: the
+// derivative for symmetric perturbations of Q, R, Qf.
+#include "lane_math.hpp"
+#include "lqt_internal.hpp"
+#include "tree_scan.hpp"
+#include "wave_tree.hpp"
+
+namespace lqt {
+namespace {
+
+template <int N, int NU>
+struct CS {
+  static constexpr int G = 0, Lc = N * N, Kc = N * N + N * NU, W = N * N + 2 * N * NU,
+                       Rinv = N * N + 2 * N * NU + NU * NU, size = N * N + 2 * N * NU + 2 * NU * NU;
+};
+
+constexpr int kT = 64;
+
+__device__ inline long gidx() { return (long)blockIdx.x * blockDim.x + threadIdx.x; }
+
+template <int N, class R>
+LQT_DEV void Sfull(const R (&Sp)[Sym<N>::size], R (&S)[N][N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) S[i][j] = Sp[Sym<N>::at(i, j)];
+}
+
+// Packed adjoint of a symmetric matrix from its symmetric gradient X: the stored entry (i, j),
+// i < j, stands for both (i, j) and (j, i).
+template <int N, class R>
+LQT_DEV void pack_grad(const R (&X)[N][N], R (&P)[Sym<N>::size]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) P[Sym<N>::at(i, j)] = i == j ? X[i][i] : X[i][j] + X[j][i];
+}
+
+// ------------------------------------------------------------------------------------------
+// Algebras of the two adjoint scans.
+// ------------------------------------------------------------------------------------------
+// lambda scan: map lambda -> (I + P) lambda + q with P = Psi_k^T - I, q = xbar_k; backward.
+template <int N, class R>
+struct LamAlg {
+  static constexpr bool kForward = false;
+  static constexpr int NMAP = Lay<N>::NM, NST = N;
+  using Map = Aff<N, R>;
+  struct State {
+    R x[N];
+  };
+  static LQT_DEV void identity(Map& m) { aff_identity(m); }
+  static LQT_DEV void load(Map& m, const R* b, long k) { aff_load(m, b, k); }
+  static LQT_DEV void store(const Map& m, R* b, long k) { aff_store(m, b, k); }
+  // first covers the earlier interval: lambda at its left end = first(second(lambda right)).
+  static LQT_DEV void chain(const Map& first, const Map& second, Map& out) {
+    Map o = first;
+    aff_after(o, second);
+    out = o;
+  }
+  static LQT_DEV void apply(const Map& m, State& st) { aff_apply(m, st.x); }
+  static LQT_DEV void sload(State& st, const R* b, long k) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) st.x[q] = b[tix<N>(q, k)];
+  }
+  static LQT_DEV void sstore(const State& st, R* b, long k) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) b[tix<N>(q, k)] = st.x[q];
+  }
+  static LQT_DEV void shfl_map(const Map& x, Map& y, int src) { shfl_aff(x, y, src); }
+  static LQT_DEV void shfl_state(const State& x, State& y, int src) { shfl_vec<N, R>(x.x, y.x, src); }
+  // aux: dL/dx [batch][T+1][N]; lambda_T = xbar_T.
+  static LQT_DEV void init(const KProb& kp, const R* aux, int p, State& st) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) st.x[q] = aux[((long)p * (kp.T + 1) + kp.T) * N + q];
+  }
+};
+
+// (Sbar, vbar) scan: map (Sbar, vbar) -> (Psi Sbar Psi^T - sym(Psi vbar alpha^T) + FS,
+// Psi vbar + Fv), Psi = I + P; forward.
+template <int N, class R>
+struct CongMap {
+  R P[N][N];
+  R a[N];
+  R FS[Sym<N>::size];
+  R Fv[N];
+};
+
+template <int N, class R>
+LQT_DEV void cong_apply(const CongMap<N, R>& m, R (&Sb)[Sym<N>::size], R (&vb)[N]) {
+  using Y = Sym<N>;
+  R Ps[N][N];  // Psi Sbar
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = Sb[Y::at(i, j)];
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(m.P[i][k], Sb[Y::at(k, j)], s);
+      Ps[i][j] = s;
+    }
+  R pv[N];  // Psi vbar
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = vb[i];
+#pragma unroll
+    for (int k = 0; k < N; ++k) s = fma(m.P[i][k], vb[k], s);
+    pv[i] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) {
+      R s = Ps[i][j];  // (Psi Sbar) Psi^T = Ps (I + P^T)
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(Ps[i][k], m.P[j][k], s);
+      s -= R(0.5) * (pv[i] * m.a[j] + pv[j] * m.a[i]);
+      Sb[Y::at(i, j)] = s + m.FS[Y::at(i, j)];
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i) vb[i] = pv[i] + m.Fv[i];
+}
+
+template <int N, class R>
+struct CongAlg {
+  static constexpr bool kForward = true;
+  static constexpr int NS = Sym<N>::size;
+  static constexpr int NMAP = N * N + 2 * N + NS, NST = NS + N;
+  using Map = CongMap<N, R>;
+  struct State {
+    R S[Sym<N>::size];
+    R v[N];
+  };
+  static LQT_DEV void identity(Map& m) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) m.P[i][j] = R(0);
+      m.a[i] = R(0);
+      m.Fv[i] = R(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) m.FS[i] = R(0);
+  }
+  static LQT_DEV void load(Map& m, const R* b, long k) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) m.P[i][j] = b[tix<NMAP>(i * N + j, k)];
+      m.a[i] = b[tix<NMAP>(N * N + i, k)];
+      m.Fv[i] = b[tix<NMAP>(N * N + N + NS + i, k)];
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) m.FS[i] = b[tix<NMAP>(N * N + N + i, k)];
+  }
+  static LQT_DEV void store(const Map& m, R* b, long k) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) b[tix<NMAP>(i * N + j, k)] = m.P[i][j];
+      b[tix<NMAP>(N * N + i, k)] = m.a[i];
+      b[tix<NMAP>(N * N + N + NS + i, k)] = m.Fv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) b[tix<NMAP>(N * N + N + i, k)] = m.FS[i];
+  }
+  // out = second after first: Psi = Psi2 Psi1, alpha = Psi2 alpha1 + alpha2,
+  // F = L2(F1) + F2 with L2 the linear part of `second`.
+  static LQT_DEV void chain(const Map& first, const Map& second, Map& out) {
+    Map o;
+    R FS[NS], Fv[N];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) FS[i] = first.FS[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) Fv[i] = first.Fv[i];
+    cong_apply(second, FS, Fv);  // L2(F1) + F2
+#pragma unroll
+    for (int i = 0; i < NS; ++i) o.FS[i] = FS[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) o.Fv[i] = Fv[i];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        R s = R(0);
+#pragma unroll
+        for (int k = 0; k < N; ++k) s = fma(second.P[i][k], first.P[k][j], s);
+        o.P[i][j] = first.P[i][j] + second.P[i][j] + s;
+      }
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(second.P[i][k], first.a[k], s);
+      o.a[i] = second.a[i] + first.a[i] + s;
+    }
+    out = o;
+  }
+  static LQT_DEV void apply(const Map& m, State& st) { cong_apply(m, st.S, st.v); }
+  static LQT_DEV void sload(State& st, const R* b, long k) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) st.S[q] = b[tix<NST>(q, k)];
+#pragma unroll
+    for (int q = 0; q < N; ++q) st.v[q] = b[tix<NST>(NS + q, k)];
+  }
+  static LQT_DEV void sstore(const State& st, R* b, long k) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) b[tix<NST>(q, k)] = st.S[q];
+#pragma unroll
+    for (int q = 0; q < N; ++q) b[tix<NST>(NS + q, k)] = st.v[q];
+  }
+  static LQT_DEV void shfl_map(const Map& x, Map& y, int src) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) y.P[i][j] = shfl(x.P[i][j], src);
+      y.a[i] = shfl(x.a[i], src);
+      y.Fv[i] = shfl(x.Fv[i], src);
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) y.FS[i] = shfl(x.FS[i], src);
+  }
+  static LQT_DEV void shfl_state(const State& x, State& y, int src) {
+    shfl_val<N, R>(x.S, x.v, y.S, y.v, src);
+  }
+  static LQT_DEV void init(const KProb&, const R*, int, State& st) {
+#pragma unroll
+    for (int q = 0; q < NS; ++q) st.S[q] = R(0);
+#pragma unroll
+    for (int q = 0; q < N; ++q) st.v[q] = R(0);
+  }
+};
+
+// ------------------------------------------------------------------------------------------
+// Per-block pieces shared by the bottom kernels.
+// ------------------------------------------------------------------------------------------
+template <int N, class R>
+struct BlockCtx {
+  R S[Sym<N>::size];  // S_{k+1}
+  R v[N];             // v_{k+1}
+  R Pd[N][N];         // Psi_k - I
+  R al[N];            // alpha_k
+};
+
+template <int N, class R>
+LQT_DEV void block_ctx(const Tup<N, R>& a, const R* Sg, const R* vg, long k, BlockCtx<N, R>& c) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) c.S[Sym<N>::at(i, j)] = Sg[(k + 1) * N * N + i * N + j];
+#pragma unroll
+  for (int i = 0; i < N; ++i) c.v[i] = vg[(k + 1) * N + i];
+  Aff<N, R> m;
+  block_map<N, R>(a.A, a.b, a.C, c.S, c.v, m);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) c.Pd[i][j] = m.P[i][j];
+    c.al[i] = m.q[i];
+  }
+}
+
+// Solve (I + S C) X = B for NB right-hand sides (I + S C = M^T).
+template <int N, int NB, class R>
+LQT_DEV void solve_MT(const Tup<N, R>& a, const R (&S)[Sym<N>::size], R (&B)[N][NB]) {
+  R Mt[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(S[Sym<N>::at(i, k)], a.C[Sym<N>::at(k, j)], s);
+      Mt[i][j] = (i == j) ? R(1) + s : s;
+    }
+  gj_solve<N, NB, R>(Mt, B);
+}
+
+// (A) level 1 of the lambda scan: per lane, the composition of its blocks' maps
+// lambda_k = Psi_k^T lambda_{k+1} + xbar_k.
+template <int N, class R>
+__global__ __launch_bounds__(kT) void k_adj_lam_bottom(const KProb kp, const R* __restrict__ elts,
+                                                       const R* __restrict__ Sg,
+                                                       const R* __restrict__ vg,
+                                                       const R* __restrict__ xbar,
+                                                       R* __restrict__ maps1, long n1) {
+  const int p = blockIdx.y;
+  const long i = gidx();
+  if (i >= n1) return;
+  const long T = kp.T;
+  const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
+  const R* Sp = Sg + (long)p * (T + 1) * N * N;
+  const R* vp = vg + (long)p * (T + 1) * N;
+  const R* xb = xbar + (long)p * (T + 1) * N;
+  const long j0 = i * kChunk, j1 = min(j0 + kChunk, T);
+  Aff<N, R> acc;
+  aff_identity(acc);
+  for (long k = j1 - 1; k >= j0; --k) {
+    Tup<N, R> a;
+    tup_load(a, ep, k);
+    BlockCtx<N, R> c;
+    block_ctx<N, R>(a, Sp, vp, k, c);
+    Aff<N, R> m;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) m.P[r][q] = c.Pd[q][r];
+      m.q[r] = xb[k * N + r];
+    }
+    LamAlg<N, R>::chain(m, acc, acc);
+  }
+  aff_store(acc, maps1 + (long)p * Lay<N>::NM * padt(n1), i);
+}
+
+// (C) lambda of every block and level 1 of the (Sbar, vbar) scan.
+template <int N, class R>
+__global__ __launch_bounds__(kT) void k_adj_cong_bottom(const KProb kp, const R* __restrict__ elts,
+                                                        const R* __restrict__ Sg,
+                                                        const R* __restrict__ vg,
+                                                        const R* __restrict__ xg,
+                                                        const R* __restrict__ xbar,
+                                                        const R* __restrict__ lam1, long n1,
+                                                        R* __restrict__ lam, R* __restrict__ maps1,
+                                                        R* __restrict__ dx0) {
+  using Y = Sym<N>;
+  const int p = blockIdx.y;
+  const long i = gidx();
+  if (i >= n1) return;
+  const long T = kp.T;
+  const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
+  const R* Sp = Sg + (long)p * (T + 1) * N * N;
+  const R* vp = vg + (long)p * (T + 1) * N;
+  const R* xp = xg + (long)p * (T + 1) * N;
+  const R* xb = xbar + (long)p * (T + 1) * N;
+  R* lp = lam + (long)p * (T + 1) * N;
+  R l[N];  // lambda at the right end of the lane's range
+#pragma unroll
+  for (int q = 0; q < N; ++q) l[q] = lam1[(long)p * N * padt(n1) + tix<N>(q, i)];
+  const long j0 = i * kChunk, j1 = min(j0 + kChunk, T);
+  if (j1 == T) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) lp[T * N + q] = l[q];
+  }
+  CongMap<N, R> acc;
+  CongAlg<N, R>::identity(acc);
+  for (long k = j1 - 1; k >= j0; --k) {
+    Tup<N, R> a;
+    tup_load(a, ep, k);
+    BlockCtx<N, R> c;
+    block_ctx<N, R>(a, Sp, vp, k, c);
+    R B[N][1];
+#pragma unroll
+    for (int q = 0; q < N; ++q) B[q][0] = l[q];
+    solve_MT<N, 1, R>(a, c.S, B);  // mu = M^{-T} lambda_{k+1}
+    R Cmu[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      R s = R(0);
+#pragma unroll
+      for (int q = 0; q < N; ++q) s = fma(a.C[Y::at(r, q)], B[q][0], s);
+      Cmu[r] = s;
+    }
+    CongMap<N, R> m;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) m.P[r][q] = c.Pd[r][q];
+      m.a[r] = c.al[r];
+      m.Fv[r] = Cmu[r];
+    }
+    R x1[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) x1[q] = xp[(k + 1) * N + q];
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = r; q < N; ++q) m.FS[Y::at(r, q)] = R(-0.5) * (Cmu[r] * x1[q] + Cmu[q] * x1[r]);
+    CongAlg<N, R>::chain(m, acc, acc);
+    // lambda_k = Psi_k^T lambda_{k+1} + xbar_k
+    R ln[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      R s = l[r] + xb[k * N + r];
+#pragma unroll
+      for (int q = 0; q < N; ++q) s = fma(c.Pd[q][r], l[q], s);
+      ln[r] = s;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      l[q] = ln[q];
+      lp[k * N + q] = ln[q];
+    }
+  }
+  if (j0 == 0 && dx0) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) dx0[(long)p * N + q] = l[q];
+  }
+  CongAlg<N, R>::store(acc, maps1 + (long)p * CongAlg<N, R>::NMAP * padt(n1), i);
+}
+
+// (E1) element gradients of every block; the element array is overwritten with them.  The lane
+// that owns block T - 1 also writes the terminal gradients.
+template <int N, class R>
+__global__ __launch_bounds__(kT) void k_adj_elem(const KProb kp, R* __restrict__ elts,
+                                                 const R* __restrict__ Sg, const R* __restrict__ vg,
+                                                 const R* __restrict__ xg, const R* __restrict__ lam,
+                                                 const R* __restrict__ sv1, long n1,
+                                                 R* __restrict__ dQf, R* __restrict__ drf) {
+  using Y = Sym<N>;
+  constexpr int NS = Y::size;
+  const int p = blockIdx.y;
+  const long i = gidx();
+  if (i >= n1) return;
+  const long T = kp.T;
+  R* ep = elts + (long)p * Lay<N>::NE * padt(T);
+  const R* Sp = Sg + (long)p * (T + 1) * N * N;
+  const R* vp = vg + (long)p * (T + 1) * N;
+  const R* xp = xg + (long)p * (T + 1) * N;
+  const R* lp = lam + (long)p * (T + 1) * N;
+  R Sb[NS], vb[N];
+  {
+    typename CongAlg<N, R>::State st;
+    CongAlg<N, R>::sload(st, sv1 + (long)p * CongAlg<N, R>::NST * padt(n1), i);
+#pragma unroll
+    for (int q = 0; q < NS; ++q) Sb[q] = st.S[q];
+#pragma unroll
+    for (int q = 0; q < N; ++q) vb[q] = st.v[q];
+  }
+  const long j0 = i * kChunk, j1 = min(j0 + kChunk, T);
+  for (long k = j0; k < j1; ++k) {
+    Tup<N, R> a;
+    tup_load(a, ep, k);
+    BlockCtx<N, R> c;
+    block_ctx<N, R>(a, Sp, vp, k, c);
+    R S[N][N];
+    Sfull<N, R>(c.S, S);
+    R xk[N], xk1[N], lk1[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      xk[q] = xp[k * N + q];
+      xk1[q] = xp[(k + 1) * N + q];
+      lk1[q] = lp[(k + 1) * N + q];
+    }
+    // mu = M^{-T} lambda_{k+1}, y = M^{-T} (v - S b)
+    R B[N][2];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      R s = c.v[r];
+#pragma unroll
+      for (int q = 0; q < N; ++q) s = fma(-S[r][q], a.b[q], s);
+      B[r][0] = lk1[r];
+      B[r][1] = s;
+    }
+    solve_MT<N, 2, R>(a, c.S, B);
+    R SP[N][N];  // S Psi
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R s = S[r][q];
+#pragma unroll
+        for (int m = 0; m < N; ++m) s = fma(S[r][m], c.Pd[m][q], s);
+        SP[r][q] = s;
+      }
+    R SB[N][N];
+    Sfull<N, R>(Sb, SB);
+    R SPS[N][N];  // S Psi Sbar
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R s = R(0);
+#pragma unroll
+        for (int m = 0; m < N; ++m) s = fma(SP[r][m], SB[m][q], s);
+        SPS[r][q] = s;
+      }
+    R spv[N];  // S Psi vbar
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      R s = R(0);
+#pragma unroll
+      for (int q = 0; q < N; ++q) s = fma(SP[r][q], vb[q], s);
+      spv[r] = s;
+    }
+    R pk1[N];  // S x_{k+1} - v
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      R s = -c.v[r];
+#pragma unroll
+      for (int q = 0; q < N; ++q) s = fma(S[r][q], xk1[q], s);
+      pk1[r] = s;
+    }
+    Tup<N, R> g;
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        g.A[r][q] = R(2) * SPS[r][q] + B[r][1] * vb[q] + B[r][0] * xk[q];
+      g.b[r] = B[r][0] - spv[r];
+      g.e[r] = vb[r];
+    }
+    {
+      R Cs[N][N];
+#pragma unroll
+      for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          R s = R(0);
+#pragma unroll
+          for (int m = 0; m < N; ++m) s = fma(SPS[r][m], SP[q][m], s);
+          Cs[r][q] = -s - R(0.5) * (spv[r] * B[q][1] + spv[q] * B[r][1]) -
+                     R(0.5) * (B[r][0] * pk1[q] + B[q][0] * pk1[r]);
+        }
+      pack_grad<N, R>(Cs, g.C);
+      pack_grad<N, R>(SB, g.J);
+    }
+    tup_store(g, ep, k);
+    // advance (Sbar, vbar) across block k
+    CongMap<N, R> m;
+    R Cmu[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+      R s = R(0);
+#pragma unroll
+      for (int q = 0; q < N; ++q) s = fma(a.C[Y::at(r, q)], B[q][0], s);
+      Cmu[r] = s;
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) m.P[r][q] = c.Pd[r][q];
+      m.a[r] = c.al[r];
+      m.Fv[r] = Cmu[r];
+    }
+#pragma unroll
+    for (int r = 0; r < N; ++r)
+#pragma unroll
+      for (int q = r; q < N; ++q) m.FS[Y::at(r, q)] = R(-0.5) * (Cmu[r] * xk1[q] + Cmu[q] * xk1[r]);
+    cong_apply(m, Sb, vb);
+  }
+  if (j1 == T) {
+    // Qf enters through S_T = Qf and v_T = Qf rf.
+    const R* Qf = (const R*)kp.Qf + (long)p * N * N;
+    const R* rf = (const R*)kp.rf + (long)p * N;
+    if (dQf) {
+#pragma unroll
+      for (int r = 0; r < N; ++r)
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+          dQf[(long)p * N * N + r * N + q] =
+              Sb[Y::at(r, q)] + R(0.5) * (vb[r] * rf[q] + vb[q] * rf[r]);
+    }
+    if (drf) {
+#pragma unroll
+      for (int r = 0; r < N; ++r) {
+        R s = R(0);
+#pragma unroll
+        for (int q = 0; q < N; ++q) s = fma(Qf[q * N + r], vb[q], s);
+        drf[(long)p * N + r] = s;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// (E2) RK4 discrete adjoint of the element build, one block per lane.
+// ------------------------------------------------------------------------------------------
+// Right-hand side of Theorem 8 on the (Ad, eta, J) part of a stage value (b and C never enter it):
+//   K = G J - F, w = G eta, fAd = K + Ad K, fb = -(w + Ad w), fC = -(A G A^T) (upper),
+//   feta = K^T eta - Q r, fJ = -Q + J K - F^T J (upper), A = I + Ad.
+template <int N, class R>
+struct Stage {
+  R A[N][N];
+  R e[N];
+  R J[Sym<N>::size];
+};
+
+template <int N, class R>
+LQT_DEV void rhs_eval(const Stage<N, R>& y, const R (&F)[N][N], const R (&G)[N][N],
+                      const R (&Q)[N][N], const R (&r)[N], Tup<N, R>& f) {
+  using Y = Sym<N>;
+  R K[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = -F[i][q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(G[i][l], y.J[Y::at(l, q)], s);
+      K[i][q] = s;
+    }
+  R w[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = R(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) s = fma(G[i][l], y.e[l], s);
+    w[i] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = K[i][q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(y.A[i][l], K[l][q], s);
+      f.A[i][q] = s;
+    }
+    R s = w[i];
+#pragma unroll
+    for (int l = 0; l < N; ++l) s = fma(y.A[i][l], w[l], s);
+    f.b[i] = -s;
+  }
+  R AG[N][N];  // A G
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = G[i][q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(y.A[i][l], G[l][q], s);
+      AG[i][q] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = i; q < N; ++q) {
+      R s = AG[i][q];  // (A G) A^T = AG (I + Ad^T)
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(AG[i][l], y.A[q][l], s);
+      f.C[Y::at(i, q)] = -s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = R(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      s = fma(K[l][i], y.e[l], s);
+      s = fma(-Q[i][l], r[l], s);
+    }
+    f.e[i] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = i; q < N; ++q) {
+      R s = -Q[i][q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        s = fma(y.J[Y::at(i, l)], K[l][q], s);
+        s = fma(-F[l][i], y.J[Y::at(l, q)], s);
+      }
+      f.J[Y::at(i, q)] = s;
+    }
+}
+
+// Vector-Jacobian product of rhs_eval at stage value y for output adjoint g (packed C, J
+// adjoints): returns the adjoint of y's (Ad, eta, J) and accumulates the entrywise adjoints of
+// Q and G and the adjoint of this stage's reference sample.
+template <int N, class R>
+LQT_DEV void rhs_vjp(const Stage<N, R>& y, const Tup<N, R>& g, const R (&F)[N][N],
+                     const R (&G)[N][N], const R (&Q)[N][N], const R (&r)[N], Stage<N, R>& yb,
+                     R (&Qb)[N][N], R (&Gb)[N][N], R (&rb)[N]) {
+  using Y = Sym<N>;
+  R K[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = -F[i][q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(G[i][l], y.J[Y::at(l, q)], s);
+      K[i][q] = s;
+    }
+  R w[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = R(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) s = fma(G[i][l], y.e[l], s);
+    w[i] = s;
+  }
+  R Kb[N][N], Ab[N][N], Jb[N][N], eb[N], wb[N];
+  // fAd = (I + Ad) K: Kb = (I + Ad)^T gA, Adb += gA K^T
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = g.A[i][q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(y.A[l][i], g.A[l][q], s);
+      Kb[i][q] = s;
+      R t = R(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) t = fma(g.A[i][l], K[q][l], t);
+      Ab[i][q] = t;
+    }
+  // fb = -(I + Ad) w: wb = -(I + Ad)^T gb, Adb -= gb w^T
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = g.b[i];
+#pragma unroll
+    for (int l = 0; l < N; ++l) s = fma(y.A[l][i], g.b[l], s);
+    wb[i] = -s;
+#pragma unroll
+    for (int q = 0; q < N; ++q) Ab[i][q] = fma(-g.b[i], w[q], Ab[i][q]);
+  }
+  // fC (upper) = -(A G A^T)_ij: with Bc upper-triangular from g.C,
+  // Adb -= (Bc + Bc^T) A G, Gb -= A^T Bc A.
+  {
+    R Bs[N][N];  // Bc + Bc^T
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int q = 0; q < N; ++q)
+        Bs[i][q] = i == q ? R(2) * g.C[Y::at(i, i)] : g.C[Y::at(i, q)];
+    R AG[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R s = G[i][q];
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(y.A[i][l], G[l][q], s);
+        AG[i][q] = s;
+      }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R s = R(0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(Bs[i][l], AG[l][q], s);
+        Ab[i][q] -= s;
+      }
+    // A^T Bc A, Bc upper triangular (Bc_ij = g.C_ij for i <= j)
+    R BA[N][N];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R s = R(0);
+#pragma unroll
+        for (int l = i; l < N; ++l) s = fma(g.C[Y::at(i, l)], (l == q ? R(1) : R(0)) + y.A[l][q], s);
+        BA[i][q] = s;
+      }
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R s = BA[i][q];
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(y.A[l][i], BA[l][q], s);
+        Gb[i][q] -= s;
+      }
+  }
+  // feta = K^T eta - Q r: Kb += eta ge^T, etab = K ge, Qb -= ge r^T, rb -= Q^T ge
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = R(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) s = fma(K[i][l], g.e[l], s);
+    eb[i] = s;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      Kb[i][q] = fma(y.e[i], g.e[q], Kb[i][q]);
+      Qb[i][q] = fma(-g.e[i], r[q], Qb[i][q]);
+    }
+    R t = R(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) t = fma(-Q[l][i], g.e[l], t);
+    rb[i] += t;
+  }
+  // fJ (upper) = -Q_ij + (J K)_ij - (F^T J)_ij with Bj upper from g.J:
+  // Qb -= Bj (upper entries), Jb += Bj K^T - F Bj, Kb += J Bj
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      if (i <= q) Qb[i][q] -= g.J[Y::at(i, q)];
+      R s = R(0), t = R(0), u = R(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        const R bil = l >= i ? g.J[Y::at(i, l)] : R(0);  // Bj[i][l]
+        const R blq = q >= l ? g.J[Y::at(l, q)] : R(0);  // Bj[l][q]
+        s = fma(bil, K[q][l], s);          // (Bj K^T)_iq
+        t = fma(F[i][l], blq, t);          // (F Bj)_iq
+        u = fma(y.J[Y::at(i, l)], blq, u); // (J Bj)_iq
+      }
+      Jb[i][q] = s - t;
+      Kb[i][q] += u;
+    }
+  // K = G J - F: Gb += Kb J, Jb += G Kb.  w = G eta: Gb += wb eta^T, etab += G wb.
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = R(0), t = R(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        s = fma(Kb[i][l], y.J[Y::at(l, q)], s);
+        t = fma(G[i][l], Kb[l][q], t);
+      }
+      Gb[i][q] += s + wb[i] * y.e[q];
+      Jb[i][q] += t;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = R(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) s = fma(G[i][l], wb[l], s);
+    eb[i] += s;
+  }
+  // Outputs: the stage adjoint (J folded onto its packed entries).
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) yb.A[i][q] = Ab[i][q];
+    yb.e[i] = eb[i];
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = i; q < N; ++q) yb.J[Y::at(i, q)] = i == q ? Jb[i][i] : Jb[i][q] + Jb[q][i];
+}
+
+template <int N, class R>
+LQT_DEV void stage_axpy(const Stage<N, R>& y, R c, const Tup<N, R>& k, Stage<N, R>& o) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) o.A[i][q] = fma(c, k.A[i][q], y.A[i][q]);
+    o.e[i] = fma(c, k.e[i], y.e[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) o.J[i] = fma(c, k.J[i], y.J[i]);
+}
+
+template <int N, class R>
+LQT_DEV void sample_r(const R* rp, long j, R (&r)[N]) {
+#pragma unroll
+  for (int q = 0; q < N; ++q) r[q] = rp[j * N + q];
+}
+
+// One classical RK4 step of -h from s = t_{k+1} - m h on the (Ad, eta, J) part.
+template <int N, class R>
+LQT_DEV void rk4_forward(Stage<N, R>& y, long j1, R hp, const R* rp, const R (&F)[N][N],
+                         const R (&G)[N][N], const R (&Q)[N][N]) {
+  R r[N];
+  Tup<N, R> k1, k2, k3, k4;
+  Stage<N, R> s;
+  sample_r<N, R>(rp, j1, r);
+  rhs_eval(y, F, G, Q, r, k1);
+  stage_axpy(y, R(0.5) * hp, k1, s);
+  sample_r<N, R>(rp, j1 - 1, r);
+  rhs_eval(s, F, G, Q, r, k2);
+  stage_axpy(y, R(0.5) * hp, k2, s);
+  rhs_eval(s, F, G, Q, r, k3);
+  stage_axpy(y, hp, k3, s);
+  sample_r<N, R>(rp, j1 - 2, r);
+  rhs_eval(s, F, G, Q, r, k4);
+  const R w6 = hp / R(6), w3 = hp / R(3);
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+      y.A[i][q] += w6 * (k1.A[i][q] + k4.A[i][q]) + w3 * (k2.A[i][q] + k3.A[i][q]);
+    y.e[i] += w6 * (k1.e[i] + k4.e[i]) + w3 * (k2.e[i] + k3.e[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i)
+    y.J[i] += w6 * (k1.J[i] + k4.J[i]) + w3 * (k2.J[i] + k3.J[i]);
+}
+
+template <int N, class R>
+LQT_DEV void tup_scale(const Tup<N, R>& x, R c, Tup<N, R>& o) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) o.A[i][q] = c * x.A[i][q];
+    o.b[i] = c * x.b[i];
+    o.e[i] = c * x.e[i];
+  }
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) {
+    o.C[i] = c * x.C[i];
+    o.J[i] = c * x.J[i];
+  }
+}
+
+// kb (A, eta, J parts) += c * sb
+template <int N, class R>
+LQT_DEV void tup_add_stage(Tup<N, R>& kb, R c, const Stage<N, R>& sb) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) kb.A[i][q] = fma(c, sb.A[i][q], kb.A[i][q]);
+    kb.e[i] = fma(c, sb.e[i], kb.e[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) kb.J[i] = fma(c, sb.J[i], kb.J[i]);
+}
+
+template <int N, int NU, class R>
+__global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restrict__ abar,
+                                               R* __restrict__ dr, R* __restrict__ bnd,
+                                               R* __restrict__ wsum) {
+  const int p = blockIdx.y;
+  const long k = gidx();
+  const long T = kp.T;
+  const int lane = threadIdx.x;
+  const int n = kp.n;
+  const long nsamp = 2L * n * T + 1;
+  const R* rp = (const R*)kp.r + (long)p * nsamp * N;
+  const R* cs = (const R*)kp.consts + (long)p * CS<N, NU>::size;
+  R F[N][N], G[N][N], Q[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      F[i][q] = ((const R*)kp.F)[i * N + q];
+      G[i][q] = cs[CS<N, NU>::G + i * N + q];
+      Q[i][q] = ((const R*)kp.Q)[(long)p * N * N + i * N + q];
+    }
+  R Qb[N][N], Gb[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      Qb[i][q] = R(0);
+      Gb[i][q] = R(0);
+    }
+  if (k < T) {
+    const R* tg = (const R*)kp.t + (long)p * (T + 1);
+    const R hp = -(tg[k + 1] - tg[k]) / R(n);
+    Tup<N, R> yb;
+    tup_load(yb, abar + (long)p * Lay<N>::NE * padt(T), k);
+    R* drp = dr + (long)p * nsamp * N;
+    // Sample j1 of step m (its first stage) is sample j1 - 2 of step m + 1 (its last stage):
+    // the stage-1 adjoint is carried to the next (earlier) step and written once.
+    R carry[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) carry[q] = R(0);
+    for (int m = n - 1; m >= 0; --m) {
+      const long j1 = 2L * n * k + 2L * (n - m);
+      // recompute the step's start value from the block's boundary values
+      Stage<N, R> y;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) y.A[i][q] = R(0);
+        y.e[i] = R(0);
+      }
+#pragma unroll
+      for (int i = 0; i < Sym<N>::size; ++i) y.J[i] = R(0);
+      for (int mm = 0; mm < m; ++mm) rk4_forward(y, 2L * n * k + 2L * (n - mm), hp, rp, F, G, Q);
+      // stage values
+      R r1[N], r2[N], r4[N];
+      sample_r<N, R>(rp, j1, r1);
+      sample_r<N, R>(rp, j1 - 1, r2);
+      sample_r<N, R>(rp, j1 - 2, r4);
+      Tup<N, R> kk;
+      Stage<N, R> s2, s3, s4;
+      rhs_eval(y, F, G, Q, r1, kk);
+      stage_axpy(y, R(0.5) * hp, kk, s2);
+      rhs_eval(s2, F, G, Q, r2, kk);
+      stage_axpy(y, R(0.5) * hp, kk, s3);
+      rhs_eval(s3, F, G, Q, r2, kk);
+      stage_axpy(y, hp, kk, s4);
+      // reverse sweep
+      Tup<N, R> kb;
+      Stage<N, R> sb;
+      R rb1[N], rb2[N], rb4[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) rb1[q] = rb2[q] = rb4[q] = R(0);
+      Stage<N, R> acc;  // sum of stage-input adjoints
+      tup_scale(yb, hp / R(6), kb);  // k4bar
+      rhs_vjp(s4, kb, F, G, Q, r4, sb, Qb, Gb, rb4);
+      acc = sb;
+      tup_scale(yb, hp / R(3), kb);  // k3bar
+      tup_add_stage(kb, hp, sb);
+      rhs_vjp(s3, kb, F, G, Q, r2, sb, Qb, Gb, rb2);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) acc.A[i][q] += sb.A[i][q];
+        acc.e[i] += sb.e[i];
+      }
+#pragma unroll
+      for (int i = 0; i < Sym<N>::size; ++i) acc.J[i] += sb.J[i];
+      tup_scale(yb, hp / R(3), kb);  // k2bar
+      tup_add_stage(kb, R(0.5) * hp, sb);
+      rhs_vjp(s2, kb, F, G, Q, r2, sb, Qb, Gb, rb2);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) acc.A[i][q] += sb.A[i][q];
+        acc.e[i] += sb.e[i];
+      }
+#pragma unroll
+      for (int i = 0; i < Sym<N>::size; ++i) acc.J[i] += sb.J[i];
+      tup_scale(yb, hp / R(6), kb);  // k1bar
+      tup_add_stage(kb, R(0.5) * hp, sb);
+      rhs_vjp(y, kb, F, G, Q, r1, sb, Qb, Gb, rb1);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) yb.A[i][q] += acc.A[i][q] + sb.A[i][q];
+        yb.e[i] += acc.e[i] + sb.e[i];
+      }
+#pragma unroll
+      for (int i = 0; i < Sym<N>::size; ++i) yb.J[i] += acc.J[i] + sb.J[i];
+      // reference-sample adjoints: j1 (stage 1), j1 - 1 (stages 2, 3), j1 - 2 (stage 4); the
+      // block's first sample (step n - 1, stage 4) and last sample (step 0, stage 1) are shared
+      // with the neighbouring blocks and summed by k_adj_bnd.
+#pragma unroll
+      for (int q = 0; q < N; ++q) drp[(j1 - 1) * N + q] = rb2[q];
+      if (m == n - 1) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) bnd[((long)p * T + k) * 2 * N + q] = rb4[q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < N; ++q) drp[(j1 - 2) * N + q] = rb4[q] + carry[q];
+      }
+#pragma unroll
+      for (int q = 0; q < N; ++q) carry[q] = rb1[q];
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) bnd[((long)p * T + k) * 2 * N + N + q] = carry[q];
+  }
+  // Wave sums of the Q and G adjoints (deterministic, one record per wave).
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R a = Qb[i][q], b = Gb[i][q];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+      }
+      Qb[i][q] = a;
+      Gb[i][q] = b;
+    }
+  if (lane == 0) {
+    const long nw = (T + kT - 1) / kT;
+    R* ws = wsum + ((long)p * nw + blockIdx.x) * 2 * N * N;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        ws[i * N + q] = Qb[i][q];
+        ws[N * N + i * N + q] = Gb[i][q];
+      }
+  }
+}
+
+// Reference samples on block boundaries: sample 2 n k is the last of block k - 1 and the first
+// of block k.
+template <int N, class R>
+__global__ __launch_bounds__(kT) void k_adj_bnd(const KProb kp, const R* __restrict__ bnd,
+                                               R* __restrict__ dr) {
+  const int p = blockIdx.y;
+  const long k = gidx();
+  const long T = kp.T;
+  if (k > T) return;
+  const long nsamp = 2L * kp.n * T + 1;
+  R* drp = dr + (long)p * nsamp * N;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    R s = R(0);
+    if (k < T) s += bnd[((long)p * T + k) * 2 * N + q];
+    if (k > 0) s += bnd[((long)p * T + k - 1) * 2 * N + N + q];
+    drp[2L * kp.n * k * N + q] = s;
+  }
+}
+
+// Per problem: Q and G adjoints summed over the waves, symmetrised; R from G = L R^{-1} L^T:
+// Rbar = -Kc Gbar Kc^T with Kc = R^{-1} L^T.
+template <int N, int NU, class R>
+__global__ __launch_bounds__(kT) void k_adj_sum(const KProb kp, const R* __restrict__ wsum,
+                                               R* __restrict__ dQ, R* __restrict__ dR) {
+  const int p = blockIdx.y;
+  const int lane = threadIdx.x;
+  const long nw = (kp.T + kT - 1) / kT;
+  R acc[2 * N * N];
+#pragma unroll
+  for (int i = 0; i < 2 * N * N; ++i) acc[i] = R(0);
+  for (long w = lane; w < nw; w += kT) {
+    const R* ws = wsum + ((long)p * nw + w) * 2 * N * N;
+#pragma unroll
+    for (int i = 0; i < 2 * N * N; ++i) acc[i] += ws[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 2 * N * N; ++i) {
+    R a = acc[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
+    acc[i] = a;
+  }
+  if (lane != 0) return;
+  R Gs[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      dQ[(long)p * N * N + i * N + q] = R(0.5) * (acc[i * N + q] + acc[q * N + i]);
+      Gs[i][q] = R(0.5) * (acc[N * N + i * N + q] + acc[N * N + q * N + i]);
+    }
+  const R* cs = (const R*)kp.consts + (long)p * CS<N, NU>::size;
+  R KG[NU][N];
+#pragma unroll
+  for (int l = 0; l < NU; ++l)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = R(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) s = fma(cs[CS<N, NU>::Kc + l * N + i], Gs[i][q], s);
+      KG[l][q] = s;
+    }
+#pragma unroll
+  for (int l = 0; l < NU; ++l)
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      R s = R(0);
+#pragma unroll
+      for (int q = 0; q < N; ++q) s = fma(KG[l][q], cs[CS<N, NU>::Kc + m * N + q], s);
+      dR[(long)p * NU * NU + l * NU + m] = -s;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Launchers.
+// ------------------------------------------------------------------------------------------
+inline dim3 lanes(long n, int batch) { return dim3((unsigned)((n + kT - 1) / kT), (unsigned)batch, 1); }
+inline dim3 waves(long w, int batch) { return dim3((unsigned)w, (unsigned)batch, 1); }
+
+template <int N, int NU, class R>
+struct A {
+  static hipError_t lam_bottom(const KProb& kp, const void* elts, const void* S, const void* v,
+                               const void* xbar, void* maps1, long n1, hipStream_t s) {
+    hipLaunchKernelGGL((k_adj_lam_bottom<N, R>), lanes(n1, kp.batch), dim3(kT), 0, s, kp,
+                       (const R*)elts, (const R*)S, (const R*)v, (const R*)xbar, (R*)maps1, n1);
+    return hipGetLastError();
+  }
+  static hipError_t lam_up(const KProb& kp, const void* src, long n_src, void* part, void* dst,
+                           long n_dst, hipStream_t s) {
+    hipLaunchKernelGGL((k_up<LamAlg<N, R>, R>), waves(n_dst, kp.batch), dim3(kT), 0, s,
+                       (const R*)src, n_src, (R*)part, (R*)dst, n_dst);
+    return hipGetLastError();
+  }
+  static hipError_t lam_top(const KProb& kp, const void* xbar, const void* src, long n,
+                            void* out, hipStream_t s) {
+    hipLaunchKernelGGL((k_top<LamAlg<N, R>, R>), dim3(1, kp.batch, 1), dim3(kT), 0, s, kp,
+                       (const R*)xbar, (const R*)src, n, (R*)out);
+    return hipGetLastError();
+  }
+  static hipError_t lam_down(const KProb& kp, const void* src, long n_child, const void* part,
+                             const void* st_par, long n_par, void* st_child, hipStream_t s) {
+    hipLaunchKernelGGL((k_down<LamAlg<N, R>, R>), waves(n_par, kp.batch), dim3(kT), 0, s,
+                       (const R*)src, n_child, (const R*)part, (const R*)st_par, n_par,
+                       (R*)st_child);
+    return hipGetLastError();
+  }
+  static hipError_t cong_bottom(const KProb& kp, const void* elts, const void* S, const void* v,
+                                const void* x, const void* xbar, const void* lam1, long n1,
+                                void* lam, void* maps1, void* dx0, hipStream_t s) {
+    hipLaunchKernelGGL((k_adj_cong_bottom<N, R>), lanes(n1, kp.batch), dim3(kT), 0, s, kp,
+                       (const R*)elts, (const R*)S, (const R*)v, (const R*)x, (const R*)xbar,
+                       (const R*)lam1, n1, (R*)lam, (R*)maps1, (R*)dx0);
+    return hipGetLastError();
+  }
+  static hipError_t cong_up(const KProb& kp, const void* src, long n_src, void* part, void* dst,
+                            long n_dst, hipStream_t s) {
+    hipLaunchKernelGGL((k_up<CongAlg<N, R>, R>), waves(n_dst, kp.batch), dim3(kT), 0, s,
+                       (const R*)src, n_src, (R*)part, (R*)dst, n_dst);
+    return hipGetLastError();
+  }
+  static hipError_t cong_top(const KProb& kp, const void* src, long n, void* out, hipStream_t s) {
+    hipLaunchKernelGGL((k_top<CongAlg<N, R>, R>), dim3(1, kp.batch, 1), dim3(kT), 0, s, kp,
+                       (const R*)nullptr, (const R*)src, n, (R*)out);
+    return hipGetLastError();
+  }
+  static hipError_t cong_down(const KProb& kp, const void* src, long n_child, const void* part,
+                              const void* st_par, long n_par, void* st_child, hipStream_t s) {
+    hipLaunchKernelGGL((k_down<CongAlg<N, R>, R>), waves(n_par, kp.batch), dim3(kT), 0, s,
+                       (const R*)src, n_child, (const R*)part, (const R*)st_par, n_par,
+                       (R*)st_child);
+    return hipGetLastError();
+  }
+  static hipError_t elem(const KProb& kp, void* elts, const void* S, const void* v,
+                         const void* x, const void* lam, const void* sv1, long n1, void* dQf,
+                         void* drf, hipStream_t s) {
+    hipLaunchKernelGGL((k_adj_elem<N, R>), lanes(n1, kp.batch), dim3(kT), 0, s, kp, (R*)elts,
+                       (const R*)S, (const R*)v, (const R*)x, (const R*)lam, (const R*)sv1, n1,
+                       (R*)dQf, (R*)drf);
+    return hipGetLastError();
+  }
+  static hipError_t rk4(const KProb& kp, const void* abar, void* dr, void* bnd, void* wsum,
+                        hipStream_t s) {
+    hipLaunchKernelGGL((k_adj_rk4<N, NU, R>), lanes(kp.T, kp.batch), dim3(kT), 0, s, kp,
+                       (const R*)abar, (R*)dr, (R*)bnd, (R*)wsum);
+    return hipGetLastError();
+  }
+  static hipError_t finish(const KProb& kp, const void* bnd, void* dr, const void* wsum, void* dQ,
+                           void* dR, hipStream_t s) {
+    hipLaunchKernelGGL((k_adj_bnd<N, R>), lanes(kp.T + 1, kp.batch), dim3(kT), 0, s, kp,
+                       (const R*)bnd, (R*)dr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_adj_sum<N, NU, R>), dim3(1, kp.batch, 1), dim3(kT), 0, s, kp,
+                       (const R*)wsum, (R*)dQ, (R*)dR);
+    return hipGetLastError();
+  }
+  static const AdjOps* ops() {
+    static const AdjOps o = {lam_bottom, lam_up,   lam_top,  lam_down, cong_bottom,
+                             cong_up,    cong_top, cong_down, elem,    rk4,
+                             finish};
+    return &o;
+  }
+};
+
+template <class R>
+const AdjOps* adj_for(int nx, int nu) {
+  switch (nx * 8 + nu) {
+    case 1 * 8 + 1: return A<1, 1, R>::ops();
+    case 2 * 8 + 1: return A<2, 1, R>::ops();
+    case 2 * 8 + 2: return A<2, 2, R>::ops();
+    case 3 * 8 + 1: return A<3, 1, R>::ops();
+    case 3 * 8 + 2: return A<3, 2, R>::ops();
+    case 3 * 8 + 3: return A<3, 3, R>::ops();
+    case 4 * 8 + 1: return A<4, 1, R>::ops();
+    case 4 * 8 + 2: return A<4, 2, R>::ops();
+    case 4 * 8 + 3: return A<4, 3, R>::ops();
+    case 4 * 8 + 4: return A<4, 4, R>::ops();
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+const AdjOps* adj_ops(int nx, int nu, int dtype) {
+  return dtype == 0 ? adj_for<double>(nx, nu) : nullptr;
+}
+
+}  // namespace lqt

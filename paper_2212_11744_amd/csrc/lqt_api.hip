@@ -93,9 +93,38 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w) {
       }
     }
   }
-  if (call == LQT_CALL_SOLVE) {
+  if (call == LQT_CALL_SOLVE || call == LQT_CALL_BACKWARD) {
     void* e = take(es * B * ne_of(d->nx) * (size_t)padt(d->T));
     if (w) w->elts = e;
+  }
+  if (call == LQT_CALL_BACKWARD) {
+    const long nx = d->nx, ns = nx * (nx + 1) / 2;
+    const long ncm = nx * nx + 2 * nx + ns, ncs = ns + nx;
+    for (int l = 1; l <= t.levels; ++l) {
+      const long lanes_above = l < t.levels ? t.n[l + 1] * 64 : 0;
+      void* a = take(es * B * nm_of(d->nx) * padt(t.n[l]));
+      void* b = take(es * B * nx * padt(t.n[l]));
+      void* c = lanes_above ? take(es * B * nm_of(d->nx) * padt(lanes_above)) : nullptr;
+      void* e = take(es * B * ncm * padt(t.n[l]));
+      void* f = take(es * B * ncs * padt(t.n[l]));
+      void* g = lanes_above ? take(es * B * ncm * padt(lanes_above)) : nullptr;
+      if (w) {
+        w->lmap[l] = a;
+        w->lst[l] = b;
+        w->lpart[l] = c;
+        w->cmap[l] = e;
+        w->cst[l] = f;
+        w->cpart[l] = g;
+      }
+    }
+    void* lam = take(es * B * (size_t)(d->T + 1) * nx);
+    void* bnd = take(es * B * (size_t)d->T * 2 * nx);
+    void* ws = take(es * B * (size_t)((d->T + 63) / 64) * 2 * nx * nx);
+    if (w) {
+      w->lam = lam;
+      w->bnd = bnd;
+      w->wsum = ws;
+    }
   }
   return off;
 }
@@ -331,10 +360,50 @@ lqt_status lqt_backward(const lqt_dims* dims, const lqt_problem* prob, const voi
                         const void* v, const void* x, const void* dLdx, void* dQ, void* dR,
                         void* dr, void* dx0, void* dQf, void* drf, void* ws, size_t ws_bytes,
                         hipStream_t stream) {
-  (void)prob; (void)S; (void)v; (void)x; (void)dLdx; (void)dQ; (void)dR; (void)dr; (void)dx0;
-  (void)dQf; (void)drf; (void)ws; (void)ws_bytes; (void)stream;
   LQT_TRY(check_supported(dims));
-  return fail(LQT_EUNSUPPORTED, "lqt_backward is not available in this build");
+  if (dims->F_sampled || dims->L_sampled || dims->has_c)
+    return fail(LQT_EUNSUPPORTED, "lqt_backward needs constant F and L and c = 0");
+  const AdjOps* ao = adj_ops(dims->nx, dims->nu, dims->dtype);
+  if (!ao) return fail(LQT_EUNSUPPORTED, "lqt_backward is available in FP64 for nx <= 4");
+  LQT_TRY(check_problem(dims, prob, true, true));
+  const size_t es = dsize(dims->dtype);
+  LQT_TRY(check_ptr(S, "S", es));
+  LQT_TRY(check_ptr(v, "v", es));
+  LQT_TRY(check_ptr(x, "x", es));
+  LQT_TRY(check_ptr(dLdx, "dLdx", es));
+  LQT_TRY(check_ptr(dQ, "dQ", es));
+  LQT_TRY(check_ptr(dR, "dR", es));
+  LQT_TRY(check_ptr(dr, "dr", es));
+  LQT_TRY(check_ptr(dx0, "dx0", es));
+  if (dQf) LQT_TRY(check_ptr(dQf, "dQf", es));
+  if (drf) LQT_TRY(check_ptr(drf, "drf", es));
+  Work w;
+  LQT_TRY(check_ws(dims, LQT_CALL_BACKWARD, ws, ws_bytes, &w));
+  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
+  KProb kp = make_kprob(dims, prob, w.consts);
+  const Tree t = tree_for(dims);
+  hipStream_t s = stream;
+  LQT_HIP(o->prep(kp, w.consts, s));
+  LQT_HIP(o->build(kp, w.elts, s));
+  // lambda_k = xbar_k + Psi_k^T lambda_{k+1} (backward)
+  LQT_HIP(ao->lam_bottom(kp, w.elts, S, v, dLdx, w.lmap[1], t.n[1], s));
+  for (int l = 1; l < t.levels; ++l)
+    LQT_HIP(ao->lam_up(kp, w.lmap[l], t.n[l], w.lpart[l], w.lmap[l + 1], t.n[l + 1], s));
+  LQT_HIP(ao->lam_top(kp, dLdx, w.lmap[t.levels], t.n[t.levels], w.lst[t.levels], s));
+  for (int l = t.levels - 1; l >= 1; --l)
+    LQT_HIP(ao->lam_down(kp, w.lmap[l], t.n[l], w.lpart[l], w.lst[l + 1], t.n[l + 1], w.lst[l], s));
+  // (Sbar_k, vbar_k) (forward)
+  LQT_HIP(ao->cong_bottom(kp, w.elts, S, v, x, dLdx, w.lst[1], t.n[1], w.lam, w.cmap[1], dx0, s));
+  for (int l = 1; l < t.levels; ++l)
+    LQT_HIP(ao->cong_up(kp, w.cmap[l], t.n[l], w.cpart[l], w.cmap[l + 1], t.n[l + 1], s));
+  LQT_HIP(ao->cong_top(kp, w.cmap[t.levels], t.n[t.levels], w.cst[t.levels], s));
+  for (int l = t.levels - 1; l >= 1; --l)
+    LQT_HIP(ao->cong_down(kp, w.cmap[l], t.n[l], w.cpart[l], w.cst[l + 1], t.n[l + 1], w.cst[l], s));
+  // element gradients, then the RK4 adjoint of every block and the reductions
+  LQT_HIP(ao->elem(kp, w.elts, S, v, x, w.lam, w.cst[1], t.n[1], dQf, drf, s));
+  LQT_HIP(ao->rk4(kp, w.elts, dr, w.bnd, w.wsum, s));
+  LQT_HIP(ao->finish(kp, w.bnd, dr, w.wsum, dQ, dR, s));
+  return ok();
 }
 
 const char* lqt_status_string(lqt_status s) {

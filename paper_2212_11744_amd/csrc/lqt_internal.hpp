@@ -54,6 +54,16 @@ struct Work {
   void* tx[kMaxLevels + 1] = {};     // trajectory tree: x at left ends of level-l nodes
   void* tpart[kMaxLevels + 1] = {};  // trajectory tree: lane partials above level l
   void* elts = nullptr;              // elements when the caller gives none (lqt_solve)
+  // adjoint
+  void* lmap[kMaxLevels + 1] = {};   // lambda scan: maps, states, lane partials per level
+  void* lst[kMaxLevels + 1] = {};
+  void* lpart[kMaxLevels + 1] = {};
+  void* cmap[kMaxLevels + 1] = {};   // (Sbar, vbar) scan
+  void* cst[kMaxLevels + 1] = {};
+  void* cpart[kMaxLevels + 1] = {};
+  void* lam = nullptr;               // lambda_k, [batch][T+1][nx]
+  void* bnd = nullptr;               // adjoints of block-boundary samples, [batch][T][2][nx]
+  void* wsum = nullptr;              // per-wave sums of the Q and G adjoints
 };
 
 // Kernel launchers of one (nx, nu, dtype) instantiation.  Each returns hipGetLastError().
@@ -81,6 +91,36 @@ struct Ops {
   hipError_t (*tbottom)(const KProb&, const void* elts, const void* S, const void* v,
                         const void* x1, long n1, void* x, void* u, hipStream_t);
 };
+
+// Adjoint kernels (lqt_adjoint.hip) of one (nx, nu, dtype) instantiation.
+struct AdjOps {
+  hipError_t (*lam_bottom)(const KProb&, const void* elts, const void* S, const void* v,
+                           const void* xbar, void* maps1, long n1, hipStream_t);
+  hipError_t (*lam_up)(const KProb&, const void* src, long n_src, void* part, void* dst,
+                       long n_dst, hipStream_t);
+  hipError_t (*lam_top)(const KProb&, const void* xbar, const void* src, long n, void* out,
+                        hipStream_t);
+  hipError_t (*lam_down)(const KProb&, const void* src, long n_child, const void* part,
+                         const void* st_par, long n_par, void* st_child, hipStream_t);
+  hipError_t (*cong_bottom)(const KProb&, const void* elts, const void* S, const void* v,
+                            const void* x, const void* xbar, const void* lam1, long n1, void* lam,
+                            void* maps1, void* dx0, hipStream_t);
+  hipError_t (*cong_up)(const KProb&, const void* src, long n_src, void* part, void* dst,
+                        long n_dst, hipStream_t);
+  hipError_t (*cong_top)(const KProb&, const void* src, long n, void* out, hipStream_t);
+  hipError_t (*cong_down)(const KProb&, const void* src, long n_child, const void* part,
+                          const void* st_par, long n_par, void* st_child, hipStream_t);
+  hipError_t (*elem)(const KProb&, void* elts, const void* S, const void* v, const void* x,
+                     const void* lam, const void* sv1, long n1, void* dQf, void* drf,
+                     hipStream_t);
+  hipError_t (*rk4)(const KProb&, const void* abar, void* dr, void* bnd, void* wsum,
+                    hipStream_t);
+  hipError_t (*finish)(const KProb&, const void* bnd, void* dr, const void* wsum, void* dQ,
+                       void* dR, hipStream_t);
+};
+
+// FP64 adjoint instantiations for 1 <= nu <= nx <= 4; nullptr otherwise.
+const AdjOps* adj_ops(int nx, int nu, int dtype);
 
 // Instantiations for 1 <= nu <= nx <= 4 (one tuple per lane); nullptr if not available.
 const Ops* lane_ops(int nx, int nu, int dtype);

@@ -7,21 +7,21 @@
 //   k_build        element build: Theorem 8 (Sec. IV-B) integrated with classical RK4.
 //   k_vreduce0     value tree, level 1: products a_j (x) ... (x) a_{j+3} of 4 blocks per lane
 //                  (Lemma 7).
-//   k_vup          value tree, upper levels: 4 nodes per lane, then a wavefront tree (256 nodes
-//                  per wave); lane partials are kept for the downward pass.
-//   k_vtop         value tree, top (<= 256 nodes, one wave): up-sweep, then the downward pass
-//                  from the terminal element (Sec. IV-D).
-//   k_vdown        value tree, downward: value at the right end of every child node.
+//   k_up / k_top / k_down (tree_scan.hpp) with ValAlg and TrajAlg
+//                  upper levels of the value scan (tuples, states (S, v) carried backward from
+//                  the terminal element of Sec. IV-D) and of the trajectory scan (affine block
+//                  maps, state x carried forward from x0).
 //   k_vbottom      values S_k, v_k of every block (Theorem 6), optionally with the level-1
 //                  products of the closed-loop block maps for the trajectory.
-//   k_tbottom_reduce / k_tup / k_ttop / k_tdown / k_tbottom
-//                  trajectory: composition scan of the block maps x_{k+1} = Psi_k x_k + alpha_k
-//                  (Method 1, Sec. IV-E) with the same tree shape, and the control law u_k
-//                  (Sec. II-B).
+//   k_tbottom_reduce / k_tbottom
+//                  trajectory: level 1 of the composition scan of the block maps
+//                  x_{k+1} = Psi_k x_k + alpha_k (Method 1, Sec. IV-E), then x_k and the control
+//                  law u_k (Sec. II-B) of every block.
 // Tree shape: level 1 has ceil(T / 4) nodes (4 blocks per lane); level l + 1 has
 // ceil(n_l / 256) nodes while n_l > 256; the top level (<= 256 nodes) is one wave.
 #include "lane_math.hpp"
 #include "lqt_internal.hpp"
+#include "tree_scan.hpp"
 #include "wave_tree.hpp"
 
 namespace lqt {
@@ -34,7 +34,6 @@ struct CS {
 };
 
 __device__ inline long gid() { return (long)blockIdx.x * blockDim.x + threadIdx.x; }
-__host__ __device__ inline long padt(long n) { return (n + kTile - 1) / kTile * kTile; }
 
 // ------------------------------------------------------------------------------------------
 // Element build (Theorem 8):
@@ -387,76 +386,6 @@ LQT_DEV void terminal_value(const KProb& kp, int p, R (&S)[Sym<N>::size], R (&v)
   }
 }
 
-// Serial downward sweep over the <= 4 nodes [j0, j1): node j receives the value at its right end,
-// then the value is folded through node j (right to left).
-template <int N, class R>
-LQT_DEV void serial_values(const R* __restrict__ tp, long j0, long j1, R (&S)[Sym<N>::size],
-                           R (&v)[N], R* __restrict__ vo) {
-  for (long j = j1 - 1; j >= j0; --j) {
-    val_store<N, R>(S, v, vo, j);
-    if (j == j0) break;
-    Tup<N, R> a;
-    tup_load(a, tp, j);
-    Aff<N, R> m;
-    fold(a, S, v, m);
-  }
-}
-
-// Upper level: lanes own 4 consecutive nodes, a wave 256; one output node per wave.
-template <int N, class R>
-__global__ __launch_bounds__(kThreads) void k_vup(const R* __restrict__ src, long n_src,
-                                                   R* __restrict__ part, R* __restrict__ dst,
-                                                   long n_dst) {
-  const int p = blockIdx.y;
-  const long gl = gid();
-  const int lane = threadIdx.x & 63;
-  const long w = gl >> 6;
-  if (w >= n_dst) return;
-  const long j0 = gl * kChunk, j1 = min(j0 + kChunk, n_src);
-  Tup<N, R> P;
-  serial_product(src + (long)p * Lay<N>::NE * padt(n_src), j0, j1, P);
-  wave_up_value(P, lane);
-  tup_store(P, part + (long)p * Lay<N>::NE * padt(n_dst * 64), gl);
-  if (lane == 0) tup_store(P, dst + (long)p * Lay<N>::NE * padt(n_dst), w);
-}
-
-template <int N, class R>
-__global__ __launch_bounds__(kThreads) void k_vtop(const KProb kp, const R* __restrict__ tup,
-                                                    long n, R* __restrict__ val) {
-  const int p = blockIdx.y;
-  const int lane = threadIdx.x;
-  const R* tp = tup + (long)p * Lay<N>::NE * padt(n);
-  const long j0 = (long)lane * kChunk, j1 = min(j0 + kChunk, n);
-  const int levels = tree_levels((n + kChunk - 1) / kChunk);
-  Tup<N, R> P;
-  serial_product(tp, j0, j1, P);
-  wave_up_value(P, lane, levels);
-  R S[Sym<N>::size], v[N];
-  terminal_value<N, R>(kp, p, S, v);
-  wave_down_value(P, S, v, lane, levels);
-  serial_values<N, R>(tp, j0, j1, S, v, val + (long)p * Lay<N>::NV * padt(n));
-}
-
-template <int N, class R>
-__global__ __launch_bounds__(kThreads) void k_vdown(const R* __restrict__ tup, long n_child,
-                                                     const R* __restrict__ part,
-                                                     const R* __restrict__ val_par, long n_par,
-                                                     R* __restrict__ val_child) {
-  const int p = blockIdx.y;
-  const long gl = gid();
-  const int lane = threadIdx.x & 63;
-  const long w = gl >> 6;
-  if (w >= n_par) return;
-  R S[Sym<N>::size], v[N];
-  val_load<N, R>(S, v, val_par + (long)p * Lay<N>::NV * padt(n_par), w);
-  Tup<N, R> P;
-  tup_load(P, part + (long)p * Lay<N>::NE * padt(n_par * 64), gl);
-  wave_down_value(P, S, v, lane);
-  const long j0 = gl * kChunk, j1 = min(j0 + kChunk, n_child);
-  serial_values<N, R>(tup + (long)p * Lay<N>::NE * padt(n_child), j0, j1, S, v,
-                      val_child + (long)p * Lay<N>::NV * padt(n_child));
-}
-
 template <int N, class R>
 LQT_DEV void S_store_full(const R (&S)[Sym<N>::size], R* dst) {
 #pragma unroll
@@ -558,91 +487,6 @@ __global__ __launch_bounds__(kThreads) void k_tbottom_reduce(const KProb kp,
     aff_then(acc, m);
   }
   aff_store(acc, maps1 + (long)p * Lay<N>::NM * padt(n1), i);
-}
-
-template <int N, class R>
-LQT_DEV void serial_compose(const R* __restrict__ s, long j0, long j1, Aff<N, R>& acc) {
-  if (j0 >= j1) {
-    aff_identity(acc);
-    return;
-  }
-  aff_load(acc, s, j0);
-  for (long j = j0 + 1; j < j1; ++j) {
-    Aff<N, R> m;
-    aff_load(m, s, j);
-    aff_then(acc, m);
-  }
-}
-
-// Serial forward sweep over the <= 4 nodes [j0, j1): node j receives the state at its left end,
-// then the state is carried through node j's map.
-template <int N, class R>
-LQT_DEV void serial_states(const R* __restrict__ mp, long j0, long j1, R (&x)[N],
-                           R* __restrict__ xo) {
-  for (long j = j0; j < j1; ++j) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) xo[tix<N>(q, j)] = x[q];
-    if (j == j1 - 1) break;
-    Aff<N, R> m;
-    aff_load(m, mp, j);
-    aff_apply(m, x);
-  }
-}
-
-template <int N, class R>
-__global__ __launch_bounds__(kThreads) void k_tup(const R* __restrict__ src, long n_src,
-                                                   R* __restrict__ part, R* __restrict__ dst,
-                                                   long n_dst) {
-  const int p = blockIdx.y;
-  const long gl = gid();
-  const int lane = threadIdx.x & 63;
-  const long w = gl >> 6;
-  if (w >= n_dst) return;
-  const long j0 = gl * kChunk, j1 = min(j0 + kChunk, n_src);
-  Aff<N, R> P;
-  serial_compose(src + (long)p * Lay<N>::NM * padt(n_src), j0, j1, P);
-  wave_up_traj(P, lane);
-  aff_store(P, part + (long)p * Lay<N>::NM * padt(n_dst * 64), gl);
-  if (lane == 63) aff_store(P, dst + (long)p * Lay<N>::NM * padt(n_dst), w);
-}
-
-template <int N, class R>
-__global__ __launch_bounds__(kThreads) void k_ttop(const KProb kp, const R* __restrict__ maps,
-                                                    long n, R* __restrict__ xs) {
-  const int p = blockIdx.y;
-  const int lane = threadIdx.x;
-  const R* mp = maps + (long)p * Lay<N>::NM * padt(n);
-  const long j0 = (long)lane * kChunk, j1 = min(j0 + kChunk, n);
-  const int levels = tree_levels((n + kChunk - 1) / kChunk);
-  Aff<N, R> P;
-  serial_compose(mp, j0, j1, P);
-  wave_up_traj(P, lane, levels);
-  R x[N];
-#pragma unroll
-  for (int q = 0; q < N; ++q) x[q] = ((const R*)kp.x0)[(long)p * N + q];
-  wave_down_traj(P, x, lane, levels);
-  serial_states<N, R>(mp, j0, j1, x, xs + (long)p * N * padt(n));
-}
-
-template <int N, class R>
-__global__ __launch_bounds__(kThreads) void k_tdown(const R* __restrict__ maps, long n_child,
-                                                     const R* __restrict__ part,
-                                                     const R* __restrict__ x_par, long n_par,
-                                                     R* __restrict__ x_child) {
-  const int p = blockIdx.y;
-  const long gl = gid();
-  const int lane = threadIdx.x & 63;
-  const long w = gl >> 6;
-  if (w >= n_par) return;
-  R x[N];
-#pragma unroll
-  for (int q = 0; q < N; ++q) x[q] = x_par[(long)p * N * padt(n_par) + tix<N>(q, w)];
-  Aff<N, R> P;
-  aff_load(P, part + (long)p * Lay<N>::NM * padt(n_par * 64), gl);
-  wave_down_traj(P, x, lane);
-  const long j0 = gl * kChunk, j1 = min(j0 + kChunk, n_child);
-  serial_states<N, R>(maps + (long)p * Lay<N>::NM * padt(n_child), j0, j1, x,
-                      x_child + (long)p * N * padt(n_child));
 }
 
 // u = -Kc (S x - v) with Kc = R^{-1} L(t_k)^T.
@@ -831,6 +675,78 @@ __global__ __launch_bounds__(kThreads) void k_prep_lane(const KProb kp, R* __res
 }
 
 // ------------------------------------------------------------------------------------------
+// Algebras of the two forward-pass scans (see tree_scan.hpp).
+// ------------------------------------------------------------------------------------------
+// Value scan: tuples combined by Lemma 7, states (S, v) carried backward by the fold (Theorem 6
+// with the terminal element of Sec. IV-D as the boundary state).
+template <int N, class R>
+struct ValAlg {
+  static constexpr bool kForward = false;
+  static constexpr int NMAP = Lay<N>::NE, NST = Lay<N>::NV;
+  using Map = Tup<N, R>;
+  struct State {
+    R S[Sym<N>::size];
+    R v[N];
+  };
+  static LQT_DEV void identity(Map& m) { tup_identity(m); }
+  static LQT_DEV void load(Map& m, const R* b, long k) { tup_load(m, b, k); }
+  static LQT_DEV void store(const Map& m, R* b, long k) { tup_store(m, b, k); }
+  static LQT_DEV void chain(const Map& first, const Map& second, Map& out) {
+    Map o;
+    combine(first, second, o);
+    out = o;
+  }
+  static LQT_DEV void apply(const Map& m, State& st) {
+    Aff<N, R> unused;
+    fold(m, st.S, st.v, unused);
+  }
+  static LQT_DEV void sload(State& st, const R* b, long k) { val_load<N, R>(st.S, st.v, b, k); }
+  static LQT_DEV void sstore(const State& st, R* b, long k) { val_store<N, R>(st.S, st.v, b, k); }
+  static LQT_DEV void shfl_map(const Map& x, Map& y, int src) { shfl_tup(x, y, src); }
+  static LQT_DEV void shfl_state(const State& x, State& y, int src) {
+    shfl_val<N, R>(x.S, x.v, y.S, y.v, src);
+  }
+  static LQT_DEV void init(const KProb& kp, const R*, int p, State& st) {
+    terminal_value<N, R>(kp, p, st.S, st.v);
+  }
+};
+
+// Trajectory scan: closed-loop block maps composed in time order, the state x carried forward
+// from x0 (Method 1, Sec. IV-E).
+template <int N, class R>
+struct TrajAlg {
+  static constexpr bool kForward = true;
+  static constexpr int NMAP = Lay<N>::NM, NST = N;
+  using Map = Aff<N, R>;
+  struct State {
+    R x[N];
+  };
+  static LQT_DEV void identity(Map& m) { aff_identity(m); }
+  static LQT_DEV void load(Map& m, const R* b, long k) { aff_load(m, b, k); }
+  static LQT_DEV void store(const Map& m, R* b, long k) { aff_store(m, b, k); }
+  static LQT_DEV void chain(const Map& first, const Map& second, Map& out) {
+    Map o = first;
+    aff_then(o, second);
+    out = o;
+  }
+  static LQT_DEV void apply(const Map& m, State& st) { aff_apply(m, st.x); }
+  static LQT_DEV void sload(State& st, const R* b, long k) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) st.x[q] = b[tix<N>(q, k)];
+  }
+  static LQT_DEV void sstore(const State& st, R* b, long k) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) b[tix<N>(q, k)] = st.x[q];
+  }
+  static LQT_DEV void shfl_map(const Map& x, Map& y, int src) { shfl_aff(x, y, src); }
+  static LQT_DEV void shfl_state(const State& x, State& y, int src) { shfl_vec<N, R>(x.x, y.x, src); }
+  static LQT_DEV void init(const KProb& kp, const R*, int p, State& st) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) st.x[q] = ((const R*)kp.x0)[(long)p * N + q];
+  }
+};
+
+// ------------------------------------------------------------------------------------------
 // Launchers.
 // ------------------------------------------------------------------------------------------
 inline dim3 grid_lanes(long n, int batch) {
@@ -869,19 +785,19 @@ struct L {
   }
   static hipError_t vup(const KProb& kp, const void* src, long n_src, void* part, void* dst,
                         long n_dst, hipStream_t s) {
-    hipLaunchKernelGGL((k_vup<N, R>), grid_waves(n_dst, kp.batch), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL((k_up<ValAlg<N, R>, R>), grid_waves(n_dst, kp.batch), dim3(kThreads), 0, s,
                        (const R*)src, n_src, (R*)part, (R*)dst, n_dst);
     return hipGetLastError();
   }
   static hipError_t vtop(const KProb& kp, const void* tup, long n, void* val, hipStream_t s) {
-    hipLaunchKernelGGL((k_vtop<N, R>), dim3(1, kp.batch, 1), dim3(kThreads), 0, s, kp,
-                       (const R*)tup, n, (R*)val);
+    hipLaunchKernelGGL((k_top<ValAlg<N, R>, R>), dim3(1, kp.batch, 1), dim3(kThreads), 0, s, kp,
+                       (const R*)nullptr, (const R*)tup, n, (R*)val);
     return hipGetLastError();
   }
   static hipError_t vdown(const KProb& kp, const void* tup, long n_child, const void* part,
                           const void* val_par, long n_par, void* val_child, hipStream_t s) {
-    hipLaunchKernelGGL((k_vdown<N, R>), grid_waves(n_par, kp.batch), dim3(kThreads), 0, s,
-                       (const R*)tup, n_child, (const R*)part, (const R*)val_par, n_par,
+    hipLaunchKernelGGL((k_down<ValAlg<N, R>, R>), grid_waves(n_par, kp.batch), dim3(kThreads), 0,
+                       s, (const R*)tup, n_child, (const R*)part, (const R*)val_par, n_par,
                        (R*)val_child);
     return hipGetLastError();
   }
@@ -899,19 +815,19 @@ struct L {
   }
   static hipError_t tup(const KProb& kp, const void* src, long n_src, void* part, void* dst,
                         long n_dst, hipStream_t s) {
-    hipLaunchKernelGGL((k_tup<N, R>), grid_waves(n_dst, kp.batch), dim3(kThreads), 0, s,
-                       (const R*)src, n_src, (R*)part, (R*)dst, n_dst);
+    hipLaunchKernelGGL((k_up<TrajAlg<N, R>, R>), grid_waves(n_dst, kp.batch), dim3(kThreads), 0,
+                       s, (const R*)src, n_src, (R*)part, (R*)dst, n_dst);
     return hipGetLastError();
   }
   static hipError_t ttop(const KProb& kp, const void* maps, long n, void* xs, hipStream_t s) {
-    hipLaunchKernelGGL((k_ttop<N, R>), dim3(1, kp.batch, 1), dim3(kThreads), 0, s, kp,
-                       (const R*)maps, n, (R*)xs);
+    hipLaunchKernelGGL((k_top<TrajAlg<N, R>, R>), dim3(1, kp.batch, 1), dim3(kThreads), 0, s, kp,
+                       (const R*)nullptr, (const R*)maps, n, (R*)xs);
     return hipGetLastError();
   }
   static hipError_t tdown(const KProb& kp, const void* maps, long n_child, const void* part,
                           const void* x_par, long n_par, void* x_child, hipStream_t s) {
-    hipLaunchKernelGGL((k_tdown<N, R>), grid_waves(n_par, kp.batch), dim3(kThreads), 0, s,
-                       (const R*)maps, n_child, (const R*)part, (const R*)x_par, n_par,
+    hipLaunchKernelGGL((k_down<TrajAlg<N, R>, R>), grid_waves(n_par, kp.batch), dim3(kThreads),
+                       0, s, (const R*)maps, n_child, (const R*)part, (const R*)x_par, n_par,
                        (R*)x_child);
     return hipGetLastError();
   }

@@ -262,3 +262,36 @@ def element_slices(nx: int):
 
 def upper_indices(nx: int):
     return np.triu_indices(nx)
+
+
+# --------------------------------------------------------------------------------------------
+# Autograd: x = solve(Q, R, r, x0, Qf, rf) with the hand-written adjoint as backward.
+# --------------------------------------------------------------------------------------------
+class SolveTrajectory(torch.autograd.Function):
+    """Optimal trajectory x [batch][T+1][nx] as a differentiable function of Q, R, r, x0, Qf, rf.
+
+    The forward pass is lqt_solve; the backward pass is lqt_backward (the exact adjoint of the
+    discrete scheme), which receives dL/dx and returns symmetric gradients for Q, R, Qf.
+    `template` supplies the fixed parts of the problem (grid, F, L, sizes)."""
+
+    @staticmethod
+    def forward(ctx, Q, R, r, x0, Qf, rf, template: DeviceProblem):
+        prob = DeviceProblem(template.nx, template.nu, template.T, template.n, template.batch,
+                             template.dtype, template.t, template.F, template.L,
+                             Q.contiguous(), R.contiguous(), r.contiguous(), Qf.contiguous(),
+                             rf.contiguous(), x0.contiguous(), template.c, template.F_sampled,
+                             template.L_sampled)
+        out = solve(prob)
+        ctx.prob = prob
+        ctx.save_for_backward(out["S"], out["v"], out["x"])
+        return out["x"]
+
+    @staticmethod
+    def backward(ctx, gx):
+        S, v, x = ctx.saved_tensors
+        g = backward(ctx.prob, S, v, x, gx.contiguous())
+        return g["Q"], g["R"], g["r"], g["x0"], g["Qf"], g["rf"], None
+
+
+def solve_trajectory(Q, R, r, x0, Qf, rf, template: DeviceProblem):
+    return SolveTrajectory.apply(Q, R, r, x0, Qf, rf, template)
