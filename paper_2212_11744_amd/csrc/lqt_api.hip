@@ -55,6 +55,14 @@ namespace {
 
 Tree tree_for(const lqt_dims* d) { return plan_tree(d->T); }
 
+// Kernel family of a call: the per-lane path (one tuple per lane, registers) where it is
+// instantiated (nu <= nx <= 4), otherwise the wavefront-per-tuple path (LDS, any nx <= 16).
+bool use_wave(const lqt_dims* d) { return lane_ops(d->nx, d->nu, d->dtype) == nullptr; }
+
+constexpr int kWaveChunk = 8;  // nodes per wave at every level of the wave path's trees
+
+WTree wtree_for(const lqt_dims* d) { return wave_tree(d->T, kWaveChunk); }
+
 // Byte layout of the workspace of one call.  Returns the total; fills w when base != nullptr.
 size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w) {
   const size_t es = dsize(d->dtype);
@@ -67,9 +75,35 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w) {
   };
   void* consts = take(es * B * consts_count(d->nx, d->nu));
   if (w) w->consts = consts;
-  const Tree t = tree_for(d);
   const bool want_v = call == LQT_CALL_SCAN_VALUE || call == LQT_CALL_SOLVE;
   const bool want_t = call == LQT_CALL_FORWARD_TRAJ || call == LQT_CALL_SOLVE;
+  if (use_wave(d)) {
+    const WTree t = wtree_for(d);
+    for (int l = 1; l <= t.levels; ++l) {
+      if (want_v) {
+        void* a = take(es * B * ne_of(d->nx) * t.n[l]);
+        void* b = take(es * B * nm_of(d->nx) * t.n[l]);
+        if (w) {
+          w->vtup[l] = a;
+          w->vval[l] = b;
+        }
+      }
+      if (want_t) {
+        void* a = take(es * B * nm_of(d->nx) * t.n[l]);
+        void* b = take(es * B * d->nx * t.n[l]);
+        if (w) {
+          w->tmap[l] = a;
+          w->tx[l] = b;
+        }
+      }
+    }
+    if (call == LQT_CALL_SOLVE) {
+      void* e = take(es * B * ne_of(d->nx) * (size_t)padt(d->T));
+      if (w) w->elts = e;
+    }
+    return off;
+  }
+  const Tree t = tree_for(d);
   for (int l = 1; l <= t.levels; ++l) {
     const long lanes_above = l < t.levels ? t.n[l + 1] * 64 : 0;
     if (want_v) {
@@ -145,13 +179,11 @@ lqt_status check_dims_valid(const lqt_dims* d) {
   return LQT_OK;
 }
 
-lqt_status check_supported(const lqt_dims* d) {
-  lqt_status st = check_dims_valid(d);
-  if (st != LQT_OK) return st;
-  if (!lane_ops(d->nx, d->nu, d->dtype))
-    return fail(LQT_EUNSUPPORTED, "nx = %d, nu = %d: no kernel instantiation in this build",
-                d->nx, d->nu);
-  return LQT_OK;
+lqt_status check_supported(const lqt_dims* d) { return check_dims_valid(d); }
+
+hipError_t prep(const lqt_dims* d, const KProb& kp, void* consts, hipStream_t s) {
+  if (use_wave(d)) return launch_prep(kp, d->dtype, consts, s);
+  return lane_ops(d->nx, d->nu, d->dtype)->prep(kp, consts, s);
 }
 
 lqt_status check_ptr(const void* p, const char* name, size_t es) {
@@ -274,10 +306,12 @@ lqt_status lqt_build_elements(const lqt_dims* dims, const lqt_problem* prob, voi
   LQT_TRY(check_ptr(elts, "elts", dsize(dims->dtype)));
   Work w;
   LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w));
-  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
   KProb kp = make_kprob(dims, prob, w.consts);
-  LQT_HIP(o->prep(kp, w.consts, stream));
-  LQT_HIP(o->build(kp, elts, stream));
+  LQT_HIP(prep(dims, kp, w.consts, stream));
+  if (use_wave(dims))
+    LQT_HIP(wave_build(kp, dims->dtype, elts, stream));
+  else
+    LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build(kp, elts, stream));
   return ok();
 }
 
@@ -292,12 +326,16 @@ lqt_status lqt_scan_value(const lqt_dims* dims, const void* elts, const void* Qf
   LQT_TRY(check_ptr(v, "v", es));
   Work w;
   LQT_TRY(check_ws(dims, LQT_CALL_SCAN_VALUE, ws, ws_bytes, &w));
-  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
   lqt_problem p;
   memset(&p, 0, sizeof(p));
   p.Qf = Qf;
   p.rf = rf;
   KProb kp = make_kprob(dims, &p, w.consts);
+  if (use_wave(dims)) {
+    LQT_HIP(wave_value(kp, dims->dtype, wtree_for(dims), w, elts, S, v, nullptr, stream));
+    return ok();
+  }
+  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
   LQT_TRY(run_value(o, kp, tree_for(dims), w, elts, S, v, nullptr, false, stream));
   return ok();
 }
@@ -318,10 +356,14 @@ lqt_status lqt_forward_traj(const lqt_dims* dims, const lqt_problem* prob, const
   if (u) LQT_TRY(check_ptr(u, "u", es));
   Work w;
   LQT_TRY(check_ws(dims, LQT_CALL_FORWARD_TRAJ, ws, ws_bytes, &w));
-  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
   KProb kp = make_kprob(dims, prob, w.consts);
+  LQT_HIP(prep(dims, kp, w.consts, stream));
+  if (use_wave(dims)) {
+    LQT_HIP(wave_traj(kp, dims->dtype, wtree_for(dims), w, elts, S, v, x, u, false, stream));
+    return ok();
+  }
+  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
   const Tree t = tree_for(dims);
-  LQT_HIP(o->prep(kp, w.consts, stream));
   LQT_HIP(o->tbottom_reduce(kp, elts, S, v, w.tmap[1], t.n[1], stream));
   LQT_TRY(run_traj(o, kp, t, w, elts, S, v, x, u, stream));
   return ok();
@@ -339,11 +381,18 @@ lqt_status lqt_solve(const lqt_dims* dims, const lqt_problem* prob, void* elts, 
   if (u) LQT_TRY(check_ptr(u, "u", es));
   Work w;
   LQT_TRY(check_ws(dims, LQT_CALL_SOLVE, ws, ws_bytes, &w));
-  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
   KProb kp = make_kprob(dims, prob, w.consts);
-  const Tree t = tree_for(dims);
   void* e = elts ? elts : w.elts;
-  LQT_HIP(o->prep(kp, w.consts, stream));
+  LQT_HIP(prep(dims, kp, w.consts, stream));
+  if (use_wave(dims)) {
+    const WTree wt = wtree_for(dims);
+    LQT_HIP(wave_build(kp, dims->dtype, e, stream));
+    LQT_HIP(wave_value(kp, dims->dtype, wt, w, e, S, v, w.tmap[1], stream));
+    LQT_HIP(wave_traj(kp, dims->dtype, wt, w, e, S, v, x, u, true, stream));
+    return ok();
+  }
+  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
+  const Tree t = tree_for(dims);
   // FP32 builds its elements and level 1 of the value tree in one kernel; in FP64 the fused
   // kernel exceeds the register file, so the build and the level-1 products run separately.
   const bool fused = dims->dtype == LQT_F32;
@@ -364,7 +413,8 @@ lqt_status lqt_backward(const lqt_dims* dims, const lqt_problem* prob, const voi
   if (dims->F_sampled || dims->L_sampled || dims->has_c)
     return fail(LQT_EUNSUPPORTED, "lqt_backward needs constant F and L and c = 0");
   const AdjOps* ao = adj_ops(dims->nx, dims->nu, dims->dtype);
-  if (!ao) return fail(LQT_EUNSUPPORTED, "lqt_backward is available in FP64 for nx <= 4");
+  if (!ao || use_wave(dims))
+    return fail(LQT_EUNSUPPORTED, "lqt_backward is available in FP64 for nx <= 4");
   LQT_TRY(check_problem(dims, prob, true, true));
   const size_t es = dsize(dims->dtype);
   LQT_TRY(check_ptr(S, "S", es));

@@ -125,6 +125,24 @@ const AdjOps* adj_ops(int nx, int nu, int dtype);
 // Instantiations for 1 <= nu <= nx <= 4 (one tuple per lane); nullptr if not available.
 const Ops* lane_ops(int nx, int nu, int dtype);
 
+// Wavefront-per-tuple path (lqt_wave.hip) for any nx <= 16: one wavefront per block or tree
+// node, matrices in LDS.  Its trees reduce `wc` nodes per wave at every level: n[0] = T,
+// n[l + 1] = ceil(n[l] / wc) while n[l] > wc.  Tree nodes are records ([batch][n[l]][record]):
+// tuples (NE values, element order), values (S full, v: nx^2 + nx), maps (P = Psi - I, q:
+// nx^2 + nx), states (nx).
+struct WTree {
+  int levels = 0;
+  int wc = 8;
+  long n[kMaxLevels + 1] = {};
+};
+WTree wave_tree(long T, int wc);
+hipError_t wave_build(const KProb& kp, int dtype, void* elts, hipStream_t s);
+hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
+                      void* S, void* v, void* maps1, hipStream_t s);
+hipError_t wave_traj(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
+                     const void* S, const void* v, void* x, void* u, bool maps_ready,
+                     hipStream_t s);
+
 // Prep kernel (any nx, nu <= 16).
 hipError_t launch_prep(const KProb& kp, int dtype, void* consts, hipStream_t stream);
 

@@ -1,0 +1,1010 @@
+// Wavefront-per-tuple path for 5 <= nx <= 16 (runtime sizes): one wavefront owns one block (or
+// one tree node) and keeps its matrices in LDS; the 64 lanes split the entries of every matrix
+// product and elimination step.  The arithmetic is that of the per-lane path (A stored as A - I,
+// pivoted Gauss-Jordan solves, the combination rule of Lemma 7, the fold of Theorem 6, the
+// closed-loop block maps of Sec. IV-E); only the distribution over lanes differs.
+//
+// Elements use the tiled layout of the C ABI; tree nodes are records ([batch][n][NQ]) with the
+// element's value order: A - I (nx*nx, row-major), b, C (upper triangle, row by row), eta, J.
+// Scans: every wave reduces `wc` consecutive nodes serially (wc chosen at run time); level l + 1
+// has ceil(n_l / wc) nodes while n_l > wc; the top (<= wc nodes) is swept by one wave.
+#include <cstring>
+
+#include "../../include/lqt.h"
+#include "lqt_internal.hpp"
+
+namespace lqt {
+namespace {
+
+constexpr int NM = 16;      // largest state size
+constexpr int kTile = 256;  // element tile (blocks per tile of the element layout)
+#define WDEV __device__ __forceinline__
+
+WDEV int lane_id() { return threadIdx.x; }
+WDEV void wsync() { __syncthreads(); }  // one wavefront per workgroup
+
+WDEV int pk(int i, int j, int n) {  // packed upper index
+  if (i > j) {
+    int t = i;
+    i = j;
+    j = t;
+  }
+  return i * n - (i * (i - 1)) / 2 + (j - i);
+}
+
+// C = alpha * op(A) op(B) + beta * C for n x n (or m x p) matrices in LDS, row-major, ld = cols.
+template <class R>
+WDEV void w_gemm(R* C, const R* A, const R* B, int m, int kk, int p, bool tA, bool tB, R alpha,
+                 R beta) {
+  for (int e = lane_id(); e < m * p; e += 64) {
+    const int i = e / p, j = e % p;
+    R s = R(0);
+    for (int k = 0; k < kk; ++k) {
+      const R a = tA ? A[k * m + i] : A[i * kk + k];
+      const R b = tB ? B[j * kk + k] : B[k * p + j];
+      s = fma(a, b, s);
+    }
+    C[e] = beta == R(0) ? alpha * s : fma(beta, C[e], alpha * s);
+  }
+  wsync();
+}
+
+template <class R>
+WDEV void w_copy(R* dst, const R* src, int n) {
+  for (int e = lane_id(); e < n; e += 64) dst[e] = src[e];
+  wsync();
+}
+
+template <class R>
+WDEV void w_fill(R* dst, R v, int n) {
+  for (int e = lane_id(); e < n; e += 64) dst[e] = v;
+  wsync();
+}
+
+// Solve M X = B in place (B <- M^{-1} B), M n x n, B n x nb, Gauss-Jordan with partial pivoting
+// (first row of largest magnitude).  M is destroyed.  f: scratch of n values.
+template <class R>
+WDEV void w_solve(R* M, R* B, int n, int nb, R* f, int* piv) {
+  for (int c = 0; c < n; ++c) {
+    if (lane_id() == 0) {
+      int p = c;
+      for (int i = c + 1; i < n; ++i)
+        if (fabs(M[i * n + c]) > fabs(M[p * n + c])) p = i;
+      *piv = p;
+    }
+    wsync();
+    const int p = *piv;
+    if (p != c) {
+      for (int j = lane_id(); j < n + nb; j += 64) {
+        R* a = j < n ? &M[c * n + j] : &B[c * nb + (j - n)];
+        R* b = j < n ? &M[p * n + j] : &B[p * nb + (j - n)];
+        R t = *a;
+        *a = *b;
+        *b = t;
+      }
+      wsync();
+    }
+    const R inv = R(1) / M[c * n + c];
+    for (int j = lane_id(); j < n + nb; j += 64) {
+      if (j < n) {
+        if (j > c) M[c * n + j] *= inv;
+      } else {
+        B[c * nb + (j - n)] *= inv;
+      }
+    }
+    for (int i = lane_id(); i < n; i += 64) f[i] = M[i * n + c];
+    wsync();
+    for (int e = lane_id(); e < n * (n + nb); e += 64) {
+      const int i = e / (n + nb), j = e % (n + nb);
+      if (i == c) continue;
+      if (j < n) {
+        if (j > c) M[i * n + j] = fma(-f[i], M[c * n + j], M[i * n + j]);
+      } else {
+        B[i * nb + (j - n)] = fma(-f[i], B[c * nb + (j - n)], B[i * nb + (j - n)]);
+      }
+    }
+    wsync();
+  }
+}
+
+// Tuple in LDS: A (= A - I, full), b, C (full symmetric), e, J (full symmetric).
+template <class R>
+struct WT {
+  R *A, *b, *C, *e, *J;
+};
+
+template <class R>
+WDEV WT<R> wt_at(R* base, int n) {  // 3 n^2 + 2 n values
+  WT<R> t;
+  t.A = base;
+  t.b = base + n * n;
+  t.C = t.b + n;
+  t.e = t.C + n * n;
+  t.J = t.e + n;
+  return t;
+}
+__host__ __device__ inline int wt_size(int n) { return 3 * n * n + 2 * n; }
+__host__ __device__ inline int ne_w(int n) { return 2 * n * n + 3 * n; }
+
+// A tuple in global memory: value q at g[q * st] (st = 1 for tree nodes, kTile for elements).
+template <class R>
+struct GRef {
+  R* g;
+  long st;
+};
+
+// Element k of problem p in the tiled element layout (tiles of kTile blocks, value-major inside a
+// tile, block k at column 64 (k % 4) + (k % 256) / 4).
+template <class R>
+WDEV GRef<R> elt_ref(R* elts, int p, long k, long T, int NE) {
+  const long nt = (T + kTile - 1) / kTile;
+  return {elts + ((p * nt + k / kTile) * NE) * kTile + ((k & 3) << 6) + ((k & 255) >> 2), kTile};
+}
+template <class R>
+WDEV GRef<R> rec_ref(R* rec, int p, long k, long n, int NE) {
+  return {rec + ((long)p * n + k) * NE, 1};
+}
+
+template <class R>
+WDEV void wt_load(WT<R> t, GRef<const R> g, int n) {
+  const int ns = n * (n + 1) / 2;
+  const int oB = n * n, oC = oB + n, oE = oC + ns, oJ = oE + n;
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    t.A[e] = g.g[e * g.st];
+    t.C[e] = g.g[(oC + pk(i, j, n)) * g.st];
+    t.J[e] = g.g[(oJ + pk(i, j, n)) * g.st];
+  }
+  for (int i = lane_id(); i < n; i += 64) {
+    t.b[i] = g.g[(oB + i) * g.st];
+    t.e[i] = g.g[(oE + i) * g.st];
+  }
+  wsync();
+}
+
+template <class R>
+WDEV void wt_store(WT<R> t, GRef<R> g, int n) {
+  const int ns = n * (n + 1) / 2;
+  const int oB = n * n, oC = oB + n, oE = oC + ns, oJ = oE + n;
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    g.g[e * g.st] = t.A[e];
+    if (i <= j) {
+      g.g[(oC + pk(i, j, n)) * g.st] = t.C[e];
+      g.g[(oJ + pk(i, j, n)) * g.st] = t.J[e];
+    }
+  }
+  for (int i = lane_id(); i < n; i += 64) {
+    g.g[(oB + i) * g.st] = t.b[i];
+    g.g[(oE + i) * g.st] = t.e[i];
+  }
+  wsync();
+}
+
+template <class R>
+WDEV void wt_identity(WT<R> t, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) t.A[e] = t.C[e] = t.J[e] = R(0);
+  for (int i = lane_id(); i < n; i += 64) t.b[i] = t.e[i] = R(0);
+  wsync();
+}
+
+// Scratch of a combination / fold: 4 n^2 + n (2 n + 1) + 2 n values.
+template <class R>
+struct WS {
+  R *M, *B, *X, *Y, *f;
+  int* piv;
+};
+
+// Lemma 7 in the deviation form of the per-lane path: o = x1 (x) x2 (o may alias x2).
+template <class R>
+WDEV void w_combine(WT<R> x1, WT<R> x2, WT<R> o, WS<R> s, int n) {
+  const int nb = 2 * n + 1;
+  // M = I + C1 J2; B = [Ad1 - C1 J2 | C1 | b1 + C1 eta2]
+  w_gemm(s.X, x1.C, x2.J, n, n, n, false, false, R(1), R(0));
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    s.M[e] = (i == j ? R(1) : R(0)) + s.X[e];
+    s.B[i * nb + j] = x1.A[e] - s.X[e];
+    s.B[i * nb + n + j] = x1.C[e];
+  }
+  for (int i = lane_id(); i < n; i += 64) {
+    R g = x1.b[i];
+    for (int k = 0; k < n; ++k) g = fma(x1.C[i * n + k], x2.e[k], g);
+    s.B[i * nb + 2 * n] = g;
+  }
+  wsync();
+  w_solve(s.M, s.B, n, nb, s.f, s.piv);
+  // W = (I + Ad2) D -> X;  C = W (I + Ad2)^T + C2 -> Y
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    R t = s.B[i * nb + n + j];
+    for (int k = 0; k < n; ++k) t = fma(x2.A[i * n + k], s.B[k * nb + n + j], t);
+    s.X[e] = t;
+  }
+  wsync();
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    const int a = i < j ? i : j, bb = i < j ? j : i;  // symmetric: compute the upper entry
+    R t = s.X[a * n + bb];
+    for (int l = 0; l < n; ++l) t = fma(s.X[a * n + l], x2.A[bb * n + l], t);
+    s.Y[e] = x2.C[a * n + bb] + t;
+  }
+  // b = g + Ad2 g + b2 -> f (n values beyond piv scratch use)
+  wsync();
+  R bn = R(0), en = R(0);
+  const int i = lane_id();
+  if (i < n) {
+    R t = R(0);
+    for (int k = 0; k < n; ++k) t = fma(x2.A[i * n + k], s.B[k * nb + 2 * n], t);
+    bn = x2.b[i] + s.B[i * nb + 2 * n] + t;
+  }
+  // w = eta2 - J2 b1 -> f
+  if (i < n) {
+    R t = x2.e[i];
+    for (int k = 0; k < n; ++k) t = fma(-x2.J[i * n + k], x1.b[k], t);
+    s.f[i] = t;
+  }
+  wsync();
+  if (i < n) {
+    R t = R(0);
+    for (int k = 0; k < n; ++k) t = fma(s.B[k * nb + i], s.f[k], t);
+    en = x1.e[i] + (s.f[i] + t);
+  }
+  // P = J2 (I + Ad1) -> X
+  wsync();
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int r = e / n, j = e % n;
+    R t = x2.J[e];
+    for (int k = 0; k < n; ++k) t = fma(x2.J[r * n + k], x1.A[k * n + j], t);
+    s.X[e] = t;
+  }
+  wsync();
+  // J = (I + Yd)^T P + J1 (upper entry mirrored);  Ad = Ad2 + Yd + Ad2 Yd -> M
+  R jn[4], an[4];
+  int cnt = 0;
+  for (int e = lane_id(); e < n * n; e += 64, ++cnt) {
+    const int r = e / n, j = e % n;
+    const int a = r < j ? r : j, bb = r < j ? j : r;
+    R t = s.X[a * n + bb];
+    for (int k = 0; k < n; ++k) t = fma(s.B[k * nb + a], s.X[k * n + bb], t);
+    jn[cnt] = x1.J[a * n + bb] + t;
+    R u = R(0);
+    for (int k = 0; k < n; ++k) u = fma(x2.A[r * n + k], s.B[k * nb + j], u);
+    an[cnt] = x2.A[e] + s.B[r * nb + j] + u;
+  }
+  wsync();
+  cnt = 0;
+  for (int e = lane_id(); e < n * n; e += 64, ++cnt) {
+    o.J[e] = jn[cnt];
+    o.A[e] = an[cnt];
+    o.C[e] = s.Y[e];
+  }
+  if (i < n) {
+    o.b[i] = bn;
+    o.e[i] = en;
+  }
+  wsync();
+}
+
+// Fold with a terminal-form right operand: (S, v) <- a (x) (S, v); also the block map
+// (P = Psi - I, q = alpha) into P, q (nullable).  S full symmetric.
+template <class R>
+WDEV void w_fold(WT<R> a, R* S, R* v, WS<R> s, int n, R* P, R* q) {
+  const int nb = n + 1;
+  w_gemm(s.X, a.C, S, n, n, n, false, false, R(1), R(0));  // C S
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    s.M[e] = (i == j ? R(1) : R(0)) + s.X[e];
+    s.B[i * nb + j] = a.A[e] - s.X[e];
+  }
+  for (int i = lane_id(); i < n; i += 64) {
+    R g = a.b[i];
+    for (int k = 0; k < n; ++k) g = fma(a.C[i * n + k], v[k], g);
+    s.B[i * nb + n] = g;
+  }
+  wsync();
+  w_solve(s.M, s.B, n, nb, s.f, s.piv);
+  if (P) {
+    for (int e = lane_id(); e < n * n; e += 64) P[e] = s.B[(e / n) * nb + e % n];
+    for (int i = lane_id(); i < n; i += 64) q[i] = s.B[i * nb + n];
+  }
+  // w = v - S b -> f;  X = S (I + Ad) -> X
+  for (int i = lane_id(); i < n; i += 64) {
+    R t = v[i];
+    for (int k = 0; k < n; ++k) t = fma(-S[i * n + k], a.b[k], t);
+    s.f[i] = t;
+  }
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    R t = S[e];
+    for (int k = 0; k < n; ++k) t = fma(S[i * n + k], a.A[k * n + j], t);
+    s.X[e] = t;
+  }
+  wsync();
+  R sn[4], vn = R(0);
+  int cnt = 0;
+  for (int e = lane_id(); e < n * n; e += 64, ++cnt) {
+    const int r = e / n, j = e % n;
+    const int aa = r < j ? r : j, bb = r < j ? j : r;
+    R t = R(0);
+    for (int k = 0; k < n; ++k) t = fma(s.B[k * nb + aa], s.X[k * n + bb], t);
+    sn[cnt] = a.J[aa * n + bb] + (s.X[aa * n + bb] + t);
+  }
+  const int i = lane_id();
+  if (i < n) {
+    R t = R(0);
+    for (int k = 0; k < n; ++k) t = fma(s.B[k * nb + i], s.f[k], t);
+    vn = a.e[i] + (s.f[i] + t);
+  }
+  wsync();
+  cnt = 0;
+  for (int e = lane_id(); e < n * n; e += 64, ++cnt) S[e] = sn[cnt];
+  if (i < n) v[i] = vn;
+  wsync();
+}
+
+// Block map only: (P, q) from (Ad, b, C) of a block and (S, v) at its right end.
+template <class R>
+WDEV void w_block_map(WT<R> a, const R* S, const R* v, WS<R> s, int n, R* P, R* q) {
+  const int nb = n + 1;
+  w_gemm(s.X, a.C, S, n, n, n, false, false, R(1), R(0));
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    s.M[e] = (i == j ? R(1) : R(0)) + s.X[e];
+    s.B[i * nb + j] = a.A[e] - s.X[e];
+  }
+  for (int i = lane_id(); i < n; i += 64) {
+    R g = a.b[i];
+    for (int k = 0; k < n; ++k) g = fma(a.C[i * n + k], v[k], g);
+    s.B[i * nb + n] = g;
+  }
+  wsync();
+  w_solve(s.M, s.B, n, nb, s.f, s.piv);
+  for (int e = lane_id(); e < n * n; e += 64) P[e] = s.B[(e / n) * nb + e % n];
+  for (int i = lane_id(); i < n; i += 64) q[i] = s.B[i * nb + n];
+  wsync();
+}
+
+// Affine maps (P = Psi - I, q): acc <- later o acc.  tmp: n^2 + n.
+template <class R>
+WDEV void w_aff_then(R* aP, R* aq, const R* lP, const R* lq, R* tmp, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    R t = R(0);
+    for (int k = 0; k < n; ++k) t = fma(lP[i * n + k], aP[k * n + j], t);
+    tmp[e] = aP[e] + lP[e] + t;
+  }
+  for (int i = lane_id(); i < n; i += 64) {
+    R t = R(0);
+    for (int k = 0; k < n; ++k) t = fma(lP[i * n + k], aq[k], t);
+    tmp[n * n + i] = lq[i] + aq[i] + t;
+  }
+  wsync();
+  for (int e = lane_id(); e < n * n; e += 64) aP[e] = tmp[e];
+  for (int i = lane_id(); i < n; i += 64) aq[i] = tmp[n * n + i];
+  wsync();
+}
+
+// acc <- acc o earlier
+template <class R>
+WDEV void w_aff_after(R* aP, R* aq, const R* eP, const R* eq, R* tmp, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    R t = R(0);
+    for (int k = 0; k < n; ++k) t = fma(aP[i * n + k], eP[k * n + j], t);
+    tmp[e] = eP[e] + aP[e] + t;
+  }
+  for (int i = lane_id(); i < n; i += 64) {
+    R t = R(0);
+    for (int k = 0; k < n; ++k) t = fma(aP[i * n + k], eq[k], t);
+    tmp[n * n + i] = aq[i] + eq[i] + t;
+  }
+  wsync();
+  for (int e = lane_id(); e < n * n; e += 64) aP[e] = tmp[e];
+  for (int i = lane_id(); i < n; i += 64) aq[i] = tmp[n * n + i];
+  wsync();
+}
+
+// x <- x + P x + q (x, tmp in LDS)
+template <class R>
+WDEV void w_aff_apply(const R* P, const R* q, R* x, R* tmp, int n) {
+  for (int i = lane_id(); i < n; i += 64) {
+    R t = R(0);
+    for (int k = 0; k < n; ++k) t = fma(P[i * n + k], x[k], t);
+    tmp[i] = x[i] + (t + q[i]);
+  }
+  wsync();
+  for (int i = lane_id(); i < n; i += 64) x[i] = tmp[i];
+  wsync();
+}
+
+template <class R>
+WDEV void w_aff_identity(R* P, R* q, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) P[e] = R(0);
+  for (int i = lane_id(); i < n; i += 64) q[i] = R(0);
+  wsync();
+}
+
+// LDS budget per workgroup (values of R): tuples and scratch for n = 16.
+constexpr int kTupW = 3 * NM * NM + 2 * NM;
+constexpr int kScr = 4 * NM * NM + NM * (2 * NM + 1) + 2 * NM;
+
+template <class R>
+WDEV WS<R> ws_at(R* base, int* piv, int n) {
+  WS<R> s;
+  s.M = base;
+  s.X = s.M + n * n;
+  s.Y = s.X + n * n;
+  s.B = s.Y + n * n;
+  s.f = s.B + n * (2 * n + 1);
+  s.piv = piv;
+  return s;
+}
+
+// ------------------------------------------------------------------------------------------
+// Element build (Theorem 8), one wave per block: RK4 on the full matrices.
+// ------------------------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ elts) {
+  __shared__ R sh[3 * kTupW + 8 * NM * NM + 4 * NM];
+  const int p = blockIdx.y;
+  const long k = blockIdx.x;
+  const int n = kp.nx, nu = kp.nu;
+  const long T = kp.T;
+  const int nn = kp.n;
+  const long nsamp = 2L * nn * T + 1;
+  const R* t = (const R*)kp.t + (long)p * (T + 1);
+  const R* r = (const R*)kp.r + (long)p * nsamp * n;
+  const R* Fb = (const R*)kp.F + (kp.F_sampled ? (long)p * nsamp * n * n : 0);
+  const R* Lb = (const R*)kp.L + (kp.L_sampled ? (long)p * nsamp * n * nu : 0);
+  const R* cb = kp.has_c ? (const R*)kp.c + (long)p * nsamp * n : nullptr;
+  const R* Qp = (const R*)kp.Q + (long)p * n * n;
+  const R* cs = (const R*)kp.consts + (long)p * consts_count(n, nu);
+  WT<R> y = wt_at(sh, n), ac = wt_at(sh + kTupW, n), st = wt_at(sh + 2 * kTupW, n);
+  R* F = sh + 3 * kTupW;
+  R* G = F + NM * NM;
+  R* K = G + NM * NM;
+  R* Lc = K + NM * NM;  // n x nu
+  R* T1 = Lc + NM * NM;
+  R* kA = T1 + NM * NM;
+  R* kC = kA + NM * NM;
+  R* kJ = kC + NM * NM;
+  R* kb = kJ + NM * NM;
+  R* ke = kb + NM;
+  R* rv = ke + NM;
+  R* cv = rv + NM;
+  wt_identity(y, n);
+  const R h = (t[k + 1] - t[k]) / R(nn);
+  for (int m = 0; m < nn; ++m) {
+    const long j1 = 2L * nn * k + 2L * (nn - m);
+    w_copy(st.A, y.A, n * n);
+    w_copy(st.e, y.e, n);
+    w_copy(st.J, y.J, n * n);
+    for (int s = 0; s < 4; ++s) {
+      const long j = s == 0 ? j1 : (s == 3 ? j1 - 2 : j1 - 1);
+      const R wk = (s == 0 || s == 3) ? -h / R(6) : -h / R(3);
+      const R cn = s == 2 ? -h : -h / R(2);
+      const R* Fj = kp.F_sampled ? Fb + j * n * n : Fb;
+      for (int e = lane_id(); e < n * n; e += 64) F[e] = Fj[e];
+      for (int i = lane_id(); i < n; i += 64) {
+        rv[i] = r[j * n + i];
+        cv[i] = cb ? cb[j * n + i] : R(0);
+      }
+      if (kp.L_sampled) {
+        const R* Lj = Lb + j * n * nu;
+        const R* W = cs + consts_off_W(n, nu);
+        for (int e = lane_id(); e < n * nu; e += 64) {
+          const int i = e / nu, l = e % nu;
+          R a = R(0);
+          for (int q2 = 0; q2 < nu; ++q2) a = fma(Lj[i * nu + q2], W[q2 * nu + l], a);
+          Lc[e] = a;
+        }
+        wsync();
+        w_gemm(G, Lc, Lc, n, nu, n, false, true, R(1), R(0));
+      } else {
+        for (int e = lane_id(); e < n * n; e += 64) G[e] = cs[consts_off_G(n, nu) + e];
+        for (int e = lane_id(); e < n * nu; e += 64) Lc[e] = cs[consts_off_Lc(n, nu) + e];
+        wsync();
+      }
+      // K = G J - F
+      for (int e = lane_id(); e < n * n; e += 64) K[e] = -F[e];
+      wsync();
+      w_gemm(K, G, st.J, n, n, n, false, false, R(1), R(1));
+      // kA = K + Ad K
+      w_copy(kA, K, n * n);
+      w_gemm(kA, st.A, K, n, n, n, false, false, R(1), R(1));
+      // kb = -(I + Ad)(G eta + c)
+      for (int i = lane_id(); i < n; i += 64) {
+        R a = cv[i];
+        for (int l = 0; l < n; ++l) a = fma(G[i * n + l], st.e[l], a);
+        T1[i] = a;
+      }
+      wsync();
+      for (int i = lane_id(); i < n; i += 64) {
+        R a = T1[i];
+        for (int l = 0; l < n; ++l) a = fma(st.A[i * n + l], T1[l], a);
+        kb[i] = -a;
+      }
+      // kC = -(A Lc)(A Lc)^T with A Lc = Lc + Ad Lc -> T1 (n x nu)
+      wsync();
+      w_copy(T1, Lc, n * nu);
+      w_gemm(T1, st.A, Lc, n, n, nu, false, false, R(1), R(1));
+      w_gemm(kC, T1, T1, n, nu, n, false, true, R(-1), R(0));
+      // ke = K^T eta + J c - Q r
+      for (int i = lane_id(); i < n; i += 64) {
+        R a = R(0);
+        for (int l = 0; l < n; ++l) {
+          a = fma(K[l * n + i], st.e[l], a);
+          a = fma(st.J[i * n + l], cv[l], a);
+          a = fma(-Qp[i * n + l], rv[l], a);
+        }
+        ke[i] = a;
+      }
+      // kJ = -Q + J K - F^T J (symmetrised from the upper entry)
+      for (int e = lane_id(); e < n * n; e += 64) {
+        const int i = e / n, q2 = e % n;
+        const int a = i < q2 ? i : q2, bb = i < q2 ? q2 : i;
+        R v = -Qp[a * n + bb];
+        for (int l = 0; l < n; ++l) {
+          v = fma(st.J[a * n + l], K[l * n + bb], v);
+          v = fma(-F[l * n + a], st.J[l * n + bb], v);
+        }
+        kJ[e] = v;
+      }
+      wsync();
+      // accumulate and form the next stage input
+      for (int e = lane_id(); e < n * n; e += 64) {
+        ac.A[e] = s == 0 ? fma(wk, kA[e], y.A[e]) : fma(wk, kA[e], ac.A[e]);
+        ac.J[e] = s == 0 ? fma(wk, kJ[e], y.J[e]) : fma(wk, kJ[e], ac.J[e]);
+        y.C[e] = fma(wk, kC[e], y.C[e]);
+        if (s < 3) {
+          st.A[e] = fma(cn, kA[e], y.A[e]);
+          st.J[e] = fma(cn, kJ[e], y.J[e]);
+        }
+      }
+      for (int i = lane_id(); i < n; i += 64) {
+        ac.e[i] = s == 0 ? fma(wk, ke[i], y.e[i]) : fma(wk, ke[i], ac.e[i]);
+        y.b[i] = fma(wk, kb[i], y.b[i]);
+        if (s < 3) st.e[i] = fma(cn, ke[i], y.e[i]);
+      }
+      wsync();
+    }
+    w_copy(y.A, ac.A, n * n);
+    w_copy(y.e, ac.e, n);
+    w_copy(y.J, ac.J, n * n);
+  }
+  wt_store(y, elt_ref(elts, p, k, T, ne_w(n)), n);
+}
+
+// ------------------------------------------------------------------------------------------
+// Value tree.
+// ------------------------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(64) void kw_vreduce(int n, int wc, int src_elts,
+                                                 const R* __restrict__ src, long n_src,
+                                                 R* __restrict__ dst, long n_dst) {
+  __shared__ R sh[2 * kTupW + kScr];
+  __shared__ int piv;
+  const int p = blockIdx.y;
+  const long i = blockIdx.x;
+  if (i >= n_dst) return;
+  const int NE = ne_w(n);
+  auto ref = [&](long j) {
+    return src_elts ? elt_ref(src, p, j, n_src, NE) : rec_ref(src, p, j, n_src, NE);
+  };
+  WT<R> acc = wt_at(sh, n), x = wt_at(sh + kTupW, n);
+  WS<R> scr = ws_at(sh + 2 * kTupW, &piv, n);
+  const long j0 = i * wc, j1 = min(j0 + wc, n_src);
+  wt_load(acc, ref(j1 - 1), n);
+  for (long j = j1 - 2; j >= j0; --j) {
+    wt_load(x, ref(j), n);
+    w_combine(x, acc, acc, scr, n);
+  }
+  wt_store(acc, rec_ref(dst, p, i, n_dst, NE), n);
+}
+
+// Value records (S full symmetric, v): n^2 + n values.
+template <class R>
+WDEV void val_st(const R* S, const R* v, R* g, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) g[e] = S[e];
+  for (int i = lane_id(); i < n; i += 64) g[n * n + i] = v[i];
+  wsync();
+}
+template <class R>
+WDEV void val_ld(R* S, R* v, const R* g, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) S[e] = g[e];
+  for (int i = lane_id(); i < n; i += 64) v[i] = g[n * n + i];
+  wsync();
+}
+
+template <class R>
+__global__ __launch_bounds__(64) void kw_vtop(const KProb kp, const R* __restrict__ tup, long n_top,
+                                              R* __restrict__ val) {
+  __shared__ R sh[kTupW + kScr + NM * NM + NM];
+  __shared__ int piv;
+  const int p = blockIdx.y;
+  const int n = kp.nx;
+  const int NE = ne_w(n);
+  WT<R> a = wt_at(sh, n);
+  WS<R> scr = ws_at(sh + kTupW, &piv, n);
+  R* S = sh + kTupW + kScr;
+  R* v = S + NM * NM;
+  const R* Qf = (const R*)kp.Qf + (long)p * n * n;
+  const R* rf = (const R*)kp.rf + (long)p * n;
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    S[e] = Qf[(i < j ? i : j) * n + (i < j ? j : i)];
+  }
+  for (int i = lane_id(); i < n; i += 64) {
+    R t = R(0);
+    for (int j = 0; j < n; ++j) t = fma(Qf[i * n + j], rf[j], t);
+    v[i] = t;
+  }
+  wsync();
+  const int VR = n * n + n;
+  for (long j = n_top - 1; j >= 0; --j) {
+    val_st(S, v, val + ((long)p * n_top + j) * VR, n);
+    if (j == 0) break;
+    wt_load(a, rec_ref(tup, p, j, n_top, NE), n);
+    w_fold(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(64) void kw_vdown(int n, int wc, const R* __restrict__ tup, long n_child,
+                                               const R* __restrict__ val_in, long n_par,
+                                               R* __restrict__ val_out) {
+  __shared__ R sh[kTupW + kScr + NM * NM + NM];
+  __shared__ int piv;
+  const int p = blockIdx.y;
+  const long i = blockIdx.x;
+  if (i >= n_par) return;
+  const int NE = ne_w(n), VR = n * n + n;
+  WT<R> a = wt_at(sh, n);
+  WS<R> scr = ws_at(sh + kTupW, &piv, n);
+  R* S = sh + kTupW + kScr;
+  R* v = S + NM * NM;
+  val_ld(S, v, val_in + ((long)p * n_par + i) * VR, n);
+  const long j0 = i * wc, j1 = min(j0 + wc, n_child);
+  for (long j = j1 - 1; j >= j0; --j) {
+    val_st(S, v, val_out + ((long)p * n_child + j) * VR, n);
+    if (j == j0) break;
+    wt_load(a, rec_ref(tup, p, j, n_child, NE), n);
+    w_fold(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
+  }
+}
+
+// Values of every block from the value at the right end of each chunk; level 1 of the
+// trajectory tree (composition of the chunk's block maps) when maps1 != nullptr.
+template <class R>
+__global__ __launch_bounds__(64) void kw_vbottom(const KProb kp, int wc, const R* __restrict__ elts,
+                                                 const R* __restrict__ val1, long n1,
+                                                 R* __restrict__ Sout, R* __restrict__ vout,
+                                                 R* __restrict__ maps1) {
+  __shared__ R sh[kTupW + kScr + NM * NM + NM + 3 * (NM * NM + NM)];
+  __shared__ int piv;
+  const int p = blockIdx.y;
+  const long i = blockIdx.x;
+  if (i >= n1) return;
+  const int n = kp.nx;
+  const long T = kp.T;
+  const int NE = ne_w(n), VR = n * n + n, MR = n * n + n;
+  WT<R> a = wt_at(sh, n);
+  WS<R> scr = ws_at(sh + kTupW, &piv, n);
+  R* S = sh + kTupW + kScr;
+  R* v = S + NM * NM;
+  R* aP = v + NM;
+  R* aq = aP + NM * NM;
+  R* mP = aq + NM;
+  R* mq = mP + NM * NM;
+  R* tmp = mq + NM;
+  val_ld(S, v, val1 + ((long)p * n1 + i) * VR, n);
+  R* Sp = Sout + (long)p * (T + 1) * n * n;
+  R* vp = vout + (long)p * (T + 1) * n;
+  const long j0 = i * wc, j1 = min(j0 + wc, T);
+  if (j1 == T) {
+    for (int e = lane_id(); e < n * n; e += 64) Sp[T * n * n + e] = S[e];
+    for (int q = lane_id(); q < n; q += 64) vp[T * n + q] = v[q];
+  }
+  w_aff_identity(aP, aq, n);
+  for (long k = j1 - 1; k >= j0; --k) {
+    wt_load(a, elt_ref(elts, p, k, T, NE), n);
+    w_fold(a, S, v, scr, n, mP, mq);
+    for (int e = lane_id(); e < n * n; e += 64) Sp[k * n * n + e] = S[e];
+    for (int q = lane_id(); q < n; q += 64) vp[k * n + q] = v[q];
+    if (maps1) w_aff_after(aP, aq, mP, mq, tmp, n);
+  }
+  if (maps1) {
+    R* g = maps1 + ((long)p * n1 + i) * MR;
+    for (int e = lane_id(); e < n * n; e += 64) g[e] = aP[e];
+    for (int q = lane_id(); q < n; q += 64) g[n * n + q] = aq[q];
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// Trajectory tree.
+// ------------------------------------------------------------------------------------------
+template <class R>
+WDEV void map_ld(R* P, R* q, const R* g, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) P[e] = g[e];
+  for (int i = lane_id(); i < n; i += 64) q[i] = g[n * n + i];
+  wsync();
+}
+template <class R>
+WDEV void map_st(const R* P, const R* q, R* g, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) g[e] = P[e];
+  for (int i = lane_id(); i < n; i += 64) g[n * n + i] = q[i];
+  wsync();
+}
+
+template <class R>
+__global__ __launch_bounds__(64) void kw_tbottom_reduce(const KProb kp, int wc, const R* __restrict__ elts,
+                                                        const R* __restrict__ Sg,
+                                                        const R* __restrict__ vg,
+                                                        R* __restrict__ maps1, long n1) {
+  __shared__ R sh[kTupW + kScr + NM * NM + NM + 3 * (NM * NM + NM)];
+  __shared__ int piv;
+  const int p = blockIdx.y;
+  const long i = blockIdx.x;
+  if (i >= n1) return;
+  const int n = kp.nx;
+  const long T = kp.T;
+  const int NE = ne_w(n), MR = n * n + n;
+  WT<R> a = wt_at(sh, n);
+  WS<R> scr = ws_at(sh + kTupW, &piv, n);
+  R* S = sh + kTupW + kScr;
+  R* v = S + NM * NM;
+  R* aP = v + NM;
+  R* aq = aP + NM * NM;
+  R* mP = aq + NM;
+  R* mq = mP + NM * NM;
+  R* tmp = mq + NM;
+  const R* Sp = Sg + (long)p * (T + 1) * n * n;
+  const R* vp = vg + (long)p * (T + 1) * n;
+  const long j0 = i * wc, j1 = min(j0 + wc, T);
+  w_aff_identity(aP, aq, n);
+  for (long k = j0; k < j1; ++k) {
+    wt_load(a, elt_ref(elts, p, k, T, NE), n);
+    for (int e = lane_id(); e < n * n; e += 64) S[e] = Sp[(k + 1) * n * n + e];
+    for (int q = lane_id(); q < n; q += 64) v[q] = vp[(k + 1) * n + q];
+    wsync();
+    w_block_map(a, S, v, scr, n, mP, mq);
+    w_aff_then(aP, aq, mP, mq, tmp, n);
+  }
+  map_st(aP, aq, maps1 + ((long)p * n1 + i) * MR, n);
+}
+
+template <class R>
+__global__ __launch_bounds__(64) void kw_treduce(int n, int wc, const R* __restrict__ src, long n_src,
+                                                 R* __restrict__ dst, long n_dst) {
+  __shared__ R sh[3 * (NM * NM + NM)];
+  const int p = blockIdx.y;
+  const long i = blockIdx.x;
+  if (i >= n_dst) return;
+  const int MR = n * n + n;
+  R* aP = sh;
+  R* aq = aP + NM * NM;
+  R* mP = aq + NM;
+  R* mq = mP + NM * NM;
+  R* tmp = mq + NM;
+  const long j0 = i * wc, j1 = min(j0 + wc, n_src);
+  map_ld(aP, aq, src + ((long)p * n_src + j0) * MR, n);
+  for (long j = j0 + 1; j < j1; ++j) {
+    map_ld(mP, mq, src + ((long)p * n_src + j) * MR, n);
+    w_aff_then(aP, aq, mP, mq, tmp, n);
+  }
+  map_st(aP, aq, dst + ((long)p * n_dst + i) * MR, n);
+}
+
+template <class R>
+__global__ __launch_bounds__(64) void kw_ttop(const KProb kp, const R* __restrict__ maps, long n_top,
+                                              R* __restrict__ xs) {
+  __shared__ R sh[NM * NM + 3 * NM];
+  const int p = blockIdx.y;
+  const int n = kp.nx;
+  const int MR = n * n + n;
+  R* mP = sh;
+  R* mq = mP + NM * NM;
+  R* x = mq + NM;
+  R* tmp = x + NM;
+  for (int q = lane_id(); q < n; q += 64) x[q] = ((const R*)kp.x0)[(long)p * n + q];
+  wsync();
+  for (long j = 0; j < n_top; ++j) {
+    for (int q = lane_id(); q < n; q += 64) xs[((long)p * n_top + j) * n + q] = x[q];
+    if (j == n_top - 1) break;
+    map_ld(mP, mq, maps + ((long)p * n_top + j) * MR, n);
+    w_aff_apply(mP, mq, x, tmp, n);
+  }
+}
+
+template <class R>
+__global__ __launch_bounds__(64) void kw_tdown(int n, int wc, const R* __restrict__ maps, long n_child,
+                                               const R* __restrict__ x_in, long n_par,
+                                               R* __restrict__ x_out) {
+  __shared__ R sh[NM * NM + 3 * NM];
+  const int p = blockIdx.y;
+  const long i = blockIdx.x;
+  if (i >= n_par) return;
+  const int MR = n * n + n;
+  R* mP = sh;
+  R* mq = mP + NM * NM;
+  R* x = mq + NM;
+  R* tmp = x + NM;
+  for (int q = lane_id(); q < n; q += 64) x[q] = x_in[((long)p * n_par + i) * n + q];
+  wsync();
+  const long j0 = i * wc, j1 = min(j0 + wc, n_child);
+  for (long j = j0; j < j1; ++j) {
+    for (int q = lane_id(); q < n; q += 64) x_out[((long)p * n_child + j) * n + q] = x[q];
+    if (j == j1 - 1) break;
+    map_ld(mP, mq, maps + ((long)p * n_child + j) * MR, n);
+    w_aff_apply(mP, mq, x, tmp, n);
+  }
+}
+
+// x_k and u_k = -R^{-1} L(t_k)^T (S_k x_k - v_k) of every block of a chunk.
+template <class R>
+__global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R* __restrict__ elts,
+                                                 const R* __restrict__ Sg, const R* __restrict__ vg,
+                                                 const R* __restrict__ x1, long n1,
+                                                 R* __restrict__ xout, R* __restrict__ uout) {
+  __shared__ R sh[kTupW + kScr + NM * NM + NM + NM * NM + 4 * NM + NM * NM];
+  __shared__ int piv;
+  const int p = blockIdx.y;
+  const long i = blockIdx.x;
+  if (i >= n1) return;
+  const int n = kp.nx, nu = kp.nu;
+  const long T = kp.T;
+  const int NE = ne_w(n);
+  WT<R> a = wt_at(sh, n);
+  WS<R> scr = ws_at(sh + kTupW, &piv, n);
+  R* S = sh + kTupW + kScr;
+  R* v = S + NM * NM;
+  R* mP = v + NM;
+  R* mq = mP + NM * NM;
+  R* x = mq + NM;
+  R* tmp = x + NM;
+  R* g = tmp + NM;
+  R* Kc = g + NM;  // nu x n
+  const R* Sp = Sg + (long)p * (T + 1) * n * n;
+  const R* vp = vg + (long)p * (T + 1) * n;
+  R* xp = xout + (long)p * (T + 1) * n;
+  R* up = uout ? uout + (long)p * (T + 1) * nu : nullptr;
+  const R* cs = (const R*)kp.consts + (long)p * consts_count(n, nu);
+  const long nsamp = 2L * kp.n * T + 1;
+  for (int q = lane_id(); q < n; q += 64) x[q] = x1[((long)p * n1 + i) * n + q];
+  wsync();
+  const long j0 = i * wc, j1 = min(j0 + wc, T);
+  auto control = [&](long k) {
+    if (!up) return;
+    if (kp.L_sampled) {
+      const R* Lk = (const R*)kp.L + ((long)p * nsamp + 2L * kp.n * k) * n * nu;
+      const R* Ri = cs + consts_off_Rinv(n, nu);
+      for (int e = lane_id(); e < nu * n; e += 64) {
+        const int l = e / n, j = e % n;
+        R s = R(0);
+        for (int q = 0; q < nu; ++q) s = fma(Ri[l * nu + q], Lk[j * nu + q], s);
+        Kc[e] = s;
+      }
+    } else {
+      for (int e = lane_id(); e < nu * n; e += 64) Kc[e] = cs[consts_off_Kc(n, nu) + e];
+    }
+    for (int r = lane_id(); r < n; r += 64) {
+      R s = -vp[k * n + r];
+      for (int j = 0; j < n; ++j) s = fma(Sp[k * n * n + r * n + j], x[j], s);
+      g[r] = s;
+    }
+    wsync();
+    for (int l = lane_id(); l < nu; l += 64) {
+      R s = R(0);
+      for (int j = 0; j < n; ++j) s = fma(-Kc[l * n + j], g[j], s);
+      up[k * nu + l] = s;
+    }
+    wsync();
+  };
+  for (long k = j0; k < j1; ++k) {
+    for (int q = lane_id(); q < n; q += 64) xp[k * n + q] = x[q];
+    control(k);
+    wt_load(a, elt_ref(elts, p, k, T, NE), n);
+    for (int e = lane_id(); e < n * n; e += 64) S[e] = Sp[(k + 1) * n * n + e];
+    for (int q = lane_id(); q < n; q += 64) v[q] = vp[(k + 1) * n + q];
+    wsync();
+    w_block_map(a, S, v, scr, n, mP, mq);
+    w_aff_apply(mP, mq, x, tmp, n);
+  }
+  if (j1 == T) {
+    for (int q = lane_id(); q < n; q += 64) xp[T * n + q] = x[q];
+    control(T);
+  }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Host orchestration of this path.
+// ------------------------------------------------------------------------------------------
+WTree wave_tree(long T, int wc) {
+  WTree t;
+  t.wc = wc;
+  t.n[0] = T;
+  t.n[1] = (T + wc - 1) / wc;
+  t.levels = 1;
+  while (t.n[t.levels] > wc && t.levels < kMaxLevels) {
+    t.n[t.levels + 1] = (t.n[t.levels] + wc - 1) / wc;
+    ++t.levels;
+  }
+  return t;
+}
+
+namespace {
+
+template <class R>
+hipError_t wave_build_t(const KProb& kp, void* elts, hipStream_t s) {
+  hipLaunchKernelGGL(kw_build<R>, dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp, (R*)elts);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t wave_value_t(const KProb& kp, const WTree& t, const Work& w, const void* elts, void* S,
+                        void* v, void* maps1, hipStream_t s) {
+  const int n = kp.nx, wc = t.wc;
+  const dim3 b(64);
+  hipLaunchKernelGGL(kw_vreduce<R>, dim3((unsigned)t.n[1], kp.batch), b, 0, s, n, wc, 1,
+                     (const R*)elts, t.n[0], (R*)w.vtup[1], t.n[1]);
+  for (int l = 1; l < t.levels; ++l)
+    hipLaunchKernelGGL(kw_vreduce<R>, dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc, 0,
+                       (const R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1], t.n[l + 1]);
+  hipLaunchKernelGGL(kw_vtop<R>, dim3(1, kp.batch), b, 0, s, kp, (const R*)w.vtup[t.levels],
+                     t.n[t.levels], (R*)w.vval[t.levels]);
+  for (int l = t.levels - 1; l >= 1; --l)
+    hipLaunchKernelGGL(kw_vdown<R>, dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
+                       (const R*)w.vtup[l], t.n[l], (const R*)w.vval[l + 1], t.n[l + 1],
+                       (R*)w.vval[l]);
+  hipLaunchKernelGGL(kw_vbottom<R>, dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
+                     (const R*)elts, (const R*)w.vval[1], t.n[1], (R*)S, (R*)v, (R*)maps1);
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t wave_traj_t(const KProb& kp, const WTree& t, const Work& w, const void* elts,
+                       const void* S, const void* v, void* x, void* u, bool maps_ready,
+                       hipStream_t s) {
+  const int n = kp.nx, wc = t.wc;
+  const dim3 b(64);
+  if (!maps_ready)
+    hipLaunchKernelGGL(kw_tbottom_reduce<R>, dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
+                       (const R*)elts, (const R*)S, (const R*)v, (R*)w.tmap[1], t.n[1]);
+  for (int l = 1; l < t.levels; ++l)
+    hipLaunchKernelGGL(kw_treduce<R>, dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
+                       (const R*)w.tmap[l], t.n[l], (R*)w.tmap[l + 1], t.n[l + 1]);
+  hipLaunchKernelGGL(kw_ttop<R>, dim3(1, kp.batch), b, 0, s, kp, (const R*)w.tmap[t.levels],
+                     t.n[t.levels], (R*)w.tx[t.levels]);
+  for (int l = t.levels - 1; l >= 1; --l)
+    hipLaunchKernelGGL(kw_tdown<R>, dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
+                       (const R*)w.tmap[l], t.n[l], (const R*)w.tx[l + 1], t.n[l + 1],
+                       (R*)w.tx[l]);
+  hipLaunchKernelGGL(kw_tbottom<R>, dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
+                     (const R*)elts, (const R*)S, (const R*)v, (const R*)w.tx[1], t.n[1], (R*)x,
+                     (R*)u);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t wave_build(const KProb& kp, int dtype, void* elts, hipStream_t s) {
+  return dtype == 0 ? wave_build_t<double>(kp, elts, s) : wave_build_t<float>(kp, elts, s);
+}
+
+hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
+                      void* S, void* v, void* maps1, hipStream_t s) {
+  return dtype == 0 ? wave_value_t<double>(kp, t, w, elts, S, v, maps1, s)
+                    : wave_value_t<float>(kp, t, w, elts, S, v, maps1, s);
+}
+
+hipError_t wave_traj(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
+                     const void* S, const void* v, void* x, void* u, bool maps_ready,
+                     hipStream_t s) {
+  return dtype == 0 ? wave_traj_t<double>(kp, t, w, elts, S, v, x, u, maps_ready, s)
+                    : wave_traj_t<float>(kp, t, w, elts, S, v, x, u, maps_ready, s);
+}
+
+}  // namespace lqt

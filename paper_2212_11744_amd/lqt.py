@@ -135,6 +135,9 @@ class DeviceProblem:
             if (p.nx, p.nu, p.T, p.n) != (p0.nx, p0.nu, p0.T, p0.n):
                 raise ValueError("batched problems must share nx, nu, T and n")
         F_s, L_s = np.ndim(p0.F) == 3, np.ndim(p0.L) == 3
+        for name, sampled in (("F", F_s), ("L", L_s)):
+            if not sampled and any(not np.array_equal(getattr(p, name), getattr(p0, name)) for p in problems):
+                raise ValueError(f"a constant {name} is shared by the batch: members differ")
         to = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
         stack = lambda name: to(np.stack([np.asarray(getattr(p, name)) for p in problems]))
         has_c = getattr(p0, "c", None) is not None

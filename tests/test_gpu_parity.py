@@ -2,7 +2,7 @@
 
 Tolerances (normwise, see helpers.relerr): 1e-9 in FP64 and 1e-4 in FP32 against the FP64 oracle
 for elements, value matrices, trajectories and controls; exact for the integer-valued scan example.
-Sizes span several scan tiles and ragged tails; the full-size case is in test_gpu_fullsize.py.
+Sizes span several scan tiles and ragged tails; the full-size T = 2^20 case is in test_gpu_fullsize.py.
 """
 import json
 import os
@@ -176,10 +176,3 @@ def test_point_mass_fp64_2pow16():
     ref = O.solve(p)
     out = lqt.solve(lqt.DeviceProblem.from_problems([p]))
     _check_solution(p, out, ref, torch.float64, label="T=2^16")
-
-
-def test_unsupported_size_is_an_error():
-    p = W.random_stable(1, nx=6, nu=2, T=16, n=2)
-    with pytest.raises(lqt.LQTError) as ei:
-        lqt.solve(lqt.DeviceProblem.from_problems([p]))
-    assert ei.value.status in (lqt.LQT_EUNSUPPORTED,)
