@@ -13,6 +13,12 @@ kernel's formulation (see build_flops_per_block), the same figure the design not
 The CPU baseline is the oracle (single-threaded, unmodified) on a bounded sample of the same
 workload: the first M blocks of the grid (same block length and reference) solved as a horizon
 of their own.
+
+Also reported (not the headline): the differentiated workload (64 point-mass problems, T = 2^16,
+FP64: one batched lqt_solve plus one lqt_backward of a tracking loss, "fwd+bwd ms") and the
+random time-varying nx = 16 workload (T = 2^14, F(t) sampled).  `--copy-probe MIB` adds a plain
+device copy of that size after the timed work, so that a counter run (rocprofv3 --pmc FETCH_SIZE
+/ WRITE_SIZE) can scale the element build's counter readings by those of a copy of known size.
 """
 from __future__ import annotations
 
@@ -94,7 +100,10 @@ def main(argv=None):
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic_build_f64_T2p20.json"))
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_build_point_mass_T2p20_traffic.txt"))
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-nx16", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for "
@@ -134,12 +143,7 @@ def main(argv=None):
     flops = build_flops_per_block(4, 2, n) * T
     achieved = flops / (ms_build * 1e-3) / 1e12
     peak = PEAK["f64_TFLOPs" if es == 8 else "f32_TFLOPs"]
-    traffic = None
-    if os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            tr = json.load(f)
-        if tr.get("T") == T and tr.get("dtype") == args.dtype and tr.get("kernel_source_sha") == _kernel_sha():
-            traffic = tr.get("bytes_per_launch")
+    traffic = _traffic(args.traffic, T, args.dtype)
     # Stage breakdown (each stage call timed on its own).
     S, v = out["S"], out["v"]
     ws_v = lqt.workspace(dp, lqt.CALL_SCAN_VALUE)
@@ -170,10 +174,70 @@ def main(argv=None):
                      "algorithmic_bytes_per_launch": build_bytes_per_block(4, n, es) * T},
         "stages_ms": {"build_elements": ms_build, "scan_value": ms_scan, "forward_traj": ms_traj},
     }
+    if not args.no_adjoint:
+        rec["adjoint"] = adjoint_leg(torch, lqt, W, max(3, args.steps // 4))
+    if not args.no_nx16:
+        rec["nx16"] = nx16_leg(torch, lqt, W, max(3, args.steps // 4))
+    if args.copy_probe:
+        a = torch.empty(args.copy_probe * 2 ** 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        rec["copy_probe_bytes"] = a.numel()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(T, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
     return 0
+
+
+def adjoint_leg(torch, lqt, W, reps):
+    """64 point-mass problems (seeds 5000 + i), T = 2^16, FP64: batched solve + adjoint of the
+    loss sum_k |x_k - g(t_k)|^2 (gradients for Q, R, r, x0, Qf, rf)."""
+    B, T, n = 64, 2 ** 16, 4
+    probs = [W.point_mass(5000 + i, T, n) for i in range(B)]
+    dp = lqt.DeviceProblem.from_problems(probs)
+    g = torch.as_tensor(np.stack([W.tracking_targets(5, p.t) for p in probs]), device="cuda")
+    ws_f, ws_b = lqt.workspace(dp, lqt.CALL_SOLVE), lqt.workspace(dp, lqt.CALL_BACKWARD)
+    out = lqt.solve(dp, ws=ws_f)
+    fwd = lambda: lqt.solve(dp, out, ws_f)
+    bwd = lambda: lqt.backward(dp, out["S"], out["v"], out["x"], 2.0 * (out["x"] - g), ws=ws_b)
+    fwd(), bwd()
+    torch.cuda.synchronize()
+    ms_f = _events_time(fwd, reps, torch)
+    ms_b = _events_time(bwd, reps, torch)
+    return {"workload": f"{B} point-mass problems, T={T} blocks x {n} RK4 steps, FP64, tracking loss",
+            "fwd_ms": ms_f, "bwd_ms": ms_b, "fwd_bwd_ms": ms_f + ms_b,
+            "sub_intervals_per_s_fwd_bwd": B * T / ((ms_f + ms_b) * 1e-3)}
+
+
+def nx16_leg(torch, lqt, W, reps):
+    """Random stable time-varying LQT, nx = 16, nu = 4, T = 2^14, F(t) sampled, FP64."""
+    T = 2 ** 14
+    p = W.random_stable(3, nx=16, nu=4, T=T, n=4)
+    dp = lqt.DeviceProblem.from_problems([p])
+    ws = lqt.workspace(dp, lqt.CALL_SOLVE)
+    out = lqt.solve(dp, ws=ws)
+    torch.cuda.synchronize()
+    ms = _events_time(lambda: lqt.solve(dp, out, ws), reps, torch)
+    return {"workload": f"random stable time-varying LQT nx=16 nu=4, T={T} x 4 RK4 steps, FP64",
+            "ms": ms, "sub_intervals_per_s": T / (ms * 1e-3)}
+
+
+def _traffic(path, T, dtype):
+    """HBM bytes per launch of the element build from a committed counter summary (key: value
+    lines), or None when it was taken for another workload or an older kernel source."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("T") != str(T) or kv.get("dtype") != dtype or kv.get("kernel_source_sha") != _kernel_sha():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
 
 
 def _kernel_sha() -> str:
