@@ -159,6 +159,66 @@ lqt_status lqt_backward(const lqt_dims *dims, const lqt_problem *prob, const voi
                         void *dr, void *dx0, void *dQf, void *drf, void *ws, size_t ws_bytes,
                         hipStream_t stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Batched solve: many problems with uneven horizons and several sizes in one call.
+ *
+ * Problems are grouped in classes that share nx, nu, n_steps, dtype and the sampling flags; a
+ * call takes several classes.  Inside a class, problem i has T_i >= 1 blocks and the arrays of
+ * all its problems are concatenated ("rows" = sum_i (T_i + 1)):
+ *   start  [count + 1] DEVICE int64: start[0] = 0, start[i + 1] = start[i] + T_i + 1,
+ *          start[count] = rows.  Row start[i] + k (k = 0..T_i) of t, S, v, x, u is boundary k
+ *          of problem i.  The kernels trust these values (they only clamp problem indices).
+ *   t      [rows]  block boundaries, strictly increasing within each problem
+ *   r      the NS_i = 2 n_steps T_i + 1 half-step samples of each problem back to back:
+ *          [2 n_steps (rows - count) + count][nx]; F, L, c when sampled likewise
+ *   F, L   when constant: one per problem, [count][nx*nx] and [count][nx*nu]
+ *   Q, R, Qf, rf, x0  [count][...] one per problem
+ *   S [rows][nx*nx], v [rows][nx], x [rows][nx], u [rows][nu] (u may be NULL)
+ * Results equal those of lqt_solve on each problem alone up to rounding.  Method: the problems
+ * of a class form one horizon in which every problem is followed by a separator element
+ * (A = 0, b = x0 of the next problem, C = 0, eta = Qf rf, J = Qf).  Folded into a value
+ * function (Theorem 6, Lemma 7) the separator returns the problem's terminal value (Sec. IV-D)
+ * whatever follows it, and its closed-loop map (Sec. IV-E) sends any state to the next x0, so
+ * one scan of each kind solves every problem of the class.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct lqt_ragged {
+  int32_t nx, nu, n_steps, dtype; /* as in lqt_dims                                             */
+  int32_t count;                  /* problems in the class (>= 1)                                */
+  int32_t F_sampled, L_sampled, has_c;
+  int64_t rows;                   /* sum over problems of (T_i + 1); at most 2^31 - 1            */
+  const int64_t *start;           /* DEVICE [count + 1]                                          */
+  lqt_problem prob;               /* concatenated problem arrays (above)                         */
+  void *S, *v, *x, *u;            /* outputs (above); u may be NULL                              */
+} lqt_ragged;
+
+/* Bytes of workspace for lqt_solve_batched / lqt_plan_create on these classes (0 if invalid). */
+size_t lqt_batched_workspace_size(const lqt_ragged *classes, int32_t nclasses);
+
+/* All classes solved eagerly on `stream`, one after another, with the default configuration. */
+lqt_status lqt_solve_batched(const lqt_ragged *classes, int32_t nclasses, void *ws,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* A plan: the batched solve of fixed classes and buffers with a configuration fixed at creation,
+ * replayed by lqt_plan_launch: every class on its own stream, forked from and joined back into
+ * the launch stream (or one after another when tuning prefers that).  The arrays named in
+ * `classes` and the workspace are bound to the plan: refill them in place between launches and
+ * keep them alive until lqt_plan_destroy; launches of one plan must not overlap.
+ * flags & LQT_PLAN_AUTOTUNE: time the candidate configurations (per class: fused or separate
+ * element build and level-1 products on the per-lane path; 4, 8 or 16 nodes per wave on the wave
+ * path; then concurrent or serial classes) by running them on `stream` (outputs are overwritten)
+ * and keep the fastest; choices are cached per class signature for the life of the process
+ * (thread-safe).  Without the flag the default configuration is used.  flags & LQT_PLAN_GRAPH
+ * (capture the plan into a HIP graph) returns LQT_EUNSUPPORTED in this build.
+ * lqt_plan_create synchronises `stream`. */
+typedef struct lqt_plan_s *lqt_plan;
+enum { LQT_PLAN_AUTOTUNE = 1, LQT_PLAN_GRAPH = 2 };
+lqt_status lqt_plan_create(const lqt_ragged *classes, int32_t nclasses, void *ws,
+                           size_t ws_bytes, int32_t flags, hipStream_t stream, lqt_plan *plan);
+lqt_status lqt_plan_launch(lqt_plan plan, hipStream_t stream);
+/* Human-readable description of the configuration a plan uses (valid until destroy). */
+const char *lqt_plan_config(lqt_plan plan);
+void lqt_plan_destroy(lqt_plan plan);
+
 /* Short description of a status code. */
 const char *lqt_status_string(lqt_status status);
 

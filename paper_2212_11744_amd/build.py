@@ -20,7 +20,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "liblqt.so")
 OBJ_DIR = os.path.join(HERE, "_build")
 
-SOURCES = ["lqt_api.hip", "lqt_prep.hip", "lqt_lane.hip", "lqt_adjoint.hip", "lqt_wave.hip"]
+SOURCES = ["lqt_api.hip", "lqt_prep.hip", "lqt_lane.hip", "lqt_adjoint.hip", "lqt_wave.hip",
+           "lqt_batched.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

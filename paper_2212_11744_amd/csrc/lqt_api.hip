@@ -63,8 +63,13 @@ constexpr int kWaveChunk = 8;  // nodes per wave at every level of the wave path
 
 WTree wtree_for(const lqt_dims* d) { return wave_tree(d->T, kWaveChunk); }
 
+}  // namespace
+
 // Byte layout of the workspace of one call.  Returns the total; fills w when base != nullptr.
-size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w) {
+// wc: nodes per wave of the wave path's trees (the layout for wc also serves any larger wc);
+// nconsts: number of problems whose constants are prepared (the batch, or the problems of a
+// ragged class).
+size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, long nconsts) {
   const size_t es = dsize(d->dtype);
   const long B = d->batch;
   size_t off = 0;
@@ -73,12 +78,12 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w) {
     off += align256(bytes);
     return p;
   };
-  void* consts = take(es * B * consts_count(d->nx, d->nu));
+  void* consts = take(es * nconsts * consts_count(d->nx, d->nu));
   if (w) w->consts = consts;
   const bool want_v = call == LQT_CALL_SCAN_VALUE || call == LQT_CALL_SOLVE;
   const bool want_t = call == LQT_CALL_FORWARD_TRAJ || call == LQT_CALL_SOLVE;
   if (use_wave(d)) {
-    const WTree t = wtree_for(d);
+    const WTree t = wave_tree(d->T, wc);
     for (int l = 1; l <= t.levels; ++l) {
       if (want_v) {
         void* a = take(es * B * ne_of(d->nx) * t.n[l]);
@@ -161,6 +166,12 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w) {
     }
   }
   return off;
+}
+
+namespace {
+
+size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w) {
+  return layout(d, call, base, w, kWaveChunk, d->batch);
 }
 
 lqt_status check_dims_valid(const lqt_dims* d) {
@@ -369,6 +380,42 @@ lqt_status lqt_forward_traj(const lqt_dims* dims, const lqt_problem* prob, const
   return ok();
 }
 
+}  // extern "C"
+
+namespace lqt {
+
+// The launch sequence of a full solve (prep, elements, value scan, trajectory scan) for
+// validated arguments; shared by lqt_solve and the batched solve.
+lqt_status run_solve(const lqt_dims* dims, const KProb& kp, const Work& w, void* e, void* S,
+                     void* v, void* x, void* u, const SolveOpts& o, hipStream_t stream) {
+  KProb kprep = kp;
+  if (kp.seg) kprep.batch = kp.nseg;
+  LQT_HIP(prep(dims, kprep, w.consts, stream));
+  if (use_wave(dims)) {
+    const WTree wt = wave_tree(dims->T, o.wave_chunk);
+    LQT_HIP(wave_build(kp, dims->dtype, e, stream));
+    LQT_HIP(wave_value(kp, dims->dtype, wt, w, e, S, v, w.tmap[1], stream));
+    LQT_HIP(wave_traj(kp, dims->dtype, wt, w, e, S, v, x, u, true, stream));
+    return LQT_OK;
+  }
+  const Ops* op = lane_ops(dims->nx, dims->nu, dims->dtype);
+  const Tree t = tree_for(dims);
+  if (o.fused)
+    LQT_HIP(op->build_reduce(kp, e, w.vtup[1], t.n[1], stream));
+  else
+    LQT_HIP(op->build(kp, e, stream));
+  LQT_TRY(run_value(op, kp, t, w, e, S, v, w.tmap[1], o.fused, stream));
+  LQT_TRY(run_traj(op, kp, t, w, e, S, v, x, u, stream));
+  return LQT_OK;
+}
+
+lqt_status set_error(lqt_status st, const char* msg) { return fail(st, "%s", msg); }
+lqt_status clear_error() { return ok(); }
+
+}  // namespace lqt
+
+extern "C" {
+
 lqt_status lqt_solve(const lqt_dims* dims, const lqt_problem* prob, void* elts, void* S, void* v,
                      void* x, void* u, void* ws, size_t ws_bytes, hipStream_t stream) {
   LQT_TRY(check_supported(dims));
@@ -383,25 +430,12 @@ lqt_status lqt_solve(const lqt_dims* dims, const lqt_problem* prob, void* elts, 
   LQT_TRY(check_ws(dims, LQT_CALL_SOLVE, ws, ws_bytes, &w));
   KProb kp = make_kprob(dims, prob, w.consts);
   void* e = elts ? elts : w.elts;
-  LQT_HIP(prep(dims, kp, w.consts, stream));
-  if (use_wave(dims)) {
-    const WTree wt = wtree_for(dims);
-    LQT_HIP(wave_build(kp, dims->dtype, e, stream));
-    LQT_HIP(wave_value(kp, dims->dtype, wt, w, e, S, v, w.tmap[1], stream));
-    LQT_HIP(wave_traj(kp, dims->dtype, wt, w, e, S, v, x, u, true, stream));
-    return ok();
-  }
-  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
-  const Tree t = tree_for(dims);
   // FP32 builds its elements and level 1 of the value tree in one kernel; in FP64 the fused
   // kernel exceeds the register file, so the build and the level-1 products run separately.
-  const bool fused = dims->dtype == LQT_F32;
-  if (fused)
-    LQT_HIP(o->build_reduce(kp, e, w.vtup[1], t.n[1], stream));
-  else
-    LQT_HIP(o->build(kp, e, stream));
-  LQT_TRY(run_value(o, kp, t, w, e, S, v, w.tmap[1], fused, stream));
-  LQT_TRY(run_traj(o, kp, t, w, e, S, v, x, u, stream));
+  SolveOpts o;
+  o.fused = dims->dtype == LQT_F32;
+  o.wave_chunk = kWaveChunk;
+  LQT_TRY(run_solve(dims, kp, w, e, S, v, x, u, o, stream));
   return ok();
 }
 

@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "../../include/lqt.h"
+
 #include <cstddef>
 #include <cstdint>
 
@@ -18,7 +20,30 @@ struct KProb {
   int F_sampled, L_sampled, has_c;
   const void *t, *F, *L, *c, *Q, *R, *r, *Qf, *rf, *x0;
   const void* consts;  // per-problem prepared constants (see consts_count)
+  // Ragged mode (batched solve of problems with uneven horizons): seg != nullptr.  The nseg
+  // problems are concatenated into one horizon of T blocks (batch = 1): problem i owns blocks
+  // seg[i] .. seg[i+1] - 2 and block seg[i+1] - 1 is a separator element (A = 0, b = x0 of
+  // problem i + 1, C = 0, eta = Qf_i rf_i, J = Qf_i).  t has T rows (row g = left end of block g),
+  // samples of problem i start at sample 2n (seg[i] - i) + i, constant F, L and Q, R, Qf, rf, x0
+  // are per problem, and outputs have T rows (row g = boundary g; no row for the end of the last
+  // separator).
+  const int64_t* seg = nullptr;
+  int nseg = 0;
 };
+
+// Index of the problem owning block (or boundary) g in ragged mode: the largest i with
+// seg[i] <= g, clamped to [0, nseg - 1].
+__device__ inline int seg_find(const int64_t* seg, int nseg, long g) {
+  int lo = 0, hi = nseg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
 
 // Per-problem constants prepared once per call by the prep kernel (values of the call dtype):
 //   G = L R^{-1} L^T [nx*nx], Lc = L W [nx*nu] with W = chol(R)^{-T} (so G = Lc Lc^T),
@@ -142,6 +167,25 @@ hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w,
 hipError_t wave_traj(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
                      const void* S, const void* v, void* x, void* u, bool maps_ready,
                      hipStream_t s);
+
+// Options of a full solve: fused element build + level-1 value products (per-lane path), and
+// the number of nodes per wave of the wave path's trees.
+struct SolveOpts {
+  bool fused = false;
+  int wave_chunk = 8;
+};
+
+// Workspace layout of one call (lqt_api.hip); the layout for wave_chunk wc also serves any larger
+// chunk.  nconsts: problems whose per-problem constants are prepared.
+size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, long nconsts);
+
+// Prep, element build, value scan and trajectory scan for validated arguments.
+lqt_status run_solve(const lqt_dims* d, const KProb& kp, const Work& w, void* elts, void* S,
+                     void* v, void* x, void* u, const SolveOpts& o, hipStream_t stream);
+
+// Record / clear the calling thread's last error (lqt_last_error).
+lqt_status set_error(lqt_status st, const char* msg);
+lqt_status clear_error();
 
 // Prep kernel (any nx, nu <= 16).
 hipError_t launch_prep(const KProb& kp, int dtype, void* consts, hipStream_t stream);

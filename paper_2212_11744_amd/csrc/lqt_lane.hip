@@ -44,18 +44,34 @@ __device__ inline long gid() { return (long)blockIdx.x * blockDim.x + threadIdx.
 // enter a right-hand side, so their RK4 increments are accumulated directly.  CONST_COEF: F, L
 // constant and c = 0 (their values are then wave-uniform and stay in scalar registers).
 // ------------------------------------------------------------------------------------------
+// Where the inputs of one block are: problem p (Q, prepared constants, constant F and L), sample
+// j of the block at global sample index s0 + 2 n k + j, and its ends at t[tk], t[tk + 1].
+struct Blk {
+  int p;
+  long k, s0, tk;
+};
+
+LQT_DEV Blk blk_plain(const KProb& kp, int p, long k) {
+  const long nsamp = 2L * kp.n * kp.T + 1;
+  return {p, k, p * nsamp, p * (kp.T + 1L) + k};
+}
+
+// Block g of problem i in ragged mode: the problem's samples start at 2 n (seg[i] - i) + i.
+LQT_DEV Blk blk_ragged(const KProb& kp, int i, long g) {
+  return {i, g, (long)i * (1 - 2L * kp.n), g};
+}
+
 template <int N, int NU, class R, bool CONST_COEF>
-LQT_DEV void build_block(const KProb& kp, int p, long k, Tup<N, R>& out) {
+LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
   using Y = Sym<N>;
   constexpr int NS = Y::size;
-  const long T = kp.T;
   const int n = kp.n;
-  const long nsamp = 2L * n * T + 1;
-  const R* __restrict__ t = (const R*)kp.t + p * (T + 1);
-  const R* __restrict__ r = (const R*)kp.r + p * nsamp * N;
-  const R* __restrict__ Fb = (const R*)kp.F + (kp.F_sampled ? p * nsamp * N * N : 0);
-  const R* __restrict__ Lb = (const R*)kp.L + (kp.L_sampled ? p * nsamp * N * NU : 0);
-  const R* __restrict__ cb = kp.has_c ? (const R*)kp.c + p * nsamp * N : nullptr;
+  const int p = bk.p;
+  const long k = bk.k;
+  const long s0 = bk.s0;
+  const long pf = kp.seg ? p : 0;  // constant F, L: shared by a batch, per problem when ragged
+  const R* __restrict__ t = (const R*)kp.t + bk.tk;
+  const R* __restrict__ Fc = (const R*)kp.F + pf * N * N;
   const R* __restrict__ Qp = (const R*)kp.Q + p * N * N;
   const R* __restrict__ cs = (const R*)kp.consts + p * CS<N, NU>::size;
 
@@ -70,7 +86,7 @@ LQT_DEV void build_block(const KProb& kp, int p, long k, Tup<N, R>& out) {
     for (int i = 0; i < N; ++i) {
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        F[i][j] = Fb[i * N + j];
+        F[i][j] = Fc[i * N + j];
         G[i][j] = cs[CS<N, NU>::G + i * N + j];
       }
 #pragma unroll
@@ -86,7 +102,7 @@ LQT_DEV void build_block(const KProb& kp, int p, long k, Tup<N, R>& out) {
       for (int j = 0; j < NU; ++j) Wr[i][j] = cs[CS<N, NU>::W + i * NU + j];
   }
 
-  const R h = (t[k + 1] - t[k]) / R(n);
+  const R h = (t[1] - t[0]) / R(n);
   R yA[N][N], yb[N], yC[NS], ye[N], yJ[NS];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -120,15 +136,15 @@ LQT_DEV void build_block(const KProb& kp, int p, long k, Tup<N, R>& out) {
       const R cn = st == 2 ? -h : -h / R(2);
       R rv[N];
 #pragma unroll
-      for (int i = 0; i < N; ++i) rv[i] = r[j * N + i];
+      for (int i = 0; i < N; ++i) rv[i] = ((const R*)kp.r)[(s0 + j) * N + i];
       if (!CONST_COEF) {
-        const R* Fj = kp.F_sampled ? Fb + j * N * N : Fb;
+        const R* Fj = kp.F_sampled ? (const R*)kp.F + (s0 + j) * N * N : Fc;
 #pragma unroll
         for (int i = 0; i < N; ++i)
 #pragma unroll
           for (int q = 0; q < N; ++q) F[i][q] = Fj[i * N + q];
         if (kp.L_sampled) {
-          const R* Lj = Lb + j * N * NU;
+          const R* Lj = (const R*)kp.L + (s0 + j) * N * NU;
 #pragma unroll
           for (int i = 0; i < N; ++i)
 #pragma unroll
@@ -157,7 +173,7 @@ LQT_DEV void build_block(const KProb& kp, int p, long k, Tup<N, R>& out) {
           }
         }
 #pragma unroll
-        for (int i = 0; i < N; ++i) cv[i] = cb ? cb[j * N + i] : R(0);
+        for (int i = 0; i < N; ++i) cv[i] = kp.has_c ? ((const R*)kp.c)[(s0 + j) * N + i] : R(0);
       }
       // K = G J - F
       R K[N][N];
@@ -287,13 +303,55 @@ LQT_DEV void build_block(const KProb& kp, int p, long k, Tup<N, R>& out) {
   }
 }
 
+// Separator element of ragged mode after problem i: A = 0 (stored A - I = -I), b = x0 of
+// problem i + 1 (0 after the last), C = 0, eta = Qf_i rf_i, J = Qf_i.  Folded into a value it
+// returns (Qf_i, Qf_i rf_i) whatever lies to its right; its closed-loop map is x -> b.
+template <int N, class R>
+LQT_DEV void separator(const KProb& kp, int i, Tup<N, R>& out) {
+  const R* Qf = (const R*)kp.Qf + (long)i * N * N;
+  const R* rf = (const R*)kp.rf + (long)i * N;
+  const R* x0n = (const R*)kp.x0 + (long)(i + 1) * N;
+  const bool last = i + 1 >= kp.nseg;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+#pragma unroll
+    for (int b = 0; b < N; ++b) out.A[a][b] = a == b ? R(-1) : R(0);
+    out.b[a] = last ? R(0) : x0n[a];
+    R s = R(0);
+#pragma unroll
+    for (int b = 0; b < N; ++b) s = fma(Qf[a * N + b], rf[b], s);
+    out.e[a] = s;
+  }
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = a; b < N; ++b) {
+      out.C[Sym<N>::at(a, b)] = R(0);
+      out.J[Sym<N>::at(a, b)] = Qf[a * N + b];
+    }
+}
+
+// Element k of problem p (plain mode) or element k of the concatenated horizon (ragged mode).
+template <int N, int NU, class R, bool CONST_COEF>
+LQT_DEV void element_at(const KProb& kp, int p, long k, Tup<N, R>& out) {
+  if (!kp.seg) {
+    build_block<N, NU, R, CONST_COEF>(kp, blk_plain(kp, p, k), out);
+    return;
+  }
+  const int i = seg_find(kp.seg, kp.nseg, k);
+  if (k == kp.seg[i + 1] - 1 || k == kp.T - 1)
+    separator<N, R>(kp, i, out);
+  else
+    build_block<N, NU, R, CONST_COEF>(kp, blk_ragged(kp, i, k), out);
+}
+
 template <int N, int NU, class R, bool CONST_COEF>
 __global__ __launch_bounds__(kThreads) void k_build(const KProb kp, R* __restrict__ elts) {
   const int p = blockIdx.y;
   const long k = gid();
   if (k >= kp.T) return;
   Tup<N, R> out;
-  build_block<N, NU, R, CONST_COEF>(kp, p, k, out);
+  element_at<N, NU, R, CONST_COEF>(kp, p, k, out);
   tup_store(out, elts + (long)p * Lay<N>::NE * padt(kp.T), k);
 }
 
@@ -309,11 +367,11 @@ __global__ __launch_bounds__(kThreads) void k_build_reduce(const KProb kp, R* __
   R* ep = elts + (long)p * Lay<N>::NE * padt(T);
   const long j0 = i * kChunk, j1 = min(j0 + kChunk, T);
   Tup<N, R> acc;
-  build_block<N, NU, R, CONST_COEF>(kp, p, j1 - 1, acc);
+  element_at<N, NU, R, CONST_COEF>(kp, p, j1 - 1, acc);
   tup_store(acc, ep, j1 - 1);
   for (long k = j1 - 2; k >= j0; --k) {
     Tup<N, R> a;
-    build_block<N, NU, R, CONST_COEF>(kp, p, k, a);
+    element_at<N, NU, R, CONST_COEF>(kp, p, k, a);
     tup_store(a, ep, k);
     combine(a, acc, acc);
   }
@@ -421,7 +479,7 @@ __global__ __launch_bounds__(kThreads) void k_vbottom(const KProb kp, const R* _
   val_load<N, R>(S, v, val1 + (long)p * Lay<N>::NV * padt(n1), i);
   const long j0 = i * kChunk;
   const long j1 = min(j0 + kChunk, T);
-  if (j1 == T) {
+  if (j1 == T && !kp.seg) {
     S_store_full<N, R>(S, Sp + T * N * N);
 #pragma unroll
     for (int q = 0; q < N; ++q) vp[T * N + q] = v[q];
@@ -459,6 +517,23 @@ LQT_DEV void elt_map_part(const R* ep, long k, R (&Ad)[N][N], R (&b)[N], R (&C)[
   for (int q = 0; q < Sym<N>::size; ++q) C[q] = ep[tix<L::NE>(L::C + q, k)];
 }
 
+// (S_{k+1}, v_{k+1}) at the right end of block k.  In ragged mode the last block is a separator
+// (C = 0), whose map does not depend on them, and row T does not exist: zeros are used.
+template <int N, class R>
+LQT_DEV void load_right_value(const KProb& kp, const R* Sp, const R* vp, long k,
+                              R (&S)[Sym<N>::size], R (&v)[N]) {
+  if (kp.seg && k + 1 >= kp.T) {
+#pragma unroll
+    for (int q = 0; q < Sym<N>::size; ++q) S[q] = R(0);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = R(0);
+    return;
+  }
+  S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
+#pragma unroll
+  for (int q = 0; q < N; ++q) v[q] = vp[(k + 1) * N + q];
+}
+
 template <int N, class R>
 __global__ __launch_bounds__(kThreads) void k_tbottom_reduce(const KProb kp,
                                                               const R* __restrict__ elts,
@@ -479,9 +554,7 @@ __global__ __launch_bounds__(kThreads) void k_tbottom_reduce(const KProb kp,
   for (long k = j0; k < j1; ++k) {
     R Ad[N][N], b[N], C[Sym<N>::size], S[Sym<N>::size], v[N];
     elt_map_part<N, R>(ep, k, Ad, b, C);
-    S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
-#pragma unroll
-    for (int q = 0; q < N; ++q) v[q] = vp[(k + 1) * N + q];
+    load_right_value<N, R>(kp, Sp, vp, k, S, v);
     Aff<N, R> m;
     block_map<N, R>(Ad, b, C, S, v, m);
     aff_then(acc, m);
@@ -510,8 +583,17 @@ LQT_DEV void control(const R (&Kc)[NU][N], const R (&S)[Sym<N>::size], const R (
   }
 }
 
+// Gain R^{-1} L(t_k)^T at boundary k of problem p (plain mode) or at boundary k of the
+// concatenated horizon (ragged mode; the owning problem is looked up).
 template <int N, int NU, class R>
 LQT_DEV void gain_at(const KProb& kp, int p, long k, R (&Kc)[NU][N]) {
+  long s0;
+  if (kp.seg) {
+    p = seg_find(kp.seg, kp.nseg, k);
+    s0 = (long)p * (1 - 2L * kp.n);
+  } else {
+    s0 = (long)p * (2L * kp.n * kp.T + 1);
+  }
   const R* cs = (const R*)kp.consts + (long)p * CS<N, NU>::size;
   if (!kp.L_sampled) {
 #pragma unroll
@@ -519,8 +601,7 @@ LQT_DEV void gain_at(const KProb& kp, int p, long k, R (&Kc)[NU][N]) {
 #pragma unroll
       for (int j = 0; j < N; ++j) Kc[l][j] = cs[CS<N, NU>::Kc + l * N + j];
   } else {
-    const long nsamp = 2L * kp.n * kp.T + 1;
-    const R* Lk = (const R*)kp.L + ((long)p * nsamp + 2L * kp.n * k) * N * NU;
+    const R* Lk = (const R*)kp.L + (s0 + 2L * kp.n * k) * N * NU;
 #pragma unroll
     for (int l = 0; l < NU; ++l)
 #pragma unroll
@@ -558,28 +639,27 @@ __global__ __launch_bounds__(kThreads) void k_tbottom(const KProb kp, const R* _
 #pragma unroll
   for (int q = 0; q < N; ++q) v[q] = vp[j0 * N + q];
   R Kc[NU][N];
-  if (!kp.L_sampled) gain_at<N, NU, R>(kp, p, 0, Kc);
+  const bool per_k = kp.L_sampled || kp.seg;
+  if (!per_k) gain_at<N, NU, R>(kp, p, 0, Kc);
   for (long k = j0; k < j1; ++k) {
 #pragma unroll
     for (int q = 0; q < N; ++q) xp[k * N + q] = x[q];
     if (up) {
-      if (kp.L_sampled) gain_at<N, NU, R>(kp, p, k, Kc);
+      if (per_k) gain_at<N, NU, R>(kp, p, k, Kc);
       control<N, NU, R>(Kc, S, v, x, up + k * NU);
     }
     R Ad[N][N], b[N], C[Sym<N>::size];
     elt_map_part<N, R>(ep, k, Ad, b, C);
-    S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
-#pragma unroll
-    for (int q = 0; q < N; ++q) v[q] = vp[(k + 1) * N + q];
+    load_right_value<N, R>(kp, Sp, vp, k, S, v);
     Aff<N, R> m;
     block_map<N, R>(Ad, b, C, S, v, m);
     aff_apply(m, x);
   }
-  if (j1 == T) {
+  if (j1 == T && !kp.seg) {
 #pragma unroll
     for (int q = 0; q < N; ++q) xp[T * N + q] = x[q];
     if (up) {
-      if (kp.L_sampled) gain_at<N, NU, R>(kp, p, T, Kc);
+      if (per_k) gain_at<N, NU, R>(kp, p, T, Kc);
       control<N, NU, R>(Kc, S, v, x, up + T * NU);
     }
   }
@@ -641,7 +721,7 @@ __global__ __launch_bounds__(kThreads) void k_prep_lane(const KProb kp, R* __res
       cs[C::Rinv + i * NU + j] = s;
     }
   if (!kp.L_sampled) {
-    const R* L = (const R*)kp.L;
+    const R* L = (const R*)kp.L + (kp.seg ? (long)p * N * NU : 0);
     R Lc[N][NU];
 #pragma unroll
     for (int i = 0; i < N; ++i)

@@ -49,7 +49,7 @@ __global__ void k_prep(const KProb kp, R* __restrict__ consts) {
       cs[oRi + i * nu + j] = s;
     }
   if (!kp.L_sampled) {
-    const R* L = (const R*)kp.L;
+    const R* L = (const R*)kp.L + (kp.seg ? (long)p * nx * nu : 0);
     const int oG = consts_off_G(nx, nu), oLc = consts_off_Lc(nx, nu), oK = consts_off_Kc(nx, nu);
     for (int i = 0; i < nx; ++i)
       for (int l = 0; l < nu; ++l) {

@@ -444,23 +444,57 @@ WDEV WS<R> ws_at(R* base, int* piv, int n) {
 // ------------------------------------------------------------------------------------------
 // Element build (Theorem 8), one wave per block: RK4 on the full matrices.
 // ------------------------------------------------------------------------------------------
+// Separator element of ragged mode after problem i (see KProb): A - I = -I, b = x0 of problem
+// i + 1 (0 after the last), C = 0, eta = Qf_i rf_i, J = Qf_i.
+template <class R>
+WDEV void w_separator(const KProb& kp, int i, WT<R> y) {
+  const int n = kp.nx;
+  const R* Qf = (const R*)kp.Qf + (long)i * n * n;
+  const R* rf = (const R*)kp.rf + (long)i * n;
+  const bool last = i + 1 >= kp.nseg;
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int a = e / n, b = e % n;
+    y.A[e] = a == b ? R(-1) : R(0);
+    y.C[e] = R(0);
+    y.J[e] = Qf[(a < b ? a : b) * n + (a < b ? b : a)];
+  }
+  for (int a = lane_id(); a < n; a += 64) {
+    y.b[a] = last ? R(0) : ((const R*)kp.x0)[(long)(i + 1) * n + a];
+    R s = R(0);
+    for (int b = 0; b < n; ++b) s = fma(Qf[a * n + b], rf[b], s);
+    y.e[a] = s;
+  }
+  wsync();
+}
+
 template <class R>
 __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ elts) {
   __shared__ R sh[3 * kTupW + 8 * NM * NM + 4 * NM];
-  const int p = blockIdx.y;
-  const long k = blockIdx.x;
   const int n = kp.nx, nu = kp.nu;
   const long T = kp.T;
   const int nn = kp.n;
-  const long nsamp = 2L * nn * T + 1;
-  const R* t = (const R*)kp.t + (long)p * (T + 1);
-  const R* r = (const R*)kp.r + (long)p * nsamp * n;
-  const R* Fb = (const R*)kp.F + (kp.F_sampled ? (long)p * nsamp * n * n : 0);
-  const R* Lb = (const R*)kp.L + (kp.L_sampled ? (long)p * nsamp * n * nu : 0);
-  const R* cb = kp.has_c ? (const R*)kp.c + (long)p * nsamp * n : nullptr;
+  const long k = blockIdx.x;
+  // Problem p, sample offset s0 (sample j of the block at s0 + 2 n k + j), left end t[tk].
+  int p = blockIdx.y;
+  long s0 = (long)p * (2L * nn * T + 1), tk = (long)p * (T + 1) + k, pf = 0;
+  WT<R> y = wt_at(sh, n), ac = wt_at(sh + kTupW, n), st = wt_at(sh + 2 * kTupW, n);
+  if (kp.seg) {
+    p = seg_find(kp.seg, kp.nseg, k);
+    if (k == kp.seg[p + 1] - 1 || k == T - 1) {
+      w_separator(kp, p, y);
+      wt_store(y, elt_ref(elts, 0, k, T, ne_w(n)), n);
+      return;
+    }
+    s0 = (long)p * (1 - 2L * nn);
+    tk = k;
+    pf = p;
+  }
+  const R* t = (const R*)kp.t + tk;
+  const R* r = (const R*)kp.r;
+  const R* Fc = (const R*)kp.F + pf * n * n;  // constant F (per problem when ragged)
+  const R* cb = kp.has_c ? (const R*)kp.c : nullptr;
   const R* Qp = (const R*)kp.Q + (long)p * n * n;
   const R* cs = (const R*)kp.consts + (long)p * consts_count(n, nu);
-  WT<R> y = wt_at(sh, n), ac = wt_at(sh + kTupW, n), st = wt_at(sh + 2 * kTupW, n);
   R* F = sh + 3 * kTupW;
   R* G = F + NM * NM;
   R* K = G + NM * NM;
@@ -474,7 +508,7 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
   R* rv = ke + NM;
   R* cv = rv + NM;
   wt_identity(y, n);
-  const R h = (t[k + 1] - t[k]) / R(nn);
+  const R h = (t[1] - t[0]) / R(nn);
   for (int m = 0; m < nn; ++m) {
     const long j1 = 2L * nn * k + 2L * (nn - m);
     w_copy(st.A, y.A, n * n);
@@ -484,14 +518,14 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
       const long j = s == 0 ? j1 : (s == 3 ? j1 - 2 : j1 - 1);
       const R wk = (s == 0 || s == 3) ? -h / R(6) : -h / R(3);
       const R cn = s == 2 ? -h : -h / R(2);
-      const R* Fj = kp.F_sampled ? Fb + j * n * n : Fb;
+      const R* Fj = kp.F_sampled ? (const R*)kp.F + (s0 + j) * n * n : Fc;
       for (int e = lane_id(); e < n * n; e += 64) F[e] = Fj[e];
       for (int i = lane_id(); i < n; i += 64) {
-        rv[i] = r[j * n + i];
-        cv[i] = cb ? cb[j * n + i] : R(0);
+        rv[i] = r[(s0 + j) * n + i];
+        cv[i] = cb ? cb[(s0 + j) * n + i] : R(0);
       }
       if (kp.L_sampled) {
-        const R* Lj = Lb + j * n * nu;
+        const R* Lj = (const R*)kp.L + (s0 + j) * n * nu;
         const R* W = cs + consts_off_W(n, nu);
         for (int e = lane_id(); e < n * nu; e += 64) {
           const int i = e / nu, l = e % nu;
@@ -573,7 +607,7 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
     w_copy(y.e, ac.e, n);
     w_copy(y.J, ac.J, n * n);
   }
-  wt_store(y, elt_ref(elts, p, k, T, ne_w(n)), n);
+  wt_store(y, elt_ref(elts, kp.seg ? 0 : p, k, T, ne_w(n)), n);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -702,7 +736,7 @@ __global__ __launch_bounds__(64) void kw_vbottom(const KProb kp, int wc, const R
   R* Sp = Sout + (long)p * (T + 1) * n * n;
   R* vp = vout + (long)p * (T + 1) * n;
   const long j0 = i * wc, j1 = min(j0 + wc, T);
-  if (j1 == T) {
+  if (j1 == T && !kp.seg) {
     for (int e = lane_id(); e < n * n; e += 64) Sp[T * n * n + e] = S[e];
     for (int q = lane_id(); q < n; q += 64) vp[T * n + q] = v[q];
   }
@@ -737,6 +771,17 @@ WDEV void map_st(const R* P, const R* q, R* g, int n) {
   wsync();
 }
 
+// (S_{k+1}, v_{k+1}) into LDS; zeros for the last block in ragged mode (a separator, whose map
+// does not depend on them; row T does not exist there).
+template <class R>
+WDEV void w_right_value(const KProb& kp, const R* Sp, const R* vp, long k, R* S, R* v) {
+  const int n = kp.nx;
+  const bool none = kp.seg && k + 1 >= kp.T;
+  for (int e = lane_id(); e < n * n; e += 64) S[e] = none ? R(0) : Sp[(k + 1) * n * n + e];
+  for (int q = lane_id(); q < n; q += 64) v[q] = none ? R(0) : vp[(k + 1) * n + q];
+  wsync();
+}
+
 template <class R>
 __global__ __launch_bounds__(64) void kw_tbottom_reduce(const KProb kp, int wc, const R* __restrict__ elts,
                                                         const R* __restrict__ Sg,
@@ -765,9 +810,7 @@ __global__ __launch_bounds__(64) void kw_tbottom_reduce(const KProb kp, int wc, 
   w_aff_identity(aP, aq, n);
   for (long k = j0; k < j1; ++k) {
     wt_load(a, elt_ref(elts, p, k, T, NE), n);
-    for (int e = lane_id(); e < n * n; e += 64) S[e] = Sp[(k + 1) * n * n + e];
-    for (int q = lane_id(); q < n; q += 64) v[q] = vp[(k + 1) * n + q];
-    wsync();
+    w_right_value(kp, Sp, vp, k, S, v);
     w_block_map(a, S, v, scr, n, mP, mq);
     w_aff_then(aP, aq, mP, mq, tmp, n);
   }
@@ -869,15 +912,17 @@ __global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R
   const R* vp = vg + (long)p * (T + 1) * n;
   R* xp = xout + (long)p * (T + 1) * n;
   R* up = uout ? uout + (long)p * (T + 1) * nu : nullptr;
-  const R* cs = (const R*)kp.consts + (long)p * consts_count(n, nu);
-  const long nsamp = 2L * kp.n * T + 1;
   for (int q = lane_id(); q < n; q += 64) x[q] = x1[((long)p * n1 + i) * n + q];
   wsync();
   const long j0 = i * wc, j1 = min(j0 + wc, T);
   auto control = [&](long k) {
     if (!up) return;
+    // Gain of the problem owning boundary k (looked up in ragged mode).
+    const int pk = kp.seg ? seg_find(kp.seg, kp.nseg, k) : p;
+    const long s0 = kp.seg ? (long)pk * (1 - 2L * kp.n) : (long)p * (2L * kp.n * T + 1);
+    const R* cs = (const R*)kp.consts + (long)pk * consts_count(n, nu);
     if (kp.L_sampled) {
-      const R* Lk = (const R*)kp.L + ((long)p * nsamp + 2L * kp.n * k) * n * nu;
+      const R* Lk = (const R*)kp.L + (s0 + 2L * kp.n * k) * n * nu;
       const R* Ri = cs + consts_off_Rinv(n, nu);
       for (int e = lane_id(); e < nu * n; e += 64) {
         const int l = e / n, j = e % n;
@@ -905,13 +950,11 @@ __global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R
     for (int q = lane_id(); q < n; q += 64) xp[k * n + q] = x[q];
     control(k);
     wt_load(a, elt_ref(elts, p, k, T, NE), n);
-    for (int e = lane_id(); e < n * n; e += 64) S[e] = Sp[(k + 1) * n * n + e];
-    for (int q = lane_id(); q < n; q += 64) v[q] = vp[(k + 1) * n + q];
-    wsync();
+    w_right_value(kp, Sp, vp, k, S, v);
     w_block_map(a, S, v, scr, n, mP, mq);
     w_aff_apply(mP, mq, x, tmp, n);
   }
-  if (j1 == T) {
+  if (j1 == T && !kp.seg) {
     for (int q = lane_id(); q < n; q += 64) xp[T * n + q] = x[q];
     control(T);
   }

@@ -46,6 +46,16 @@ class Problem(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("t", "F", "L", "c", "Q", "R", "r", "Qf", "rf", "x0")]
 
 
+class Ragged(ctypes.Structure):
+    """lqt_ragged: one class of the batched solve (include/lqt.h)."""
+    _fields_ = [(n, ctypes.c_int32) for n in
+                ("nx", "nu", "n_steps", "dtype", "count", "F_sampled", "L_sampled", "has_c")] + [
+        ("rows", ctypes.c_int64), ("start", ctypes.c_void_p), ("prob", Problem),
+        ("S", ctypes.c_void_p), ("v", ctypes.c_void_p), ("x", ctypes.c_void_p), ("u", ctypes.c_void_p)]
+
+
+LQT_PLAN_AUTOTUNE, LQT_PLAN_GRAPH = 1, 2
+
 _lib = None
 
 
@@ -69,6 +79,18 @@ def lib():
         L.lqt_backward.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, st]
         for f in ("lqt_build_elements", "lqt_scan_value", "lqt_forward_traj", "lqt_solve", "lqt_backward"):
             getattr(L, f).restype = ctypes.c_int
+        L.lqt_batched_workspace_size.argtypes = [P(Ragged), ctypes.c_int32]
+        L.lqt_batched_workspace_size.restype = sz
+        L.lqt_solve_batched.argtypes = [P(Ragged), ctypes.c_int32, vp, sz, st]
+        L.lqt_solve_batched.restype = ctypes.c_int
+        L.lqt_plan_create.argtypes = [P(Ragged), ctypes.c_int32, vp, sz, ctypes.c_int32, st, P(vp)]
+        L.lqt_plan_create.restype = ctypes.c_int
+        L.lqt_plan_launch.argtypes = [vp, st]
+        L.lqt_plan_launch.restype = ctypes.c_int
+        L.lqt_plan_config.argtypes = [vp]
+        L.lqt_plan_config.restype = ctypes.c_char_p
+        L.lqt_plan_destroy.argtypes = [vp]
+        L.lqt_plan_destroy.restype = None
         L.lqt_status_string.argtypes = [ctypes.c_int]
         L.lqt_status_string.restype = ctypes.c_char_p
         L.lqt_last_error.restype = ctypes.c_char_p
@@ -298,3 +320,103 @@ class SolveTrajectory(torch.autograd.Function):
 
 def solve_trajectory(Q, R, r, x0, Qf, rf, template: DeviceProblem):
     return SolveTrajectory.apply(Q, R, r, x0, Qf, rf, template)
+
+
+# --------------------------------------------------------------------------------------------
+# Batched solve of problems with uneven horizons and sizes (lqt_ragged / lqt_plan).
+# --------------------------------------------------------------------------------------------
+def _class_key(p):
+    return (p.nx, p.nu, p.n, np.ndim(p.F) == 3, np.ndim(p.L) == 3, getattr(p, "c", None) is not None)
+
+
+class BatchedSolve:
+    """Problems of any horizons and sizes, grouped into classes of equal (nx, nu, n, sampling
+    flags), each class concatenated along time (layout of lqt_ragged).  `launch()` replays the
+    plan (tuned configuration, one stream per class); `solve_eager()` calls lqt_solve_batched.
+    Inputs can be refilled in place between launches (`classes[c]` holds the device arrays)."""
+
+    def __init__(self, problems: Sequence, dtype=torch.float64, device="cuda", autotune=True,
+                 plan=True, graph=False):
+        self.dtype, self.device = dtype, device
+        keys, groups = [], {}
+        for i, p in enumerate(problems):
+            k = _class_key(p)
+            if k not in groups:
+                groups[k] = []
+                keys.append(k)
+            groups[k].append(i)
+        to = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+        self.classes, self.where = [], {}
+        for ci, k in enumerate(keys):
+            members = [problems[i] for i in groups[k]]
+            nx, nu, n, F_s, L_s, has_c = k
+            Ts = np.array([p.T for p in members], dtype=np.int64)
+            start = np.concatenate([[0], np.cumsum(Ts + 1)]).astype(np.int64)
+            rows = int(start[-1])
+            cat = lambda name: to(np.concatenate([np.asarray(getattr(p, name)) for p in members]))
+            stack = lambda name: to(np.stack([np.asarray(getattr(p, name)) for p in members]))
+            c = {"members": groups[k], "nx": nx, "nu": nu, "n": n, "rows": rows,
+                 "F_sampled": F_s, "L_sampled": L_s,
+                 "start": torch.as_tensor(start, device=device), "start_host": start,
+                 "t": cat("t"), "r": cat("r"), "F": cat("F") if F_s else stack("F"),
+                 "L": cat("L") if L_s else stack("L"), "c": cat("c") if has_c else None,
+                 "Q": stack("Q"), "R": stack("R"), "Qf": stack("Qf"), "rf": stack("rf"),
+                 "x0": stack("x0"),
+                 "S": torch.empty(rows, nx, nx, dtype=dtype, device=device),
+                 "v": torch.empty(rows, nx, dtype=dtype, device=device),
+                 "x": torch.empty(rows, nx, dtype=dtype, device=device),
+                 "u": torch.empty(rows, nu, dtype=dtype, device=device)}
+            self.classes.append(c)
+            for j, i in enumerate(groups[k]):
+                self.where[i] = (ci, int(start[j]), int(Ts[j]))
+        self._structs = (Ragged * len(self.classes))()
+        for ci, c in enumerate(self.classes):
+            pr = Problem(*[None if c[k] is None else c[k].data_ptr()
+                           for k in ("t", "F", "L", "c", "Q", "R", "r", "Qf", "rf", "x0")])
+            self._structs[ci] = Ragged(c["nx"], c["nu"], c["n"],
+                                       LQT_F64 if dtype == torch.float64 else LQT_F32,
+                                       len(c["members"]), int(c["F_sampled"]), int(c["L_sampled"]),
+                                       int(c["c"] is not None), c["rows"], c["start"].data_ptr(), pr,
+                                       c["S"].data_ptr(), c["v"].data_ptr(), c["x"].data_ptr(),
+                                       c["u"].data_ptr())
+        nbytes = int(lib().lqt_batched_workspace_size(self._structs, len(self.classes)))
+        if nbytes == 0:
+            raise LQTError(LQT_EINVAL, "invalid classes for the batched solve")
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-ws.data_ptr()) % 256
+        self.ws = ws[off:off + nbytes]
+        self.plan = None
+        if plan:
+            h = ctypes.c_void_p()
+            _check(lib().lqt_plan_create(self._structs, len(self.classes), _ptr(self.ws),
+                                         self.ws.numel(),
+                                         (LQT_PLAN_AUTOTUNE if autotune else 0) | (LQT_PLAN_GRAPH if graph else 0),
+                                         _stream(), ctypes.byref(h)))
+            self.plan = h
+
+    def launch(self):
+        _check(lib().lqt_plan_launch(self.plan, _stream()))
+
+    def solve_eager(self):
+        _check(lib().lqt_solve_batched(self._structs, len(self.classes), _ptr(self.ws),
+                                       self.ws.numel(), _stream()))
+
+    def config(self) -> str:
+        return lib().lqt_plan_config(self.plan).decode() if self.plan else "eager"
+
+    def result(self, i: int) -> dict:
+        """S, v, x, u of problem i (views of the class outputs, T_i + 1 rows)."""
+        ci, r0, T = self.where[i]
+        c = self.classes[ci]
+        return {k: c[k][r0:r0 + T + 1] for k in ("S", "v", "x", "u")}
+
+    def close(self):
+        if self.plan is not None:
+            lib().lqt_plan_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -85,3 +85,40 @@ def test_workspace_too_small_rejected_before_launch():
     assert st == lqt.LQT_EWORKSPACE
     st = L.lqt_scan_value(ctypes.byref(d), fake, fake, fake, fake, fake, fake + 8, 1 << 40, None)
     assert st == lqt.LQT_EWORKSPACE  # misaligned workspace
+
+
+def _ragged(**kw):
+    base = dict(nx=4, nu=2, n_steps=4, dtype=lqt.LQT_F64, count=3, F_sampled=0, L_sampled=0,
+                has_c=0, rows=3 * 101)
+    base.update(kw)
+    r = lqt.Ragged()
+    for k, v in base.items():
+        setattr(r, k, v)
+    return r
+
+
+def test_batched_workspace_and_validation():
+    L = lqt.lib()
+    one = (lqt.Ragged * 1)(_ragged())
+    n = L.lqt_batched_workspace_size(one, 1)
+    assert n > 0 and n % 256 == 0
+    big = (lqt.Ragged * 1)(_ragged(rows=3 * 10001))
+    assert L.lqt_batched_workspace_size(big, 1) > n
+    two = (lqt.Ragged * 2)(_ragged(), _ragged(nx=8, nu=4))
+    assert L.lqt_batched_workspace_size(two, 2) > n
+    for bad in (dict(rows=5), dict(count=0), dict(nx=17), dict(nu=5), dict(dtype=7),
+                dict(rows=2 ** 31)):
+        b = (lqt.Ragged * 1)(_ragged(**bad))
+        assert L.lqt_batched_workspace_size(b, 1) == 0, bad
+        assert L.lqt_solve_batched(b, 1, None, 0, None) == lqt.LQT_EINVAL, bad
+    # Null arrays are rejected before anything is launched.
+    assert L.lqt_solve_batched(one, 1, None, 0, None) == lqt.LQT_EINVAL
+    assert b"is NULL" in L.lqt_last_error()
+    assert L.lqt_solve_batched(None, 0, None, 0, None) == lqt.LQT_EINVAL
+    h = ctypes.c_void_p()
+    assert L.lqt_plan_create(one, 1, None, 0, 1, None, ctypes.byref(h)) == lqt.LQT_EINVAL
+    assert not h.value
+    assert L.lqt_plan_create(one, 1, None, 0, 1, None, None) == lqt.LQT_EINVAL
+    assert L.lqt_plan_launch(None, None) == lqt.LQT_EINVAL
+    assert L.lqt_plan_config(None) == b""
+    L.lqt_plan_destroy(None)

@@ -1,0 +1,157 @@
+"""Batched solve of problems with uneven horizons and several sizes (lqt_ragged, lqt_plan).
+
+Every member is checked against the oracle's sequential solve (normwise 1e-9 in FP64, 1e-4 in
+FP32) and against lqt_solve on the member alone (1e-12 in FP64: the same kernels, only the scan
+trees group the blocks differently).  The tuned plan is replayed several times with eager work
+and in-place input updates in between, and every replay is checked.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from helpers import relerr
+from paper_2212_11744_amd import lqt
+from paper_2212_11744_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-9, torch.float32: 1e-4}
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lqt.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _mixed(seed=0):
+    """Members of five classes: point mass in 1 and 2 axes, random stable nx = 8 (constant F),
+    nx = 3 with sampled F(t) and a drift c(t), nx = 5 with sampled L(t)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    Ts = [1, 2, 5, 63, 64, 65, 257, 300, 3, 130]
+    for j, T in enumerate(Ts):
+        dt = 0.01
+        kind = j % 5
+        if kind == 0:
+            p = W.point_mass(10 + j, T, 4, 0.0, dt * T, d=1)
+        elif kind == 1:
+            p = W.point_mass(10 + j, T, 4, 0.0, dt * T, d=2)
+        elif kind == 2:
+            p = W.random_stable(10 + j, 8, 4, T, 3, 0.0, dt * T + 0.2, time_varying=False)
+        elif kind == 3:
+            p = W.random_stable(10 + j, 3, 2, T, 2, 0.0, dt * T + 0.1, time_varying=True)
+            p.c = 0.2 * np.cos(np.linspace(0, 2, p.r.shape[0]))[:, None] * rng.standard_normal(3)[None]
+        else:
+            p = W.random_stable(10 + j, 5, 2, T, 2, 0.0, dt * T + 0.1, time_varying=False)
+            ts = W.half_step_times(p.t, p.n)
+            p.L = p.L[None] * (1.0 + 0.3 * np.sin(ts))[:, None, None]
+        out.append(p)
+    return out
+
+
+def _check_member(res, ref, tol, label):
+    for k in ("S", "v", "x", "u"):
+        e = relerr(_np(res[k]), ref[k])
+        assert e < tol, f"{label} {k}: {e:.3e}"
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_mixed_classes_eager(dtype):
+    probs = _mixed()
+    bs = lqt.BatchedSolve(probs, dtype=dtype, plan=False)
+    assert len(bs.classes) == 5
+    bs.solve_eager()
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        res = bs.result(i)
+        _check_member(res, O.solve(p), TOL[dtype], f"member {i} (nx={p.nx}, T={p.T})")
+        if dtype == torch.float64:
+            single = lqt.solve(lqt.DeviceProblem.from_problems([p]))
+            for k in ("S", "v", "x", "u"):
+                assert relerr(_np(res[k]), _np(single[k][0])) < 1e-12, f"member {i} {k} vs single"
+
+
+def test_plan_replays_and_follows_inputs():
+    probs = _mixed(1)
+    bs = lqt.BatchedSolve(probs, autotune=True)
+    assert bs.config()
+    eager = lqt.BatchedSolve(probs, plan=False)
+    eager.solve_eager()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        bs.launch()
+        torch.cuda.synchronize()
+        for i in range(len(probs)):
+            a, b = bs.result(i), eager.result(i)
+            for k in ("S", "v", "x", "u"):
+                assert relerr(_np(a[k]), _np(b[k])) < 1e-12, f"replay {rep} member {i} {k}"
+        # eager work between replays
+        torch.cuda.synchronize()
+        _ = (eager.classes[0]["x"] * 2.0).sum().item()
+    # Refill inputs in place: new initial states, then one more replay against the oracle.
+    rng = np.random.default_rng(5)
+    for c in bs.classes:
+        new = rng.standard_normal(tuple(c["x0"].shape))
+        c["x0"].copy_(torch.as_tensor(new, dtype=c["x0"].dtype))
+        for j, i in enumerate(c["members"]):
+            probs[i].x0 = new[j]
+    bs.launch()
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        _check_member(bs.result(i), O.solve(p), 1e-9, f"refilled member {i}")
+
+
+@pytest.mark.skip(reason="graph capture of a plan is switched off: its first replay crashed the "
+                         "host inside hipGraphLaunch (segmentation fault) and the cause is not "
+                         "established; lqt_plan_create rejects LQT_PLAN_GRAPH until it is")
+def test_graph_plan_replays():
+    probs = _mixed(1)
+    bs = lqt.BatchedSolve(probs, autotune=True, graph=True)
+    for rep in range(3):
+        bs.launch()
+        torch.cuda.synchronize()
+        for i, p in enumerate(probs):
+            _check_member(bs.result(i), O.solve(p), 1e-9, f"replay {rep} member {i}")
+
+
+def test_graph_flag_is_rejected():
+    with pytest.raises(lqt.LQTError) as ei:
+        lqt.BatchedSolve(_mixed(2)[:3], autotune=False, graph=True)
+    assert ei.value.status == lqt.LQT_EUNSUPPORTED
+
+
+def test_single_member_class_and_one_block_problems():
+    probs = [W.point_mass(3, 1, 4, 0.0, 0.05), W.point_mass(4, 1, 4, 0.0, 0.05),
+             W.point_mass(5, 7, 4, 0.0, 0.2, d=1)]
+    bs = lqt.BatchedSolve(probs)
+    bs.launch()
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        _check_member(bs.result(i), O.solve(p), 1e-9, f"member {i}")
+
+
+def test_batched_mix_full_size():
+    """1024 problems, nx in {2, 4, 8}, T_i ~ U{256..8192} (the batched workload at full size):
+    every member against lqt_solve alone on sampled members, and the oracle on one per class."""
+    probs = W.batched_mix()
+    bs = lqt.BatchedSolve(probs, autotune=True)
+    bs.launch()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(0)
+    sample = sorted(set(rng.choice(len(probs), 24, replace=False).tolist()) | {0, 1, 2, 1021, 1022, 1023})
+    for i in sample:
+        p = probs[i]
+        single = lqt.solve(lqt.DeviceProblem.from_problems([p]))
+        res = bs.result(i)
+        for k in ("S", "v", "x", "u"):
+            assert relerr(_np(res[k]), _np(single[k][0])) < 1e-12, f"member {i} {k}"
+    for i in (0, 1, 2):
+        _check_member(bs.result(i), O.solve(probs[i]), 1e-9, f"member {i} vs oracle")
