@@ -103,6 +103,7 @@ def main(argv=None):
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "k_build_point_mass_T2p20_traffic.txt"))
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-nx16", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -178,6 +179,8 @@ def main(argv=None):
         rec["adjoint"] = adjoint_leg(torch, lqt, W, max(3, args.steps // 4))
     if not args.no_nx16:
         rec["nx16"] = nx16_leg(torch, lqt, W, max(3, args.steps // 4))
+    if not args.no_batched:
+        rec["batched"] = batched_leg(torch, lqt, W, max(3, args.steps // 4))
     if args.copy_probe:
         a = torch.empty(args.copy_probe * 2 ** 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
@@ -222,6 +225,31 @@ def nx16_leg(torch, lqt, W, reps):
     ms = _events_time(lambda: lqt.solve(dp, out, ws), reps, torch)
     return {"workload": f"random stable time-varying LQT nx=16 nu=4, T={T} x 4 RK4 steps, FP64",
             "ms": ms, "sub_intervals_per_s": T / (ms * 1e-3)}
+
+
+def batched_leg(torch, lqt, W, reps):
+    """1024 problems (nx in {2, 4, 8}, nu = nx / 2, T_i ~ U{256..8192}, FP64): one tuned plan
+    launch vs 1024 separate lqt_solve calls on one stream (all inputs and outputs resident)."""
+    probs = W.batched_mix()
+    bs = lqt.BatchedSolve(probs, autotune=True)
+    torch.cuda.synchronize()
+    ms_plan = _events_time(bs.launch, reps, torch)
+    singles = []
+    for p in probs:
+        dp = lqt.DeviceProblem.from_problems([p])
+        singles.append((dp, lqt.solve(dp), lqt.workspace(dp, lqt.CALL_SOLVE)))
+    torch.cuda.synchronize()
+
+    def separate():
+        for dp, out, ws in singles:
+            lqt.solve(dp, out, ws)
+
+    ms_sep = _events_time(separate, max(2, reps // 2), torch)
+    blocks = sum(p.T for p in probs)
+    return {"workload": f"{len(probs)} problems, nx in (2, 4, 8), nu = nx/2, T_i ~ U{{256..8192}} "
+                        f"(sum {blocks} blocks) x 4 RK4 steps, FP64",
+            "plan_ms": ms_plan, "separate_solves_ms": ms_sep, "speedup": ms_sep / ms_plan,
+            "sub_intervals_per_s": blocks / (ms_plan * 1e-3), "plan_config": bs.config()}
 
 
 def _traffic(path, T, dtype):

@@ -425,10 +425,6 @@ WDEV void w_aff_identity(R* P, R* q, int n) {
   wsync();
 }
 
-// LDS budget per workgroup (values of R): tuples and scratch for n = 16.
-constexpr int kTupW = 3 * NM * NM + 2 * NM;
-constexpr int kScr = 4 * NM * NM + NM * (2 * NM + 1) + 2 * NM;
-
 template <class R>
 WDEV WS<R> ws_at(R* base, int* piv, int n) {
   WS<R> s;
@@ -447,8 +443,7 @@ WDEV WS<R> ws_at(R* base, int* piv, int n) {
 // Separator element of ragged mode after problem i (see KProb): A - I = -I, b = x0 of problem
 // i + 1 (0 after the last), C = 0, eta = Qf_i rf_i, J = Qf_i.
 template <class R>
-WDEV void w_separator(const KProb& kp, int i, WT<R> y) {
-  const int n = kp.nx;
+WDEV void w_separator(const KProb& kp, int i, WT<R> y, int n) {
   const R* Qf = (const R*)kp.Qf + (long)i * n * n;
   const R* rf = (const R*)kp.rf + (long)i * n;
   const bool last = i + 1 >= kp.nseg;
@@ -467,10 +462,12 @@ WDEV void w_separator(const KProb& kp, int i, WT<R> y) {
   wsync();
 }
 
-template <class R>
+template <int N, class R>
 __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ elts) {
+  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
   __shared__ R sh[3 * kTupW + 8 * NM * NM + 4 * NM];
-  const int n = kp.nx, nu = kp.nu;
+  constexpr int n = N;
+  const int nu = kp.nu;
   const long T = kp.T;
   const int nn = kp.n;
   const long k = blockIdx.x;
@@ -481,7 +478,7 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
   if (kp.seg) {
     p = seg_find(kp.seg, kp.nseg, k);
     if (k == kp.seg[p + 1] - 1 || k == T - 1) {
-      w_separator(kp, p, y);
+      w_separator(kp, p, y, n);
       wt_store(y, elt_ref(elts, 0, k, T, ne_w(n)), n);
       return;
     }
@@ -613,10 +610,12 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
 // ------------------------------------------------------------------------------------------
 // Value tree.
 // ------------------------------------------------------------------------------------------
-template <class R>
-__global__ __launch_bounds__(64) void kw_vreduce(int n, int wc, int src_elts,
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_vreduce(int, int wc, int src_elts,
                                                  const R* __restrict__ src, long n_src,
                                                  R* __restrict__ dst, long n_dst) {
+  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
+  constexpr int n = N;
   __shared__ R sh[2 * kTupW + kScr];
   __shared__ int piv;
   const int p = blockIdx.y;
@@ -651,13 +650,14 @@ WDEV void val_ld(R* S, R* v, const R* g, int n) {
   wsync();
 }
 
-template <class R>
+template <int N, class R>
 __global__ __launch_bounds__(64) void kw_vtop(const KProb kp, const R* __restrict__ tup, long n_top,
                                               R* __restrict__ val) {
+  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
   __shared__ R sh[kTupW + kScr + NM * NM + NM];
   __shared__ int piv;
   const int p = blockIdx.y;
-  const int n = kp.nx;
+  constexpr int n = N;
   const int NE = ne_w(n);
   WT<R> a = wt_at(sh, n);
   WS<R> scr = ws_at(sh + kTupW, &piv, n);
@@ -684,10 +684,12 @@ __global__ __launch_bounds__(64) void kw_vtop(const KProb kp, const R* __restric
   }
 }
 
-template <class R>
-__global__ __launch_bounds__(64) void kw_vdown(int n, int wc, const R* __restrict__ tup, long n_child,
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_vdown(int, int wc, const R* __restrict__ tup, long n_child,
                                                const R* __restrict__ val_in, long n_par,
                                                R* __restrict__ val_out) {
+  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
+  constexpr int n = N;
   __shared__ R sh[kTupW + kScr + NM * NM + NM];
   __shared__ int piv;
   const int p = blockIdx.y;
@@ -710,17 +712,18 @@ __global__ __launch_bounds__(64) void kw_vdown(int n, int wc, const R* __restric
 
 // Values of every block from the value at the right end of each chunk; level 1 of the
 // trajectory tree (composition of the chunk's block maps) when maps1 != nullptr.
-template <class R>
+template <int N, class R>
 __global__ __launch_bounds__(64) void kw_vbottom(const KProb kp, int wc, const R* __restrict__ elts,
                                                  const R* __restrict__ val1, long n1,
                                                  R* __restrict__ Sout, R* __restrict__ vout,
                                                  R* __restrict__ maps1) {
+  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
   __shared__ R sh[kTupW + kScr + NM * NM + NM + 3 * (NM * NM + NM)];
   __shared__ int piv;
   const int p = blockIdx.y;
   const long i = blockIdx.x;
   if (i >= n1) return;
-  const int n = kp.nx;
+  constexpr int n = N;
   const long T = kp.T;
   const int NE = ne_w(n), VR = n * n + n, MR = n * n + n;
   WT<R> a = wt_at(sh, n);
@@ -774,25 +777,25 @@ WDEV void map_st(const R* P, const R* q, R* g, int n) {
 // (S_{k+1}, v_{k+1}) into LDS; zeros for the last block in ragged mode (a separator, whose map
 // does not depend on them; row T does not exist there).
 template <class R>
-WDEV void w_right_value(const KProb& kp, const R* Sp, const R* vp, long k, R* S, R* v) {
-  const int n = kp.nx;
+WDEV void w_right_value(const KProb& kp, const R* Sp, const R* vp, long k, R* S, R* v, int n) {
   const bool none = kp.seg && k + 1 >= kp.T;
   for (int e = lane_id(); e < n * n; e += 64) S[e] = none ? R(0) : Sp[(k + 1) * n * n + e];
   for (int q = lane_id(); q < n; q += 64) v[q] = none ? R(0) : vp[(k + 1) * n + q];
   wsync();
 }
 
-template <class R>
+template <int N, class R>
 __global__ __launch_bounds__(64) void kw_tbottom_reduce(const KProb kp, int wc, const R* __restrict__ elts,
                                                         const R* __restrict__ Sg,
                                                         const R* __restrict__ vg,
                                                         R* __restrict__ maps1, long n1) {
+  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
   __shared__ R sh[kTupW + kScr + NM * NM + NM + 3 * (NM * NM + NM)];
   __shared__ int piv;
   const int p = blockIdx.y;
   const long i = blockIdx.x;
   if (i >= n1) return;
-  const int n = kp.nx;
+  constexpr int n = N;
   const long T = kp.T;
   const int NE = ne_w(n), MR = n * n + n;
   WT<R> a = wt_at(sh, n);
@@ -810,16 +813,18 @@ __global__ __launch_bounds__(64) void kw_tbottom_reduce(const KProb kp, int wc, 
   w_aff_identity(aP, aq, n);
   for (long k = j0; k < j1; ++k) {
     wt_load(a, elt_ref(elts, p, k, T, NE), n);
-    w_right_value(kp, Sp, vp, k, S, v);
+    w_right_value(kp, Sp, vp, k, S, v, n);
     w_block_map(a, S, v, scr, n, mP, mq);
     w_aff_then(aP, aq, mP, mq, tmp, n);
   }
   map_st(aP, aq, maps1 + ((long)p * n1 + i) * MR, n);
 }
 
-template <class R>
-__global__ __launch_bounds__(64) void kw_treduce(int n, int wc, const R* __restrict__ src, long n_src,
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_treduce(int, int wc, const R* __restrict__ src, long n_src,
                                                  R* __restrict__ dst, long n_dst) {
+  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
+  constexpr int n = N;
   __shared__ R sh[3 * (NM * NM + NM)];
   const int p = blockIdx.y;
   const long i = blockIdx.x;
@@ -839,12 +844,13 @@ __global__ __launch_bounds__(64) void kw_treduce(int n, int wc, const R* __restr
   map_st(aP, aq, dst + ((long)p * n_dst + i) * MR, n);
 }
 
-template <class R>
+template <int N, class R>
 __global__ __launch_bounds__(64) void kw_ttop(const KProb kp, const R* __restrict__ maps, long n_top,
                                               R* __restrict__ xs) {
+  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
   __shared__ R sh[NM * NM + 3 * NM];
   const int p = blockIdx.y;
-  const int n = kp.nx;
+  constexpr int n = N;
   const int MR = n * n + n;
   R* mP = sh;
   R* mq = mP + NM * NM;
@@ -860,10 +866,12 @@ __global__ __launch_bounds__(64) void kw_ttop(const KProb kp, const R* __restric
   }
 }
 
-template <class R>
-__global__ __launch_bounds__(64) void kw_tdown(int n, int wc, const R* __restrict__ maps, long n_child,
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_tdown(int, int wc, const R* __restrict__ maps, long n_child,
                                                const R* __restrict__ x_in, long n_par,
                                                R* __restrict__ x_out) {
+  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
+  constexpr int n = N;
   __shared__ R sh[NM * NM + 3 * NM];
   const int p = blockIdx.y;
   const long i = blockIdx.x;
@@ -885,17 +893,19 @@ __global__ __launch_bounds__(64) void kw_tdown(int n, int wc, const R* __restric
 }
 
 // x_k and u_k = -R^{-1} L(t_k)^T (S_k x_k - v_k) of every block of a chunk.
-template <class R>
+template <int N, class R>
 __global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R* __restrict__ elts,
                                                  const R* __restrict__ Sg, const R* __restrict__ vg,
                                                  const R* __restrict__ x1, long n1,
                                                  R* __restrict__ xout, R* __restrict__ uout) {
+  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
   __shared__ R sh[kTupW + kScr + NM * NM + NM + NM * NM + 4 * NM + NM * NM];
   __shared__ int piv;
   const int p = blockIdx.y;
   const long i = blockIdx.x;
   if (i >= n1) return;
-  const int n = kp.nx, nu = kp.nu;
+  constexpr int n = N;
+  const int nu = kp.nu;
   const long T = kp.T;
   const int NE = ne_w(n);
   WT<R> a = wt_at(sh, n);
@@ -950,7 +960,7 @@ __global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R
     for (int q = lane_id(); q < n; q += 64) xp[k * n + q] = x[q];
     control(k);
     wt_load(a, elt_ref(elts, p, k, T, NE), n);
-    w_right_value(kp, Sp, vp, k, S, v);
+    w_right_value(kp, Sp, vp, k, S, v, n);
     w_block_map(a, S, v, scr, n, mP, mq);
     w_aff_apply(mP, mq, x, tmp, n);
   }
@@ -980,74 +990,115 @@ WTree wave_tree(long T, int wc) {
 
 namespace {
 
-template <class R>
+template <int N, class R>
 hipError_t wave_build_t(const KProb& kp, void* elts, hipStream_t s) {
-  hipLaunchKernelGGL(kw_build<R>, dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp, (R*)elts);
+  hipLaunchKernelGGL((kw_build<N, R>), dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
+                     (R*)elts);
   return hipGetLastError();
 }
 
-template <class R>
+template <int N, class R>
 hipError_t wave_value_t(const KProb& kp, const WTree& t, const Work& w, const void* elts, void* S,
                         void* v, void* maps1, hipStream_t s) {
-  const int n = kp.nx, wc = t.wc;
+  const int n = N, wc = t.wc;
   const dim3 b(64);
-  hipLaunchKernelGGL(kw_vreduce<R>, dim3((unsigned)t.n[1], kp.batch), b, 0, s, n, wc, 1,
+  hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, n, wc, 1,
                      (const R*)elts, t.n[0], (R*)w.vtup[1], t.n[1]);
   for (int l = 1; l < t.levels; ++l)
-    hipLaunchKernelGGL(kw_vreduce<R>, dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc, 0,
-                       (const R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1], t.n[l + 1]);
-  hipLaunchKernelGGL(kw_vtop<R>, dim3(1, kp.batch), b, 0, s, kp, (const R*)w.vtup[t.levels],
+    hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
+                       0, (const R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1], t.n[l + 1]);
+  hipLaunchKernelGGL((kw_vtop<N, R>), dim3(1, kp.batch), b, 0, s, kp, (const R*)w.vtup[t.levels],
                      t.n[t.levels], (R*)w.vval[t.levels]);
   for (int l = t.levels - 1; l >= 1; --l)
-    hipLaunchKernelGGL(kw_vdown<R>, dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
+    hipLaunchKernelGGL((kw_vdown<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
                        (const R*)w.vtup[l], t.n[l], (const R*)w.vval[l + 1], t.n[l + 1],
                        (R*)w.vval[l]);
-  hipLaunchKernelGGL(kw_vbottom<R>, dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
+  hipLaunchKernelGGL((kw_vbottom<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
                      (const R*)elts, (const R*)w.vval[1], t.n[1], (R*)S, (R*)v, (R*)maps1);
   return hipGetLastError();
 }
 
-template <class R>
+template <int N, class R>
 hipError_t wave_traj_t(const KProb& kp, const WTree& t, const Work& w, const void* elts,
                        const void* S, const void* v, void* x, void* u, bool maps_ready,
                        hipStream_t s) {
-  const int n = kp.nx, wc = t.wc;
+  const int n = N, wc = t.wc;
   const dim3 b(64);
   if (!maps_ready)
-    hipLaunchKernelGGL(kw_tbottom_reduce<R>, dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
-                       (const R*)elts, (const R*)S, (const R*)v, (R*)w.tmap[1], t.n[1]);
+    hipLaunchKernelGGL((kw_tbottom_reduce<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp,
+                       wc, (const R*)elts, (const R*)S, (const R*)v, (R*)w.tmap[1], t.n[1]);
   for (int l = 1; l < t.levels; ++l)
-    hipLaunchKernelGGL(kw_treduce<R>, dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
+    hipLaunchKernelGGL((kw_treduce<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
                        (const R*)w.tmap[l], t.n[l], (R*)w.tmap[l + 1], t.n[l + 1]);
-  hipLaunchKernelGGL(kw_ttop<R>, dim3(1, kp.batch), b, 0, s, kp, (const R*)w.tmap[t.levels],
+  hipLaunchKernelGGL((kw_ttop<N, R>), dim3(1, kp.batch), b, 0, s, kp, (const R*)w.tmap[t.levels],
                      t.n[t.levels], (R*)w.tx[t.levels]);
   for (int l = t.levels - 1; l >= 1; --l)
-    hipLaunchKernelGGL(kw_tdown<R>, dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
+    hipLaunchKernelGGL((kw_tdown<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
                        (const R*)w.tmap[l], t.n[l], (const R*)w.tx[l + 1], t.n[l + 1],
                        (R*)w.tx[l]);
-  hipLaunchKernelGGL(kw_tbottom<R>, dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
+  hipLaunchKernelGGL((kw_tbottom<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
                      (const R*)elts, (const R*)S, (const R*)v, (const R*)w.tx[1], t.n[1], (R*)x,
                      (R*)u);
   return hipGetLastError();
 }
 
+// Calls F<N, R>::run(args...) for the state size of the call (5 <= nx <= 16).
+template <template <int, class> class F, class R, class... A>
+hipError_t by_size(int nx, A&&... a) {
+  switch (nx) {
+    case 5: return F<5, R>::run(a...);
+    case 6: return F<6, R>::run(a...);
+    case 7: return F<7, R>::run(a...);
+    case 8: return F<8, R>::run(a...);
+    case 9: return F<9, R>::run(a...);
+    case 10: return F<10, R>::run(a...);
+    case 11: return F<11, R>::run(a...);
+    case 12: return F<12, R>::run(a...);
+    case 13: return F<13, R>::run(a...);
+    case 14: return F<14, R>::run(a...);
+    case 15: return F<15, R>::run(a...);
+    case 16: return F<16, R>::run(a...);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int N, class R>
+struct BuildF {
+  static hipError_t run(const KProb& kp, void* e, hipStream_t s) { return wave_build_t<N, R>(kp, e, s); }
+};
+template <int N, class R>
+struct ValueF {
+  static hipError_t run(const KProb& kp, const WTree& t, const Work& w, const void* e, void* S,
+                        void* v, void* m, hipStream_t s) {
+    return wave_value_t<N, R>(kp, t, w, e, S, v, m, s);
+  }
+};
+template <int N, class R>
+struct TrajF {
+  static hipError_t run(const KProb& kp, const WTree& t, const Work& w, const void* e,
+                        const void* S, const void* v, void* x, void* u, bool ready, hipStream_t s) {
+    return wave_traj_t<N, R>(kp, t, w, e, S, v, x, u, ready, s);
+  }
+};
+
 }  // namespace
 
 hipError_t wave_build(const KProb& kp, int dtype, void* elts, hipStream_t s) {
-  return dtype == 0 ? wave_build_t<double>(kp, elts, s) : wave_build_t<float>(kp, elts, s);
+  return dtype == 0 ? by_size<BuildF, double>(kp.nx, kp, elts, s)
+                    : by_size<BuildF, float>(kp.nx, kp, elts, s);
 }
 
 hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
                       void* S, void* v, void* maps1, hipStream_t s) {
-  return dtype == 0 ? wave_value_t<double>(kp, t, w, elts, S, v, maps1, s)
-                    : wave_value_t<float>(kp, t, w, elts, S, v, maps1, s);
+  return dtype == 0 ? by_size<ValueF, double>(kp.nx, kp, t, w, elts, S, v, maps1, s)
+                    : by_size<ValueF, float>(kp.nx, kp, t, w, elts, S, v, maps1, s);
 }
 
 hipError_t wave_traj(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
                      const void* S, const void* v, void* x, void* u, bool maps_ready,
                      hipStream_t s) {
-  return dtype == 0 ? wave_traj_t<double>(kp, t, w, elts, S, v, x, u, maps_ready, s)
-                    : wave_traj_t<float>(kp, t, w, elts, S, v, x, u, maps_ready, s);
+  return dtype == 0 ? by_size<TrajF, double>(kp.nx, kp, t, w, elts, S, v, x, u, maps_ready, s)
+                    : by_size<TrajF, float>(kp.nx, kp, t, w, elts, S, v, x, u, maps_ready, s);
 }
 
 }  // namespace lqt
