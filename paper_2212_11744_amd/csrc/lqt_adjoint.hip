@@ -583,10 +583,17 @@ __global__ __launch_bounds__(kT) void k_adj_elem(const KProb kp, R* __restrict__
 
 // ------------------------------------------------------------------------------------------
 // (E2) RK4 discrete adjoint of the element build, one block per lane.
-// ------------------------------------------------------------------------------------------
-// Right-hand side of Theorem 8 on the (Ad, eta, J) part of a stage value (b and C never enter it):
+//
+// Right-hand side of Theorem 8 on the (Ad, eta, J) part of a stage value (b and C never enter a
+// right-hand side, so their adjoints pass through the steps unchanged):
 //   K = G J - F, w = G eta, fAd = K + Ad K, fb = -(w + Ad w), fC = -(A G A^T) (upper),
 //   feta = K^T eta - Q r, fJ = -Q + J K - F^T J (upper), A = I + Ad.
+// F, G, Q are the same for every lane of a workgroup and are read from LDS.  Register use is
+// kept low: the step's start value and the running sum of stage adjoints live in per-lane LDS
+// slots, stage values are recomputed from the step's start value when their adjoint is formed,
+// and the Q and G adjoints are accumulated as their symmetric parts (packed), which is all the
+// symmetric gradients need.
+// ------------------------------------------------------------------------------------------
 template <int N, class R>
 struct Stage {
   R A[N][N];
@@ -594,257 +601,69 @@ struct Stage {
   R J[Sym<N>::size];
 };
 
-template <int N, class R>
-LQT_DEV void rhs_eval(const Stage<N, R>& y, const R (&F)[N][N], const R (&G)[N][N],
-                      const R (&Q)[N][N], const R (&r)[N], Tup<N, R>& f) {
-  using Y = Sym<N>;
-  R K[N][N];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      R s = -F[i][q];
-#pragma unroll
-      for (int l = 0; l < N; ++l) s = fma(G[i][l], y.J[Y::at(l, q)], s);
-      K[i][q] = s;
-    }
-  R w[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    R s = R(0);
-#pragma unroll
-    for (int l = 0; l < N; ++l) s = fma(G[i][l], y.e[l], s);
-    w[i] = s;
-  }
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      R s = K[i][q];
-#pragma unroll
-      for (int l = 0; l < N; ++l) s = fma(y.A[i][l], K[l][q], s);
-      f.A[i][q] = s;
-    }
-    R s = w[i];
-#pragma unroll
-    for (int l = 0; l < N; ++l) s = fma(y.A[i][l], w[l], s);
-    f.b[i] = -s;
-  }
-  R AG[N][N];  // A G
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      R s = G[i][q];
-#pragma unroll
-      for (int l = 0; l < N; ++l) s = fma(y.A[i][l], G[l][q], s);
-      AG[i][q] = s;
-    }
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int q = i; q < N; ++q) {
-      R s = AG[i][q];  // (A G) A^T = AG (I + Ad^T)
-#pragma unroll
-      for (int l = 0; l < N; ++l) s = fma(AG[i][l], y.A[q][l], s);
-      f.C[Y::at(i, q)] = -s;
-    }
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    R s = R(0);
-#pragma unroll
-    for (int l = 0; l < N; ++l) {
-      s = fma(K[l][i], y.e[l], s);
-      s = fma(-Q[i][l], r[l], s);
-    }
-    f.e[i] = s;
-  }
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int q = i; q < N; ++q) {
-      R s = -Q[i][q];
-#pragma unroll
-      for (int l = 0; l < N; ++l) {
-        s = fma(y.J[Y::at(i, l)], K[l][q], s);
-        s = fma(-F[l][i], y.J[Y::at(l, q)], s);
-      }
-      f.J[Y::at(i, q)] = s;
-    }
-}
+template <int N>
+struct StageLay {
+  static constexpr int A = 0, E = N * N, J = N * N + N, size = N * N + N + Sym<N>::size;
+};
 
-// Vector-Jacobian product of rhs_eval at stage value y for output adjoint g (packed C, J
-// adjoints): returns the adjoint of y's (Ad, eta, J) and accumulates the entrywise adjoints of
-// Q and G and the adjoint of this stage's reference sample.
+// Per-lane LDS slot: value v of lane l at base[v * kT + l].
 template <int N, class R>
-LQT_DEV void rhs_vjp(const Stage<N, R>& y, const Tup<N, R>& g, const R (&F)[N][N],
-                     const R (&G)[N][N], const R (&Q)[N][N], const R (&r)[N], Stage<N, R>& yb,
-                     R (&Qb)[N][N], R (&Gb)[N][N], R (&rb)[N]) {
-  using Y = Sym<N>;
-  R K[N][N];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      R s = -F[i][q];
-#pragma unroll
-      for (int l = 0; l < N; ++l) s = fma(G[i][l], y.J[Y::at(l, q)], s);
-      K[i][q] = s;
-    }
-  R w[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    R s = R(0);
-#pragma unroll
-    for (int l = 0; l < N; ++l) s = fma(G[i][l], y.e[l], s);
-    w[i] = s;
-  }
-  R Kb[N][N], Ab[N][N], Jb[N][N], eb[N], wb[N];
-  // fAd = (I + Ad) K: Kb = (I + Ad)^T gA, Adb += gA K^T
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      R s = g.A[i][q];
-#pragma unroll
-      for (int l = 0; l < N; ++l) s = fma(y.A[l][i], g.A[l][q], s);
-      Kb[i][q] = s;
-      R t = R(0);
-#pragma unroll
-      for (int l = 0; l < N; ++l) t = fma(g.A[i][l], K[q][l], t);
-      Ab[i][q] = t;
-    }
-  // fb = -(I + Ad) w: wb = -(I + Ad)^T gb, Adb -= gb w^T
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    R s = g.b[i];
-#pragma unroll
-    for (int l = 0; l < N; ++l) s = fma(y.A[l][i], g.b[l], s);
-    wb[i] = -s;
-#pragma unroll
-    for (int q = 0; q < N; ++q) Ab[i][q] = fma(-g.b[i], w[q], Ab[i][q]);
-  }
-  // fC (upper) = -(A G A^T)_ij: with Bc upper-triangular from g.C,
-  // Adb -= (Bc + Bc^T) A G, Gb -= A^T Bc A.
-  {
-    R Bs[N][N];  // Bc + Bc^T
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int q = 0; q < N; ++q)
-        Bs[i][q] = i == q ? R(2) * g.C[Y::at(i, i)] : g.C[Y::at(i, q)];
-    R AG[N][N];
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        R s = G[i][q];
-#pragma unroll
-        for (int l = 0; l < N; ++l) s = fma(y.A[i][l], G[l][q], s);
-        AG[i][q] = s;
-      }
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        R s = R(0);
-#pragma unroll
-        for (int l = 0; l < N; ++l) s = fma(Bs[i][l], AG[l][q], s);
-        Ab[i][q] -= s;
-      }
-    // A^T Bc A, Bc upper triangular (Bc_ij = g.C_ij for i <= j)
-    R BA[N][N];
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        R s = R(0);
-#pragma unroll
-        for (int l = i; l < N; ++l) s = fma(g.C[Y::at(i, l)], (l == q ? R(1) : R(0)) + y.A[l][q], s);
-        BA[i][q] = s;
-      }
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        R s = BA[i][q];
-#pragma unroll
-        for (int l = 0; l < N; ++l) s = fma(y.A[l][i], BA[l][q], s);
-        Gb[i][q] -= s;
-      }
-  }
-  // feta = K^T eta - Q r: Kb += eta ge^T, etab = K ge, Qb -= ge r^T, rb -= Q^T ge
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    R s = R(0);
-#pragma unroll
-    for (int l = 0; l < N; ++l) s = fma(K[i][l], g.e[l], s);
-    eb[i] = s;
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      Kb[i][q] = fma(y.e[i], g.e[q], Kb[i][q]);
-      Qb[i][q] = fma(-g.e[i], r[q], Qb[i][q]);
-    }
-    R t = R(0);
-#pragma unroll
-    for (int l = 0; l < N; ++l) t = fma(-Q[l][i], g.e[l], t);
-    rb[i] += t;
-  }
-  // fJ (upper) = -Q_ij + (J K)_ij - (F^T J)_ij with Bj upper from g.J:
-  // Qb -= Bj (upper entries), Jb += Bj K^T - F Bj, Kb += J Bj
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      if (i <= q) Qb[i][q] -= g.J[Y::at(i, q)];
-      R s = R(0), t = R(0), u = R(0);
-#pragma unroll
-      for (int l = 0; l < N; ++l) {
-        const R bil = l >= i ? g.J[Y::at(i, l)] : R(0);  // Bj[i][l]
-        const R blq = q >= l ? g.J[Y::at(l, q)] : R(0);  // Bj[l][q]
-        s = fma(bil, K[q][l], s);          // (Bj K^T)_iq
-        t = fma(F[i][l], blq, t);          // (F Bj)_iq
-        u = fma(y.J[Y::at(i, l)], blq, u); // (J Bj)_iq
-      }
-      Jb[i][q] = s - t;
-      Kb[i][q] += u;
-    }
-  // K = G J - F: Gb += Kb J, Jb += G Kb.  w = G eta: Gb += wb eta^T, etab += G wb.
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      R s = R(0), t = R(0);
-#pragma unroll
-      for (int l = 0; l < N; ++l) {
-        s = fma(Kb[i][l], y.J[Y::at(l, q)], s);
-        t = fma(G[i][l], Kb[l][q], t);
-      }
-      Gb[i][q] += s + wb[i] * y.e[q];
-      Jb[i][q] += t;
-    }
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    R s = R(0);
-#pragma unroll
-    for (int l = 0; l < N; ++l) s = fma(G[i][l], wb[l], s);
-    eb[i] += s;
-  }
-  // Outputs: the stage adjoint (J folded onto its packed entries).
+LQT_DEV void stage_to_lds(const Stage<N, R>& y, R* base, int lane) {
+  using L = StageLay<N>;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
 #pragma unroll
-    for (int q = 0; q < N; ++q) yb.A[i][q] = Ab[i][q];
-    yb.e[i] = eb[i];
+    for (int q = 0; q < N; ++q) base[(L::A + i * N + q) * kT + lane] = y.A[i][q];
+    base[(L::E + i) * kT + lane] = y.e[i];
   }
 #pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int q = i; q < N; ++q) yb.J[Y::at(i, q)] = i == q ? Jb[i][i] : Jb[i][q] + Jb[q][i];
+  for (int i = 0; i < Sym<N>::size; ++i) base[(L::J + i) * kT + lane] = y.J[i];
 }
 
 template <int N, class R>
-LQT_DEV void stage_axpy(const Stage<N, R>& y, R c, const Tup<N, R>& k, Stage<N, R>& o) {
+LQT_DEV void stage_from_lds(Stage<N, R>& y, const R* base, int lane) {
+  using L = StageLay<N>;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) y.A[i][q] = base[(L::A + i * N + q) * kT + lane];
+    y.e[i] = base[(L::E + i) * kT + lane];
+  }
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) y.J[i] = base[(L::J + i) * kT + lane];
+}
+
+template <int N, class R>
+LQT_DEV void stage_add_lds(const Stage<N, R>& y, R* base, int lane) {
+  using L = StageLay<N>;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) base[(L::A + i * N + q) * kT + lane] += y.A[i][q];
+    base[(L::E + i) * kT + lane] += y.e[i];
+  }
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) base[(L::J + i) * kT + lane] += y.J[i];
+}
+
+// Compiler-only memory barrier (no instruction): values written to LDS are read back from LDS.
+LQT_DEV void lds_fence() { asm volatile("" ::: "memory"); }
+
+template <int N, class R>
+LQT_DEV void stage_zero(Stage<N, R>& y) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) y.A[i][q] = R(0);
+    y.e[i] = R(0);
+  }
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) y.J[i] = R(0);
+}
+
+// o = y + c k (A, eta, J parts)
+template <int N, class R>
+LQT_DEV void stage_axpy(const Stage<N, R>& y, R c, const Stage<N, R>& k, Stage<N, R>& o) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
 #pragma unroll
@@ -855,75 +674,280 @@ LQT_DEV void stage_axpy(const Stage<N, R>& y, R c, const Tup<N, R>& k, Stage<N, 
   for (int i = 0; i < Sym<N>::size; ++i) o.J[i] = fma(c, k.J[i], y.J[i]);
 }
 
+// The (Ad, eta, J) part of the right-hand side.  F, G, Q: row-major N x N in LDS.
+template <int N, class R>
+LQT_DEV void rhs_aej(const Stage<N, R>& y, const R* F, const R* G,
+                     const R* Q, const R (&r)[N],
+                     Stage<N, R>& f) {
+  using Y = Sym<N>;
+  R K[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = -F[i * N + q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(G[i * N + l], y.J[Y::at(l, q)], s);
+      K[i][q] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = K[i][q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(y.A[i][l], K[l][q], s);
+      f.A[i][q] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = R(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      s = fma(K[l][i], y.e[l], s);
+      s = fma(-Q[i * N + l], r[l], s);
+    }
+    f.e[i] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = i; q < N; ++q) {
+      R s = -Q[i * N + q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        s = fma(y.J[Y::at(i, l)], K[l][q], s);
+        s = fma(-F[l * N + i], y.J[Y::at(l, q)], s);
+      }
+      f.J[Y::at(i, q)] = s;
+    }
+}
+
+// Vector-Jacobian product of the right-hand side at stage value y.  The output adjoint has
+// (Ad, eta, J) parts g and b, C parts c1 * yb_b, c1 * yb_C (packed upper C, J adjoints).
+// Returns the adjoint of y's (Ad, eta, J) in `out`, accumulates the symmetric parts of the Q and
+// G adjoints (packed, per-lane LDS slots Qs, Gs) and the adjoint of this stage's reference
+// sample into rb.  The phases are ordered so that each temporary dies early (register pressure).
+template <int N, class R>
+LQT_DEV void rhs_vjp(const Stage<N, R>& y, const Stage<N, R>& g, R c1, const R (&yb_b)[N],
+                     const R (&yb_C)[Sym<N>::size], const R* F, const R* G, const R* Q,
+                     const R (&r)[N], Stage<N, R>& out, R* Qs, R* Gs, int lane, R (&rb)[N]) {
+  using Y = Sym<N>;
+  // Bs = Bc + Bc^T from the C adjoint (upper triangular Bc); Bj upper triangular from g.J.
+  auto Bs = [&](int i, int l) -> R {
+    return i == l ? R(2) * c1 * yb_C[Y::at(i, i)] : c1 * yb_C[Y::at(i, l)];
+  };
+  auto Bj = [&](int i, int l) -> R { return l >= i ? g.J[Y::at(i, l)] : R(0); };
+  // K = G J - F
+  R K[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = -F[i * N + q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(G[i * N + l], y.J[Y::at(l, q)], s);
+      K[i][q] = s;
+    }
+  lds_fence();
+  // Kb = (I + Ad)^T gA + eta ge^T + J Bj
+  R Kb[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = fma(y.e[i], g.e[q], g.A[i][q]);
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        s = fma(y.A[l][i], g.A[l][q], s);
+        s = fma(y.J[Y::at(i, l)], Bj(l, q), s);
+      }
+      Kb[i][q] = s;
+    }
+  // out.J: Jb = Bj K^T - F Bj + G Kb folded onto the packed entries as it is formed.
+#pragma unroll
+  for (int i = 0; i < Y::size; ++i) out.J[i] = R(0);
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = R(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        s = fma(Bj(i, l), K[q][l], s);
+        s = fma(-F[i * N + l], Bj(l, q), s);
+        s = fma(G[i * N + l], Kb[l][q], s);
+      }
+      out.J[Y::at(i, q)] += s;
+    }
+  // Qs: symmetric parts of -ge r^T and of -Bj (upper entries).
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = i; q < N; ++q) {
+      const R outer = R(0.5) * (g.e[i] * r[q] + g.e[q] * r[i]);
+      Qs[Y::at(i, q) * kT + lane] -= outer + (i == q ? Bj(i, i) : R(0.5) * Bj(i, q));
+    }
+  lds_fence();
+  // wb = -(I + Ad)^T gb,  w = G eta
+  R wb[N], w[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = yb_b[i], t = R(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      s = fma(y.A[l][i], yb_b[l], s);
+      t = fma(G[i * N + l], y.e[l], t);
+    }
+    wb[i] = -c1 * s;
+    w[i] = t;
+  }
+  // Gs: symmetric parts of Kb J and wb eta^T.
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = i; q < N; ++q) {
+      R s = R(0), t = R(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        s = fma(Kb[i][l], y.J[Y::at(l, q)], s);
+        t = fma(Kb[q][l], y.J[Y::at(l, i)], t);
+      }
+      Gs[Y::at(i, q) * kT + lane] += R(0.5) * (s + t + wb[i] * y.e[q] + wb[q] * y.e[i]);
+    }
+  lds_fence();
+  // out.eta = K ge + G wb;  rb -= Q ge
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = R(0), t = R(0);
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      s = fma(K[i][l], g.e[l], s);
+      s = fma(G[i * N + l], wb[l], s);
+      t = fma(Q[i * N + l], g.e[l], t);
+    }
+    out.e[i] = s;
+    rb[i] -= t;
+  }
+  lds_fence();
+  // out.A = gA K^T - gb w^T - Bs A G, with A G = G + Ad G.
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    R AGq[N];  // column q of A G
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      R s = G[l * N + q];
+#pragma unroll
+      for (int m = 0; m < N; ++m) s = fma(y.A[l][m], G[m * N + q], s);
+      AGq[l] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      R s = -c1 * yb_b[i] * w[q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        s = fma(g.A[i][l], K[q][l], s);
+        s = fma(-Bs(i, l), AGq[l], s);
+      }
+      out.A[i][q] = s;
+    }
+  }
+  // Gs -= 1/2 A^T Bs A (already symmetric), column by column of Bs A.
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    R BsAq[N];
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      R s = Bs(l, q);
+#pragma unroll
+      for (int m = 0; m < N; ++m) s = fma(Bs(l, m), y.A[m][q], s);
+      BsAq[l] = s;
+    }
+#pragma unroll
+    for (int i = 0; i <= q; ++i) {
+      R s = BsAq[i];
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(y.A[l][i], BsAq[l], s);
+      Gs[Y::at(i, q) * kT + lane] = fma(R(-0.5), s, Gs[Y::at(i, q) * kT + lane]);
+    }
+  }
+}
+
 template <int N, class R>
 LQT_DEV void sample_r(const R* rp, long j, R (&r)[N]) {
 #pragma unroll
   for (int q = 0; q < N; ++q) r[q] = rp[j * N + q];
 }
 
-// One classical RK4 step of -h from s = t_{k+1} - m h on the (Ad, eta, J) part.
+// One classical RK4 step of -h (hp = -h) from the sample j1 (stage 1) to j1 - 2 (stage 4).
 template <int N, class R>
-LQT_DEV void rk4_forward(Stage<N, R>& y, long j1, R hp, const R* rp, const R (&F)[N][N],
-                         const R (&G)[N][N], const R (&Q)[N][N]) {
+LQT_DEV void rk4_forward(Stage<N, R>& y, long j1, R hp, const R* rp, const R* F,
+                         const R* G, const R* Q) {
   R r[N];
-  Tup<N, R> k1, k2, k3, k4;
-  Stage<N, R> s;
-  sample_r<N, R>(rp, j1, r);
-  rhs_eval(y, F, G, Q, r, k1);
-  stage_axpy(y, R(0.5) * hp, k1, s);
-  sample_r<N, R>(rp, j1 - 1, r);
-  rhs_eval(s, F, G, Q, r, k2);
-  stage_axpy(y, R(0.5) * hp, k2, s);
-  rhs_eval(s, F, G, Q, r, k3);
-  stage_axpy(y, hp, k3, s);
-  sample_r<N, R>(rp, j1 - 2, r);
-  rhs_eval(s, F, G, Q, r, k4);
+  Stage<N, R> acc, s, k;
   const R w6 = hp / R(6), w3 = hp / R(3);
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-#pragma unroll
-    for (int q = 0; q < N; ++q)
-      y.A[i][q] += w6 * (k1.A[i][q] + k4.A[i][q]) + w3 * (k2.A[i][q] + k3.A[i][q]);
-    y.e[i] += w6 * (k1.e[i] + k4.e[i]) + w3 * (k2.e[i] + k3.e[i]);
-  }
-#pragma unroll
-  for (int i = 0; i < Sym<N>::size; ++i)
-    y.J[i] += w6 * (k1.J[i] + k4.J[i]) + w3 * (k2.J[i] + k3.J[i]);
+  sample_r<N, R>(rp, j1, r);
+  rhs_aej(y, F, G, Q, r, k);
+  stage_axpy(y, w6, k, acc);
+  stage_axpy(y, R(0.5) * hp, k, s);
+  sample_r<N, R>(rp, j1 - 1, r);
+  lds_fence();
+  rhs_aej(s, F, G, Q, r, k);
+  stage_axpy(acc, w3, k, acc);
+  stage_axpy(y, R(0.5) * hp, k, s);
+  lds_fence();
+  rhs_aej(s, F, G, Q, r, k);
+  stage_axpy(acc, w3, k, acc);
+  stage_axpy(y, hp, k, s);
+  sample_r<N, R>(rp, j1 - 2, r);
+  lds_fence();
+  rhs_aej(s, F, G, Q, r, k);
+  stage_axpy(acc, w6, k, y);
 }
 
+// Stage value `stage` (2, 3 or 4) of the RK4 step starting at y (samples j1, j1 - 1).
 template <int N, class R>
-LQT_DEV void tup_scale(const Tup<N, R>& x, R c, Tup<N, R>& o) {
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) o.A[i][q] = c * x.A[i][q];
-    o.b[i] = c * x.b[i];
-    o.e[i] = c * x.e[i];
-  }
-#pragma unroll
-  for (int i = 0; i < Sym<N>::size; ++i) {
-    o.C[i] = c * x.C[i];
-    o.J[i] = c * x.J[i];
-  }
+LQT_DEV void stage_value(const Stage<N, R>& y, int stage, long j1, R hp, const R* rp,
+                         const R* F, const R* G, const R* Q,
+                         Stage<N, R>& s) {
+  R r[N];
+  Stage<N, R> k;
+  sample_r<N, R>(rp, j1, r);
+  rhs_aej(y, F, G, Q, r, k);
+  stage_axpy(y, R(0.5) * hp, k, s);
+  if (stage == 2) return;
+  sample_r<N, R>(rp, j1 - 1, r);
+  lds_fence();
+  rhs_aej(s, F, G, Q, r, k);
+  stage_axpy(y, R(0.5) * hp, k, s);
+  if (stage == 3) return;
+  lds_fence();
+  rhs_aej(s, F, G, Q, r, k);
+  stage_axpy(y, hp, k, s);
 }
 
-// kb (A, eta, J parts) += c * sb
+// g = c1 * yb + c2 * sn on the (Ad, eta, J) parts.
 template <int N, class R>
-LQT_DEV void tup_add_stage(Tup<N, R>& kb, R c, const Stage<N, R>& sb) {
+LQT_DEV void stage_seed(R c1, const Tup<N, R>& yb, R c2, const Stage<N, R>& sn, Stage<N, R>& g) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
 #pragma unroll
-    for (int q = 0; q < N; ++q) kb.A[i][q] = fma(c, sb.A[i][q], kb.A[i][q]);
-    kb.e[i] = fma(c, sb.e[i], kb.e[i]);
+    for (int q = 0; q < N; ++q) g.A[i][q] = fma(c2, sn.A[i][q], c1 * yb.A[i][q]);
+    g.e[i] = fma(c2, sn.e[i], c1 * yb.e[i]);
   }
 #pragma unroll
-  for (int i = 0; i < Sym<N>::size; ++i) kb.J[i] = fma(c, sb.J[i], kb.J[i]);
+  for (int i = 0; i < Sym<N>::size; ++i) g.J[i] = fma(c2, sn.J[i], c1 * yb.J[i]);
 }
 
 template <int N, int NU, class R>
 __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restrict__ abar,
                                                R* __restrict__ dr, R* __restrict__ bnd,
                                                R* __restrict__ wsum) {
+  using Y = Sym<N>;
+  constexpr int NS = Y::size, SL = StageLay<N>::size;
+  __shared__ R sF[N * N], sG[N * N], sQ[N * N];
+  // per-lane slots: step start value, running sum of stage adjoints, symmetric Q and G adjoints
+  __shared__ R yL[SL * kT], aL[SL * kT], qL[NS * kT], gL[NS * kT];
   const int p = blockIdx.y;
   const long k = gidx();
   const long T = kp.T;
@@ -932,26 +956,28 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
   const long nsamp = 2L * n * T + 1;
   const R* rp = (const R*)kp.r + (long)p * nsamp * N;
   const R* cs = (const R*)kp.consts + (long)p * CS<N, NU>::size;
-  R F[N][N], G[N][N], Q[N][N];
+  if (lane < N * N) {
+    sF[lane] = ((const R*)kp.F)[lane];
+    sG[lane] = cs[CS<N, NU>::G + lane];
+    sQ[lane] = ((const R*)kp.Q)[(long)p * N * N + lane];
+  }
 #pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      F[i][q] = ((const R*)kp.F)[i * N + q];
-      G[i][q] = cs[CS<N, NU>::G + i * N + q];
-      Q[i][q] = ((const R*)kp.Q)[(long)p * N * N + i * N + q];
-    }
-  R Qb[N][N], Gb[N][N];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int q = 0; q < N; ++q) {
-      Qb[i][q] = R(0);
-      Gb[i][q] = R(0);
-    }
+  for (int i = 0; i < NS; ++i) {
+    qL[i * kT + lane] = R(0);
+    gL[i * kT + lane] = R(0);
+  }
+  __syncthreads();
+  const R* vF = sF;
+  const R* vG = sG;
+  const R* vQ = sQ;
+  R* vq = qL;
+  R* vg = gL;
+  // Compiler memory barriers below keep the per-lane LDS slots in LDS: without them the values
+  // stored there would be forwarded in registers and raise register pressure.
   if (k < T) {
     const R* tg = (const R*)kp.t + (long)p * (T + 1);
     const R hp = -(tg[k + 1] - tg[k]) / R(n);
+    const R w6 = hp / R(6), w3 = hp / R(3);
     Tup<N, R> yb;
     tup_load(yb, abar + (long)p * Lay<N>::NE * padt(T), k);
     R* drp = dr + (long)p * nsamp * N;
@@ -960,117 +986,131 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
     R carry[N];
 #pragma unroll
     for (int q = 0; q < N; ++q) carry[q] = R(0);
+#pragma unroll 1
     for (int m = n - 1; m >= 0; --m) {
       const long j1 = 2L * n * k + 2L * (n - m);
-      // recompute the step's start value from the block's boundary values
-      Stage<N, R> y;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-#pragma unroll
-        for (int q = 0; q < N; ++q) y.A[i][q] = R(0);
-        y.e[i] = R(0);
+      {
+        Stage<N, R> y;
+        stage_zero(y);
+#pragma unroll 1
+        for (int mm = 0; mm < m; ++mm)
+          rk4_forward(y, 2L * n * k + 2L * (n - mm), hp, rp, vF, vG, vQ);
+        stage_to_lds(y, yL, lane);
+        Stage<N, R> z;
+        stage_zero(z);
+        stage_to_lds(z, aL, lane);
       }
-#pragma unroll
-      for (int i = 0; i < Sym<N>::size; ++i) y.J[i] = R(0);
-      for (int mm = 0; mm < m; ++mm) rk4_forward(y, 2L * n * k + 2L * (n - mm), hp, rp, F, G, Q);
-      // stage values
-      R r1[N], r2[N], r4[N];
-      sample_r<N, R>(rp, j1, r1);
-      sample_r<N, R>(rp, j1 - 1, r2);
-      sample_r<N, R>(rp, j1 - 2, r4);
-      Tup<N, R> kk;
-      Stage<N, R> s2, s3, s4;
-      rhs_eval(y, F, G, Q, r1, kk);
-      stage_axpy(y, R(0.5) * hp, kk, s2);
-      rhs_eval(s2, F, G, Q, r2, kk);
-      stage_axpy(y, R(0.5) * hp, kk, s3);
-      rhs_eval(s3, F, G, Q, r2, kk);
-      stage_axpy(y, hp, kk, s4);
-      // reverse sweep
-      Tup<N, R> kb;
-      Stage<N, R> sb;
-      R rb1[N], rb2[N], rb4[N];
-#pragma unroll
-      for (int q = 0; q < N; ++q) rb1[q] = rb2[q] = rb4[q] = R(0);
-      Stage<N, R> acc;  // sum of stage-input adjoints
-      tup_scale(yb, hp / R(6), kb);  // k4bar
-      rhs_vjp(s4, kb, F, G, Q, r4, sb, Qb, Gb, rb4);
-      acc = sb;
-      tup_scale(yb, hp / R(3), kb);  // k3bar
-      tup_add_stage(kb, hp, sb);
-      rhs_vjp(s3, kb, F, G, Q, r2, sb, Qb, Gb, rb2);
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-#pragma unroll
-        for (int q = 0; q < N; ++q) acc.A[i][q] += sb.A[i][q];
-        acc.e[i] += sb.e[i];
-      }
-#pragma unroll
-      for (int i = 0; i < Sym<N>::size; ++i) acc.J[i] += sb.J[i];
-      tup_scale(yb, hp / R(3), kb);  // k2bar
-      tup_add_stage(kb, R(0.5) * hp, sb);
-      rhs_vjp(s2, kb, F, G, Q, r2, sb, Qb, Gb, rb2);
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-#pragma unroll
-        for (int q = 0; q < N; ++q) acc.A[i][q] += sb.A[i][q];
-        acc.e[i] += sb.e[i];
-      }
-#pragma unroll
-      for (int i = 0; i < Sym<N>::size; ++i) acc.J[i] += sb.J[i];
-      tup_scale(yb, hp / R(6), kb);  // k1bar
-      tup_add_stage(kb, R(0.5) * hp, sb);
-      rhs_vjp(y, kb, F, G, Q, r1, sb, Qb, Gb, rb1);
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-#pragma unroll
-        for (int q = 0; q < N; ++q) yb.A[i][q] += acc.A[i][q] + sb.A[i][q];
-        yb.e[i] += acc.e[i] + sb.e[i];
-      }
-#pragma unroll
-      for (int i = 0; i < Sym<N>::size; ++i) yb.J[i] += acc.J[i] + sb.J[i];
-      // reference-sample adjoints: j1 (stage 1), j1 - 1 (stages 2, 3), j1 - 2 (stage 4); the
+      lds_fence();
+      // Reference-sample adjoints: j1 (stage 1), j1 - 1 (stages 2, 3), j1 - 2 (stage 4).  The
       // block's first sample (step n - 1, stage 4) and last sample (step 0, stage 1) are shared
-      // with the neighbouring blocks and summed by k_adj_bnd.
+      // with the neighbouring blocks and summed by k_adj_bnd; sample j1 of step m is sample
+      // j1 - 2 of step m + 1, so the stage-1 adjoint is carried to the next (earlier) step.
+      Stage<N, R> sn;  // adjoint of the later stage's input
+      // stage 4: kbar4 = w6 ybar
+      {
+        Stage<N, R> y, s, g;
+        R r[N], rbs[N];
+        stage_from_lds(y, yL, lane);
+        stage_value(y, 4, j1, hp, rp, vF, vG, vQ, s);
+        stage_zero(sn);
+        stage_seed(w6, yb, R(0), sn, g);
+        sample_r<N, R>(rp, j1 - 2, r);
 #pragma unroll
-      for (int q = 0; q < N; ++q) drp[(j1 - 1) * N + q] = rb2[q];
-      if (m == n - 1) {
+        for (int q = 0; q < N; ++q) rbs[q] = R(0);
+        rhs_vjp(s, g, w6, yb.b, yb.C, vF, vG, vQ, r, sn, vq, vg, lane, rbs);
+        stage_add_lds(sn, aL, lane);
+        if (m == n - 1) {
 #pragma unroll
-        for (int q = 0; q < N; ++q) bnd[((long)p * T + k) * 2 * N + q] = rb4[q];
-      } else {
+          for (int q = 0; q < N; ++q) bnd[((long)p * T + k) * 2 * N + q] = rbs[q];
+        } else {
 #pragma unroll
-        for (int q = 0; q < N; ++q) drp[(j1 - 2) * N + q] = rb4[q] + carry[q];
+          for (int q = 0; q < N; ++q) drp[(j1 - 2) * N + q] = rbs[q] + carry[q];
+        }
       }
+      lds_fence();
+      // stage 3: kbar3 = w3 ybar + h s4bar
+      {
+        Stage<N, R> y, s, g;
+        R r[N], rbs[N];
+        stage_from_lds(y, yL, lane);
+        stage_value(y, 3, j1, hp, rp, vF, vG, vQ, s);
+        stage_seed(w3, yb, hp, sn, g);
+        sample_r<N, R>(rp, j1 - 1, r);
 #pragma unroll
-      for (int q = 0; q < N; ++q) carry[q] = rb1[q];
+        for (int q = 0; q < N; ++q) rbs[q] = R(0);
+        rhs_vjp(s, g, w3, yb.b, yb.C, vF, vG, vQ, r, sn, vq, vg, lane, rbs);
+        stage_add_lds(sn, aL, lane);
+#pragma unroll
+        for (int q = 0; q < N; ++q) drp[(j1 - 1) * N + q] = rbs[q];
+      }
+      lds_fence();
+      // stage 2: kbar2 = w3 ybar + h/2 s3bar
+      {
+        Stage<N, R> y, s, g;
+        R r[N], rbs[N];
+        stage_from_lds(y, yL, lane);
+        stage_value(y, 2, j1, hp, rp, vF, vG, vQ, s);
+        stage_seed(w3, yb, R(0.5) * hp, sn, g);
+        sample_r<N, R>(rp, j1 - 1, r);
+#pragma unroll
+        for (int q = 0; q < N; ++q) rbs[q] = drp[(j1 - 1) * N + q];
+        rhs_vjp(s, g, w3, yb.b, yb.C, vF, vG, vQ, r, sn, vq, vg, lane, rbs);
+        stage_add_lds(sn, aL, lane);
+#pragma unroll
+        for (int q = 0; q < N; ++q) drp[(j1 - 1) * N + q] = rbs[q];
+      }
+      lds_fence();
+      // stage 1: kbar1 = w6 ybar + h/2 s2bar, at the step's start value
+      {
+        Stage<N, R> y, g;
+        R r[N];
+        stage_from_lds(y, yL, lane);
+        stage_seed(w6, yb, R(0.5) * hp, sn, g);
+        sample_r<N, R>(rp, j1, r);
+#pragma unroll
+        for (int q = 0; q < N; ++q) carry[q] = R(0);
+        rhs_vjp(y, g, w6, yb.b, yb.C, vF, vG, vQ, r, sn, vq, vg, lane, carry);
+        stage_add_lds(sn, aL, lane);
+      }
+      lds_fence();
+      // ybar of the step's start value: ybar + sum of the stage-input adjoints
+      {
+        Stage<N, R> a;
+        stage_from_lds(a, aL, lane);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+#pragma unroll
+          for (int q = 0; q < N; ++q) yb.A[i][q] += a.A[i][q];
+          yb.e[i] += a.e[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i) yb.J[i] += a.J[i];
+      }
     }
 #pragma unroll
     for (int q = 0; q < N; ++q) bnd[((long)p * T + k) * 2 * N + N + q] = carry[q];
   }
-  // Wave sums of the Q and G adjoints (deterministic, one record per wave).
+  // Wave sums of the symmetric Q and G adjoints (deterministic, one record per wave).
+  R Qs[NS], Gs[NS];
 #pragma unroll
-  for (int i = 0; i < N; ++i)
+  for (int i = 0; i < NS; ++i) {
+    R a = qL[i * kT + lane], b = gL[i * kT + lane];
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-      R a = Qb[i][q], b = Gb[i][q];
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off, 64);
-        b += __shfl_xor(b, off, 64);
-      }
-      Qb[i][q] = a;
-      Gb[i][q] = b;
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_xor(a, off, 64);
+      b += __shfl_xor(b, off, 64);
     }
+    Qs[i] = a;
+    Gs[i] = b;
+  }
   if (lane == 0) {
     const long nw = (T + kT - 1) / kT;
-    R* ws = wsum + ((long)p * nw + blockIdx.x) * 2 * N * N;
+    R* ws = wsum + ((long)p * nw + blockIdx.x) * 2 * NS;
 #pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int q = 0; q < N; ++q) {
-        ws[i * N + q] = Qb[i][q];
-        ws[N * N + i * N + q] = Gb[i][q];
-      }
+    for (int i = 0; i < NS; ++i) {
+      ws[i] = Qs[i];
+      ws[NS + i] = Gs[i];
+    }
   }
 }
 
@@ -1099,19 +1139,21 @@ __global__ __launch_bounds__(kT) void k_adj_bnd(const KProb kp, const R* __restr
 template <int N, int NU, class R>
 __global__ __launch_bounds__(kT) void k_adj_sum(const KProb kp, const R* __restrict__ wsum,
                                                R* __restrict__ dQ, R* __restrict__ dR) {
+  using Y = Sym<N>;
+  constexpr int NS = Y::size;
   const int p = blockIdx.y;
   const int lane = threadIdx.x;
   const long nw = (kp.T + kT - 1) / kT;
-  R acc[2 * N * N];
+  R acc[2 * NS];
 #pragma unroll
-  for (int i = 0; i < 2 * N * N; ++i) acc[i] = R(0);
+  for (int i = 0; i < 2 * NS; ++i) acc[i] = R(0);
   for (long w = lane; w < nw; w += kT) {
-    const R* ws = wsum + ((long)p * nw + w) * 2 * N * N;
+    const R* ws = wsum + ((long)p * nw + w) * 2 * NS;
 #pragma unroll
-    for (int i = 0; i < 2 * N * N; ++i) acc[i] += ws[i];
+    for (int i = 0; i < 2 * NS; ++i) acc[i] += ws[i];
   }
 #pragma unroll
-  for (int i = 0; i < 2 * N * N; ++i) {
+  for (int i = 0; i < 2 * NS; ++i) {
     R a = acc[i];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
@@ -1123,8 +1165,8 @@ __global__ __launch_bounds__(kT) void k_adj_sum(const KProb kp, const R* __restr
   for (int i = 0; i < N; ++i)
 #pragma unroll
     for (int q = 0; q < N; ++q) {
-      dQ[(long)p * N * N + i * N + q] = R(0.5) * (acc[i * N + q] + acc[q * N + i]);
-      Gs[i][q] = R(0.5) * (acc[N * N + i * N + q] + acc[N * N + q * N + i]);
+      dQ[(long)p * N * N + i * N + q] = acc[Y::at(i, q)];
+      Gs[i][q] = acc[NS + Y::at(i, q)];
     }
   const R* cs = (const R*)kp.consts + (long)p * CS<N, NU>::size;
   R KG[NU][N];
