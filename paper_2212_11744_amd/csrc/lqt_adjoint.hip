@@ -646,6 +646,33 @@ LQT_DEV void stage_add_lds(const Stage<N, R>& y, R* base, int lane) {
   for (int i = 0; i < Sym<N>::size; ++i) base[(L::J + i) * kT + lane] += y.J[i];
 }
 
+// Stage value of block k in a global buffer laid out [value][stride] (coalesced over blocks).
+template <int N, class R>
+LQT_DEV void stage_to_global(const Stage<N, R>& y, R* base, long stride, long k) {
+  using L = StageLay<N>;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) base[(L::A + i * N + q) * stride + k] = y.A[i][q];
+    base[(L::E + i) * stride + k] = y.e[i];
+  }
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) base[(L::J + i) * stride + k] = y.J[i];
+}
+
+template <int N, class R>
+LQT_DEV void stage_from_global(Stage<N, R>& y, const R* base, long stride, long k) {
+  using L = StageLay<N>;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) y.A[i][q] = base[(L::A + i * N + q) * stride + k];
+    y.e[i] = base[(L::E + i) * stride + k];
+  }
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) y.J[i] = base[(L::J + i) * stride + k];
+}
+
 // Compiler-only memory barrier (no instruction): values written to LDS are read back from LDS.
 LQT_DEV void lds_fence() { asm volatile("" ::: "memory"); }
 
@@ -942,7 +969,7 @@ LQT_DEV void stage_seed(R c1, const Tup<N, R>& yb, R c2, const Stage<N, R>& sn, 
 template <int N, int NU, class R>
 __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restrict__ abar,
                                                R* __restrict__ dr, R* __restrict__ bnd,
-                                               R* __restrict__ wsum) {
+                                               R* __restrict__ wsum, R* __restrict__ ckpt) {
   using Y = Sym<N>;
   constexpr int NS = Y::size, SL = StageLay<N>::size;
   __shared__ R sF[N * N], sG[N * N], sQ[N * N];
@@ -986,15 +1013,33 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
     R carry[N];
 #pragma unroll
     for (int q = 0; q < N; ++q) carry[q] = R(0);
+    // Step start values: with a checkpoint buffer, one forward pass stores y_1 .. y_{n-1}
+    // (layout [problem][step - 1][value][block], coalesced over the blocks of a wave);
+    // without one, y_m is recomputed from y_0 = 0 for every step.
+    const long ck_stride = padt(T);
+    R* ckp = ckpt ? ckpt + (long)p * (n - 1) * SL * ck_stride : nullptr;
+    if (ckp) {
+      Stage<N, R> y;
+      stage_zero(y);
+#pragma unroll 1
+      for (int mm = 0; mm < n - 1; ++mm) {
+        rk4_forward(y, 2L * n * k + 2L * (n - mm), hp, rp, vF, vG, vQ);
+        stage_to_global(y, ckp + (long)mm * SL * ck_stride, ck_stride, k);
+      }
+    }
 #pragma unroll 1
     for (int m = n - 1; m >= 0; --m) {
       const long j1 = 2L * n * k + 2L * (n - m);
       {
         Stage<N, R> y;
         stage_zero(y);
+        if (ckp && m > 0) {
+          stage_from_global(y, ckp + (long)(m - 1) * SL * ck_stride, ck_stride, k);
+        } else if (!ckp) {
 #pragma unroll 1
-        for (int mm = 0; mm < m; ++mm)
-          rk4_forward(y, 2L * n * k + 2L * (n - mm), hp, rp, vF, vG, vQ);
+          for (int mm = 0; mm < m; ++mm)
+            rk4_forward(y, 2L * n * k + 2L * (n - mm), hp, rp, vF, vG, vQ);
+        }
         stage_to_lds(y, yL, lane);
         Stage<N, R> z;
         stage_zero(z);
@@ -1258,9 +1303,9 @@ struct A {
     return hipGetLastError();
   }
   static hipError_t rk4(const KProb& kp, const void* abar, void* dr, void* bnd, void* wsum,
-                        hipStream_t s) {
+                        void* ckpt, hipStream_t s) {
     hipLaunchKernelGGL((k_adj_rk4<N, NU, R>), lanes(kp.T, kp.batch), dim3(kT), 0, s, kp,
-                       (const R*)abar, (R*)dr, (R*)bnd, (R*)wsum);
+                       (const R*)abar, (R*)dr, (R*)bnd, (R*)wsum, (R*)ckpt);
     return hipGetLastError();
   }
   static hipError_t finish(const KProb& kp, const void* bnd, void* dr, const void* wsum, void* dQ,

@@ -159,6 +159,12 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
     void* lam = take(es * B * (size_t)(d->T + 1) * nx);
     void* bnd = take(es * B * (size_t)d->T * 2 * nx);
     void* ws = take(es * B * (size_t)((d->T + 63) / 64) * 2 * nx * nx);
+    // step start values (A, eta, J parts) of steps 1 .. n - 1 of every block
+    void* ck = d->n_steps <= kCkptMaxSteps && d->n_steps > 1
+                   ? take(es * B * (size_t)(d->n_steps - 1) * (nx * nx + nx + nx * (nx + 1) / 2) *
+                          padt(d->T))
+                   : nullptr;
+    if (w) w->ckpt = ck;
     if (w) {
       w->lam = lam;
       w->bnd = bnd;
@@ -485,7 +491,7 @@ lqt_status lqt_backward(const lqt_dims* dims, const lqt_problem* prob, const voi
     LQT_HIP(ao->cong_down(kp, w.cmap[l], t.n[l], w.cpart[l], w.cst[l + 1], t.n[l + 1], w.cst[l], s));
   // element gradients, then the RK4 adjoint of every block and the reductions
   LQT_HIP(ao->elem(kp, w.elts, S, v, x, w.lam, w.cst[1], t.n[1], dQf, drf, s));
-  LQT_HIP(ao->rk4(kp, w.elts, dr, w.bnd, w.wsum, s));
+  LQT_HIP(ao->rk4(kp, w.elts, dr, w.bnd, w.wsum, w.ckpt, s));
   LQT_HIP(ao->finish(kp, w.bnd, dr, w.wsum, dQ, dR, s));
   return ok();
 }

@@ -89,7 +89,12 @@ struct Work {
   void* lam = nullptr;               // lambda_k, [batch][T+1][nx]
   void* bnd = nullptr;               // adjoints of block-boundary samples, [batch][T][2][nx]
   void* wsum = nullptr;              // per-wave sums of the Q and G adjoints
+  void* ckpt = nullptr;              // RK4 step start values of every block (nullptr: recompute)
 };
+
+// Largest n_steps for which the adjoint keeps the RK4 step start values of every block in the
+// workspace (above it they are recomputed from the block's start).
+constexpr int kCkptMaxSteps = 16;
 
 // Kernel launchers of one (nx, nu, dtype) instantiation.  Each returns hipGetLastError().
 struct Ops {
@@ -138,7 +143,7 @@ struct AdjOps {
   hipError_t (*elem)(const KProb&, void* elts, const void* S, const void* v, const void* x,
                      const void* lam, const void* sv1, long n1, void* dQf, void* drf,
                      hipStream_t);
-  hipError_t (*rk4)(const KProb&, const void* abar, void* dr, void* bnd, void* wsum,
+  hipError_t (*rk4)(const KProb&, const void* abar, void* dr, void* bnd, void* wsum, void* ckpt,
                     hipStream_t);
   hipError_t (*finish)(const KProb&, const void* bnd, void* dr, const void* wsum, void* dQ,
                        void* dR, hipStream_t);
