@@ -75,19 +75,21 @@ LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
   const R* __restrict__ Qp = (const R*)kp.Q + p * N * N;
   const R* __restrict__ cs = (const R*)kp.consts + p * CS<N, NU>::size;
 
-  R Q[N][N];
+  // Q and G are symmetric: only their upper triangles are kept (fewer registers; with constant
+  // coefficients all of F, G, Lc, Q are wave-uniform and fit the scalar register file).
+  R Q[NS];
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < N; ++j) Q[i][j] = Qp[i * N + j];
-  R F[N][N], G[N][N], Lc[N][NU], cv[N];
+    for (int j = i; j < N; ++j) Q[Y::at(i, j)] = Qp[i * N + j];
+  R F[N][N], G[NS], Lc[N][NU], cv[N];
   if (CONST_COEF) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
 #pragma unroll
       for (int j = 0; j < N; ++j) {
         F[i][j] = Fc[i * N + j];
-        G[i][j] = cs[CS<N, NU>::G + i * N + j];
+        if (j >= i) G[Y::at(i, j)] = cs[CS<N, NU>::G + i * N + j];
       }
 #pragma unroll
       for (int l = 0; l < NU; ++l) Lc[i][l] = cs[CS<N, NU>::Lc + i * NU + l];
@@ -117,6 +119,7 @@ LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
     yJ[i] = R(0);
   }
 
+#pragma unroll 1
   for (int m = 0; m < n; ++m) {
     const long j1 = 2L * n * k + 2L * (n - m);  // sample at s = t_{k+1} - m h
     R sA[N][N], se[N], sJ[NS], aA[N][N], ae[N], aJ[NS];
@@ -157,17 +160,17 @@ LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
 #pragma unroll
           for (int i = 0; i < N; ++i)
 #pragma unroll
-            for (int q = 0; q < N; ++q) {
+            for (int q = i; q < N; ++q) {
               R s = R(0);
 #pragma unroll
               for (int l = 0; l < NU; ++l) s = fma(Lc[i][l], Lc[q][l], s);
-              G[i][q] = s;
+              G[Y::at(i, q)] = s;
             }
         } else {
 #pragma unroll
           for (int i = 0; i < N; ++i) {
 #pragma unroll
-            for (int q = 0; q < N; ++q) G[i][q] = cs[CS<N, NU>::G + i * N + q];
+            for (int q = i; q < N; ++q) G[Y::at(i, q)] = cs[CS<N, NU>::G + i * N + q];
 #pragma unroll
             for (int l = 0; l < NU; ++l) Lc[i][l] = cs[CS<N, NU>::Lc + i * NU + l];
           }
@@ -183,7 +186,7 @@ LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
         for (int q = 0; q < N; ++q) {
           R s = -F[i][q];
 #pragma unroll
-          for (int l = 0; l < N; ++l) s = fma(G[i][l], sJ[Y::at(l, q)], s);
+          for (int l = 0; l < N; ++l) s = fma(G[Y::at(i, l)], sJ[Y::at(l, q)], s);
           K[i][q] = s;
         }
       // b: += wk * ( -(I + Ad)(G eta + c) )
@@ -193,7 +196,7 @@ LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
         for (int i = 0; i < N; ++i) {
           R s = cv[i];
 #pragma unroll
-          for (int l = 0; l < N; ++l) s = fma(G[i][l], se[l], s);
+          for (int l = 0; l < N; ++l) s = fma(G[Y::at(i, l)], se[l], s);
           wv[i] = s;
         }
 #pragma unroll
@@ -235,7 +238,7 @@ LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
         for (int l = 0; l < N; ++l) {
           s = fma(K[l][i], se[l], s);
           if (!CONST_COEF) s = fma(sJ[Y::at(i, l)], cv[l], s);
-          s = fma(-Q[i][l], rv[l], s);
+          s = fma(-Q[Y::at(i, l)], rv[l], s);
         }
         ke[i] = s;
       }
@@ -243,7 +246,7 @@ LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
       for (int i = 0; i < N; ++i)
 #pragma unroll
         for (int q = i; q < N; ++q) {
-          R s = -Q[i][q];
+          R s = -Q[Y::at(i, q)];
 #pragma unroll
           for (int l = 0; l < N; ++l) {
             s = fma(sJ[Y::at(i, l)], K[l][q], s);
