@@ -14,7 +14,7 @@
  *                       x_{k+1} = Psi_k x_k + alpha_k (Method 1, Sec. IV-E; the per-block map is
  *                       the Method 2 formula applied to one block) and the control law of Sec.
  *                       II-B, u_k = -R^{-1} L(t_k)^T (S_k x_k - v_k).
- * plus lqt_solve (the three stages in one call, with fused kernels) and lqt_backward (the adjoint:
+ * plus lqt_solve (the three stages in one call) and lqt_backward (the adjoint:
  * gradients of a loss on the trajectory with respect to Q, R, r, x0, Qf and rf).
  *
  * Problem (Sec. II-B with H = I, so Q = H^T X H and the reference r is in state space):
@@ -136,7 +136,8 @@ lqt_status lqt_forward_traj(const lqt_dims *dims, const lqt_problem *prob, const
                             const void *S, const void *v, void *x, void *u, void *ws,
                             size_t ws_bytes, hipStream_t stream);
 
-/* All three stages in one call (fused kernels; same results as the stage calls up to rounding).
+/* All three stages in one call (the value kernel also forms level 1 of the trajectory tree, so
+ * the elements are read once less; same results as the stage calls up to rounding).
  * elts may be NULL (then the elements live in the workspace); S, v, x must be non-NULL; u may be
  * NULL. */
 lqt_status lqt_solve(const lqt_dims *dims, const lqt_problem *prob, void *elts, void *S, void *v,

@@ -135,7 +135,7 @@ lqt_status prepare(const lqt_ragged* cls, int ncls, void* ws, size_t ws_bytes,
 
 SolveOpts default_opts(const ClassRun& r) {
   SolveOpts o;
-  o.fused = r.d.dtype == LQT_F32;
+  o.fused = false;
   o.wave_chunk = 8;
   return o;
 }
