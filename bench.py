@@ -104,6 +104,7 @@ def main(argv=None):
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-nx16", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-lti", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args(argv)
     if args.gpus != 1:
@@ -175,6 +176,8 @@ def main(argv=None):
                      "algorithmic_bytes_per_launch": build_bytes_per_block(4, n, es) * T},
         "stages_ms": {"build_elements": ms_build, "scan_value": ms_scan, "forward_traj": ms_traj},
     }
+    if not args.no_lti:
+        rec["lti"] = lti_leg(torch, lqt, p, dtype, args.steps, out, T)
     if not args.no_adjoint:
         rec["adjoint"] = adjoint_leg(torch, lqt, W, max(3, args.steps // 4))
     if not args.no_nx16:
@@ -192,6 +195,20 @@ def main(argv=None):
         rec["cpu_baseline"] = cpu_baseline(T, args.cpu_seconds)
     print(json.dumps(rec), flush=True)
     return 0
+
+
+def lti_leg(torch, lqt, p, dtype, reps, out, T):
+    """The same workload through the time-invariant path (lqt_dims.lti): shared A, C, J per
+    problem and each block's b, eta as weighted sums of its samples; same outputs up to rounding."""
+    dp = lqt.DeviceProblem.from_problems([p], dtype=dtype, lti=True)
+    ws = lqt.workspace(dp, lqt.CALL_SOLVE)
+    ws_b = lqt.workspace(dp, lqt.CALL_BUILD)
+    lqt.solve(dp, out, ws)
+    torch.cuda.synchronize()
+    ms = _events_time(lambda: lqt.solve(dp, out, ws), reps, torch)
+    ms_b = _events_time(lambda: lqt.build_elements(dp, out["elts"], ws_b), reps, torch)
+    return {"workload": "same problem, time-invariant path (F, L constant, c = 0, uniform grid)",
+            "ms_per_step": ms, "sub_intervals_per_s": T / (ms * 1e-3), "build_ms": ms_b}
 
 
 def adjoint_leg(torch, lqt, W, reps):

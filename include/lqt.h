@@ -81,6 +81,16 @@ typedef struct lqt_dims {
   int32_t F_sampled; /* 0: F constant [nx*nx] shared by the batch; 1: F [batch][NS][nx*nx]      */
   int32_t L_sampled; /* 0: L constant [nx*nu] shared by the batch; 1: L [batch][NS][nx*nu]      */
   int32_t has_c;     /* 0: c = 0 (c may be NULL); 1: c [batch][NS][nx]                          */
+  int32_t lti;       /* 1: the caller asserts a time-invariant problem on a uniform grid (F, L
+                        constant, c = 0, t_k = t_0 + k (t_1 - t_0) for every problem).  The ODEs
+                        of A, C, J (Theorem 8) then do not involve r and are the same for every
+                        block, and b, eta are linear in the block's 2 n_steps + 1 reference
+                        samples: the build integrates one block per problem with unit-impulse
+                        references to tabulate those linear maps, and forms each block's b, eta
+                        as weighted sums of its samples (same results as the general build up to
+                        rounding).  Requires F_sampled = L_sampled = has_c = 0 (LQT_EINVAL
+                        otherwise); used by lqt_build_elements and lqt_solve for nx <= 4 and
+                        ignored otherwise.  0: general path.                                    */
 } lqt_dims;
 
 typedef struct lqt_problem {

@@ -80,6 +80,10 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
   };
   void* consts = take(es * nconsts * consts_count(d->nx, d->nu));
   if (w) w->consts = consts;
+  if (d->lti && !use_wave(d) && (call == LQT_CALL_BUILD || call == LQT_CALL_SOLVE)) {
+    void* t = take(es * nconsts * lti_count(d->nx, d->n_steps));
+    if (w) w->lti = t;
+  }
   const bool want_v = call == LQT_CALL_SCAN_VALUE || call == LQT_CALL_SOLVE;
   const bool want_t = call == LQT_CALL_FORWARD_TRAJ || call == LQT_CALL_SOLVE;
   if (use_wave(d)) {
@@ -191,6 +195,8 @@ lqt_status check_dims_valid(const lqt_dims* d) {
     return fail(LQT_EINVAL, "n_steps = %d outside [1, 4096]", d->n_steps);
   if (d->batch < 1 || d->batch > 65535)
     return fail(LQT_EINVAL, "batch = %d outside [1, 65535]", d->batch);
+  if (d->lti && (d->F_sampled || d->L_sampled || d->has_c))
+    return fail(LQT_EINVAL, "lti needs constant F and L and c = 0");
   const long double ns = 2.0L * d->n_steps * d->T + 1;
   if (ns * d->nx * d->nx > 9.0e18L) return fail(LQT_EINVAL, "sample arrays too large");
   return LQT_OK;
@@ -258,6 +264,7 @@ KProb make_kprob(const lqt_dims* d, const lqt_problem* p, const void* consts) {
   k.F_sampled = d->F_sampled;
   k.L_sampled = d->L_sampled;
   k.has_c = d->has_c;
+  k.lti = d->lti;
   k.t = p ? p->t : nullptr;
   k.F = p ? p->F : nullptr;
   k.L = p ? p->L : nullptr;
@@ -325,10 +332,15 @@ lqt_status lqt_build_elements(const lqt_dims* dims, const lqt_problem* prob, voi
   LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w));
   KProb kp = make_kprob(dims, prob, w.consts);
   LQT_HIP(prep(dims, kp, w.consts, stream));
-  if (use_wave(dims))
+  if (use_wave(dims)) {
     LQT_HIP(wave_build(kp, dims->dtype, elts, stream));
-  else
+  } else if (dims->lti) {
+    const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
+    LQT_HIP(o->lti_prep(kp, w.lti, stream));
+    LQT_HIP(o->lti_build(kp, w.lti, elts, stream));
+  } else {
     LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build(kp, elts, stream));
+  }
   return ok();
 }
 
@@ -406,11 +418,17 @@ lqt_status run_solve(const lqt_dims* dims, const KProb& kp, const Work& w, void*
   }
   const Ops* op = lane_ops(dims->nx, dims->nu, dims->dtype);
   const Tree t = tree_for(dims);
-  if (o.fused)
+  const bool lti = kp.lti && !kp.seg && w.lti;
+  const bool fused = o.fused && !lti;
+  if (lti) {
+    LQT_HIP(op->lti_prep(kp, w.lti, stream));
+    LQT_HIP(op->lti_build(kp, w.lti, e, stream));
+  } else if (fused) {
     LQT_HIP(op->build_reduce(kp, e, w.vtup[1], t.n[1], stream));
-  else
+  } else {
     LQT_HIP(op->build(kp, e, stream));
-  LQT_TRY(run_value(op, kp, t, w, e, S, v, w.tmap[1], o.fused, stream));
+  }
+  LQT_TRY(run_value(op, kp, t, w, e, S, v, w.tmap[1], fused, stream));
   LQT_TRY(run_traj(op, kp, t, w, e, S, v, x, u, stream));
   return LQT_OK;
 }

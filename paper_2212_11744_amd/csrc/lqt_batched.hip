@@ -26,6 +26,7 @@ size_t dsize(int dtype) { return dtype == LQT_F64 ? 8 : 4; }
 
 lqt_dims class_dims(const lqt_ragged& c) {
   lqt_dims d;
+  memset(&d, 0, sizeof(d));  // lti = 0: the batched solve uses the general build
   d.nx = c.nx;
   d.nu = c.nu;
   d.T = (int32_t)c.rows;

@@ -29,7 +29,20 @@ struct KProb {
   // separator).
   const int64_t* seg = nullptr;
   int nseg = 0;
+  // Time-invariant path (lqt_dims.lti): per-problem shared element parts and response tables.
+  int lti = 0;
 };
+
+// Per-problem table of the time-invariant path (values of the call dtype): A - I [nx*nx],
+// C and J packed upper [ns each], then V[j] and W[j] for the 2n+1 samples j of a block
+// ([nx][nx] each, row-major): b = sum_j V[j] r_j, eta = sum_j W[j] r_j.
+__host__ __device__ inline long lti_off_V(int nx) { return (long)nx * nx + nx * (nx + 1); }
+__host__ __device__ inline long lti_off_W(int nx, int n) {
+  return lti_off_V(nx) + (2L * n + 1) * nx * nx;
+}
+__host__ __device__ inline long lti_count(int nx, int n) {
+  return lti_off_V(nx) + 2 * (2L * n + 1) * nx * nx;
+}
 
 // Index of the problem owning block (or boundary) g in ragged mode: the largest i with
 // seg[i] <= g, clamped to [0, nseg - 1].
@@ -90,6 +103,7 @@ struct Work {
   void* bnd = nullptr;               // adjoints of block-boundary samples, [batch][T][2][nx]
   void* wsum = nullptr;              // per-wave sums of the Q and G adjoints
   void* ckpt = nullptr;              // RK4 step start values of every block (nullptr: recompute)
+  void* lti = nullptr;               // time-invariant path tables, [batch][lti_count]
 };
 
 // Largest n_steps for which the adjoint keeps the RK4 step start values of every block in the
@@ -120,6 +134,9 @@ struct Ops {
                       const void* x_par, long n_par, void* x_child, hipStream_t);
   hipError_t (*tbottom)(const KProb&, const void* elts, const void* S, const void* v,
                         const void* x1, long n1, void* x, void* u, hipStream_t);
+  // time-invariant path: response tables, then the elements from them
+  hipError_t (*lti_prep)(const KProb&, void* tab, hipStream_t);
+  hipError_t (*lti_build)(const KProb&, const void* tab, void* elts, hipStream_t);
 };
 
 // Adjoint kernels (lqt_adjoint.hip) of one (nx, nu, dtype) instantiation.

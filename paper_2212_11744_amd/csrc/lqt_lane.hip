@@ -61,8 +61,23 @@ LQT_DEV Blk blk_ragged(const KProb& kp, int i, long g) {
   return {i, g, (long)i * (1 - 2L * kp.n), g};
 }
 
-template <int N, int NU, class R, bool CONST_COEF>
-LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
+// Reference samples of a block: from memory (the problem's r), or a unit impulse (component
+// `i0` of sample `j0` set to one, every other sample zero), used to tabulate the linear response
+// of b and eta to the samples on the time-invariant path.
+template <int N, class R>
+struct RMem {
+  const R* r;
+  LQT_DEV R operator()(long j, int i) const { return r[j * N + i]; }
+};
+template <class R>
+struct RImpulse {
+  long j0;
+  int i0;
+  LQT_DEV R operator()(long j, int i) const { return j == j0 && i == i0 ? R(1) : R(0); }
+};
+
+template <int N, int NU, class R, bool CONST_COEF, class RS>
+LQT_DEV void build_block_rs(const KProb& kp, const Blk& bk, const RS& rs, Tup<N, R>& out) {
   using Y = Sym<N>;
   constexpr int NS = Y::size;
   const int n = kp.n;
@@ -139,7 +154,7 @@ LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
       const R cn = st == 2 ? -h : -h / R(2);
       R rv[N];
 #pragma unroll
-      for (int i = 0; i < N; ++i) rv[i] = ((const R*)kp.r)[(s0 + j) * N + i];
+      for (int i = 0; i < N; ++i) rv[i] = rs(s0 + j, i);
       if (!CONST_COEF) {
         const R* Fj = kp.F_sampled ? (const R*)kp.F + (s0 + j) * N * N : Fc;
 #pragma unroll
@@ -304,6 +319,135 @@ LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
     out.C[i] = yC[i];
     out.J[i] = yJ[i];
   }
+}
+
+template <int N, int NU, class R, bool CONST_COEF>
+LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
+  build_block_rs<N, NU, R, CONST_COEF>(kp, bk, RMem<N, R>{(const R*)kp.r}, out);
+}
+
+// ------------------------------------------------------------------------------------------
+// Time-invariant path (F, L constant, c = 0, uniform grid).  The RK4 recursion of Theorem 8 for
+// (A, C, J) does not involve r, so every block has the same A, C, J; b and eta are linear in the
+// block's samples r_0 .. r_2n.  k_lti_prep integrates block 0 once per unit impulse (sample j0,
+// component i0) to tabulate those linear maps; k_build_lti forms every block's element from them.
+// ------------------------------------------------------------------------------------------
+template <int N, int NU, class R>
+__global__ __launch_bounds__(kThreads) void k_lti_prep(const KProb kp, R* __restrict__ tab) {
+  const int p = blockIdx.y;
+  const long m = gid();
+  const long M = (2L * kp.n + 1) * N;
+  if (m >= M) return;
+  const long j0 = m / N;
+  const int i0 = (int)(m % N);
+  Tup<N, R> out;
+  const Blk bk{p, 0, 0, (long)p * (kp.T + 1L)};
+  build_block_rs<N, NU, R, true>(kp, bk, RImpulse<R>{j0, i0}, out);
+  R* tp = tab + (long)p * lti_count(N, kp.n);
+  R* V = tp + lti_off_V(N) + j0 * N * N;
+  R* W = tp + lti_off_W(N, kp.n) + j0 * N * N;
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    V[a * N + i0] = out.b[a];
+    W[a * N + i0] = out.e[a];
+  }
+  if (m == 0) {
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+      for (int b = 0; b < N; ++b) tp[a * N + b] = out.A[a][b];
+#pragma unroll
+    for (int q = 0; q < Sym<N>::size; ++q) {
+      tp[N * N + q] = out.C[q];
+      tp[N * N + Sym<N>::size + q] = out.J[q];
+    }
+  }
+}
+
+// b = sum_j V[j] r_j, eta = sum_j W[j] r_j over the block's samples r_0 .. r_2n (rp points at
+// r_0).  MAXJ > 0: the loop is unrolled to MAXJ samples (n_steps <= (MAXJ - 1) / 2) so that all
+// loads of the block are in flight together.
+template <int N, class R, int MAXJ>
+LQT_DEV void lti_sums(const R* rp, const R* tp, int n, Tup<N, R>& out) {
+#pragma unroll
+  for (int a = 0; a < N; ++a) {
+    out.b[a] = R(0);
+    out.e[a] = R(0);
+  }
+  const R* V0 = tp + lti_off_V(N);
+  const R* W0 = tp + lti_off_W(N, n);
+  auto term = [&](int j) {
+    R r[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) r[i] = rp[j * N + i];
+    const R* V = V0 + (long)j * N * N;
+    const R* W = W0 + (long)j * N * N;
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        out.b[a] = fma(V[a * N + i], r[i], out.b[a]);
+        out.e[a] = fma(W[a * N + i], r[i], out.e[a]);
+      }
+  };
+  if (MAXJ > 0) {
+#pragma unroll
+    for (int j = 0; j < MAXJ; ++j)
+      if (j <= 2 * n) term(j);
+  } else {
+    for (int j = 0; j <= 2 * n; ++j) term(j);
+  }
+}
+
+// For n_steps <= 4 the samples of the wave's 64 blocks ([2 n k0, 2 n (k0 + 64)], contiguous) are
+// first copied to LDS with coalesced loads, all issued before the first LDS write; each lane then
+// reads its block's samples from LDS instead of a 256-byte-strided global access.
+constexpr int kLtiMaxStageSteps = 4;
+
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_build_lti(const KProb kp, const R* __restrict__ tab,
+                                                         R* __restrict__ elts) {
+  constexpr int kMaxJ = 2 * kLtiMaxStageSteps + 1;
+  constexpr int kStage = (2 * kLtiMaxStageSteps * kThreads + 1) * N;
+  constexpr int kPer = (kStage + kThreads - 1) / kThreads;
+  __shared__ R rs[kPer * kThreads];
+  const int p = blockIdx.y;
+  const long k = gid();
+  const int n = kp.n;
+  const long T = kp.T;
+  const R* tp = tab + (long)p * lti_count(N, n);
+  const R* rbase = (const R*)kp.r + (long)p * (2L * n * T + 1) * N;
+  Tup<N, R> out;
+  if (n <= kLtiMaxStageSteps) {
+    const long k0 = (long)blockIdx.x * kThreads;
+    const long k1 = min(k0 + kThreads, T);
+    const long cnt = (2L * n * (k1 - k0) + 1) * N;
+    const R* src = rbase + 2L * n * k0 * N;
+    R tmp[kPer];
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) {
+      const long e = (long)it * kThreads + threadIdx.x;
+      tmp[it] = e < cnt ? src[e] : R(0);
+    }
+#pragma unroll
+    for (int it = 0; it < kPer; ++it) rs[it * kThreads + threadIdx.x] = tmp[it];
+    __syncthreads();
+    if (k >= T) return;
+    lti_sums<N, R, kMaxJ>(rs + 2L * n * (k - k0) * N, tp, n, out);
+  } else {
+    if (k >= T) return;
+    lti_sums<N, R, 0>(rbase + 2L * n * k * N, tp, n, out);
+  }
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int b = 0; b < N; ++b) out.A[a][b] = tp[a * N + b];
+#pragma unroll
+  for (int q = 0; q < Sym<N>::size; ++q) {
+    out.C[q] = tp[N * N + q];
+    out.J[q] = tp[N * N + Sym<N>::size + q];
+  }
+  tup_store(out, elts + (long)p * Lay<N>::NE * padt(T), k);
 }
 
 // Separator element of ragged mode after problem i: A = 0 (stored A - I = -I), b = x0 of
@@ -925,9 +1069,20 @@ struct L {
                        dim3(kThreads), 0, s, kp, (R*)consts);
     return hipGetLastError();
   }
+  static hipError_t lti_prep(const KProb& kp, void* tab, hipStream_t s) {
+    hipLaunchKernelGGL((k_lti_prep<N, NU, R>), grid_lanes((2L * kp.n + 1) * N, kp.batch),
+                       dim3(kThreads), 0, s, kp, (R*)tab);
+    return hipGetLastError();
+  }
+  static hipError_t lti_build(const KProb& kp, const void* tab, void* elts, hipStream_t s) {
+    hipLaunchKernelGGL((k_build_lti<N, R>), grid_lanes(kp.T, kp.batch), dim3(kThreads), 0, s,
+                       kp, (const R*)tab, (R*)elts);
+    return hipGetLastError();
+  }
   static const Ops* ops() {
-    static const Ops o = {prep, build, build_reduce, vreduce0, vup,   vtop, vdown,
-                          vbottom, tbottom_reduce, tup, ttop, tdown, tbottom};
+    static const Ops o = {prep,    build,          build_reduce, vreduce0, vup,    vtop,
+                          vdown,   vbottom,        tbottom_reduce, tup,    ttop,   tdown,
+                          tbottom, lti_prep,       lti_build};
     return &o;
   }
 };

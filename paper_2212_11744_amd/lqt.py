@@ -39,7 +39,8 @@ class LQTError(RuntimeError):
 
 class Dims(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("nx", "nu", "T", "n_steps", "batch", "dtype", "F_sampled", "L_sampled", "has_c")]
+                ("nx", "nu", "T", "n_steps", "batch", "dtype", "F_sampled", "L_sampled", "has_c",
+                 "lti")]
 
 
 class Problem(ctypes.Structure):
@@ -134,6 +135,7 @@ class DeviceProblem:
     c: Optional[torch.Tensor] = None
     F_sampled: bool = False
     L_sampled: bool = False
+    lti: bool = False  # time-invariant path (lqt_dims.lti): F, L constant, c = 0, uniform grid
 
     @property
     def nsamp(self) -> int:
@@ -142,16 +144,20 @@ class DeviceProblem:
     def dims(self) -> Dims:
         return Dims(self.nx, self.nu, self.T, self.n, self.batch,
                     LQT_F64 if self.dtype == torch.float64 else LQT_F32,
-                    int(self.F_sampled), int(self.L_sampled), int(self.c is not None))
+                    int(self.F_sampled), int(self.L_sampled), int(self.c is not None),
+                    int(self.lti))
 
     def ptrs(self) -> Problem:
         return Problem(*[None if getattr(self, k) is None else getattr(self, k).data_ptr()
                          for k in ("t", "F", "L", "c", "Q", "R", "r", "Qf", "rf", "x0")])
 
     @classmethod
-    def from_problems(cls, problems: Sequence, dtype=torch.float64, device="cuda") -> "DeviceProblem":
+    def from_problems(cls, problems: Sequence, dtype=torch.float64, device="cuda",
+                      lti: bool = False) -> "DeviceProblem":
         """Stack host problems (objects with the fields of `workloads.Problem`) onto the device.
-        All members must share nx, nu, T, n and, when constant, F and L."""
+        All members must share nx, nu, T, n and, when constant, F and L.  lti=True selects the
+        time-invariant path; it is checked here on the host data (constant F and L, no drift,
+        block lengths equal to within 1e-12 relative)."""
         p0 = problems[0]
         for p in problems:
             if (p.nx, p.nu, p.T, p.n) != (p0.nx, p0.nu, p0.T, p0.n):
@@ -163,10 +169,17 @@ class DeviceProblem:
         to = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
         stack = lambda name: to(np.stack([np.asarray(getattr(p, name)) for p in problems]))
         has_c = getattr(p0, "c", None) is not None
+        if lti:
+            if F_s or L_s or has_c:
+                raise ValueError("the time-invariant path needs constant F, L and no drift")
+            for p in problems:
+                d = np.diff(np.asarray(p.t, dtype=np.float64))
+                if np.max(np.abs(d - d[0])) > 1e-12 * abs(d[0]):
+                    raise ValueError("the time-invariant path needs a uniform grid")
         return cls(p0.nx, p0.nu, p0.T, p0.n, len(problems), dtype,
                    stack("t"), stack("F") if F_s else to(p0.F), stack("L") if L_s else to(p0.L),
                    stack("Q"), stack("R"), stack("r"), stack("Qf"), stack("rf"), stack("x0"),
-                   stack("c") if has_c else None, F_s, L_s)
+                   stack("c") if has_c else None, F_s, L_s, lti)
 
 
 def element_count(nx: int) -> int:
@@ -305,7 +318,7 @@ class SolveTrajectory(torch.autograd.Function):
                              template.dtype, template.t, template.F, template.L,
                              Q.contiguous(), R.contiguous(), r.contiguous(), Qf.contiguous(),
                              rf.contiguous(), x0.contiguous(), template.c, template.F_sampled,
-                             template.L_sampled)
+                             template.L_sampled, template.lti)
         out = solve(prob)
         ctx.prob = prob
         ctx.save_for_backward(out["S"], out["v"], out["x"])

@@ -122,3 +122,18 @@ def test_batched_workspace_and_validation():
     assert L.lqt_plan_launch(None, None) == lqt.LQT_EINVAL
     assert L.lqt_plan_config(None) == b""
     L.lqt_plan_destroy(None)
+
+
+def test_lti_flag_validation_and_workspace():
+    L = lqt.lib()
+    plain = L.lqt_workspace_size(ctypes.byref(_dims()), lqt.CALL_SOLVE)
+    lti = L.lqt_workspace_size(ctypes.byref(_dims(lti=1)), lqt.CALL_SOLVE)
+    assert lti > plain  # the response tables
+    assert L.lqt_workspace_size(ctypes.byref(_dims(lti=1)), lqt.CALL_SCAN_VALUE) == \
+        L.lqt_workspace_size(ctypes.byref(_dims()), lqt.CALL_SCAN_VALUE)
+    for bad in (dict(F_sampled=1), dict(L_sampled=1), dict(has_c=1)):
+        d = _dims(lti=1, **bad)
+        assert L.lqt_workspace_size(ctypes.byref(d), lqt.CALL_SOLVE) == 0
+        p = lqt.Problem()
+        assert L.lqt_build_elements(ctypes.byref(d), ctypes.byref(p), None, None, 0, None) == lqt.LQT_EINVAL
+        assert b"lti" in L.lqt_last_error()
