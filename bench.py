@@ -153,6 +153,9 @@ def main(argv=None):
     ms_scan = _events_time(lambda: lqt.scan_value(dp, out["elts"], S, v, ws_v), max(3, args.steps // 2), torch)
     ms_traj = _events_time(lambda: lqt.forward_traj(dp, out["elts"], S, v, out["x"], out["u"], ws_t),
                            max(3, args.steps // 2), torch)
+    # Elements from the forward conditional ODEs (Theorem 9) on the same problem.
+    ms_fwd = _events_time(lambda: lqt.build_elements_forward(dp, out["elts"], ws_b),
+                          max(3, args.steps // 2), torch)
 
     rec = {
         "metric": "sub-intervals/s for full LQT solve (value+trajectory) at nx=4",
@@ -174,7 +177,8 @@ def main(argv=None):
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "flops_per_launch": flops, "launch_ms": ms_build,
                      "algorithmic_bytes_per_launch": build_bytes_per_block(4, n, es) * T},
-        "stages_ms": {"build_elements": ms_build, "scan_value": ms_scan, "forward_traj": ms_traj},
+        "stages_ms": {"build_elements": ms_build, "scan_value": ms_scan, "forward_traj": ms_traj,
+                      "build_elements_forward": ms_fwd},
     }
     if not args.no_lti:
         rec["lti"] = lti_leg(torch, lqt, p, dtype, args.steps, out, T)

@@ -132,6 +132,18 @@ size_t lqt_workspace_size(const lqt_dims *dims, lqt_call call);
 lqt_status lqt_build_elements(const lqt_dims *dims, const lqt_problem *prob, void *elts, void *ws,
                               size_t ws_bytes, hipStream_t stream);
 
+/* The same elements from the forward conditional ODEs (Theorem 9, Sec. IV-C), integrated in the
+ * upper limit tau from tau = t_k, where (A, b, C, eta, J) = (I, 0, 0, 0, 0), up to t_{k+1} with
+ * n_steps classical RK4 steps of +h_k:
+ * dA/dtau = (F - C Q) A, db/dtau = (F - C Q) b + C Q r + c, dC/dtau = G + F C + C F^T - C Q C,
+ * deta/dtau = A^T Q (r - b), dJ/dtau = A^T Q A.  Samples of step m: 2 n_steps k + 2m (stage 1),
+ * + 1 (stages 2, 3), + 2 (stage 4).  Both theorems describe the same conditional value function,
+ * so the two builds agree to the order of RK4 (O(h^4) per block), not to rounding.  Same
+ * arguments and layout as lqt_build_elements (workspace LQT_CALL_BUILD; lqt_dims.lti ignored);
+ * nx <= 4 (LQT_EUNSUPPORTED otherwise). */
+lqt_status lqt_build_elements_forward(const lqt_dims *dims, const lqt_problem *prob, void *elts,
+                                      void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Value functions (Theorem 6 with the terminal element A = b = C = 0, eta = Qf rf, J = Qf):
  * S [batch][T+1][nx*nx] (full symmetric) and v [batch][T+1][nx], V(x, t_k) = 1/2 x^T S_k x -
  * v_k^T x + const.  elts: as written by lqt_build_elements (any producer of the same layout). */

@@ -344,6 +344,21 @@ lqt_status lqt_build_elements(const lqt_dims* dims, const lqt_problem* prob, voi
   return ok();
 }
 
+lqt_status lqt_build_elements_forward(const lqt_dims* dims, const lqt_problem* prob, void* elts,
+                                      void* ws, size_t ws_bytes, hipStream_t stream) {
+  LQT_TRY(check_supported(dims));
+  if (use_wave(dims))
+    return fail(LQT_EUNSUPPORTED, "the forward element build is available for nx <= 4");
+  LQT_TRY(check_problem(dims, prob, true, false));
+  LQT_TRY(check_ptr(elts, "elts", dsize(dims->dtype)));
+  Work w;
+  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w));
+  KProb kp = make_kprob(dims, prob, w.consts);
+  LQT_HIP(prep(dims, kp, w.consts, stream));
+  LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build_fwd(kp, elts, stream));
+  return ok();
+}
+
 lqt_status lqt_scan_value(const lqt_dims* dims, const void* elts, const void* Qf, const void* rf,
                           void* S, void* v, void* ws, size_t ws_bytes, hipStream_t stream) {
   LQT_TRY(check_supported(dims));

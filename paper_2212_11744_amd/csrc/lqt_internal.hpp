@@ -137,6 +137,8 @@ struct Ops {
   // time-invariant path: response tables, then the elements from them
   hipError_t (*lti_prep)(const KProb&, void* tab, hipStream_t);
   hipError_t (*lti_build)(const KProb&, const void* tab, void* elts, hipStream_t);
+  // elements from the forward conditional ODEs (Theorem 9)
+  hipError_t (*build_fwd)(const KProb&, void* elts, hipStream_t);
 };
 
 // Adjoint kernels (lqt_adjoint.hip) of one (nx, nu, dtype) instantiation.

@@ -327,6 +327,257 @@ LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
 }
 
 // ------------------------------------------------------------------------------------------
+// Element build from Theorem 9 (Sec. IV-C, forward conditional ODEs in the upper limit tau),
+// integrated with classical RK4 from tau = t_k (boundary values (I, 0, 0, 0, 0)) up to t_{k+1}:
+//   dA/dtau = (F - C Q) A,  db/dtau = (F - C Q) b + C Q r + c,
+//   dC/dtau = G + F C + C F^T - C Q C,  deta/dtau = A^T Q (r - b),  dJ/dtau = A^T Q A.
+// With M = F - C Q and A = I + Ad: dAd/dtau = M + M Ad (column q of the result needs column q of
+// Ad only), db/dtau = M b + (F - M) r + c, dC/dtau = G + M C + C F^T.  eta and J never enter a
+// right-hand side, so their RK4 increments are accumulated directly.  Samples: stage 1 at
+// 2 n k + 2 m, stages 2 and 3 at + 1, stage 4 at + 2.
+// ------------------------------------------------------------------------------------------
+template <int N, int NU, class R, bool CONST_COEF>
+LQT_DEV void build_block_fwd(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
+  using Y = Sym<N>;
+  constexpr int NS = Y::size;
+  const int n = kp.n;
+  const int p = bk.p;
+  const long k = bk.k;
+  const long s0 = bk.s0;
+  const long pf = kp.seg ? p : 0;
+  const R* __restrict__ t = (const R*)kp.t + bk.tk;
+  const R* __restrict__ Fc = (const R*)kp.F + pf * N * N;
+  const R* __restrict__ Qp = (const R*)kp.Q + p * N * N;
+  const R* __restrict__ cs = (const R*)kp.consts + p * CS<N, NU>::size;
+  R Q[NS];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = i; j < N; ++j) Q[Y::at(i, j)] = Qp[i * N + j];
+  R F[N][N], G[NS], cv[N];
+  if (CONST_COEF) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        F[i][j] = Fc[i * N + j];
+        if (j >= i) G[Y::at(i, j)] = cs[CS<N, NU>::G + i * N + j];
+      }
+      cv[i] = R(0);
+    }
+  }
+  R Wr[NU][NU];
+  if (!CONST_COEF) {
+#pragma unroll
+    for (int i = 0; i < NU; ++i)
+#pragma unroll
+      for (int j = 0; j < NU; ++j) Wr[i][j] = cs[CS<N, NU>::W + i * NU + j];
+  }
+  const R h = (t[1] - t[0]) / R(n);
+  R yA[N][N], yb[N], yC[NS], ye[N], yJ[NS];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) yA[i][j] = R(0);
+    yb[i] = R(0);
+    ye[i] = R(0);
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    yC[i] = R(0);
+    yJ[i] = R(0);
+  }
+#pragma unroll 1
+  for (int m = 0; m < n; ++m) {
+    const long j0 = 2L * n * k + 2L * m;  // sample at tau = t_k + m h
+    R sA[N][N], sb[N], sC[NS], aA[N][N], ab[N], aC[NS];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) sA[i][j] = yA[i][j];
+      sb[i] = yb[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) sC[i] = yC[i];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const long j = st == 0 ? j0 : (st == 3 ? j0 + 2 : j0 + 1);
+      const R wk = (st == 0 || st == 3) ? h / R(6) : h / R(3);
+      const R cn = st == 2 ? h : h / R(2);
+      R rv[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) rv[i] = ((const R*)kp.r)[(s0 + j) * N + i];
+      if (!CONST_COEF) {
+        const R* Fj = kp.F_sampled ? (const R*)kp.F + (s0 + j) * N * N : Fc;
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int q = 0; q < N; ++q) F[i][q] = Fj[i * N + q];
+        if (kp.L_sampled) {
+          const R* Lj = (const R*)kp.L + (s0 + j) * N * NU;
+          R Lc[N][NU];
+#pragma unroll
+          for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int l = 0; l < NU; ++l) {
+              R s = R(0);
+#pragma unroll
+              for (int q = 0; q < NU; ++q) s = fma(Lj[i * NU + q], Wr[q][l], s);
+              Lc[i][l] = s;
+            }
+#pragma unroll
+          for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int q = i; q < N; ++q) {
+              R s = R(0);
+#pragma unroll
+              for (int l = 0; l < NU; ++l) s = fma(Lc[i][l], Lc[q][l], s);
+              G[Y::at(i, q)] = s;
+            }
+        } else {
+#pragma unroll
+          for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int q = i; q < N; ++q) G[Y::at(i, q)] = cs[CS<N, NU>::G + i * N + q];
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) cv[i] = kp.has_c ? ((const R*)kp.c)[(s0 + j) * N + i] : R(0);
+      }
+      // M = F - C Q
+      R M[N][N];
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          R s = F[i][q];
+#pragma unroll
+          for (int l = 0; l < N; ++l) s = fma(-sC[Y::at(i, l)], Q[Y::at(l, q)], s);
+          M[i][q] = s;
+        }
+      // eta and J increments from the stage value (accumulated directly):
+      // w = Q (r - b), deta = w + Ad^T w;  P = Q (I + Ad), dJ = P + Ad^T P (upper)
+      {
+        R w[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          R s = R(0);
+#pragma unroll
+          for (int l = 0; l < N; ++l) s = fma(Q[Y::at(i, l)], rv[l] - sb[l], s);
+          w[i] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          R s = w[i];
+#pragma unroll
+          for (int l = 0; l < N; ++l) s = fma(sA[l][i], w[l], s);
+          ye[i] = fma(wk, s, ye[i]);
+        }
+        R P[N][N];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int q = 0; q < N; ++q) {
+            R s = Q[Y::at(i, q)];
+#pragma unroll
+            for (int l = 0; l < N; ++l) s = fma(Q[Y::at(i, l)], sA[l][q], s);
+            P[i][q] = s;
+          }
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int q = i; q < N; ++q) {
+            R s = P[i][q];
+#pragma unroll
+            for (int l = 0; l < N; ++l) s = fma(sA[l][i], P[l][q], s);
+            yJ[Y::at(i, q)] = fma(wk, s, yJ[Y::at(i, q)]);
+          }
+      }
+      // kC (upper) = G + M C + C F^T and kb = M b + (F - M) r + c, from the stage values
+      R kC[NS], kb[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int q = i; q < N; ++q) {
+          R s = G[Y::at(i, q)];
+#pragma unroll
+          for (int l = 0; l < N; ++l) {
+            s = fma(M[i][l], sC[Y::at(l, q)], s);
+            s = fma(sC[Y::at(i, l)], F[q][l], s);
+          }
+          kC[Y::at(i, q)] = s;
+        }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        R s = cv[i];
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+          s = fma(M[i][l], sb[l], s);
+          s = fma(F[i][l] - M[i][l], rv[l], s);
+        }
+        kb[i] = s;
+      }
+      // Ad columns: kA = M + M Ad (column q needs column q of Ad only)
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R kc[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          R s = M[i][q];
+#pragma unroll
+          for (int l = 0; l < N; ++l) s = fma(M[i][l], sA[l][q], s);
+          kc[i] = s;
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          aA[i][q] = st == 0 ? fma(wk, kc[i], yA[i][q]) : fma(wk, kc[i], aA[i][q]);
+          if (st < 3) sA[i][q] = fma(cn, kc[i], yA[i][q]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        ab[i] = st == 0 ? fma(wk, kb[i], yb[i]) : fma(wk, kb[i], ab[i]);
+        if (st < 3) sb[i] = fma(cn, kb[i], yb[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < NS; ++i) {
+        aC[i] = st == 0 ? fma(wk, kC[i], yC[i]) : fma(wk, kC[i], aC[i]);
+        if (st < 3) sC[i] = fma(cn, kC[i], yC[i]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) yA[i][j] = aA[i][j];
+      yb[i] = ab[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i) yC[i] = aC[i];
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) out.A[i][j] = yA[i][j];
+    out.b[i] = yb[i];
+    out.e[i] = ye[i];
+  }
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    out.C[i] = yC[i];
+    out.J[i] = yJ[i];
+  }
+}
+
+template <int N, int NU, class R, bool CONST_COEF>
+__global__ __launch_bounds__(kThreads) void k_build_fwd(const KProb kp, R* __restrict__ elts) {
+  const int p = blockIdx.y;
+  const long k = gid();
+  if (k >= kp.T) return;
+  Tup<N, R> out;
+  build_block_fwd<N, NU, R, CONST_COEF>(kp, blk_plain(kp, p, k), out);
+  tup_store(out, elts + (long)p * Lay<N>::NE * padt(kp.T), k);
+}
+
+// ------------------------------------------------------------------------------------------
 // Time-invariant path (F, L constant, c = 0, uniform grid).  The RK4 recursion of Theorem 8 for
 // (A, C, J) does not involve r, so every block has the same A, C, J; b and eta are linear in the
 // block's samples r_0 .. r_2n.  k_lti_prep integrates block 0 once per unit impulse (sample j0,
@@ -1069,6 +1320,16 @@ struct L {
                        dim3(kThreads), 0, s, kp, (R*)consts);
     return hipGetLastError();
   }
+  static hipError_t build_fwd(const KProb& kp, void* elts, hipStream_t s) {
+    const bool cc = !kp.F_sampled && !kp.L_sampled && !kp.has_c;
+    if (cc)
+      hipLaunchKernelGGL((k_build_fwd<N, NU, R, true>), grid_lanes(kp.T, kp.batch),
+                         dim3(kThreads), 0, s, kp, (R*)elts);
+    else
+      hipLaunchKernelGGL((k_build_fwd<N, NU, R, false>), grid_lanes(kp.T, kp.batch),
+                         dim3(kThreads), 0, s, kp, (R*)elts);
+    return hipGetLastError();
+  }
   static hipError_t lti_prep(const KProb& kp, void* tab, hipStream_t s) {
     hipLaunchKernelGGL((k_lti_prep<N, NU, R>), grid_lanes((2L * kp.n + 1) * N, kp.batch),
                        dim3(kThreads), 0, s, kp, (R*)tab);
@@ -1082,7 +1343,7 @@ struct L {
   static const Ops* ops() {
     static const Ops o = {prep,    build,          build_reduce, vreduce0, vup,    vtop,
                           vdown,   vbottom,        tbottom_reduce, tup,    ttop,   tdown,
-                          tbottom, lti_prep,       lti_build};
+                          tbottom, lti_prep,       lti_build,    build_fwd};
     return &o;
   }
 };

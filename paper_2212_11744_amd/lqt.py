@@ -74,11 +74,13 @@ def lib():
         L.lqt_workspace_size.argtypes = [P(Dims), ctypes.c_int]
         L.lqt_workspace_size.restype = sz
         L.lqt_build_elements.argtypes = [P(Dims), P(Problem), vp, vp, sz, st]
+        L.lqt_build_elements_forward.argtypes = [P(Dims), P(Problem), vp, vp, sz, st]
         L.lqt_scan_value.argtypes = [P(Dims), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_forward_traj.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_solve.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_backward.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, st]
-        for f in ("lqt_build_elements", "lqt_scan_value", "lqt_forward_traj", "lqt_solve", "lqt_backward"):
+        for f in ("lqt_build_elements", "lqt_build_elements_forward", "lqt_scan_value",
+                  "lqt_forward_traj", "lqt_solve", "lqt_backward"):
             getattr(L, f).restype = ctypes.c_int
         L.lqt_batched_workspace_size.argtypes = [P(Ragged), ctypes.c_int32]
         L.lqt_batched_workspace_size.restype = sz
@@ -227,6 +229,17 @@ def build_elements(prob: DeviceProblem, elts: Optional[torch.Tensor] = None,
     d, p = prob.dims(), prob.ptrs()
     _check(lib().lqt_build_elements(ctypes.byref(d), ctypes.byref(p), _ptr(elts), _ptr(ws),
                                     ws.numel(), _stream()))
+    return elts
+
+
+def build_elements_forward(prob: DeviceProblem, elts: Optional[torch.Tensor] = None,
+                           ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Elements from the forward conditional ODEs (Theorem 9); same layout as build_elements."""
+    elts = empty_elements(prob) if elts is None else elts
+    ws = workspace(prob, CALL_BUILD) if ws is None else ws
+    d, p = prob.dims(), prob.ptrs()
+    _check(lib().lqt_build_elements_forward(ctypes.byref(d), ctypes.byref(p), _ptr(elts), _ptr(ws),
+                                            ws.numel(), _stream()))
     return elts
 
 
