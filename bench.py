@@ -153,6 +153,10 @@ def main(argv=None):
     ms_scan = _events_time(lambda: lqt.scan_value(dp, out["elts"], S, v, ws_v), max(3, args.steps // 2), torch)
     ms_traj = _events_time(lambda: lqt.forward_traj(dp, out["elts"], S, v, out["x"], out["u"], ws_t),
                            max(3, args.steps // 2), torch)
+    # Method 2 trajectory (forward prefix scan) from the same elements and values.
+    ws_m2 = lqt.workspace(dp, lqt.CALL_TRAJ_METHOD2)
+    ms_m2 = _events_time(lambda: lqt.forward_traj_method2(dp, out["elts"], S, v, out["x"], out["u"], ws_m2),
+                         max(3, args.steps // 2), torch)
     # Elements from the forward conditional ODEs (Theorem 9) on the same problem.
     ms_fwd = _events_time(lambda: lqt.build_elements_forward(dp, out["elts"], ws_b),
                           max(3, args.steps // 2), torch)
@@ -178,7 +182,7 @@ def main(argv=None):
                      "flops_per_launch": flops, "launch_ms": ms_build,
                      "algorithmic_bytes_per_launch": build_bytes_per_block(4, n, es) * T},
         "stages_ms": {"build_elements": ms_build, "scan_value": ms_scan, "forward_traj": ms_traj,
-                      "build_elements_forward": ms_fwd},
+                      "build_elements_forward": ms_fwd, "forward_traj_method2": ms_m2},
     }
     if not args.no_lti:
         rec["lti"] = lti_leg(torch, lqt, p, dtype, args.steps, out, T)

@@ -68,7 +68,8 @@ typedef enum lqt_call {
   LQT_CALL_SCAN_VALUE = 1,
   LQT_CALL_FORWARD_TRAJ = 2,
   LQT_CALL_SOLVE = 3,
-  LQT_CALL_BACKWARD = 4
+  LQT_CALL_BACKWARD = 4,
+  LQT_CALL_TRAJ_METHOD2 = 5
 } lqt_call;
 
 typedef struct lqt_dims {
@@ -157,6 +158,16 @@ lqt_status lqt_scan_value(const lqt_dims *dims, const void *elts, const void *Qf
 lqt_status lqt_forward_traj(const lqt_dims *dims, const lqt_problem *prob, const void *elts,
                             const void *S, const void *v, void *x, void *u, void *ws,
                             size_t ws_bytes, hipStream_t stream);
+
+/* The same trajectory by Method 2 (Sec. IV-E): x_k minimises V(x0, t_0; x, t_k) + V(x, t_k), with the
+ * conditional value function on [t_0, t_k] the prefix a_0 (x) ... (x) a_{k-1} (Lemma 7) and
+ * V(., t_k) from S_k, v_k:  x_k = (I + C S_k)^{-1} (A x0 + b + C v_k) for the prefix's A, b, C,
+ * computed by a forward parallel scan; u_k as in lqt_forward_traj.  Agrees with lqt_forward_traj
+ * up to rounding.  Same arguments (workspace LQT_CALL_TRAJ_METHOD2); nx <= 4 (LQT_EUNSUPPORTED
+ * otherwise). */
+lqt_status lqt_forward_traj_method2(const lqt_dims *dims, const lqt_problem *prob,
+                                    const void *elts, const void *S, const void *v, void *x,
+                                    void *u, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* All three stages in one call (the value kernel also forms level 1 of the trajectory tree, so
  * the elements are read once less; same results as the stage calls up to rounding).

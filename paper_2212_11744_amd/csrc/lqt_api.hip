@@ -84,7 +84,9 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
     void* t = take(es * nconsts * lti_count(d->nx, d->n_steps));
     if (w) w->lti = t;
   }
-  const bool want_v = call == LQT_CALL_SCAN_VALUE || call == LQT_CALL_SOLVE;
+  // The Method 2 trajectory uses the value-scan arrays for its node products and prefix states.
+  const bool want_v = call == LQT_CALL_SCAN_VALUE || call == LQT_CALL_SOLVE ||
+                      call == LQT_CALL_TRAJ_METHOD2;
   const bool want_t = call == LQT_CALL_FORWARD_TRAJ || call == LQT_CALL_SOLVE;
   if (use_wave(d)) {
     const WTree t = wave_tree(d->T, wc);
@@ -319,7 +321,7 @@ size_t lqt_element_count(int32_t nx) { return nx < 1 ? 0 : (size_t)ne_of(nx); }
 
 size_t lqt_workspace_size(const lqt_dims* dims, lqt_call call) {
   if (check_dims_valid(dims) != LQT_OK) return 0;
-  if (call < LQT_CALL_BUILD || call > LQT_CALL_BACKWARD) return 0;
+  if (call < LQT_CALL_BUILD || call > LQT_CALL_TRAJ_METHOD2) return 0;
   return layout(dims, call, nullptr, nullptr);
 }
 
@@ -356,6 +358,38 @@ lqt_status lqt_build_elements_forward(const lqt_dims* dims, const lqt_problem* p
   KProb kp = make_kprob(dims, prob, w.consts);
   LQT_HIP(prep(dims, kp, w.consts, stream));
   LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build_fwd(kp, elts, stream));
+  return ok();
+}
+
+lqt_status lqt_forward_traj_method2(const lqt_dims* dims, const lqt_problem* prob,
+                                    const void* elts, const void* S, const void* v, void* x,
+                                    void* u, void* ws, size_t ws_bytes, hipStream_t stream) {
+  LQT_TRY(check_supported(dims));
+  if (use_wave(dims)) return fail(LQT_EUNSUPPORTED, "the Method 2 trajectory is available for nx <= 4");
+  const size_t es = dsize(dims->dtype);
+  if (!prob) return fail(LQT_EINVAL, "problem is NULL");
+  LQT_TRY(check_ptr(prob->L, "L", es));
+  LQT_TRY(check_ptr(prob->R, "R", es));
+  LQT_TRY(check_ptr(prob->x0, "x0", es));
+  LQT_TRY(check_ptr(elts, "elts", es));
+  LQT_TRY(check_ptr(S, "S", es));
+  LQT_TRY(check_ptr(v, "v", es));
+  LQT_TRY(check_ptr(x, "x", es));
+  if (u) LQT_TRY(check_ptr(u, "u", es));
+  Work w;
+  LQT_TRY(check_ws(dims, LQT_CALL_TRAJ_METHOD2, ws, ws_bytes, &w));
+  KProb kp = make_kprob(dims, prob, w.consts);
+  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
+  const Tree t = tree_for(dims);
+  LQT_HIP(o->prep(kp, w.consts, stream));
+  LQT_HIP(o->vreduce0(kp, elts, w.vtup[1], t.n[1], stream));  // products of 4 blocks
+  for (int l = 1; l < t.levels; ++l)
+    LQT_HIP(o->m2_up(kp, w.vtup[l], t.n[l], w.vpart[l], w.vtup[l + 1], t.n[l + 1], stream));
+  LQT_HIP(o->m2_top(kp, w.vtup[t.levels], t.n[t.levels], w.vval[t.levels], stream));
+  for (int l = t.levels - 1; l >= 1; --l)
+    LQT_HIP(o->m2_down(kp, w.vtup[l], t.n[l], w.vpart[l], w.vval[l + 1], t.n[l + 1], w.vval[l],
+                       stream));
+  LQT_HIP(o->m2_bottom(kp, elts, S, v, w.vval[1], t.n[1], x, u, stream));
   return ok();
 }
 

@@ -139,6 +139,14 @@ struct Ops {
   hipError_t (*lti_build)(const KProb&, const void* tab, void* elts, hipStream_t);
   // elements from the forward conditional ODEs (Theorem 9)
   hipError_t (*build_fwd)(const KProb&, void* elts, hipStream_t);
+  // Method 2 trajectory: forward prefix scan of (C, z) over the node products
+  hipError_t (*m2_up)(const KProb&, const void* src, long n_src, void* part, void* dst, long n_dst,
+                      hipStream_t);
+  hipError_t (*m2_top)(const KProb&, const void* tup, long n, void* st, hipStream_t);
+  hipError_t (*m2_down)(const KProb&, const void* tup, long n_child, const void* part,
+                        const void* st_par, long n_par, void* st_child, hipStream_t);
+  hipError_t (*m2_bottom)(const KProb&, const void* elts, const void* S, const void* v,
+                          const void* st1, long n1, void* x, void* u, hipStream_t);
 };
 
 // Adjoint kernels (lqt_adjoint.hip) of one (nx, nu, dtype) instantiation.

@@ -1225,6 +1225,161 @@ struct TrajAlg {
 };
 
 // ------------------------------------------------------------------------------------------
+// Method 2 of Sec. IV-E: x_k minimises V(x0, t_0; x, t_k) + V(x, t_k), where the conditional value
+// function on [t_0, t_k] is the prefix P_k = a_0 (x) ... (x) a_{k-1}:
+//   x_k = (I + C(P_k) S_k)^{-1} (A(P_k) x0 + b(P_k) + C(P_k) v_k).
+// Only z = A(P) x0 + b(P) and C(P) are needed, and appending a tuple a to the prefix (Lemma 7
+// with the prefix on the left) maps them without the prefix's eta and J:
+//   z' = A_a (I + C J_a)^{-1} (z + C eta_a) + b_a,  C' = A_a (I + C J_a)^{-1} C A_a^T + C_a.
+// So the forward scan carries the state (C packed, z) over the same node products as the value
+// scan.
+// ------------------------------------------------------------------------------------------
+template <int N, class R>
+LQT_DEV void fwd_fold(const Tup<N, R>& a, R (&C)[Sym<N>::size], R (&z)[N]) {
+  using Y = Sym<N>;
+  R M[N][N], B[N][N + 1];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = R(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(C[Y::at(i, l)], a.J[Y::at(l, q)], s);
+      M[i][q] = (i == q) ? R(1) + s : s;
+      B[i][q] = C[Y::at(i, q)];
+    }
+    R g = z[i];
+#pragma unroll
+    for (int l = 0; l < N; ++l) g = fma(C[Y::at(i, l)], a.e[l], g);
+    B[i][N] = g;
+  }
+  gj_solve<N, N + 1>(M, B);  // B = [(I + C J)^{-1} C | (I + C J)^{-1} (z + C eta)]
+  // z' = g + Ad g + b;  W = (I + Ad) D,  C' = W (I + Ad)^T + C_a (upper)
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = B[i][N] + a.b[i];
+#pragma unroll
+    for (int l = 0; l < N; ++l) s = fma(a.A[i][l], B[l][N], s);
+    z[i] = s;
+  }
+  R W[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R s = B[i][q];
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(a.A[i][l], B[l][q], s);
+      W[i][q] = s;
+    }
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = i; q < N; ++q) {
+      R s = W[i][q] + a.C[Y::at(i, q)];
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(W[i][l], a.A[q][l], s);
+      C[Y::at(i, q)] = s;
+    }
+}
+
+template <int N, class R>
+struct PreAlg {
+  static constexpr bool kForward = true;
+  static constexpr int NMAP = Lay<N>::NE, NST = Lay<N>::NV;
+  using Map = Tup<N, R>;
+  struct State {
+    R S[Sym<N>::size];  // C of the prefix
+    R v[N];             // z = A x0 + b of the prefix
+  };
+  static LQT_DEV void identity(Map& m) { tup_identity(m); }
+  static LQT_DEV void load(Map& m, const R* b, long k) { tup_load(m, b, k); }
+  static LQT_DEV void store(const Map& m, R* b, long k) { tup_store(m, b, k); }
+  static LQT_DEV void chain(const Map& first, const Map& second, Map& out) {
+    Map o;
+    combine(first, second, o);
+    out = o;
+  }
+  static LQT_DEV void apply(const Map& m, State& st) { fwd_fold(m, st.S, st.v); }
+  static LQT_DEV void sload(State& st, const R* b, long k) { val_load<N, R>(st.S, st.v, b, k); }
+  static LQT_DEV void sstore(const State& st, R* b, long k) { val_store<N, R>(st.S, st.v, b, k); }
+  static LQT_DEV void shfl_map(const Map& x, Map& y, int src) { shfl_tup(x, y, src); }
+  static LQT_DEV void shfl_state(const State& x, State& y, int src) {
+    shfl_val<N, R>(x.S, x.v, y.S, y.v, src);
+  }
+  static LQT_DEV void init(const KProb& kp, const R*, int p, State& st) {
+#pragma unroll
+    for (int q = 0; q < Sym<N>::size; ++q) st.S[q] = R(0);
+#pragma unroll
+    for (int q = 0; q < N; ++q) st.v[q] = ((const R*)kp.x0)[(long)p * N + q];
+  }
+};
+
+// x_k = (I + C S_k)^{-1} (z + C v_k) and u_k for the 4 blocks of lane i, from the prefix state at
+// the left end of its level-1 node; the last lane also gives x_T, u_T.
+template <int N, int NU, class R>
+__global__ __launch_bounds__(kThreads) void k_m2_bottom(const KProb kp, const R* __restrict__ elts,
+                                                         const R* __restrict__ Sg,
+                                                         const R* __restrict__ vg,
+                                                         const R* __restrict__ st1, long n1,
+                                                         R* __restrict__ xout,
+                                                         R* __restrict__ uout) {
+  using Y = Sym<N>;
+  const int p = blockIdx.y;
+  const long i = gid();
+  if (i >= n1) return;
+  const long T = kp.T;
+  const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
+  const R* Sp = Sg + (long)p * (T + 1) * N * N;
+  const R* vp = vg + (long)p * (T + 1) * N;
+  R* xp = xout + (long)p * (T + 1) * N;
+  R* up = uout ? uout + (long)p * (T + 1) * NU : nullptr;
+  R C[Y::size], z[N];
+  val_load<N, R>(C, z, st1 + (long)p * Lay<N>::NV * padt(n1), i);
+  const long j0 = i * kChunk;
+  const long j1 = min(j0 + kChunk, T);
+  R Kc[NU][N];
+  if (!kp.L_sampled) gain_at<N, NU, R>(kp, p, 0, Kc);
+  auto emit = [&](long k) {
+    R S[Y::size], v[N], M[N][N], B[N][1];
+    S_load_upper<N, R>(S, Sp + k * N * N);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = vp[k * N + q];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      R g = z[a];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R s = R(0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(C[Y::at(a, l)], S[Y::at(l, q)], s);
+        M[a][q] = (a == q) ? R(1) + s : s;
+        g = fma(C[Y::at(a, q)], v[q], g);
+      }
+      B[a][0] = g;
+    }
+    gj_solve<N, 1>(M, B);
+    R x[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      x[q] = B[q][0];
+      xp[k * N + q] = x[q];
+    }
+    if (up) {
+      if (kp.L_sampled) gain_at<N, NU, R>(kp, p, k, Kc);
+      control<N, NU, R>(Kc, S, v, x, up + k * NU);
+    }
+  };
+  for (long k = j0; k < j1; ++k) {
+    emit(k);
+    Tup<N, R> a;
+    tup_load(a, ep, k);
+    fwd_fold(a, C, z);
+  }
+  if (j1 == T) emit(T);
+}
+
+// ------------------------------------------------------------------------------------------
 // Launchers.
 // ------------------------------------------------------------------------------------------
 inline dim3 grid_lanes(long n, int batch) {
@@ -1320,6 +1475,32 @@ struct L {
                        dim3(kThreads), 0, s, kp, (R*)consts);
     return hipGetLastError();
   }
+  // Method 2: forward prefix scan over the node products (the value tree's level 1 and up)
+  static hipError_t m2_up(const KProb& kp, const void* src, long n_src, void* part, void* dst,
+                          long n_dst, hipStream_t s) {
+    hipLaunchKernelGGL((k_up<PreAlg<N, R>, R>), grid_waves(n_dst, kp.batch), dim3(kThreads), 0, s,
+                       (const R*)src, n_src, (R*)part, (R*)dst, n_dst);
+    return hipGetLastError();
+  }
+  static hipError_t m2_top(const KProb& kp, const void* tup, long n, void* st, hipStream_t s) {
+    hipLaunchKernelGGL((k_top<PreAlg<N, R>, R>), dim3(1, kp.batch, 1), dim3(kThreads), 0, s, kp,
+                       (const R*)nullptr, (const R*)tup, n, (R*)st);
+    return hipGetLastError();
+  }
+  static hipError_t m2_down(const KProb& kp, const void* tup, long n_child, const void* part,
+                            const void* st_par, long n_par, void* st_child, hipStream_t s) {
+    hipLaunchKernelGGL((k_down<PreAlg<N, R>, R>), grid_waves(n_par, kp.batch), dim3(kThreads), 0,
+                       s, (const R*)tup, n_child, (const R*)part, (const R*)st_par, n_par,
+                       (R*)st_child);
+    return hipGetLastError();
+  }
+  static hipError_t m2_bottom(const KProb& kp, const void* elts, const void* S, const void* v,
+                              const void* st1, long n1, void* x, void* u, hipStream_t s) {
+    hipLaunchKernelGGL((k_m2_bottom<N, NU, R>), grid_lanes(n1, kp.batch), dim3(kThreads), 0, s,
+                       kp, (const R*)elts, (const R*)S, (const R*)v, (const R*)st1, n1, (R*)x,
+                       (R*)u);
+    return hipGetLastError();
+  }
   static hipError_t build_fwd(const KProb& kp, void* elts, hipStream_t s) {
     const bool cc = !kp.F_sampled && !kp.L_sampled && !kp.has_c;
     if (cc)
@@ -1343,7 +1524,8 @@ struct L {
   static const Ops* ops() {
     static const Ops o = {prep,    build,          build_reduce, vreduce0, vup,    vtop,
                           vdown,   vbottom,        tbottom_reduce, tup,    ttop,   tdown,
-                          tbottom, lti_prep,       lti_build,    build_fwd};
+                          tbottom, lti_prep,       lti_build,    build_fwd,
+                          m2_up,   m2_top,         m2_down,      m2_bottom};
     return &o;
   }
 };

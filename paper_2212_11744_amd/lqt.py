@@ -28,7 +28,7 @@ LIB_PATH = os.path.join(_HERE, "liblqt.so")
 
 LQT_OK, LQT_EINVAL, LQT_EUNSUPPORTED, LQT_EWORKSPACE, LQT_EHIP = 0, -1, -2, -3, -4
 LQT_F64, LQT_F32 = 0, 1
-CALL_BUILD, CALL_SCAN_VALUE, CALL_FORWARD_TRAJ, CALL_SOLVE, CALL_BACKWARD = range(5)
+CALL_BUILD, CALL_SCAN_VALUE, CALL_FORWARD_TRAJ, CALL_SOLVE, CALL_BACKWARD, CALL_TRAJ_METHOD2 = range(6)
 
 
 class LQTError(RuntimeError):
@@ -77,10 +77,11 @@ def lib():
         L.lqt_build_elements_forward.argtypes = [P(Dims), P(Problem), vp, vp, sz, st]
         L.lqt_scan_value.argtypes = [P(Dims), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_forward_traj.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
+        L.lqt_forward_traj_method2.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_solve.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_backward.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, st]
         for f in ("lqt_build_elements", "lqt_build_elements_forward", "lqt_scan_value",
-                  "lqt_forward_traj", "lqt_solve", "lqt_backward"):
+                  "lqt_forward_traj", "lqt_forward_traj_method2", "lqt_solve", "lqt_backward"):
             getattr(L, f).restype = ctypes.c_int
         L.lqt_batched_workspace_size.argtypes = [P(Ragged), ctypes.c_int32]
         L.lqt_batched_workspace_size.restype = sz
@@ -263,6 +264,19 @@ def forward_traj(prob: DeviceProblem, elts, S, v, x=None, u=None, ws=None, want_
     d, p = prob.dims(), prob.ptrs()
     _check(lib().lqt_forward_traj(ctypes.byref(d), ctypes.byref(p), _ptr(elts), _ptr(S), _ptr(v),
                                   _ptr(x), _ptr(u), _ptr(ws), ws.numel(), _stream()))
+    return x, u
+
+
+def forward_traj_method2(prob: DeviceProblem, elts, S, v, x=None, u=None, ws=None, want_u=True):
+    """Trajectory and control by Method 2 (forward prefix scan of conditional value functions)."""
+    x = _empty(prob, prob.batch, prob.T + 1, prob.nx) if x is None else x
+    if want_u and u is None:
+        u = _empty(prob, prob.batch, prob.T + 1, prob.nu)
+    ws = workspace(prob, CALL_TRAJ_METHOD2) if ws is None else ws
+    d, p = prob.dims(), prob.ptrs()
+    _check(lib().lqt_forward_traj_method2(ctypes.byref(d), ctypes.byref(p), _ptr(elts), _ptr(S),
+                                          _ptr(v), _ptr(x), _ptr(u), _ptr(ws), ws.numel(),
+                                          _stream()))
     return x, u
 
 

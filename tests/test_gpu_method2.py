@@ -1,0 +1,90 @@
+"""Method 2 trajectory (Sec. IV-E: prefix products of conditional value functions combined with
+the value function at t_k) on the GPU.
+
+Against the oracle's Method 2 solve (normwise 1e-9 FP64, 1e-4 FP32) and against the Method 1
+trajectory of the same elements and values (the two routes agree up to rounding).  Sizes span
+one to three levels of the scan tree with ragged last nodes, every (nx, nu) of the per-lane path,
+sampled F, L, a drift c, and batches.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from helpers import relerr
+from paper_2212_11744_amd import lqt
+from paper_2212_11744_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = {torch.float64: 1e-9, torch.float32: 1e-4}
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _device():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lqt.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _run(p, dtype=torch.float64, batch=None):
+    probs = batch or [p]
+    dp = lqt.DeviceProblem.from_problems(probs, dtype=dtype)
+    out = lqt.solve(dp, keep_elements=True)
+    x2, u2 = lqt.forward_traj_method2(dp, out["elts"], out["S"], out["v"])
+    torch.cuda.synchronize()
+    return out, x2, u2
+
+
+@pytest.mark.parametrize("T", [1, 2, 5, 64, 257, 1023, 1025, 4 * 256 * 256 + 3])
+def test_point_mass_against_oracle_method2(T):
+    p = W.point_mass(30 + T % 7, T, 2, tf=10.0 * T / 2 ** 16 + 0.05)
+    ref = O.solve(p, method2=True)
+    out, x2, u2 = _run(p)
+    assert relerr(_np(x2[0]), ref["x"]) < 1e-9
+    assert relerr(_np(u2[0]), ref["u"]) < 1e-9
+    assert relerr(_np(x2[0]), _np(out["x"][0])) < 1e-10
+
+
+@pytest.mark.parametrize("nx,nu", [(1, 1), (2, 1), (2, 2), (3, 1), (3, 2), (3, 3), (4, 1), (4, 2), (4, 3), (4, 4)])
+def test_every_size_time_varying_with_drift(nx, nu):
+    p = W.random_stable(11 * nx + nu, nx=nx, nu=nu, T=300, n=3, tf=3.0, time_varying=True)
+    rng = np.random.default_rng(nx + 3 * nu)
+    p.c = 0.3 * np.sin(np.linspace(0, 3, p.r.shape[0]))[:, None] * rng.standard_normal(nx)[None, :]
+    ref = O.solve(p, method2=True)
+    _, x2, u2 = _run(p)
+    assert relerr(_np(x2[0]), ref["x"]) < 1e-9
+    assert relerr(_np(u2[0]), ref["u"]) < 1e-9
+
+
+def test_sampled_L_and_batch():
+    probs = [W.random_stable(40 + i, nx=4, nu=2, T=200, n=4, tf=2.0) for i in range(3)]
+    for p in probs:
+        ts = W.half_step_times(p.t, p.n)
+        p.L = probs[0].L[None] * (1.0 + 0.2 * np.cos(ts))[:, None, None] if np.ndim(probs[0].L) == 2 \
+            else probs[0].L
+    _, x2, u2 = _run(None, batch=probs)
+    for b, p in enumerate(probs):
+        ref = O.solve(p, method2=True)
+        assert relerr(_np(x2[b]), ref["x"]) < 1e-9, b
+        assert relerr(_np(u2[b]), ref["u"]) < 1e-9, b
+
+
+def test_fp32():
+    p = W.point_mass(2, 2 ** 12, 4, tf=10.0 * 2 ** 12 / 2 ** 16)
+    ref = O.solve(p, method2=True)
+    _, x2, _ = _run(p, torch.float32)
+    assert relerr(_np(x2[0]), ref["x"]) < 1e-4
+
+
+def test_large_state_is_unsupported():
+    p = W.random_stable(1, nx=6, nu=2, T=8, n=2)
+    dp = lqt.DeviceProblem.from_problems([p])
+    out = lqt.solve(dp, keep_elements=True)
+    with pytest.raises(lqt.LQTError) as ei:
+        lqt.forward_traj_method2(dp, out["elts"], out["S"], out["v"])
+    assert ei.value.status == lqt.LQT_EUNSUPPORTED
