@@ -32,6 +32,10 @@
 //                       applied to one block, which is the closed-loop block map of Method 1;
 //                       control from the LQT optimal control law (Sec. II-B).
 //   trajectory_method2- Method 2 of Sec. IV-E with prefix products a_0 x ... x a_{k-1}.
+//   dense_output      - values inside the blocks (Sec. VI-A, parallel method): S, v by RK4 on the
+//                       S, v ODEs of Sec. II-B backwards over each block from its right-end value;
+//                       x from the intermediate A, b, C of Theorem 9 combined with V(., tau) by
+//                       the Method 2 formula (Sec. IV-E); u by the control law (Sec. II-B).
 //   oracle_riccati    - the sequential baseline of Sec. VI-A: RK4 on the S, v ODEs of Sec. II-B
 //                       on a fine grid, then RK4 on the closed-loop state ODE.
 //   objective_*       - derivatives of sum_k <W_k, x_k> with respect to Q, R, r, x0, Qf, rf, by
@@ -169,6 +173,12 @@ Mat<S> scale(double s, const Mat<S>& x) {
     for (int j = 0; j < x.c; ++j) m(i, j) = S(s) * x(i, j);
   return m;
 }
+
+// y + a k
+template <class S>
+Mat<S> axpy_m(const Mat<S>& y, double a, const Mat<S>& k) {
+  return add(y, scale(a, k));
+}
 // Copy the upper triangle onto the lower one (the stored form of a symmetric matrix).
 template <class S>
 Mat<S> sym_upper(const Mat<S>& x) {
@@ -218,6 +228,7 @@ Mat<S> solve(Mat<S> M, Mat<S> B) {
 // Problem data converted to the scalar type.
 // ------------------------------------------------------------------------------------------
 }  // namespace oracle
+
 
 extern "C" {
 // Mirrors the Python-side ctypes structure.  Arrays are row-major doubles.
@@ -547,6 +558,81 @@ void store(const Mat<S>& m, double* dst) {
 
 using namespace oracle;
 
+// Values inside the blocks.  Node i = n k + m (m = 0..n-1) is t_k + m h_k, node nT is t_T.  Block
+// boundaries take the given values (S_k, v_k, x_k).  Inside block k:
+//  - S, v: classical RK4 of -h_k on dS/dt = -F^T S - S F - Q + S G S,
+//    dv/dt = -Q r - F^T v + S G v + S c (Sec. II-B) from (S_{k+1}, v_{k+1}), with F, G, c, r at
+//    the half-step samples (stage 1 at 2nk + 2(n - m'), stages 2 and 3 at - 1, stage 4 at - 2);
+//  - x at t_k + m h: the conditional value function on [t_k, t_k + m h] is the Theorem 9 state
+//    after m RK4 steps (A, b, C of element_forward's recursion); with V(., tau) = (S, v) at the node
+//    the minimiser is x = (I + C S)^{-1} (A x_k + b + C v) (Method 2 formula, Sec. IV-E);
+//  - u = -R^{-1} L(tau)^T (S x - v) with L at sample 2i.
+template <class S>
+void dense_output(const Prob<S>& p, const std::vector<Mat<S>>& Sb, const std::vector<Mat<S>>& vb,
+                  const std::vector<Mat<S>>& xb, std::vector<Mat<S>>& Sd,
+                  std::vector<Mat<S>>& vd, std::vector<Mat<S>>& xd, std::vector<Mat<S>>& ud) {
+  const int n = p.n;
+  const long T = p.T, nodes = (long)n * T + 1;
+  Sd.assign(nodes, Mat<S>());
+  vd.assign(nodes, Mat<S>());
+  xd.assign(nodes, Mat<S>());
+  ud.assign(nodes, Mat<S>());
+  Mat<S> I = eye<S>(p.nx);
+  auto dS = [&](long j, const Mat<S>& Sm) {
+    Mat<S> F = F_at(p, j), G = G_at(p, j);
+    return add(sub(sub(neg(mul(tr(F), Sm)), mul(Sm, F)), p.Q), mul(mul(Sm, G), Sm));
+  };
+  auto dv = [&](long j, const Mat<S>& Sm, const Mat<S>& vm) {
+    Mat<S> F = F_at(p, j), G = G_at(p, j), c = c_at(p, j), r = r_at(p, j);
+    return add(add(sub(neg(mul(p.Q, r)), mul(tr(F), vm)), mul(mul(Sm, G), vm)), mul(Sm, c));
+  };
+  for (long k = 0; k < T; ++k) {
+    const double h = (p.t[k + 1] - p.t[k]) / n;
+    Sd[(long)n * k] = Sb[k];
+    vd[(long)n * k] = vb[k];
+    // backward RK4 on S, v from the block's right end
+    Mat<S> Sm = Sb[k + 1], vm = vb[k + 1];
+    for (int mp = 0; mp < n - 1; ++mp) {
+      const long j1 = 2L * n * k + 2L * (n - mp);
+      Mat<S> kS1 = dS(j1, Sm), kv1 = dv(j1, Sm, vm);
+      Mat<S> S1 = axpy_m(Sm, -0.5 * h, kS1), v1 = axpy_m(vm, -0.5 * h, kv1);
+      Mat<S> kS2 = dS(j1 - 1, S1), kv2 = dv(j1 - 1, S1, v1);
+      Mat<S> S2 = axpy_m(Sm, -0.5 * h, kS2), v2 = axpy_m(vm, -0.5 * h, kv2);
+      Mat<S> kS3 = dS(j1 - 1, S2), kv3 = dv(j1 - 1, S2, v2);
+      Mat<S> S3 = axpy_m(Sm, -h, kS3), v3 = axpy_m(vm, -h, kv3);
+      Mat<S> kS4 = dS(j1 - 2, S3), kv4 = dv(j1 - 2, S3, v3);
+      Sm = sym_upper(axpy_m(Sm, -h / 6.0, add(add(kS1, scale(2.0, kS2)), add(scale(2.0, kS3), kS4))));
+      vm = axpy_m(vm, -h / 6.0, add(add(kv1, scale(2.0, kv2)), add(scale(2.0, kv3), kv4)));
+      Sd[(long)n * k + (n - mp - 1)] = Sm;
+      vd[(long)n * k + (n - mp - 1)] = vm;
+    }
+    // forward: Theorem 9 recursion from t_k, x by the Method 2 formula after each step
+    xd[(long)n * k] = xb[k];
+    Elem<S> y = identity_element<S>(p.nx);
+    for (int m = 0; m < n - 1; ++m) {
+      const long j0 = 2L * n * k + 2L * m;
+      Elem<S> k1 = thm3_rhs(p, j0, y);
+      Elem<S> k2 = thm3_rhs(p, j0 + 1, axpy(y, 0.5 * h, k1));
+      Elem<S> k3 = thm3_rhs(p, j0 + 1, axpy(y, 0.5 * h, k2));
+      Elem<S> k4 = thm3_rhs(p, j0 + 2, axpy(y, h, k3));
+      y = axpy(y, h / 6.0, axpy(axpy(axpy(k1, 2.0, k2), 2.0, k3), 1.0, k4));
+      y.C = sym_upper(y.C);
+      y.J = sym_upper(y.J);
+      const long i = (long)n * k + m + 1;
+      Mat<S> rhs = add(add(mul(y.A, xb[k]), y.b), mul(y.C, vd[i]));
+      xd[i] = solve(add(I, mul(y.C, Sd[i])), rhs);
+    }
+  }
+  Sd[nodes - 1] = Sb[T];
+  vd[nodes - 1] = vb[T];
+  xd[nodes - 1] = xb[T];
+  for (long i = 0; i < nodes; ++i) {
+    Mat<S> L = L_at(p, 2 * i);
+    Mat<S> g = sub(mul(Sd[i], xd[i]), vd[i]);
+    ud[i] = neg(solve(p.R, mul(tr(L), g)));
+  }
+}
+
 extern "C" {
 
 int oracle_abi_version(void) { return 1; }
@@ -646,6 +732,28 @@ int oracle_solve(const oracle_problem* prob, int method2, double* S, double* v, 
     if (v) store(V[k].eta, v + k * nx);
     if (x) store(xs[k], x + k * nx);
     if (u) store(us[k], u + k * nu);
+  }
+  return 0;
+}
+
+// Values inside the blocks (dense_output) from the block-boundary S [T+1][nx][nx], v, x [T+1][nx];
+// outputs at the nT+1 nodes: Sd [nT+1][nx][nx], vd, xd [nT+1][nx], ud [nT+1][nu].
+int oracle_dense(const oracle_problem* prob, const double* S, const double* v, const double* x,
+                 double* Sd, double* vd, double* xd, double* ud) {
+  Prob<double> p = load_problem<double>(prob, nullptr);
+  const int nx = p.nx, nu = p.nu;
+  std::vector<Mat<double>> Sb(p.T + 1), vb(p.T + 1), xb(p.T + 1), Sdv, vdv, xdv, udv;
+  for (long k = 0; k <= p.T; ++k) {
+    Sb[k] = load_mat<double>(S + k * nx * nx, nx, nx, nullptr);
+    vb[k] = load_mat<double>(v + k * nx, nx, 1, nullptr);
+    xb[k] = load_mat<double>(x + k * nx, nx, 1, nullptr);
+  }
+  dense_output(p, Sb, vb, xb, Sdv, vdv, xdv, udv);
+  for (size_t i = 0; i < Sdv.size(); ++i) {
+    store(Sdv[i], Sd + i * nx * nx);
+    store(vdv[i], vd + i * nx);
+    store(xdv[i], xd + i * nx);
+    store(udv[i], ud + i * nu);
   }
   return 0;
 }

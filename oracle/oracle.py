@@ -20,6 +20,7 @@ __all__ = [
     "value",
     "solve",
     "trajectory",
+    "dense",
     "riccati",
     "objective_jvp",
     "objective_grad",
@@ -163,6 +164,20 @@ def trajectory(prob, el, S, v):
     S, v = _f64(S), _f64(v)
     lib().oracle_trajectory(ctypes.byref(k.s), _ptr(A), _ptr(b), _ptr(C), _ptr(S), _ptr(v), _ptr(x), _ptr(u))
     return x, u
+
+
+def dense(prob, sol):
+    """Values inside the blocks at the nT+1 RK4 nodes t_k + m h_k (and t_T) from the block-boundary
+    solution `sol` (dict with S, v, x): dict of S, v, x, u."""
+    k = _Keep(prob)
+    nodes = prob.n * prob.T + 1
+    nx, nu = prob.nx, prob.nu
+    out = {"S": np.zeros((nodes, nx, nx)), "v": np.zeros((nodes, nx)), "x": np.zeros((nodes, nx)),
+           "u": np.zeros((nodes, nu))}
+    S, v, x = _f64(sol["S"]), _f64(sol["v"]), _f64(sol["x"])
+    lib().oracle_dense(ctypes.byref(k.s), _ptr(S), _ptr(v), _ptr(x),
+                       *[_ptr(out[n]) for n in ("S", "v", "x", "u")])
+    return out
 
 
 def riccati(F, L, Q, R, Qf, rf, x0, t0, tf, N, rfine, want_x=True):

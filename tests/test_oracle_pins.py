@@ -355,3 +355,47 @@ def test_sequential_adjoint_matches_jvp_and_differences():
         fd = (fp - fm) / (2 * h)
         tol = 1e-6 if name in ("Q", "R", "Qf") else 1e-9
         assert abs(fd - df) <= tol * max(1.0, abs(df)), name
+
+
+def test_dense_output_converges_to_riccati_at_fourth_order():
+    """Values inside the blocks (Sec. VI-A: S, v by RK4 on their ODEs over each block, x by the
+    intermediate Theorem 9 parts and the Method 2 formula) approach the fine-grid truth at the
+    order of RK4 when the number of steps per block doubles."""
+    T, tf = 8, 2.0
+    N = 16 * T * 2 * 4
+    p0 = W.point_mass(1, T, 8, tf=tf)
+    rfine = p0.ref(np.linspace(0.0, tf, 2 * N + 1))
+    S2, v2, x2 = O.riccati(p0.F, p0.L, p0.Q, p0.R, p0.Qf, p0.rf, p0.x0, 0.0, tf, N, rfine)
+    e = []
+    for n in (8, 16):
+        p = W.point_mass(1, T, n, tf=tf)
+        sol = O.solve(p)
+        d = O.dense(p, sol)
+        for k in ("S", "v", "x", "u"):  # block boundaries carry the scan's values unchanged
+            assert np.array_equal(d[k][::n], sol[k]), k
+        stride = N // (n * T)
+        e.append((relerr(d["S"], S2[::stride]), relerr(d["v"], v2[::stride]),
+                  relerr(d["x"], x2[::stride // 2])))
+    for i in range(3):
+        assert e[1][i] < 1e-6, e
+        assert 10.0 < e[0][i] / e[1][i] < 24.0, e
+
+
+def test_dense_S_matches_partial_backward_elements():
+    """Inside a block, V(., tau) is also the partial backward element on [tau, t_{k+1}] (Theorem 8
+    after m RK4 steps) folded with V(., t_{k+1}); both routes are RK4 approximations of the same
+    value function, so they agree to fourth order."""
+    gaps = []
+    for n in (6, 12):
+        p = W.random_stable(9, nx=3, nu=2, T=4, n=n, tf=2.0, time_varying=False)
+        sol = O.solve(p)
+        d = O.dense(p, sol)
+        k, mp = 2, n // 2  # tau = t_{k+1} - mp h
+        sub = W.Problem(p.nx, p.nu, 1, mp, np.array([p.t[k + 1] - mp * (p.t[k + 1] - p.t[k]) / n,
+                                                     p.t[k + 1]]), p.F, p.L, p.Q, p.R, p.Qf, p.rf,
+                        p.x0, p.r[2 * n * k + 2 * (n - mp):2 * n * (k + 1) + 1].copy(), None, None, None)
+        el = O.elements(sub)
+        S1, v1 = sol["S"][k + 1], sol["v"][k + 1]
+        S_tau, _ = O.value(el, S1, np.linalg.solve(S1, v1))
+        gaps.append(relerr(S_tau[0], d["S"][n * k + n - mp]))
+    assert gaps[1] < 1e-5 and 10.0 < gaps[0] / gaps[1] < 24.0, gaps
