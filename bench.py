@@ -160,6 +160,15 @@ def main(argv=None):
     # Elements from the forward conditional ODEs (Theorem 9) on the same problem.
     ms_fwd = _events_time(lambda: lqt.build_elements_forward(dp, out["elts"], ws_b),
                           max(3, args.steps // 2), torch)
+    # Values inside the blocks: S, v, x, u at the n T + 1 RK4 nodes from the boundary values.
+    nodes = n * T + 1
+    dense = {"S": torch.empty(1, nodes, 4, 4, dtype=dtype, device="cuda"),
+             "v": torch.empty(1, nodes, 4, dtype=dtype, device="cuda"),
+             "x": torch.empty(1, nodes, 4, dtype=dtype, device="cuda"),
+             "u": torch.empty(1, nodes, 2, dtype=dtype, device="cuda")}
+    ms_dense = _events_time(lambda: lqt.dense_output(dp, S, v, out["x"], dense, ws_b),
+                            max(3, args.steps // 2), torch)
+    del dense
 
     rec = {
         "metric": "sub-intervals/s for full LQT solve (value+trajectory) at nx=4",
@@ -182,7 +191,8 @@ def main(argv=None):
                      "flops_per_launch": flops, "launch_ms": ms_build,
                      "algorithmic_bytes_per_launch": build_bytes_per_block(4, n, es) * T},
         "stages_ms": {"build_elements": ms_build, "scan_value": ms_scan, "forward_traj": ms_traj,
-                      "build_elements_forward": ms_fwd, "forward_traj_method2": ms_m2},
+                      "build_elements_forward": ms_fwd, "forward_traj_method2": ms_m2,
+                      "dense_output": ms_dense},
     }
     if not args.no_lti:
         rec["lti"] = lti_leg(torch, lqt, p, dtype, args.steps, out, T)

@@ -169,6 +169,22 @@ lqt_status lqt_forward_traj_method2(const lqt_dims *dims, const lqt_problem *pro
                                     const void *elts, const void *S, const void *v, void *x,
                                     void *u, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Values inside the blocks (Sec. VI-A): S, v, x, u at the n T + 1 nodes t_k + m h_k (block k,
+ * 0 <= m < n_steps, node index n_steps k + m) and t_T (node n_steps T), from the block-boundary
+ * solution S, v, x (as written by lqt_scan_value and lqt_forward_traj, [batch][T+1][...]).  Node
+ * n_steps k takes S_k, v_k, x_k unchanged.  Inside block k, S and v come from classical RK4 on
+ * dS/dt = -F^T S - S F - Q + S G S and dv/dt = -Q r - F^T v + S G v + S c (Sec. II-B), n_steps - 1
+ * steps of -h_k from S_{k+1}, v_{k+1} (step mp: samples 2 n_steps k + 2(n_steps - mp) for stage
+ * 1, - 1 for stages 2 and 3, - 2 for stage 4); x from the forward parts A, b, C of Theorem 9 on
+ * [t_k, t_k + m h_k] (the RK4 steps of lqt_build_elements_forward) by the Method 2 formula
+ * x = (I + C S)^{-1} (A x_k + b + C v) (Sec. IV-E); u = -R^{-1} L^T (S x - v) with L at sample 2 x
+ * node.  Outputs (device, caller-allocated): Sd [batch][n T + 1][nx*nx] (full symmetric),
+ * vd and xd [batch][n T + 1][nx], ud [batch][n T + 1][nu] (may be NULL).  Reads prob->{t, F, L,
+ * c, Q, R, r}.  ws: LQT_CALL_BUILD bytes.  nx <= 4 (LQT_EUNSUPPORTED otherwise). */
+lqt_status lqt_dense_output(const lqt_dims *dims, const lqt_problem *prob, const void *S,
+                            const void *v, const void *x, void *Sd, void *vd, void *xd, void *ud,
+                            void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* All three stages in one call (the value kernel also forms level 1 of the trajectory tree, so
  * the elements are read once less; same results as the stage calls up to rounding).
  * elts may be NULL (then the elements live in the workspace); S, v, x must be non-NULL; u may be

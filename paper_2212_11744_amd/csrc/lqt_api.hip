@@ -393,6 +393,29 @@ lqt_status lqt_forward_traj_method2(const lqt_dims* dims, const lqt_problem* pro
   return ok();
 }
 
+lqt_status lqt_dense_output(const lqt_dims* dims, const lqt_problem* prob, const void* S,
+                            const void* v, const void* x, void* Sd, void* vd, void* xd, void* ud,
+                            void* ws, size_t ws_bytes, hipStream_t stream) {
+  LQT_TRY(check_supported(dims));
+  if (use_wave(dims)) return fail(LQT_EUNSUPPORTED, "values inside the blocks are available for nx <= 4");
+  LQT_TRY(check_problem(dims, prob, true, false));
+  const size_t es = dsize(dims->dtype);
+  LQT_TRY(check_ptr(S, "S", es));
+  LQT_TRY(check_ptr(v, "v", es));
+  LQT_TRY(check_ptr(x, "x", es));
+  LQT_TRY(check_ptr(Sd, "Sd", es));
+  LQT_TRY(check_ptr(vd, "vd", es));
+  LQT_TRY(check_ptr(xd, "xd", es));
+  if (ud) LQT_TRY(check_ptr(ud, "ud", es));
+  Work w;
+  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w));
+  KProb kp = make_kprob(dims, prob, w.consts);
+  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
+  LQT_HIP(o->prep(kp, w.consts, stream));
+  LQT_HIP(o->dense(kp, S, v, x, Sd, vd, xd, ud, stream));
+  return ok();
+}
+
 lqt_status lqt_scan_value(const lqt_dims* dims, const void* elts, const void* Qf, const void* rf,
                           void* S, void* v, void* ws, size_t ws_bytes, hipStream_t stream) {
   LQT_TRY(check_supported(dims));

@@ -147,6 +147,9 @@ struct Ops {
                         const void* st_par, long n_par, void* st_child, hipStream_t);
   hipError_t (*m2_bottom)(const KProb&, const void* elts, const void* S, const void* v,
                           const void* st1, long n1, void* x, void* u, hipStream_t);
+  // values inside the blocks at the n T + 1 RK4 nodes
+  hipError_t (*dense)(const KProb&, const void* S, const void* v, const void* x, void* Sd,
+                      void* vd, void* xd, void* ud, hipStream_t);
 };
 
 // Adjoint kernels (lqt_adjoint.hip) of one (nx, nu, dtype) instantiation.

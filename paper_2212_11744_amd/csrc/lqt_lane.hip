@@ -336,8 +336,17 @@ LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
 // right-hand side, so their RK4 increments are accumulated directly.  Samples: stage 1 at
 // 2 n k + 2 m, stages 2 and 3 at + 1, stage 4 at + 2.
 // ------------------------------------------------------------------------------------------
-template <int N, int NU, class R, bool CONST_COEF>
-LQT_DEV void build_block_fwd(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
+// fwd_parts takes `nsteps` RK4 steps and calls step(m, Ad, b, C) after step m, with the parts
+// on [t_k, t_k + (m + 1) h]; EJ = false leaves eta and J at zero (the state formula of Method 2
+// needs A, b, C only).
+struct NoStep {
+  template <class... X>
+  LQT_DEV void operator()(int, const X&...) const {}
+};
+
+template <int N, int NU, class R, bool CONST_COEF, bool EJ, class STEP>
+LQT_DEV void fwd_parts(const KProb& kp, const Blk& bk, int nsteps, Tup<N, R>& out,
+                       const STEP& step) {
   using Y = Sym<N>;
   constexpr int NS = Y::size;
   const int n = kp.n;
@@ -388,7 +397,7 @@ LQT_DEV void build_block_fwd(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
     yJ[i] = R(0);
   }
 #pragma unroll 1
-  for (int m = 0; m < n; ++m) {
+  for (int m = 0; m < nsteps; ++m) {
     const long j0 = 2L * n * k + 2L * m;  // sample at tau = t_k + m h
     R sA[N][N], sb[N], sC[NS], aA[N][N], ab[N], aC[NS];
 #pragma unroll
@@ -456,7 +465,7 @@ LQT_DEV void build_block_fwd(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
         }
       // eta and J increments from the stage value (accumulated directly):
       // w = Q (r - b), deta = w + Ad^T w;  P = Q (I + Ad), dJ = P + Ad^T P (upper)
-      {
+      if (EJ) {
         R w[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
@@ -552,6 +561,7 @@ LQT_DEV void build_block_fwd(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
     }
 #pragma unroll
     for (int i = 0; i < NS; ++i) yC[i] = aC[i];
+    step(m, yA, yb, yC);
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -573,7 +583,7 @@ __global__ __launch_bounds__(kThreads) void k_build_fwd(const KProb kp, R* __res
   const long k = gid();
   if (k >= kp.T) return;
   Tup<N, R> out;
-  build_block_fwd<N, NU, R, CONST_COEF>(kp, blk_plain(kp, p, k), out);
+  fwd_parts<N, NU, R, CONST_COEF, true>(kp, blk_plain(kp, p, k), kp.n, out, NoStep{});
   tup_store(out, elts + (long)p * Lay<N>::NE * padt(kp.T), k);
 }
 
@@ -981,8 +991,31 @@ LQT_DEV void control(const R (&Kc)[NU][N], const R (&S)[Sym<N>::size], const R (
   }
 }
 
-// Gain R^{-1} L(t_k)^T at boundary k of problem p (plain mode) or at boundary k of the
-// concatenated horizon (ragged mode; the owning problem is looked up).
+// Gain R^{-1} L^T of problem p with L at global sample index s (used when L is sampled).
+template <int N, int NU, class R>
+LQT_DEV void gain_sample(const KProb& kp, int p, long s, R (&Kc)[NU][N]) {
+  const R* cs = (const R*)kp.consts + (long)p * CS<N, NU>::size;
+  if (!kp.L_sampled) {
+#pragma unroll
+    for (int l = 0; l < NU; ++l)
+#pragma unroll
+      for (int j = 0; j < N; ++j) Kc[l][j] = cs[CS<N, NU>::Kc + l * N + j];
+  } else {
+    const R* Lk = (const R*)kp.L + s * N * NU;
+#pragma unroll
+    for (int l = 0; l < NU; ++l)
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        R a = R(0);
+#pragma unroll
+        for (int q = 0; q < NU; ++q) a = fma(cs[CS<N, NU>::Rinv + l * NU + q], Lk[j * NU + q], a);
+        Kc[l][j] = a;
+      }
+  }
+}
+
+// Gain at boundary k of problem p (plain mode) or at boundary k of the concatenated horizon
+// (ragged mode; the owning problem is looked up).
 template <int N, int NU, class R>
 LQT_DEV void gain_at(const KProb& kp, int p, long k, R (&Kc)[NU][N]) {
   long s0;
@@ -992,24 +1025,7 @@ LQT_DEV void gain_at(const KProb& kp, int p, long k, R (&Kc)[NU][N]) {
   } else {
     s0 = (long)p * (2L * kp.n * kp.T + 1);
   }
-  const R* cs = (const R*)kp.consts + (long)p * CS<N, NU>::size;
-  if (!kp.L_sampled) {
-#pragma unroll
-    for (int l = 0; l < NU; ++l)
-#pragma unroll
-      for (int j = 0; j < N; ++j) Kc[l][j] = cs[CS<N, NU>::Kc + l * N + j];
-  } else {
-    const R* Lk = (const R*)kp.L + (s0 + 2L * kp.n * k) * N * NU;
-#pragma unroll
-    for (int l = 0; l < NU; ++l)
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        R s = R(0);
-#pragma unroll
-        for (int q = 0; q < NU; ++q) s = fma(cs[CS<N, NU>::Rinv + l * NU + q], Lk[j * NU + q], s);
-        Kc[l][j] = s;
-      }
-  }
+  gain_sample<N, NU, R>(kp, p, s0 + 2L * kp.n * k, Kc);
 }
 
 template <int N, int NU, class R>
@@ -1380,6 +1396,265 @@ __global__ __launch_bounds__(kThreads) void k_m2_bottom(const KProb kp, const R*
 }
 
 // ------------------------------------------------------------------------------------------
+// Values inside the blocks (Sec. VI-A).  At the nodes t_k + m h (m = 1 .. n - 1) of block k:
+//   S, v by classical RK4 on their backward ODEs (Sec. II-B) from the right-end values
+//     dS/dt = -F^T S - S F - Q + S G S,  dv/dt = -Q r - F^T v + S G v + S c,
+//   x by the Method 2 formula (Sec. IV-E) with the forward parts A, b, C of Theorem 9 on
+//     [t_k, t_k + m h]:  x = (I + C S)^{-1} (A x_k + b + C v),
+//   u by the control law at the node's sample.  Node n k carries the block-boundary values and
+//   node n T those at t_T.  One lane per block; the forward sweep reads back the S, v that the
+//   same lane stored in the backward sweep.
+// ------------------------------------------------------------------------------------------
+template <int N, int NU, class R, bool CONST_COEF>
+__global__ __launch_bounds__(kThreads) void k_dense(const KProb kp, const R* __restrict__ Sg,
+                                                     const R* __restrict__ vg,
+                                                     const R* __restrict__ xg, R* __restrict__ Sd,
+                                                     R* __restrict__ vd, R* __restrict__ xd,
+                                                     R* __restrict__ ud) {
+  using Y = Sym<N>;
+  constexpr int NS = Y::size;
+  const int p = blockIdx.y;
+  const long k = gid();
+  if (k >= kp.T) return;
+  const int n = kp.n;
+  const long T = kp.T;
+  const long nodes = (long)n * T + 1;
+  const Blk bk = blk_plain(kp, p, k);
+  const R* Sp = Sg + (long)p * (T + 1) * N * N;
+  const R* vp = vg + (long)p * (T + 1) * N;
+  const R* xp = xg + (long)p * (T + 1) * N;
+  R* Sdp = Sd + (long)p * nodes * N * N;
+  R* vdp = vd + (long)p * nodes * N;
+  R* xdp = xd + (long)p * nodes * N;
+  R* udp = ud ? ud + (long)p * nodes * NU : nullptr;
+  const R* __restrict__ t = (const R*)kp.t + bk.tk;
+  const R* __restrict__ Fc = (const R*)kp.F;
+  const R* __restrict__ Qp = (const R*)kp.Q + p * N * N;
+  const R* __restrict__ cs = (const R*)kp.consts + p * CS<N, NU>::size;
+  const R h = (t[1] - t[0]) / R(n);
+  R Kc[NU][N];
+  if (!kp.L_sampled) gain_sample<N, NU, R>(kp, p, 0, Kc);
+  auto emit_u = [&](long node, const R (&S)[NS], const R (&v)[N], const R (&x)[N]) {
+    if (!udp) return;
+    if (kp.L_sampled) gain_sample<N, NU, R>(kp, p, bk.s0 + 2 * node, Kc);
+    control<N, NU, R>(Kc, S, v, x, udp + node * NU);
+  };
+
+  // ---- backward sweep: S, v at nodes n k + n - 1 down to n k + 1 ----
+  {
+    R Q[NS];
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+#pragma unroll
+      for (int j = i; j < N; ++j) Q[Y::at(i, j)] = Qp[i * N + j];
+    R F[N][N], G[NS], cv[N];
+    if (CONST_COEF) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          F[i][j] = Fc[i * N + j];
+          if (j >= i) G[Y::at(i, j)] = cs[CS<N, NU>::G + i * N + j];
+        }
+        cv[i] = R(0);
+      }
+    }
+    R Wr[NU][NU];
+    if (!CONST_COEF) {
+#pragma unroll
+      for (int i = 0; i < NU; ++i)
+#pragma unroll
+        for (int j = 0; j < NU; ++j) Wr[i][j] = cs[CS<N, NU>::W + i * NU + j];
+    }
+    R S[NS], v[N];
+    S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = vp[(k + 1) * N + i];
+#pragma unroll 1
+    for (int mp = 0; mp < n - 1; ++mp) {
+      const long j1 = 2L * n * k + 2L * (n - mp);  // sample at t = t_{k+1} - mp h
+      R sS[NS], sv[N], aS[NS], av[N];
+#pragma unroll
+      for (int i = 0; i < NS; ++i) sS[i] = S[i];
+#pragma unroll
+      for (int i = 0; i < N; ++i) sv[i] = v[i];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const long j = st == 0 ? j1 : (st == 3 ? j1 - 2 : j1 - 1);
+        const R wk = (st == 0 || st == 3) ? h / R(6) : h / R(3);
+        const R cn = st == 2 ? h : h / R(2);
+        R rv[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) rv[i] = ((const R*)kp.r)[(bk.s0 + j) * N + i];
+        if (!CONST_COEF) {
+          const R* Fj = kp.F_sampled ? (const R*)kp.F + (bk.s0 + j) * N * N : Fc;
+#pragma unroll
+          for (int i = 0; i < N; ++i)
+#pragma unroll
+            for (int q = 0; q < N; ++q) F[i][q] = Fj[i * N + q];
+          if (kp.L_sampled) {
+            const R* Lj = (const R*)kp.L + (bk.s0 + j) * N * NU;
+            R Lc[N][NU];
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+#pragma unroll
+              for (int l = 0; l < NU; ++l) {
+                R a = R(0);
+#pragma unroll
+                for (int q = 0; q < NU; ++q) a = fma(Lj[i * NU + q], Wr[q][l], a);
+                Lc[i][l] = a;
+              }
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+#pragma unroll
+              for (int q = i; q < N; ++q) {
+                R a = R(0);
+#pragma unroll
+                for (int l = 0; l < NU; ++l) a = fma(Lc[i][l], Lc[q][l], a);
+                G[Y::at(i, q)] = a;
+              }
+          } else {
+#pragma unroll
+            for (int i = 0; i < N; ++i)
+#pragma unroll
+              for (int q = i; q < N; ++q) G[Y::at(i, q)] = cs[CS<N, NU>::G + i * N + q];
+          }
+#pragma unroll
+          for (int i = 0; i < N; ++i)
+            cv[i] = kp.has_c ? ((const R*)kp.c)[(bk.s0 + j) * N + i] : R(0);
+        }
+        // P = S G;  kS (upper) = -F^T S - S F - Q + P S;  kv = -Q r - F^T v + P v + S c
+        R P[N][N];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int q = 0; q < N; ++q) {
+            R a = R(0);
+#pragma unroll
+            for (int l = 0; l < N; ++l) a = fma(sS[Y::at(i, l)], G[Y::at(l, q)], a);
+            P[i][q] = a;
+          }
+        R kS[NS], kv[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+#pragma unroll
+          for (int q = i; q < N; ++q) {
+            R a = -Q[Y::at(i, q)];
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+              a = fma(-F[l][i], sS[Y::at(l, q)], a);
+              a = fma(-sS[Y::at(i, l)], F[l][q], a);
+              a = fma(P[i][l], sS[Y::at(l, q)], a);
+            }
+            kS[Y::at(i, q)] = a;
+          }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          R a = R(0);
+#pragma unroll
+          for (int l = 0; l < N; ++l) {
+            a = fma(-Q[Y::at(i, l)], rv[l], a);
+            a = fma(-F[l][i], sv[l], a);
+            a = fma(P[i][l], sv[l], a);
+            a = fma(sS[Y::at(i, l)], cv[l], a);
+          }
+          kv[i] = a;
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+          aS[i] = st == 0 ? fma(-wk, kS[i], S[i]) : fma(-wk, kS[i], aS[i]);
+          if (st < 3) sS[i] = fma(-cn, kS[i], S[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+          av[i] = st == 0 ? fma(-wk, kv[i], v[i]) : fma(-wk, kv[i], av[i]);
+          if (st < 3) sv[i] = fma(-cn, kv[i], v[i]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < NS; ++i) S[i] = aS[i];
+      const long node = (long)n * k + (n - mp - 1);
+      S_store_full<N, R>(S, Sdp + node * N * N);
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        v[i] = av[i];
+        vdp[node * N + i] = v[i];
+      }
+    }
+  }
+
+  // ---- block-boundary nodes ----
+  R xk[N];
+  {
+    R S[NS], v[N];
+    S_load_upper<N, R>(S, Sp + k * N * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      v[i] = vp[k * N + i];
+      xk[i] = xp[k * N + i];
+    }
+    const long node = (long)n * k;
+    S_store_full<N, R>(S, Sdp + node * N * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      vdp[node * N + i] = v[i];
+      xdp[node * N + i] = xk[i];
+    }
+    emit_u(node, S, v, xk);
+  }
+  if (k == T - 1) {
+    R S[NS], v[N], x[N];
+    S_load_upper<N, R>(S, Sp + T * N * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      v[i] = vp[T * N + i];
+      x[i] = xp[T * N + i];
+    }
+    const long node = (long)n * T;
+    S_store_full<N, R>(S, Sdp + node * N * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      vdp[node * N + i] = v[i];
+      xdp[node * N + i] = x[i];
+    }
+    emit_u(node, S, v, x);
+  }
+
+  // ---- forward sweep: Theorem 9 parts, x and u at nodes n k + 1 .. n k + n - 1 ----
+  auto step = [&](int m, const R (&Ad)[N][N], const R (&b)[N], const R (&C)[NS]) {
+    const long node = (long)n * k + m + 1;
+    R S[NS], v[N], M[N][N], B[N][1];
+    S_load_upper<N, R>(S, Sdp + node * N * N);
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = vdp[node * N + i];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      R g = xk[a] + b[a];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        g = fma(Ad[a][q], xk[q], g);
+        g = fma(C[Y::at(a, q)], v[q], g);
+        R s = R(0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(C[Y::at(a, l)], S[Y::at(l, q)], s);
+        M[a][q] = (a == q) ? R(1) + s : s;
+      }
+      B[a][0] = g;
+    }
+    gj_solve<N, 1>(M, B);
+    R x[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      x[i] = B[i][0];
+      xdp[node * N + i] = x[i];
+    }
+    emit_u(node, S, v, x);
+  };
+  Tup<N, R> parts;
+  fwd_parts<N, NU, R, CONST_COEF, false>(kp, bk, n - 1, parts, step);
+}
+
+// ------------------------------------------------------------------------------------------
 // Launchers.
 // ------------------------------------------------------------------------------------------
 inline dim3 grid_lanes(long n, int batch) {
@@ -1511,6 +1786,19 @@ struct L {
                          dim3(kThreads), 0, s, kp, (R*)elts);
     return hipGetLastError();
   }
+  static hipError_t dense(const KProb& kp, const void* S, const void* v, const void* x, void* Sd,
+                          void* vd, void* xd, void* ud, hipStream_t s) {
+    const bool cc = !kp.F_sampled && !kp.L_sampled && !kp.has_c;
+    if (cc)
+      hipLaunchKernelGGL((k_dense<N, NU, R, true>), grid_lanes(kp.T, kp.batch), dim3(kThreads), 0,
+                         s, kp, (const R*)S, (const R*)v, (const R*)x, (R*)Sd, (R*)vd, (R*)xd,
+                         (R*)ud);
+    else
+      hipLaunchKernelGGL((k_dense<N, NU, R, false>), grid_lanes(kp.T, kp.batch), dim3(kThreads),
+                         0, s, kp, (const R*)S, (const R*)v, (const R*)x, (R*)Sd, (R*)vd, (R*)xd,
+                         (R*)ud);
+    return hipGetLastError();
+  }
   static hipError_t lti_prep(const KProb& kp, void* tab, hipStream_t s) {
     hipLaunchKernelGGL((k_lti_prep<N, NU, R>), grid_lanes((2L * kp.n + 1) * N, kp.batch),
                        dim3(kThreads), 0, s, kp, (R*)tab);
@@ -1525,7 +1813,8 @@ struct L {
     static const Ops o = {prep,    build,          build_reduce, vreduce0, vup,    vtop,
                           vdown,   vbottom,        tbottom_reduce, tup,    ttop,   tdown,
                           tbottom, lti_prep,       lti_build,    build_fwd,
-                          m2_up,   m2_top,         m2_down,      m2_bottom};
+                          m2_up,   m2_top,         m2_down,      m2_bottom,
+                          dense};
     return &o;
   }
 };

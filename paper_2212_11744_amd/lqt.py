@@ -78,10 +78,12 @@ def lib():
         L.lqt_scan_value.argtypes = [P(Dims), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_forward_traj.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_forward_traj_method2.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
+        L.lqt_dense_output.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_solve.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_backward.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, st]
         for f in ("lqt_build_elements", "lqt_build_elements_forward", "lqt_scan_value",
-                  "lqt_forward_traj", "lqt_forward_traj_method2", "lqt_solve", "lqt_backward"):
+                  "lqt_forward_traj", "lqt_forward_traj_method2", "lqt_dense_output", "lqt_solve",
+                  "lqt_backward"):
             getattr(L, f).restype = ctypes.c_int
         L.lqt_batched_workspace_size.argtypes = [P(Ragged), ctypes.c_int32]
         L.lqt_batched_workspace_size.restype = sz
@@ -278,6 +280,24 @@ def forward_traj_method2(prob: DeviceProblem, elts, S, v, x=None, u=None, ws=Non
                                           _ptr(v), _ptr(x), _ptr(u), _ptr(ws), ws.numel(),
                                           _stream()))
     return x, u
+
+
+def dense_output(prob: DeviceProblem, S, v, x, out: Optional[dict] = None, ws=None, want_u=True):
+    """S, v, x, u at the n T + 1 RK4 nodes inside the blocks from the block-boundary S, v, x.
+    Returns dict with S [batch][nT+1][nx][nx], v, x [batch][nT+1][nx], u [batch][nT+1][nu]."""
+    nodes = prob.n * prob.T + 1
+    if out is None:
+        out = {"S": _empty(prob, prob.batch, nodes, prob.nx, prob.nx),
+               "v": _empty(prob, prob.batch, nodes, prob.nx),
+               "x": _empty(prob, prob.batch, nodes, prob.nx)}
+        if want_u:
+            out["u"] = _empty(prob, prob.batch, nodes, prob.nu)
+    ws = workspace(prob, CALL_BUILD) if ws is None else ws
+    d, p = prob.dims(), prob.ptrs()
+    _check(lib().lqt_dense_output(ctypes.byref(d), ctypes.byref(p), _ptr(S), _ptr(v), _ptr(x),
+                                  _ptr(out["S"]), _ptr(out["v"]), _ptr(out["x"]), _ptr(out.get("u")),
+                                  _ptr(ws), ws.numel(), _stream()))
+    return out
 
 
 def solve(prob: DeviceProblem, out: Optional[dict] = None, ws=None, keep_elements=False):
