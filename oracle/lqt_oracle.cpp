@@ -24,6 +24,8 @@
 //                       values of a zero-length interval, RK4 in s from t_{k+1} down to t_k.
 //   element_forward   - Theorem 9 (Sec. IV-C, forward conditional LQT ODEs), RK4 in tau from t_k
 //                       up to t_{k+1}.
+//   element_split     - the block split in two (Sec. IV-D): Theorem 9 over the first floor(n/2)
+//                       steps, Theorem 8 over the remaining ones, joined by Lemma 7.
 //   combine           - Lemma 7 (Sec. IV-A, combination rule of LQT conditional value functions).
 //   value_functions   - Theorem 6 (Sec. III-D; suffix products a_k x ... x a_T) with the terminal
 //                       element of Sec. IV-D, folded sequentially from the right.
@@ -393,13 +395,14 @@ Elem<S> thm2_rhs(const Prob<S>& p, long j, const Elem<S>& y) {
 
 // Element a_k = V(., t_k; ., t_{k+1}): integrate Theorem 8 in s from s = t_{k+1} (zero-length
 // boundary values) down to s = t_k with n classical RK4 steps of -h.  C and J are symmetrised
-// (upper triangle kept) after every step.
+// (upper triangle kept) after every step.  With steps < n it stops at s = t_{k+1} - steps h and
+// returns V(., t_{k+1} - steps h; ., t_{k+1}).
 template <class S>
-Elem<S> element_backward(const Prob<S>& p, long k) {
+Elem<S> element_backward(const Prob<S>& p, long k, int steps) {
   const int n = p.n;
   const double h = (p.t[k + 1] - p.t[k]) / n;
   Elem<S> y = identity_element<S>(p.nx);
-  for (int m = 0; m < n; ++m) {
+  for (int m = 0; m < steps; ++m) {
     const long j0 = 2L * n * k + 2L * (n - m);  // sample at s = t_{k+1} - m h
     Elem<S> k1 = thm2_rhs(p, j0, y);
     Elem<S> k2 = thm2_rhs(p, j0 - 1, axpy(y, -0.5 * h, k1));
@@ -428,13 +431,14 @@ Elem<S> thm3_rhs(const Prob<S>& p, long j, const Elem<S>& y) {
 }
 
 // Element a_k from Theorem 9: integrate in tau from tau = t_k (zero-length boundary values) up to
-// t_{k+1} with n classical RK4 steps of +h.
+// t_{k+1} with n classical RK4 steps of +h.  With steps < n it stops at tau = t_k + steps h and
+// returns V(., t_k; ., t_k + steps h).
 template <class S>
-Elem<S> element_forward(const Prob<S>& p, long k) {
+Elem<S> element_forward(const Prob<S>& p, long k, int steps) {
   const int n = p.n;
   const double h = (p.t[k + 1] - p.t[k]) / n;
   Elem<S> y = identity_element<S>(p.nx);
-  for (int m = 0; m < n; ++m) {
+  for (int m = 0; m < steps; ++m) {
     const long j0 = 2L * n * k + 2L * m;  // sample at tau = t_k + m h
     Elem<S> k1 = thm3_rhs(p, j0, y);
     Elem<S> k2 = thm3_rhs(p, j0 + 1, axpy(y, 0.5 * h, k1));
@@ -476,10 +480,27 @@ Elem<S> terminal_element(const Prob<S>& p) {
   return e;
 }
 
+// Element a_k with the block split at tau = t_k + floor(n/2) h (Sec. IV-D): the forward ODEs of
+// Theorem 9 give V(., t_k; ., tau), the backward ODEs of Theorem 8 give V(., tau; ., t_{k+1}),
+// and Lemma 7 joins them.
 template <class S>
-std::vector<Elem<S>> elements(const Prob<S>& p, bool forward = false) {
+Elem<S> element_split(const Prob<S>& p, long k) {
+  const int m = p.n / 2;
+  return combine(element_forward(p, k, m), element_backward(p, k, p.n - m));
+}
+
+// mode 0: Theorem 8, 1: Theorem 9, 2: split block.
+template <class S>
+Elem<S> element(const Prob<S>& p, long k, int mode) {
+  if (mode == 1) return element_forward(p, k, p.n);
+  if (mode == 2) return element_split(p, k);
+  return element_backward(p, k, p.n);
+}
+
+template <class S>
+std::vector<Elem<S>> elements(const Prob<S>& p, int mode = 0) {
   std::vector<Elem<S>> a(p.T);
-  for (long k = 0; k < p.T; ++k) a[k] = forward ? element_forward(p, k) : element_backward(p, k);
+  for (long k = 0; k < p.T; ++k) a[k] = element(p, k, mode);
   return a;
 }
 
@@ -637,14 +658,14 @@ extern "C" {
 
 int oracle_abi_version(void) { return 1; }
 
-// Elements a_0..a_{T-1} (Theorem 8, or Theorem 9 if forward != 0).  Outputs, plain matrices:
-// A, C, J [T][nx][nx]; b, eta [T][nx].
-int oracle_elements(const oracle_problem* prob, int forward, double* A, double* b, double* C,
+// Elements a_0..a_{T-1} (mode 0: Theorem 8, 1: Theorem 9, 2: split block).  Outputs, plain
+// matrices: A, C, J [T][nx][nx]; b, eta [T][nx].
+int oracle_elements(const oracle_problem* prob, int mode, double* A, double* b, double* C,
                     double* eta, double* J) {
   Prob<double> p = load_problem<double>(prob, nullptr);
   const int nx = p.nx;
   for (long k = 0; k < p.T; ++k) {
-    Elem<double> e = forward ? element_forward(p, k) : element_backward(p, k);
+    Elem<double> e = element(p, k, mode);
     store(e.A, A + k * nx * nx);
     store(e.b, b + k * nx);
     store(e.C, C + k * nx * nx);

@@ -103,13 +103,16 @@ class _Keep:
         )
 
 
-def elements(prob, forward: bool = False):
-    """Elements a_0..a_{T-1}: dict of A, C, J (T, nx, nx) and b, eta (T, nx)."""
+def elements(prob, forward: bool = False, split: bool = False):
+    """Elements a_0..a_{T-1}: dict of A, C, J (T, nx, nx) and b, eta (T, nx).  Theorem 8 by
+    default, Theorem 9 with forward=True, the split block (Theorem 9 on the first floor(n/2) steps,
+    Theorem 8 on the rest, joined by Lemma 7) with split=True."""
     k = _Keep(prob)
     T, nx = prob.T, prob.nx
     out = {"A": np.zeros((T, nx, nx)), "b": np.zeros((T, nx)), "C": np.zeros((T, nx, nx)),
            "eta": np.zeros((T, nx)), "J": np.zeros((T, nx, nx))}
-    lib().oracle_elements(ctypes.byref(k.s), int(forward), *[_ptr(out[n]) for n in ("A", "b", "C", "eta", "J")])
+    mode = 2 if split else int(forward)
+    lib().oracle_elements(ctypes.byref(k.s), mode, *[_ptr(out[n]) for n in ("A", "b", "C", "eta", "J")])
     return out
 
 

@@ -154,13 +154,12 @@ def _closed_form_element(F, L, Q, R, r, c, delta):
     return A, b, C, eta, J
 
 
-@pytest.mark.parametrize("forward", [False, True])
-def test_element_closed_form_and_fourth_order(forward):
-    rng = np.random.default_rng(11)
+@pytest.mark.parametrize("mode", ["backward", "forward", "split"])
+def test_element_closed_form_and_fourth_order(mode):
     errs = []
     for n in (10, 20, 40):
         prob, r, c = _lti_problem(np.random.default_rng(11), n=n)
-        el = O.elements(prob, forward=forward)
+        el = O.elements(prob, forward=mode == "forward", split=mode == "split")
         ref = _closed_form_element(prob.F, prob.L, prob.Q, prob.R, r, c, 0.7)
         errs.append(max(relerr(el[k][0], v) for k, v in zip(("A", "b", "C", "eta", "J"), ref)))
     assert errs[-1] < 1e-6
@@ -177,6 +176,25 @@ def test_backward_and_forward_elements_agree():
         gaps.append(max(relerr(eb[k], ef[k]) for k in ("A", "b", "C", "eta", "J")))
     # Both are fourth-order approximations of the same tuple: their gap shrinks ~16x per halving.
     assert gaps[1] < 5e-5 and 12.0 < gaps[0] / gaps[1] < 20.0
+
+
+def test_split_block_element():
+    """The block split in two (Sec. IV-D: forward ODEs on the first part, backward ODEs on the
+    second, joined by Lemma 7).  With one RK4 step the forward part is empty and the split
+    element is the Theorem 8 element bit for bit; otherwise it approximates the same tuple as
+    Theorem 8 to fourth order, also with odd step counts and time-varying F, L and drift."""
+    p1 = W.random_stable(4, nx=3, nu=2, T=5, n=1, tf=1.0)
+    eb, es = O.elements(p1), O.elements(p1, split=True)
+    for k in ("A", "b", "C", "eta", "J"):
+        assert np.array_equal(eb[k], es[k]), k
+    gaps = []
+    for n in (5, 10, 20):
+        p = W.random_stable(4, nx=3, nu=2, T=5, n=n, tf=2.0)
+        p.c = 0.2 * np.cos(np.linspace(0, 2, p.r.shape[0]))[:, None] * np.ones(3)[None, :]
+        eb, es = O.elements(p), O.elements(p, split=True)
+        gaps.append(max(relerr(eb[k], es[k]) for k in ("A", "b", "C", "eta", "J")))
+    assert gaps[-1] < 1e-6
+    assert 10.0 < gaps[1] / gaps[2] < 24.0, gaps
 
 
 def test_elements_symmetric_psd():
