@@ -160,6 +160,9 @@ def main(argv=None):
     # Elements from the forward conditional ODEs (Theorem 9) on the same problem.
     ms_fwd = _events_time(lambda: lqt.build_elements_forward(dp, out["elts"], ws_b),
                           max(3, args.steps // 2), torch)
+    # Elements with every block split (Theorem 9 on the first half, Theorem 8 on the second).
+    ms_split = _events_time(lambda: lqt.build_elements_split(dp, out["elts"], ws_b),
+                            max(3, args.steps // 2), torch)
     # Values inside the blocks: S, v, x, u at the n T + 1 RK4 nodes from the boundary values.
     nodes = n * T + 1
     dense = {"S": torch.empty(1, nodes, 4, 4, dtype=dtype, device="cuda"),
@@ -192,7 +195,7 @@ def main(argv=None):
                      "algorithmic_bytes_per_launch": build_bytes_per_block(4, n, es) * T},
         "stages_ms": {"build_elements": ms_build, "scan_value": ms_scan, "forward_traj": ms_traj,
                       "build_elements_forward": ms_fwd, "forward_traj_method2": ms_m2,
-                      "dense_output": ms_dense},
+                      "build_elements_split": ms_split, "dense_output": ms_dense},
     }
     if not args.no_lti:
         rec["lti"] = lti_leg(torch, lqt, p, dtype, args.steps, out, T)

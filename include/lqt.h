@@ -145,6 +145,18 @@ lqt_status lqt_build_elements(const lqt_dims *dims, const lqt_problem *prob, voi
 lqt_status lqt_build_elements_forward(const lqt_dims *dims, const lqt_problem *prob, void *elts,
                                       void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* The same elements with every block split in two (Sec. IV-D): with m = floor(n_steps / 2), the
+ * forward ODEs of Theorem 9 over the first m RK4 steps give V(., t_k; ., tau), tau = t_k + m h_k
+ * (the steps of lqt_build_elements_forward), the backward ODEs of Theorem 8 over the last
+ * n_steps - m steps give V(., tau; ., t_{k+1}) (the steps of lqt_build_elements), and Lemma 7
+ * joins them.  The two parts of a block are integrated at the same time by two wavefronts, so the
+ * span of the build is about halved (useful when T is small).  Agrees with lqt_build_elements to
+ * the order of RK4; equal up to rounding for n_steps = 1.  Same arguments and layout as
+ * lqt_build_elements (workspace LQT_CALL_BUILD; lqt_dims.lti ignored); nx <= 4
+ * (LQT_EUNSUPPORTED otherwise). */
+lqt_status lqt_build_elements_split(const lqt_dims *dims, const lqt_problem *prob, void *elts,
+                                    void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Value functions (Theorem 6 with the terminal element A = b = C = 0, eta = Qf rf, J = Qf):
  * S [batch][T+1][nx*nx] (full symmetric) and v [batch][T+1][nx], V(x, t_k) = 1/2 x^T S_k x -
  * v_k^T x + const.  elts: as written by lqt_build_elements (any producer of the same layout). */

@@ -361,6 +361,21 @@ lqt_status lqt_build_elements_forward(const lqt_dims* dims, const lqt_problem* p
   return ok();
 }
 
+lqt_status lqt_build_elements_split(const lqt_dims* dims, const lqt_problem* prob, void* elts,
+                                    void* ws, size_t ws_bytes, hipStream_t stream) {
+  LQT_TRY(check_supported(dims));
+  if (use_wave(dims))
+    return fail(LQT_EUNSUPPORTED, "the split-block element build is available for nx <= 4");
+  LQT_TRY(check_problem(dims, prob, true, false));
+  LQT_TRY(check_ptr(elts, "elts", dsize(dims->dtype)));
+  Work w;
+  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w));
+  KProb kp = make_kprob(dims, prob, w.consts);
+  LQT_HIP(prep(dims, kp, w.consts, stream));
+  LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build_split(kp, elts, stream));
+  return ok();
+}
+
 lqt_status lqt_forward_traj_method2(const lqt_dims* dims, const lqt_problem* prob,
                                     const void* elts, const void* S, const void* v, void* x,
                                     void* u, void* ws, size_t ws_bytes, hipStream_t stream) {

@@ -150,6 +150,8 @@ struct Ops {
   // values inside the blocks at the n T + 1 RK4 nodes
   hipError_t (*dense)(const KProb&, const void* S, const void* v, const void* x, void* Sd,
                       void* vd, void* xd, void* ud, hipStream_t);
+  // elements with every block split: Theorem 9 on the first half, Theorem 8 on the second
+  hipError_t (*build_split)(const KProb&, void* elts, hipStream_t);
 };
 
 // Adjoint kernels (lqt_adjoint.hip) of one (nx, nu, dtype) instantiation.

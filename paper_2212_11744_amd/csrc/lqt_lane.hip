@@ -76,8 +76,10 @@ struct RImpulse {
   LQT_DEV R operator()(long j, int i) const { return j == j0 && i == i0 ? R(1) : R(0); }
 };
 
+// nsteps < n stops at s = t_{k+1} - nsteps h: the tuple of V(., t_{k+1} - nsteps h; ., t_{k+1}).
 template <int N, int NU, class R, bool CONST_COEF, class RS>
-LQT_DEV void build_block_rs(const KProb& kp, const Blk& bk, const RS& rs, Tup<N, R>& out) {
+LQT_DEV void build_block_rs(const KProb& kp, const Blk& bk, const RS& rs, Tup<N, R>& out,
+                            int nsteps) {
   using Y = Sym<N>;
   constexpr int NS = Y::size;
   const int n = kp.n;
@@ -135,7 +137,7 @@ LQT_DEV void build_block_rs(const KProb& kp, const Blk& bk, const RS& rs, Tup<N,
   }
 
 #pragma unroll 1
-  for (int m = 0; m < n; ++m) {
+  for (int m = 0; m < nsteps; ++m) {
     const long j1 = 2L * n * k + 2L * (n - m);  // sample at s = t_{k+1} - m h
     R sA[N][N], se[N], sJ[NS], aA[N][N], ae[N], aJ[NS];
 #pragma unroll
@@ -323,7 +325,7 @@ LQT_DEV void build_block_rs(const KProb& kp, const Blk& bk, const RS& rs, Tup<N,
 
 template <int N, int NU, class R, bool CONST_COEF>
 LQT_DEV void build_block(const KProb& kp, const Blk& bk, Tup<N, R>& out) {
-  build_block_rs<N, NU, R, CONST_COEF>(kp, bk, RMem<N, R>{(const R*)kp.r}, out);
+  build_block_rs<N, NU, R, CONST_COEF>(kp, bk, RMem<N, R>{(const R*)kp.r}, out, kp.n);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -588,6 +590,73 @@ __global__ __launch_bounds__(kThreads) void k_build_fwd(const KProb kp, R* __res
 }
 
 // ------------------------------------------------------------------------------------------
+// Element build with each block split at tau = t_k + floor(n/2) h (Sec. IV-D): the forward ODEs
+// of Theorem 9 give V(., t_k; ., tau) and the backward ODEs of Theorem 8 give
+// V(., tau; ., t_{k+1}); Lemma 7 joins them.  A workgroup is two wavefronts over the same 64
+// blocks: wave 0 integrates the first parts, wave 1 the second parts at the same time, and passes
+// them through LDS (one 64-wide row per tuple value) to wave 0, which combines and stores.  The
+// span of a block's build is about halved; the total work grows by one combination per block.
+// ------------------------------------------------------------------------------------------
+constexpr int kSplitThreads = 2 * kThreads;
+
+template <int N, int NU, class R, bool CONST_COEF>
+__global__ __launch_bounds__(kSplitThreads) void k_build_split(const KProb kp,
+                                                                R* __restrict__ elts) {
+  using Lq = Lay<N>;
+  __shared__ R xch[Lq::NE * kThreads];
+  const int p = blockIdx.y;
+  const int lane = threadIdx.x % kThreads;
+  const int wave = threadIdx.x / kThreads;
+  const long k = (long)blockIdx.x * kThreads + lane;
+  const int m = kp.n / 2;
+  const bool live = k < kp.T;
+  Tup<N, R> f;
+  if (wave == 1) {
+    if (live) {
+      Tup<N, R> b;
+      build_block_rs<N, NU, R, CONST_COEF>(kp, blk_plain(kp, p, k), RMem<N, R>{(const R*)kp.r}, b,
+                                           kp.n - m);
+#pragma unroll
+      for (int i = 0; i < N; ++i)
+#pragma unroll
+        for (int j = 0; j < N; ++j) xch[(Lq::A + i * N + j) * kThreads + lane] = b.A[i][j];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        xch[(Lq::B + i) * kThreads + lane] = b.b[i];
+        xch[(Lq::E + i) * kThreads + lane] = b.e[i];
+      }
+#pragma unroll
+      for (int i = 0; i < Sym<N>::size; ++i) {
+        xch[(Lq::C + i) * kThreads + lane] = b.C[i];
+        xch[(Lq::J + i) * kThreads + lane] = b.J[i];
+      }
+    }
+  } else if (live) {
+    fwd_parts<N, NU, R, CONST_COEF, true>(kp, blk_plain(kp, p, k), m, f, NoStep{});
+  }
+  __syncthreads();
+  if (wave == 1) return;
+  if (!live) return;
+  Tup<N, R> b, o;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) b.A[i][j] = xch[(Lq::A + i * N + j) * kThreads + lane];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    b.b[i] = xch[(Lq::B + i) * kThreads + lane];
+    b.e[i] = xch[(Lq::E + i) * kThreads + lane];
+  }
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) {
+    b.C[i] = xch[(Lq::C + i) * kThreads + lane];
+    b.J[i] = xch[(Lq::J + i) * kThreads + lane];
+  }
+  combine(f, b, o);
+  tup_store(o, elts + (long)p * Lq::NE * padt(kp.T), k);
+}
+
+// ------------------------------------------------------------------------------------------
 // Time-invariant path (F, L constant, c = 0, uniform grid).  The RK4 recursion of Theorem 8 for
 // (A, C, J) does not involve r, so every block has the same A, C, J; b and eta are linear in the
 // block's samples r_0 .. r_2n.  k_lti_prep integrates block 0 once per unit impulse (sample j0,
@@ -603,7 +672,7 @@ __global__ __launch_bounds__(kThreads) void k_lti_prep(const KProb kp, R* __rest
   const int i0 = (int)(m % N);
   Tup<N, R> out;
   const Blk bk{p, 0, 0, (long)p * (kp.T + 1L)};
-  build_block_rs<N, NU, R, true>(kp, bk, RImpulse<R>{j0, i0}, out);
+  build_block_rs<N, NU, R, true>(kp, bk, RImpulse<R>{j0, i0}, out, kp.n);
   R* tp = tab + (long)p * lti_count(N, kp.n);
   R* V = tp + lti_off_V(N) + j0 * N * N;
   R* W = tp + lti_off_W(N, kp.n) + j0 * N * N;
@@ -1799,6 +1868,17 @@ struct L {
                          (R*)ud);
     return hipGetLastError();
   }
+  static hipError_t build_split(const KProb& kp, void* elts, hipStream_t s) {
+    const bool cc = !kp.F_sampled && !kp.L_sampled && !kp.has_c;
+    const dim3 g((unsigned)((kp.T + kThreads - 1) / kThreads), (unsigned)kp.batch, 1);
+    if (cc)
+      hipLaunchKernelGGL((k_build_split<N, NU, R, true>), g, dim3(kSplitThreads), 0, s, kp,
+                         (R*)elts);
+    else
+      hipLaunchKernelGGL((k_build_split<N, NU, R, false>), g, dim3(kSplitThreads), 0, s, kp,
+                         (R*)elts);
+    return hipGetLastError();
+  }
   static hipError_t lti_prep(const KProb& kp, void* tab, hipStream_t s) {
     hipLaunchKernelGGL((k_lti_prep<N, NU, R>), grid_lanes((2L * kp.n + 1) * N, kp.batch),
                        dim3(kThreads), 0, s, kp, (R*)tab);
@@ -1814,7 +1894,7 @@ struct L {
                           vdown,   vbottom,        tbottom_reduce, tup,    ttop,   tdown,
                           tbottom, lti_prep,       lti_build,    build_fwd,
                           m2_up,   m2_top,         m2_down,      m2_bottom,
-                          dense};
+                          dense,   build_split};
     return &o;
   }
 };

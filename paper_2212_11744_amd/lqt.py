@@ -75,13 +75,15 @@ def lib():
         L.lqt_workspace_size.restype = sz
         L.lqt_build_elements.argtypes = [P(Dims), P(Problem), vp, vp, sz, st]
         L.lqt_build_elements_forward.argtypes = [P(Dims), P(Problem), vp, vp, sz, st]
+        L.lqt_build_elements_split.argtypes = [P(Dims), P(Problem), vp, vp, sz, st]
         L.lqt_scan_value.argtypes = [P(Dims), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_forward_traj.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_forward_traj_method2.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_dense_output.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_solve.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_backward.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, st]
-        for f in ("lqt_build_elements", "lqt_build_elements_forward", "lqt_scan_value",
+        for f in ("lqt_build_elements", "lqt_build_elements_forward", "lqt_build_elements_split",
+                  "lqt_scan_value",
                   "lqt_forward_traj", "lqt_forward_traj_method2", "lqt_dense_output", "lqt_solve",
                   "lqt_backward"):
             getattr(L, f).restype = ctypes.c_int
@@ -243,6 +245,18 @@ def build_elements_forward(prob: DeviceProblem, elts: Optional[torch.Tensor] = N
     d, p = prob.dims(), prob.ptrs()
     _check(lib().lqt_build_elements_forward(ctypes.byref(d), ctypes.byref(p), _ptr(elts), _ptr(ws),
                                             ws.numel(), _stream()))
+    return elts
+
+
+def build_elements_split(prob: DeviceProblem, elts: Optional[torch.Tensor] = None,
+                         ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Elements with every block split: Theorem 9 on the first floor(n/2) steps, Theorem 8 on the
+    rest, joined by Lemma 7; same layout as build_elements."""
+    elts = empty_elements(prob) if elts is None else elts
+    ws = workspace(prob, CALL_BUILD) if ws is None else ws
+    d, p = prob.dims(), prob.ptrs()
+    _check(lib().lqt_build_elements_split(ctypes.byref(d), ctypes.byref(p), _ptr(elts), _ptr(ws),
+                                          ws.numel(), _stream()))
     return elts
 
 

@@ -1,9 +1,10 @@
-"""Element build from the forward conditional ODEs (Theorem 9, Sec. IV-C) on the GPU vs the
-oracle's forward build: normwise 1e-9 in FP64, 1e-4 in FP32.  The forward and backward builds
-describe the same conditional value functions, so they agree only to the order of RK4: their
-difference falls by about 2^4 when the number of steps per block doubles.  Value functions and
-trajectories computed from forward elements are compared with the oracle's fold and trajectory
-of the oracle's forward elements.
+"""Element builds from the forward conditional ODEs (Theorem 9, Sec. IV-C) and with every block
+split in two (Sec. IV-D: Theorem 9 on the first floor(n/2) RK4 steps, Theorem 8 on the rest,
+joined by Lemma 7) on the GPU vs the oracle's builds of the same kind: normwise 1e-9 in FP64,
+1e-4 in FP32.  These builds and the backward build describe the same conditional value functions,
+so they agree only to the order of RK4: their difference falls by about 2^4 when the number of
+steps per block doubles.  Value functions and trajectories computed from these elements are
+compared with the oracle's fold and trajectory of the oracle's elements of the same kind.
 """
 import numpy as np
 import pytest
@@ -22,9 +23,17 @@ def _np(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-def _elements(p, dtype=torch.float64):
+MODES = ["forward", "split"]
+
+
+def _elements(p, dtype=torch.float64, mode="forward"):
     dp = lqt.DeviceProblem.from_problems([p], dtype=dtype)
-    return dp, lqt.build_elements_forward(dp)
+    f = lqt.build_elements_forward if mode == "forward" else lqt.build_elements_split
+    return dp, f(dp)
+
+
+def _ref(p, mode):
+    return O.elements(p, forward=mode == "forward", split=mode == "split")
 
 
 def _check_el(el, ref, tol, label):
@@ -41,62 +50,89 @@ def _device():
     torch.cuda.synchronize()
 
 
-def test_config1():
+@pytest.mark.parametrize("mode", MODES)
+def test_config1(mode):
     p = W.point_mass(1, 64, 10)
-    _, e = _elements(p)
-    _check_el(soa_to_dense(_np(e[0]), p.nx, p.T), O.elements(p, forward=True), 1e-9, "config 1")
+    _, e = _elements(p, mode=mode)
+    _check_el(soa_to_dense(_np(e[0]), p.nx, p.T), _ref(p, mode), 1e-9, "config 1")
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("nx,nu,T", [(1, 1, 5), (2, 1, 33), (3, 2, 257), (4, 2, 300), (4, 4, 1)])
-def test_time_varying_with_drift(nx, nu, T):
+def test_time_varying_with_drift(nx, nu, T, mode):
     p = W.random_stable(5 * nx + T, nx=nx, nu=nu, T=T, n=3, tf=0.01 * T + 0.5, time_varying=True)
     rng = np.random.default_rng(nx)
     p.c = 0.3 * np.sin(np.linspace(0, 3, p.r.shape[0]))[:, None] * rng.standard_normal(nx)[None, :]
-    _, e = _elements(p)
-    _check_el(soa_to_dense(_np(e[0]), nx, T), O.elements(p, forward=True), 1e-9, f"nx={nx}")
+    _, e = _elements(p, mode=mode)
+    _check_el(soa_to_dense(_np(e[0]), nx, T), _ref(p, mode), 1e-9, f"nx={nx}")
 
 
-def test_sampled_L():
+@pytest.mark.parametrize("mode", MODES)
+def test_sampled_L(mode):
     p = W.random_stable(8, nx=4, nu=3, T=100, n=4, tf=2.0)
     ts = W.half_step_times(p.t, p.n)
     p.L = p.L[None] * (1.0 + 0.2 * np.cos(ts))[:, None, None]
-    _, e = _elements(p)
-    _check_el(soa_to_dense(_np(e[0]), 4, 100), O.elements(p, forward=True), 1e-9, "sampled L")
+    _, e = _elements(p, mode=mode)
+    _check_el(soa_to_dense(_np(e[0]), 4, 100), _ref(p, mode), 1e-9, "sampled L")
 
 
-def test_fp32():
+@pytest.mark.parametrize("mode", MODES)
+def test_fp32(mode):
     p = W.point_mass(2, 4096, 4, tf=10.0 * 4096 / 2 ** 16)
-    _, e = _elements(p, torch.float32)
-    _check_el(soa_to_dense(_np(e[0]), 4, p.T), O.elements(p, forward=True), 1e-4, "fp32")
+    _, e = _elements(p, torch.float32, mode=mode)
+    _check_el(soa_to_dense(_np(e[0]), 4, p.T), _ref(p, mode), 1e-4, "fp32")
 
 
-def test_value_and_trajectory_from_forward_elements():
+@pytest.mark.parametrize("T,n", [(1, 1), (63, 1), (65, 2), (129, 5), (1000, 7)])
+def test_split_step_counts(T, n):
+    """Odd and even step counts, one step (the first part is empty), ragged last workgroups."""
+    p = W.random_stable(90 + n, nx=4, nu=2, T=T, n=n, tf=0.01 * T + 0.5, time_varying=True)
+    dp, e = _elements(p, mode="split")
+    _check_el(soa_to_dense(_np(e[0]), 4, T), _ref(p, "split"), 1e-9, f"T={T} n={n}")
+    if n == 1:
+        eb = soa_to_dense(_np(lqt.build_elements(dp)[0]), 4, T)
+        _check_el(soa_to_dense(_np(e[0]), 4, T), eb, 1e-14, "n=1 vs backward build")
+
+
+def test_split_batch():
+    probs = [W.point_mass(200 + i, 300, 6) for i in range(3)]
+    dp = lqt.DeviceProblem.from_problems(probs)
+    e = lqt.build_elements_split(dp)
+    for b, p in enumerate(probs):
+        _check_el(soa_to_dense(_np(e[b]), 4, 300), _ref(p, "split"), 1e-9, f"member {b}")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_value_and_trajectory_from_these_elements(mode):
     p = W.random_stable(21, nx=4, nu=2, T=500, n=4, tf=5.0)
-    dp, e = _elements(p)
+    dp, e = _elements(p, mode=mode)
     S, v = lqt.scan_value(dp, e)
     x, u = lqt.forward_traj(dp, e, S, v)
-    el = O.elements(p, forward=True)
+    el = _ref(p, mode)
     S_ref, v_ref = O.value(el, p.Qf, p.rf)
     x_ref, u_ref = O.trajectory(p, el, S_ref, v_ref)
     for got, ref, name in ((S, S_ref, "S"), (v, v_ref, "v"), (x, x_ref, "x"), (u, u_ref, "u")):
         assert relerr(_np(got[0]), ref) < 1e-9, name
 
 
-def test_agrees_with_backward_build_at_fourth_order():
-    """GPU forward vs GPU backward build of the point-mass elements (as the oracle's own pin):
-    the gap shrinks by about 16 when the number of RK4 steps per block doubles."""
+@pytest.mark.parametrize("mode", MODES)
+def test_agrees_with_backward_build_at_fourth_order(mode):
+    """GPU forward (or split) vs GPU backward build of the point-mass elements (as the oracle's
+    own pin): the gap shrinks by about 16 when the number of RK4 steps per block doubles."""
     gaps = []
     for n in (10, 20):
         p = W.point_mass(1, 8, n)
         dp = lqt.DeviceProblem.from_problems([p])
-        ef = soa_to_dense(_np(lqt.build_elements_forward(dp)[0]), 4, 8)
+        _, e = _elements(p, mode=mode)
+        ef = soa_to_dense(_np(e[0]), 4, 8)
         eb = soa_to_dense(_np(lqt.build_elements(dp)[0]), 4, 8)
         gaps.append(max(relerr(ef[k], eb[k]) for k in ("A", "b", "C", "eta", "J")))
     assert gaps[1] < 5e-5 and 12.0 < gaps[0] / gaps[1] < 20.0, gaps
 
 
-def test_large_state_is_unsupported():
+@pytest.mark.parametrize("mode", MODES)
+def test_large_state_is_unsupported(mode):
     p = W.random_stable(1, nx=6, nu=2, T=8, n=2)
     with pytest.raises(lqt.LQTError) as ei:
-        _elements(p)
+        _elements(p, mode=mode)
     assert ei.value.status == lqt.LQT_EUNSUPPORTED
