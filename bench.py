@@ -197,6 +197,7 @@ def main(argv=None):
                       "build_elements_forward": ms_fwd, "forward_traj_method2": ms_m2,
                       "build_elements_split": ms_split, "dense_output": ms_dense},
     }
+    rec["small"] = small_leg(torch, lqt, W, dtype)
     if not args.no_lti:
         rec["lti"] = lti_leg(torch, lqt, p, dtype, args.steps, out, T)
     if not args.no_adjoint:
@@ -230,6 +231,24 @@ def lti_leg(torch, lqt, p, dtype, reps, out, T):
     ms_b = _events_time(lambda: lqt.build_elements(dp, out["elts"], ws_b), reps, torch)
     return {"workload": "same problem, time-invariant path (F, L constant, c = 0, uniform grid)",
             "ms_per_step": ms, "sub_intervals_per_s": T / (ms * 1e-3), "build_ms": ms_b}
+
+
+def small_leg(torch, lqt, W, dtype):
+    """Point mass with T = 64 blocks x 10 RK4 steps (the small case): solve latency, and the element
+    build with whole blocks (Theorem 8) vs split blocks (two wavefronts per block)."""
+    p = W.point_mass(1, 64, 10)
+    dp = lqt.DeviceProblem.from_problems([p], dtype=dtype)
+    out = lqt.solve(dp, keep_elements=True)
+    ws, ws_b = lqt.workspace(dp, lqt.CALL_SOLVE), lqt.workspace(dp, lqt.CALL_BUILD)
+    solve = lambda: lqt.solve(dp, out, ws)
+    build = lambda: lqt.build_elements(dp, out["elts"], ws_b)
+    split = lambda: lqt.build_elements_split(dp, out["elts"], ws_b)
+    for f in (solve, build, split):
+        f()
+    torch.cuda.synchronize()
+    return {"workload": "point-mass LQT tracking, T=64 blocks x 10 RK4 steps on [0,10]",
+            "solve_ms": _events_time(solve, 200, torch), "build_ms": _events_time(build, 200, torch),
+            "build_split_ms": _events_time(split, 200, torch)}
 
 
 def adjoint_leg(torch, lqt, W, reps):

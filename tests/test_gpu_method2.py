@@ -6,6 +6,9 @@ trajectory of the same elements and values (the two routes agree up to rounding)
 one to three levels of the scan tree with ragged last nodes, every (nx, nu) of the per-lane path,
 sampled F, L, a drift c, and batches.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -17,6 +20,7 @@ from paper_2212_11744_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 TOL = {torch.float64: 1e-9, torch.float32: 1e-4}
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fullsize_point_mass_T2p20.json")
 
 
 def _np(t):
@@ -88,3 +92,19 @@ def test_large_state_is_unsupported():
     with pytest.raises(lqt.LQTError) as ei:
         lqt.forward_traj_method2(dp, out["elts"], out["S"], out["v"])
     assert ei.value.status == lqt.LQT_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_full_size_against_oracle_samples(dtype):
+    """T = 2^20 blocks x 4 steps (the benchmark's problem): Method 2 at the stored oracle samples
+    (Method 1 and Method 2 give the same x up to rounding, pinned in the oracle) and against the
+    GPU's Method 1 trajectory on every boundary."""
+    with open(GOLDEN) as f:
+        g = json.load(f)
+    p = W.point_mass(g["seed"], g["T"], g["n_steps"])
+    out, x2, u2 = _run(p, dtype)
+    idx = torch.as_tensor(g["k"], device="cuda")
+    for got, name in ((x2, "x"), (u2, "u")):
+        e = relerr(got[0].index_select(0, idx).double().cpu().numpy(), np.asarray(g[name]))
+        assert e < TOL[dtype], f"{name}: {e:.3e}"
+    assert relerr(_np(x2[0]), _np(out["x"][0])) < (1e-10 if dtype == torch.float64 else 1e-4)
