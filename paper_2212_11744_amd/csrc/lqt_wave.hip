@@ -32,10 +32,46 @@ WDEV int pk(int i, int j, int n) {  // packed upper index
   return i * n - (i * (i - 1)) / 2 + (j - i);
 }
 
+// 16 x 16 FP64 products on the matrix cores: v_mfma_f64_16x16x4f64 takes A(i, k0 + q) and
+// B(k0 + q, j) from lane 16 q + i (resp. 16 q + j) and returns C(q + 4 r, j) in register r of lane
+// 16 q + j.  One instruction per 4 steps of the inner dimension; the operands come straight from
+// LDS, so a 16^3 product costs 8 LDS reads per lane instead of 128.
+typedef double wd4 __attribute__((ext_vector_type(4)));
+
+WDEV void w_gemm16(double* C, const double* A, const double* B, int kk, bool tA, bool tB,
+                   double alpha, double beta) {
+  const int l = lane_id(), li = l & 15, lq = l >> 4;
+  wd4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kk; k0 += 4) {
+    const int k = k0 + lq;
+    const double a = tA ? A[k * 16 + li] : A[li * kk + k];
+    const double b = tB ? B[li * kk + k] : B[k * 16 + li];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  wsync();  // C may be an operand
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int e = (lq + 4 * r) * 16 + li;
+    C[e] = beta == 0.0 ? alpha * acc[r] : fma(beta, C[e], alpha * acc[r]);
+  }
+  wsync();
+}
+
+// Whether the kernels of state size N use the matrix cores for their 16 x 16 products.
+template <int N, class R>
+constexpr bool kMfma = N == 16 && sizeof(R) == 8;
+
 // C = alpha * op(A) op(B) + beta * C for n x n (or m x p) matrices in LDS, row-major, ld = cols.
-template <class R>
+// MF: 16 x 16 FP64 products (inner dimension a multiple of 4) go to the matrix cores.
+template <bool MF = false, class R>
 WDEV void w_gemm(R* C, const R* A, const R* B, int m, int kk, int p, bool tA, bool tB, R alpha,
                  R beta) {
+  if constexpr (MF && sizeof(R) == 8) {
+    if (m == 16 && p == 16 && (kk & 3) == 0) {
+      w_gemm16((double*)C, (const double*)A, (const double*)B, kk, tA, tB, alpha, beta);
+      return;
+    }
+  }
   for (int e = lane_id(); e < m * p; e += 64) {
     const int i = e / p, j = e % p;
     R s = R(0);
@@ -61,50 +97,77 @@ WDEV void w_fill(R* dst, R v, int n) {
   wsync();
 }
 
-// Solve M X = B in place (B <- M^{-1} B), M n x n, B n x nb, Gauss-Jordan with partial pivoting
-// (first row of largest magnitude).  M is destroyed.  f: scratch of n values.
-template <class R>
-WDEV void w_solve(R* M, R* B, int n, int nb, R* f, int* piv) {
-  for (int c = 0; c < n; ++c) {
-    if (lane_id() == 0) {
-      int p = c;
-      for (int i = c + 1; i < n; ++i)
-        if (fabs(M[i * n + c]) > fabs(M[p * n + c])) p = i;
-      *piv = p;
-    }
-    wsync();
-    const int p = *piv;
-    if (p != c) {
-      for (int j = lane_id(); j < n + nb; j += 64) {
-        R* a = j < n ? &M[c * n + j] : &B[c * nb + (j - n)];
-        R* b = j < n ? &M[p * n + j] : &B[p * nb + (j - n)];
-        R t = *a;
-        *a = *b;
-        *b = t;
-      }
-      wsync();
-    }
-    const R inv = R(1) / M[c * n + c];
-    for (int j = lane_id(); j < n + nb; j += 64) {
-      if (j < n) {
-        if (j > c) M[c * n + j] *= inv;
-      } else {
-        B[c * nb + (j - n)] *= inv;
-      }
-    }
-    for (int i = lane_id(); i < n; i += 64) f[i] = M[i * n + c];
-    wsync();
-    for (int e = lane_id(); e < n * (n + nb); e += 64) {
-      const int i = e / (n + nb), j = e % (n + nb);
-      if (i == c) continue;
-      if (j < n) {
-        if (j > c) M[i * n + j] = fma(-f[i], M[c * n + j], M[i * n + j]);
-      } else {
-        B[i * nb + (j - n)] = fma(-f[i], B[c * nb + (j - n)], B[i * nb + (j - n)]);
-      }
-    }
-    wsync();
+// Solve M X = B in place (B <- M^{-1} B), M n x n (n = N), B n x nb with n + nb <= 3n + 1, by
+// Gauss-Jordan elimination with partial pivoting (first row of largest magnitude).  The system
+// lives in registers: row i of [M | B] belongs to LP = 64 / RP lanes (RP = 8 or 16 rows, padded),
+// lane phase c0 holding columns c0, c0 + LP, ...  Per pivot: an argmax butterfly across the rows,
+// a register swap when the pivot row moves, and one LDS broadcast of the pivot row and of column c
+// (M's own storage is reused for it), after which every lane updates its columns.  M is
+// destroyed; the arithmetic per entry is that of the textbook elimination (scale the pivot row by
+// 1 / pivot, subtract f_i times it from every other row).
+template <int N, class R>
+WDEV void w_solve(R* M, R* B, int n, int nb, R*, int*) {
+  constexpr int RP = N <= 8 ? 8 : 16;
+  constexpr int LP = 64 / RP;
+  constexpr int NT = (3 * N + 1 + LP - 1) / LP;
+  const int l = lane_id(), i = l / LP, c0 = l % LP;
+  const int W = N + nb;
+  R x[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = c0 + LP * t;
+    x[t] = i < N && j < W ? (j < N ? M[i * N + j] : B[i * nb + (j - N)]) : R(0);
   }
+  wsync();  // M's storage becomes the broadcast buffer
+  R* rowc = M;      // pivot row (W values)
+  R* fcol = M + W;  // column c of every row (N values)
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    const int tc = c / LP, cc = c % LP;
+    R v = c0 == cc && i >= c && i < N ? fabs(x[tc]) : R(-1);
+    int ix = i;
+#pragma unroll
+    for (int d = LP; d < 64; d <<= 1) {
+      const R vo = __shfl_xor(v, d);
+      const int io = __shfl_xor(ix, d);
+      if (vo > v || (vo == v && io < ix)) {
+        v = vo;
+        ix = io;
+      }
+    }
+    const int p = __shfl(ix, cc);  // lane cc (row 0, phase cc) saw every row's column c
+    if (p != c) {
+      const int src = i == c ? l + (p - c) * LP : (i == p ? l - (p - c) * LP : l);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) x[t] = __shfl(x[t], src);
+    }
+    if (i == c) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int j = c0 + LP * t;
+        if (j < W) rowc[j] = x[t];
+      }
+    }
+    if (c0 == cc && i < N) fcol[i] = x[tc];
+    wsync();
+    const R inv = R(1) / rowc[c];
+    const R f = fcol[i < N ? i : 0];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int j = c0 + LP * t;
+      if (i < N && j < W && (j > c || j >= N)) {
+        const R rj = rowc[j] * inv;
+        x[t] = i == c ? rj : fma(-f, rj, x[t]);
+      }
+    }
+    wsync();  // the next pivot overwrites the buffer
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int j = c0 + LP * t;
+    if (i < N && j >= N && j < W) B[i * nb + (j - N)] = x[t];
+  }
+  wsync();
 }
 
 // Tuple in LDS: A (= A - I, full), b, C (full symmetric), e, J (full symmetric).
@@ -196,11 +259,11 @@ struct WS {
 };
 
 // Lemma 7 in the deviation form of the per-lane path: o = x1 (x) x2 (o may alias x2).
-template <class R>
+template <int N, class R>
 WDEV void w_combine(WT<R> x1, WT<R> x2, WT<R> o, WS<R> s, int n) {
   const int nb = 2 * n + 1;
   // M = I + C1 J2; B = [Ad1 - C1 J2 | C1 | b1 + C1 eta2]
-  w_gemm(s.X, x1.C, x2.J, n, n, n, false, false, R(1), R(0));
+  w_gemm<kMfma<N, R>>(s.X, x1.C, x2.J, n, n, n, false, false, R(1), R(0));
   for (int e = lane_id(); e < n * n; e += 64) {
     const int i = e / n, j = e % n;
     s.M[e] = (i == j ? R(1) : R(0)) + s.X[e];
@@ -213,7 +276,7 @@ WDEV void w_combine(WT<R> x1, WT<R> x2, WT<R> o, WS<R> s, int n) {
     s.B[i * nb + 2 * n] = g;
   }
   wsync();
-  w_solve(s.M, s.B, n, nb, s.f, s.piv);
+  w_solve<N>(s.M, s.B, n, nb, s.f, s.piv);
   // W = (I + Ad2) D -> X;  C = W (I + Ad2)^T + C2 -> Y
   for (int e = lane_id(); e < n * n; e += 64) {
     const int i = e / n, j = e % n;
@@ -288,10 +351,10 @@ WDEV void w_combine(WT<R> x1, WT<R> x2, WT<R> o, WS<R> s, int n) {
 
 // Fold with a terminal-form right operand: (S, v) <- a (x) (S, v); also the block map
 // (P = Psi - I, q = alpha) into P, q (nullable).  S full symmetric.
-template <class R>
+template <int N, class R>
 WDEV void w_fold(WT<R> a, R* S, R* v, WS<R> s, int n, R* P, R* q) {
   const int nb = n + 1;
-  w_gemm(s.X, a.C, S, n, n, n, false, false, R(1), R(0));  // C S
+  w_gemm<kMfma<N, R>>(s.X, a.C, S, n, n, n, false, false, R(1), R(0));  // C S
   for (int e = lane_id(); e < n * n; e += 64) {
     const int i = e / n, j = e % n;
     s.M[e] = (i == j ? R(1) : R(0)) + s.X[e];
@@ -303,7 +366,7 @@ WDEV void w_fold(WT<R> a, R* S, R* v, WS<R> s, int n, R* P, R* q) {
     s.B[i * nb + n] = g;
   }
   wsync();
-  w_solve(s.M, s.B, n, nb, s.f, s.piv);
+  w_solve<N>(s.M, s.B, n, nb, s.f, s.piv);
   if (P) {
     for (int e = lane_id(); e < n * n; e += 64) P[e] = s.B[(e / n) * nb + e % n];
     for (int i = lane_id(); i < n; i += 64) q[i] = s.B[i * nb + n];
@@ -344,10 +407,10 @@ WDEV void w_fold(WT<R> a, R* S, R* v, WS<R> s, int n, R* P, R* q) {
 }
 
 // Block map only: (P, q) from (Ad, b, C) of a block and (S, v) at its right end.
-template <class R>
+template <int N, class R>
 WDEV void w_block_map(WT<R> a, const R* S, const R* v, WS<R> s, int n, R* P, R* q) {
   const int nb = n + 1;
-  w_gemm(s.X, a.C, S, n, n, n, false, false, R(1), R(0));
+  w_gemm<kMfma<N, R>>(s.X, a.C, S, n, n, n, false, false, R(1), R(0));
   for (int e = lane_id(); e < n * n; e += 64) {
     const int i = e / n, j = e % n;
     s.M[e] = (i == j ? R(1) : R(0)) + s.X[e];
@@ -359,7 +422,7 @@ WDEV void w_block_map(WT<R> a, const R* S, const R* v, WS<R> s, int n, R* P, R* 
     s.B[i * nb + n] = g;
   }
   wsync();
-  w_solve(s.M, s.B, n, nb, s.f, s.piv);
+  w_solve<N>(s.M, s.B, n, nb, s.f, s.piv);
   for (int e = lane_id(); e < n * n; e += 64) P[e] = s.B[(e / n) * nb + e % n];
   for (int i = lane_id(); i < n; i += 64) q[i] = s.B[i * nb + n];
   wsync();
@@ -531,7 +594,7 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
           Lc[e] = a;
         }
         wsync();
-        w_gemm(G, Lc, Lc, n, nu, n, false, true, R(1), R(0));
+        w_gemm<kMfma<N, R>>(G, Lc, Lc, n, nu, n, false, true, R(1), R(0));
       } else {
         for (int e = lane_id(); e < n * n; e += 64) G[e] = cs[consts_off_G(n, nu) + e];
         for (int e = lane_id(); e < n * nu; e += 64) Lc[e] = cs[consts_off_Lc(n, nu) + e];
@@ -540,10 +603,10 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
       // K = G J - F
       for (int e = lane_id(); e < n * n; e += 64) K[e] = -F[e];
       wsync();
-      w_gemm(K, G, st.J, n, n, n, false, false, R(1), R(1));
+      w_gemm<kMfma<N, R>>(K, G, st.J, n, n, n, false, false, R(1), R(1));
       // kA = K + Ad K
       w_copy(kA, K, n * n);
-      w_gemm(kA, st.A, K, n, n, n, false, false, R(1), R(1));
+      w_gemm<kMfma<N, R>>(kA, st.A, K, n, n, n, false, false, R(1), R(1));
       // kb = -(I + Ad)(G eta + c)
       for (int i = lane_id(); i < n; i += 64) {
         R a = cv[i];
@@ -559,8 +622,8 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
       // kC = -(A Lc)(A Lc)^T with A Lc = Lc + Ad Lc -> T1 (n x nu)
       wsync();
       w_copy(T1, Lc, n * nu);
-      w_gemm(T1, st.A, Lc, n, n, nu, false, false, R(1), R(1));
-      w_gemm(kC, T1, T1, n, nu, n, false, true, R(-1), R(0));
+      w_gemm<kMfma<N, R>>(T1, st.A, Lc, n, n, nu, false, false, R(1), R(1));
+      w_gemm<kMfma<N, R>>(kC, T1, T1, n, nu, n, false, true, R(-1), R(0));
       // ke = K^T eta + J c - Q r
       for (int i = lane_id(); i < n; i += 64) {
         R a = R(0);
@@ -572,15 +635,31 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
         ke[i] = a;
       }
       // kJ = -Q + J K - F^T J (symmetrised from the upper entry)
-      for (int e = lane_id(); e < n * n; e += 64) {
-        const int i = e / n, q2 = e % n;
-        const int a = i < q2 ? i : q2, bb = i < q2 ? q2 : i;
-        R v = -Qp[a * n + bb];
-        for (int l = 0; l < n; ++l) {
-          v = fma(st.J[a * n + l], K[l * n + bb], v);
-          v = fma(-F[l * n + a], st.J[l * n + bb], v);
+      if constexpr (N == 16 && sizeof(R) == 8) {
+        wsync();  // ke has read K before the products below run
+        w_gemm<kMfma<N, R>>(kJ, st.J, K, n, n, n, false, false, R(1), R(0));
+        w_gemm<kMfma<N, R>>(kJ, F, st.J, n, n, n, true, false, R(-1), R(1));
+        R v[4];
+        int cnt = 0;
+        for (int e = lane_id(); e < n * n; e += 64, ++cnt) {
+          const int i = e / n, q2 = e % n;
+          const int a = i < q2 ? i : q2, bb = i < q2 ? q2 : i;
+          v[cnt] = kJ[a * n + bb] - Qp[a * n + bb];
         }
-        kJ[e] = v;
+        wsync();
+        cnt = 0;
+        for (int e = lane_id(); e < n * n; e += 64, ++cnt) kJ[e] = v[cnt];
+      } else {
+        for (int e = lane_id(); e < n * n; e += 64) {
+          const int i = e / n, q2 = e % n;
+          const int a = i < q2 ? i : q2, bb = i < q2 ? q2 : i;
+          R v = -Qp[a * n + bb];
+          for (int l = 0; l < n; ++l) {
+            v = fma(st.J[a * n + l], K[l * n + bb], v);
+            v = fma(-F[l * n + a], st.J[l * n + bb], v);
+          }
+          kJ[e] = v;
+        }
       }
       wsync();
       // accumulate and form the next stage input
@@ -631,7 +710,7 @@ __global__ __launch_bounds__(64) void kw_vreduce(int, int wc, int src_elts,
   wt_load(acc, ref(j1 - 1), n);
   for (long j = j1 - 2; j >= j0; --j) {
     wt_load(x, ref(j), n);
-    w_combine(x, acc, acc, scr, n);
+    w_combine<N>(x, acc, acc, scr, n);
   }
   wt_store(acc, rec_ref(dst, p, i, n_dst, NE), n);
 }
@@ -680,7 +759,7 @@ __global__ __launch_bounds__(64) void kw_vtop(const KProb kp, const R* __restric
     val_st(S, v, val + ((long)p * n_top + j) * VR, n);
     if (j == 0) break;
     wt_load(a, rec_ref(tup, p, j, n_top, NE), n);
-    w_fold(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
+    w_fold<N>(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
   }
 }
 
@@ -706,7 +785,7 @@ __global__ __launch_bounds__(64) void kw_vdown(int, int wc, const R* __restrict_
     val_st(S, v, val_out + ((long)p * n_child + j) * VR, n);
     if (j == j0) break;
     wt_load(a, rec_ref(tup, p, j, n_child, NE), n);
-    w_fold(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
+    w_fold<N>(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
   }
 }
 
@@ -746,7 +825,7 @@ __global__ __launch_bounds__(64) void kw_vbottom(const KProb kp, int wc, const R
   w_aff_identity(aP, aq, n);
   for (long k = j1 - 1; k >= j0; --k) {
     wt_load(a, elt_ref(elts, p, k, T, NE), n);
-    w_fold(a, S, v, scr, n, mP, mq);
+    w_fold<N>(a, S, v, scr, n, mP, mq);
     for (int e = lane_id(); e < n * n; e += 64) Sp[k * n * n + e] = S[e];
     for (int q = lane_id(); q < n; q += 64) vp[k * n + q] = v[q];
     if (maps1) w_aff_after(aP, aq, mP, mq, tmp, n);
@@ -814,7 +893,7 @@ __global__ __launch_bounds__(64) void kw_tbottom_reduce(const KProb kp, int wc, 
   for (long k = j0; k < j1; ++k) {
     wt_load(a, elt_ref(elts, p, k, T, NE), n);
     w_right_value(kp, Sp, vp, k, S, v, n);
-    w_block_map(a, S, v, scr, n, mP, mq);
+    w_block_map<N>(a, S, v, scr, n, mP, mq);
     w_aff_then(aP, aq, mP, mq, tmp, n);
   }
   map_st(aP, aq, maps1 + ((long)p * n1 + i) * MR, n);
@@ -961,7 +1040,7 @@ __global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R
     control(k);
     wt_load(a, elt_ref(elts, p, k, T, NE), n);
     w_right_value(kp, Sp, vp, k, S, v, n);
-    w_block_map(a, S, v, scr, n, mP, mq);
+    w_block_map<N>(a, S, v, scr, n, mP, mq);
     w_aff_apply(mP, mq, x, tmp, n);
   }
   if (j1 == T && !kp.seg) {
