@@ -687,6 +687,240 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
 }
 
 // ------------------------------------------------------------------------------------------
+// Element build for nx <= 8 with 8 blocks per wave: lane 8 g + i owns row i of every matrix of
+// block 8 w + g (A - I, C, J rows, b_i, eta_i) in registers, with its rows of G, Q, F and F^T.
+// The products of a stage need other rows of J, K, Lc and A Lc, and the vectors eta and G eta + c;
+// each group publishes them in its own LDS area (rows padded to nx + 1 values, so the 8 rows of a
+// group sit in different banks) and reads them back after a barrier: three barriers per stage
+// for 8 blocks, and each LDS read serves the 8 lanes of a group at once.  Same RK4 recursion of
+// Theorem 8 as the per-lane path; J and C are symmetrised from their upper entries after every
+// step.
+// ------------------------------------------------------------------------------------------
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_build_rows(const KProb kp, R* __restrict__ elts) {
+  static_assert(N <= 8, "8 lanes per block");
+  constexpr int P = N + 1;  // padded row length in LDS
+  __shared__ R sJ[8][8 * P], sK[8][8 * P], sL[8][8 * P], sAL[8][8 * P], se[8][8], sw[8][8];
+  const int lane = lane_id(), g = lane >> 3, i = lane & 7;
+  const int nu = kp.nu;
+  const long T = kp.T;
+  const int nn = kp.n;
+  const long k = (long)blockIdx.x * 8 + g;
+  const bool row = i < N;
+  bool live = k < T;
+  bool sep = false;
+  int p = blockIdx.y;
+  long s0 = (long)p * (2L * nn * T + 1), tk = (long)p * (T + 1) + k, pf = 0;
+  if (kp.seg && live) {
+    p = seg_find(kp.seg, kp.nseg, k);
+    sep = k == kp.seg[p + 1] - 1 || k == T - 1;
+    s0 = (long)p * (1 - 2L * nn);
+    tk = k;
+    pf = p;
+  }
+  const bool work = live && !sep;  // this group integrates a block
+  const bool act = work && row;    // this lane owns a row of it
+  const R* cs = (const R*)kp.consts + (long)p * consts_count(N, nu);
+  const R* Qp = (const R*)kp.Q + (long)p * N * N;
+  const R* Fc = (const R*)kp.F + pf * N * N;
+  // constant rows: G_i, Q_i, F_i, (F^T)_i, Lc_i
+  R Gr[N], Qr[N], Fr[N], Fk[N], Lr[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    Gr[q] = act ? cs[consts_off_G(N, nu) + i * N + q] : R(0);
+    Qr[q] = act ? Qp[i * N + q] : R(0);
+    Fr[q] = act ? Fc[i * N + q] : R(0);
+    Fk[q] = act ? Fc[q * N + i] : R(0);
+    Lr[q] = act && q < nu ? cs[consts_off_Lc(N, nu) + i * nu + q] : R(0);
+  }
+  const R* W = cs + consts_off_W(N, nu);
+  R yA[N], yJ[N], yC[N], aA[N], aJ[N], tA[N], tJ[N];
+  R ye = R(0), yb = R(0), ae = R(0), te = R(0);
+#pragma unroll
+  for (int q = 0; q < N; ++q) yA[q] = yJ[q] = yC[q] = R(0);
+  const R h = work ? (((const R*)kp.t)[tk + 1] - ((const R*)kp.t)[tk]) / R(nn) : R(0);
+  if (!kp.L_sampled) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) sL[g][i * P + q] = Lr[q];
+  }
+  for (int m = 0; m < nn; ++m) {
+    const long j1 = 2L * nn * k + 2L * (nn - m);
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      tA[q] = yA[q];
+      tJ[q] = yJ[q];
+    }
+    te = ye;
+    for (int st = 0; st < 4; ++st) {
+      const long j = st == 0 ? j1 : (st == 3 ? j1 - 2 : j1 - 1);
+      const R wk = (st == 0 || st == 3) ? -h / R(6) : -h / R(3);
+      const R cn = st == 2 ? -h : -h / R(2);
+      R rv[N], cv[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        rv[q] = act ? ((const R*)kp.r)[(s0 + j) * N + q] : R(0);
+        cv[q] = act && kp.has_c ? ((const R*)kp.c)[(s0 + j) * N + q] : R(0);
+      }
+      if (kp.F_sampled) {
+        const R* Fj = (const R*)kp.F + (s0 + j) * N * N;
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          Fr[q] = act ? Fj[i * N + q] : R(0);
+          Fk[q] = act ? Fj[q * N + i] : R(0);
+        }
+      }
+      if (kp.L_sampled) {  // Lc = L(t_j) W, G = Lc Lc^T
+        const R* Lj = (const R*)kp.L + (s0 + j) * N * nu;
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+          R a = R(0);
+          if (act && l < nu)
+            for (int q = 0; q < nu; ++q) a = fma(Lj[i * nu + q], W[q * nu + l], a);
+          Lr[l] = a;
+          sL[g][i * P + l] = a;
+        }
+        wsync();
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+          R a = R(0);
+#pragma unroll
+          for (int l = 0; l < N; ++l) a = fma(Lr[l], sL[g][q * P + l], a);
+          Gr[q] = a;
+        }
+      }
+      // publish the stage's J row and eta_i
+#pragma unroll
+      for (int q = 0; q < N; ++q) sJ[g][i * P + q] = tJ[q];
+      se[g][i] = te;
+      wsync();
+      // K_i = G_i J - F_i;  w_i = G_i eta + c_i
+      R K[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R a = -Fr[q];
+#pragma unroll
+        for (int l = 0; l < N; ++l) a = fma(Gr[l], sJ[g][l * P + q], a);
+        K[q] = a;
+      }
+      R w = row ? cv[i] : R(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) w = fma(Gr[l], se[g][l], w);
+#pragma unroll
+      for (int q = 0; q < N; ++q) sK[g][i * P + q] = K[q];
+      sw[g][i] = w;
+      wsync();
+      // kA_i = K_i + (Ad)_i K;  kb_i = -(w_i + (Ad)_i w);  (A Lc)_i = Lc_i + (Ad)_i Lc
+      R kA[N], AL[N], kJ[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R a = K[q];
+#pragma unroll
+        for (int l = 0; l < N; ++l) a = fma(tA[l], sK[g][l * P + q], a);
+        kA[q] = a;
+      }
+      R kb = w;
+#pragma unroll
+      for (int l = 0; l < N; ++l) kb = fma(tA[l], sw[g][l], kb);
+      kb = -kb;
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R a = Lr[q];
+#pragma unroll
+        for (int l = 0; l < N; ++l) a = fma(tA[l], sL[g][l * P + q], a);
+        AL[q] = q < nu ? a : R(0);
+        sAL[g][i * P + q] = AL[q];
+      }
+      // ke_i = (K^T eta)_i + J_i c - Q_i r;  kJ_i = -Q_i + J_i K - (F^T)_i J
+      R ke = R(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        ke = fma(sK[g][l * P + i], se[g][l], ke);
+        if (kp.has_c) ke = fma(tJ[l], cv[l], ke);
+        ke = fma(-Qr[l], rv[l], ke);
+      }
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R a = -Qr[q];
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+          a = fma(tJ[l], sK[g][l * P + q], a);
+          a = fma(-Fk[l], sJ[g][l * P + q], a);
+        }
+        kJ[q] = a;
+      }
+      wsync();
+      // kC_i = -(A Lc)_i (A Lc)^T
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        R a = R(0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) a = fma(AL[l], sAL[g][q * P + l], a);
+        yC[q] = fma(-wk, a, yC[q]);
+      }
+      yb = fma(wk, kb, yb);
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        aA[q] = st == 0 ? fma(wk, kA[q], yA[q]) : fma(wk, kA[q], aA[q]);
+        aJ[q] = st == 0 ? fma(wk, kJ[q], yJ[q]) : fma(wk, kJ[q], aJ[q]);
+        if (st < 3) {
+          tA[q] = fma(cn, kA[q], yA[q]);
+          tJ[q] = fma(cn, kJ[q], yJ[q]);
+        }
+      }
+      ae = st == 0 ? fma(wk, ke, ye) : fma(wk, ke, ae);
+      if (st < 3) te = fma(cn, ke, ye);
+    }
+    // end of step: new start value; J and C take their upper entries
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      yA[q] = aA[q];
+      sJ[g][i * P + q] = aJ[q];
+      sK[g][i * P + q] = yC[q];
+    }
+    ye = ae;
+    wsync();
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      yJ[q] = q < i ? sJ[g][q * P + i] : aJ[q];
+      yC[q] = q < i ? sK[g][q * P + i] : yC[q];
+    }
+    wsync();
+  }
+  if (!live || !row) return;
+  const GRef<R> o = elt_ref(elts, kp.seg ? 0 : p, k, T, ne_w(N));
+  const int ns = N * (N + 1) / 2;
+  const int oB = N * N, oC = oB + N, oE = oC + ns, oJ = oE + N;
+  if (sep) {  // separator after problem p (see KProb): A - I = -I, b = next x0, C = 0
+    const R* Qf = (const R*)kp.Qf + (long)p * N * N;
+    const R* rf = (const R*)kp.rf + (long)p * N;
+    const bool last = p + 1 >= kp.nseg;
+    R e = R(0);
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      o.g[(i * N + q) * o.st] = q == i ? R(-1) : R(0);
+      e = fma(Qf[i * N + q], rf[q], e);
+      if (q >= i) {
+        o.g[(oC + pk(i, q, N)) * o.st] = R(0);
+        o.g[(oJ + pk(i, q, N)) * o.st] = Qf[i * N + q];
+      }
+    }
+    o.g[(oB + i) * o.st] = last ? R(0) : ((const R*)kp.x0)[(long)(p + 1) * N + i];
+    o.g[(oE + i) * o.st] = e;
+    return;
+  }
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    o.g[(i * N + q) * o.st] = yA[q];
+    if (q >= i) {
+      o.g[(oC + pk(i, q, N)) * o.st] = yC[q];
+      o.g[(oJ + pk(i, q, N)) * o.st] = yJ[q];
+    }
+  }
+  o.g[(oB + i) * o.st] = yb;
+  o.g[(oE + i) * o.st] = ye;
+}
+
+// ------------------------------------------------------------------------------------------
 // Value tree.
 // ------------------------------------------------------------------------------------------
 template <int N, class R>
@@ -1071,8 +1305,12 @@ namespace {
 
 template <int N, class R>
 hipError_t wave_build_t(const KProb& kp, void* elts, hipStream_t s) {
-  hipLaunchKernelGGL((kw_build<N, R>), dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
-                     (R*)elts);
+  if constexpr (N <= 8)
+    hipLaunchKernelGGL((kw_build_rows<N, R>), dim3((unsigned)((kp.T + 7) / 8), kp.batch), dim3(64),
+                       0, s, kp, (R*)elts);
+  else
+    hipLaunchKernelGGL((kw_build<N, R>), dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
+                       (R*)elts);
   return hipGetLastError();
 }
 
