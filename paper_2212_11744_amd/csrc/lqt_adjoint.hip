@@ -969,7 +969,8 @@ LQT_DEV void stage_seed(R c1, const Tup<N, R>& yb, R c2, const Stage<N, R>& sn, 
 template <int N, int NU, class R>
 __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restrict__ abar,
                                                R* __restrict__ dr, R* __restrict__ bnd,
-                                               R* __restrict__ wsum, R* __restrict__ ckpt) {
+                                               R* __restrict__ wsum, R* __restrict__ ckpt,
+                                               int ckpt_ready) {
   using Y = Sym<N>;
   constexpr int NS = Y::size, SL = StageLay<N>::size;
   __shared__ R sF[N * N], sG[N * N], sQ[N * N];
@@ -1013,12 +1014,13 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
     R carry[N];
 #pragma unroll
     for (int q = 0; q < N; ++q) carry[q] = R(0);
-    // Step start values: with a checkpoint buffer, one forward pass stores y_1 .. y_{n-1}
-    // (layout [problem][step - 1][value][block], coalesced over the blocks of a wave);
-    // without one, y_m is recomputed from y_0 = 0 for every step.
+    // Step start values: with a checkpoint buffer, y_1 .. y_{n-1} are read from it (layout
+    // [problem][step - 1][value][block], coalesced over the blocks of a wave), written by the
+    // element build of the backward pass (ckpt_ready) or else by one forward pass here; without
+    // a buffer, y_m is recomputed from y_0 = 0 for every step.
     const long ck_stride = padt(T);
     R* ckp = ckpt ? ckpt + (long)p * (n - 1) * SL * ck_stride : nullptr;
-    if (ckp) {
+    if (ckp && !ckpt_ready) {
       Stage<N, R> y;
       stage_zero(y);
 #pragma unroll 1
@@ -1303,9 +1305,9 @@ struct A {
     return hipGetLastError();
   }
   static hipError_t rk4(const KProb& kp, const void* abar, void* dr, void* bnd, void* wsum,
-                        void* ckpt, hipStream_t s) {
+                        void* ckpt, bool ckpt_ready, hipStream_t s) {
     hipLaunchKernelGGL((k_adj_rk4<N, NU, R>), lanes(kp.T, kp.batch), dim3(kT), 0, s, kp,
-                       (const R*)abar, (R*)dr, (R*)bnd, (R*)wsum, (R*)ckpt);
+                       (const R*)abar, (R*)dr, (R*)bnd, (R*)wsum, (R*)ckpt, (int)ckpt_ready);
     return hipGetLastError();
   }
   static hipError_t finish(const KProb& kp, const void* bnd, void* dr, const void* wsum, void* dQ,

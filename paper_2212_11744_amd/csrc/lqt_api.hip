@@ -581,7 +581,11 @@ lqt_status lqt_backward(const lqt_dims* dims, const lqt_problem* prob, const voi
   const Tree t = tree_for(dims);
   hipStream_t s = stream;
   LQT_HIP(o->prep(kp, w.consts, s));
-  LQT_HIP(o->build(kp, w.elts, s));
+  // rebuild the elements; with a checkpoint buffer also keep the RK4 step start values
+  if (w.ckpt)
+    LQT_HIP(o->build_ckpt(kp, w.elts, w.ckpt, s));
+  else
+    LQT_HIP(o->build(kp, w.elts, s));
   // lambda_k = xbar_k + Psi_k^T lambda_{k+1} (backward)
   LQT_HIP(ao->lam_bottom(kp, w.elts, S, v, dLdx, w.lmap[1], t.n[1], s));
   for (int l = 1; l < t.levels; ++l)
@@ -598,7 +602,7 @@ lqt_status lqt_backward(const lqt_dims* dims, const lqt_problem* prob, const voi
     LQT_HIP(ao->cong_down(kp, w.cmap[l], t.n[l], w.cpart[l], w.cst[l + 1], t.n[l + 1], w.cst[l], s));
   // element gradients, then the RK4 adjoint of every block and the reductions
   LQT_HIP(ao->elem(kp, w.elts, S, v, x, w.lam, w.cst[1], t.n[1], dQf, drf, s));
-  LQT_HIP(ao->rk4(kp, w.elts, dr, w.bnd, w.wsum, w.ckpt, s));
+  LQT_HIP(ao->rk4(kp, w.elts, dr, w.bnd, w.wsum, w.ckpt, w.ckpt != nullptr, s));
   LQT_HIP(ao->finish(kp, w.bnd, dr, w.wsum, dQ, dR, s));
   return ok();
 }

@@ -152,6 +152,8 @@ struct Ops {
                       void* vd, void* xd, void* ud, hipStream_t);
   // elements with every block split: Theorem 9 on the first half, Theorem 8 on the second
   hipError_t (*build_split)(const KProb&, void* elts, hipStream_t);
+  // elements (constant coefficients) plus the RK4 step start values the adjoint re-linearises at
+  hipError_t (*build_ckpt)(const KProb&, void* elts, void* ckpt, hipStream_t);
 };
 
 // Adjoint kernels (lqt_adjoint.hip) of one (nx, nu, dtype) instantiation.
@@ -175,8 +177,9 @@ struct AdjOps {
   hipError_t (*elem)(const KProb&, void* elts, const void* S, const void* v, const void* x,
                      const void* lam, const void* sv1, long n1, void* dQf, void* drf,
                      hipStream_t);
+  // ckpt_ready: the step start values are already in ckpt (written by Ops::build_ckpt)
   hipError_t (*rk4)(const KProb&, const void* abar, void* dr, void* bnd, void* wsum, void* ckpt,
-                    hipStream_t);
+                    bool ckpt_ready, hipStream_t);
   hipError_t (*finish)(const KProb&, const void* bnd, void* dr, const void* wsum, void* dQ,
                        void* dR, hipStream_t);
 };

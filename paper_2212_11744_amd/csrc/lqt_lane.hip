@@ -77,9 +77,15 @@ struct RImpulse {
 };
 
 // nsteps < n stops at s = t_{k+1} - nsteps h: the tuple of V(., t_{k+1} - nsteps h; ., t_{k+1}).
-template <int N, int NU, class R, bool CONST_COEF, class RS>
+struct NoBackStep {
+  template <class... X>
+  LQT_DEV void operator()(int, const X&...) const {}
+};
+
+// step(m, Ad, eta, J) is called after step m with the values at s = t_{k+1} - (m + 1) h.
+template <int N, int NU, class R, bool CONST_COEF, class RS, class STEP = NoBackStep>
 LQT_DEV void build_block_rs(const KProb& kp, const Blk& bk, const RS& rs, Tup<N, R>& out,
-                            int nsteps) {
+                            int nsteps, const STEP& step = STEP()) {
   using Y = Sym<N>;
   constexpr int NS = Y::size;
   const int n = kp.n;
@@ -307,6 +313,7 @@ LQT_DEV void build_block_rs(const KProb& kp, const Blk& bk, const RS& rs, Tup<N,
     }
 #pragma unroll
     for (int i = 0; i < NS; ++i) yJ[i] = aJ[i];
+    step(m, yA, ye, yJ);
   }
 
 #pragma unroll
@@ -829,6 +836,36 @@ __global__ __launch_bounds__(kThreads) void k_build(const KProb kp, R* __restric
   if (k >= kp.T) return;
   Tup<N, R> out;
   element_at<N, NU, R, CONST_COEF>(kp, p, k, out);
+  tup_store(out, elts + (long)p * Lay<N>::NE * padt(kp.T), k);
+}
+
+// Element build that also keeps the start values (A - I, eta, J) of steps 1 .. n - 1 of every
+// block for the RK4 adjoint: layout [problem][step - 1][value][padt(T)], values in the order
+// A - I (row-major), eta, J (packed upper), so a wave's stores of one value are coalesced.
+template <int N, int NU, class R>
+__global__ __launch_bounds__(kThreads) void k_build_ckpt(const KProb kp, R* __restrict__ elts,
+                                                          R* __restrict__ ckpt) {
+  constexpr int SL = N * N + N + Sym<N>::size;
+  const int p = blockIdx.y;
+  const long k = gid();
+  if (k >= kp.T) return;
+  const long st = padt(kp.T);
+  R* ck = ckpt + (long)p * (kp.n - 1) * SL * st + k;
+  auto keep = [&](int m, const R (&A)[N][N], const R (&e)[N], const R (&J)[Sym<N>::size]) {
+    if (m + 1 >= kp.n) return;
+    R* c = ck + (long)m * SL * st;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) c[(i * N + q) * st] = A[i][q];
+      c[(N * N + i) * st] = e[i];
+    }
+#pragma unroll
+    for (int i = 0; i < Sym<N>::size; ++i) c[(N * N + N + i) * st] = J[i];
+  };
+  Tup<N, R> out;
+  build_block_rs<N, NU, R, true>(kp, blk_plain(kp, p, k), RMem<N, R>{(const R*)kp.r}, out, kp.n,
+                                 keep);
   tup_store(out, elts + (long)p * Lay<N>::NE * padt(kp.T), k);
 }
 
@@ -1879,6 +1916,11 @@ struct L {
                          (R*)elts);
     return hipGetLastError();
   }
+  static hipError_t build_ckpt(const KProb& kp, void* elts, void* ckpt, hipStream_t s) {
+    hipLaunchKernelGGL((k_build_ckpt<N, NU, R>), grid_lanes(kp.T, kp.batch), dim3(kThreads), 0,
+                       s, kp, (R*)elts, (R*)ckpt);
+    return hipGetLastError();
+  }
   static hipError_t lti_prep(const KProb& kp, void* tab, hipStream_t s) {
     hipLaunchKernelGGL((k_lti_prep<N, NU, R>), grid_lanes((2L * kp.n + 1) * N, kp.batch),
                        dim3(kThreads), 0, s, kp, (R*)tab);
@@ -1894,7 +1936,7 @@ struct L {
                           vdown,   vbottom,        tbottom_reduce, tup,    ttop,   tdown,
                           tbottom, lti_prep,       lti_build,    build_fwd,
                           m2_up,   m2_top,         m2_down,      m2_bottom,
-                          dense,   build_split};
+                          dense,   build_split,    build_ckpt};
     return &o;
   }
 };
