@@ -701,7 +701,7 @@ LQT_DEV void stage_axpy(const Stage<N, R>& y, R c, const Stage<N, R>& k, Stage<N
   for (int i = 0; i < Sym<N>::size; ++i) o.J[i] = fma(c, k.J[i], y.J[i]);
 }
 
-// The (Ad, eta, J) part of the right-hand side.  F, G, Q: row-major N x N in LDS.
+// The (Ad, eta, J) part of the right-hand side.  F, G, Q: row-major N x N.
 template <int N, class R>
 LQT_DEV void rhs_aej(const Stage<N, R>& y, const R* F, const R* G,
                      const R* Q, const R (&r)[N],
@@ -970,11 +970,14 @@ template <int N, int NU, class R>
 __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restrict__ abar,
                                                R* __restrict__ dr, R* __restrict__ bnd,
                                                R* __restrict__ wsum, R* __restrict__ ckpt,
-                                               int ckpt_ready) {
+                                               int ckpt_ready, const R* __restrict__ cF,
+                                               const R* __restrict__ cG,
+                                               const R* __restrict__ cQ) {
   using Y = Sym<N>;
   constexpr int NS = Y::size, SL = StageLay<N>::size;
-  __shared__ R sF[N * N], sG[N * N], sQ[N * N];
   // per-lane slots: step start value, running sum of stage adjoints, symmetric Q and G adjoints
+  // (40 KB in FP64 at nx = 4, so four workgroups fit the 160 KB of LDS of a CU; F, G and Q are
+  // read through the scalar cache instead of being staged here)
   __shared__ R yL[SL * kT], aL[SL * kT], qL[NS * kT], gL[NS * kT];
   const int p = blockIdx.y;
   const long k = gidx();
@@ -983,21 +986,14 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
   const int n = kp.n;
   const long nsamp = 2L * n * T + 1;
   const R* rp = (const R*)kp.r + (long)p * nsamp * N;
-  const R* cs = (const R*)kp.consts + (long)p * CS<N, NU>::size;
-  if (lane < N * N) {
-    sF[lane] = ((const R*)kp.F)[lane];
-    sG[lane] = cs[CS<N, NU>::G + lane];
-    sQ[lane] = ((const R*)kp.Q)[(long)p * N * N + lane];
-  }
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     qL[i * kT + lane] = R(0);
     gL[i * kT + lane] = R(0);
   }
-  __syncthreads();
-  const R* vF = sF;
-  const R* vG = sG;
-  const R* vQ = sQ;
+  const R* vF = cF;
+  const R* vG = cG + (long)p * CS<N, NU>::size;
+  const R* vQ = cQ + (long)p * N * N;
   R* vq = qL;
   R* vg = gL;
   // Compiler memory barriers below keep the per-lane LDS slots in LDS: without them the values
@@ -1307,7 +1303,8 @@ struct A {
   static hipError_t rk4(const KProb& kp, const void* abar, void* dr, void* bnd, void* wsum,
                         void* ckpt, bool ckpt_ready, hipStream_t s) {
     hipLaunchKernelGGL((k_adj_rk4<N, NU, R>), lanes(kp.T, kp.batch), dim3(kT), 0, s, kp,
-                       (const R*)abar, (R*)dr, (R*)bnd, (R*)wsum, (R*)ckpt, (int)ckpt_ready);
+                       (const R*)abar, (R*)dr, (R*)bnd, (R*)wsum, (R*)ckpt, (int)ckpt_ready,
+                       (const R*)kp.F, (const R*)kp.consts + CS<N, NU>::G, (const R*)kp.Q);
     return hipGetLastError();
   }
   static hipError_t finish(const KProb& kp, const void* bnd, void* dr, const void* wsum, void* dQ,
