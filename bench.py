@@ -326,11 +326,17 @@ def _traffic(path, T, dtype):
 
 
 def _kernel_sha() -> str:
+    """sha256 (first 16 hex digits) of the code of lane_math.hpp + lqt_lane.hip: every line with
+    its // comment removed and surrounding blanks stripped, blank lines dropped, so edits to
+    comments alone keep a counter summary valid."""
     import hashlib
     h = hashlib.sha256()
     for f in ("lane_math.hpp", "lqt_lane.hip"):
-        with open(os.path.join(ROOT, "paper_2212_11744_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2212_11744_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

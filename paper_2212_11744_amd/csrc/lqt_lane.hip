@@ -17,6 +17,17 @@
 //                  trajectory: level 1 of the composition scan of the block maps
 //                  x_{k+1} = Psi_k x_k + alpha_k (Method 1, Sec. IV-E), then x_k and the control
 //                  law u_k (Sec. II-B) of every block.
+//   k_build_reduce element build fused with level 1 of the value tree.
+//   k_build_fwd    element build from Theorem 9 (Sec. IV-C).
+//   k_build_split  element build with each block split in a Theorem 9 part and a Theorem 8 part
+//                  joined by Lemma 7 (Sec. IV-D), the two parts on two wavefronts.
+//   k_build_ckpt   element build that also keeps the RK4 step start values for the adjoint.
+//   k_lti_prep / k_build_lti
+//                  time-invariant path: shared A, C, J and b, eta as weighted sums of samples.
+//   k_up / k_top / k_down with PreAlg, k_m2_bottom
+//                  Method 2 trajectory (Sec. IV-E): forward prefix scan of the conditional value
+//                  functions and x_k = (I + C S_k)^{-1} (A x0 + b + C v_k).
+//   k_dense        values inside the blocks (Sec. IV-D): S, v, x, u at every RK4 node.
 // Tree shape: level 1 has ceil(T / 4) nodes (4 blocks per lane); level l + 1 has
 // ceil(n_l / 256) nodes while n_l > 256; the top level (<= 256 nodes) is one wave.
 #include "lane_math.hpp"
