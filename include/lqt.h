@@ -38,6 +38,17 @@
  *    device itself surface at the caller's next synchronisation as HIP errors.
  *  - Q, R, Qf must be symmetric; R must be positive definite (its Cholesky factor is taken; a
  *    non-positive-definite R yields NaN outputs, not an error code).
+ *  - Finite check: with the environment variable LQT_CHECK_FINITE set to a value other than "0",
+ *    every single-problem entry point (lqt_build_elements*, lqt_scan_value, lqt_forward_traj*,
+ *    lqt_dense_output, lqt_solve, lqt_backward) scans its outputs for NaN and Inf on `stream`
+ *    after its kernels, waits for the stream, and returns LQT_ENONFINITE if any is found (the
+ *    outputs are still written).  The (I + C J) systems of the combination rule are
+ *    non-singular for symmetric positive semidefinite C, J (Lemma 10), so a breakdown of the
+ *    pivoted elimination needs invalid inputs (e.g. an indefinite Q) and shows up as non-finite
+ *    outputs, which this check reports.  The check costs one synchronisation per call; the
+ *    batched calls and plans do not run it.  Unset, nothing is scanned and calls stay
+ *    asynchronous.  The check uses 256 bytes at the end of the workspace (included in
+ *    lqt_workspace_size).
  *  - Supported sizes: 1 <= nu <= nx <= 16; T >= 1; 1 <= n_steps <= 4096; batch >= 1.
  */
 #ifndef LQT_H
@@ -57,7 +68,8 @@ typedef enum lqt_status {
   LQT_EINVAL = -1,       /* an argument is invalid (null pointer, size out of range, ...)        */
   LQT_EUNSUPPORTED = -2, /* a valid request outside what this build implements                   */
   LQT_EWORKSPACE = -3,   /* workspace pointer missing, misaligned or smaller than required       */
-  LQT_EHIP = -4          /* a HIP runtime call (kernel launch) failed                            */
+  LQT_EHIP = -4,         /* a HIP runtime call (kernel launch) failed                            */
+  LQT_ENONFINITE = -5    /* an output holds NaN or Inf (only with LQT_CHECK_FINITE set, below)   */
 } lqt_status;
 
 typedef enum lqt_dtype { LQT_F64 = 0, LQT_F32 = 1 } lqt_dtype;

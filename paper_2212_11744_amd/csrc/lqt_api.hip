@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <string>
 
 #include "../../include/lqt.h"
@@ -80,6 +81,8 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
   };
   void* consts = take(es * nconsts * consts_count(d->nx, d->nu));
   if (w) w->consts = consts;
+  void* fl = take(256);  // finite-check flag (taken here: the wave branch below returns early)
+  if (w) w->flag = (int*)fl;
   if (d->lti && !use_wave(d) && (call == LQT_CALL_BUILD || call == LQT_CALL_SOLVE)) {
     void* t = take(es * nconsts * lti_count(d->nx, d->n_steps));
     if (w) w->lti = t;
@@ -240,6 +243,77 @@ lqt_status check_ws(const lqt_dims* d, lqt_call call, void* ws, size_t ws_bytes,
       return fail(LQT_EHIP, "%s failed: %s", #x, hipGetErrorString(_e));            \
   } while (0)
 
+// ------------------------------------------------------------------------------------------
+// Finite check of the outputs (LQT_CHECK_FINITE).
+// ------------------------------------------------------------------------------------------
+__global__ void k_flag_clear(int* flag) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *flag = 0;
+}
+
+// Plain arrays of n values.
+template <class R>
+__global__ void k_nonfinite(const R* __restrict__ a, long n, int* __restrict__ flag) {
+  bool bad = false;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    bad |= !isfinite(a[i]);
+  if (bad) *flag = 1;
+}
+
+// Elements in the tiled layout: only the columns of blocks k < T (tile padding is never written).
+template <class R>
+__global__ void k_nonfinite_elts(const R* __restrict__ e, int NE, long T, long pt, int batch,
+                                 int* __restrict__ flag) {
+  const long n = (long)batch * NE * T;
+  bool bad = false;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long k = i % T, q = (i / T) % NE, p = i / ((long)NE * T);
+    const long idx = p * NE * pt + (k >> 8) * (NE * 256L) + q * 256L + ((k & 3) << 6) + ((k & 255) >> 2);
+    bad |= !isfinite(e[idx]);
+  }
+  if (bad) *flag = 1;
+}
+
+bool finite_check_on() {
+  const char* v = getenv("LQT_CHECK_FINITE");
+  return v && *v && strcmp(v, "0") != 0;
+}
+
+struct Arr {
+  const void* p;  // nullptr: skipped
+  long n;         // values
+  bool elts;      // tiled element layout (n unused)
+};
+
+// Scans the arrays when LQT_CHECK_FINITE is set; LQT_ENONFINITE if any value is NaN or Inf.
+lqt_status finite_check(const lqt_dims* d, const Work& w, hipStream_t s,
+                        std::initializer_list<Arr> arrays) {
+  if (!finite_check_on()) return LQT_OK;
+  if (!w.flag) return fail(LQT_EWORKSPACE, "no finite-check flag in the workspace layout");
+  hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(64), 0, s, w.flag);
+  const dim3 g(1024), b(256);
+  for (const Arr& a : arrays) {
+    if (!a.p) continue;
+    if (a.elts) {
+      if (d->dtype == LQT_F64)
+        hipLaunchKernelGGL(k_nonfinite_elts<double>, g, b, 0, s, (const double*)a.p, (int)ne_of(d->nx),
+                           (long)d->T, padt(d->T), d->batch, w.flag);
+      else
+        hipLaunchKernelGGL(k_nonfinite_elts<float>, g, b, 0, s, (const float*)a.p, (int)ne_of(d->nx),
+                           (long)d->T, padt(d->T), d->batch, w.flag);
+    } else if (d->dtype == LQT_F64) {
+      hipLaunchKernelGGL(k_nonfinite<double>, g, b, 0, s, (const double*)a.p, a.n, w.flag);
+    } else {
+      hipLaunchKernelGGL(k_nonfinite<float>, g, b, 0, s, (const float*)a.p, a.n, w.flag);
+    }
+  }
+  int h = 0;
+  LQT_HIP(hipGetLastError());
+  LQT_HIP(hipMemcpyAsync(&h, w.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  LQT_HIP(hipStreamSynchronize(s));
+  if (h) return fail(LQT_ENONFINITE, "an output holds NaN or Inf (LQT_CHECK_FINITE)");
+  return LQT_OK;
+}
+
 lqt_status check_problem(const lqt_dims* d, const lqt_problem* p, bool need_r, bool need_x0) {
   const size_t es = dsize(d->dtype);
   if (!p) return fail(LQT_EINVAL, "problem is NULL");
@@ -343,6 +417,7 @@ lqt_status lqt_build_elements(const lqt_dims* dims, const lqt_problem* prob, voi
   } else {
     LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build(kp, elts, stream));
   }
+  LQT_TRY(finite_check(dims, w, stream, {{elts, 0, true}}));
   return ok();
 }
 
@@ -358,6 +433,7 @@ lqt_status lqt_build_elements_forward(const lqt_dims* dims, const lqt_problem* p
   KProb kp = make_kprob(dims, prob, w.consts);
   LQT_HIP(prep(dims, kp, w.consts, stream));
   LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build_fwd(kp, elts, stream));
+  LQT_TRY(finite_check(dims, w, stream, {{elts, 0, true}}));
   return ok();
 }
 
@@ -373,6 +449,7 @@ lqt_status lqt_build_elements_split(const lqt_dims* dims, const lqt_problem* pro
   KProb kp = make_kprob(dims, prob, w.consts);
   LQT_HIP(prep(dims, kp, w.consts, stream));
   LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build_split(kp, elts, stream));
+  LQT_TRY(finite_check(dims, w, stream, {{elts, 0, true}}));
   return ok();
 }
 
@@ -405,6 +482,8 @@ lqt_status lqt_forward_traj_method2(const lqt_dims* dims, const lqt_problem* pro
     LQT_HIP(o->m2_down(kp, w.vtup[l], t.n[l], w.vpart[l], w.vval[l + 1], t.n[l + 1], w.vval[l],
                        stream));
   LQT_HIP(o->m2_bottom(kp, elts, S, v, w.vval[1], t.n[1], x, u, stream));
+  const long nb = dims->batch, T1 = (long)dims->T + 1;
+  LQT_TRY(finite_check(dims, w, stream, {{x, nb * T1 * dims->nx, false}, {u, nb * T1 * dims->nu, false}}));
   return ok();
 }
 
@@ -428,6 +507,9 @@ lqt_status lqt_dense_output(const lqt_dims* dims, const lqt_problem* prob, const
   const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
   LQT_HIP(o->prep(kp, w.consts, stream));
   LQT_HIP(o->dense(kp, S, v, x, Sd, vd, xd, ud, stream));
+  const long nb = dims->batch, nodes = (long)dims->n_steps * dims->T + 1, nx = dims->nx;
+  LQT_TRY(finite_check(dims, w, stream, {{Sd, nb * nodes * nx * nx, false}, {vd, nb * nodes * nx, false},
+                                         {xd, nb * nodes * nx, false}, {ud, nb * nodes * dims->nu, false}}));
   return ok();
 }
 
@@ -449,10 +531,12 @@ lqt_status lqt_scan_value(const lqt_dims* dims, const void* elts, const void* Qf
   KProb kp = make_kprob(dims, &p, w.consts);
   if (use_wave(dims)) {
     LQT_HIP(wave_value(kp, dims->dtype, wtree_for(dims), w, elts, S, v, nullptr, stream));
-    return ok();
+  } else {
+    const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
+    LQT_TRY(run_value(o, kp, tree_for(dims), w, elts, S, v, nullptr, false, stream));
   }
-  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
-  LQT_TRY(run_value(o, kp, tree_for(dims), w, elts, S, v, nullptr, false, stream));
+  const long nb = dims->batch, T1 = (long)dims->T + 1, nx = dims->nx;
+  LQT_TRY(finite_check(dims, w, stream, {{S, nb * T1 * nx * nx, false}, {v, nb * T1 * nx, false}}));
   return ok();
 }
 
@@ -476,12 +560,14 @@ lqt_status lqt_forward_traj(const lqt_dims* dims, const lqt_problem* prob, const
   LQT_HIP(prep(dims, kp, w.consts, stream));
   if (use_wave(dims)) {
     LQT_HIP(wave_traj(kp, dims->dtype, wtree_for(dims), w, elts, S, v, x, u, false, stream));
-    return ok();
+  } else {
+    const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
+    const Tree t = tree_for(dims);
+    LQT_HIP(o->tbottom_reduce(kp, elts, S, v, w.tmap[1], t.n[1], stream));
+    LQT_TRY(run_traj(o, kp, t, w, elts, S, v, x, u, stream));
   }
-  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
-  const Tree t = tree_for(dims);
-  LQT_HIP(o->tbottom_reduce(kp, elts, S, v, w.tmap[1], t.n[1], stream));
-  LQT_TRY(run_traj(o, kp, t, w, elts, S, v, x, u, stream));
+  const long nb = dims->batch, T1 = (long)dims->T + 1;
+  LQT_TRY(finite_check(dims, w, stream, {{x, nb * T1 * dims->nx, false}, {u, nb * T1 * dims->nu, false}}));
   return ok();
 }
 
@@ -549,6 +635,10 @@ lqt_status lqt_solve(const lqt_dims* dims, const lqt_problem* prob, void* elts, 
   o.fused = false;
   o.wave_chunk = kWaveChunk;
   LQT_TRY(run_solve(dims, kp, w, e, S, v, x, u, o, stream));
+  const long nb = dims->batch, T1 = (long)dims->T + 1, nx = dims->nx;
+  LQT_TRY(finite_check(dims, w, stream, {{S, nb * T1 * nx * nx, false}, {v, nb * T1 * nx, false},
+                                         {x, nb * T1 * nx, false}, {u, nb * T1 * dims->nu, false},
+                                         {elts, 0, true}}));
   return ok();
 }
 
@@ -604,6 +694,11 @@ lqt_status lqt_backward(const lqt_dims* dims, const lqt_problem* prob, const voi
   LQT_HIP(ao->elem(kp, w.elts, S, v, x, w.lam, w.cst[1], t.n[1], dQf, drf, s));
   LQT_HIP(ao->rk4(kp, w.elts, dr, w.bnd, w.wsum, w.ckpt, w.ckpt != nullptr, s));
   LQT_HIP(ao->finish(kp, w.bnd, dr, w.wsum, dQ, dR, s));
+  const long nb = dims->batch, nx = dims->nx, nu = dims->nu;
+  const long ns = 2L * dims->n_steps * dims->T + 1;
+  LQT_TRY(finite_check(dims, w, s, {{dQ, nb * nx * nx, false}, {dR, nb * nu * nu, false},
+                                    {dr, nb * ns * nx, false}, {dx0, nb * nx, false},
+                                    {dQf, nb * nx * nx, false}, {drf, nb * nx, false}}));
   return ok();
 }
 
@@ -614,6 +709,7 @@ const char* lqt_status_string(lqt_status s) {
     case LQT_EUNSUPPORTED: return "unsupported";
     case LQT_EWORKSPACE: return "workspace missing or too small";
     case LQT_EHIP: return "HIP runtime error";
+    case LQT_ENONFINITE: return "non-finite output";
   }
   return "unknown status";
 }

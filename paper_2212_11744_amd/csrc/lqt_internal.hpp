@@ -104,6 +104,7 @@ struct Work {
   void* wsum = nullptr;              // per-wave sums of the Q and G adjoints
   void* ckpt = nullptr;              // RK4 step start values of every block (nullptr: recompute)
   void* lti = nullptr;               // time-invariant path tables, [batch][lti_count]
+  int* flag = nullptr;               // finite check: set to 1 when an output is NaN or Inf
 };
 
 // Largest n_steps for which the adjoint keeps the RK4 step start values of every block in the

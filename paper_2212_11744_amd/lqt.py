@@ -26,7 +26,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblqt.so")
 
-LQT_OK, LQT_EINVAL, LQT_EUNSUPPORTED, LQT_EWORKSPACE, LQT_EHIP = 0, -1, -2, -3, -4
+LQT_OK, LQT_EINVAL, LQT_EUNSUPPORTED, LQT_EWORKSPACE, LQT_EHIP, LQT_ENONFINITE = 0, -1, -2, -3, -4, -5
 LQT_F64, LQT_F32 = 0, 1
 CALL_BUILD, CALL_SCAN_VALUE, CALL_FORWARD_TRAJ, CALL_SOLVE, CALL_BACKWARD, CALL_TRAJ_METHOD2 = range(6)
 

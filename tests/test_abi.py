@@ -30,6 +30,7 @@ def test_element_count_and_version():
     assert lqt.element_count(16) == 2 * 256 + 48
     assert lqt.lib().lqt_version() >= 100
     assert lqt.lib().lqt_status_string(lqt.LQT_EWORKSPACE).decode().startswith("workspace")
+    assert lqt.lib().lqt_status_string(lqt.LQT_ENONFINITE).decode() == "non-finite output"
 
 
 def _dims(**kw):
