@@ -921,6 +921,242 @@ __global__ __launch_bounds__(64) void kw_build_rows(const KProb kp, R* __restric
 }
 
 // ------------------------------------------------------------------------------------------
+// Element build at nx = 16 in FP64 on the matrix cores, one wave per block.  Every 16 x 16
+// matrix of the RK4 state (A - I, J: start value, stage value, accumulator; C: accumulator) stays
+// in registers in the result layout of v_mfma_f64_16x16x4f64 (lane 16 q + j holds entries
+// (q + 4 r, j), r = 0..3); only the stage values of A, J and the stage's K go through LDS (rows
+// padded to 17 values) to become matrix-core operands.  Per stage:
+//   publish A, J, eta  | K = G J - F (MFMA from -F),  w = G eta + c,  (A Lc) = Lc + A Lc
+//   publish K, w       | kA = K + A K,  kJ = -Q + J K - F^T J,  kC = -(A Lc)(A Lc)^T (MFMA),
+//                      | keta = K^T eta + J c - Q r,  kb = -(w + A w); RK4 updates in registers.
+// Two barriers per stage.  J and C take their upper entries after every step (as the oracle).
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void kw_build_mfma16(const KProb kp, double* __restrict__ elts) {
+  constexpr int N = 16, P = 17;
+  typedef double R;
+  __shared__ R sA[N * P], sJ[N * P], sK[N * P], sG[N * P], sF[N * P], sQ[N * P], sL[N * P];
+  __shared__ R se[N], sw[N], sr[N], sc[N];
+  const int lane = lane_id(), li = lane & 15, lq = lane >> 4;
+  const int nu = kp.nu;
+  const long T = kp.T;
+  const int nn = kp.n;
+  const long k = blockIdx.x;
+  int p = blockIdx.y;
+  long s0 = (long)p * (2L * nn * T + 1), tk = (long)p * (T + 1) + k, pf = 0;
+  bool sep = false;
+  if (kp.seg) {
+    p = seg_find(kp.seg, kp.nseg, k);
+    sep = k == kp.seg[p + 1] - 1 || k == T - 1;
+    s0 = (long)p * (1 - 2L * nn);
+    tk = k;
+    pf = p;
+  }
+  const GRef<R> o = elt_ref(elts, kp.seg ? 0 : p, k, T, ne_w(N));
+  const int ns = N * (N + 1) / 2;
+  const int oB = N * N, oC = oB + N, oE = oC + ns, oJ = oE + N;
+  if (sep) {  // separator after problem p (see KProb): A - I = -I, b = next x0, C = 0, J = Qf
+    const R* Qf = (const R*)kp.Qf + (long)p * N * N;
+    const R* rf = (const R*)kp.rf + (long)p * N;
+    for (int e = lane; e < N * N; e += 64) {
+      const int i = e / N, j = e % N;
+      o.g[e * o.st] = i == j ? R(-1) : R(0);
+      if (j >= i) {
+        o.g[(oC + pk(i, j, N)) * o.st] = R(0);
+        o.g[(oJ + pk(i, j, N)) * o.st] = Qf[i * N + j];
+      }
+    }
+    if (lane < N) {
+      R e = R(0);
+      for (int q = 0; q < N; ++q) e = fma(Qf[lane * N + q], rf[q], e);
+      o.g[(oB + lane) * o.st] = p + 1 >= kp.nseg ? R(0) : ((const R*)kp.x0)[(long)(p + 1) * N + lane];
+      o.g[(oE + lane) * o.st] = e;
+    }
+    return;
+  }
+  const R* cs = (const R*)kp.consts + (long)p * consts_count(N, nu);
+  const R* Qp = (const R*)kp.Q + (long)p * N * N;
+  const R* Fc = (const R*)kp.F + pf * N * N;
+  // per-block constants in LDS: G, Q, F (constant case), Lc
+  for (int e = lane; e < N * N; e += 64) {
+    const int i = e / N, j = e % N;
+    sG[i * P + j] = cs[consts_off_G(N, nu) + e];
+    sQ[i * P + j] = Qp[e];
+    if (!kp.F_sampled) sF[i * P + j] = Fc[e];
+  }
+  for (int e = lane; e < N * nu; e += 64) sL[(e / nu) * P + e % nu] = cs[consts_off_Lc(N, nu) + e];
+  const R* W = cs + consts_off_W(N, nu);
+  const R h = (((const R*)kp.t)[tk + 1] - ((const R*)kp.t)[tk]) / R(nn);
+  // state in the MFMA result layout: entry (lq + 4 r, li)
+  R yA[4], yJ[4], yC[4], aA[4], aJ[4], tA[4], tJ[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) yA[r] = yJ[r] = yC[r] = R(0);
+  R ye = R(0), yb = R(0), ae = R(0), te = R(0);  // lanes < 16: component li
+  wsync();
+  for (int m = 0; m < nn; ++m) {
+    const long j1 = 2L * nn * k + 2L * (nn - m);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      tA[r] = yA[r];
+      tJ[r] = yJ[r];
+    }
+    te = ye;
+    for (int st = 0; st < 4; ++st) {
+      const long j = st == 0 ? j1 : (st == 3 ? j1 - 2 : j1 - 1);
+      const R wk = (st == 0 || st == 3) ? -h / R(6) : -h / R(3);
+      const R cn = st == 2 ? -h : -h / R(2);
+      // samples of this stage; stage values of A, J, eta as operands
+      if (lane < N) {
+        sr[lane] = ((const R*)kp.r)[(s0 + j) * N + lane];
+        sc[lane] = kp.has_c ? ((const R*)kp.c)[(s0 + j) * N + lane] : R(0);
+        se[lane] = te;
+      }
+      if (kp.F_sampled) {
+        const R* Fj = (const R*)kp.F + (s0 + j) * N * N;
+        for (int e = lane; e < N * N; e += 64) sF[(e / N) * P + e % N] = Fj[e];
+      }
+      if (kp.L_sampled) {  // Lc = L(t_j) W, G = Lc Lc^T
+        const R* Lj = (const R*)kp.L + (s0 + j) * N * nu;
+        for (int e = lane; e < N * nu; e += 64) {
+          const int i = e / nu, l = e % nu;
+          R a = R(0);
+          for (int q = 0; q < nu; ++q) a = fma(Lj[i * nu + q], W[q * nu + l], a);
+          sL[i * P + l] = a;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        sA[(lq + 4 * r) * P + li] = tA[r];
+        sJ[(lq + 4 * r) * P + li] = tJ[r];
+      }
+      wsync();
+      if (kp.L_sampled) {
+        for (int e = lane; e < N * N; e += 64) {
+          const int i = e / N, q = e % N;
+          R a = R(0);
+          for (int l = 0; l < nu; ++l) a = fma(sL[i * P + l], sL[q * P + l], a);
+          sG[i * P + q] = a;
+        }
+        wsync();
+      }
+      // K = G J - F
+      wd4 K;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) K[r] = -sF[(lq + 4 * r) * P + li];
+#pragma unroll
+      for (int k0 = 0; k0 < N; k0 += 4) {
+        const int kk = k0 + lq;
+        K = __builtin_amdgcn_mfma_f64_16x16x4f64(sG[li * P + kk], sJ[kk * P + li], K, 0, 0, 0);
+      }
+      // w = G eta + c (lanes < 16)
+      R w = R(0);
+      if (lane < N) {
+        w = sc[li];
+        for (int q = 0; q < N; ++q) w = fma(sG[li * P + q], se[q], w);
+      }
+      // (A Lc)(i, m) for i = li, m = 4 kb + lq: Lc + (A - I) Lc
+      R AL[4];
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        const int mm = 4 * kb + lq;
+        R a = R(0);
+        if (mm < nu) {
+          a = sL[li * P + mm];
+          for (int q = 0; q < N; ++q) a = fma(sA[li * P + q], sL[q * P + mm], a);
+        }
+        AL[kb] = a;
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sK[(lq + 4 * r) * P + li] = K[r];
+      if (lane < N) sw[lane] = w;
+      wsync();
+      // kA = K + (A - I) K
+      wd4 kA = K;
+#pragma unroll
+      for (int k0 = 0; k0 < N; k0 += 4) {
+        const int kk = k0 + lq;
+        kA = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[li * P + kk], sK[kk * P + li], kA, 0, 0, 0);
+      }
+      // kJ = -Q + J K - F^T J
+      wd4 kJ;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) kJ[r] = -sQ[(lq + 4 * r) * P + li];
+#pragma unroll
+      for (int k0 = 0; k0 < N; k0 += 4) {
+        const int kk = k0 + lq;
+        kJ = __builtin_amdgcn_mfma_f64_16x16x4f64(sJ[li * P + kk], sK[kk * P + li], kJ, 0, 0, 0);
+      }
+#pragma unroll
+      for (int k0 = 0; k0 < N; k0 += 4) {
+        const int kk = k0 + lq;
+        kJ = __builtin_amdgcn_mfma_f64_16x16x4f64(-sF[kk * P + li], sJ[kk * P + li], kJ, 0, 0, 0);
+      }
+      // kC = -(A Lc)(A Lc)^T: operand (li, 4 kb + lq) of both factors is this lane's AL[kb]
+      wd4 kC = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb)
+        if (4 * kb < nu) kC = __builtin_amdgcn_mfma_f64_16x16x4f64(AL[kb], AL[kb], kC, 0, 0, 0);
+      // keta = K^T eta + J c - Q r;  kb = -(w + (A - I) w)   (lanes < 16, component li)
+      R ke = R(0), kbv = R(0);
+      if (lane < N) {
+        R a = R(0), b = sw[li];
+        for (int q = 0; q < N; ++q) {
+          a = fma(sK[q * P + li], se[q], a);
+          if (kp.has_c) a = fma(sJ[li * P + q], sc[q], a);
+          a = fma(-sQ[li * P + q], sr[q], a);
+          b = fma(sA[li * P + q], sw[q], b);
+        }
+        ke = a;
+        kbv = -b;
+      }
+      // RK4 accumulation and the next stage value
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        aA[r] = st == 0 ? fma(wk, kA[r], yA[r]) : fma(wk, kA[r], aA[r]);
+        aJ[r] = st == 0 ? fma(wk, kJ[r], yJ[r]) : fma(wk, kJ[r], aJ[r]);
+        yC[r] = fma(-wk, kC[r], yC[r]);
+        if (st < 3) {
+          tA[r] = fma(cn, kA[r], yA[r]);
+          tJ[r] = fma(cn, kJ[r], yJ[r]);
+        }
+      }
+      ae = st == 0 ? fma(wk, ke, ye) : fma(wk, ke, ae);
+      yb = fma(wk, kbv, yb);
+      if (st < 3) te = fma(cn, ke, ye);
+      wsync();  // the next stage overwrites the operand buffers
+    }
+    // end of step: J and C take their upper entries
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      yA[r] = aA[r];
+      sJ[(lq + 4 * r) * P + li] = aJ[r];
+      sK[(lq + 4 * r) * P + li] = yC[r];
+    }
+    ye = ae;
+    wsync();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = lq + 4 * r;
+      yJ[r] = i > li ? sJ[li * P + i] : aJ[r];
+      yC[r] = i > li ? sK[li * P + i] : yC[r];
+    }
+    wsync();
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = lq + 4 * r;
+    o.g[(i * N + li) * o.st] = yA[r];
+    if (li >= i) {
+      o.g[(oC + pk(i, li, N)) * o.st] = yC[r];
+      o.g[(oJ + pk(i, li, N)) * o.st] = yJ[r];
+    }
+  }
+  if (lane < N) {
+    o.g[(oB + lane) * o.st] = yb;
+    o.g[(oE + lane) * o.st] = ye;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Value tree.
 // ------------------------------------------------------------------------------------------
 template <int N, class R>
@@ -1308,6 +1544,9 @@ hipError_t wave_build_t(const KProb& kp, void* elts, hipStream_t s) {
   if constexpr (N <= 8)
     hipLaunchKernelGGL((kw_build_rows<N, R>), dim3((unsigned)((kp.T + 7) / 8), kp.batch), dim3(64),
                        0, s, kp, (R*)elts);
+  else if constexpr (kMfma<N, R>)
+    hipLaunchKernelGGL(kw_build_mfma16, dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
+                       (double*)elts);
   else
     hipLaunchKernelGGL((kw_build<N, R>), dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
                        (R*)elts);
