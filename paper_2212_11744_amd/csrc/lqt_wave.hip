@@ -61,6 +61,44 @@ WDEV void w_gemm16(double* C, const double* A, const double* B, int kk, bool tA,
 template <int N, class R>
 constexpr bool kMfma = N == 16 && sizeof(R) == 8;
 
+// C = alpha * op(A) op(B) + beta * D for a 16 x 16 result with row strides ldc, lda, ldb, ldd
+// (op(A)(i, k) = tA ? A[k lda + i] : A[i lda + k], likewise B; D nullable, may be C).
+WDEV void w_mm16(double* C, int ldc, const double* A, int lda, bool tA, const double* B, int ldb,
+                 bool tB, int kk, double alpha, const double* D, int ldd, double beta) {
+  const int l = lane_id(), li = l & 15, lq = l >> 4;
+  wd4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < kk; k0 += 4) {
+    const int k = k0 + lq;
+    const double a = tA ? A[k * lda + li] : A[li * lda + k];
+    const double b = tB ? B[li * ldb + k] : B[k * ldb + li];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  wsync();  // C may be an operand
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = lq + 4 * r;
+    double v = alpha * acc[r];
+    if (D) v = fma(beta, D[i * ldd + li], v);
+    C[i * ldc + li] = v;
+  }
+  wsync();
+}
+
+// M (16 x 16, row-major) <- its upper triangle mirrored, plus the upper triangle of `add`.
+WDEV void w_symadd16(double* M, const double* add) {
+  double t[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int e = lane_id() + 64 * c, i = e >> 4, j = e & 15;
+    const int u = i < j ? i * 16 + j : j * 16 + i;
+    t[c] = M[u] + add[u];
+  }
+  wsync();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) M[lane_id() + 64 * c] = t[c];
+  wsync();
+}
+
 // C = alpha * op(A) op(B) + beta * C for n x n (or m x p) matrices in LDS, row-major, ld = cols.
 // MF: 16 x 16 FP64 products (inner dimension a multiple of 4) go to the matrix cores.
 template <bool MF = false, class R>
@@ -277,6 +315,43 @@ WDEV void w_combine(WT<R> x1, WT<R> x2, WT<R> o, WS<R> s, int n) {
   }
   wsync();
   w_solve<N>(s.M, s.B, n, nb, s.f, s.piv);
+  if constexpr (kMfma<N, R>) {
+    // The same products on the matrix cores; every result goes to scratch first (o may be x2).
+    const int l = lane_id();
+    w_mm16(s.X, 16, x2.A, 16, false, s.B + n, nb, false, 16, 1.0, s.B + n, nb, 1.0);  // W
+    w_mm16(s.Y, 16, s.X, 16, false, x2.A, 16, true, 16, 1.0, s.X, 16, 1.0);  // W (I + Ad2)^T
+    w_symadd16(s.Y, x2.C);                                                   // C
+    R bn = R(0), en = R(0);
+    if (l < n) {
+      R t = R(0);
+      for (int k = 0; k < n; ++k) t = fma(x2.A[l * n + k], s.B[k * nb + 2 * n], t);
+      bn = x2.b[l] + s.B[l * nb + 2 * n] + t;
+      R u = x2.e[l];
+      for (int k = 0; k < n; ++k) u = fma(-x2.J[l * n + k], x1.b[k], u);
+      s.f[l] = u;
+    }
+    w_mm16(s.X, 16, x2.J, 16, false, x1.A, 16, false, 16, 1.0, x2.J, 16, 1.0);  // P
+    w_mm16(s.M, 16, s.B, nb, true, s.X, 16, false, 16, 1.0, s.X, 16, 1.0);     // (I + Yd)^T P
+    w_symadd16(s.M, x1.J);                                                      // J
+    w_mm16(s.X, 16, x2.A, 16, false, s.B, nb, false, 16, 1.0, s.B, nb, 1.0);   // Yd + Ad2 Yd
+    if (l < n) {
+      R t = R(0);
+      for (int k = 0; k < n; ++k) t = fma(s.B[k * nb + l], s.f[k], t);
+      en = x1.e[l] + (s.f[l] + t);
+    }
+    wsync();
+    for (int e = l; e < n * n; e += 64) {
+      o.J[e] = s.M[e];
+      o.A[e] = x2.A[e] + s.X[e];
+      o.C[e] = s.Y[e];
+    }
+    if (l < n) {
+      o.b[l] = bn;
+      o.e[l] = en;
+    }
+    wsync();
+    return;
+  }
   // W = (I + Ad2) D -> X;  C = W (I + Ad2)^T + C2 -> Y
   for (int e = lane_id(); e < n * n; e += 64) {
     const int i = e / n, j = e % n;
@@ -376,6 +451,23 @@ WDEV void w_fold(WT<R> a, R* S, R* v, WS<R> s, int n, R* P, R* q) {
     R t = v[i];
     for (int k = 0; k < n; ++k) t = fma(-S[i * n + k], a.b[k], t);
     s.f[i] = t;
+  }
+  if constexpr (kMfma<N, R>) {
+    w_mm16(s.X, 16, S, 16, false, a.A, 16, false, 16, 1.0, S, 16, 1.0);     // S (I + Ad)
+    w_mm16(s.M, 16, s.B, nb, true, s.X, 16, false, 16, 1.0, s.X, 16, 1.0);  // (I + Yd)^T X
+    w_symadd16(s.M, a.J);
+    const int i = lane_id();
+    R vn = R(0);
+    if (i < n) {
+      R t = R(0);
+      for (int k = 0; k < n; ++k) t = fma(s.B[k * nb + i], s.f[k], t);
+      vn = a.e[i] + (s.f[i] + t);
+    }
+    wsync();
+    for (int e = i; e < n * n; e += 64) S[e] = s.M[e];
+    if (i < n) v[i] = vn;
+    wsync();
+    return;
   }
   for (int e = lane_id(); e < n * n; e += 64) {
     const int i = e / n, j = e % n;
