@@ -170,12 +170,14 @@ class DeviceProblem:
             if (p.nx, p.nu, p.T, p.n) != (p0.nx, p0.nu, p0.T, p0.n):
                 raise ValueError("batched problems must share nx, nu, T and n")
         F_s, L_s = np.ndim(p0.F) == 3, np.ndim(p0.L) == 3
+        has_c = getattr(p0, "c", None) is not None
+        for i, p in enumerate(problems):
+            _check_arrays(p, i, F_s, L_s, has_c)
         for name, sampled in (("F", F_s), ("L", L_s)):
             if not sampled and any(not np.array_equal(getattr(p, name), getattr(p0, name)) for p in problems):
                 raise ValueError(f"a constant {name} is shared by the batch: members differ")
         to = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
         stack = lambda name: to(np.stack([np.asarray(getattr(p, name)) for p in problems]))
-        has_c = getattr(p0, "c", None) is not None
         if lti:
             if F_s or L_s or has_c:
                 raise ValueError("the time-invariant path needs constant F, L and no drift")
@@ -187,6 +189,25 @@ class DeviceProblem:
                    stack("t"), stack("F") if F_s else to(p0.F), stack("L") if L_s else to(p0.L),
                    stack("Q"), stack("R"), stack("r"), stack("Qf"), stack("rf"), stack("x0"),
                    stack("c") if has_c else None, F_s, L_s, lti)
+
+
+def _check_arrays(p, i: int, F_s: bool, L_s: bool, has_c: bool) -> None:
+    """Host check of one problem's arrays: the kernels index them by the dims alone, so a short
+    array would be read past its end.  Also: the grid must be strictly increasing."""
+    nx, nu, T, ns = p.nx, p.nu, p.T, 2 * p.n * p.T + 1
+    want = {"t": (T + 1,), "F": (ns, nx, nx) if F_s else (nx, nx),
+            "L": (ns, nx, nu) if L_s else (nx, nu), "Q": (nx, nx), "R": (nu, nu), "r": (ns, nx),
+            "Qf": (nx, nx), "rf": (nx,), "x0": (nx,)}
+    if has_c:
+        want["c"] = (ns, nx)
+    for name, shape in want.items():
+        a = getattr(p, name, None)
+        if a is None or np.shape(a) != shape:
+            raise ValueError(f"problem {i}: {name} has shape {np.shape(a)}, expected {shape}")
+    if (getattr(p, "c", None) is not None) != has_c:
+        raise ValueError(f"problem {i}: a drift c must be given for every member or none")
+    if not np.all(np.diff(np.asarray(p.t, dtype=np.float64)) > 0):
+        raise ValueError(f"problem {i}: the grid t must be strictly increasing")
 
 
 def element_count(nx: int) -> int:
@@ -414,6 +435,7 @@ class BatchedSolve:
         self.dtype, self.device = dtype, device
         keys, groups = [], {}
         for i, p in enumerate(problems):
+            _check_arrays(p, i, np.ndim(p.F) == 3, np.ndim(p.L) == 3, getattr(p, "c", None) is not None)
             k = _class_key(p)
             if k not in groups:
                 groups[k] = []

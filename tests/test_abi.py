@@ -138,3 +138,33 @@ def test_lti_flag_validation_and_workspace():
         p = lqt.Problem()
         assert L.lqt_build_elements(ctypes.byref(d), ctypes.byref(p), None, None, 0, None) == lqt.LQT_EINVAL
         assert b"lti" in L.lqt_last_error()
+
+
+def test_host_checks_of_problem_arrays():
+    """Array shapes and the grid are checked on the host before anything reaches the device (the
+    kernels index the arrays by the dims alone)."""
+    import numpy as np
+    from paper_2212_11744_amd import workloads as W
+    p = W.point_mass(1, 16, 2)
+    bad_r = W.point_mass(1, 16, 2)
+    bad_r.r = bad_r.r[:-1]
+    with pytest.raises(ValueError, match="r has shape"):
+        lqt.DeviceProblem.from_problems([p, bad_r], device="cpu")
+    bad_t = W.point_mass(1, 16, 2)
+    bad_t.t = bad_t.t.copy()
+    bad_t.t[5] = bad_t.t[4]
+    with pytest.raises(ValueError, match="strictly increasing"):
+        lqt.DeviceProblem.from_problems([bad_t], device="cpu")
+    bad_q = W.point_mass(1, 16, 2)
+    bad_q.Q = np.eye(3)
+    with pytest.raises(ValueError, match="Q has shape"):
+        lqt.DeviceProblem.from_problems([bad_q], device="cpu")
+
+
+def test_host_checks_of_batched_members():
+    from paper_2212_11744_amd import workloads as W
+    good = W.point_mass(1, 16, 2)
+    bad = W.point_mass(2, 20, 2)
+    bad.r = bad.r[:-3]
+    with pytest.raises(ValueError, match="problem 1: r has shape"):
+        lqt.BatchedSolve([good, bad], device="cpu", plan=False)
