@@ -1026,7 +1026,8 @@ __global__ __launch_bounds__(64) void kw_build_rows(const KProb kp, R* __restric
 __global__ __launch_bounds__(64) void kw_build_mfma16(const KProb kp, double* __restrict__ elts) {
   constexpr int N = 16, P = 17;
   typedef double R;
-  __shared__ R sA[N * P], sJ[N * P], sK[N * P], sG[N * P], sF[N * P], sQ[N * P], sL[N * P];
+  __shared__ R sA[N * P], sJ[N * P], sK[N * P], sG[N * P], sF[N * P], sQ[N * P], sL[N * P],
+      sAL[N * P];
   __shared__ R se[N], sw[N], sr[N], sc[N];
   const int lane = lane_id(), li = lane & 15, lq = lane >> 4;
   const int nu = kp.nu;
@@ -1139,28 +1140,34 @@ __global__ __launch_bounds__(64) void kw_build_mfma16(const KProb kp, double* __
         const int kk = k0 + lq;
         K = __builtin_amdgcn_mfma_f64_16x16x4f64(sG[li * P + kk], sJ[kk * P + li], K, 0, 0, 0);
       }
-      // w = G eta + c (lanes < 16)
+      // w = G eta + c: lanes 16 q + i sum terms 4 q .. 4 q + 3 of component i, then a butterfly
       R w = R(0);
-      if (lane < N) {
-        w = sc[li];
-        for (int q = 0; q < N; ++q) w = fma(sG[li * P + q], se[q], w);
-      }
-      // (A Lc)(i, m) for i = li, m = 4 kb + lq: Lc + (A - I) Lc
-      R AL[4];
 #pragma unroll
-      for (int kb = 0; kb < 4; ++kb) {
-        const int mm = 4 * kb + lq;
-        R a = R(0);
-        if (mm < nu) {
-          a = sL[li * P + mm];
-          for (int q = 0; q < N; ++q) a = fma(sA[li * P + q], sL[q * P + mm], a);
-        }
-        AL[kb] = a;
+      for (int t = 0; t < 4; ++t) w = fma(sG[li * P + 4 * lq + t], se[4 * lq + t], w);
+      w += __shfl_xor(w, 16);
+      w += __shfl_xor(w, 32);
+      w += sc[li];
+      // A Lc = Lc + (A - I) Lc on the matrix cores (Lc padded to 16 columns with zeros)
+      wd4 ALc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) ALc[r] = li < nu ? sL[(lq + 4 * r) * P + li] : R(0);
+#pragma unroll
+      for (int k0 = 0; k0 < N; k0 += 4) {
+        const int kk = k0 + lq;
+        ALc = __builtin_amdgcn_mfma_f64_16x16x4f64(sA[li * P + kk], li < nu ? sL[kk * P + li] : R(0),
+                                                   ALc, 0, 0, 0);
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sK[(lq + 4 * r) * P + li] = K[r];
+      for (int r = 0; r < 4; ++r) {
+        sK[(lq + 4 * r) * P + li] = K[r];
+        sAL[(lq + 4 * r) * P + li] = ALc[r];
+      }
       if (lane < N) sw[lane] = w;
       wsync();
+      // (A Lc)(li, 4 kb + lq): this lane's operand of both factors of -(A Lc)(A Lc)^T
+      R AL[4];
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) AL[kb] = 4 * kb + lq < nu ? sAL[li * P + 4 * kb + lq] : R(0);
       // kA = K + (A - I) K
       wd4 kA = K;
 #pragma unroll
@@ -1187,19 +1194,22 @@ __global__ __launch_bounds__(64) void kw_build_mfma16(const KProb kp, double* __
 #pragma unroll
       for (int kb = 0; kb < 4; ++kb)
         if (4 * kb < nu) kC = __builtin_amdgcn_mfma_f64_16x16x4f64(AL[kb], AL[kb], kC, 0, 0, 0);
-      // keta = K^T eta + J c - Q r;  kb = -(w + (A - I) w)   (lanes < 16, component li)
+      // keta = K^T eta + J c - Q r;  kb = -(w + (A - I) w): component li, terms 4 lq .. 4 lq + 3
+      // on lane 16 lq + li, then a butterfly over lq
       R ke = R(0), kbv = R(0);
-      if (lane < N) {
-        R a = R(0), b = sw[li];
-        for (int q = 0; q < N; ++q) {
-          a = fma(sK[q * P + li], se[q], a);
-          if (kp.has_c) a = fma(sJ[li * P + q], sc[q], a);
-          a = fma(-sQ[li * P + q], sr[q], a);
-          b = fma(sA[li * P + q], sw[q], b);
-        }
-        ke = a;
-        kbv = -b;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int q = 4 * lq + t;
+        ke = fma(sK[q * P + li], se[q], ke);
+        if (kp.has_c) ke = fma(sJ[li * P + q], sc[q], ke);
+        ke = fma(-sQ[li * P + q], sr[q], ke);
+        kbv = fma(sA[li * P + q], sw[q], kbv);
       }
+      ke += __shfl_xor(ke, 16);
+      ke += __shfl_xor(ke, 32);
+      kbv += __shfl_xor(kbv, 16);
+      kbv += __shfl_xor(kbv, 32);
+      kbv = -(kbv + sw[li]);
       // RK4 accumulation and the next stage value
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
