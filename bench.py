@@ -108,7 +108,7 @@ def main(argv=None):
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for "
+        print(f"bench.py measures one GPU only: the library has no multi-GPU path (asked for "
               f"--gpus {args.gpus}); the design notes describe how the solve would shard.",
               file=sys.stderr)
         return 2

@@ -66,7 +66,7 @@ extern "C" {
 typedef enum lqt_status {
   LQT_OK = 0,
   LQT_EINVAL = -1,       /* an argument is invalid (null pointer, size out of range, ...)        */
-  LQT_EUNSUPPORTED = -2, /* a valid request outside what this build implements                   */
+  LQT_EUNSUPPORTED = -2, /* a valid request outside what this library implements                 */
   LQT_EWORKSPACE = -3,   /* workspace pointer missing, misaligned or smaller than required       */
   LQT_EHIP = -4,         /* a HIP runtime call (kernel launch) failed                            */
   LQT_ENONFINITE = -5    /* an output holds NaN or Inf (only with LQT_CHECK_FINITE set, below)   */
@@ -282,7 +282,7 @@ lqt_status lqt_solve_batched(const lqt_ragged *classes, int32_t nclasses, void *
  * path; then concurrent or serial classes) by running them on `stream` (outputs are overwritten)
  * and keep the fastest; choices are cached per class signature for the life of the process
  * (thread-safe).  Without the flag the default configuration is used.  flags & LQT_PLAN_GRAPH
- * (capture the plan into a HIP graph) returns LQT_EUNSUPPORTED in this build.
+ * (capture the plan into a HIP graph) returns LQT_EUNSUPPORTED in this version of the library.
  * lqt_plan_create synchronises `stream`. */
 typedef struct lqt_plan_s *lqt_plan;
 enum { LQT_PLAN_AUTOTUNE = 1, LQT_PLAN_GRAPH = 2 };

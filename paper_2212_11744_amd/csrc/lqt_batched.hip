@@ -339,7 +339,7 @@ lqt_status lqt_plan_create(const lqt_ragged* classes, int32_t nclasses, void* ws
   if (flags & ~(LQT_PLAN_AUTOTUNE | LQT_PLAN_GRAPH)) return set_error(LQT_EINVAL, "unknown flags");
   if (flags & LQT_PLAN_GRAPH)
     return set_error(LQT_EUNSUPPORTED,
-                     "graph capture of a plan is switched off in this build (its first replay "
+                     "graph capture of a plan is switched off in this version (its first replay "
                      "crashed inside hipGraphLaunch; the cause is not established)");
   lqt_plan_s* p = new lqt_plan_s();
   lqt_status st = prepare(classes, nclasses, ws, ws_bytes, p->cls);
