@@ -47,7 +47,7 @@
  *    pivoted elimination needs invalid inputs (e.g. an indefinite Q) and shows up as non-finite
  *    outputs, which this check reports.  The check costs one synchronisation per call; the
  *    batched calls and plans do not run it.  Unset, nothing is scanned and calls stay
- *    asynchronous.  The check uses 256 bytes at the end of the workspace (included in
+ *    asynchronous.  The check uses a 256-byte slot of the workspace (included in
  *    lqt_workspace_size).
  *  - Supported sizes: 1 <= nu <= nx <= 16; T >= 1; 1 <= n_steps <= 4096; batch >= 1.
  */
