@@ -198,6 +198,7 @@ def main(argv=None):
                       "build_elements_split": ms_split, "dense_output": ms_dense},
     }
     rec["small"] = small_leg(torch, lqt, W, dtype)
+    rec["t2p16"] = t2p16_leg(torch, lqt, W, dtype)
     if not args.no_lti:
         rec["lti"] = lti_leg(torch, lqt, p, dtype, args.steps, out, T)
     if not args.no_adjoint:
@@ -231,6 +232,22 @@ def lti_leg(torch, lqt, p, dtype, reps, out, T):
     ms_b = _events_time(lambda: lqt.build_elements(dp, out["elts"], ws_b), reps, torch)
     return {"workload": "same problem, time-invariant path (F, L constant, c = 0, uniform grid)",
             "ms_per_step": ms, "sub_intervals_per_s": T / (ms * 1e-3), "build_ms": ms_b}
+
+
+def t2p16_leg(torch, lqt, W, dtype):
+    """The same point-mass generator at T = 2^16 blocks x 4 RK4 steps (the smaller size of the
+    benchmark configuration): solve time and throughput."""
+    T = 2 ** 16
+    p = W.point_mass(2, T, 4)
+    dp = lqt.DeviceProblem.from_problems([p], dtype=dtype)
+    out = lqt.solve(dp, keep_elements=True)
+    ws = lqt.workspace(dp, lqt.CALL_SOLVE)
+    solve = lambda: lqt.solve(dp, out, ws)
+    solve()
+    torch.cuda.synchronize()
+    ms = _events_time(solve, 50, torch)
+    return {"workload": "point-mass LQT tracking, T=65536 blocks x 4 RK4 steps on [0,10]",
+            "ms_per_step": ms, "sub_intervals_per_s": T / (ms * 1e-3)}
 
 
 def small_leg(torch, lqt, W, dtype):
