@@ -10,13 +10,16 @@
 //   Alg::init(kp, aux, p, state)     the state at the free end of the horizon (terminal value,
 //                                    initial state, ...).
 //
-// A level reduces 4 consecutive nodes per lane serially, then the 64 lanes of a wave by a
-// Blelloch tree in registers; the downward pass replays the tree from the wave's boundary state
-// and then each lane's 4 nodes.  The orientation decides which end of a block is "free":
-//   backward: lane m absorbs lane m + 2^s (its later neighbour); lane 0 holds the wave product,
-//             the boundary state enters at lane 0 (right end) and flows to earlier lanes;
-//   forward:  lane r absorbs lane r - 2^s (its earlier neighbour); lane 63 holds the product and
-//             the boundary state (left end) enters at the block's last lane.
+// A level reduces 4 consecutive nodes per lane serially, then scans the 64 lane products of a wave
+// in registers by recursive doubling (every lane combines with the lane 2^s away at step s), so
+// that each lane ends with the product of every lane between itself and the wave's free end.  The
+// upward pass stores that exclusive product per lane; the downward pass then needs one
+// application per lane to carry the wave's boundary state to the lane's range, where a tree
+// replay would need one per level.  The orientation decides which end is "free":
+//   backward: lane m absorbs lane m + 2^s (its later neighbour); lane 0 ends with the wave
+//             product and the boundary state enters at the right end (after lane 63);
+//   forward:  lane r absorbs lane r - 2^s (its earlier neighbour); lane 63 ends with the product
+//             and the boundary state enters at the left end (before lane 0).
 #pragma once
 
 #include "lane_math.hpp"
@@ -55,48 +58,36 @@ LQT_DEV void serial_chain(const R* __restrict__ s, long j0, long j1, typename Al
   }
 }
 
+// Inclusive scan of the lane products over `levels` doubling steps: on return P holds the product
+// of lanes [lane, lane + 2^levels) (backward) or (lane - 2^levels, lane] (forward), clipped to
+// the wave.  With 2^levels >= the number of lanes holding data, that is every later (earlier)
+// data lane.
 template <class Alg>
-LQT_DEV void wave_up(typename Alg::Map& P, int lane, int levels = 6) {
+LQT_DEV void wave_scan(typename Alg::Map& P, int lane, int levels = 6) {
   for (int s = 0; s < levels; ++s) {
     const int d = 1 << s;
     typename Alg::Map y;
     if (!Alg::kForward) {
       Alg::shfl_map(P, y, min(lane + d, 63));
-      if ((lane & (2 * d - 1)) == 0) Alg::chain(P, y, P);
+      if (lane + d < 64) Alg::chain(P, y, P);
     } else {
       Alg::shfl_map(P, y, max(lane - d, 0));
-      if ((lane & (2 * d - 1)) == 2 * d - 1) Alg::chain(y, P, P);
+      if (lane >= d) Alg::chain(y, P, P);
     }
   }
 }
 
+// The lane nearest the wave's free end: its range borders the boundary directly.
 template <class Alg>
-LQT_DEV void wave_down(const typename Alg::Map& P, typename Alg::State& st, int lane,
-                       int levels = 6) {
-  using State = typename Alg::State;
-  for (int s = levels - 1; s >= 0; --s) {
-    const int d = 1 << s;
-    int holder, worker, other;  // holder: lane with the block's boundary state
-    if (!Alg::kForward) {
-      holder = lane & ~(2 * d - 1);  // left lane holds the right-end state of the block
-      worker = holder + d;           // right half: carries it across its product
-      other = holder;
-    } else {
-      holder = lane | (2 * d - 1);   // right lane holds the left-end state of the block
-      worker = holder - d;           // left half: carries it across its product
-      other = holder;
-    }
-    State sb;
-    Alg::shfl_state(st, sb, holder);
-    State sw = sb;
-    if (lane == worker) Alg::apply(P, sw);
-    State sx;
-    Alg::shfl_state(sw, sx, worker);
-    if (lane == worker)
-      st = sb;
-    else if (lane == other)
-      st = sx;
-  }
+LQT_DEV constexpr int edge_lane() {
+  return Alg::kForward ? 0 : 63;
+}
+
+// Exclusive form of wave_scan's result: the product of the lanes strictly between this lane and
+// the free end (undefined on the edge lane, which must not use it).
+template <class Alg>
+LQT_DEV void wave_exclusive(const typename Alg::Map& I, typename Alg::Map& E, int lane) {
+  Alg::shfl_map(I, E, Alg::kForward ? max(lane - 1, 0) : min(lane + 1, 63));
 }
 
 // Serial downward sweep over the <= 4 nodes [j0, j1): node j receives the state at its free end,
@@ -123,7 +114,7 @@ LQT_DEV void serial_states(const R* __restrict__ mp, long j0, long j1, typename 
   }
 }
 
-// Level l -> l + 1: 256 nodes per wave; lane partials kept for the downward pass.
+// Level l -> l + 1: 256 nodes per wave; each lane's exclusive product kept for the downward pass.
 template <class Alg, class R>
 __global__ __launch_bounds__(64) void k_up(const R* __restrict__ src, long n_src,
                                            R* __restrict__ part, R* __restrict__ dst,
@@ -136,12 +127,14 @@ __global__ __launch_bounds__(64) void k_up(const R* __restrict__ src, long n_src
   const long j0 = gl * kChunk, j1 = min(j0 + kChunk, n_src);
   typename Alg::Map P;
   serial_chain<Alg, R>(src + (long)p * Alg::NMAP * padt(n_src), j0, j1, P);
-  wave_up<Alg>(P, lane);
-  Alg::store(P, part + (long)p * Alg::NMAP * padt(n_dst * 64), gl);
+  wave_scan<Alg>(P, lane);
   if (lane == (Alg::kForward ? 63 : 0)) Alg::store(P, dst + (long)p * Alg::NMAP * padt(n_dst), w);
+  typename Alg::Map E;
+  wave_exclusive<Alg>(P, E, lane);
+  Alg::store(E, part + (long)p * Alg::NMAP * padt(n_dst * 64), gl);
 }
 
-// Top level (<= 256 nodes, one wave): up-sweep, boundary state from Alg::init, downward pass.
+// Top level (<= 256 nodes, one wave): scan, boundary state from Alg::init, carried to every lane.
 template <class Alg, class R>
 __global__ __launch_bounds__(64) void k_top(const KProb kp, const R* __restrict__ aux,
                                             const R* __restrict__ src, long n,
@@ -154,10 +147,14 @@ __global__ __launch_bounds__(64) void k_top(const KProb kp, const R* __restrict_
   const int levels = tree_levels(active);
   typename Alg::Map P;
   serial_chain<Alg, R>(mp, j0, j1, P);
-  wave_up<Alg>(P, lane, levels);
+  wave_scan<Alg>(P, lane, levels);
+  typename Alg::Map E;
+  wave_exclusive<Alg>(P, E, lane);
   typename Alg::State st;
   Alg::init(kp, aux, p, st);
-  wave_down<Alg>(P, st, lane, levels);
+  // Only lanes with data and with data lanes between them and the free end carry the state (with
+  // one data lane, as at the top of a long horizon, the branch is skipped by the whole wave).
+  if (lane < active && (Alg::kForward ? lane > 0 : lane + 1 < active)) Alg::apply(E, st);
   serial_states<Alg, R>(mp, j0, j1, st, out + (long)p * Alg::NST * padt(n));
 }
 
@@ -174,9 +171,11 @@ __global__ __launch_bounds__(64) void k_down(const R* __restrict__ src, long n_c
   if (w >= n_par) return;
   typename Alg::State st;
   Alg::sload(st, st_par + (long)p * Alg::NST * padt(n_par), w);
-  typename Alg::Map P;
-  Alg::load(P, part + (long)p * Alg::NMAP * padt(n_par * 64), gl);
-  wave_down<Alg>(P, st, lane);
+  if (lane != edge_lane<Alg>()) {
+    typename Alg::Map E;
+    Alg::load(E, part + (long)p * Alg::NMAP * padt(n_par * 64), gl);
+    Alg::apply(E, st);
+  }
   const long j0 = gl * kChunk, j1 = min(j0 + kChunk, n_child);
   serial_states<Alg, R>(src + (long)p * Alg::NMAP * padt(n_child), j0, j1, st,
                         st_child + (long)p * Alg::NST * padt(n_child));
