@@ -134,7 +134,8 @@ __global__ __launch_bounds__(64) void k_up(const R* __restrict__ src, long n_src
   Alg::store(E, part + (long)p * Alg::NMAP * padt(n_dst * 64), gl);
 }
 
-// Top level (<= 256 nodes, one wave): scan, boundary state from Alg::init, carried to every lane.
+// Top level (<= 256 nodes, one wave, ceil(n / 64) per lane): scan, boundary state from Alg::init,
+// carried to every lane.
 template <class Alg, class R>
 __global__ __launch_bounds__(64) void k_top(const KProb kp, const R* __restrict__ aux,
                                             const R* __restrict__ src, long n,
@@ -142,8 +143,10 @@ __global__ __launch_bounds__(64) void k_top(const KProb kp, const R* __restrict_
   const int p = blockIdx.y;
   const int lane = threadIdx.x;
   const R* mp = src + (long)p * Alg::NMAP * padt(n);
-  const long j0 = (long)lane * kChunk, j1 = min(j0 + kChunk, n);
-  const long active = (n + kChunk - 1) / kChunk;
+  // As few nodes per lane as fit the wave: the serial chains are the slow part of a short level.
+  const long c = n > 64 ? (n + 63) / 64 : 1;
+  const long j0 = (long)lane * c, j1 = min(j0 + c, n);
+  const long active = (n + c - 1) / c;
   const int levels = tree_levels(active);
   typename Alg::Map P;
   serial_chain<Alg, R>(mp, j0, j1, P);
