@@ -1059,6 +1059,17 @@ LQT_DEV void load_right_value(const KProb& kp, const R* Sp, const R* vp, long k,
   for (int q = 0; q < N; ++q) v[q] = vp[(k + 1) * N + q];
 }
 
+// S_{k+1} alone (see load_right_value).
+template <int N, class R>
+LQT_DEV void load_right_S(const KProb& kp, const R* Sp, long k, R (&S)[Sym<N>::size]) {
+  if (kp.seg && k + 1 >= kp.T) {
+#pragma unroll
+    for (int q = 0; q < Sym<N>::size; ++q) S[q] = R(0);
+    return;
+  }
+  S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
+}
+
 template <int N, class R>
 __global__ __launch_bounds__(kThreads) void k_tbottom_reduce(const KProb kp,
                                                               const R* __restrict__ elts,
@@ -1165,26 +1176,58 @@ __global__ __launch_bounds__(kThreads) void k_tbottom(const KProb kp, const R* _
   for (int q = 0; q < N; ++q) x[q] = x1[(long)p * N * padt(n1) + tix<N>(q, i)];
   const long j0 = i * kChunk;
   const long j1 = min(j0 + kChunk, T);
+  const int cnt = (int)(j1 - j0);
+  // v at the boundaries j0 .. j1 of the lane's blocks, loaded together up front: the values of one
+  // lane share cache lines, which would otherwise be fetched again between its blocks.  x and u
+  // are written together at the end for the same reason.  Boundaries past the horizon (and row T in
+  // ragged mode, which does not exist) read as zero.
+  R vv[kChunk + 1][N];
+#pragma unroll
+  for (int r = 0; r <= kChunk; ++r) {
+    const bool ok = r <= cnt && !(kp.seg && j0 + r >= T);
+#pragma unroll
+    for (int q = 0; q < N; ++q) vv[r][q] = ok ? vp[(j0 + r) * N + q] : R(0);
+  }
   R S[Sym<N>::size], v[N];
   S_load_upper<N, R>(S, Sp + j0 * N * N);
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] = vp[j0 * N + q];
+  for (int q = 0; q < N; ++q) v[q] = vv[0][q];
   R Kc[NU][N];
   const bool per_k = kp.L_sampled || kp.seg;
   if (!per_k) gain_at<N, NU, R>(kp, p, 0, Kc);
-  for (long k = j0; k < j1; ++k) {
+  R xs[kChunk][N], us[kChunk][NU];
 #pragma unroll
-    for (int q = 0; q < N; ++q) xp[k * N + q] = x[q];
+  for (int r = 0; r < kChunk; ++r) {
+    if (r >= cnt) break;
+    const long k = j0 + r;
+#pragma unroll
+    for (int q = 0; q < N; ++q) xs[r][q] = x[q];
     if (up) {
       if (per_k) gain_at<N, NU, R>(kp, p, k, Kc);
-      control<N, NU, R>(Kc, S, v, x, up + k * NU);
+      control<N, NU, R>(Kc, S, v, x, us[r]);
     }
     R Ad[N][N], b[N], C[Sym<N>::size];
     elt_map_part<N, R>(ep, k, Ad, b, C);
-    load_right_value<N, R>(kp, Sp, vp, k, S, v);
+    load_right_S<N, R>(kp, Sp, k, S);
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = vv[r + 1][q];
     Aff<N, R> m;
     block_map<N, R>(Ad, b, C, S, v, m);
     aff_apply(m, x);
+  }
+#pragma unroll
+  for (int r = 0; r < kChunk; ++r) {
+    if (r >= cnt) break;
+#pragma unroll
+    for (int q = 0; q < N; ++q) xp[(j0 + r) * N + q] = xs[r][q];
+  }
+  if (up) {
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) {
+      if (r >= cnt) break;
+#pragma unroll
+      for (int l = 0; l < NU; ++l) up[(j0 + r) * NU + l] = us[r][l];
+    }
   }
   if (j1 == T && !kp.seg) {
 #pragma unroll
