@@ -1059,6 +1059,7 @@ LQT_DEV void load_right_value(const KProb& kp, const R* Sp, const R* vp, long k,
   for (int q = 0; q < N; ++q) v[q] = vp[(k + 1) * N + q];
 }
 
+
 // S_{k+1} alone (see load_right_value).
 template <int N, class R>
 LQT_DEV void load_right_S(const KProb& kp, const R* Sp, long k, R (&S)[Sym<N>::size]) {
@@ -1069,6 +1070,7 @@ LQT_DEV void load_right_S(const KProb& kp, const R* Sp, long k, R (&S)[Sym<N>::s
   }
   S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
 }
+
 
 template <int N, class R>
 __global__ __launch_bounds__(kThreads) void k_tbottom_reduce(const KProb kp,
@@ -1085,14 +1087,27 @@ __global__ __launch_bounds__(kThreads) void k_tbottom_reduce(const KProb kp,
   const R* vp = vg + (long)p * (T + 1) * N;
   const long j0 = i * kChunk;
   const long j1 = min(j0 + kChunk, T);
+  const int cnt = (int)(j1 - j0);
+  // v at the right ends j0 + 1 .. j1 of the lane's blocks, loaded together up front (the values of
+  // one lane share cache lines); zero past the horizon and at row T in ragged mode.
+  R vv[kChunk][N];
+#pragma unroll
+  for (int r = 0; r < kChunk; ++r) {
+    const bool ok = r < cnt && !(kp.seg && j0 + r + 1 >= T);
+#pragma unroll
+    for (int q = 0; q < N; ++q) vv[r][q] = ok ? vp[(j0 + r + 1) * N + q] : R(0);
+  }
   Aff<N, R> acc;
   aff_identity(acc);
-  for (long k = j0; k < j1; ++k) {
-    R Ad[N][N], b[N], C[Sym<N>::size], S[Sym<N>::size], v[N];
+#pragma unroll
+  for (int r = 0; r < kChunk; ++r) {
+    if (r >= cnt) break;
+    const long k = j0 + r;
+    R Ad[N][N], b[N], C[Sym<N>::size], S[Sym<N>::size];
     elt_map_part<N, R>(ep, k, Ad, b, C);
-    load_right_value<N, R>(kp, Sp, vp, k, S, v);
+    load_right_S<N, R>(kp, Sp, k, S);
     Aff<N, R> m;
-    block_map<N, R>(Ad, b, C, S, v, m);
+    block_map<N, R>(Ad, b, C, S, vv[r], m);
     aff_then(acc, m);
   }
   aff_store(acc, maps1 + (long)p * Lay<N>::NM * padt(n1), i);
