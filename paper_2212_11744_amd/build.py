@@ -22,6 +22,23 @@ OBJ_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["lqt_api.hip", "lqt_prep.hip", "lqt_lane.hip", "lqt_adjoint.hip", "lqt_wave.hip",
            "lqt_batched.hip"]
+# Sources compiled once per build shard (-DLQT_SHARD=i): each object holds a share of the
+# template instantiations, so the shards compile in parallel.  Must match kLaneShards and
+# kWaveShards in csrc/lqt_internal.hpp (a mismatch fails at link time).
+SHARDS = {"lqt_lane.hip": 4, "lqt_wave.hip": 8}
+
+
+def units() -> list:
+    """(source, shard or None, object path) of every object of the library."""
+    out = []
+    for src in SOURCES:
+        stem = os.path.splitext(src)[0]
+        n = SHARDS.get(src)
+        if n is None:
+            out.append((src, None, os.path.join(OBJ_DIR, stem + ".o")))
+        else:
+            out.extend((src, i, os.path.join(OBJ_DIR, f"{stem}.{i}.o")) for i in range(n))
+    return out
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -37,9 +54,11 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJ_DIR, os.path.splitext(src)[0] + ".o")
+def _compile(unit: tuple, verbose: bool) -> str:
+    src, shard, obj = unit
     cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    if shard is not None:
+        cmd.append(f"-DLQT_SHARD={shard}")
     if verbose:
         cmd.append("-Rpass-analysis=kernel-resource-usage")
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -53,8 +72,12 @@ def _compile(src: str, verbose: bool) -> str:
 def build(verbose: bool = False) -> str:
     """Compile every HIP translation unit for gfx950 and link liblqt.so; returns its path."""
     os.makedirs(OBJ_DIR, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+    todo = units()
+    # Longest compiles first, so the pool's tail is short.
+    todo.sort(key=lambda u: (u[1] is None, u[0] != "lqt_wave.hip"))
+    with cf.ThreadPoolExecutor(max_workers=min(len(todo), os.cpu_count() or 1, 16)) as ex:
+        list(ex.map(lambda u: _compile(u, verbose), todo))
+    objs = [u[2] for u in units()]
     tmp = LIB + ".tmp"
     r = subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp],
                        capture_output=True, text=True)

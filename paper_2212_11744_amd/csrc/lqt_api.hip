@@ -52,6 +52,62 @@ Tree plan_tree(long T) {
   return t;
 }
 
+// Wave-path trees: n[0] = T, n[l + 1] = ceil(n[l] / wc) while n[l] > wc.
+WTree wave_tree(long T, int wc) {
+  WTree t;
+  t.wc = wc;
+  t.n[0] = T;
+  t.n[1] = (T + wc - 1) / wc;
+  t.levels = 1;
+  while (t.n[t.levels] > wc && t.levels < kMaxLevels) {
+    t.n[t.levels + 1] = (t.n[t.levels] + wc - 1) / wc;
+    ++t.levels;
+  }
+  return t;
+}
+
+// Dispatch over the build shards (see lqt_internal.hpp).
+const Ops* lane_ops(int nx, int nu, int dtype) {
+  static const Ops* (*const shard[kLaneShards])(int, int, int) = {
+      lane_ops_shard<0>, lane_ops_shard<1>, lane_ops_shard<2>, lane_ops_shard<3>};
+  static_assert(kLaneShards == 4, "one entry per per-lane shard");
+  for (auto f : shard)
+    if (const Ops* o = f(nx, nu, dtype)) return o;
+  return nullptr;
+}
+
+namespace {
+
+const WaveFns* wave_fns(int nx, int dtype) {
+  static const WaveFns* (*const shard[kWaveShards])(int, int) = {
+      wave_fns_shard<0>, wave_fns_shard<1>, wave_fns_shard<2>, wave_fns_shard<3>,
+      wave_fns_shard<4>, wave_fns_shard<5>, wave_fns_shard<6>, wave_fns_shard<7>};
+  static_assert(kWaveShards == 8, "one entry per wave shard");
+  for (auto f : shard)
+    if (const WaveFns* w = f(nx, dtype)) return w;
+  return nullptr;
+}
+
+}  // namespace
+
+hipError_t wave_build(const KProb& kp, int dtype, void* elts, hipStream_t s) {
+  const WaveFns* f = wave_fns(kp.nx, dtype);
+  return f ? f->build(kp, elts, s) : hipErrorInvalidValue;
+}
+
+hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
+                      void* S, void* v, void* maps1, hipStream_t s) {
+  const WaveFns* f = wave_fns(kp.nx, dtype);
+  return f ? f->value(kp, t, w, elts, S, v, maps1, s) : hipErrorInvalidValue;
+}
+
+hipError_t wave_traj(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
+                     const void* S, const void* v, void* x, void* u, bool maps_ready,
+                     hipStream_t s) {
+  const WaveFns* f = wave_fns(kp.nx, dtype);
+  return f ? f->traj(kp, t, w, elts, S, v, x, u, maps_ready, s) : hipErrorInvalidValue;
+}
+
 namespace {
 
 Tree tree_for(const lqt_dims* d) { return plan_tree(d->T); }

@@ -188,6 +188,22 @@ struct AdjOps {
 // FP64 adjoint instantiations for 1 <= nu <= nx <= 4; nullptr otherwise.
 const AdjOps* adj_ops(int nx, int nu, int dtype);
 
+// Build shards.  The per-lane and wave sources hold many template instantiations, so each is
+// compiled several times (with -DLQT_SHARD=i, i < the shard count below) and every object keeps
+// only the instantiations of its shard; the shard functions return nullptr for the sizes they do
+// not hold, and the dispatchers (lane_ops, wave_*) ask every shard.
+constexpr int kLaneShards = 4;
+constexpr int kWaveShards = 8;
+// Shard of a per-lane instantiation: (nx, nu) numbered 0..9 in (nx, nu) order, FP32 after FP64.
+__host__ __device__ constexpr int lane_shard(int nx, int nu, bool f32) {
+  return ((nx * (nx - 1)) / 2 + nu - 1 + (f32 ? 10 : 0)) % kLaneShards;
+}
+__host__ __device__ constexpr int wave_shard(int nx, bool f32) {
+  return (2 * (nx - 5) + (f32 ? 1 : 0)) % kWaveShards;
+}
+template <int S>
+const Ops* lane_ops_shard(int nx, int nu, int dtype);
+
 // Instantiations for 1 <= nu <= nx <= 4 (one tuple per lane); nullptr if not available.
 const Ops* lane_ops(int nx, int nu, int dtype);
 
@@ -202,6 +218,16 @@ struct WTree {
   long n[kMaxLevels + 1] = {};
 };
 WTree wave_tree(long T, int wc);
+// Launchers of one wave-path instantiation (state size, dtype).
+struct WaveFns {
+  hipError_t (*build)(const KProb&, void* elts, hipStream_t);
+  hipError_t (*value)(const KProb&, const WTree&, const Work&, const void* elts, void* S, void* v,
+                      void* maps1, hipStream_t);
+  hipError_t (*traj)(const KProb&, const WTree&, const Work&, const void* elts, const void* S,
+                     const void* v, void* x, void* u, bool maps_ready, hipStream_t);
+};
+template <int S>
+const WaveFns* wave_fns_shard(int nx, int dtype);
 hipError_t wave_build(const KProb& kp, int dtype, void* elts, hipStream_t s);
 hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
                       void* S, void* v, void* maps1, hipStream_t s);

@@ -2010,26 +2010,41 @@ struct L {
   }
 };
 
+#ifndef LQT_SHARD
+#define LQT_SHARD 0
+#endif
+static_assert(LQT_SHARD >= 0 && LQT_SHARD < kLaneShards, "LQT_SHARD out of range");
+
+// The instantiation of (N, NU, R) if it belongs to this object's shard.
+template <int N, int NU, class R>
+const Ops* ops_if() {
+  if constexpr (lane_shard(N, NU, sizeof(R) == 4) == LQT_SHARD)
+    return L<N, NU, R>::ops();
+  else
+    return nullptr;
+}
+
 template <class R>
 const Ops* ops_for(int nx, int nu) {
   switch (nx * 8 + nu) {
-    case 1 * 8 + 1: return L<1, 1, R>::ops();
-    case 2 * 8 + 1: return L<2, 1, R>::ops();
-    case 2 * 8 + 2: return L<2, 2, R>::ops();
-    case 3 * 8 + 1: return L<3, 1, R>::ops();
-    case 3 * 8 + 2: return L<3, 2, R>::ops();
-    case 3 * 8 + 3: return L<3, 3, R>::ops();
-    case 4 * 8 + 1: return L<4, 1, R>::ops();
-    case 4 * 8 + 2: return L<4, 2, R>::ops();
-    case 4 * 8 + 3: return L<4, 3, R>::ops();
-    case 4 * 8 + 4: return L<4, 4, R>::ops();
+    case 1 * 8 + 1: return ops_if<1, 1, R>();
+    case 2 * 8 + 1: return ops_if<2, 1, R>();
+    case 2 * 8 + 2: return ops_if<2, 2, R>();
+    case 3 * 8 + 1: return ops_if<3, 1, R>();
+    case 3 * 8 + 2: return ops_if<3, 2, R>();
+    case 3 * 8 + 3: return ops_if<3, 3, R>();
+    case 4 * 8 + 1: return ops_if<4, 1, R>();
+    case 4 * 8 + 2: return ops_if<4, 2, R>();
+    case 4 * 8 + 3: return ops_if<4, 3, R>();
+    case 4 * 8 + 4: return ops_if<4, 4, R>();
     default: return nullptr;
   }
 }
 
 }  // namespace
 
-const Ops* lane_ops(int nx, int nu, int dtype) {
+template <>
+const Ops* lane_ops_shard<LQT_SHARD>(int nx, int nu, int dtype) {
   return dtype == 0 ? ops_for<double>(nx, nu) : ops_for<float>(nx, nu);
 }
 

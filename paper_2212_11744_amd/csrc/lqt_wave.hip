@@ -1023,6 +1023,7 @@ __global__ __launch_bounds__(64) void kw_build_rows(const KProb kp, R* __restric
 //                      | keta = K^T eta + J c - Q r,  kb = -(w + A w); RK4 updates in registers.
 // Two barriers per stage.  J and C take their upper entries after every step (as the oracle).
 // ------------------------------------------------------------------------------------------
+template <int DUMMY = 0>
 __global__ __launch_bounds__(64) void kw_build_mfma16(const KProb kp, double* __restrict__ elts) {
   constexpr int N = 16, P = 17;
   typedef double R;
@@ -1626,18 +1627,6 @@ __global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R
 // ------------------------------------------------------------------------------------------
 // Host orchestration of this path.
 // ------------------------------------------------------------------------------------------
-WTree wave_tree(long T, int wc) {
-  WTree t;
-  t.wc = wc;
-  t.n[0] = T;
-  t.n[1] = (T + wc - 1) / wc;
-  t.levels = 1;
-  while (t.n[t.levels] > wc && t.levels < kMaxLevels) {
-    t.n[t.levels + 1] = (t.n[t.levels] + wc - 1) / wc;
-    ++t.levels;
-  }
-  return t;
-}
 
 namespace {
 
@@ -1647,7 +1636,7 @@ hipError_t wave_build_t(const KProb& kp, void* elts, hipStream_t s) {
     hipLaunchKernelGGL((kw_build_rows<N, R>), dim3((unsigned)((kp.T + 7) / 8), kp.batch), dim3(64),
                        0, s, kp, (R*)elts);
   else if constexpr (kMfma<N, R>)
-    hipLaunchKernelGGL(kw_build_mfma16, dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
+    hipLaunchKernelGGL(kw_build_mfma16<0>, dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
                        (double*)elts);
   else
     hipLaunchKernelGGL((kw_build<N, R>), dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
@@ -1700,63 +1689,47 @@ hipError_t wave_traj_t(const KProb& kp, const WTree& t, const Work& w, const voi
   return hipGetLastError();
 }
 
-// Calls F<N, R>::run(args...) for the state size of the call (5 <= nx <= 16).
-template <template <int, class> class F, class R, class... A>
-hipError_t by_size(int nx, A&&... a) {
-  switch (nx) {
-    case 5: return F<5, R>::run(a...);
-    case 6: return F<6, R>::run(a...);
-    case 7: return F<7, R>::run(a...);
-    case 8: return F<8, R>::run(a...);
-    case 9: return F<9, R>::run(a...);
-    case 10: return F<10, R>::run(a...);
-    case 11: return F<11, R>::run(a...);
-    case 12: return F<12, R>::run(a...);
-    case 13: return F<13, R>::run(a...);
-    case 14: return F<14, R>::run(a...);
-    case 15: return F<15, R>::run(a...);
-    case 16: return F<16, R>::run(a...);
-  }
-  return hipErrorInvalidValue;
-}
+#ifndef LQT_SHARD
+#define LQT_SHARD 0
+#endif
+static_assert(LQT_SHARD >= 0 && LQT_SHARD < kWaveShards, "LQT_SHARD out of range");
 
 template <int N, class R>
-struct BuildF {
-  static hipError_t run(const KProb& kp, void* e, hipStream_t s) { return wave_build_t<N, R>(kp, e, s); }
-};
-template <int N, class R>
-struct ValueF {
-  static hipError_t run(const KProb& kp, const WTree& t, const Work& w, const void* e, void* S,
-                        void* v, void* m, hipStream_t s) {
-    return wave_value_t<N, R>(kp, t, w, e, S, v, m, s);
+struct Fns {
+  static const WaveFns* get() {
+    if constexpr (wave_shard(N, sizeof(R) == 4) == LQT_SHARD) {
+      static const WaveFns f = {wave_build_t<N, R>, wave_value_t<N, R>, wave_traj_t<N, R>};
+      return &f;
+    } else {
+      return nullptr;
+    }
   }
 };
-template <int N, class R>
-struct TrajF {
-  static hipError_t run(const KProb& kp, const WTree& t, const Work& w, const void* e,
-                        const void* S, const void* v, void* x, void* u, bool ready, hipStream_t s) {
-    return wave_traj_t<N, R>(kp, t, w, e, S, v, x, u, ready, s);
+
+template <class R>
+const WaveFns* fns_for(int nx) {
+  switch (nx) {
+    case 5: return Fns<5, R>::get();
+    case 6: return Fns<6, R>::get();
+    case 7: return Fns<7, R>::get();
+    case 8: return Fns<8, R>::get();
+    case 9: return Fns<9, R>::get();
+    case 10: return Fns<10, R>::get();
+    case 11: return Fns<11, R>::get();
+    case 12: return Fns<12, R>::get();
+    case 13: return Fns<13, R>::get();
+    case 14: return Fns<14, R>::get();
+    case 15: return Fns<15, R>::get();
+    case 16: return Fns<16, R>::get();
   }
-};
+  return nullptr;
+}
 
 }  // namespace
 
-hipError_t wave_build(const KProb& kp, int dtype, void* elts, hipStream_t s) {
-  return dtype == 0 ? by_size<BuildF, double>(kp.nx, kp, elts, s)
-                    : by_size<BuildF, float>(kp.nx, kp, elts, s);
-}
-
-hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
-                      void* S, void* v, void* maps1, hipStream_t s) {
-  return dtype == 0 ? by_size<ValueF, double>(kp.nx, kp, t, w, elts, S, v, maps1, s)
-                    : by_size<ValueF, float>(kp.nx, kp, t, w, elts, S, v, maps1, s);
-}
-
-hipError_t wave_traj(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
-                     const void* S, const void* v, void* x, void* u, bool maps_ready,
-                     hipStream_t s) {
-  return dtype == 0 ? by_size<TrajF, double>(kp.nx, kp, t, w, elts, S, v, x, u, maps_ready, s)
-                    : by_size<TrajF, float>(kp.nx, kp, t, w, elts, S, v, x, u, maps_ready, s);
+template <>
+const WaveFns* wave_fns_shard<LQT_SHARD>(int nx, int dtype) {
+  return dtype == 0 ? fns_for<double>(nx) : fns_for<float>(nx);
 }
 
 }  // namespace lqt

@@ -276,6 +276,90 @@ def test_discrete_scheme_converges_to_riccati_at_fourth_order():
         assert 10.0 < e[0][i] / e[1][i] < 24.0
 
 
+# --------------------------------------------------------------------------------------------
+# Sec. II-B: the control law, pinned through the dynamics rather than its own formula.  The
+# optimal input is whatever input drives the optimal trajectory, so u(t) = L(t)^+ (dx/dt - F x)
+# wherever L(t) has full column rank.  dx/dt comes from sixth-order finite differences of an
+# independent fine solve; a sign error, a dropped R^{-1}, a transposed or wrongly sampled L(t)
+# in the oracle's u_k all fail these.
+# --------------------------------------------------------------------------------------------
+_D1_CENTRAL = np.array([-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0]) / 60.0   # offsets -3..3
+_D1_FORWARD = np.array([-49 / 20, 6.0, -15 / 2, 20 / 3, -15 / 4, 6 / 5, -1 / 6])  # offsets 0..6
+
+
+def _derivative(f, t, d, t0, t1):
+    """Sixth-order first derivative of the callable f at t with spacing d (one-sided near the
+    ends of [t0, t1])."""
+    if t - 3 * d < t0:
+        return _D1_FORWARD @ f(t + d * np.arange(7)) / d
+    if t + 3 * d > t1:
+        return -(_D1_FORWARD @ f(t - d * np.arange(7))) / d
+    return _D1_CENTRAL @ f(t + d * np.arange(-3, 4)) / d
+
+
+def test_control_is_velocity_rate_point_mass():
+    """Point mass (F = [[0, I], [0, 0]], L = [[0], [I]]): the control is the rate of change of
+    the velocity components.  The fine sequential solve gives x on a 2^14-step grid; the oracle's
+    u_k must agree with d(velocity)/dt at every block boundary and converge at fourth order."""
+    p = W.point_mass(1, 64, 10)
+    m = 256
+    N = p.T * 2 * m
+    rfine = p.ref(np.linspace(p.t[0], p.t[-1], 2 * N + 1))
+    _, _, x = O.riccati(p.F, p.L, p.Q, p.R, p.Qf, p.rf, p.x0, p.t[0], p.t[-1], N, rfine)
+    d = (p.t[-1] - p.t[0]) / (N // 2)
+    grid = np.arange(x.shape[0])
+    vel = x[:, 2:]
+    u_dyn = np.zeros((p.T + 1, 2))
+    for k in range(p.T + 1):
+        i = k * m
+        for ax in range(2):
+            u_dyn[k, ax] = _derivative(lambda j: vel[np.rint(j).astype(int), ax], i, 1.0, 0,
+                                       grid[-1]) / d
+    e = [relerr(O.solve(W.point_mass(1, 64, n))["u"], u_dyn) for n in (10, 20)]
+    assert e[1] < 2e-9
+    assert 12.0 < e[0] / e[1] < 21.0
+
+
+def test_control_from_dynamics_time_varying_input_matrix():
+    """Scalar tracker with a time-varying, sampled input gain l(t) and a non-zero reference:
+    u(t_k) = (dx/dt - a x) / l(t_k), with x from SciPy's DOP853 on the Riccati and offset ODEs
+    (Sec. II-B) and the closed-loop state.  Fourth-order convergence in n pins the sample of L
+    used at boundary k (a half-step shift changes u by O(h))."""
+    from scipy.integrate import solve_ivp
+
+    a, q, rho, Sf, tf = -0.3, 2.0, 0.5, 4.0, 2.0
+    lf = lambda t: 1.3 + 0.4 * np.sin(1.7 * t)
+    rr = lambda t: np.sin(1.1 * t) + 0.5 * np.cos(2.3 * t)
+    tol = dict(method="DOP853", rtol=1e-13, atol=1e-15, dense_output=True, max_step=2e-3)
+
+    def sv_rhs(t, y):
+        g = lf(t) ** 2 / rho
+        return [-2 * a * y[0] - q + g * y[0] ** 2, -q * rr(t) - a * y[1] + g * y[0] * y[1]]
+
+    sv = solve_ivp(sv_rhs, [tf, 0.0], [Sf, Sf * rr(tf)], **tol).sol
+
+    def x_rhs(t, y):
+        S, v = sv(t)
+        g = lf(t) ** 2 / rho
+        return [(a - g * S) * y[0] + g * v]
+
+    xs = solve_ivp(x_rhs, [0.0, tf], [1.0], **tol).sol
+    T = 32
+    t = np.linspace(0.0, tf, T + 1)
+    u_dyn = np.array([(_derivative(lambda s: xs(s)[0], tk, 1e-3, 0.0, tf) - a * xs(tk)[0]) / lf(tk)
+                      for tk in t])
+    e = []
+    for n in (8, 16):
+        ts = W.half_step_times(t, n)
+        ns = 2 * n * T + 1
+        prob = W.Problem(1, 1, T, n, t, np.array([[a]]), lf(ts).reshape(ns, 1, 1), np.array([[q]]),
+                         np.array([[rho]]), np.array([[Sf]]), np.array([rr(tf)]), np.array([1.0]),
+                         rr(ts).reshape(ns, 1))
+        e.append(relerr(O.solve(prob)["u"][:, 0], u_dyn))
+    assert e[1] < 5e-10
+    assert 12.0 < e[0] / e[1] < 21.0
+
+
 def test_point_mass_structure():
     p = W.point_mass(2, 32, 4)
     el = O.elements(p)
