@@ -121,6 +121,62 @@ LQT_DEV void tup_store(const Tup<N, R>& x, R* __restrict__ base, long k) {
   for (int i = 0; i < Sym<N>::size; ++i) base[tix<L::NE>(L::J + i, k)] = x.J[i];
 }
 
+// Access policies of the record functions below.  PlainAcc: ordinary loads and stores (LDS, or
+// memory private to one wave).  DevAcc: relaxed atomic loads and stores at agent scope, which are
+// coherent per location across the XCDs of the device without any cache maintenance (they go
+// past the non-coherent caches); the single-pass scans exchange every record value this way.
+struct PlainAcc {
+  template <class R>
+  static LQT_DEV void st(R* p, R v) { *p = v; }
+  template <class R>
+  static LQT_DEV R ld(const R* p) { return *p; }
+};
+struct DevAcc {
+  template <class R>
+  static LQT_DEV void st(R* p, R v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  template <class R>
+  static LQT_DEV R ld(const R* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+};
+
+// Records: value q of record r at base[q * stride + r] (element order).
+template <class Acc, int N, class R>
+LQT_DEV void tup_store_rec(const Tup<N, R>& x, R* base, long stride, long r) {
+  using L = Lay<N>;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) Acc::st(base + (L::A + i * N + j) * stride + r, x.A[i][j]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) Acc::st(base + (L::B + i) * stride + r, x.b[i]);
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) Acc::st(base + (L::C + i) * stride + r, x.C[i]);
+#pragma unroll
+  for (int i = 0; i < N; ++i) Acc::st(base + (L::E + i) * stride + r, x.e[i]);
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) Acc::st(base + (L::J + i) * stride + r, x.J[i]);
+}
+
+template <class Acc, int N, class R>
+LQT_DEV void tup_load_rec(Tup<N, R>& x, const R* base, long stride, long r) {
+  using L = Lay<N>;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) x.A[i][j] = Acc::ld(base + (L::A + i * N + j) * stride + r);
+#pragma unroll
+  for (int i = 0; i < N; ++i) x.b[i] = Acc::ld(base + (L::B + i) * stride + r);
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) x.C[i] = Acc::ld(base + (L::C + i) * stride + r);
+#pragma unroll
+  for (int i = 0; i < N; ++i) x.e[i] = Acc::ld(base + (L::E + i) * stride + r);
+#pragma unroll
+  for (int i = 0; i < Sym<N>::size; ++i) x.J[i] = Acc::ld(base + (L::J + i) * stride + r);
+}
+
 // 1 / x from the hardware reciprocal estimate refined by two Newton-Raphson steps
 // (r <- r + r (1 - x r)): within about an ulp of the quotient for the pivots met here (entries of
 // I + C J, Lemma 10), with half the dependent operations of the IEEE division sequence.
@@ -495,6 +551,26 @@ LQT_DEV void aff_load(Aff<N, R>& m, const R* __restrict__ base, long k) {
 #pragma unroll
     for (int j = 0; j < N; ++j) m.P[i][j] = base[tix<Lay<N>::NM>(i * N + j, k)];
     m.q[i] = base[tix<Lay<N>::NM>(N * N + i, k)];
+  }
+}
+
+template <class Acc, int N, class R>
+LQT_DEV void aff_store_rec(const Aff<N, R>& m, R* base, long stride, long r) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) Acc::st(base + (i * N + j) * stride + r, m.P[i][j]);
+    Acc::st(base + (N * N + i) * stride + r, m.q[i]);
+  }
+}
+
+template <class Acc, int N, class R>
+LQT_DEV void aff_load_rec(Aff<N, R>& m, const R* base, long stride, long r) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) m.P[i][j] = Acc::ld(base + (i * N + j) * stride + r);
+    m.q[i] = Acc::ld(base + (N * N + i) * stride + r);
   }
 }
 

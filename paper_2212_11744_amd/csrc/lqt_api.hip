@@ -174,9 +174,34 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
     return off;
   }
   const Tree t = tree_for(d);
-  for (int l = 1; l <= t.levels; ++l) {
-    const long lanes_above = l < t.levels ? t.n[l + 1] * 64 : 0;
-    if (want_v) {
+  // Single-pass scans: the counter and status words of a scan first (one clear), then payloads.
+  auto take_lb = [&](LbRecs* r, long tile, long nmap, long nst) {
+    const long G = (d->T + tile - 1) / tile, NG = (G + kLbGroupTiles - 1) / kLbGroupTiles;
+    const long nwords = B + B * G + B * NG;
+    unsigned* words = (unsigned*)take(sizeof(unsigned) * nwords);
+    void* tagg = take(es * B * nmap * G);
+    void* tst = take(es * B * nst * G);
+    void* gagg = take(es * B * nmap * NG);
+    void* gst = take(es * B * nst * NG);
+    if (w) {
+      r->ctr = words;
+      r->tflag = words ? words + B : nullptr;
+      r->gflag = words ? words + B + B * G : nullptr;
+      r->tagg = tagg;
+      r->tst = tst;
+      r->gagg = gagg;
+      r->gst = gst;
+      r->G = G;
+      r->NG = NG;
+      r->nwords = nwords;
+    }
+  };
+  if (call == LQT_CALL_SCAN_VALUE || call == LQT_CALL_SOLVE) take_lb(w ? &w->lbv : nullptr, kVTile, ne_of(d->nx), nv_of(d->nx));
+  if (want_t) take_lb(w ? &w->lbt : nullptr, kTTile, nm_of(d->nx), d->nx);
+  // Method 2: the tree of node products and prefix states
+  if (call == LQT_CALL_TRAJ_METHOD2) {
+    for (int l = 1; l <= t.levels; ++l) {
+      const long lanes_above = l < t.levels ? t.n[l + 1] * 64 : 0;
       void* a = take(es * B * ne_of(d->nx) * padt(t.n[l]));
       void* b = take(es * B * nv_of(d->nx) * padt(t.n[l]));
       void* c = lanes_above ? take(es * B * ne_of(d->nx) * padt(lanes_above)) : nullptr;
@@ -184,16 +209,6 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
         w->vtup[l] = a;
         w->vval[l] = b;
         w->vpart[l] = c;
-      }
-    }
-    if (want_t) {
-      void* a = take(es * B * nm_of(d->nx) * padt(t.n[l]));
-      void* b = take(es * B * d->nx * padt(t.n[l]));
-      void* c = lanes_above ? take(es * B * nm_of(d->nx) * padt(lanes_above)) : nullptr;
-      if (w) {
-        w->tmap[l] = a;
-        w->tx[l] = b;
-        w->tpart[l] = c;
       }
     }
   }
@@ -298,6 +313,26 @@ lqt_status check_ws(const lqt_dims* d, lqt_call call, void* ws, size_t ws_bytes,
     if (_e != hipSuccess)                                                           \
       return fail(LQT_EHIP, "%s failed: %s", #x, hipGetErrorString(_e));            \
   } while (0)
+
+// ------------------------------------------------------------------------------------------
+// Status words of the single-pass scans: zeroed by a fill kernel before every scan (a kernel
+// rather than a memset, so that a captured launch sequence replays it as an ordinary node).
+// ------------------------------------------------------------------------------------------
+__global__ void k_lb_clear(unsigned* __restrict__ w, long n) {
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long)gridDim.x * blockDim.x)
+    w[k] = 0u;
+}
+
+}  // namespace
+
+hipError_t lb_clear(const LbRecs& r, hipStream_t s) {
+  const long blocks = min((r.nwords + 255) / 256, 1024L);
+  hipLaunchKernelGGL(k_lb_clear, dim3((unsigned)blocks), dim3(256), 0, s, r.ctr, r.nwords);
+  return hipGetLastError();
+}
+
+namespace {
 
 // ------------------------------------------------------------------------------------------
 // Finite check of the outputs (LQT_CHECK_FINITE).
@@ -411,32 +446,19 @@ KProb make_kprob(const lqt_dims* d, const lqt_problem* p, const void* consts) {
   return k;
 }
 
-// Value tree over elements: upward products, top sweep from the terminal element, downward
-// values, then the values of every block (and, when maps1 != nullptr, level 1 of the trajectory
-// tree).
-// level1_ready: level 1 was produced together with the elements (fused build).
-lqt_status run_value(const Ops* o, const KProb& kp, const Tree& t, const Work& w, const void* elts,
-                     void* S, void* v, void* maps1, bool level1_ready, hipStream_t s) {
-  if (!level1_ready) LQT_HIP(o->vreduce0(kp, elts, w.vtup[1], t.n[1], s));
-  for (int l = 1; l < t.levels; ++l)
-    LQT_HIP(o->vup(kp, w.vtup[l], t.n[l], w.vpart[l], w.vtup[l + 1], t.n[l + 1], s));
-  LQT_HIP(o->vtop(kp, w.vtup[t.levels], t.n[t.levels], w.vval[t.levels], s));
-  for (int l = t.levels - 1; l >= 1; --l)
-    LQT_HIP(o->vdown(kp, w.vtup[l], t.n[l], w.vpart[l], w.vval[l + 1], t.n[l + 1], w.vval[l], s));
-  LQT_HIP(o->vbottom(kp, elts, w.vval[1], t.n[1], S, v, maps1, s));
+// Value scan over elements (single pass; per-lane path).
+lqt_status run_value(const Ops* o, const KProb& kp, const Work& w, const void* elts, void* S,
+                     void* v, hipStream_t s) {
+  LQT_HIP(lb_clear(w.lbv, s));
+  LQT_HIP(o->vscan(kp, elts, S, v, w.lbv, s));
   return LQT_OK;
 }
 
-// Trajectory tree from level-1 maps: upward compositions, top sweep from x0, downward left-end
-// states, then x_k, u_k of every block.
-lqt_status run_traj(const Ops* o, const KProb& kp, const Tree& t, const Work& w, const void* elts,
+// Trajectory scan (single pass; per-lane path): x_k, u_k of every boundary.
+lqt_status run_traj(const Ops* o, const KProb& kp, const Work& w, const void* elts,
                     const void* S, const void* v, void* x, void* u, hipStream_t s) {
-  for (int l = 1; l < t.levels; ++l)
-    LQT_HIP(o->tup(kp, w.tmap[l], t.n[l], w.tpart[l], w.tmap[l + 1], t.n[l + 1], s));
-  LQT_HIP(o->ttop(kp, w.tmap[t.levels], t.n[t.levels], w.tx[t.levels], s));
-  for (int l = t.levels - 1; l >= 1; --l)
-    LQT_HIP(o->tdown(kp, w.tmap[l], t.n[l], w.tpart[l], w.tx[l + 1], t.n[l + 1], w.tx[l], s));
-  LQT_HIP(o->tbottom(kp, elts, S, v, w.tx[1], t.n[1], x, u, s));
+  LQT_HIP(lb_clear(w.lbt, s));
+  LQT_HIP(o->tscan(kp, elts, S, v, x, u, w.lbt, s));
   return LQT_OK;
 }
 
@@ -589,7 +611,7 @@ lqt_status lqt_scan_value(const lqt_dims* dims, const void* elts, const void* Qf
     LQT_HIP(wave_value(kp, dims->dtype, wtree_for(dims), w, elts, S, v, nullptr, stream));
   } else {
     const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
-    LQT_TRY(run_value(o, kp, tree_for(dims), w, elts, S, v, nullptr, false, stream));
+    LQT_TRY(run_value(o, kp, w, elts, S, v, stream));
   }
   const long nb = dims->batch, T1 = (long)dims->T + 1, nx = dims->nx;
   LQT_TRY(finite_check(dims, w, stream, {{S, nb * T1 * nx * nx, false}, {v, nb * T1 * nx, false}}));
@@ -618,9 +640,7 @@ lqt_status lqt_forward_traj(const lqt_dims* dims, const lqt_problem* prob, const
     LQT_HIP(wave_traj(kp, dims->dtype, wtree_for(dims), w, elts, S, v, x, u, false, stream));
   } else {
     const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
-    const Tree t = tree_for(dims);
-    LQT_HIP(o->tbottom_reduce(kp, elts, S, v, w.tmap[1], t.n[1], stream));
-    LQT_TRY(run_traj(o, kp, t, w, elts, S, v, x, u, stream));
+    LQT_TRY(run_traj(o, kp, w, elts, S, v, x, u, stream));
   }
   const long nb = dims->batch, T1 = (long)dims->T + 1;
   LQT_TRY(finite_check(dims, w, stream, {{x, nb * T1 * dims->nx, false}, {u, nb * T1 * dims->nu, false}}));
@@ -646,19 +666,15 @@ lqt_status run_solve(const lqt_dims* dims, const KProb& kp, const Work& w, void*
     return LQT_OK;
   }
   const Ops* op = lane_ops(dims->nx, dims->nu, dims->dtype);
-  const Tree t = tree_for(dims);
   const bool lti = kp.lti && !kp.seg && w.lti;
-  const bool fused = o.fused && !lti;
   if (lti) {
     LQT_HIP(op->lti_prep(kp, w.lti, stream));
     LQT_HIP(op->lti_build(kp, w.lti, e, stream));
-  } else if (fused) {
-    LQT_HIP(op->build_reduce(kp, e, w.vtup[1], t.n[1], stream));
   } else {
     LQT_HIP(op->build(kp, e, stream));
   }
-  LQT_TRY(run_value(op, kp, t, w, e, S, v, w.tmap[1], fused, stream));
-  LQT_TRY(run_traj(op, kp, t, w, e, S, v, x, u, stream));
+  LQT_TRY(run_value(op, kp, w, e, S, v, stream));
+  LQT_TRY(run_traj(op, kp, w, e, S, v, x, u, stream));
   return LQT_OK;
 }
 
@@ -683,12 +699,7 @@ lqt_status lqt_solve(const lqt_dims* dims, const lqt_problem* prob, void* elts, 
   LQT_TRY(check_ws(dims, LQT_CALL_SOLVE, ws, ws_bytes, &w));
   KProb kp = make_kprob(dims, prob, w.consts);
   void* e = elts ? elts : w.elts;
-  // The element build and the level-1 value products run as separate kernels: the fused
-  // kernel (4 blocks per lane, built serially) runs fewer, longer waves and measured slower in
-  // both precisions (FP32, T = 2^20: 247 us fused vs 151 + 44 us split).  The batched solve's
-  // autotuner still tries both.
   SolveOpts o;
-  o.fused = false;
   o.wave_chunk = kWaveChunk;
   LQT_TRY(run_solve(dims, kp, w, e, S, v, x, u, o, stream));
   const long nb = dims->batch, T1 = (long)dims->T + 1, nx = dims->nx;

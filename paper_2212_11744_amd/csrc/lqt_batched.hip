@@ -136,7 +136,6 @@ lqt_status prepare(const lqt_ragged* cls, int ncls, void* ws, size_t ws_bytes,
 
 SolveOpts default_opts(const ClassRun& r) {
   SolveOpts o;
-  o.fused = false;
   o.wave_chunk = 8;
   return o;
 }
@@ -262,11 +261,7 @@ lqt_status tune(lqt_plan_s* p, hipStream_t s, Choice* ch) {
         cands.push_back(o);
       }
     } else {
-      for (int f = 0; f < 2; ++f) {
-        SolveOpts o;
-        o.fused = f == 1;
-        cands.push_back(o);
-      }
+      cands.push_back(SolveOpts());  // the per-lane path has no options
     }
     float best = 1e30f;
     SolveOpts bo = cands[0];
@@ -281,8 +276,7 @@ lqt_status tune(lqt_plan_s* p, hipStream_t s, Choice* ch) {
     ch->opts.push_back(bo);
     const std::string choice = is_wave(r.d) ? "wave path, " + std::to_string(bo.wave_chunk) +
                                                   " nodes per wave"
-                                            : (bo.fused ? "lane path, fused build"
-                                                        : "lane path, separate build");
+                                            : std::string("lane path");
     snprintf(buf, sizeof(buf), "class %zu (nx=%d nu=%d count=%d rows=%lld): %s, %.3f ms; ", i,
              r.c.nx, r.c.nu, r.c.count, (long long)r.c.rows, choice.c_str(), best);
     text += buf;

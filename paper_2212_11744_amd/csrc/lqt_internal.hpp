@@ -73,6 +73,10 @@ __host__ __device__ inline int consts_count(int nx, int nu) { return nx * nx + 2
 // level `levels` (<= 256 nodes) is swept by one wavefront.
 constexpr int kLaneChunk = 4;
 constexpr int kWaveSpan = 256;
+constexpr int kLbGroupTiles = 64;  // tiles per group record of the single-pass scans
+// Blocks per lane and per tile (one wave) of the single-pass value and trajectory scans.
+constexpr int kVChunk = 8, kVTile = kVChunk * 64;
+constexpr int kTChunk = 4, kTTile = kTChunk * 64;
 
 struct Tree {
   int levels = 0;
@@ -81,10 +85,27 @@ struct Tree {
 
 Tree plan_tree(long T);
 
+// Records of one single-pass scan with decoupled look-back (lookback.hpp), for `batch` problems
+// of G tiles and NG = ceil(G / 64) groups each.  ctr, tflag and gflag are consecutive words (one
+// clear covers them); payloads hold value q of record r at [q * G + r] (tiles) or [q * NG + r]
+// (groups) per problem.
+struct LbRecs {
+  unsigned* ctr = nullptr;    // [batch] tile counters
+  unsigned* tflag = nullptr;  // [batch][G] status words of the tiles
+  unsigned* gflag = nullptr;  // [batch][NG] status words of the groups
+  void* tagg = nullptr;       // [batch][NMAP][G] tile aggregates
+  void* tst = nullptr;        // [batch][NST][G] inclusive states of the tiles
+  void* gagg = nullptr;       // [batch][NMAP][NG] group aggregates
+  void* gst = nullptr;        // [batch][NST][NG] inclusive states of the groups
+  long G = 0, NG = 0;
+  long nwords = 0;            // ctr .. end of gflag
+};
+
 // Workspace pointers of one call (all per-level arrays hold `batch` problems back to back, each in
 // tiles of 256 items).
 struct Work {
   void* consts = nullptr;
+  LbRecs lbv, lbt;                   // single-pass value and trajectory scans (per-lane path)
   void* vtup[kMaxLevels + 1] = {};   // value tree: tuples at level l >= 1
   void* vval[kMaxLevels + 1] = {};   // value tree: (packed S, v) at right ends of level-l nodes
   void* vpart[kMaxLevels + 1] = {};  // value tree: lane partials of the wave trees above level l
@@ -115,26 +136,12 @@ constexpr int kCkptMaxSteps = 16;
 struct Ops {
   hipError_t (*prep)(const KProb&, void* consts, hipStream_t);
   hipError_t (*build)(const KProb&, void* elts, hipStream_t);
-  hipError_t (*build_reduce)(const KProb&, void* elts, void* lvl1, long n1, hipStream_t);
-  // value tree
+  // single-pass scans: values S, v of every boundary; trajectory x, u (u nullable)
+  hipError_t (*vscan)(const KProb&, const void* elts, void* S, void* v, const LbRecs&, hipStream_t);
+  hipError_t (*tscan)(const KProb&, const void* elts, const void* S, const void* v, void* x,
+                      void* u, const LbRecs&, hipStream_t);
+  // level 1 of the node products (4 blocks per lane), for the Method 2 tree
   hipError_t (*vreduce0)(const KProb&, const void* elts, void* lvl1, long n1, hipStream_t);
-  hipError_t (*vup)(const KProb&, const void* src, long n_src, void* part, void* dst, long n_dst,
-                    hipStream_t);
-  hipError_t (*vtop)(const KProb&, const void* tup, long n, void* val, hipStream_t);
-  hipError_t (*vdown)(const KProb&, const void* tup, long n_child, const void* part,
-                      const void* val_par, long n_par, void* val_child, hipStream_t);
-  hipError_t (*vbottom)(const KProb&, const void* elts, const void* val1, long n1, void* S,
-                        void* v, void* maps1, hipStream_t);
-  // trajectory tree
-  hipError_t (*tbottom_reduce)(const KProb&, const void* elts, const void* S, const void* v,
-                               void* maps1, long n1, hipStream_t);
-  hipError_t (*tup)(const KProb&, const void* src, long n_src, void* part, void* dst, long n_dst,
-                    hipStream_t);
-  hipError_t (*ttop)(const KProb&, const void* maps, long n, void* xs, hipStream_t);
-  hipError_t (*tdown)(const KProb&, const void* maps, long n_child, const void* part,
-                      const void* x_par, long n_par, void* x_child, hipStream_t);
-  hipError_t (*tbottom)(const KProb&, const void* elts, const void* S, const void* v,
-                        const void* x1, long n1, void* x, void* u, hipStream_t);
   // time-invariant path: response tables, then the elements from them
   hipError_t (*lti_prep)(const KProb&, void* tab, hipStream_t);
   hipError_t (*lti_build)(const KProb&, const void* tab, void* elts, hipStream_t);
@@ -148,6 +155,7 @@ struct Ops {
                         const void* st_par, long n_par, void* st_child, hipStream_t);
   hipError_t (*m2_bottom)(const KProb&, const void* elts, const void* S, const void* v,
                           const void* st1, long n1, void* x, void* u, hipStream_t);
+  // (Method 2's tree levels use the value-tree arrays vtup, vpart, vval of Work)
   // values inside the blocks at the n T + 1 RK4 nodes
   hipError_t (*dense)(const KProb&, const void* S, const void* v, const void* x, void* Sd,
                       void* vd, void* xd, void* ud, hipStream_t);
@@ -235,12 +243,13 @@ hipError_t wave_traj(const KProb& kp, int dtype, const WTree& t, const Work& w, 
                      const void* S, const void* v, void* x, void* u, bool maps_ready,
                      hipStream_t s);
 
-// Options of a full solve: fused element build + level-1 value products (per-lane path), and
-// the number of nodes per wave of the wave path's trees.
+// Options of a full solve: the number of nodes per wave of the wave path's trees.
 struct SolveOpts {
-  bool fused = false;
   int wave_chunk = 8;
 };
+
+// Zeroes the counter and status words of a single-pass scan (before every launch).
+hipError_t lb_clear(const LbRecs& r, hipStream_t s);
 
 // Workspace layout of one call (lqt_api.hip); the layout for wave_chunk wc also serves any larger
 // chunk.  nconsts: problems whose per-problem constants are prepared.

@@ -32,6 +32,7 @@
 // ceil(n_l / 256) nodes while n_l > 256; the top level (<= 256 nodes) is one wave.
 #include "lane_math.hpp"
 #include "lqt_internal.hpp"
+#include "lookback.hpp"
 #include "tree_scan.hpp"
 #include "wave_tree.hpp"
 
@@ -880,29 +881,6 @@ __global__ __launch_bounds__(kThreads) void k_build_ckpt(const KProb kp, R* __re
   tup_store(out, elts + (long)p * Lay<N>::NE * padt(kp.T), k);
 }
 
-// Element build fused with level 1 of the value tree: lane i builds its 4 blocks from the last to
-// the first, stores each element and folds it into the running product a_k (x) ... (x) a_{4i+3}.
-template <int N, int NU, class R, bool CONST_COEF>
-__global__ __launch_bounds__(kThreads) void k_build_reduce(const KProb kp, R* __restrict__ elts,
-                                                            R* __restrict__ lvl1, long n1) {
-  const int p = blockIdx.y;
-  const long i = gid();
-  if (i >= n1) return;
-  const long T = kp.T;
-  R* ep = elts + (long)p * Lay<N>::NE * padt(T);
-  const long j0 = i * kChunk, j1 = min(j0 + kChunk, T);
-  Tup<N, R> acc;
-  element_at<N, NU, R, CONST_COEF>(kp, p, j1 - 1, acc);
-  tup_store(acc, ep, j1 - 1);
-  for (long k = j1 - 2; k >= j0; --k) {
-    Tup<N, R> a;
-    element_at<N, NU, R, CONST_COEF>(kp, p, k, a);
-    tup_store(a, ep, k);
-    combine(a, acc, acc);
-  }
-  tup_store(acc, lvl1 + (long)p * Lay<N>::NE * padt(n1), i);
-}
-
 // ------------------------------------------------------------------------------------------
 // Value tree.
 // ------------------------------------------------------------------------------------------
@@ -985,47 +963,6 @@ LQT_DEV void S_load_upper(R (&S)[Sym<N>::size], const R* src) {
     for (int j = i; j < N; ++j) S[Sym<N>::at(i, j)] = src[i * N + j];
 }
 
-// Values of every block: S_k, v_k for the 4 blocks of lane i, folded from the value at the right
-// end of its level-1 node.  maps1 (optional): the composition of the lane's closed-loop block maps,
-// level 1 of the trajectory tree (the maps come out of the fold for free).
-template <int N, class R>
-__global__ __launch_bounds__(kThreads) void k_vbottom(const KProb kp, const R* __restrict__ elts,
-                                                       const R* __restrict__ val1, long n1,
-                                                       R* __restrict__ Sout, R* __restrict__ vout,
-                                                       R* __restrict__ maps1) {
-  const int p = blockIdx.y;
-  const long i = gid();
-  if (i >= n1) return;
-  const long T = kp.T;
-  const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
-  R* Sp = Sout + (long)p * (T + 1) * N * N;
-  R* vp = vout + (long)p * (T + 1) * N;
-  R S[Sym<N>::size], v[N];
-  val_load<N, R>(S, v, val1 + (long)p * Lay<N>::NV * padt(n1), i);
-  const long j0 = i * kChunk;
-  const long j1 = min(j0 + kChunk, T);
-  if (j1 == T && !kp.seg) {
-    S_store_full<N, R>(S, Sp + T * N * N);
-#pragma unroll
-    for (int q = 0; q < N; ++q) vp[T * N + q] = v[q];
-  }
-  Aff<N, R> acc;
-  aff_identity(acc);
-  Tup<N, R> nxt;
-  tup_load(nxt, ep, j1 - 1);
-  for (long k = j1 - 1; k >= j0; --k) {
-    Tup<N, R> a = nxt;
-    if (k - 1 >= j0) tup_load(nxt, ep, k - 1);
-    Aff<N, R> m;
-    fold(a, S, v, m);
-    S_store_full<N, R>(S, Sp + k * N * N);
-#pragma unroll
-    for (int q = 0; q < N; ++q) vp[k * N + q] = v[q];
-    if (maps1) aff_after(acc, m);
-  }
-  if (maps1) aff_store(acc, maps1 + (long)p * Lay<N>::NM * padt(n1), i);
-}
-
 // ------------------------------------------------------------------------------------------
 // Trajectory tree.
 // ------------------------------------------------------------------------------------------
@@ -1071,47 +1008,6 @@ LQT_DEV void load_right_S(const KProb& kp, const R* Sp, long k, R (&S)[Sym<N>::s
   S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
 }
 
-
-template <int N, class R>
-__global__ __launch_bounds__(kThreads) void k_tbottom_reduce(const KProb kp,
-                                                              const R* __restrict__ elts,
-                                                              const R* __restrict__ Sg,
-                                                              const R* __restrict__ vg,
-                                                              R* __restrict__ maps1, long n1) {
-  const int p = blockIdx.y;
-  const long i = gid();
-  if (i >= n1) return;
-  const long T = kp.T;
-  const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
-  const R* Sp = Sg + (long)p * (T + 1) * N * N;
-  const R* vp = vg + (long)p * (T + 1) * N;
-  const long j0 = i * kChunk;
-  const long j1 = min(j0 + kChunk, T);
-  const int cnt = (int)(j1 - j0);
-  // v at the right ends j0 + 1 .. j1 of the lane's blocks, loaded together up front (the values of
-  // one lane share cache lines); zero past the horizon and at row T in ragged mode.
-  R vv[kChunk][N];
-#pragma unroll
-  for (int r = 0; r < kChunk; ++r) {
-    const bool ok = r < cnt && !(kp.seg && j0 + r + 1 >= T);
-#pragma unroll
-    for (int q = 0; q < N; ++q) vv[r][q] = ok ? vp[(j0 + r + 1) * N + q] : R(0);
-  }
-  Aff<N, R> acc;
-  aff_identity(acc);
-#pragma unroll
-  for (int r = 0; r < kChunk; ++r) {
-    if (r >= cnt) break;
-    const long k = j0 + r;
-    R Ad[N][N], b[N], C[Sym<N>::size], S[Sym<N>::size];
-    elt_map_part<N, R>(ep, k, Ad, b, C);
-    load_right_S<N, R>(kp, Sp, k, S);
-    Aff<N, R> m;
-    block_map<N, R>(Ad, b, C, S, vv[r], m);
-    aff_then(acc, m);
-  }
-  aff_store(acc, maps1 + (long)p * Lay<N>::NM * padt(n1), i);
-}
 
 // u = -Kc (S x - v) with Kc = R^{-1} L(t_k)^T.
 template <int N, int NU, class R>
@@ -1169,89 +1065,6 @@ LQT_DEV void gain_at(const KProb& kp, int p, long k, R (&Kc)[NU][N]) {
     s0 = (long)p * (2L * kp.n * kp.T + 1);
   }
   gain_sample<N, NU, R>(kp, p, s0 + 2L * kp.n * k, Kc);
-}
-
-template <int N, int NU, class R>
-__global__ __launch_bounds__(kThreads) void k_tbottom(const KProb kp, const R* __restrict__ elts,
-                                                       const R* __restrict__ Sg,
-                                                       const R* __restrict__ vg,
-                                                       const R* __restrict__ x1, long n1,
-                                                       R* __restrict__ xout, R* __restrict__ uout) {
-  const int p = blockIdx.y;
-  const long i = gid();
-  if (i >= n1) return;
-  const long T = kp.T;
-  const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
-  const R* Sp = Sg + (long)p * (T + 1) * N * N;
-  const R* vp = vg + (long)p * (T + 1) * N;
-  R* xp = xout + (long)p * (T + 1) * N;
-  R* up = uout ? uout + (long)p * (T + 1) * NU : nullptr;
-  R x[N];
-#pragma unroll
-  for (int q = 0; q < N; ++q) x[q] = x1[(long)p * N * padt(n1) + tix<N>(q, i)];
-  const long j0 = i * kChunk;
-  const long j1 = min(j0 + kChunk, T);
-  const int cnt = (int)(j1 - j0);
-  // v at the boundaries j0 .. j1 of the lane's blocks, loaded together up front: the values of one
-  // lane share cache lines, which would otherwise be fetched again between its blocks.  x and u
-  // are written together at the end for the same reason.  Boundaries past the horizon (and row T in
-  // ragged mode, which does not exist) read as zero.
-  R vv[kChunk + 1][N];
-#pragma unroll
-  for (int r = 0; r <= kChunk; ++r) {
-    const bool ok = r <= cnt && !(kp.seg && j0 + r >= T);
-#pragma unroll
-    for (int q = 0; q < N; ++q) vv[r][q] = ok ? vp[(j0 + r) * N + q] : R(0);
-  }
-  R S[Sym<N>::size], v[N];
-  S_load_upper<N, R>(S, Sp + j0 * N * N);
-#pragma unroll
-  for (int q = 0; q < N; ++q) v[q] = vv[0][q];
-  R Kc[NU][N];
-  const bool per_k = kp.L_sampled || kp.seg;
-  if (!per_k) gain_at<N, NU, R>(kp, p, 0, Kc);
-  R xs[kChunk][N], us[kChunk][NU];
-#pragma unroll
-  for (int r = 0; r < kChunk; ++r) {
-    if (r >= cnt) break;
-    const long k = j0 + r;
-#pragma unroll
-    for (int q = 0; q < N; ++q) xs[r][q] = x[q];
-    if (up) {
-      if (per_k) gain_at<N, NU, R>(kp, p, k, Kc);
-      control<N, NU, R>(Kc, S, v, x, us[r]);
-    }
-    R Ad[N][N], b[N], C[Sym<N>::size];
-    elt_map_part<N, R>(ep, k, Ad, b, C);
-    load_right_S<N, R>(kp, Sp, k, S);
-#pragma unroll
-    for (int q = 0; q < N; ++q) v[q] = vv[r + 1][q];
-    Aff<N, R> m;
-    block_map<N, R>(Ad, b, C, S, v, m);
-    aff_apply(m, x);
-  }
-#pragma unroll
-  for (int r = 0; r < kChunk; ++r) {
-    if (r >= cnt) break;
-#pragma unroll
-    for (int q = 0; q < N; ++q) xp[(j0 + r) * N + q] = xs[r][q];
-  }
-  if (up) {
-#pragma unroll
-    for (int r = 0; r < kChunk; ++r) {
-      if (r >= cnt) break;
-#pragma unroll
-      for (int l = 0; l < NU; ++l) up[(j0 + r) * NU + l] = us[r][l];
-    }
-  }
-  if (j1 == T && !kp.seg) {
-#pragma unroll
-    for (int q = 0; q < N; ++q) xp[T * N + q] = x[q];
-    if (up) {
-      if (per_k) gain_at<N, NU, R>(kp, p, T, Kc);
-      control<N, NU, R>(Kc, S, v, x, up + T * NU);
-    }
-  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1378,6 +1191,25 @@ struct ValAlg {
   static LQT_DEV void init(const KProb& kp, const R*, int p, State& st) {
     terminal_value<N, R>(kp, p, st.S, st.v);
   }
+  // records of the single-pass scan (device-scope coherent accesses)
+  static LQT_DEV void store_rec(const Map& m, R* b, long stride, long r) {
+    tup_store_rec<DevAcc>(m, b, stride, r);
+  }
+  static LQT_DEV void load_rec(Map& m, const R* b, long stride, long r) {
+    tup_load_rec<DevAcc>(m, b, stride, r);
+  }
+  static LQT_DEV void sstore_rec(const State& st, R* b, long stride, long r) {
+#pragma unroll
+    for (int q = 0; q < Sym<N>::size; ++q) DevAcc::st(b + q * stride + r, st.S[q]);
+#pragma unroll
+    for (int q = 0; q < N; ++q) DevAcc::st(b + (Sym<N>::size + q) * stride + r, st.v[q]);
+  }
+  static LQT_DEV void sload_rec(State& st, const R* b, long stride, long r) {
+#pragma unroll
+    for (int q = 0; q < Sym<N>::size; ++q) st.S[q] = DevAcc::ld(b + q * stride + r);
+#pragma unroll
+    for (int q = 0; q < N; ++q) st.v[q] = DevAcc::ld(b + (Sym<N>::size + q) * stride + r);
+  }
 };
 
 // Trajectory scan: closed-loop block maps composed in time order, the state x carried forward
@@ -1413,7 +1245,188 @@ struct TrajAlg {
 #pragma unroll
     for (int q = 0; q < N; ++q) st.x[q] = ((const R*)kp.x0)[(long)p * N + q];
   }
+  // records of the single-pass scan (device-scope coherent accesses)
+  static LQT_DEV void store_rec(const Map& m, R* b, long stride, long r) {
+    aff_store_rec<DevAcc>(m, b, stride, r);
+  }
+  static LQT_DEV void load_rec(Map& m, const R* b, long stride, long r) {
+    aff_load_rec<DevAcc>(m, b, stride, r);
+  }
+  static LQT_DEV void sstore_rec(const State& st, R* b, long stride, long r) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) DevAcc::st(b + q * stride + r, st.x[q]);
+  }
+  static LQT_DEV void sload_rec(State& st, const R* b, long stride, long r) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) st.x[q] = DevAcc::ld(b + q * stride + r);
+  }
 };
+
+// ------------------------------------------------------------------------------------------
+// Single-pass scans (lookback.hpp).  One wave per tile of 256 blocks (4 consecutive blocks per
+// lane, the tile of the element layout); the wave reduces its tile, resolves the state at the
+// tile's free end from the records of the tiles before it in the flow, carries that state to
+// every lane through the lane's exclusive product, and sweeps the lane's blocks.
+// ------------------------------------------------------------------------------------------
+// Value scan (Theorem 6, Lemma 7, terminal element of Sec. IV-D).  The flow is backward in time:
+// place i takes tile G - 1 - i, so the first place holds the end of the horizon.  Tiles are 512
+// blocks, 8 per lane (two tiles of the element layout): with four waves per CU at most (a lane
+// holds two tuples and a Lemma 7 combination), a horizon of 2^20 blocks then needs two rounds of
+// resident waves instead of four, and the per-tile costs that do not grow with the tile (the
+// lane scan of the wave and the look-back) are spread over twice the blocks.
+template <int N, class R>
+__global__ __launch_bounds__(kThreads) void k_vscan(const KProb kp, const R* __restrict__ elts,
+                                                     R* __restrict__ Sout, R* __restrict__ vout,
+                                                     const LbRecs lb) {
+  using Alg = ValAlg<N, R>;
+  const int p = blockIdx.y;
+  const int lane = threadIdx.x;
+  const long T = kp.T;
+  const long i = lb_place(lb, p);
+  const long tile = lb.G - 1 - i;
+  const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
+  const long j0 = tile * kVTile + (long)lane * kVChunk;
+  const long j1 = min(j0 + kVChunk, T);
+  typename Alg::State st;
+  // The lane's exclusive product waits in LDS during the look-back (registers are short: the
+  // look-back combines tuples of its own).
+  __shared__ R sE[Lay<N>::NE][kThreads];
+  {
+    Tup<N, R> P;
+    serial_product(ep, j0, j1, P);
+    wave_scan<Alg>(P, lane);  // lane m: product of lanes m .. 63; lane 0: the tile
+    Tup<N, R> E;
+    wave_exclusive<Alg>(P, E, lane);
+    tup_store_rec<PlainAcc>(E, &sE[0][0], kThreads, lane);
+    typename Alg::State st0;
+    lb_resolve<Alg, R>(kp, (const R*)nullptr, p, lb, i, P, lane, st0);
+    if (j0 >= T) return;
+    tup_load_rec<PlainAcc>(E, &sE[0][0], kThreads, lane);
+    if (lane != 63) Alg::apply(E, st0);  // the value at the right end of the lane's blocks
+    st = st0;
+  }
+  R* Sp = Sout + (long)p * (T + 1) * N * N;
+  R* vp = vout + (long)p * (T + 1) * N;
+  if (j1 == T && !kp.seg) {
+    S_store_full<N, R>(st.S, Sp + T * N * N);
+#pragma unroll
+    for (int q = 0; q < N; ++q) vp[T * N + q] = st.v[q];
+  }
+  Tup<N, R> nxt;
+  tup_load(nxt, ep, j1 - 1);
+  for (long k = j1 - 1; k >= j0; --k) {
+    Tup<N, R> a = nxt;
+    if (k - 1 >= j0) tup_load(nxt, ep, k - 1);
+    Aff<N, R> m;
+    fold(a, st.S, st.v, m);
+    S_store_full<N, R>(st.S, Sp + k * N * N);
+#pragma unroll
+    for (int q = 0; q < N; ++q) vp[k * N + q] = st.v[q];
+  }
+}
+
+// Trajectory (Method 1 of Sec. IV-E with the exact block maps, control law of Sec. II-B): the
+// flow is forward in time (place i takes tile i).  The lane's block maps stay in registers
+// between the reduction and the sweep.
+template <int N, int NU, class R>
+__global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __restrict__ elts,
+                                                     const R* __restrict__ Sg,
+                                                     const R* __restrict__ vg,
+                                                     R* __restrict__ xout, R* __restrict__ uout,
+                                                     const LbRecs lb) {
+  using Alg = TrajAlg<N, R>;
+  const int p = blockIdx.y;
+  const int lane = threadIdx.x;
+  const long T = kp.T;
+  const long i = lb_place(lb, p);
+  const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
+  const R* Sp = Sg + (long)p * (T + 1) * N * N;
+  const R* vp = vg + (long)p * (T + 1) * N;
+  static_assert(kTChunk == kChunk && kTTile == kTile, "trajectory tiles are element tiles");
+  const long j0 = i * kTTile + (long)lane * kTChunk;
+  const long j1 = min(j0 + kTChunk, T);
+  const int cnt = (int)max(j1 - j0, 0L);
+  // v at the boundaries j0 .. j1 of the lane's blocks, loaded together (zero past the horizon, for
+  // lanes without blocks and at row T in ragged mode, which does not exist).
+  R vv[kChunk + 1][N];
+#pragma unroll
+  for (int r = 0; r <= kChunk; ++r) {
+    const bool ok = cnt > 0 && r <= cnt && !(kp.seg && j0 + r >= T);
+#pragma unroll
+    for (int q = 0; q < N; ++q) vv[r][q] = ok ? vp[(j0 + r) * N + q] : R(0);
+  }
+  Aff<N, R> mk[kChunk];
+  Aff<N, R> P;
+  aff_identity(P);
+#pragma unroll
+  for (int r = 0; r < kChunk; ++r) {
+    if (r < cnt) {
+      const long k = j0 + r;
+      R Ad[N][N], b[N], C[Sym<N>::size], S[Sym<N>::size];
+      elt_map_part<N, R>(ep, k, Ad, b, C);
+      load_right_S<N, R>(kp, Sp, k, S);
+      block_map<N, R>(Ad, b, C, S, vv[r + 1], mk[r]);
+      aff_then(P, mk[r]);
+    }
+  }
+  wave_scan<Alg>(P, lane);  // lane m: product of lanes 0 .. m; lane 63: the tile
+  Aff<N, R> E, agg;
+  wave_exclusive<Alg>(P, E, lane);
+  Alg::shfl_map(P, agg, 63);
+  typename Alg::State st;
+  lb_resolve<Alg, R>(kp, (const R*)nullptr, p, lb, i, agg, lane, st);
+  if (cnt == 0) return;
+  if (lane != 0) Alg::apply(E, st);  // x at the left end of the lane's blocks
+  R* xp = xout + (long)p * (T + 1) * N;
+  R* up = uout ? uout + (long)p * (T + 1) * NU : nullptr;
+  R Kc[NU][N];
+  const bool per_k = kp.L_sampled || kp.seg;
+  if (up && !per_k) gain_at<N, NU, R>(kp, p, 0, Kc);
+  R xs[kChunk][N], us[kChunk][NU];
+#pragma unroll
+  for (int r = 0; r < kChunk; ++r) {
+    if (r < cnt) {
+      const long k = j0 + r;
+#pragma unroll
+      for (int q = 0; q < N; ++q) xs[r][q] = st.x[q];
+      if (up) {
+        R S[Sym<N>::size];
+        S_load_upper<N, R>(S, Sp + k * N * N);
+        if (per_k) gain_at<N, NU, R>(kp, p, k, Kc);
+        control<N, NU, R>(Kc, S, vv[r], st.x, us[r]);
+      }
+      aff_apply(mk[r], st.x);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kChunk; ++r) {
+    if (r < cnt) {
+#pragma unroll
+      for (int q = 0; q < N; ++q) xp[(j0 + r) * N + q] = xs[r][q];
+    }
+  }
+  if (up) {
+#pragma unroll
+    for (int r = 0; r < kChunk; ++r) {
+      if (r < cnt) {
+#pragma unroll
+        for (int l = 0; l < NU; ++l) up[(j0 + r) * NU + l] = us[r][l];
+      }
+    }
+  }
+  if (j1 == T && !kp.seg) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) xp[T * N + q] = st.x[q];
+    if (up) {
+      R S[Sym<N>::size], vT[N];
+      S_load_upper<N, R>(S, Sp + T * N * N);
+#pragma unroll
+      for (int q = 0; q < N; ++q) vT[q] = vp[T * N + q];
+      if (per_k) gain_at<N, NU, R>(kp, p, T, Kc);
+      control<N, NU, R>(Kc, S, vT, st.x, up + T * NU);
+    }
+  }
+}
 
 // ------------------------------------------------------------------------------------------
 // Method 2 of Sec. IV-E: x_k minimises V(x0, t_0; x, t_k) + V(x, t_k), where the conditional value
@@ -1849,75 +1862,22 @@ struct L {
                          0, s, kp, (R*)elts);
     return hipGetLastError();
   }
-  static hipError_t build_reduce(const KProb& kp, void* elts, void* lvl1, long n1,
-                                 hipStream_t s) {
-    const bool cc = !kp.F_sampled && !kp.L_sampled && !kp.has_c;
-    if (cc)
-      hipLaunchKernelGGL((k_build_reduce<N, NU, R, true>), grid_lanes(n1, kp.batch),
-                         dim3(kThreads), 0, s, kp, (R*)elts, (R*)lvl1, n1);
-    else
-      hipLaunchKernelGGL((k_build_reduce<N, NU, R, false>), grid_lanes(n1, kp.batch),
-                         dim3(kThreads), 0, s, kp, (R*)elts, (R*)lvl1, n1);
-    return hipGetLastError();
-  }
   static hipError_t vreduce0(const KProb& kp, const void* elts, void* dst, long n1,
                              hipStream_t s) {
     hipLaunchKernelGGL((k_vreduce0<N, R>), grid_lanes(n1, kp.batch), dim3(kThreads), 0, s,
                        (const R*)elts, (long)kp.T, (R*)dst, n1);
     return hipGetLastError();
   }
-  static hipError_t vup(const KProb& kp, const void* src, long n_src, void* part, void* dst,
-                        long n_dst, hipStream_t s) {
-    hipLaunchKernelGGL((k_up<ValAlg<N, R>, R>), grid_waves(n_dst, kp.batch), dim3(kThreads), 0, s,
-                       (const R*)src, n_src, (R*)part, (R*)dst, n_dst);
+  static hipError_t vscan(const KProb& kp, const void* elts, void* S, void* v, const LbRecs& lb,
+                          hipStream_t s) {
+    hipLaunchKernelGGL((k_vscan<N, R>), dim3((unsigned)lb.G, kp.batch), dim3(kThreads), 0, s, kp,
+                       (const R*)elts, (R*)S, (R*)v, lb);
     return hipGetLastError();
   }
-  static hipError_t vtop(const KProb& kp, const void* tup, long n, void* val, hipStream_t s) {
-    hipLaunchKernelGGL((k_top<ValAlg<N, R>, R>), dim3(1, kp.batch, 1), dim3(kThreads), 0, s, kp,
-                       (const R*)nullptr, (const R*)tup, n, (R*)val);
-    return hipGetLastError();
-  }
-  static hipError_t vdown(const KProb& kp, const void* tup, long n_child, const void* part,
-                          const void* val_par, long n_par, void* val_child, hipStream_t s) {
-    hipLaunchKernelGGL((k_down<ValAlg<N, R>, R>), grid_waves(n_par, kp.batch), dim3(kThreads), 0,
-                       s, (const R*)tup, n_child, (const R*)part, (const R*)val_par, n_par,
-                       (R*)val_child);
-    return hipGetLastError();
-  }
-  static hipError_t vbottom(const KProb& kp, const void* elts, const void* val1, long n1, void* S,
-                            void* v, void* maps1, hipStream_t s) {
-    hipLaunchKernelGGL((k_vbottom<N, R>), grid_lanes(n1, kp.batch), dim3(kThreads), 0, s, kp,
-                       (const R*)elts, (const R*)val1, n1, (R*)S, (R*)v, (R*)maps1);
-    return hipGetLastError();
-  }
-  static hipError_t tbottom_reduce(const KProb& kp, const void* elts, const void* S,
-                                   const void* v, void* maps1, long n1, hipStream_t s) {
-    hipLaunchKernelGGL((k_tbottom_reduce<N, R>), grid_lanes(n1, kp.batch), dim3(kThreads), 0, s,
-                       kp, (const R*)elts, (const R*)S, (const R*)v, (R*)maps1, n1);
-    return hipGetLastError();
-  }
-  static hipError_t tup(const KProb& kp, const void* src, long n_src, void* part, void* dst,
-                        long n_dst, hipStream_t s) {
-    hipLaunchKernelGGL((k_up<TrajAlg<N, R>, R>), grid_waves(n_dst, kp.batch), dim3(kThreads), 0,
-                       s, (const R*)src, n_src, (R*)part, (R*)dst, n_dst);
-    return hipGetLastError();
-  }
-  static hipError_t ttop(const KProb& kp, const void* maps, long n, void* xs, hipStream_t s) {
-    hipLaunchKernelGGL((k_top<TrajAlg<N, R>, R>), dim3(1, kp.batch, 1), dim3(kThreads), 0, s, kp,
-                       (const R*)nullptr, (const R*)maps, n, (R*)xs);
-    return hipGetLastError();
-  }
-  static hipError_t tdown(const KProb& kp, const void* maps, long n_child, const void* part,
-                          const void* x_par, long n_par, void* x_child, hipStream_t s) {
-    hipLaunchKernelGGL((k_down<TrajAlg<N, R>, R>), grid_waves(n_par, kp.batch), dim3(kThreads),
-                       0, s, (const R*)maps, n_child, (const R*)part, (const R*)x_par, n_par,
-                       (R*)x_child);
-    return hipGetLastError();
-  }
-  static hipError_t tbottom(const KProb& kp, const void* elts, const void* S, const void* v,
-                            const void* x1, long n1, void* x, void* u, hipStream_t s) {
-    hipLaunchKernelGGL((k_tbottom<N, NU, R>), grid_lanes(n1, kp.batch), dim3(kThreads), 0, s, kp,
-                       (const R*)elts, (const R*)S, (const R*)v, (const R*)x1, n1, (R*)x, (R*)u);
+  static hipError_t tscan(const KProb& kp, const void* elts, const void* S, const void* v,
+                          void* x, void* u, const LbRecs& lb, hipStream_t s) {
+    hipLaunchKernelGGL((k_tscan<N, NU, R>), dim3((unsigned)lb.G, kp.batch), dim3(kThreads), 0, s,
+                       kp, (const R*)elts, (const R*)S, (const R*)v, (R*)x, (R*)u, lb);
     return hipGetLastError();
   }
   static hipError_t prep(const KProb& kp, void* consts, hipStream_t s) {
@@ -2001,9 +1961,8 @@ struct L {
     return hipGetLastError();
   }
   static const Ops* ops() {
-    static const Ops o = {prep,    build,          build_reduce, vreduce0, vup,    vtop,
-                          vdown,   vbottom,        tbottom_reduce, tup,    ttop,   tdown,
-                          tbottom, lti_prep,       lti_build,    build_fwd,
+    static const Ops o = {prep,    build,          vscan,        tscan,    vreduce0,
+                          lti_prep,       lti_build,    build_fwd,
                           m2_up,   m2_top,         m2_down,      m2_bottom,
                           dense,   build_split,    build_ckpt};
     return &o;
