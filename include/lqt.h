@@ -209,10 +209,9 @@ lqt_status lqt_dense_output(const lqt_dims *dims, const lqt_problem *prob, const
                             const void *v, const void *x, void *Sd, void *vd, void *xd, void *ud,
                             void *ws, size_t ws_bytes, hipStream_t stream);
 
-/* All three stages in one call (the value kernel also forms level 1 of the trajectory tree, so
- * the elements are read once less; same results as the stage calls up to rounding).
- * elts may be NULL (then the elements live in the workspace); S, v, x must be non-NULL; u may be
- * NULL. */
+/* All three stages in one call (prep, element build, value scan, trajectory scan; the same
+ * kernels and results as the stage calls).  elts may be NULL (then the elements live in the
+ * workspace); S, v, x must be non-NULL; u may be NULL. */
 lqt_status lqt_solve(const lqt_dims *dims, const lqt_problem *prob, void *elts, void *S, void *v,
                      void *x, void *u, void *ws, size_t ws_bytes, hipStream_t stream);
 
@@ -281,9 +280,11 @@ lqt_status lqt_solve_batched(const lqt_ragged *classes, int32_t nclasses, void *
  * element build and level-1 products on the per-lane path; 4, 8 or 16 nodes per wave on the wave
  * path; then concurrent or serial classes) by running them on `stream` (outputs are overwritten)
  * and keep the fastest; choices are cached per class signature for the life of the process
- * (thread-safe).  Without the flag the default configuration is used.  flags & LQT_PLAN_GRAPH
- * (capture the plan into a HIP graph) returns LQT_EUNSUPPORTED in this version of the library.
- * lqt_plan_create synchronises `stream`. */
+ * (thread-safe).  Without the flag the default configuration is used.  flags & LQT_PLAN_GRAPH:
+ * after tuning, the plan's launch sequence is captured once into a HIP graph (on a stream of the
+ * plan's own; the tuner never captures) and lqt_plan_launch replays it with one hipGraphLaunch on
+ * `stream`.  lqt_plan_create synchronises `stream`; lqt_plan_destroy waits for the plan's last
+ * replay before it releases the graph. */
 typedef struct lqt_plan_s *lqt_plan;
 enum { LQT_PLAN_AUTOTUNE = 1, LQT_PLAN_GRAPH = 2 };
 lqt_status lqt_plan_create(const lqt_ragged *classes, int32_t nclasses, void *ws,

@@ -173,12 +173,31 @@ struct lqt_plan_s {
   std::vector<hipStream_t> branch;
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
+  // LQT_PLAN_GRAPH: the launch sequence captured once, on a stream of the plan's own, after
+  // tuning; replayed with hipGraphLaunch.  `done` is recorded behind every replay so that the
+  // executable graph is destroyed only once no replay of it is pending.
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  bool replayed = false;
 };
 
 namespace lqt {
 namespace {
 
 void release(lqt_plan_s* p) {
+  if (p->exec) {
+    if (p->replayed) hipEventSynchronize(p->done);
+    hipGraphExecDestroy(p->exec);
+    p->exec = nullptr;
+  }
+  if (p->graph) hipGraphDestroy(p->graph);
+  p->graph = nullptr;
+  if (p->done) hipEventDestroy(p->done);
+  p->done = nullptr;
+  if (p->cap) hipStreamDestroy(p->cap);
+  p->cap = nullptr;
   for (auto e : p->join) hipEventDestroy(e);
   if (p->fork) hipEventDestroy(p->fork);
   for (auto s : p->branch) hipStreamDestroy(s);
@@ -297,6 +316,29 @@ lqt_status tune(lqt_plan_s* p, hipStream_t s, Choice* ch) {
   return LQT_OK;
 }
 
+// Captures the plan's launch sequence (enqueue with its chosen options) into a graph on the
+// plan's own capture stream: the fork and join events and the branch streams are the plan's,
+// created before and destroyed after the executable graph; nothing is captured while tuning.
+lqt_status capture(lqt_plan_s* p) {
+  PLAN_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+  PLAN_HIP(hipEventCreateWithFlags(&p->done, hipEventDisableTiming));
+  PLAN_HIP(hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal));
+  const lqt_status st = enqueue(p, p->choice.opts, p->choice.parallel, p->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(p->cap, &g);  // ends the capture on every path
+  if (st != LQT_OK) {
+    if (g) hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess || !g) {
+    if (g) hipGraphDestroy(g);
+    return set_error(LQT_EHIP, "hipStreamEndCapture failed");
+  }
+  p->graph = g;
+  PLAN_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+  return LQT_OK;
+}
+
 }  // namespace
 }  // namespace lqt
 
@@ -331,10 +373,6 @@ lqt_status lqt_plan_create(const lqt_ragged* classes, int32_t nclasses, void* ws
   if (!plan) return set_error(LQT_EINVAL, "plan is NULL");
   *plan = nullptr;
   if (flags & ~(LQT_PLAN_AUTOTUNE | LQT_PLAN_GRAPH)) return set_error(LQT_EINVAL, "unknown flags");
-  if (flags & LQT_PLAN_GRAPH)
-    return set_error(LQT_EUNSUPPORTED,
-                     "graph capture of a plan is switched off in this version (its first replay "
-                     "crashed inside hipGraphLaunch; the cause is not established)");
   lqt_plan_s* p = new lqt_plan_s();
   lqt_status st = prepare(classes, nclasses, ws, ws_bytes, p->cls);
   auto fail_with = [&](lqt_status s) {
@@ -380,13 +418,23 @@ lqt_status lqt_plan_create(const lqt_ragged* classes, int32_t nclasses, void* ws
   }
   if (hipStreamSynchronize(stream) != hipSuccess)
     return fail_with(set_error(LQT_EHIP, "stream synchronisation failed"));
+  if (flags & LQT_PLAN_GRAPH) {
+    st = capture(p);
+    if (st != LQT_OK) return fail_with(st);
+  }
   *plan = p;
   return clear_error();
 }
 
 lqt_status lqt_plan_launch(lqt_plan plan, hipStream_t stream) {
   if (!plan) return set_error(LQT_EINVAL, "plan is NULL");
-  PLAN_TRY(enqueue(plan, plan->choice.opts, plan->choice.parallel, stream));
+  if (plan->exec) {
+    PLAN_HIP(hipGraphLaunch(plan->exec, stream));
+    PLAN_HIP(hipEventRecord(plan->done, stream));
+    plan->replayed = true;
+  } else {
+    PLAN_TRY(enqueue(plan, plan->choice.opts, plan->choice.parallel, stream));
+  }
   return clear_error();
 }
 
