@@ -240,110 +240,127 @@ LQT_DEV void gj_solve(R (&M)[N][N], R (&B)[N][NB]) {
 // Yd = M^{-1} (Ad1 - C1 J2), D = M^{-1} C1 and g = M^{-1} (b1 + C1 eta2); then
 //   Ad = Ad2 + Yd + Ad2 Yd,  b = g + Ad2 g + b2,  C = (I + Ad2) D (I + Ad2)^T + C2,
 //   eta = w + Yd^T w + eta1 (w = eta2 - J2 b1),  J = (I + Yd)^T J2 (I + Ad1) + J1.
+// The factorisation shared by both output orders below: M = I + C1 J2 solved against
+// B = [Ad1 - C1 J2 | C1 | b1 + C1 eta2], giving [Yd | D | g] = M^{-1} B.
 template <int N, class R>
-LQT_DEV void combine(const Tup<N, R>& x1, const Tup<N, R>& x2, Tup<N, R>& o) {
+LQT_DEV void combine_solve(const Tup<N, R>& x1, const Tup<N, R>& x2, R (&B)[N][2 * N + 1]) {
   using Y = Sym<N>;
-  R CJ[N][N], M[N][N], B[N][2 * N + 1];
-#pragma unroll
-  for (int i = 0; i < N; ++i)
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-      R s = R(0);
-#pragma unroll
-      for (int k = 0; k < N; ++k) s = fma(x1.C[Y::at(i, k)], x2.J[Y::at(k, j)], s);
-      CJ[i][j] = s;
-      M[i][j] = (i == j) ? R(1) + s : s;
-    }
+  R M[N][N];
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     R g = x1.b[i];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      B[i][j] = x1.A[i][j] - CJ[i][j];
+      R s = R(0);
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(x1.C[Y::at(i, k)], x2.J[Y::at(k, j)], s);
+      M[i][j] = (i == j) ? R(1) + s : s;
+      B[i][j] = x1.A[i][j] - s;
       B[i][N + j] = x1.C[Y::at(i, j)];
       g = fma(x1.C[Y::at(i, j)], x2.e[j], g);
     }
     B[i][2 * N] = g;
   }
   gj_solve<N, 2 * N + 1>(M, B);
-  // Outputs are produced in an order that consumes each input component before the matching
-  // output is written, so `o` may alias x2 (the running product of a reduction).
-  // C: W = (I + Ad2) D, C = W (I + Ad2)^T + C2 (upper triangle)
-  {
-    R Wm[N][N];
+}
+
+// Output parts of the combination from the solved B (see combine).  Each reads only the inputs
+// named and writes one component of o; the two orders below rely on that.
+template <int N, class R>
+LQT_DEV void combine_C(const Tup<N, R>& x2, const R (&B)[N][2 * N + 1], R (&oC)[Sym<N>::size]) {
+  using Y = Sym<N>;
+  // W = (I + Ad2) D, C = W (I + Ad2)^T + C2 (upper triangle)
+  R Wm[N][N];
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+  for (int i = 0; i < N; ++i)
 #pragma unroll
-      for (int j = 0; j < N; ++j) {
-        R s = B[i][N + j];
+    for (int j = 0; j < N; ++j) {
+      R s = B[i][N + j];
 #pragma unroll
-        for (int k = 0; k < N; ++k) s = fma(x2.A[i][k], B[k][N + j], s);
-        Wm[i][j] = s;
-      }
+      for (int k = 0; k < N; ++k) s = fma(x2.A[i][k], B[k][N + j], s);
+      Wm[i][j] = s;
+    }
 #pragma unroll
-    for (int i = 0; i < N; ++i)
+  for (int i = 0; i < N; ++i)
 #pragma unroll
-      for (int j = i; j < N; ++j) {
-        R s = Wm[i][j];
+    for (int j = i; j < N; ++j) {
+      R s = Wm[i][j];
 #pragma unroll
-        for (int l = 0; l < N; ++l) s = fma(Wm[i][l], x2.A[j][l], s);
-        o.C[Y::at(i, j)] = x2.C[Y::at(i, j)] + s;
-      }
-  }
+      for (int l = 0; l < N; ++l) s = fma(Wm[i][l], x2.A[j][l], s);
+      oC[Y::at(i, j)] = x2.C[Y::at(i, j)] + s;
+    }
+}
+
+template <int N, class R>
+LQT_DEV void combine_b(const Tup<N, R>& x2, const R (&B)[N][2 * N + 1], R (&ob)[N]) {
   // b = g + Ad2 g + b2
-  {
-    R bn[N];
+  R bn[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      R s = R(0);
+  for (int i = 0; i < N; ++i) {
+    R s = R(0);
 #pragma unroll
-      for (int k = 0; k < N; ++k) s = fma(x2.A[i][k], B[k][2 * N], s);
-      bn[i] = x2.b[i] + B[i][2 * N] + s;
+    for (int k = 0; k < N; ++k) s = fma(x2.A[i][k], B[k][2 * N], s);
+    bn[i] = x2.b[i] + B[i][2 * N] + s;
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) ob[i] = bn[i];
+}
+
+// w = eta2 - J2 b1
+template <int N, class R>
+LQT_DEV void combine_w(const Tup<N, R>& x1, const Tup<N, R>& x2, R (&w)[N]) {
+  using Y = Sym<N>;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = x2.e[i];
+#pragma unroll
+    for (int k = 0; k < N; ++k) s = fma(-x2.J[Y::at(i, k)], x1.b[k], s);
+    w[i] = s;
+  }
+}
+
+// eta = w + Yd^T w + eta1 (o.e may be x1.e)
+template <int N, class R>
+LQT_DEV void combine_e(const R (&e1)[N], const R (&w)[N], const R (&B)[N][2 * N + 1], R (&oe)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    R s = R(0);
+#pragma unroll
+    for (int k = 0; k < N; ++k) s = fma(B[k][i], w[k], s);
+    oe[i] = e1[i] + (w[i] + s);
+  }
+}
+
+// J: P = J2 (I + Ad1), J = (I + Yd)^T P + J1 (upper triangle; o.J may be x1.J or x2.J)
+template <int N, class R>
+LQT_DEV void combine_J(const Tup<N, R>& x1, const Tup<N, R>& x2, const R (&B)[N][2 * N + 1],
+                       R (&oJ)[Sym<N>::size]) {
+  using Y = Sym<N>;
+  R P[N][N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      R s = x2.J[Y::at(i, j)];
+#pragma unroll
+      for (int k = 0; k < N; ++k) s = fma(x2.J[Y::at(i, k)], x1.A[k][j], s);
+      P[i][j] = s;
     }
 #pragma unroll
-    for (int i = 0; i < N; ++i) o.b[i] = bn[i];
-  }
-  // eta = w + Yd^T w + eta1, w = eta2 - J2 b1
-  {
-    R w[N];
+  for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      R s = x2.e[i];
+    for (int j = i; j < N; ++j) {
+      R s = P[i][j];
 #pragma unroll
-      for (int k = 0; k < N; ++k) s = fma(-x2.J[Y::at(i, k)], x1.b[k], s);
-      w[i] = s;
+      for (int k = 0; k < N; ++k) s = fma(B[k][i], P[k][j], s);
+      oJ[Y::at(i, j)] = x1.J[Y::at(i, j)] + s;
     }
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      R s = R(0);
-#pragma unroll
-      for (int k = 0; k < N; ++k) s = fma(B[k][i], w[k], s);
-      o.e[i] = x1.e[i] + (w[i] + s);
-    }
-  }
-  // J: P = J2 (I + Ad1), J = (I + Yd)^T P + J1 (upper triangle)
-  {
-    R P[N][N];
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        R s = x2.J[Y::at(i, j)];
-#pragma unroll
-        for (int k = 0; k < N; ++k) s = fma(x2.J[Y::at(i, k)], x1.A[k][j], s);
-        P[i][j] = s;
-      }
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-#pragma unroll
-      for (int j = i; j < N; ++j) {
-        R s = P[i][j];
-#pragma unroll
-        for (int k = 0; k < N; ++k) s = fma(B[k][i], P[k][j], s);
-        o.J[Y::at(i, j)] = x1.J[Y::at(i, j)] + s;
-      }
-  }
-  // Ad = Ad2 + Yd + Ad2 Yd (row by row: row i of the result needs only row i of Ad2)
+}
+
+// Ad = Ad2 + Yd + Ad2 Yd (row by row: row i of the result needs only row i of Ad2; o.A may be
+// x1.A or x2.A)
+template <int N, class R>
+LQT_DEV void combine_A(const R (&A2)[N][N], const R (&B)[N][2 * N + 1], R (&oA)[N][N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     R row[N];
@@ -351,12 +368,51 @@ LQT_DEV void combine(const Tup<N, R>& x1, const Tup<N, R>& x2, Tup<N, R>& o) {
     for (int j = 0; j < N; ++j) {
       R s = R(0);
 #pragma unroll
-      for (int k = 0; k < N; ++k) s = fma(x2.A[i][k], B[k][j], s);
-      row[j] = x2.A[i][j] + B[i][j] + s;
+      for (int k = 0; k < N; ++k) s = fma(A2[i][k], B[k][j], s);
+      row[j] = A2[i][j] + B[i][j] + s;
     }
 #pragma unroll
-    for (int j = 0; j < N; ++j) o.A[i][j] = row[j];
+    for (int j = 0; j < N; ++j) oA[i][j] = row[j];
   }
+}
+
+// Lemma 7 (Sec. IV-A): o = x1 (x) x2 with x1 on [s, tau] (earlier) and x2 on [tau, t] (later).
+// With M = I + C1 J2 (invertible by Lemma 10, Appendix B):
+//   A = A2 M^{-1} A1,  b = A2 M^{-1} (b1 + C1 eta2) + b2,  C = A2 M^{-1} C1 A2^T + C2,
+//   eta = A1^T M^{-T} (eta2 - J2 b1) + eta1,  J = A1^T M^{-T} J2 A1 + J1,
+// using (I + J2 C1)^{-1} = M^{-T}.  One factorisation serves all: Y = M^{-1} A1 = I + Yd with
+// Yd = M^{-1} (Ad1 - C1 J2), D = M^{-1} C1 and g = M^{-1} (b1 + C1 eta2); then
+//   Ad = Ad2 + Yd + Ad2 Yd,  b = g + Ad2 g + b2,  C = (I + Ad2) D (I + Ad2)^T + C2,
+//   eta = w + Yd^T w + eta1 (w = eta2 - J2 b1),  J = (I + Yd)^T J2 (I + Ad1) + J1.
+// The outputs are produced in an order that consumes each input component before the matching
+// output is written, so `o` may alias x2 (the running product of a right-to-left reduction).
+template <int N, class R>
+LQT_DEV void combine(const Tup<N, R>& x1, const Tup<N, R>& x2, Tup<N, R>& o) {
+  R B[N][2 * N + 1];
+  combine_solve(x1, x2, B);
+  combine_C(x2, B, o.C);
+  combine_b(x2, B, o.b);
+  R w[N];
+  combine_w(x1, x2, w);
+  combine_e(x1.e, w, B, o.e);
+  combine_J(x1, x2, B, o.J);
+  combine_A(x2.A, B, o.A);
+}
+
+// x1 <- x1 (x) x2 in place: the same arithmetic as combine, its outputs ordered so that every
+// component of x1 is read before it is overwritten (w and J, which read b1 and Ad1, come first),
+// which saves the registers of a separate result tuple.
+template <int N, class R>
+LQT_DEV void combine_into_first(Tup<N, R>& x1, const Tup<N, R>& x2) {
+  R B[N][2 * N + 1];
+  combine_solve(x1, x2, B);
+  R w[N];
+  combine_w(x1, x2, w);
+  combine_J(x1, x2, B, x1.J);
+  combine_e(x1.e, w, B, x1.e);
+  combine_C(x2, B, x1.C);
+  combine_b(x2, B, x1.b);
+  combine_A(x2.A, B, x1.A);
 }
 
 // One step of the value recursion: the Lemma with a right operand of the terminal form

@@ -1173,10 +1173,19 @@ struct ValAlg {
   static LQT_DEV void identity(Map& m) { tup_identity(m); }
   static LQT_DEV void load(Map& m, const R* b, long k) { tup_load(m, b, k); }
   static LQT_DEV void store(const Map& m, R* b, long k) { tup_store(m, b, k); }
+  // Lemma 7; in place when out is the first operand (combine_into_first) or the second (combine
+  // writes each output after its inputs are read), through a temporary otherwise.  The address
+  // test folds away after inlining.
   static LQT_DEV void chain(const Map& first, const Map& second, Map& out) {
-    Map o;
-    combine(first, second, o);
-    out = o;
+    if (&out == &first) {
+      combine_into_first(out, second);
+    } else if (&out == &second) {
+      combine(first, second, out);
+    } else {
+      Map o;
+      combine(first, second, o);
+      out = o;
+    }
   }
   static LQT_DEV void apply(const Map& m, State& st) {
     Aff<N, R> unused;
@@ -1499,10 +1508,19 @@ struct PreAlg {
   static LQT_DEV void identity(Map& m) { tup_identity(m); }
   static LQT_DEV void load(Map& m, const R* b, long k) { tup_load(m, b, k); }
   static LQT_DEV void store(const Map& m, R* b, long k) { tup_store(m, b, k); }
+  // Lemma 7; in place when out is the first operand (combine_into_first) or the second (combine
+  // writes each output after its inputs are read), through a temporary otherwise.  The address
+  // test folds away after inlining.
   static LQT_DEV void chain(const Map& first, const Map& second, Map& out) {
-    Map o;
-    combine(first, second, o);
-    out = o;
+    if (&out == &first) {
+      combine_into_first(out, second);
+    } else if (&out == &second) {
+      combine(first, second, out);
+    } else {
+      Map o;
+      combine(first, second, o);
+      out = o;
+    }
   }
   static LQT_DEV void apply(const Map& m, State& st) { fwd_fold(m, st.S, st.v); }
   static LQT_DEV void sload(State& st, const R* b, long k) { val_load<N, R>(st.S, st.v, b, k); }
