@@ -215,6 +215,22 @@ lqt_status lqt_dense_output(const lqt_dims *dims, const lqt_problem *prob, const
 lqt_status lqt_solve(const lqt_dims *dims, const lqt_problem *prob, void *elts, void *S, void *v,
                      void *x, void *u, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): lqt_solve with its scratch memory in a fixed device array of the
+ * library instead of a workspace argument.  The array holds LQT_NOALLOC_SCRATCH_BYTES bytes on
+ * every device the library runs on, from the first call on that device until the process ends;
+ * a problem whose scratch need (lqt_noalloc_scratch_size) exceeds it returns LQT_EWORKSPACE
+ * before anything is launched.  Unlike lqt_solve, elts is required (the caller's output buffer,
+ * layout above), so only per-problem constants and the scan records live in the scratch array
+ * (about 2 MB for the 2^20-block point mass).  The call allocates and frees nothing.  All calls
+ * on one device share its array, and each clears what must start at zero: calls that overlap on
+ * one device (concurrent streams or threads) race and must not be issued.  `stream` must belong
+ * to the current device.  Other arguments and errors as lqt_solve. */
+#define LQT_NOALLOC_SCRATCH_BYTES (64u << 20)
+size_t lqt_noalloc_scratch_size(const lqt_dims *dims);
+lqt_status lqt_solve_noalloc(const lqt_dims *dims, const lqt_problem *prob, void *elts, void *S,
+                             void *v, void *x, void *u, hipStream_t stream);
+
 /* Adjoint of lqt_solve for a loss whose gradient with respect to the trajectory is dLdx
  * [batch][T+1][nx] (the exact adjoint of the discrete scheme, not of the continuous problem).
  * Overwrites (accumulates nothing):

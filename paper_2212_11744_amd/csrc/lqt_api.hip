@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <initializer_list>
+#include <mutex>
 #include <string>
 
 #include "../../include/lqt.h"
@@ -126,7 +127,8 @@ WTree wtree_for(const lqt_dims* d) { return wave_tree(d->T, kWaveChunk); }
 // wc: nodes per wave of the wave path's trees (the layout for wc also serves any larger wc);
 // nconsts: number of problems whose constants are prepared (the batch, or the problems of a
 // ragged class).
-size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, long nconsts) {
+size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, long nconsts,
+              bool ws_elts) {
   const size_t es = dsize(d->dtype);
   const long B = d->batch;
   size_t off = 0;
@@ -167,7 +169,7 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
         }
       }
     }
-    if (call == LQT_CALL_SOLVE) {
+    if (call == LQT_CALL_SOLVE && ws_elts) {
       void* e = take(es * B * ne_of(d->nx) * (size_t)padt(d->T));
       if (w) w->elts = e;
     }
@@ -212,7 +214,7 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
       }
     }
   }
-  if (call == LQT_CALL_SOLVE || call == LQT_CALL_BACKWARD) {
+  if ((call == LQT_CALL_SOLVE && ws_elts) || call == LQT_CALL_BACKWARD) {
     void* e = take(es * B * ne_of(d->nx) * (size_t)padt(d->T));
     if (w) w->elts = e;
   }
@@ -257,7 +259,7 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
 namespace {
 
 size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w) {
-  return layout(d, call, base, w, kWaveChunk, d->batch);
+  return layout(d, call, base, w, kWaveChunk, d->batch, true);
 }
 
 lqt_status check_dims_valid(const lqt_dims* d) {
@@ -702,6 +704,85 @@ lqt_status lqt_solve(const lqt_dims* dims, const lqt_problem* prob, void* elts, 
   SolveOpts o;
   o.wave_chunk = kWaveChunk;
   LQT_TRY(run_solve(dims, kp, w, e, S, v, x, u, o, stream));
+  const long nb = dims->batch, T1 = (long)dims->T + 1, nx = dims->nx;
+  LQT_TRY(finite_check(dims, w, stream, {{S, nb * T1 * nx * nx, false}, {v, nb * T1 * nx, false},
+                                         {x, nb * T1 * nx, false}, {u, nb * T1 * dims->nu, false},
+                                         {elts, 0, true}}));
+  return ok();
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// The solve without allocation (lqt_solve_noalloc): its scratch memory is a fixed device array of
+// the library, one per GPU the library runs on (each device's copy lives until the process ends).
+// Host code only ever uses the device address hipGetSymbolAddress returns for the current
+// device, never the array's name.
+// ------------------------------------------------------------------------------------------
+namespace lqt {
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = (size_t)LQT_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up once per device).
+lqt_status noalloc_scratch(void** out) {
+  int dev = -1;
+  LQT_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(LQT_EUNSUPPORTED, "device %d: the no-allocation entry point serves devices 0..%d",
+                dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LQT_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return LQT_OK;
+}
+
+}  // namespace
+}  // namespace lqt
+
+extern "C" {
+
+size_t lqt_noalloc_scratch_size(const lqt_dims* dims) {
+  if (check_dims_valid(dims) != LQT_OK) return 0;
+  return layout(dims, LQT_CALL_SOLVE, nullptr, nullptr, kWaveChunk, dims->batch, false);
+}
+
+lqt_status lqt_solve_noalloc(const lqt_dims* dims, const lqt_problem* prob, void* elts, void* S,
+                             void* v, void* x, void* u, hipStream_t stream) {
+  LQT_TRY(check_supported(dims));
+  LQT_TRY(check_problem(dims, prob, true, true));
+  const size_t es = dsize(dims->dtype);
+  LQT_TRY(check_ptr(elts, "elts", es));
+  LQT_TRY(check_ptr(S, "S", es));
+  LQT_TRY(check_ptr(v, "v", es));
+  LQT_TRY(check_ptr(x, "x", es));
+  if (u) LQT_TRY(check_ptr(u, "u", es));
+  const size_t need = layout(dims, LQT_CALL_SOLVE, nullptr, nullptr, kWaveChunk, dims->batch, false);
+  if (need > kNoAllocScratchBytes)
+    return fail(LQT_EWORKSPACE,
+                "this problem needs %zu bytes of scratch; the no-allocation entry point has %zu "
+                "(use lqt_solve with a workspace)",
+                need, kNoAllocScratchBytes);
+  void* base = nullptr;
+  LQT_TRY(noalloc_scratch(&base));
+  Work w;
+  layout(dims, LQT_CALL_SOLVE, (char*)base, &w, kWaveChunk, dims->batch, false);
+  KProb kp = make_kprob(dims, prob, w.consts);
+  SolveOpts o;
+  o.wave_chunk = kWaveChunk;
+  LQT_TRY(run_solve(dims, kp, w, elts, S, v, x, u, o, stream));
   const long nb = dims->batch, T1 = (long)dims->T + 1, nx = dims->nx;
   LQT_TRY(finite_check(dims, w, stream, {{S, nb * T1 * nx * nx, false}, {v, nb * T1 * nx, false},
                                          {x, nb * T1 * nx, false}, {u, nb * T1 * dims->nu, false},

@@ -253,7 +253,9 @@ hipError_t lb_clear(const LbRecs& r, hipStream_t s);
 
 // Workspace layout of one call (lqt_api.hip); the layout for wave_chunk wc also serves any larger
 // chunk.  nconsts: problems whose per-problem constants are prepared.
-size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, long nconsts);
+// ws_elts: a solve keeps its elements in the workspace (false when the caller provides them).
+size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, long nconsts,
+              bool ws_elts = true);
 
 // Prep, element build, value scan and trajectory scan for validated arguments.
 lqt_status run_solve(const lqt_dims* d, const KProb& kp, const Work& w, void* elts, void* S,

@@ -81,6 +81,10 @@ def lib():
         L.lqt_forward_traj_method2.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_dense_output.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, vp, vp, sz, st]
         L.lqt_solve.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, sz, st]
+        L.lqt_solve_noalloc.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, st]
+        L.lqt_solve_noalloc.restype = ctypes.c_int
+        L.lqt_noalloc_scratch_size.argtypes = [P(Dims)]
+        L.lqt_noalloc_scratch_size.restype = sz
         L.lqt_backward.argtypes = [P(Dims), P(Problem), vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, st]
         for f in ("lqt_build_elements", "lqt_build_elements_forward", "lqt_build_elements_split",
                   "lqt_scan_value",
@@ -333,6 +337,32 @@ def dense_output(prob: DeviceProblem, S, v, x, out: Optional[dict] = None, ws=No
                                   _ptr(out["S"]), _ptr(out["v"]), _ptr(out["x"]), _ptr(out.get("u")),
                                   _ptr(ws), ws.numel(), _stream()))
     return out
+
+
+def solve_noalloc(prob: DeviceProblem, out: Optional[dict] = None):
+    """lqt_solve_noalloc: the whole solve with the library's fixed scratch array instead of a
+    workspace (the library allocates nothing; torch allocates the outputs here unless `out` is
+    given).  Returns dict with elts, S, v, x, u."""
+    if out is None:
+        out = {"elts": empty_elements(prob),
+               "S": _empty(prob, prob.batch, prob.T + 1, prob.nx, prob.nx),
+               "v": _empty(prob, prob.batch, prob.T + 1, prob.nx),
+               "x": _empty(prob, prob.batch, prob.T + 1, prob.nx),
+               "u": _empty(prob, prob.batch, prob.T + 1, prob.nu)}
+    d, p = prob.dims(), prob.ptrs()
+    _check(lib().lqt_solve_noalloc(ctypes.byref(d), ctypes.byref(p), _ptr(out["elts"]),
+                                   _ptr(out["S"]), _ptr(out["v"]), _ptr(out["x"]),
+                                   _ptr(out.get("u")), _stream()))
+    return out
+
+
+def noalloc_scratch_size(prob: DeviceProblem) -> int:
+    """Bytes of the fixed scratch array lqt_solve_noalloc needs for this problem."""
+    d = prob.dims()
+    return int(lib().lqt_noalloc_scratch_size(ctypes.byref(d)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def solve(prob: DeviceProblem, out: Optional[dict] = None, ws=None, keep_elements=False):
