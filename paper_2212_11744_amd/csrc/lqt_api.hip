@@ -198,8 +198,10 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
       r->nwords = nwords;
     }
   };
-  if (call == LQT_CALL_SCAN_VALUE || call == LQT_CALL_SOLVE) take_lb(w ? &w->lbv : nullptr, kVTile, ne_of(d->nx), nv_of(d->nx));
-  if (want_t) take_lb(w ? &w->lbt : nullptr, kTTile, nm_of(d->nx), d->nx);
+  // laid out for one block per lane (the most tiles any chunk gives)
+  if (call == LQT_CALL_SCAN_VALUE || call == LQT_CALL_SOLVE)
+    take_lb(w ? &w->lbv : nullptr, 64, ne_of(d->nx), nv_of(d->nx));
+  if (want_t) take_lb(w ? &w->lbt : nullptr, 64, nm_of(d->nx), d->nx);
   // Method 2: the tree of node products and prefix states
   if (call == LQT_CALL_TRAJ_METHOD2) {
     for (int l = 1; l <= t.levels; ++l) {
@@ -448,19 +450,30 @@ KProb make_kprob(const lqt_dims* d, const lqt_problem* p, const void* consts) {
   return k;
 }
 
+// The records of a single-pass scan with `chunk` blocks per lane: tile and group counts of the
+// launch (the arrays are laid out for one block per lane, so they hold any chunk's records).
+LbRecs lb_for(const LbRecs& r, long T, int chunk) {
+  LbRecs l = r;
+  l.G = (T + 64L * chunk - 1) / (64L * chunk);
+  l.NG = (l.G + kLbGroupTiles - 1) / kLbGroupTiles;
+  return l;
+}
+
 // Value scan over elements (single pass; per-lane path).
 lqt_status run_value(const Ops* o, const KProb& kp, const Work& w, const void* elts, void* S,
                      void* v, hipStream_t s) {
+  const int c = scan_chunk(kp.T, kScanMaxVChunk);
   LQT_HIP(lb_clear(w.lbv, s));
-  LQT_HIP(o->vscan(kp, elts, S, v, w.lbv, s));
+  LQT_HIP(o->vscan(kp, elts, S, v, lb_for(w.lbv, kp.T, c), c, s));
   return LQT_OK;
 }
 
 // Trajectory scan (single pass; per-lane path): x_k, u_k of every boundary.
 lqt_status run_traj(const Ops* o, const KProb& kp, const Work& w, const void* elts,
                     const void* S, const void* v, void* x, void* u, hipStream_t s) {
+  const int c = scan_chunk(kp.T, kScanMaxTChunk);
   LQT_HIP(lb_clear(w.lbt, s));
-  LQT_HIP(o->tscan(kp, elts, S, v, x, u, w.lbt, s));
+  LQT_HIP(o->tscan(kp, elts, S, v, x, u, lb_for(w.lbt, kp.T, c), c, s));
   return LQT_OK;
 }
 

@@ -74,9 +74,19 @@ __host__ __device__ inline int consts_count(int nx, int nu) { return nx * nx + 2
 constexpr int kLaneChunk = 4;
 constexpr int kWaveSpan = 256;
 constexpr int kLbGroupTiles = 64;  // tiles per group record of the single-pass scans
-// Blocks per lane and per tile (one wave) of the single-pass value and trajectory scans.
-constexpr int kVChunk = 8, kVTile = kVChunk * 64;
-constexpr int kTChunk = 4, kTTile = kTChunk * 64;
+// Blocks per lane of the single-pass scans (a tile is one wave: 64 lanes), chosen from the
+// horizon.  A longer chunk costs serial steps per lane; more tiles cost look-back depth (about
+// log2 of the tiles in flight, in Lemma 7 combinations) and, beyond the ~1024 waves resident at
+// once, another round of tiles.  Measured on the FP64 point mass (value scan): 4 blocks per lane
+// are best from 2^13 to 2^18 blocks (2^16: 73 us vs 89 us with 1), 8 from 2^19 on (2^20: 359 us
+// vs 395 us with 4); very short horizons do best with 1 (64 blocks: one tile, no serial steps).
+// The trajectory scan keeps its lanes' block maps in registers and stops at 4.  The records are
+// laid out for one block per lane, so they hold any chunk's tiles.
+constexpr int kScanMaxVChunk = 8, kScanMaxTChunk = 4;
+inline int scan_chunk(long T, int cmax) {
+  const int c = T <= (1L << 11) ? 1 : T <= (1L << 13) ? 2 : T < (1L << 19) ? 4 : 8;
+  return c < cmax ? c : cmax;
+}
 
 struct Tree {
   int levels = 0;
@@ -137,9 +147,11 @@ struct Ops {
   hipError_t (*prep)(const KProb&, void* consts, hipStream_t);
   hipError_t (*build)(const KProb&, void* elts, hipStream_t);
   // single-pass scans: values S, v of every boundary; trajectory x, u (u nullable)
-  hipError_t (*vscan)(const KProb&, const void* elts, void* S, void* v, const LbRecs&, hipStream_t);
+  // (chunk: blocks per lane, 1, 2, 4 or 8 (value) / 4 (trajectory); see scan_chunk)
+  hipError_t (*vscan)(const KProb&, const void* elts, void* S, void* v, const LbRecs&, int chunk,
+                      hipStream_t);
   hipError_t (*tscan)(const KProb&, const void* elts, const void* S, const void* v, void* x,
-                      void* u, const LbRecs&, hipStream_t);
+                      void* u, const LbRecs&, int chunk, hipStream_t);
   // level 1 of the node products (4 blocks per lane), for the Method 2 tree
   hipError_t (*vreduce0)(const KProb&, const void* elts, void* lvl1, long n1, hipStream_t);
   // time-invariant path: response tables, then the elements from them

@@ -1283,7 +1283,7 @@ struct TrajAlg {
 // holds two tuples and a Lemma 7 combination), a horizon of 2^20 blocks then needs two rounds of
 // resident waves instead of four, and the per-tile costs that do not grow with the tile (the
 // lane scan of the wave and the look-back) are spread over twice the blocks.
-template <int N, class R>
+template <int N, class R, int CH>
 __global__ __launch_bounds__(kThreads) void k_vscan(const KProb kp, const R* __restrict__ elts,
                                                      R* __restrict__ Sout, R* __restrict__ vout,
                                                      const LbRecs lb) {
@@ -1294,8 +1294,10 @@ __global__ __launch_bounds__(kThreads) void k_vscan(const KProb kp, const R* __r
   const long i = lb_place(lb, p);
   const long tile = lb.G - 1 - i;
   const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
-  const long j0 = tile * kVTile + (long)lane * kVChunk;
-  const long j1 = min(j0 + kVChunk, T);
+  const long j0 = tile * (64L * CH) + (long)lane * CH;
+  const long j1 = min(j0 + CH, T);
+  // lanes holding blocks (fewer than 64 only in the tile at the end of a short horizon)
+  const int active = (int)min((T - tile * 64L * CH + CH - 1) / CH, 64L);
   typename Alg::State st;
   // The lane's exclusive product waits in LDS during the look-back (registers are short: the
   // look-back combines tuples of its own).
@@ -1303,7 +1305,7 @@ __global__ __launch_bounds__(kThreads) void k_vscan(const KProb kp, const R* __r
   {
     Tup<N, R> P;
     serial_product(ep, j0, j1, P);
-    wave_scan<Alg>(P, lane);  // lane m: product of lanes m .. 63; lane 0: the tile
+    wave_scan<Alg>(P, lane, tree_levels(active));  // lane m: product of lanes m ..; lane 0: tile
     Tup<N, R> E;
     wave_exclusive<Alg>(P, E, lane);
     tup_store_rec<PlainAcc>(E, &sE[0][0], kThreads, lane);
@@ -1337,7 +1339,7 @@ __global__ __launch_bounds__(kThreads) void k_vscan(const KProb kp, const R* __r
 // Trajectory (Method 1 of Sec. IV-E with the exact block maps, control law of Sec. II-B): the
 // flow is forward in time (place i takes tile i).  The lane's block maps stay in registers
 // between the reduction and the sweep.
-template <int N, int NU, class R>
+template <int N, int NU, class R, int CH>
 __global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __restrict__ elts,
                                                      const R* __restrict__ Sg,
                                                      const R* __restrict__ vg,
@@ -1351,24 +1353,24 @@ __global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __r
   const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
   const R* Sp = Sg + (long)p * (T + 1) * N * N;
   const R* vp = vg + (long)p * (T + 1) * N;
-  static_assert(kTChunk == kChunk && kTTile == kTile, "trajectory tiles are element tiles");
-  const long j0 = i * kTTile + (long)lane * kTChunk;
-  const long j1 = min(j0 + kTChunk, T);
+  const long j0 = i * (64L * CH) + (long)lane * CH;
+  const long j1 = min(j0 + CH, T);
   const int cnt = (int)max(j1 - j0, 0L);
+  const int active = (int)min((T - i * 64L * CH + CH - 1) / CH, 64L);
   // v at the boundaries j0 .. j1 of the lane's blocks, loaded together (zero past the horizon, for
   // lanes without blocks and at row T in ragged mode, which does not exist).
-  R vv[kChunk + 1][N];
+  R vv[CH + 1][N];
 #pragma unroll
-  for (int r = 0; r <= kChunk; ++r) {
+  for (int r = 0; r <= CH; ++r) {
     const bool ok = cnt > 0 && r <= cnt && !(kp.seg && j0 + r >= T);
 #pragma unroll
     for (int q = 0; q < N; ++q) vv[r][q] = ok ? vp[(j0 + r) * N + q] : R(0);
   }
-  Aff<N, R> mk[kChunk];
+  Aff<N, R> mk[CH];
   Aff<N, R> P;
   aff_identity(P);
 #pragma unroll
-  for (int r = 0; r < kChunk; ++r) {
+  for (int r = 0; r < CH; ++r) {
     if (r < cnt) {
       const long k = j0 + r;
       R Ad[N][N], b[N], C[Sym<N>::size], S[Sym<N>::size];
@@ -1378,10 +1380,10 @@ __global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __r
       aff_then(P, mk[r]);
     }
   }
-  wave_scan<Alg>(P, lane);  // lane m: product of lanes 0 .. m; lane 63: the tile
+  wave_scan<Alg>(P, lane, tree_levels(active));  // lane m: product of lanes 0 .. m
   Aff<N, R> E, agg;
   wave_exclusive<Alg>(P, E, lane);
-  Alg::shfl_map(P, agg, 63);
+  Alg::shfl_map(P, agg, active - 1);  // the last lane with blocks: product of the whole tile
   typename Alg::State st;
   lb_resolve<Alg, R>(kp, (const R*)nullptr, p, lb, i, agg, lane, st);
   if (cnt == 0) return;
@@ -1391,9 +1393,9 @@ __global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __r
   R Kc[NU][N];
   const bool per_k = kp.L_sampled || kp.seg;
   if (up && !per_k) gain_at<N, NU, R>(kp, p, 0, Kc);
-  R xs[kChunk][N], us[kChunk][NU];
+  R xs[CH][N], us[CH][NU];
 #pragma unroll
-  for (int r = 0; r < kChunk; ++r) {
+  for (int r = 0; r < CH; ++r) {
     if (r < cnt) {
       const long k = j0 + r;
 #pragma unroll
@@ -1408,7 +1410,7 @@ __global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __r
     }
   }
 #pragma unroll
-  for (int r = 0; r < kChunk; ++r) {
+  for (int r = 0; r < CH; ++r) {
     if (r < cnt) {
 #pragma unroll
       for (int q = 0; q < N; ++q) xp[(j0 + r) * N + q] = xs[r][q];
@@ -1416,7 +1418,7 @@ __global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __r
   }
   if (up) {
 #pragma unroll
-    for (int r = 0; r < kChunk; ++r) {
+    for (int r = 0; r < CH; ++r) {
       if (r < cnt) {
 #pragma unroll
         for (int l = 0; l < NU; ++l) up[(j0 + r) * NU + l] = us[r][l];
@@ -1886,16 +1888,37 @@ struct L {
                        (const R*)elts, (long)kp.T, (R*)dst, n1);
     return hipGetLastError();
   }
+  template <int CH>
+  static void vscan_c(const KProb& kp, const void* elts, void* S, void* v, const LbRecs& lb,
+                      hipStream_t s) {
+    hipLaunchKernelGGL((k_vscan<N, R, CH>), dim3((unsigned)lb.G, kp.batch), dim3(kThreads), 0, s,
+                       kp, (const R*)elts, (R*)S, (R*)v, lb);
+  }
   static hipError_t vscan(const KProb& kp, const void* elts, void* S, void* v, const LbRecs& lb,
-                          hipStream_t s) {
-    hipLaunchKernelGGL((k_vscan<N, R>), dim3((unsigned)lb.G, kp.batch), dim3(kThreads), 0, s, kp,
-                       (const R*)elts, (R*)S, (R*)v, lb);
+                          int chunk, hipStream_t s) {
+    switch (chunk) {
+      case 1: vscan_c<1>(kp, elts, S, v, lb, s); break;
+      case 2: vscan_c<2>(kp, elts, S, v, lb, s); break;
+      case 4: vscan_c<4>(kp, elts, S, v, lb, s); break;
+      case 8: vscan_c<8>(kp, elts, S, v, lb, s); break;
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
+  template <int CH>
+  static void tscan_c(const KProb& kp, const void* elts, const void* S, const void* v, void* x,
+                      void* u, const LbRecs& lb, hipStream_t s) {
+    hipLaunchKernelGGL((k_tscan<N, NU, R, CH>), dim3((unsigned)lb.G, kp.batch), dim3(kThreads), 0,
+                       s, kp, (const R*)elts, (const R*)S, (const R*)v, (R*)x, (R*)u, lb);
+  }
   static hipError_t tscan(const KProb& kp, const void* elts, const void* S, const void* v,
-                          void* x, void* u, const LbRecs& lb, hipStream_t s) {
-    hipLaunchKernelGGL((k_tscan<N, NU, R>), dim3((unsigned)lb.G, kp.batch), dim3(kThreads), 0, s,
-                       kp, (const R*)elts, (const R*)S, (const R*)v, (R*)x, (R*)u, lb);
+                          void* x, void* u, const LbRecs& lb, int chunk, hipStream_t s) {
+    switch (chunk) {
+      case 1: tscan_c<1>(kp, elts, S, v, x, u, lb, s); break;
+      case 2: tscan_c<2>(kp, elts, S, v, x, u, lb, s); break;
+      case 4: tscan_c<4>(kp, elts, S, v, x, u, lb, s); break;
+      default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
   }
   static hipError_t prep(const KProb& kp, void* consts, hipStream_t s) {

@@ -1,14 +1,15 @@
 """Single-pass value and trajectory scans (decoupled look-back) vs the oracle, through the C ABI.
 
-The scans give every tile (512 blocks in the value scan, 256 in the trajectory scan) a place in
-the flow order from a counter; a tile resolves the state at its free end from up to 63 preceding
-tile records and then from group records (64 tiles each), 64 groups per round.  The horizons
-below put the last tile of either scan just before, on and after a group boundary, and past the
-first 64 groups (a second round of group records); batches
-check that every problem has its own counter and records; a reused workspace checks that the
-status words are cleared before every call.  Stage tests feed oracle elements to the GPU scans,
-so only the scans' rounding differs (1e-11 normwise); whole solves are held to 1e-9 (FP64) and
-1e-4 (FP32).
+The scans give every tile (one wave; 1, 2, 4 or 8 blocks per lane, chosen from the horizon: 1 up
+to 2^11 blocks, 2 up to 2^13, 4 below 2^19, then 8 in the value scan and 4 in the trajectory
+scan) a place in the flow order from a counter; a tile resolves the state at its free end from up
+to 63 preceding tile records and then from group records (64 tiles each), 64 groups per round.
+The horizons below use every chunk size, put the last tile just before, on and after group
+boundaries, and go past the first 64 groups (a second round of group records); batches check
+that every problem has its own counter and records; a reused workspace checks that the status
+words are cleared before every call.  Stage tests feed oracle elements to the GPU scans, so only
+the scans' rounding differs (1e-11 normwise); whole solves are held to 1e-9 (FP64) and 1e-4
+(FP32).
 """
 import numpy as np
 import pytest
@@ -55,9 +56,10 @@ def _stage_check(p, tol=1e-11, reps=1):
             assert e < tol, f"T={p.T} rep {rep} {name}: {e:.3e}"
 
 
-@pytest.mark.parametrize("T", [5, 256, 257, 512, 513, 63 * TTILE, GROUP * TTILE, GROUP * TTILE + 1,
-                               GROUP * VTILE - 1, GROUP * VTILE, GROUP * VTILE + 1,
-                               65 * VTILE + 17, 2 * GROUP * VTILE + 255])
+@pytest.mark.parametrize("T", [5, 64, 65, 256, 257, 512, 513, 4095, 4096, 4097, 63 * TTILE,
+                               GROUP * TTILE, GROUP * TTILE + 1, GROUP * VTILE - 1, GROUP * VTILE,
+                               GROUP * VTILE + 1, 65 * VTILE + 17, 2 * GROUP * VTILE + 255,
+                               2 ** 17 + 5])
 def test_stage_scans_across_group_boundaries(T):
     p = W.random_stable(900 + T % 1000, nx=3, nu=2, T=T, n=2, tf=0.002 * T + 0.5)
     _stage_check(p)
