@@ -1013,6 +1013,305 @@ __global__ __launch_bounds__(64) void kw_build_rows(const KProb kp, R* __restric
 }
 
 // ------------------------------------------------------------------------------------------
+// Element build for nx <= 8 in FP64 on the matrix cores, two blocks per wave.  A 16 x 16 product
+// tile of v_mfma_f64_16x16x4f64 takes the two blocks' left factors stacked (rows 8 b + i) and
+// their right factors side by side (columns 8 b + j), so its diagonal 8 x 8 blocks are the two
+// blocks' products (the off-diagonal blocks mix the two and are not used).  In the result layout
+// (lane 16 q + j holds entries (q + 4 r, j)) the lanes of columns 8 b .. 8 b + 7 hold rows q and
+// q + 4 of block b in registers r = 2 b and 2 b + 1, so every state matrix of the RK4 recursion
+// (A - I, J: start, stage, accumulator; C: accumulator) is two registers per lane with nothing
+// wasted; only operands pass through LDS (rows padded).  Entries beyond nx are zero throughout.
+// Same arithmetic as kw_build_mfma16 (K = G J - F, kA = K + A K, kJ = -Q + J K - F^T J,
+// kC = -(A Lc)(A Lc)^T, Theorem 8 with K factored out), two barriers per stage.
+// ------------------------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(64, 3) void kw_build_mfma8(const KProb kp, double* __restrict__ elts) {
+  static_assert(N <= 8, "two blocks of at most 8 states per 16 x 16 tile");
+  constexpr int XP = 9, YP = 17;  // padded row lengths: stacked (16 x 8), side by side (8 x 16)
+  typedef double R;
+  // left factors stacked [16][XP], right factors side by side [8][YP]
+  __shared__ R xA[16 * XP], xJ[16 * XP], xG[16 * XP], xFT[16 * XP], xAL[16 * XP];
+  __shared__ R yJ[8 * YP], yK[8 * YP], yL[8 * YP], yALT[8 * YP];
+  __shared__ R sF[16 * XP], sQ[16 * XP];  // F and Q of each block's problem (row 8 b + i)
+  __shared__ R se[2][8], sw[2][8], sr[2][3][8], sc[2][3][8];  // samples: 3 per RK4 step
+  const int lane = lane_id(), li = lane & 15, lq = lane >> 4;
+  const int b = li >> 3, lj = li & 7;  // block of this lane's columns, column inside the block
+  const int nu = kp.nu;
+  const long T = kp.T;
+  const int nn = kp.n;
+  // the two blocks of this wave and their problems
+  long kb2[2], s0b[2], tkb[2];
+  int pb[2];
+  bool liveb[2], sepb[2];
+  for (int c = 0; c < 2; ++c) {
+    const long k = 2L * blockIdx.x + c;
+    int p = blockIdx.y;
+    long s0 = (long)p * (2L * nn * T + 1), tk = (long)p * (T + 1) + k;
+    bool live = k < T, sep = false;
+    if (kp.seg && live) {
+      p = seg_find(kp.seg, kp.nseg, k);
+      sep = k == kp.seg[p + 1] - 1 || k == T - 1;
+      s0 = (long)p * (1 - 2L * nn);
+      tk = k;
+    }
+    kb2[c] = k;
+    s0b[c] = s0;
+    tkb[c] = tk;
+    pb[c] = p;
+    liveb[c] = live;
+    sepb[c] = sep;
+  }
+  const bool work0 = liveb[0] && !sepb[0], work1 = liveb[1] && !sepb[1];
+  // per-block constants: G (stacked), F (rows 8 b + i), -F^T (stacked), Q, Lc (side by side)
+  for (int e = lane; e < 2 * 64; e += 64) {
+    const int c = e >> 6, i = (e >> 3) & 7, j = e & 7;
+    const bool wk = c == 0 ? work0 : work1;
+    const bool in = wk && i < N && j < N;
+    const long pc = kp.seg ? pb[c] : 0;
+    const R* cs = (const R*)kp.consts + (long)pb[c] * consts_count(N, nu);
+    xG[(8 * c + i) * XP + j] = in ? cs[consts_off_G(N, nu) + i * N + j] : R(0);
+    sQ[(8 * c + i) * XP + j] = in ? ((const R*)kp.Q)[(long)pb[c] * N * N + i * N + j] : R(0);
+    if (!kp.F_sampled) {
+      const R* Fc = (const R*)kp.F + pc * N * N;
+      sF[(8 * c + i) * XP + j] = in ? Fc[i * N + j] : R(0);
+      xFT[(8 * c + i) * XP + j] = in ? -Fc[j * N + i] : R(0);
+    }
+    yL[i * YP + 8 * c + j] = in && j < nu ? cs[consts_off_Lc(N, nu) + i * nu + j] : R(0);
+  }
+  const R h0 = work0 ? (((const R*)kp.t)[tkb[0] + 1] - ((const R*)kp.t)[tkb[0]]) / R(nn) : R(0);
+  const R h1 = work1 ? (((const R*)kp.t)[tkb[1] + 1] - ((const R*)kp.t)[tkb[1]]) / R(nn) : R(0);
+  const R h = b == 0 ? h0 : h1;  // (selects, not indexing: per-lane indices would go to scratch)
+  // state: entries (lq + 4 s, lj) of block b in slot s
+  R yAs[2], yJs[2], yCs[2], aAs[2], aJs[2], tAs[2], tJs[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) yAs[t] = yJs[t] = yCs[t] = R(0);
+  R ye = R(0), yb = R(0), ae = R(0), te = R(0);  // component lj of block b (all four lq alike)
+  // Reference (and drift) samples of an RK4 step: lane L < 48 holds sample 2 n (k + 1) - 2 m - o
+  // (o = (L % 24) / 8) component L % 8 of block L / 24; the next step's are loaded while the
+  // current step runs, so only the first step waits for memory.
+  const int pc_ = lane < 48 ? lane / 24 : 0, po = (lane % 24) / 8, pi = lane & 7;
+  const bool pl = lane < 48 && (pc_ == 0 ? work0 : work1) && pi < N;
+  const long sbase = (pc_ == 0 ? s0b[0] + 2L * nn * kb2[0] : s0b[1] + 2L * nn * kb2[1]) - po;
+  auto sample_at = [&](int m, const void* arr) -> R {
+    if (!pl || !arr) return R(0);
+    return ((const R*)arr)[(sbase + 2L * (nn - m)) * N + pi];
+  };
+  R nr = sample_at(0, kp.r), ncv = sample_at(0, kp.has_c ? kp.c : nullptr);
+  wsync();
+  for (int m = 0; m < nn; ++m) {
+    if (lane < 48) {
+      sr[pc_][po][pi] = nr;
+      sc[pc_][po][pi] = ncv;
+    }
+    if (m + 1 < nn) {
+      nr = sample_at(m + 1, kp.r);
+      ncv = sample_at(m + 1, kp.has_c ? kp.c : nullptr);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      tAs[t] = yAs[t];
+      tJs[t] = yJs[t];
+    }
+    te = ye;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int jo = st == 0 ? 0 : (st == 3 ? 2 : 1);  // sample offset below 2 n (k + 1) - 2 m
+      const R wk = (st == 0 || st == 3) ? -h / R(6) : -h / R(3);
+      const R cn = st == 2 ? -h : -h / R(2);
+      if (kp.F_sampled) {
+        for (int e = lane; e < 2 * 64; e += 64) {
+          const int c = e >> 6, i = (e >> 3) & 7, q = e & 7;
+          const bool in = (c == 0 ? work0 : work1) && i < N && q < N;
+          const long j = s0b[c] + 2L * nn * kb2[c] + 2L * (nn - m) - jo;
+          const R* Fj = (const R*)kp.F + j * N * N;
+          sF[(8 * c + i) * XP + q] = in ? Fj[i * N + q] : R(0);
+          xFT[(8 * c + i) * XP + q] = in ? -Fj[q * N + i] : R(0);
+        }
+      }
+      if (kp.L_sampled) {  // Lc = L(t_j) W (side by side), G = Lc Lc^T after the barrier
+        for (int e = lane; e < 2 * 64; e += 64) {
+          const int c = e >> 6, i = (e >> 3) & 7, l = e & 7;
+          const bool in = (c == 0 ? work0 : work1) && i < N && l < nu;
+          const long j = s0b[c] + 2L * nn * kb2[c] + 2L * (nn - m) - jo;
+          const R* Lj = (const R*)kp.L + j * N * nu;
+          const R* Wc = (const R*)kp.consts + (long)pb[c] * consts_count(N, nu) + consts_off_W(N, nu);
+          R a = R(0);
+          if (in)
+            for (int q = 0; q < nu; ++q) a = fma(Lj[i * nu + q], Wc[q * nu + l], a);
+          yL[i * YP + 8 * c + l] = a;
+        }
+      }
+      // publish the stage values: A (left), J (left and right), eta
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int i = lq + 4 * t;
+        xA[(8 * b + i) * XP + lj] = tAs[t];
+        xJ[(8 * b + i) * XP + lj] = tJs[t];
+        yJ[i * YP + li] = tJs[t];
+      }
+      if (lq == 0) se[b][lj] = te;
+      wsync();
+      if (kp.L_sampled) {
+        for (int e = lane; e < 2 * 64; e += 64) {
+          const int c = e >> 6, i = (e >> 3) & 7, q = e & 7;
+          R a = R(0);
+          for (int l = 0; l < nu; ++l) a = fma(yL[i * YP + 8 * c + l], yL[q * YP + 8 * c + l], a);
+          xG[(8 * c + i) * XP + q] = a;
+        }
+        wsync();
+      }
+      // K = G J - F
+      wd4 K;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) K[r] = (r >> 1) == b ? -sF[(8 * b + lq + 4 * (r & 1)) * XP + lj] : R(0);
+#pragma unroll
+      for (int k0 = 0; k0 < 8; k0 += 4)
+        K = __builtin_amdgcn_mfma_f64_16x16x4f64(xG[li * XP + k0 + lq], yJ[(k0 + lq) * YP + li], K, 0, 0, 0);
+      // A Lc = Lc + (A - I) Lc
+      wd4 ALc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        ALc[r] = (r >> 1) == b ? yL[(lq + 4 * (r & 1)) * YP + li] : R(0);
+#pragma unroll
+      for (int k0 = 0; k0 < 8; k0 += 4)
+        ALc = __builtin_amdgcn_mfma_f64_16x16x4f64(xA[li * XP + k0 + lq], yL[(k0 + lq) * YP + li], ALc, 0, 0, 0);
+      // w = G eta + c: lane 16 q + li sums terms 2 q, 2 q + 1 of component lj of block b
+      R w = R(0);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) w = fma(xG[(8 * b + lj) * XP + 2 * lq + t], se[b][2 * lq + t], w);
+      w += __shfl_xor(w, 16);
+      w += __shfl_xor(w, 32);
+      w += sc[b][jo][lj];
+      // publish K (right factor) and A Lc (left factor and its transpose as a right factor)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int i = lq + 4 * t;
+        const R kv = K[2 * b + t], av = ALc[2 * b + t];
+        yK[i * YP + li] = kv;
+        xAL[(8 * b + i) * XP + lj] = av;
+        yALT[lj * YP + 8 * b + i] = av;
+      }
+      if (lq == 0) sw[b][lj] = w;
+      wsync();
+      // kA = K + (A - I) K
+      wd4 kA = K;
+#pragma unroll
+      for (int k0 = 0; k0 < 8; k0 += 4)
+        kA = __builtin_amdgcn_mfma_f64_16x16x4f64(xA[li * XP + k0 + lq], yK[(k0 + lq) * YP + li], kA, 0, 0, 0);
+      // kJ = -Q + J K - F^T J
+      wd4 kJ;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) kJ[r] = (r >> 1) == b ? -sQ[(8 * b + lq + 4 * (r & 1)) * XP + lj] : R(0);
+#pragma unroll
+      for (int k0 = 0; k0 < 8; k0 += 4)
+        kJ = __builtin_amdgcn_mfma_f64_16x16x4f64(xJ[li * XP + k0 + lq], yK[(k0 + lq) * YP + li], kJ, 0, 0, 0);
+#pragma unroll
+      for (int k0 = 0; k0 < 8; k0 += 4)
+        kJ = __builtin_amdgcn_mfma_f64_16x16x4f64(xFT[li * XP + k0 + lq], yJ[(k0 + lq) * YP + li], kJ, 0, 0, 0);
+      // kC = -(A Lc)(A Lc)^T (nu <= 4 columns: one k-slice)
+      wd4 kC = {0.0, 0.0, 0.0, 0.0};
+      kC = __builtin_amdgcn_mfma_f64_16x16x4f64(lq < nu ? xAL[li * XP + lq] : R(0),
+                                                lq < nu ? yALT[lq * YP + li] : R(0), kC, 0, 0, 0);
+      if (nu > 4)
+        kC = __builtin_amdgcn_mfma_f64_16x16x4f64(4 + lq < nu ? xAL[li * XP + 4 + lq] : R(0),
+                                                  4 + lq < nu ? yALT[(4 + lq) * YP + li] : R(0), kC, 0, 0, 0);
+      // keta = K^T eta + J c - Q r;  kb = -(w + (A - I) w): component lj of block b, terms 2 q,
+      // 2 q + 1 on lane 16 q + li, then a butterfly over q
+      R ke = R(0), kbv = R(0);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int q = 2 * lq + t;
+        ke = fma(yK[q * YP + li], se[b][q], ke);
+        if (kp.has_c) ke = fma(xJ[(8 * b + lj) * XP + q], sc[b][jo][q], ke);
+        ke = fma(-sQ[(8 * b + lj) * XP + q], sr[b][jo][q], ke);
+        kbv = fma(xA[(8 * b + lj) * XP + q], sw[b][q], kbv);
+      }
+      ke += __shfl_xor(ke, 16);
+      ke += __shfl_xor(ke, 32);
+      kbv += __shfl_xor(kbv, 16);
+      kbv += __shfl_xor(kbv, 32);
+      kbv = -(kbv + sw[b][lj]);
+      // RK4 accumulation and the next stage value (this lane's block only)
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const R ka = kA[2 * b + t], kj = kJ[2 * b + t], kc = kC[2 * b + t];
+        aAs[t] = st == 0 ? fma(wk, ka, yAs[t]) : fma(wk, ka, aAs[t]);
+        aJs[t] = st == 0 ? fma(wk, kj, yJs[t]) : fma(wk, kj, aJs[t]);
+        yCs[t] = fma(-wk, kc, yCs[t]);
+        if (st < 3) {
+          tAs[t] = fma(cn, ka, yAs[t]);
+          tJs[t] = fma(cn, kj, yJs[t]);
+        }
+      }
+      ae = st == 0 ? fma(wk, ke, ye) : fma(wk, ke, ae);
+      yb = fma(wk, kbv, yb);
+      if (st < 3) te = fma(cn, ke, ye);
+      wsync();  // the next stage overwrites the operand buffers
+    }
+    // end of step: J and C take their upper entries
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int i = lq + 4 * t;
+      yAs[t] = aAs[t];
+      yJ[i * YP + li] = aJs[t];
+      yK[i * YP + li] = yCs[t];
+    }
+    ye = ae;
+    wsync();
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int i = lq + 4 * t;
+      yJs[t] = i > lj ? yJ[lj * YP + 8 * b + i] : aJs[t];
+      yCs[t] = i > lj ? yK[lj * YP + 8 * b + i] : yCs[t];
+    }
+    wsync();
+  }
+  // outputs of this lane's block (separators write their fixed element)
+  if (!liveb[b]) return;
+  const int pbl = pb[b];
+  const GRef<R> o = elt_ref(elts, kp.seg ? 0 : pbl, kb2[b], T, ne_w(N));
+  constexpr int ns = N * (N + 1) / 2;
+  constexpr int oB = N * N, oC = oB + N, oE = oC + ns, oJ = oE + N;
+  if (sepb[b]) {  // separator after problem p (see KProb): A - I = -I, b = next x0, C = 0, J = Qf
+    const R* Qf = (const R*)kp.Qf + (long)pbl * N * N;
+    const R* rf = (const R*)kp.rf + (long)pbl * N;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int i = lq + 4 * t;
+      if (i < N && lj < N) {
+        o.g[(i * N + lj) * o.st] = i == lj ? R(-1) : R(0);
+        if (lj >= i) {
+          o.g[(oC + pk(i, lj, N)) * o.st] = R(0);
+          o.g[(oJ + pk(i, lj, N)) * o.st] = Qf[i * N + lj];
+        }
+      }
+    }
+    if (lq == 0 && lj < N) {
+      R e = R(0);
+      for (int q = 0; q < N; ++q) e = fma(Qf[lj * N + q], rf[q], e);
+      o.g[(oB + lj) * o.st] = pbl + 1 >= kp.nseg ? R(0) : ((const R*)kp.x0)[(long)(pbl + 1) * N + lj];
+      o.g[(oE + lj) * o.st] = e;
+    }
+    return;
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int i = lq + 4 * t;
+    if (i < N && lj < N) {
+      o.g[(i * N + lj) * o.st] = yAs[t];
+      if (lj >= i) {
+        o.g[(oC + pk(i, lj, N)) * o.st] = yCs[t];
+        o.g[(oJ + pk(i, lj, N)) * o.st] = yJs[t];
+      }
+    }
+  }
+  if (lq == 0 && lj < N) {
+    o.g[(oB + lj) * o.st] = yb;
+    o.g[(oE + lj) * o.st] = ye;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Element build at nx = 16 in FP64 on the matrix cores, one wave per block.  Every 16 x 16
 // matrix of the RK4 state (A - I, J: start value, stage value, accumulator; C: accumulator) stays
 // in registers in the result layout of v_mfma_f64_16x16x4f64 (lane 16 q + j holds entries
@@ -1632,7 +1931,10 @@ namespace {
 
 template <int N, class R>
 hipError_t wave_build_t(const KProb& kp, void* elts, hipStream_t s) {
-  if constexpr (N <= 8)
+  if constexpr (N <= 8 && sizeof(R) == 8)
+    hipLaunchKernelGGL((kw_build_mfma8<N>), dim3((unsigned)((kp.T + 1) / 2), kp.batch), dim3(64), 0,
+                       s, kp, (double*)elts);
+  else if constexpr (N <= 8)
     hipLaunchKernelGGL((kw_build_rows<N, R>), dim3((unsigned)((kp.T + 7) / 8), kp.batch), dim3(64),
                        0, s, kp, (R*)elts);
   else if constexpr (kMfma<N, R>)
