@@ -5,6 +5,9 @@ Gradients of Q, R, Qf are symmetric (derivative for symmetric perturbations), so
 entrywise gradients are symmetrised before comparison.  Tolerance: 1e-9 normwise against the
 oracle; central differences (h = 1e-6) 1e-6 for Q, R and 1e-8 for r, x0 (x is affine in them).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -15,6 +18,8 @@ from paper_2212_11744_amd import lqt
 from paper_2212_11744_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
 def _np(t):
@@ -71,6 +76,26 @@ def test_adjoint_large_against_dual_jvp():
             _, df = O.objective_jvp(p, Ws[b], {name: d})
             got = float(np.sum(_np(g[name][b]) * d))
             assert abs(got - df) <= 1e-9 * max(1.0, abs(df)), (b, name, got, df)
+
+
+def test_adjoint_full_size_entrywise_against_golden():
+    """The differentiated workload's shape (point mass, T = 2^16 blocks x 4 RK4 steps, two problems
+    in one batch): every entry of dQ, dR, dQf, drf, dx0 and dr at 64 sampled samples against the
+    oracle's exact directional derivatives along unit directions (tests/golden/
+    adjoint_point_mass_T2p16.json, written by make_adjoint_golden.py, which calls only the
+    oracle).  1e-9 normwise per gradient (for dr, over the sampled entries)."""
+    g = json.load(open(os.path.join(GOLDEN, "adjoint_point_mass_T2p16.json")))
+    T, n = g["T"], g["n_steps"]
+    probs = [W.point_mass(s, T, n) for s in g["seeds"]]
+    Ws = [np.random.default_rng(g["w_seed0"] + b).standard_normal((T + 1, 4)) for b in range(len(probs))]
+    got = _gpu_grads(probs, Ws)
+    for b in range(len(probs)):
+        for name, entries in g["grads"][b].items():
+            ref = np.array([v for _, v in entries])
+            arr = _np(got[name][b])
+            mine = np.array([arr[tuple(idx)] for idx, _ in entries])
+            e = relerr(mine, ref)
+            assert e < 1e-9, f"problem {b} d{name}: {e:.3e} over {len(entries)} entries"
 
 
 def test_autograd_function_and_central_differences():
