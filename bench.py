@@ -53,6 +53,21 @@ def build_flops_per_block(nx: int, nu: int, n: int, has_c: bool = False) -> int:
     return 2 * n * (3 * per_stage + last_stage)
 
 
+# Dense-generic flop estimate of one block of the element build (nx = 4, nu = 2, n = 4): the
+# theorem's right-hand sides evaluated as written, FMA = 2 (the survey's per-sub-interval figure).
+DENSE_GENERIC_BUILD_FLOPS = 19000
+# Algorithmic HBM bytes per block of the two scan stages at nx = 4, nu = 2 in FP64 (halved in FP32):
+# value scan 352 (element) + 128 (S, full) + 32 (v) = 512; trajectory 240 (A, b, C of the element)
+# + 160 (S, v) + 32 (x) + 16 (u) = 448.
+SCAN_VALUE_BYTES, FORWARD_TRAJ_BYTES = 512, 448
+
+
+def _hbm_frac(nbytes: int, ms: float) -> dict:
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    return {"bytes": nbytes, "ms": ms, "achieved_GBps": gbps, "peak_GBps": PEAK["hbm_GBps"],
+            "frac": gbps / PEAK["hbm_GBps"]}
+
+
 def build_bytes_per_block(nx: int, n: int, es: int) -> int:
     """HBM bytes per block of the element build: 2n new reference samples read, one element
     (2 nx^2 + 3 nx values) written."""
@@ -192,7 +207,19 @@ def main(argv=None):
         "roofline": {"bound": "alu", "kernel": "k_build (element build)", "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
                      "flops_per_launch": flops, "launch_ms": ms_build,
+                     "flops_per_block": build_flops_per_block(4, 2, n),
+                     "flops_per_block_counting": "the kernel's own formulation (K = G J - F factored "
+                                                 "out, packed symmetric products); frac uses it",
+                     "flops_per_block_dense_generic": DENSE_GENERIC_BUILD_FLOPS,
+                     "frac_dense_generic": DENSE_GENERIC_BUILD_FLOPS * T / (ms_build * 1e-3) / 1e12 / peak,
                      "algorithmic_bytes_per_launch": build_bytes_per_block(4, n, es) * T},
+        # The two scans are bound by HBM: achieved algorithmic bytes (value scan: element read +
+        # S (full) and v written; trajectory: element map part + S, v read, x, u written) over
+        # each stage call's time, against 8 TB/s.
+        "scan_hbm": {
+            "value": _hbm_frac(SCAN_VALUE_BYTES * es // 8 * T, ms_scan),
+            "trajectory": _hbm_frac(FORWARD_TRAJ_BYTES * es // 8 * T, ms_traj),
+        },
         "stages_ms": {"build_elements": ms_build, "scan_value": ms_scan, "forward_traj": ms_traj,
                       "build_elements_forward": ms_fwd, "forward_traj_method2": ms_m2,
                       "build_elements_split": ms_split, "dense_output": ms_dense},
