@@ -268,7 +268,12 @@ lqt_status lqt_backward(const lqt_dims *dims, const lqt_problem *prob, const voi
  * (A = 0, b = x0 of the next problem, C = 0, eta = Qf rf, J = Qf).  Folded into a value
  * function (Theorem 6, Lemma 7) the separator returns the problem's terminal value (Sec. IV-D)
  * whatever follows it, and its closed-loop map (Sec. IV-E) sends any state to the next x0, so
- * one scan of each kind solves every problem of the class.
+ * one scan of each kind solves every problem of the class.  Launches per class: problem
+ * constants, elements, clearing of status words, and one launch for both scans, whose waves take
+ * tiles (nx <= 4: value tiles in the value scan's order, then trajectory tiles) or tree nodes
+ * (nx >= 5: every level of both trees, in dependency order) from a work queue; a wave only waits
+ * for work taken before its own, so every wait ends.  The number of launches does not depend on
+ * the number of problems.
  * ------------------------------------------------------------------------------------------- */
 typedef struct lqt_ragged {
   int32_t nx, nu, n_steps, dtype; /* as in lqt_dims                                             */
@@ -292,9 +297,10 @@ lqt_status lqt_solve_batched(const lqt_ragged *classes, int32_t nclasses, void *
  * the launch stream (or one after another when tuning prefers that).  The arrays named in
  * `classes` and the workspace are bound to the plan: refill them in place between launches and
  * keep them alive until lqt_plan_destroy; launches of one plan must not overlap.
- * flags & LQT_PLAN_AUTOTUNE: time the candidate configurations (per class: fused or separate
- * element build and level-1 products on the per-lane path; 4, 8 or 16 nodes per wave on the wave
- * path; then concurrent or serial classes) by running them on `stream` (outputs are overwritten)
+ * flags & LQT_PLAN_AUTOTUNE: time the candidate configurations (per class: the blocks per lane
+ * of the value tiles on the per-lane path, two candidates chosen from the class's rows among 1,
+ * 4 and 8; 4, 8 or 16 nodes per wave on the wave path; then concurrent or serial classes) by
+ * running them on `stream` (outputs are overwritten)
  * and keep the fastest; choices are cached per class signature for the life of the process
  * (thread-safe).  Without the flag the default configuration is used.  flags & LQT_PLAN_GRAPH:
  * after tuning, the plan's launch sequence is captured once into a HIP graph (on a stream of the

@@ -14,6 +14,8 @@
 
 #define LQT_DEV __device__ __forceinline__
 
+#include "coherent.hpp"
+
 namespace lqt {
 
 template <int N>
@@ -120,27 +122,6 @@ LQT_DEV void tup_store(const Tup<N, R>& x, R* __restrict__ base, long k) {
 #pragma unroll
   for (int i = 0; i < Sym<N>::size; ++i) base[tix<L::NE>(L::J + i, k)] = x.J[i];
 }
-
-// Access policies of the record functions below.  PlainAcc: ordinary loads and stores (LDS, or
-// memory private to one wave).  DevAcc: relaxed atomic loads and stores at agent scope, which are
-// coherent per location across the XCDs of the device without any cache maintenance (they go
-// past the non-coherent caches); the single-pass scans exchange every record value this way.
-struct PlainAcc {
-  template <class R>
-  static LQT_DEV void st(R* p, R v) { *p = v; }
-  template <class R>
-  static LQT_DEV R ld(const R* p) { return *p; }
-};
-struct DevAcc {
-  template <class R>
-  static LQT_DEV void st(R* p, R v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  template <class R>
-  static LQT_DEV R ld(const R* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-};
 
 // Records: value q of record r at base[q * stride + r] (element order).
 template <class Acc, int N, class R>

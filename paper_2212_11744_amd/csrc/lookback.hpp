@@ -22,10 +22,10 @@
 // before it, however many tiles are still busy; with flat tile records alone the inclusive states
 // would advance by at most 64 tiles per look-back round trip.
 //
-// Memory ordering without cache maintenance: every record value and status word is accessed with
-// relaxed atomics at agent scope, which are coherent per location across the XCDs and go past
-// the per-XCD L2 caches instead of requiring them to be written back or invalidated (an
-// agent-scope release or acquire does both, for the whole L2, on every use: with thousands of
+// Memory ordering without cache maintenance (coherent.hpp): every record value and status word is
+// accessed with relaxed atomics at agent scope, which are coherent per location across the XCDs
+// and go past the per-XCD L2 caches instead of requiring them to be written back or invalidated
+// (an agent-scope release or acquire does both, for the whole L2, on every use: with thousands of
 // tiles per kernel that flushes the caches the element loads rely on).  A record's payload is
 // written by one lane, which waits until those stores are complete at device scope before it
 // stores the status word; a reader loads status words, and only once the statuses it needs are
@@ -41,27 +41,17 @@ namespace lqt {
 
 constexpr unsigned kLbAgg = 1;   // aggregate published
 constexpr unsigned kLbIncl = 2;  // aggregate and inclusive state published
+constexpr unsigned kLbDone = 3;  // inclusive state published and the tile's outputs written
+                                 // (set by launches that read the outputs back themselves)
 constexpr int kLbGroup = kLbGroupTiles;
 
 // Besides the tree-scan members, an algebra used here provides record access with value q of
 // record r at base[q * stride + r]: store_rec / load_rec (maps), sstore_rec / sload_rec (states).
 // The records live in an LbRecs (lqt_internal.hpp).
 
-LQT_DEV unsigned lb_flag_load(const unsigned* f) { return DevAcc::ld(f); }
-
-// Stores status word v once every earlier store of this lane is complete at device scope
-// (s_waitcnt vmcnt(0); the compiler barriers keep the stores on their side of it).
-LQT_DEV void lb_flag_store(unsigned* f, unsigned v) {
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unconstrained (GFX9 encoding)
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  DevAcc::st(f, v);
-}
-
-// Payload loads of records whose status was just seen: issued after the status loads returned
-// (their values decided the branch that leads here); the barrier keeps the compiler from moving
-// them above.
-LQT_DEV void lb_acquire() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+LQT_DEV unsigned lb_flag_load(const unsigned* f) { return lq_flag_load(f); }
+LQT_DEV void lb_flag_store(unsigned* f, unsigned v) { lq_flag_store(f, v); }
+LQT_DEV void lb_acquire() { lq_acquire(); }
 
 // Place of this wave's tile in the flow order of problem p (one atomic per wave).
 LQT_DEV long lb_place(const LbRecs& lb, int p) {
@@ -100,7 +90,7 @@ LQT_DEV void lb_reduce(typename Alg::Map& m, int lane, int n) {
 LQT_DEV int lb_wait(const unsigned* flag, long idx, int n, int lane) {
   for (;;) {
     const unsigned f = lane < n ? lb_flag_load(flag + idx - 1 - lane) : 0u;
-    const unsigned long long incl = __ballot(lane < n && f == kLbIncl);
+    const unsigned long long incl = __ballot(lane < n && f >= kLbIncl);
     const unsigned long long ready = __ballot(lane < n && f >= kLbAgg);
     const int lp = incl ? __ffsll((long long)incl) - 1 : n;
     const unsigned long long need = lp >= 64 ? ~0ull : ((1ull << lp) - 1ull);

@@ -91,6 +91,50 @@ const WaveFns* wave_fns(int nx, int dtype) {
 
 }  // namespace
 
+// Stage order of kw_solve_queue: value reduce 1 .. L, value top, value down L - 1 .. 1, value
+// bottom, trajectory reduce 2 .. L, trajectory top, trajectory down L - 1 .. 1, bottom.
+bool wave_queue(const WTree& t, long batch, const Work& w, WQueue* q) {
+  if (t.levels > kWqMaxLevels || !w.wq_done) return false;
+  const int L = t.levels;
+  q->levels = L;
+  q->wc = t.wc;
+  for (int l = 0; l <= L; ++l) q->n[l] = t.n[l];
+  for (int l = 1; l <= L; ++l) {
+    q->vtup[l] = w.vtup[l];
+    q->vval[l] = w.vval[l];
+    q->tmap[l] = w.tmap[l];
+    q->tx[l] = w.tx[l];
+  }
+  int ns = 0;
+  long at = 0;
+  auto add = [&](int kind, int level, long nodes) {
+    q->kind[ns] = kind;
+    q->level[ns] = level;
+    q->start[ns] = at;
+    at += batch * nodes;
+    ++ns;
+  };
+  enum { VRed = 0, VTop, VDown, VBot, TRed, TTop, TDown, TBot };  // WqKind of lqt_wave.hip
+  for (int l = 1; l <= L; ++l) add(VRed, l, t.n[l]);
+  add(VTop, L, 1);
+  for (int l = L - 1; l >= 1; --l) add(VDown, l, t.n[l + 1]);
+  add(VBot, 1, t.n[1]);
+  for (int l = 2; l <= L; ++l) add(TRed, l, t.n[l]);
+  add(TTop, L, 1);
+  for (int l = L - 1; l >= 1; --l) add(TDown, l, t.n[l + 1]);
+  add(TBot, 1, t.n[1]);
+  q->nst = ns;
+  q->total = at;
+  q->done = w.wq_done;
+  return at + 1 <= w.wq_words;
+}
+
+hipError_t wave_solve_queue(const KProb& kp, int dtype, const WQueue& q, const void* elts, void* S,
+                            void* v, void* x, void* u, hipStream_t s) {
+  const WaveFns* f = wave_fns(kp.nx, dtype);
+  return f ? f->solve_queue(kp, q, elts, S, v, x, u, s) : hipErrorInvalidValue;
+}
+
 hipError_t wave_build(const KProb& kp, int dtype, void* elts, hipStream_t s) {
   const WaveFns* f = wave_fns(kp.nx, dtype);
   return f ? f->build(kp, elts, s) : hipErrorInvalidValue;
@@ -172,6 +216,17 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
     if (call == LQT_CALL_SOLVE && ws_elts) {
       void* e = take(es * B * ne_of(d->nx) * (size_t)padt(d->T));
       if (w) w->elts = e;
+    }
+    if (call == LQT_CALL_SOLVE) {
+      // status words of the queue solve (an item per tree node and stage) and its counter
+      long items = 3 * t.n[1] + 2;
+      for (int l = 2; l <= t.levels; ++l) items += 4 * t.n[l];
+      const long words = B * items + 1;
+      void* q = take(sizeof(unsigned) * words);
+      if (w) {
+        w->wq_done = (unsigned*)q;
+        w->wq_words = words;
+      }
     }
     return off;
   }
@@ -333,6 +388,23 @@ __global__ void k_lb_clear(unsigned* __restrict__ w, long n) {
 hipError_t lb_clear(const LbRecs& r, hipStream_t s) {
   const long blocks = min((r.nwords + 255) / 256, 1024L);
   hipLaunchKernelGGL(k_lb_clear, dim3((unsigned)blocks), dim3(256), 0, s, r.ctr, r.nwords);
+  return hipGetLastError();
+}
+
+__global__ void k_lb_clear2(unsigned* __restrict__ a, long na, unsigned* __restrict__ b, long nb) {
+  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < na + nb;
+       k += (long)gridDim.x * blockDim.x) {
+    if (k < na)
+      a[k] = 0u;
+    else
+      b[k - na] = 0u;
+  }
+}
+
+hipError_t lb_clear2(const LbRecs& a, const LbRecs& b, hipStream_t s) {
+  const long blocks = min((a.nwords + b.nwords + 255) / 256, 1024L);
+  hipLaunchKernelGGL(k_lb_clear2, dim3((unsigned)blocks), dim3(256), 0, s, a.ctr, a.nwords, b.ctr,
+                     b.nwords);
   return hipGetLastError();
 }
 
@@ -676,6 +748,14 @@ lqt_status run_solve(const lqt_dims* dims, const KProb& kp, const Work& w, void*
   if (use_wave(dims)) {
     const WTree wt = wave_tree(dims->T, o.wave_chunk);
     LQT_HIP(wave_build(kp, dims->dtype, e, stream));
+    WQueue q;
+    if (o.queue_chunk && wave_queue(wt, kp.batch, w, &q)) {
+      hipLaunchKernelGGL(k_lb_clear, dim3((unsigned)min((w.wq_words + 255) / 256, 1024L)),
+                         dim3(256), 0, stream, w.wq_done, w.wq_words);
+      LQT_HIP(hipGetLastError());
+      LQT_HIP(wave_solve_queue(kp, dims->dtype, q, e, S, v, x, u, stream));
+      return LQT_OK;
+    }
     LQT_HIP(wave_value(kp, dims->dtype, wt, w, e, S, v, w.tmap[1], stream));
     LQT_HIP(wave_traj(kp, dims->dtype, wt, w, e, S, v, x, u, true, stream));
     return LQT_OK;
@@ -687,6 +767,13 @@ lqt_status run_solve(const lqt_dims* dims, const KProb& kp, const Work& w, void*
     LQT_HIP(op->lti_build(kp, w.lti, e, stream));
   } else {
     LQT_HIP(op->build(kp, e, stream));
+  }
+  if (o.queue_chunk) {
+    const int cv = o.queue_chunk;
+    LQT_HIP(lb_clear2(w.lbv, w.lbt, stream));
+    LQT_HIP(op->scan_queue(kp, e, S, v, x, u, lb_for(w.lbv, kp.T, cv),
+                             lb_for(w.lbt, kp.T, queue_tchunk(cv)), cv, stream));
+    return LQT_OK;
   }
   LQT_TRY(run_value(op, kp, w, e, S, v, stream));
   LQT_TRY(run_traj(op, kp, w, e, S, v, x, u, stream));

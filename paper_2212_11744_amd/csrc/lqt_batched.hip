@@ -2,9 +2,12 @@
 // of lqt.h): validation, workspace planning, the eager solve, and plans (a fixed configuration
 // chosen by a small autotuner, replayed with one branch per class on its own stream).
 //
-// Each class runs the ordinary solve sequence over its concatenated horizon in ragged mode
-// (KProb::seg): the element build inserts a separator element after every problem, the control
-// and value kernels look up the owning problem of a boundary, and the scan trees are unchanged.
+// Each class runs the solve over its concatenated horizon in ragged mode (KProb::seg): the element
+// build inserts a separator element after every problem, the control and value kernels look up
+// the owning problem of a boundary.  After the element build, both scans of a class run in one
+// launch whose waves take their tiles (per-lane path) or tree nodes (wave path) from a work queue
+// in dependency order, so a plan is four launches per class (constants, elements, clearing of the
+// queue's status words, the queue launch), whatever the number of problems.
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -134,9 +137,19 @@ lqt_status prepare(const lqt_ragged* cls, int ncls, void* ws, size_t ws_bytes,
   return LQT_OK;
 }
 
+// Value chunks of the per-lane work-queue scans worth trying for a class of `rows` blocks (more
+// blocks per lane only pay once there are enough tiles to fill the device).
+std::vector<int> lane_chunks(long rows) {
+  if (rows <= (1L << 11)) return {1, 4};
+  if (rows < (1L << 19)) return {4, 8};
+  return {8, 4};
+}
+
+// Every class runs its scans in one launch over a work queue (queue_chunk != 0).
 SolveOpts default_opts(const ClassRun& r) {
   SolveOpts o;
   o.wave_chunk = 8;
+  o.queue_chunk = is_wave(r.d) ? 1 : lane_chunks(r.c.rows)[0];
   return o;
 }
 
@@ -277,10 +290,15 @@ lqt_status tune(lqt_plan_s* p, hipStream_t s, Choice* ch) {
       for (int wc : kWaveChunks) {
         SolveOpts o;
         o.wave_chunk = wc;
+        o.queue_chunk = 1;
         cands.push_back(o);
       }
     } else {
-      cands.push_back(SolveOpts());  // the per-lane path has no options
+      for (int cv : lane_chunks(r.c.rows)) {
+        SolveOpts o;
+        o.queue_chunk = cv;
+        cands.push_back(o);
+      }
     }
     float best = 1e30f;
     SolveOpts bo = cands[0];
@@ -293,9 +311,11 @@ lqt_status tune(lqt_plan_s* p, hipStream_t s, Choice* ch) {
       }
     }
     ch->opts.push_back(bo);
-    const std::string choice = is_wave(r.d) ? "wave path, " + std::to_string(bo.wave_chunk) +
-                                                  " nodes per wave"
-                                            : std::string("lane path");
+    const std::string choice =
+        is_wave(r.d) ? "wave path, both trees in one queue launch, " +
+                           std::to_string(bo.wave_chunk) + " nodes per wave"
+                     : "lane path, both scans in one queue launch, " +
+                           std::to_string(bo.queue_chunk) + " blocks per lane (value scan)";
     snprintf(buf, sizeof(buf), "class %zu (nx=%d nu=%d count=%d rows=%lld): %s, %.3f ms; ", i,
              r.c.nx, r.c.nu, r.c.count, (long long)r.c.rows, choice.c_str(), best);
     text += buf;

@@ -123,6 +123,8 @@ struct Work {
   void* tx[kMaxLevels + 1] = {};     // trajectory tree: x at left ends of level-l nodes
   void* tpart[kMaxLevels + 1] = {};  // trajectory tree: lane partials above level l
   void* elts = nullptr;              // elements when the caller gives none (lqt_solve)
+  unsigned* wq_done = nullptr;       // wave path: status words and counter of the queue solve
+  long wq_words = 0;
   // adjoint
   void* lmap[kMaxLevels + 1] = {};   // lambda scan: maps, states, lane partials per level
   void* lst[kMaxLevels + 1] = {};
@@ -175,6 +177,10 @@ struct Ops {
   hipError_t (*build_split)(const KProb&, void* elts, hipStream_t);
   // elements (constant coefficients) plus the RK4 step start values the adjoint re-linearises at
   hipError_t (*build_ckpt)(const KProb&, void* elts, void* ckpt, hipStream_t);
+  // value and trajectory scans in one launch over a work queue (records lbv, lbt cleared; value chunk
+  // cv = 1, 4 or 8 blocks per lane, trajectory chunk queue_tchunk(cv))
+  hipError_t (*scan_queue)(const KProb&, const void* elts, void* S, void* v, void* x, void* u,
+                             const LbRecs& lbv, const LbRecs& lbt, int cv, hipStream_t);
 };
 
 // Adjoint kernels (lqt_adjoint.hip) of one (nx, nu, dtype) instantiation.
@@ -238,6 +244,25 @@ struct WTree {
   long n[kMaxLevels + 1] = {};
 };
 WTree wave_tree(long T, int wc);
+// The wave path's solve after the element build in one launch over a work queue: the stages of
+// the two trees (4 levels + 1 of them) and where their items start; done: one status word per
+// item, then the item counter (total + 1 words, zero before the launch).
+constexpr int kWqMaxLevels = 16;
+struct WQueue {
+  int levels = 0, wc = 0, nst = 0;
+  long total = 0;
+  long n[kWqMaxLevels + 1] = {};      // nodes per problem at level l (n[0] = T)
+  long start[4 * kWqMaxLevels + 1] = {};
+  int kind[4 * kWqMaxLevels + 1] = {};
+  int level[4 * kWqMaxLevels + 1] = {};
+  unsigned* done = nullptr;
+  void* vtup[kWqMaxLevels + 1] = {};
+  void* vval[kWqMaxLevels + 1] = {};
+  void* tmap[kWqMaxLevels + 1] = {};
+  void* tx[kWqMaxLevels + 1] = {};
+};
+// The queue of a tree (pointers from w; false if the tree is deeper than kWqMaxLevels).
+bool wave_queue(const WTree& t, long batch, const Work& w, WQueue* q);
 // Launchers of one wave-path instantiation (state size, dtype).
 struct WaveFns {
   hipError_t (*build)(const KProb&, void* elts, hipStream_t);
@@ -245,6 +270,9 @@ struct WaveFns {
                       void* maps1, hipStream_t);
   hipError_t (*traj)(const KProb&, const WTree&, const Work&, const void* elts, const void* S,
                      const void* v, void* x, void* u, bool maps_ready, hipStream_t);
+  // both trees in one launch (q.done cleared)
+  hipError_t (*solve_queue)(const KProb&, const WQueue& q, const void* elts, void* S, void* v,
+                            void* x, void* u, hipStream_t);
 };
 template <int S>
 const WaveFns* wave_fns_shard(int nx, int dtype);
@@ -254,14 +282,25 @@ hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w,
 hipError_t wave_traj(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
                      const void* S, const void* v, void* x, void* u, bool maps_ready,
                      hipStream_t s);
+hipError_t wave_solve_queue(const KProb& kp, int dtype, const WQueue& q, const void* elts, void* S,
+                            void* v, void* x, void* u, hipStream_t s);
 
 // Options of a full solve: the number of nodes per wave of the wave path's trees.
 struct SolveOpts {
   int wave_chunk = 8;
+  // Per-lane path: 0 runs the value and trajectory scans as two launches (chunks from
+  // scan_chunk); 1, 4 or 8 runs both in one work-queue launch with that value chunk.
+  // Wave path: nonzero runs both trees in one work-queue launch (wave_queue).
+  int queue_chunk = 0;
 };
 
 // Zeroes the counter and status words of a single-pass scan (before every launch).
 hipError_t lb_clear(const LbRecs& r, hipStream_t s);
+// The same for two record sets in one launch.
+hipError_t lb_clear2(const LbRecs& a, const LbRecs& b, hipStream_t s);
+
+// Trajectory chunk of the work-queue scans for value chunk cv.
+inline int queue_tchunk(int cv) { return cv < 4 ? cv : 4; }
 
 // Workspace layout of one call (lqt_api.hip); the layout for wave_chunk wc also serves any larger
 // chunk.  nconsts: problems whose per-problem constants are prepared.

@@ -947,20 +947,21 @@ LQT_DEV void terminal_value(const KProb& kp, int p, R (&S)[Sym<N>::size], R (&v)
   }
 }
 
-template <int N, class R>
+// Acc: the access policy (DevAcc where another wave of the same launch reads the values back).
+template <int N, class R, class Acc = PlainAcc>
 LQT_DEV void S_store_full(const R (&S)[Sym<N>::size], R* dst) {
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = 0; j < N; ++j) dst[i * N + j] = S[Sym<N>::at(i, j)];
+    for (int j = 0; j < N; ++j) Acc::st(dst + i * N + j, S[Sym<N>::at(i, j)]);
 }
 
-template <int N, class R>
+template <int N, class R, class Acc = PlainAcc>
 LQT_DEV void S_load_upper(R (&S)[Sym<N>::size], const R* src) {
 #pragma unroll
   for (int i = 0; i < N; ++i)
 #pragma unroll
-    for (int j = i; j < N; ++j) S[Sym<N>::at(i, j)] = src[i * N + j];
+    for (int j = i; j < N; ++j) S[Sym<N>::at(i, j)] = Acc::ld(src + i * N + j);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -998,14 +999,14 @@ LQT_DEV void load_right_value(const KProb& kp, const R* Sp, const R* vp, long k,
 
 
 // S_{k+1} alone (see load_right_value).
-template <int N, class R>
+template <int N, class R, class Acc = PlainAcc>
 LQT_DEV void load_right_S(const KProb& kp, const R* Sp, long k, R (&S)[Sym<N>::size]) {
   if (kp.seg && k + 1 >= kp.T) {
 #pragma unroll
     for (int q = 0; q < Sym<N>::size; ++q) S[q] = R(0);
     return;
   }
-  S_load_upper<N, R>(S, Sp + (k + 1) * N * N);
+  S_load_upper<N, R, Acc>(S, Sp + (k + 1) * N * N);
 }
 
 
@@ -1283,15 +1284,14 @@ struct TrajAlg {
 // holds two tuples and a Lemma 7 combination), a horizon of 2^20 blocks then needs two rounds of
 // resident waves instead of four, and the per-tile costs that do not grow with the tile (the
 // lane scan of the wave and the look-back) are spread over twice the blocks.
+// Value tile of place i of problem p (the kernel body).
 template <int N, class R, int CH>
-__global__ __launch_bounds__(kThreads) void k_vscan(const KProb kp, const R* __restrict__ elts,
-                                                     R* __restrict__ Sout, R* __restrict__ vout,
-                                                     const LbRecs lb) {
+LQT_DEV void vscan_tile(const KProb& kp, int p, long i, const R* __restrict__ elts,
+                        R* __restrict__ Sout, R* __restrict__ vout, const LbRecs& lb,
+                        R (&sE)[Lay<N>::NE][kThreads]) {
   using Alg = ValAlg<N, R>;
-  const int p = blockIdx.y;
   const int lane = threadIdx.x;
   const long T = kp.T;
-  const long i = lb_place(lb, p);
   const long tile = lb.G - 1 - i;
   const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
   const long j0 = tile * (64L * CH) + (long)lane * CH;
@@ -1301,7 +1301,6 @@ __global__ __launch_bounds__(kThreads) void k_vscan(const KProb kp, const R* __r
   typename Alg::State st;
   // The lane's exclusive product waits in LDS during the look-back (registers are short: the
   // look-back combines tuples of its own).
-  __shared__ R sE[Lay<N>::NE][kThreads];
   {
     Tup<N, R> P;
     serial_product(ep, j0, j1, P);
@@ -1336,20 +1335,26 @@ __global__ __launch_bounds__(kThreads) void k_vscan(const KProb kp, const R* __r
   }
 }
 
+template <int N, class R, int CH>
+__global__ __launch_bounds__(kThreads) void k_vscan(const KProb kp, const R* __restrict__ elts,
+                                                     R* __restrict__ Sout, R* __restrict__ vout,
+                                                     const LbRecs lb) {
+  __shared__ R sE[Lay<N>::NE][kThreads];
+  const int p = blockIdx.y;
+  vscan_tile<N, R, CH>(kp, p, lb_place(lb, p), elts, Sout, vout, lb, sE);
+}
+
 // Trajectory (Method 1 of Sec. IV-E with the exact block maps, control law of Sec. II-B): the
 // flow is forward in time (place i takes tile i).  The lane's block maps stay in registers
 // between the reduction and the sweep.
-template <int N, int NU, class R, int CH>
-__global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __restrict__ elts,
-                                                     const R* __restrict__ Sg,
-                                                     const R* __restrict__ vg,
-                                                     R* __restrict__ xout, R* __restrict__ uout,
-                                                     const LbRecs lb) {
+// Trajectory tile of place i of problem p (the kernel body; Acc: access policy of the S, v loads).
+template <int N, int NU, class R, int CH, class Acc>
+LQT_DEV void tscan_tile(const KProb& kp, int p, long i, const R* __restrict__ elts,
+                        const R* __restrict__ Sg, const R* __restrict__ vg, R* __restrict__ xout,
+                        R* __restrict__ uout, const LbRecs& lb) {
   using Alg = TrajAlg<N, R>;
-  const int p = blockIdx.y;
   const int lane = threadIdx.x;
   const long T = kp.T;
-  const long i = lb_place(lb, p);
   const R* ep = elts + (long)p * Lay<N>::NE * padt(T);
   const R* Sp = Sg + (long)p * (T + 1) * N * N;
   const R* vp = vg + (long)p * (T + 1) * N;
@@ -1364,7 +1369,7 @@ __global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __r
   for (int r = 0; r <= CH; ++r) {
     const bool ok = cnt > 0 && r <= cnt && !(kp.seg && j0 + r >= T);
 #pragma unroll
-    for (int q = 0; q < N; ++q) vv[r][q] = ok ? vp[(j0 + r) * N + q] : R(0);
+    for (int q = 0; q < N; ++q) vv[r][q] = ok ? Acc::ld(vp + (j0 + r) * N + q) : R(0);
   }
   Aff<N, R> mk[CH];
   Aff<N, R> P;
@@ -1375,7 +1380,7 @@ __global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __r
       const long k = j0 + r;
       R Ad[N][N], b[N], C[Sym<N>::size], S[Sym<N>::size];
       elt_map_part<N, R>(ep, k, Ad, b, C);
-      load_right_S<N, R>(kp, Sp, k, S);
+      load_right_S<N, R, Acc>(kp, Sp, k, S);
       block_map<N, R>(Ad, b, C, S, vv[r + 1], mk[r]);
       aff_then(P, mk[r]);
     }
@@ -1402,7 +1407,7 @@ __global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __r
       for (int q = 0; q < N; ++q) xs[r][q] = st.x[q];
       if (up) {
         R S[Sym<N>::size];
-        S_load_upper<N, R>(S, Sp + k * N * N);
+        S_load_upper<N, R, Acc>(S, Sp + k * N * N);
         if (per_k) gain_at<N, NU, R>(kp, p, k, Kc);
         control<N, NU, R>(Kc, S, vv[r], st.x, us[r]);
       }
@@ -1430,12 +1435,82 @@ __global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __r
     for (int q = 0; q < N; ++q) xp[T * N + q] = st.x[q];
     if (up) {
       R S[Sym<N>::size], vT[N];
-      S_load_upper<N, R>(S, Sp + T * N * N);
+      S_load_upper<N, R, Acc>(S, Sp + T * N * N);
 #pragma unroll
-      for (int q = 0; q < N; ++q) vT[q] = vp[T * N + q];
+      for (int q = 0; q < N; ++q) vT[q] = Acc::ld(vp + T * N + q);
       if (per_k) gain_at<N, NU, R>(kp, p, T, Kc);
       control<N, NU, R>(Kc, S, vT, st.x, up + T * NU);
     }
+  }
+}
+
+template <int N, int NU, class R, int CH>
+__global__ __launch_bounds__(kThreads) void k_tscan(const KProb kp, const R* __restrict__ elts,
+                                                     const R* __restrict__ Sg,
+                                                     const R* __restrict__ vg,
+                                                     R* __restrict__ xout, R* __restrict__ uout,
+                                                     const LbRecs lb) {
+  const int p = blockIdx.y;
+  tscan_tile<N, NU, R, CH, PlainAcc>(kp, p, lb_place(lb, p), elts, Sg, vg, xout, uout, lb);
+}
+
+// Both scans of a solve in one launch over a work queue.  Every wave takes the next item from one
+// counter: first the value tiles of every problem (place-major, in the flow order of the value
+// scan), then the trajectory tiles (in the flow order of the trajectory scan).  A value tile marks
+// its record kLbDone once its S, v rows are written; a trajectory tile first waits for the value
+// tiles that hold its rows (at most two: CT <= CV and the tiles are aligned), so no kernel
+// boundary separates the scans.  Every wait is for an item taken earlier from the counter, whose
+// wave is running, so every wait ends.  A value tile writes S and v with plain stores and
+// releases them at agent scope (the L2 of its XCD written back) before it sets kLbDone; a
+// trajectory tile acquires at agent scope (the non-coherent lines of its L2 dropped) after it
+// has seen the flags and then reads S and v with plain loads.  Per-value coherent accesses would
+// move every 8-byte value as a partial line: a lane's rows are a kilobyte apart.  x and u are
+// plain stores.
+// The launch has one wave per item.  A wave looping over items would keep the item-independent
+// values of both tile bodies live across the loop, and the compiler then spills about a hundred
+// of the registers the value tile needs (nx = 4, FP64).
+template <int N, int NU, class R, int CV, int CT>
+__global__ __launch_bounds__(kThreads) void k_scan_queue(const KProb kp,
+                                                            const R* __restrict__ elts,
+                                                            R* __restrict__ Sg, R* __restrict__ vg,
+                                                            R* __restrict__ xout,
+                                                            R* __restrict__ uout,
+                                                            const LbRecs lbv, const LbRecs lbt) {
+  static_assert(CT <= CV && CV % CT == 0, "trajectory tiles must nest in value tiles");
+  __shared__ R sE[Lay<N>::NE][kThreads];
+  const int lane = threadIdx.x;
+  const long B = kp.batch, T = kp.T;
+  const long nV = B * lbv.G, nAll = nV + B * lbt.G;
+  auto take = [&]() {
+    unsigned it0 = 0;
+    if (lane == 0) it0 = atomicAdd(lbv.ctr, 1u);
+    return (long)__shfl(it0, 0, 64);
+  };
+  const long it = take();
+  if (it < nV) {
+    const int p = (int)(it % B);
+    const long i = it / B;
+    vscan_tile<N, R, CV>(kp, p, i, elts, Sg, vg, lbv, sE);
+    // Plain S, v stores (a lane's rows are 1 KB apart, so per-value coherent stores would each
+    // reach memory as a partial line), made visible at device scope by one release per tile.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) lb_flag_store(lbv.tflag + (long)p * lbv.G + i, kLbDone);
+  } else if (it < nAll) {
+    const int p = (int)((it - nV) % B);
+    const long i = (it - nV) / B;
+    // rows i * 64 CT .. (i + 1) * 64 CT of S, v (row T is written with block T - 1)
+    const long r0 = i * 64L * CT, r1 = min(r0 + 64L * CT, T - 1);
+    const long ta = r0 / (64L * CV), tb = r1 / (64L * CV);
+    const unsigned* vf = lbv.tflag + (long)p * lbv.G + (lbv.G - 1);  // place of tile t: -t
+    for (;;) {
+      const unsigned f = lane <= tb - ta ? lb_flag_load(vf - (ta + lane)) : kLbDone;
+      if (__ballot(f < kLbDone) == 0ull) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    // pairs with the value tiles' release: lines of S, v this XCD may hold are dropped, so the
+    // plain loads below see the rows the value tiles wrote
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    tscan_tile<N, NU, R, CT, PlainAcc>(kp, p, i, elts, Sg, vg, xout, uout, lbt);
   }
 }
 
@@ -1921,6 +1996,24 @@ struct L {
     }
     return hipGetLastError();
   }
+  template <int CV, int CT>
+  static void queue_c(const KProb& kp, const void* elts, void* S, void* v, void* x, void* u,
+                      const LbRecs& lbv, const LbRecs& lbt, hipStream_t s) {
+    const long items = (long)kp.batch * (lbv.G + lbt.G);
+    hipLaunchKernelGGL((k_scan_queue<N, NU, R, CV, CT>), dim3((unsigned)items), dim3(kThreads), 0,
+                       s, kp, (const R*)elts, (R*)S, (R*)v, (R*)x, (R*)u, lbv, lbt);
+  }
+  static hipError_t scan_queue(const KProb& kp, const void* elts, void* S, void* v, void* x,
+                                 void* u, const LbRecs& lbv, const LbRecs& lbt, int cv,
+                                 hipStream_t s) {
+    switch (cv) {
+      case 1: queue_c<1, 1>(kp, elts, S, v, x, u, lbv, lbt, s); break;
+      case 4: queue_c<4, 4>(kp, elts, S, v, x, u, lbv, lbt, s); break;
+      case 8: queue_c<8, 4>(kp, elts, S, v, x, u, lbv, lbt, s); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   static hipError_t prep(const KProb& kp, void* consts, hipStream_t s) {
     hipLaunchKernelGGL((k_prep_lane<N, NU, R>), dim3((kp.batch + kThreads - 1) / kThreads),
                        dim3(kThreads), 0, s, kp, (R*)consts);
@@ -2005,7 +2098,7 @@ struct L {
     static const Ops o = {prep,    build,          vscan,        tscan,    vreduce0,
                           lti_prep,       lti_build,    build_fwd,
                           m2_up,   m2_top,         m2_down,      m2_bottom,
-                          dense,   build_split,    build_ckpt};
+                          dense,   build_split,    build_ckpt,   scan_queue};
     return &o;
   }
 };

@@ -11,6 +11,7 @@
 #include <cstring>
 
 #include "../../include/lqt.h"
+#include "coherent.hpp"
 #include "lqt_internal.hpp"
 
 namespace lqt {
@@ -246,38 +247,39 @@ WDEV GRef<R> rec_ref(R* rec, int p, long k, long n, int NE) {
   return {rec + ((long)p * n + k) * NE, 1};
 }
 
-template <class R>
+// Acc (coherent.hpp): the access policy of the global side.
+template <class Acc = PlainAcc, class R>
 WDEV void wt_load(WT<R> t, GRef<const R> g, int n) {
   const int ns = n * (n + 1) / 2;
   const int oB = n * n, oC = oB + n, oE = oC + ns, oJ = oE + n;
   for (int e = lane_id(); e < n * n; e += 64) {
     const int i = e / n, j = e % n;
-    t.A[e] = g.g[e * g.st];
-    t.C[e] = g.g[(oC + pk(i, j, n)) * g.st];
-    t.J[e] = g.g[(oJ + pk(i, j, n)) * g.st];
+    t.A[e] = Acc::ld(g.g + e * g.st);
+    t.C[e] = Acc::ld(g.g + (oC + pk(i, j, n)) * g.st);
+    t.J[e] = Acc::ld(g.g + (oJ + pk(i, j, n)) * g.st);
   }
   for (int i = lane_id(); i < n; i += 64) {
-    t.b[i] = g.g[(oB + i) * g.st];
-    t.e[i] = g.g[(oE + i) * g.st];
+    t.b[i] = Acc::ld(g.g + (oB + i) * g.st);
+    t.e[i] = Acc::ld(g.g + (oE + i) * g.st);
   }
   wsync();
 }
 
-template <class R>
+template <class Acc = PlainAcc, class R>
 WDEV void wt_store(WT<R> t, GRef<R> g, int n) {
   const int ns = n * (n + 1) / 2;
   const int oB = n * n, oC = oB + n, oE = oC + ns, oJ = oE + n;
   for (int e = lane_id(); e < n * n; e += 64) {
     const int i = e / n, j = e % n;
-    g.g[e * g.st] = t.A[e];
+    Acc::st(g.g + e * g.st, t.A[e]);
     if (i <= j) {
-      g.g[(oC + pk(i, j, n)) * g.st] = t.C[e];
-      g.g[(oJ + pk(i, j, n)) * g.st] = t.J[e];
+      Acc::st(g.g + (oC + pk(i, j, n)) * g.st, t.C[e]);
+      Acc::st(g.g + (oJ + pk(i, j, n)) * g.st, t.J[e]);
     }
   }
   for (int i = lane_id(); i < n; i += 64) {
-    g.g[(oB + i) * g.st] = t.b[i];
-    g.g[(oE + i) * g.st] = t.e[i];
+    Acc::st(g.g + (oB + i) * g.st, t.b[i]);
+    Acc::st(g.g + (oE + i) * g.st, t.e[i]);
   }
   wsync();
 }
@@ -1559,61 +1561,83 @@ __global__ __launch_bounds__(64) void kw_build_mfma16(const KProb kp, double* __
 }
 
 // ------------------------------------------------------------------------------------------
-// Value tree.
+// Value tree.  The kernels below are thin launches of device bodies that take their node and
+// problem, LDS and access policy A (coherent.hpp) from the caller: A applies to the tree records,
+// S, v and x0 passed between the bodies (elements, written by an earlier launch, are plain loads),
+// so the same bodies run as one launch per tree level (A = PlainAcc) and as the items of the
+// single-launch solve below (A = DevAcc).
 // ------------------------------------------------------------------------------------------
+template <int N>
+struct WSh {  // LDS of the bodies (values of the solve's type)
+  static constexpr int kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
+  static constexpr int vreduce = 2 * kTupW + kScr;
+  static constexpr int vfold = kTupW + kScr + N * N + N;
+  static constexpr int vbottom = vfold + 3 * (N * N + N);
+  static constexpr int treduce = 3 * (N * N + N);
+  static constexpr int tsweep = N * N + 3 * N;
+  static constexpr int tbottom = kTupW + kScr + N * N + N + N * N + 4 * N + N * N;
+  static constexpr int max2(int a, int b) { return a > b ? a : b; }
+  static constexpr int all =
+      max2(max2(max2(vreduce, vfold), max2(vbottom, treduce)), max2(tsweep, tbottom));
+};
+
+// Value records (S full symmetric, v): n^2 + n values.
+template <class A = PlainAcc, class R>
+WDEV void val_st(const R* S, const R* v, R* g, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) A::st(g + e, S[e]);
+  for (int i = lane_id(); i < n; i += 64) A::st(g + n * n + i, v[i]);
+  wsync();
+}
+template <class A = PlainAcc, class R>
+WDEV void val_ld(R* S, R* v, const R* g, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) S[e] = A::ld(g + e);
+  for (int i = lane_id(); i < n; i += 64) v[i] = A::ld(g + n * n + i);
+  wsync();
+}
+
+// Node i of level l + 1: the product of the wc nodes i wc .. of level l (elements when
+// src_elts), right to left.
+template <int N, class A, class R>
+WDEV void wb_vreduce(R* sh, int* piv, int p, long i, int wc, int src_elts, const R* src,
+                     long n_src, R* dst, long n_dst) {
+  constexpr int n = N, kTupW = WSh<N>::kTupW;
+  const int NE = ne_w(n);
+  WT<R> acc = wt_at(sh, n), x = wt_at(sh + kTupW, n);
+  WS<R> scr = ws_at(sh + 2 * kTupW, piv, n);
+  const long j0 = i * wc, j1 = min(j0 + wc, n_src);
+  auto load = [&](WT<R> t, long j) {
+    if (src_elts)
+      wt_load<PlainAcc>(t, elt_ref(src, p, j, n_src, NE), n);
+    else
+      wt_load<A>(t, rec_ref(src, p, j, n_src, NE), n);
+  };
+  load(acc, j1 - 1);
+  for (long j = j1 - 2; j >= j0; --j) {
+    load(x, j);
+    w_combine<N>(x, acc, acc, scr, n);
+  }
+  wt_store<A>(acc, rec_ref(dst, p, i, n_dst, NE), n);
+}
+
 template <int N, class R>
 __global__ __launch_bounds__(64) void kw_vreduce(int, int wc, int src_elts,
                                                  const R* __restrict__ src, long n_src,
                                                  R* __restrict__ dst, long n_dst) {
-  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
-  constexpr int n = N;
-  __shared__ R sh[2 * kTupW + kScr];
+  __shared__ R sh[WSh<N>::vreduce];
   __shared__ int piv;
-  const int p = blockIdx.y;
-  const long i = blockIdx.x;
-  if (i >= n_dst) return;
-  const int NE = ne_w(n);
-  auto ref = [&](long j) {
-    return src_elts ? elt_ref(src, p, j, n_src, NE) : rec_ref(src, p, j, n_src, NE);
-  };
-  WT<R> acc = wt_at(sh, n), x = wt_at(sh + kTupW, n);
-  WS<R> scr = ws_at(sh + 2 * kTupW, &piv, n);
-  const long j0 = i * wc, j1 = min(j0 + wc, n_src);
-  wt_load(acc, ref(j1 - 1), n);
-  for (long j = j1 - 2; j >= j0; --j) {
-    wt_load(x, ref(j), n);
-    w_combine<N>(x, acc, acc, scr, n);
-  }
-  wt_store(acc, rec_ref(dst, p, i, n_dst, NE), n);
+  if ((long)blockIdx.x >= n_dst) return;
+  wb_vreduce<N, PlainAcc>(sh, &piv, blockIdx.y, blockIdx.x, wc, src_elts, src, n_src, dst, n_dst);
 }
 
-// Value records (S full symmetric, v): n^2 + n values.
-template <class R>
-WDEV void val_st(const R* S, const R* v, R* g, int n) {
-  for (int e = lane_id(); e < n * n; e += 64) g[e] = S[e];
-  for (int i = lane_id(); i < n; i += 64) g[n * n + i] = v[i];
-  wsync();
-}
-template <class R>
-WDEV void val_ld(R* S, R* v, const R* g, int n) {
-  for (int e = lane_id(); e < n * n; e += 64) S[e] = g[e];
-  for (int i = lane_id(); i < n; i += 64) v[i] = g[n * n + i];
-  wsync();
-}
-
-template <int N, class R>
-__global__ __launch_bounds__(64) void kw_vtop(const KProb kp, const R* __restrict__ tup, long n_top,
-                                              R* __restrict__ val) {
-  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
-  __shared__ R sh[kTupW + kScr + NM * NM + NM];
-  __shared__ int piv;
-  const int p = blockIdx.y;
-  constexpr int n = N;
+// The values at the right ends of the n_top top nodes: the terminal value carried leftwards.
+template <int N, class A, class R>
+WDEV void wb_vtop(R* sh, int* piv, const KProb& kp, int p, const R* tup, long n_top, R* val) {
+  constexpr int n = N, kTupW = WSh<N>::kTupW, kScr = WSh<N>::kScr;
   const int NE = ne_w(n);
   WT<R> a = wt_at(sh, n);
-  WS<R> scr = ws_at(sh + kTupW, &piv, n);
+  WS<R> scr = ws_at(sh + kTupW, piv, n);
   R* S = sh + kTupW + kScr;
-  R* v = S + NM * NM;
+  R* v = S + n * n;
   const R* Qf = (const R*)kp.Qf + (long)p * n * n;
   const R* rf = (const R*)kp.rf + (long)p * n;
   for (int e = lane_id(); e < n * n; e += 64) {
@@ -1628,9 +1652,37 @@ __global__ __launch_bounds__(64) void kw_vtop(const KProb kp, const R* __restric
   wsync();
   const int VR = n * n + n;
   for (long j = n_top - 1; j >= 0; --j) {
-    val_st(S, v, val + ((long)p * n_top + j) * VR, n);
+    val_st<A>(S, v, val + ((long)p * n_top + j) * VR, n);
     if (j == 0) break;
-    wt_load(a, rec_ref(tup, p, j, n_top, NE), n);
+    wt_load<A>(a, rec_ref(tup, p, j, n_top, NE), n);
+    w_fold<N>(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
+  }
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_vtop(const KProb kp, const R* __restrict__ tup, long n_top,
+                                              R* __restrict__ val) {
+  __shared__ R sh[WSh<N>::vfold];
+  __shared__ int piv;
+  wb_vtop<N, PlainAcc>(sh, &piv, kp, blockIdx.y, tup, n_top, val);
+}
+
+// Values at the right ends of the children of node i of level l + 1, from the node's own.
+template <int N, class A, class R>
+WDEV void wb_vdown(R* sh, int* piv, int p, long i, int wc, const R* tup, long n_child,
+                   const R* val_in, long n_par, R* val_out) {
+  constexpr int n = N, kTupW = WSh<N>::kTupW, kScr = WSh<N>::kScr;
+  const int NE = ne_w(n), VR = n * n + n;
+  WT<R> a = wt_at(sh, n);
+  WS<R> scr = ws_at(sh + kTupW, piv, n);
+  R* S = sh + kTupW + kScr;
+  R* v = S + n * n;
+  val_ld<A>(S, v, val_in + ((long)p * n_par + i) * VR, n);
+  const long j0 = i * wc, j1 = min(j0 + wc, n_child);
+  for (long j = j1 - 1; j >= j0; --j) {
+    val_st<A>(S, v, val_out + ((long)p * n_child + j) * VR, n);
+    if (j == j0) break;
+    wt_load<A>(a, rec_ref(tup, p, j, n_child, NE), n);
     w_fold<N>(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
   }
 }
@@ -1639,99 +1691,88 @@ template <int N, class R>
 __global__ __launch_bounds__(64) void kw_vdown(int, int wc, const R* __restrict__ tup, long n_child,
                                                const R* __restrict__ val_in, long n_par,
                                                R* __restrict__ val_out) {
-  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
-  constexpr int n = N;
-  __shared__ R sh[kTupW + kScr + NM * NM + NM];
+  __shared__ R sh[WSh<N>::vfold];
   __shared__ int piv;
-  const int p = blockIdx.y;
-  const long i = blockIdx.x;
-  if (i >= n_par) return;
-  const int NE = ne_w(n), VR = n * n + n;
-  WT<R> a = wt_at(sh, n);
-  WS<R> scr = ws_at(sh + kTupW, &piv, n);
-  R* S = sh + kTupW + kScr;
-  R* v = S + NM * NM;
-  val_ld(S, v, val_in + ((long)p * n_par + i) * VR, n);
-  const long j0 = i * wc, j1 = min(j0 + wc, n_child);
-  for (long j = j1 - 1; j >= j0; --j) {
-    val_st(S, v, val_out + ((long)p * n_child + j) * VR, n);
-    if (j == j0) break;
-    wt_load(a, rec_ref(tup, p, j, n_child, NE), n);
-    w_fold<N>(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
-  }
+  if ((long)blockIdx.x >= n_par) return;
+  wb_vdown<N, PlainAcc>(sh, &piv, blockIdx.y, blockIdx.x, wc, tup, n_child, val_in, n_par,
+                        val_out);
 }
 
 // Values of every block from the value at the right end of each chunk; level 1 of the
 // trajectory tree (composition of the chunk's block maps) when maps1 != nullptr.
+template <int N, class A, class R>
+WDEV void wb_vbottom(R* sh, int* piv, const KProb& kp, int p, long i, int wc, const R* elts,
+                     const R* val1, long n1, R* Sout, R* vout, R* maps1) {
+  constexpr int n = N, kTupW = WSh<N>::kTupW, kScr = WSh<N>::kScr;
+  const long T = kp.T;
+  const int NE = ne_w(n), VR = n * n + n, MR = n * n + n;
+  WT<R> a = wt_at(sh, n);
+  WS<R> scr = ws_at(sh + kTupW, piv, n);
+  R* S = sh + kTupW + kScr;
+  R* v = S + n * n;
+  R* aP = v + n;
+  R* aq = aP + n * n;
+  R* mP = aq + n;
+  R* mq = mP + n * n;
+  R* tmp = mq + n;
+  val_ld<A>(S, v, val1 + ((long)p * n1 + i) * VR, n);
+  R* Sp = Sout + (long)p * (T + 1) * n * n;
+  R* vp = vout + (long)p * (T + 1) * n;
+  const long j0 = i * wc, j1 = min(j0 + wc, T);
+  if (j1 == T && !kp.seg) {
+    for (int e = lane_id(); e < n * n; e += 64) A::st(Sp + T * n * n + e, S[e]);
+    for (int q = lane_id(); q < n; q += 64) A::st(vp + T * n + q, v[q]);
+  }
+  w_aff_identity(aP, aq, n);
+  for (long k = j1 - 1; k >= j0; --k) {
+    wt_load<PlainAcc>(a, elt_ref(elts, p, k, T, NE), n);
+    w_fold<N>(a, S, v, scr, n, mP, mq);
+    for (int e = lane_id(); e < n * n; e += 64) A::st(Sp + k * n * n + e, S[e]);
+    for (int q = lane_id(); q < n; q += 64) A::st(vp + k * n + q, v[q]);
+    if (maps1) w_aff_after(aP, aq, mP, mq, tmp, n);
+  }
+  if (maps1) {
+    R* g = maps1 + ((long)p * n1 + i) * MR;
+    for (int e = lane_id(); e < n * n; e += 64) A::st(g + e, aP[e]);
+    for (int q = lane_id(); q < n; q += 64) A::st(g + n * n + q, aq[q]);
+  }
+}
+
 template <int N, class R>
 __global__ __launch_bounds__(64) void kw_vbottom(const KProb kp, int wc, const R* __restrict__ elts,
                                                  const R* __restrict__ val1, long n1,
                                                  R* __restrict__ Sout, R* __restrict__ vout,
                                                  R* __restrict__ maps1) {
-  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
-  __shared__ R sh[kTupW + kScr + NM * NM + NM + 3 * (NM * NM + NM)];
+  __shared__ R sh[WSh<N>::vbottom];
   __shared__ int piv;
-  const int p = blockIdx.y;
-  const long i = blockIdx.x;
-  if (i >= n1) return;
-  constexpr int n = N;
-  const long T = kp.T;
-  const int NE = ne_w(n), VR = n * n + n, MR = n * n + n;
-  WT<R> a = wt_at(sh, n);
-  WS<R> scr = ws_at(sh + kTupW, &piv, n);
-  R* S = sh + kTupW + kScr;
-  R* v = S + NM * NM;
-  R* aP = v + NM;
-  R* aq = aP + NM * NM;
-  R* mP = aq + NM;
-  R* mq = mP + NM * NM;
-  R* tmp = mq + NM;
-  val_ld(S, v, val1 + ((long)p * n1 + i) * VR, n);
-  R* Sp = Sout + (long)p * (T + 1) * n * n;
-  R* vp = vout + (long)p * (T + 1) * n;
-  const long j0 = i * wc, j1 = min(j0 + wc, T);
-  if (j1 == T && !kp.seg) {
-    for (int e = lane_id(); e < n * n; e += 64) Sp[T * n * n + e] = S[e];
-    for (int q = lane_id(); q < n; q += 64) vp[T * n + q] = v[q];
-  }
-  w_aff_identity(aP, aq, n);
-  for (long k = j1 - 1; k >= j0; --k) {
-    wt_load(a, elt_ref(elts, p, k, T, NE), n);
-    w_fold<N>(a, S, v, scr, n, mP, mq);
-    for (int e = lane_id(); e < n * n; e += 64) Sp[k * n * n + e] = S[e];
-    for (int q = lane_id(); q < n; q += 64) vp[k * n + q] = v[q];
-    if (maps1) w_aff_after(aP, aq, mP, mq, tmp, n);
-  }
-  if (maps1) {
-    R* g = maps1 + ((long)p * n1 + i) * MR;
-    for (int e = lane_id(); e < n * n; e += 64) g[e] = aP[e];
-    for (int q = lane_id(); q < n; q += 64) g[n * n + q] = aq[q];
-  }
+  if ((long)blockIdx.x >= n1) return;
+  wb_vbottom<N, PlainAcc>(sh, &piv, kp, blockIdx.y, blockIdx.x, wc, elts, val1, n1, Sout, vout,
+                          maps1);
 }
 
 // ------------------------------------------------------------------------------------------
 // Trajectory tree.
 // ------------------------------------------------------------------------------------------
-template <class R>
+template <class A = PlainAcc, class R>
 WDEV void map_ld(R* P, R* q, const R* g, int n) {
-  for (int e = lane_id(); e < n * n; e += 64) P[e] = g[e];
-  for (int i = lane_id(); i < n; i += 64) q[i] = g[n * n + i];
+  for (int e = lane_id(); e < n * n; e += 64) P[e] = A::ld(g + e);
+  for (int i = lane_id(); i < n; i += 64) q[i] = A::ld(g + n * n + i);
   wsync();
 }
-template <class R>
+template <class A = PlainAcc, class R>
 WDEV void map_st(const R* P, const R* q, R* g, int n) {
-  for (int e = lane_id(); e < n * n; e += 64) g[e] = P[e];
-  for (int i = lane_id(); i < n; i += 64) g[n * n + i] = q[i];
+  for (int e = lane_id(); e < n * n; e += 64) A::st(g + e, P[e]);
+  for (int i = lane_id(); i < n; i += 64) A::st(g + n * n + i, q[i]);
   wsync();
 }
 
 // (S_{k+1}, v_{k+1}) into LDS; zeros for the last block in ragged mode (a separator, whose map
 // does not depend on them; row T does not exist there).
-template <class R>
+template <class A = PlainAcc, class R>
 WDEV void w_right_value(const KProb& kp, const R* Sp, const R* vp, long k, R* S, R* v, int n) {
   const bool none = kp.seg && k + 1 >= kp.T;
-  for (int e = lane_id(); e < n * n; e += 64) S[e] = none ? R(0) : Sp[(k + 1) * n * n + e];
-  for (int q = lane_id(); q < n; q += 64) v[q] = none ? R(0) : vp[(k + 1) * n + q];
+  for (int e = lane_id(); e < n * n; e += 64) S[e] = none ? R(0) : A::ld(Sp + (k + 1) * n * n + e);
+  for (int q = lane_id(); q < n; q += 64) v[q] = none ? R(0) : A::ld(vp + (k + 1) * n + q);
   wsync();
 }
 
@@ -1740,8 +1781,8 @@ __global__ __launch_bounds__(64) void kw_tbottom_reduce(const KProb kp, int wc, 
                                                         const R* __restrict__ Sg,
                                                         const R* __restrict__ vg,
                                                         R* __restrict__ maps1, long n1) {
-  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
-  __shared__ R sh[kTupW + kScr + NM * NM + NM + 3 * (NM * NM + NM)];
+  constexpr int kTupW = WSh<N>::kTupW, kScr = WSh<N>::kScr;
+  __shared__ R sh[WSh<N>::vbottom];
   __shared__ int piv;
   const int p = blockIdx.y;
   const long i = blockIdx.x;
@@ -1752,12 +1793,12 @@ __global__ __launch_bounds__(64) void kw_tbottom_reduce(const KProb kp, int wc, 
   WT<R> a = wt_at(sh, n);
   WS<R> scr = ws_at(sh + kTupW, &piv, n);
   R* S = sh + kTupW + kScr;
-  R* v = S + NM * NM;
-  R* aP = v + NM;
-  R* aq = aP + NM * NM;
-  R* mP = aq + NM;
-  R* mq = mP + NM * NM;
-  R* tmp = mq + NM;
+  R* v = S + n * n;
+  R* aP = v + n;
+  R* aq = aP + n * n;
+  R* mP = aq + n;
+  R* mq = mP + n * n;
+  R* tmp = mq + n;
   const R* Sp = Sg + (long)p * (T + 1) * n * n;
   const R* vp = vg + (long)p * (T + 1) * n;
   const long j0 = i * wc, j1 = min(j0 + wc, T);
@@ -1771,109 +1812,114 @@ __global__ __launch_bounds__(64) void kw_tbottom_reduce(const KProb kp, int wc, 
   map_st(aP, aq, maps1 + ((long)p * n1 + i) * MR, n);
 }
 
+// Map of node i of level l + 1: the composition of the wc maps i wc .. of level l (time order).
+template <int N, class A, class R>
+WDEV void wb_treduce(R* sh, int p, long i, int wc, const R* src, long n_src, R* dst, long n_dst) {
+  constexpr int n = N;
+  const int MR = n * n + n;
+  R* aP = sh;
+  R* aq = aP + n * n;
+  R* mP = aq + n;
+  R* mq = mP + n * n;
+  R* tmp = mq + n;
+  const long j0 = i * wc, j1 = min(j0 + wc, n_src);
+  map_ld<A>(aP, aq, src + ((long)p * n_src + j0) * MR, n);
+  for (long j = j0 + 1; j < j1; ++j) {
+    map_ld<A>(mP, mq, src + ((long)p * n_src + j) * MR, n);
+    w_aff_then(aP, aq, mP, mq, tmp, n);
+  }
+  map_st<A>(aP, aq, dst + ((long)p * n_dst + i) * MR, n);
+}
+
 template <int N, class R>
 __global__ __launch_bounds__(64) void kw_treduce(int, int wc, const R* __restrict__ src, long n_src,
                                                  R* __restrict__ dst, long n_dst) {
-  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
+  __shared__ R sh[WSh<N>::treduce];
+  if ((long)blockIdx.x >= n_dst) return;
+  wb_treduce<N, PlainAcc>(sh, blockIdx.y, blockIdx.x, wc, src, n_src, dst, n_dst);
+}
+
+// x at the left ends of the n_top top nodes: x0 carried rightwards.
+template <int N, class A, class R>
+WDEV void wb_ttop(R* sh, const KProb& kp, int p, const R* maps, long n_top, R* xs) {
   constexpr int n = N;
-  __shared__ R sh[3 * (NM * NM + NM)];
-  const int p = blockIdx.y;
-  const long i = blockIdx.x;
-  if (i >= n_dst) return;
   const int MR = n * n + n;
-  R* aP = sh;
-  R* aq = aP + NM * NM;
-  R* mP = aq + NM;
-  R* mq = mP + NM * NM;
-  R* tmp = mq + NM;
-  const long j0 = i * wc, j1 = min(j0 + wc, n_src);
-  map_ld(aP, aq, src + ((long)p * n_src + j0) * MR, n);
-  for (long j = j0 + 1; j < j1; ++j) {
-    map_ld(mP, mq, src + ((long)p * n_src + j) * MR, n);
-    w_aff_then(aP, aq, mP, mq, tmp, n);
+  R* mP = sh;
+  R* mq = mP + n * n;
+  R* x = mq + n;
+  R* tmp = x + n;
+  for (int q = lane_id(); q < n; q += 64) x[q] = ((const R*)kp.x0)[(long)p * n + q];
+  wsync();
+  for (long j = 0; j < n_top; ++j) {
+    for (int q = lane_id(); q < n; q += 64) A::st(xs + ((long)p * n_top + j) * n + q, x[q]);
+    if (j == n_top - 1) break;
+    map_ld<A>(mP, mq, maps + ((long)p * n_top + j) * MR, n);
+    w_aff_apply(mP, mq, x, tmp, n);
   }
-  map_st(aP, aq, dst + ((long)p * n_dst + i) * MR, n);
+  wsync();
 }
 
 template <int N, class R>
 __global__ __launch_bounds__(64) void kw_ttop(const KProb kp, const R* __restrict__ maps, long n_top,
                                               R* __restrict__ xs) {
-  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
-  __shared__ R sh[NM * NM + 3 * NM];
-  const int p = blockIdx.y;
+  __shared__ R sh[WSh<N>::tsweep];
+  wb_ttop<N, PlainAcc>(sh, kp, blockIdx.y, maps, n_top, xs);
+}
+
+// x at the left ends of the children of node i of level l + 1, from the node's own.
+template <int N, class A, class R>
+WDEV void wb_tdown(R* sh, int p, long i, int wc, const R* maps, long n_child, const R* x_in,
+                   long n_par, R* x_out) {
   constexpr int n = N;
   const int MR = n * n + n;
   R* mP = sh;
-  R* mq = mP + NM * NM;
-  R* x = mq + NM;
-  R* tmp = x + NM;
-  for (int q = lane_id(); q < n; q += 64) x[q] = ((const R*)kp.x0)[(long)p * n + q];
+  R* mq = mP + n * n;
+  R* x = mq + n;
+  R* tmp = x + n;
+  for (int q = lane_id(); q < n; q += 64) x[q] = A::ld(x_in + ((long)p * n_par + i) * n + q);
   wsync();
-  for (long j = 0; j < n_top; ++j) {
-    for (int q = lane_id(); q < n; q += 64) xs[((long)p * n_top + j) * n + q] = x[q];
-    if (j == n_top - 1) break;
-    map_ld(mP, mq, maps + ((long)p * n_top + j) * MR, n);
+  const long j0 = i * wc, j1 = min(j0 + wc, n_child);
+  for (long j = j0; j < j1; ++j) {
+    for (int q = lane_id(); q < n; q += 64) A::st(x_out + ((long)p * n_child + j) * n + q, x[q]);
+    if (j == j1 - 1) break;
+    map_ld<A>(mP, mq, maps + ((long)p * n_child + j) * MR, n);
     w_aff_apply(mP, mq, x, tmp, n);
   }
+  wsync();
 }
 
 template <int N, class R>
 __global__ __launch_bounds__(64) void kw_tdown(int, int wc, const R* __restrict__ maps, long n_child,
                                                const R* __restrict__ x_in, long n_par,
                                                R* __restrict__ x_out) {
-  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
-  constexpr int n = N;
-  __shared__ R sh[NM * NM + 3 * NM];
-  const int p = blockIdx.y;
-  const long i = blockIdx.x;
-  if (i >= n_par) return;
-  const int MR = n * n + n;
-  R* mP = sh;
-  R* mq = mP + NM * NM;
-  R* x = mq + NM;
-  R* tmp = x + NM;
-  for (int q = lane_id(); q < n; q += 64) x[q] = x_in[((long)p * n_par + i) * n + q];
-  wsync();
-  const long j0 = i * wc, j1 = min(j0 + wc, n_child);
-  for (long j = j0; j < j1; ++j) {
-    for (int q = lane_id(); q < n; q += 64) x_out[((long)p * n_child + j) * n + q] = x[q];
-    if (j == j1 - 1) break;
-    map_ld(mP, mq, maps + ((long)p * n_child + j) * MR, n);
-    w_aff_apply(mP, mq, x, tmp, n);
-  }
+  __shared__ R sh[WSh<N>::tsweep];
+  if ((long)blockIdx.x >= n_par) return;
+  wb_tdown<N, PlainAcc>(sh, blockIdx.y, blockIdx.x, wc, maps, n_child, x_in, n_par, x_out);
 }
 
 // x_k and u_k = -R^{-1} L(t_k)^T (S_k x_k - v_k) of every block of a chunk.
-template <int N, class R>
-__global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R* __restrict__ elts,
-                                                 const R* __restrict__ Sg, const R* __restrict__ vg,
-                                                 const R* __restrict__ x1, long n1,
-                                                 R* __restrict__ xout, R* __restrict__ uout) {
-  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
-  __shared__ R sh[kTupW + kScr + NM * NM + NM + NM * NM + 4 * NM + NM * NM];
-  __shared__ int piv;
-  const int p = blockIdx.y;
-  const long i = blockIdx.x;
-  if (i >= n1) return;
-  constexpr int n = N;
+template <int N, class A, class R>
+WDEV void wb_tbottom(R* sh, int* piv, const KProb& kp, int p, long i, int wc, const R* elts,
+                     const R* Sg, const R* vg, const R* x1, long n1, R* xout, R* uout) {
+  constexpr int n = N, kTupW = WSh<N>::kTupW, kScr = WSh<N>::kScr;
   const int nu = kp.nu;
   const long T = kp.T;
   const int NE = ne_w(n);
   WT<R> a = wt_at(sh, n);
-  WS<R> scr = ws_at(sh + kTupW, &piv, n);
+  WS<R> scr = ws_at(sh + kTupW, piv, n);
   R* S = sh + kTupW + kScr;
-  R* v = S + NM * NM;
-  R* mP = v + NM;
-  R* mq = mP + NM * NM;
-  R* x = mq + NM;
-  R* tmp = x + NM;
-  R* g = tmp + NM;
-  R* Kc = g + NM;  // nu x n
+  R* v = S + n * n;
+  R* mP = v + n;
+  R* mq = mP + n * n;
+  R* x = mq + n;
+  R* tmp = x + n;
+  R* g = tmp + n;
+  R* Kc = g + n;  // nu x n
   const R* Sp = Sg + (long)p * (T + 1) * n * n;
   const R* vp = vg + (long)p * (T + 1) * n;
   R* xp = xout + (long)p * (T + 1) * n;
   R* up = uout ? uout + (long)p * (T + 1) * nu : nullptr;
-  for (int q = lane_id(); q < n; q += 64) x[q] = x1[((long)p * n1 + i) * n + q];
+  for (int q = lane_id(); q < n; q += 64) x[q] = A::ld(x1 + ((long)p * n1 + i) * n + q);
   wsync();
   const long j0 = i * wc, j1 = min(j0 + wc, T);
   auto control = [&](long k) {
@@ -1895,8 +1941,8 @@ __global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R
       for (int e = lane_id(); e < nu * n; e += 64) Kc[e] = cs[consts_off_Kc(n, nu) + e];
     }
     for (int r = lane_id(); r < n; r += 64) {
-      R s = -vp[k * n + r];
-      for (int j = 0; j < n; ++j) s = fma(Sp[k * n * n + r * n + j], x[j], s);
+      R s = -A::ld(vp + k * n + r);
+      for (int j = 0; j < n; ++j) s = fma(A::ld(Sp + k * n * n + r * n + j), x[j], s);
       g[r] = s;
     }
     wsync();
@@ -1910,8 +1956,8 @@ __global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R
   for (long k = j0; k < j1; ++k) {
     for (int q = lane_id(); q < n; q += 64) xp[k * n + q] = x[q];
     control(k);
-    wt_load(a, elt_ref(elts, p, k, T, NE), n);
-    w_right_value(kp, Sp, vp, k, S, v, n);
+    wt_load<PlainAcc>(a, elt_ref(elts, p, k, T, NE), n);
+    w_right_value<A>(kp, Sp, vp, k, S, v, n);
     w_block_map<N>(a, S, v, scr, n, mP, mq);
     w_aff_apply(mP, mq, x, tmp, n);
   }
@@ -1919,6 +1965,122 @@ __global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R
     for (int q = lane_id(); q < n; q += 64) xp[T * n + q] = x[q];
     control(T);
   }
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R* __restrict__ elts,
+                                                 const R* __restrict__ Sg, const R* __restrict__ vg,
+                                                 const R* __restrict__ x1, long n1,
+                                                 R* __restrict__ xout, R* __restrict__ uout) {
+  __shared__ R sh[WSh<N>::tbottom];
+  __shared__ int piv;
+  if ((long)blockIdx.x >= n1) return;
+  wb_tbottom<N, PlainAcc>(sh, &piv, kp, blockIdx.y, blockIdx.x, wc, elts, Sg, vg, x1, n1, xout,
+                          uout);
+}
+
+// ------------------------------------------------------------------------------------------
+// The whole solve after the element build (both trees, every level) in one launch over a work
+// queue.  The items are the nodes of every stage, in the order of the per-level launches above:
+//   value reduce (levels 1 .. L), value top, value down (levels L - 1 .. 1), value bottom,
+//   trajectory reduce (levels 2 .. L), trajectory top, trajectory down (L - 1 .. 1), bottom,
+// problem-minor within a stage.  Every wave takes the next item from a counter, waits until the
+// items it reads from are done (their status words, set after their stores are complete), runs
+// the body and marks its own item done.  An item only reads from items of earlier stages, which
+// were taken from the counter earlier and whose waves are therefore running, so every wait ends;
+// an item reads only what the items it waits for wrote or what those items waited for in turn.
+// ------------------------------------------------------------------------------------------
+enum WqKind : int { kWqVRed = 0, kWqVTop, kWqVDown, kWqVBot, kWqTRed, kWqTTop, kWqTDown, kWqTBot };
+
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_solve_queue(const KProb kp, const WQueue q,
+                                                     const R* __restrict__ elts, R* __restrict__ S,
+                                                     R* __restrict__ v, R* __restrict__ x,
+                                                     R* __restrict__ u) {
+  __shared__ R sh[WSh<N>::all];
+  __shared__ int piv;
+  const int lane = lane_id();
+  unsigned it0 = 0;
+  if (lane == 0) it0 = atomicAdd(q.done + q.total, 1u);  // the counter follows the status words
+  const long it = (long)__shfl(it0, 0, 64);
+  if (it >= q.total) return;
+  int s = 0;
+  while (s + 1 < q.nst && q.start[s + 1] <= it) ++s;
+  const long B = kp.batch, L = q.levels, wc = q.wc;
+  const int p = (int)((it - q.start[s]) % B);
+  const long i = (it - q.start[s]) / B;
+  // stage index of each kind (see the order above)
+  auto st_vred = [&](long l) { return (int)(l - 1); };
+  auto st_vdown = [&](long l) { return (int)(2 * L - l); };  // l = L - 1 .. 1
+  const int st_vtop = (int)L, st_vbot = (int)(2 * L);
+  auto st_tred = [&](long l) { return (int)(2 * L + l - 1); };  // l = 2 .. L
+  auto st_tdown = [&](long l) { return (int)(4 * L - l); };     // l = L - 1 .. 1
+  const int st_ttop = (int)(3 * L);
+  // waits until nodes a .. b - 1 of stage t (problem p) are done
+  auto wait = [&](int t, long a, long b) {
+    const unsigned* f = q.done + q.start[t] + p;
+    for (;;) {
+      const unsigned d = a + lane < b ? lq_flag_load(f + (a + lane) * B) : 1u;
+      if (__ballot(d == 0u) == 0ull) break;
+      __builtin_amdgcn_s_sleep(1);
+    }
+    lq_acquire();
+  };
+  const int kind = q.kind[s];
+  const long l = q.level[s];
+  const R* e = elts;
+  switch (kind) {
+    case kWqVRed:
+      if (l > 1) wait(st_vred(l - 1), i * wc, min(i * wc + wc, q.n[l - 1]));
+      wb_vreduce<N, DevAcc>(sh, &piv, p, i, (int)wc, l == 1, l == 1 ? e : (const R*)q.vtup[l - 1],
+                            q.n[l - 1], (R*)q.vtup[l], q.n[l]);
+      break;
+    case kWqVTop:
+      wait(st_vred(L), 0, q.n[L]);
+      wb_vtop<N, DevAcc>(sh, &piv, kp, p, (const R*)q.vtup[L], q.n[L], (R*)q.vval[L]);
+      break;
+    case kWqVDown:  // node i of level l + 1 -> its children at level l
+      if (l + 1 == L)
+        wait(st_vtop, 0, 1);
+      else
+        wait(st_vdown(l + 1), i / wc, i / wc + 1);
+      wb_vdown<N, DevAcc>(sh, &piv, p, i, (int)wc, (const R*)q.vtup[l], q.n[l],
+                          (const R*)q.vval[l + 1], q.n[l + 1], (R*)q.vval[l]);
+      break;
+    case kWqVBot:
+      if (L == 1)
+        wait(st_vtop, 0, 1);
+      else
+        wait(st_vdown(1), i / wc, i / wc + 1);
+      wb_vbottom<N, DevAcc>(sh, &piv, kp, p, i, (int)wc, e, (const R*)q.vval[1], q.n[1], S, v,
+                            (R*)q.tmap[1]);
+      break;
+    case kWqTRed:
+      wait(l == 2 ? st_vbot : st_tred(l - 1), i * wc, min(i * wc + wc, q.n[l - 1]));
+      wb_treduce<N, DevAcc>(sh, p, i, (int)wc, (const R*)q.tmap[l - 1], q.n[l - 1], (R*)q.tmap[l],
+                            q.n[l]);
+      break;
+    case kWqTTop:
+      wait(L == 1 ? st_vbot : st_tred(L), 0, q.n[L]);
+      wb_ttop<N, DevAcc>(sh, kp, p, (const R*)q.tmap[L], q.n[L], (R*)q.tx[L]);
+      break;
+    case kWqTDown:
+      if (l + 1 == L)
+        wait(st_ttop, 0, 1);
+      else
+        wait(st_tdown(l + 1), i / wc, i / wc + 1);
+      wb_tdown<N, DevAcc>(sh, p, i, (int)wc, (const R*)q.tmap[l], q.n[l], (const R*)q.tx[l + 1],
+                          q.n[l + 1], (R*)q.tx[l]);
+      break;
+    case kWqTBot:
+      if (L == 1)
+        wait(st_ttop, 0, 1);
+      else
+        wait(st_tdown(1), i / wc, i / wc + 1);
+      wb_tbottom<N, DevAcc>(sh, &piv, kp, p, i, (int)wc, e, S, v, (const R*)q.tx[1], q.n[1], x, u);
+      break;
+  }
+  if (lane == 0) lq_flag_store(q.done + it, 1u);
 }
 
 }  // namespace
@@ -1991,6 +2153,14 @@ hipError_t wave_traj_t(const KProb& kp, const WTree& t, const Work& w, const voi
   return hipGetLastError();
 }
 
+template <int N, class R>
+hipError_t wave_solve_queue_t(const KProb& kp, const WQueue& q, const void* elts, void* S, void* v,
+                              void* x, void* u, hipStream_t s) {
+  hipLaunchKernelGGL((kw_solve_queue<N, R>), dim3((unsigned)q.total), dim3(64), 0, s, kp, q,
+                     (const R*)elts, (R*)S, (R*)v, (R*)x, (R*)u);
+  return hipGetLastError();
+}
+
 #ifndef LQT_SHARD
 #define LQT_SHARD 0
 #endif
@@ -2000,7 +2170,8 @@ template <int N, class R>
 struct Fns {
   static const WaveFns* get() {
     if constexpr (wave_shard(N, sizeof(R) == 4) == LQT_SHARD) {
-      static const WaveFns f = {wave_build_t<N, R>, wave_value_t<N, R>, wave_traj_t<N, R>};
+      static const WaveFns f = {wave_build_t<N, R>, wave_value_t<N, R>, wave_traj_t<N, R>,
+                                wave_solve_queue_t<N, R>};
       return &f;
     } else {
       return nullptr;

@@ -176,3 +176,43 @@ def test_batched_mix_full_size():
             assert relerr(_np(res[k]), _np(single[k][0])) < 1e-12, f"member {i} {k}"
     for i in (0, 1, 2):
         _check_member(bs.result(i), O.solve(probs[i]), 1e-9, f"member {i} vs oracle")
+
+
+@pytest.mark.parametrize("Ts", [(1, 2), (20, 30), (100, 130), (300, 257, 500), (4000, 3000, 2500)],
+                         ids=["one-node", "one-level", "two-level", "three-level", "four-level"])
+def test_wave_class_queue_tree_depths(Ts):
+    """One wave-path class (nx = 6) in the single queue launch, with trees of 1 to 4 levels
+    (8 nodes per wave; rows = sum of T_i + 1: 5 and 52 give one level, 232 two, 1060 three, 9503
+    four): every member against the oracle and against lqt_solve alone."""
+    probs = [W.random_stable(40 + i, 6, 3, T, 2, 0.0, 0.004 * T + 0.1, time_varying=False)
+             for i, T in enumerate(Ts)]
+    bs = lqt.BatchedSolve(probs, plan=False)
+    bs.solve_eager()
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        res = bs.result(i)
+        _check_member(res, O.solve(p), 1e-9, f"member {i} (T={p.T})")
+        single = lqt.solve(lqt.DeviceProblem.from_problems([p]))
+        for k in ("S", "v", "x", "u"):
+            assert relerr(_np(res[k]), _np(single[k][0])) < 1e-12, f"member {i} {k} vs single"
+
+
+@pytest.mark.parametrize("Ts,chunk", [((700, 900, 300), 1), ((5000, 7000, 129), 4),
+                                      ((2 ** 18, 2 ** 18 + 77, 3), 8)])
+def test_lane_class_queue_chunks(Ts, chunk):
+    """One per-lane class (nx = 2) in the single queue launch at each value chunk of the eager
+    solve (1 block per lane up to 2^11 rows, 4 below 2^19, 8 from there): members against
+    lqt_solve alone (1e-12) and the smallest against the oracle (1e-9)."""
+    probs = [W.point_mass(60 + i, T, 2, 0.0, 0.002 * T + 0.5, d=1) for i, T in enumerate(Ts)]
+    rows = sum(T + 1 for T in Ts)
+    assert (rows <= 2 ** 11) == (chunk == 1) and (rows >= 2 ** 19) == (chunk == 8)
+    bs = lqt.BatchedSolve(probs, plan=False)
+    bs.solve_eager()
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        res = bs.result(i)
+        single = lqt.solve(lqt.DeviceProblem.from_problems([p]))
+        for k in ("S", "v", "x", "u"):
+            assert relerr(_np(res[k]), _np(single[k][0])) < 1e-12, f"member {i} {k} vs single"
+    i = int(np.argmin(Ts))
+    _check_member(bs.result(i), O.solve(probs[i]), 1e-9, f"member {i} vs oracle")
