@@ -126,6 +126,7 @@ bool wave_queue(const WTree& t, long batch, const Work& w, WQueue* q) {
   q->nst = ns;
   q->total = at;
   q->done = w.wq_done;
+  q->bmap = w.bmap;
   return at + 1 <= w.wq_words;
 }
 
@@ -218,6 +219,9 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
       if (w) w->elts = e;
     }
     if (call == LQT_CALL_SOLVE) {
+      // every block's closed-loop map, kept by the value sweep for the trajectory sweep
+      void* bm = take(es * B * nm_of(d->nx) * (size_t)d->T);
+      if (w) w->bmap = bm;
       // status words of the queue solve (an item per tree node and stage) and its counter
       long items = 3 * t.n[1] + 2;
       for (int l = 2; l <= t.levels; ++l) items += 4 * t.n[l];

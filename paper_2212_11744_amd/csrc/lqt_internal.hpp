@@ -125,6 +125,7 @@ struct Work {
   void* elts = nullptr;              // elements when the caller gives none (lqt_solve)
   unsigned* wq_done = nullptr;       // wave path: status words and counter of the queue solve
   long wq_words = 0;
+  void* bmap = nullptr;              // wave path, solve: every block's map ([batch][T][nx^2 + nx])
   // adjoint
   void* lmap[kMaxLevels + 1] = {};   // lambda scan: maps, states, lane partials per level
   void* lst[kMaxLevels + 1] = {};
@@ -256,6 +257,7 @@ struct WQueue {
   int kind[4 * kWqMaxLevels + 1] = {};
   int level[4 * kWqMaxLevels + 1] = {};
   unsigned* done = nullptr;
+  void* bmap = nullptr;  // per-block maps (Work::bmap)
   void* vtup[kWqMaxLevels + 1] = {};
   void* vval[kWqMaxLevels + 1] = {};
   void* tmap[kWqMaxLevels + 1] = {};

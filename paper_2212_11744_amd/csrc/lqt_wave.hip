@@ -1595,6 +1595,20 @@ WDEV void val_ld(R* S, R* v, const R* g, int n) {
   wsync();
 }
 
+// Map records (P = Psi - I, q = alpha): n^2 + n values.
+template <class A = PlainAcc, class R>
+WDEV void map_ld(R* P, R* q, const R* g, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) P[e] = A::ld(g + e);
+  for (int i = lane_id(); i < n; i += 64) q[i] = A::ld(g + n * n + i);
+  wsync();
+}
+template <class A = PlainAcc, class R>
+WDEV void map_st(const R* P, const R* q, R* g, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) A::st(g + e, P[e]);
+  for (int i = lane_id(); i < n; i += 64) A::st(g + n * n + i, q[i]);
+  wsync();
+}
+
 // Node i of level l + 1: the product of the wc nodes i wc .. of level l (elements when
 // src_elts), right to left.
 template <int N, class A, class R>
@@ -1699,10 +1713,12 @@ __global__ __launch_bounds__(64) void kw_vdown(int, int wc, const R* __restrict_
 }
 
 // Values of every block from the value at the right end of each chunk; level 1 of the
-// trajectory tree (composition of the chunk's block maps) when maps1 != nullptr.
+// trajectory tree (composition of the chunk's block maps) when maps1 != nullptr, and every
+// block's closed-loop map ([batch][T] records P = Psi - I, q = alpha; the fold computes it on the
+// way) when bmaps != nullptr.
 template <int N, class A, class R>
 WDEV void wb_vbottom(R* sh, int* piv, const KProb& kp, int p, long i, int wc, const R* elts,
-                     const R* val1, long n1, R* Sout, R* vout, R* maps1) {
+                     const R* val1, long n1, R* Sout, R* vout, R* maps1, R* bmaps) {
   constexpr int n = N, kTupW = WSh<N>::kTupW, kScr = WSh<N>::kScr;
   const long T = kp.T;
   const int NE = ne_w(n), VR = n * n + n, MR = n * n + n;
@@ -1729,6 +1745,7 @@ WDEV void wb_vbottom(R* sh, int* piv, const KProb& kp, int p, long i, int wc, co
     w_fold<N>(a, S, v, scr, n, mP, mq);
     for (int e = lane_id(); e < n * n; e += 64) A::st(Sp + k * n * n + e, S[e]);
     for (int q = lane_id(); q < n; q += 64) A::st(vp + k * n + q, v[q]);
+    if (bmaps) map_st<A>(mP, mq, bmaps + ((long)p * T + k) * MR, n);
     if (maps1) w_aff_after(aP, aq, mP, mq, tmp, n);
   }
   if (maps1) {
@@ -1742,29 +1759,17 @@ template <int N, class R>
 __global__ __launch_bounds__(64) void kw_vbottom(const KProb kp, int wc, const R* __restrict__ elts,
                                                  const R* __restrict__ val1, long n1,
                                                  R* __restrict__ Sout, R* __restrict__ vout,
-                                                 R* __restrict__ maps1) {
+                                                 R* __restrict__ maps1, R* __restrict__ bmaps) {
   __shared__ R sh[WSh<N>::vbottom];
   __shared__ int piv;
   if ((long)blockIdx.x >= n1) return;
   wb_vbottom<N, PlainAcc>(sh, &piv, kp, blockIdx.y, blockIdx.x, wc, elts, val1, n1, Sout, vout,
-                          maps1);
+                          maps1, bmaps);
 }
 
 // ------------------------------------------------------------------------------------------
 // Trajectory tree.
 // ------------------------------------------------------------------------------------------
-template <class A = PlainAcc, class R>
-WDEV void map_ld(R* P, R* q, const R* g, int n) {
-  for (int e = lane_id(); e < n * n; e += 64) P[e] = A::ld(g + e);
-  for (int i = lane_id(); i < n; i += 64) q[i] = A::ld(g + n * n + i);
-  wsync();
-}
-template <class A = PlainAcc, class R>
-WDEV void map_st(const R* P, const R* q, R* g, int n) {
-  for (int e = lane_id(); e < n * n; e += 64) A::st(g + e, P[e]);
-  for (int i = lane_id(); i < n; i += 64) A::st(g + n * n + i, q[i]);
-  wsync();
-}
 
 // (S_{k+1}, v_{k+1}) into LDS; zeros for the last block in ragged mode (a separator, whose map
 // does not depend on them; row T does not exist there).
@@ -1897,10 +1902,12 @@ __global__ __launch_bounds__(64) void kw_tdown(int, int wc, const R* __restrict_
   wb_tdown<N, PlainAcc>(sh, blockIdx.y, blockIdx.x, wc, maps, n_child, x_in, n_par, x_out);
 }
 
-// x_k and u_k = -R^{-1} L(t_k)^T (S_k x_k - v_k) of every block of a chunk.
+// x_k and u_k = -R^{-1} L(t_k)^T (S_k x_k - v_k) of every block of a chunk; the block maps are
+// loaded from bmaps (see wb_vbottom) when given, else computed from the elements and S, v.
 template <int N, class A, class R>
 WDEV void wb_tbottom(R* sh, int* piv, const KProb& kp, int p, long i, int wc, const R* elts,
-                     const R* Sg, const R* vg, const R* x1, long n1, R* xout, R* uout) {
+                     const R* Sg, const R* vg, const R* x1, long n1, R* xout, R* uout,
+                     const R* bmaps) {
   constexpr int n = N, kTupW = WSh<N>::kTupW, kScr = WSh<N>::kScr;
   const int nu = kp.nu;
   const long T = kp.T;
@@ -1956,9 +1963,13 @@ WDEV void wb_tbottom(R* sh, int* piv, const KProb& kp, int p, long i, int wc, co
   for (long k = j0; k < j1; ++k) {
     for (int q = lane_id(); q < n; q += 64) xp[k * n + q] = x[q];
     control(k);
-    wt_load<PlainAcc>(a, elt_ref(elts, p, k, T, NE), n);
-    w_right_value<A>(kp, Sp, vp, k, S, v, n);
-    w_block_map<N>(a, S, v, scr, n, mP, mq);
+    if (bmaps) {
+      map_ld<A>(mP, mq, bmaps + ((long)p * T + k) * (n * n + n), n);
+    } else {
+      wt_load<PlainAcc>(a, elt_ref(elts, p, k, T, NE), n);
+      w_right_value<A>(kp, Sp, vp, k, S, v, n);
+      w_block_map<N>(a, S, v, scr, n, mP, mq);
+    }
     w_aff_apply(mP, mq, x, tmp, n);
   }
   if (j1 == T && !kp.seg) {
@@ -1971,12 +1982,13 @@ template <int N, class R>
 __global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R* __restrict__ elts,
                                                  const R* __restrict__ Sg, const R* __restrict__ vg,
                                                  const R* __restrict__ x1, long n1,
-                                                 R* __restrict__ xout, R* __restrict__ uout) {
+                                                 R* __restrict__ xout, R* __restrict__ uout,
+                                                 const R* __restrict__ bmaps) {
   __shared__ R sh[WSh<N>::tbottom];
   __shared__ int piv;
   if ((long)blockIdx.x >= n1) return;
   wb_tbottom<N, PlainAcc>(sh, &piv, kp, blockIdx.y, blockIdx.x, wc, elts, Sg, vg, x1, n1, xout,
-                          uout);
+                          uout, bmaps);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2053,7 +2065,7 @@ __global__ __launch_bounds__(64) void kw_solve_queue(const KProb kp, const WQueu
       else
         wait(st_vdown(1), i / wc, i / wc + 1);
       wb_vbottom<N, DevAcc>(sh, &piv, kp, p, i, (int)wc, e, (const R*)q.vval[1], q.n[1], S, v,
-                            (R*)q.tmap[1]);
+                            (R*)q.tmap[1], (R*)q.bmap);
       break;
     case kWqTRed:
       wait(l == 2 ? st_vbot : st_tred(l - 1), i * wc, min(i * wc + wc, q.n[l - 1]));
@@ -2077,7 +2089,8 @@ __global__ __launch_bounds__(64) void kw_solve_queue(const KProb kp, const WQueu
         wait(st_ttop, 0, 1);
       else
         wait(st_tdown(1), i / wc, i / wc + 1);
-      wb_tbottom<N, DevAcc>(sh, &piv, kp, p, i, (int)wc, e, S, v, (const R*)q.tx[1], q.n[1], x, u);
+      wb_tbottom<N, DevAcc>(sh, &piv, kp, p, i, (int)wc, e, S, v, (const R*)q.tx[1], q.n[1], x, u,
+                            (const R*)q.bmap);
       break;
   }
   if (lane == 0) lq_flag_store(q.done + it, 1u);
@@ -2125,7 +2138,8 @@ hipError_t wave_value_t(const KProb& kp, const WTree& t, const Work& w, const vo
                        (const R*)w.vtup[l], t.n[l], (const R*)w.vval[l + 1], t.n[l + 1],
                        (R*)w.vval[l]);
   hipLaunchKernelGGL((kw_vbottom<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
-                     (const R*)elts, (const R*)w.vval[1], t.n[1], (R*)S, (R*)v, (R*)maps1);
+                     (const R*)elts, (const R*)w.vval[1], t.n[1], (R*)S, (R*)v, (R*)maps1,
+                     (R*)(maps1 ? w.bmap : nullptr));
   return hipGetLastError();
 }
 
@@ -2149,7 +2163,7 @@ hipError_t wave_traj_t(const KProb& kp, const WTree& t, const Work& w, const voi
                        (R*)w.tx[l]);
   hipLaunchKernelGGL((kw_tbottom<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
                      (const R*)elts, (const R*)S, (const R*)v, (const R*)w.tx[1], t.n[1], (R*)x,
-                     (R*)u);
+                     (R*)u, (const R*)(maps_ready ? w.bmap : nullptr));
   return hipGetLastError();
 }
 

@@ -111,9 +111,11 @@ def test_plan_replays_and_follows_inputs():
 
 def test_graph_plan_replays():
     """The tuned plan captured once into a HIP graph (LQT_PLAN_GRAPH) and replayed: every replay,
-    with the program's own eager work and synchronisations between replays, equals the first
-    bit for bit, the eager solve at 1e-12 (the tuner may pick other tree shapes) and the oracle
-    at 1e-9; inputs refilled in place reach the next replay."""
+    with the program's own eager work and synchronisations between replays, equals the first and
+    the eager solve at 1e-12 and the oracle at 1e-9; inputs refilled in place reach the next
+    replay.  Replays are not compared bit for bit: a single-pass scan tile combines the records of
+    the tiles before it in an order that depends on which of them have already published, so the
+    rounding of the per-lane scans varies from run to run."""
     probs = _mixed(1)
     eager = lqt.BatchedSolve(probs, autotune=False, plan=False)
     eager.solve_eager()
@@ -128,7 +130,7 @@ def test_graph_plan_replays():
         for i, p in enumerate(probs):
             a, b = bs.result(i), eager.result(i)
             for k in ("S", "v", "x", "u"):
-                assert torch.equal(a[k], first[i][k]), f"replay {rep} member {i} {k}"
+                assert relerr(_np(a[k]), _np(first[i][k])) < 1e-12, f"replay {rep} member {i} {k}"
                 assert relerr(_np(a[k]), _np(b[k])) < 1e-12, f"replay {rep} member {i} {k}"
             if rep == 0:
                 _check_member(a, O.solve(p), 1e-9, f"replay {rep} member {i}")
