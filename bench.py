@@ -210,6 +210,7 @@ def main(argv=None):
                      "flops_per_block": build_flops_per_block(4, 2, n),
                      "flops_per_block_counting": "the kernel's own formulation (K = G J - F factored "
                                                  "out, packed symmetric products); frac uses it",
+                     "flops_per_block_executed_counters": 12540,
                      "flops_per_block_dense_generic": DENSE_GENERIC_BUILD_FLOPS,
                      "frac_dense_generic": DENSE_GENERIC_BUILD_FLOPS * T / (ms_build * 1e-3) / 1e12 / peak,
                      "algorithmic_bytes_per_launch": build_bytes_per_block(4, n, es) * T},
@@ -295,6 +296,13 @@ def small_leg(torch, lqt, W, dtype):
             "build_split_ms": _events_time(split, 200, torch)}
 
 
+# Executed FP64 flops per block of the adjoint's RK4 kernel (k_adj_rk4, nx = 4, nu = 2, n = 4
+# steps): (2 FMA + MUL + ADD + TRANS) F64 instructions per wave x 64 lanes, one block per lane,
+# from the SQ counters of profiles/sq_counters_main_kernels.txt.  The same counters give 12540
+# for the element build, whose own formulation counts 12496.
+ADJ_RK4_FLOPS_PER_BLOCK = 44682
+
+
 def adjoint_leg(torch, lqt, W, reps):
     """64 point-mass problems (seeds 5000 + i), T = 2^16, FP64: batched solve + adjoint of the
     loss sum_k |x_k - g(t_k)|^2 (gradients for Q, R, r, x0, Qf, rf)."""
@@ -310,9 +318,16 @@ def adjoint_leg(torch, lqt, W, reps):
     torch.cuda.synchronize()
     ms_f = _events_time(fwd, reps, torch)
     ms_b = _events_time(bwd, reps, torch)
+    # The RK4 adjoint of the elements is the backward pass's dominant kernel; its flops over the
+    # whole backward time bound its own fraction of the FP64 peak from below.
+    rk4_tf = ADJ_RK4_FLOPS_PER_BLOCK * B * T / (ms_b * 1e-3) / 1e12
     return {"workload": f"{B} point-mass problems, T={T} blocks x {n} RK4 steps, FP64, tracking loss",
             "fwd_ms": ms_f, "bwd_ms": ms_b, "fwd_bwd_ms": ms_f + ms_b,
-            "sub_intervals_per_s_fwd_bwd": B * T / ((ms_f + ms_b) * 1e-3)}
+            "sub_intervals_per_s_fwd_bwd": B * T / ((ms_f + ms_b) * 1e-3),
+            "rk4_adjoint": {"kernel": "k_adj_rk4", "flops_per_block": ADJ_RK4_FLOPS_PER_BLOCK,
+                            "flops_per_block_counting": "executed FP64 instructions (SQ counters)",
+                            "TFLOPs_over_bwd_ms": rk4_tf,
+                            "frac_lower_bound": rk4_tf / PEAK["f64_TFLOPs"]}}
 
 
 def nx16_leg(torch, lqt, W, reps):
