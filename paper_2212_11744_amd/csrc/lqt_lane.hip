@@ -1679,6 +1679,9 @@ __global__ __launch_bounds__(kThreads) void k_m2_bottom(const KProb kp, const R*
 }
 
 // ------------------------------------------------------------------------------------------
+// Interior nodes per block whose S, v the dense-output kernel keeps in LDS (n <= 5 RK4 steps).
+constexpr int kDenseSlots = 4;
+
 // Values inside the blocks (Sec. VI-A).  At the nodes t_k + m h (m = 1 .. n - 1) of block k:
 //   S, v by classical RK4 on their backward ODEs (Sec. II-B) from the right-end values
 //     dS/dt = -F^T S - S F - Q + S G S,  dv/dt = -Q r - F^T v + S G v + S c,
@@ -1696,10 +1699,16 @@ __global__ __launch_bounds__(kThreads) void k_dense(const KProb kp, const R* __r
                                                      R* __restrict__ ud) {
   using Y = Sym<N>;
   constexpr int NS = Y::size;
+  // S (upper) and v at the interior nodes of the lane's block, kept from the backward sweep for
+  // the forward sweep when the block has at most kDenseSlots of them (else read back from the
+  // outputs, by then mostly evicted from the L2).
+  __shared__ R sSv[kDenseSlots][NS + N][kThreads];
   const int p = blockIdx.y;
   const long k = gid();
   if (k >= kp.T) return;
   const int n = kp.n;
+  const bool keep = n - 1 <= kDenseSlots;
+  const int lane = threadIdx.x;
   const long T = kp.T;
   const long nodes = (long)n * T + 1;
   const Blk bk = blk_plain(kp, p, k);
@@ -1863,6 +1872,13 @@ __global__ __launch_bounds__(kThreads) void k_dense(const KProb kp, const R* __r
         v[i] = av[i];
         vdp[node * N + i] = v[i];
       }
+      if (keep) {
+        const int slot = n - mp - 2;  // interior node m = n - mp - 1 in slot m - 1
+#pragma unroll
+        for (int i = 0; i < NS; ++i) sSv[slot][i][lane] = S[i];
+#pragma unroll
+        for (int i = 0; i < N; ++i) sSv[slot][NS + i][lane] = v[i];
+      }
     }
   }
 
@@ -1907,9 +1923,16 @@ __global__ __launch_bounds__(kThreads) void k_dense(const KProb kp, const R* __r
   auto step = [&](int m, const R (&Ad)[N][N], const R (&b)[N], const R (&C)[NS]) {
     const long node = (long)n * k + m + 1;
     R S[NS], v[N], M[N][N], B[N][1];
-    S_load_upper<N, R>(S, Sdp + node * N * N);
+    if (keep) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) v[i] = vdp[node * N + i];
+      for (int i = 0; i < NS; ++i) S[i] = sSv[m][i][lane];
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = sSv[m][NS + i][lane];
+    } else {
+      S_load_upper<N, R>(S, Sdp + node * N * N);
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = vdp[node * N + i];
+    }
 #pragma unroll
     for (int a = 0; a < N; ++a) {
       R g = xk[a] + b[a];
