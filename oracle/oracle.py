@@ -62,9 +62,14 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
-            build(force=True)
-        L = ctypes.CDLL(_SO)
+        # LQT_ORACLE_LIB: another build of lqt_oracle.cpp (the sanitizer test loads one built
+        # with AddressSanitizer and UndefinedBehaviorSanitizer)
+        path = os.environ.get("LQT_ORACLE_LIB")
+        if not path:
+            path = _SO
+            if not os.path.exists(_SO):
+                build(force=True)
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER
         d = P(ctypes.c_double)
         L.oracle_elements.argtypes = [P(_Problem), ctypes.c_int, d, d, d, d, d]

@@ -24,7 +24,9 @@ import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liblqt.so")
+# LQT_LIBRARY: another build of the same sources (the sanitizer test loads one whose host code is
+# built with AddressSanitizer and UndefinedBehaviorSanitizer)
+LIB_PATH = os.environ.get("LQT_LIBRARY") or os.path.join(_HERE, "liblqt.so")
 
 LQT_OK, LQT_EINVAL, LQT_EUNSUPPORTED, LQT_EWORKSPACE, LQT_EHIP, LQT_ENONFINITE = 0, -1, -2, -3, -4, -5
 LQT_F64, LQT_F32 = 0, 1
