@@ -316,6 +316,27 @@ lqt_status lqt_plan_launch(lqt_plan plan, hipStream_t stream);
 const char *lqt_plan_config(lqt_plan plan);
 void lqt_plan_destroy(lqt_plan plan);
 
+/* ---- Debugging aids (process-wide settings; not for calls that run concurrently) ----
+ * lqt_debug_canary(mode): mode 1 places a 256-byte canary after every region of the workspace
+ * layout (lqt_workspace_size grows accordingly: query it after changing the mode); every
+ * single-problem call then fills the canaries before its first launch and, at its end,
+ * synchronises its stream and checks them, returning LQT_EWORKSPACE ("workspace canary i of n
+ * overwritten") if a kernel wrote past a region.  Mode 2 does the same and spoils canary 0
+ * itself after filling it, so the check must fire (a test of the check).  0 turns it off.
+ * Batched calls and lqt_solve_noalloc lay the canaries out but do not check them.  The
+ * environment variable LQT_CANARY=1|2 sets the mode when the library loads.
+ * lqt_debug_fail_launch(n): the n-th checked HIP call from now on (n >= 1; 0 disables) reports
+ * hipErrorLaunchFailure: the call itself is made, and the entry point returns LQT_EHIP with a
+ * message naming the simulation, as it would for a real failure (the error paths of callers
+ * can be tested without a fault).  LQT_FAIL_LAUNCH=n sets it when the library loads.
+ * Also read from the environment: LQT_CHECK_FINITE (above); LQT_AUTOTUNE=off|on|force
+ * (lqt_plan_create: off never tunes, on tunes plans created with LQT_PLAN_AUTOTUNE unless the
+ * cache holds their classes, force always tunes) and LQT_TUNE_CACHE=<file> (the tuner's choices
+ * persist in that file, keyed by GPU architecture and class signature, read when the first plan
+ * is created and rewritten after every tuning). */
+void lqt_debug_canary(int32_t mode);
+void lqt_debug_fail_launch(int32_t n);
+
 /* Short description of a status code. */
 const char *lqt_status_string(lqt_status status);
 

@@ -8,6 +8,9 @@
 #include <mutex>
 #include <string>
 
+#include <atomic>
+#include <cstdlib>
+
 #include "../../include/lqt.h"
 #include "lqt_internal.hpp"
 
@@ -32,6 +35,24 @@ lqt_status ok() {
   return LQT_OK;
 }
 
+// Simulated failures of checked HIP calls (lqt_debug_fail_launch, or LQT_FAIL_LAUNCH=n in the
+// environment when the library loads): the n-th checked call from then on reports
+// hipErrorLaunchFailure; the call itself is made as usual.
+std::atomic<int> g_fail_countdown{[] {
+  const char* e = getenv("LQT_FAIL_LAUNCH");
+  return e ? atoi(e) : 0;
+}()};
+thread_local bool g_fail_fired = false;
+
+// Canary mode (lqt_debug_canary, or LQT_CANARY=1|2 in the environment when the library loads):
+// 0 off, 1 on, 2 on and every call overwrites its first canary itself after filling it (which
+// the check must then report).
+std::atomic<int> g_canary{[] {
+  const char* e = getenv("LQT_CANARY");
+  return e ? atoi(e) : 0;
+}()};
+constexpr unsigned kCanaryWord = 0xC0DEFACEu;
+
 size_t dsize(int dtype) { return dtype == LQT_F64 ? 8 : 4; }
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 long ne_of(int nx) { return 2L * nx * nx + 3L * nx; }
@@ -40,6 +61,21 @@ long nm_of(int nx) { return (long)nx * nx + nx; }
 long padt(long n) { return (n + 255) / 256 * 256; }
 
 }  // namespace
+
+hipError_t debug_gate(hipError_t e) {
+  if (e != hipSuccess || g_fail_countdown.load(std::memory_order_relaxed) <= 0) return e;
+  if (g_fail_countdown.fetch_sub(1) == 1) {
+    g_fail_fired = true;
+    return hipErrorLaunchFailure;
+  }
+  return e;
+}
+
+const char* debug_gate_note() {
+  const bool f = g_fail_fired;
+  g_fail_fired = false;
+  return f ? " (simulated by lqt_debug_fail_launch)" : "";
+}
 
 Tree plan_tree(long T) {
   Tree t;
@@ -173,15 +209,28 @@ WTree wtree_for(const lqt_dims* d) { return wave_tree(d->T, kWaveChunk); }
 // nconsts: number of problems whose constants are prepared (the batch, or the problems of a
 // ragged class).
 size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, long nconsts,
-              bool ws_elts) {
+              bool ws_elts, bool keep_maps) {
   const size_t es = dsize(d->dtype);
   const long B = d->batch;
   size_t off = 0;
+  const bool canaries = g_canary.load() != 0;
+  if (w) {
+    w->ncanary = 0;
+    w->canary_armed = false;
+  }
   auto take = [&](size_t bytes) -> void* {
     void* p = base ? base + off : nullptr;
     off += align256(bytes);
+    if (canaries) {
+      if (w && base && w->ncanary < Work::kMaxCanaries) w->canary[w->ncanary++] = (unsigned*)(base + off);
+      off += 256;
+    }
     return p;
   };
+  if (canaries) {
+    void* r = take(sizeof(int));
+    if (w) w->canary_res = (int*)r;
+  }
   void* consts = take(es * nconsts * consts_count(d->nx, d->nu));
   if (w) w->consts = consts;
   void* fl = take(256);  // finite-check flag (taken here: the wave branch below returns early)
@@ -220,8 +269,10 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
     }
     if (call == LQT_CALL_SOLVE) {
       // every block's closed-loop map, kept by the value sweep for the trajectory sweep
-      void* bm = take(es * B * nm_of(d->nx) * (size_t)d->T);
-      if (w) w->bmap = bm;
+      if (keep_maps) {
+        void* bm = take(es * B * nm_of(d->nx) * (size_t)d->T);
+        if (w) w->bmap = bm;
+      }
       // status words of the queue solve (an item per tree node and stage) and its counter
       long items = 3 * t.n[1] + 2;
       for (int l = 2; l <= t.levels; ++l) items += 4 * t.n[l];
@@ -354,13 +405,46 @@ lqt_status check_ptr(const void* p, const char* name, size_t es) {
   return LQT_OK;
 }
 
-lqt_status check_ws(const lqt_dims* d, lqt_call call, void* ws, size_t ws_bytes, Work* w) {
+struct CanaryList {
+  unsigned* p[Work::kMaxCanaries];
+  int n;
+};
+
+// One workgroup per slot, one thread per word.
+__global__ void k_canary_fill(const CanaryList c, int* res, int spoil) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *res = 0x7fffffff;
+  if ((int)blockIdx.x < c.n)
+    c.p[blockIdx.x][threadIdx.x] = spoil && blockIdx.x == 0 ? ~kCanaryWord : kCanaryWord;
+}
+
+__global__ void k_canary_check(const CanaryList c, int* res) {
+  if ((int)blockIdx.x < c.n && c.p[blockIdx.x][threadIdx.x] != kCanaryWord)
+    atomicMin(res, (int)blockIdx.x);
+}
+
+CanaryList canary_list(const Work& w) {
+  CanaryList c;
+  c.n = w.ncanary;
+  for (int i = 0; i < w.ncanary; ++i) c.p[i] = w.canary[i];
+  return c;
+}
+
+lqt_status check_ws(const lqt_dims* d, lqt_call call, void* ws, size_t ws_bytes, Work* w,
+                    hipStream_t s) {
   const size_t need = layout(d, call, nullptr, nullptr);
   if (need > 0 && !ws) return fail(LQT_EWORKSPACE, "workspace is NULL (%zu bytes needed)", need);
   if (((uintptr_t)ws) % 256) return fail(LQT_EWORKSPACE, "workspace is not 256-byte aligned");
   if (ws_bytes < need)
     return fail(LQT_EWORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, need);
   layout(d, call, (char*)ws, w);
+  if (w->ncanary > 0 && w->canary_res) {
+    hipLaunchKernelGGL(k_canary_fill, dim3((unsigned)w->ncanary), dim3(64), 0, s, canary_list(*w),
+                       w->canary_res, g_canary.load() == 2 ? 1 : 0);
+    const hipError_t e = debug_gate(hipGetLastError());
+    if (e != hipSuccess)
+      return fail(LQT_EHIP, "canary fill failed: %s%s", hipGetErrorString(e), debug_gate_note());
+    w->canary_armed = true;
+  }
   return LQT_OK;
 }
 
@@ -372,9 +456,10 @@ lqt_status check_ws(const lqt_dims* d, lqt_call call, void* ws, size_t ws_bytes,
 
 #define LQT_HIP(x)                                                                  \
   do {                                                                              \
-    hipError_t _e = (x);                                                            \
+    hipError_t _e = debug_gate(x);                                                  \
     if (_e != hipSuccess)                                                           \
-      return fail(LQT_EHIP, "%s failed: %s", #x, hipGetErrorString(_e));            \
+      return fail(LQT_EHIP, "%s failed: %s%s", #x, hipGetErrorString(_e),           \
+                  debug_gate_note());                                               \
   } while (0)
 
 // ------------------------------------------------------------------------------------------
@@ -456,8 +541,25 @@ struct Arr {
 };
 
 // Scans the arrays when LQT_CHECK_FINITE is set; LQT_ENONFINITE if any value is NaN or Inf.
+// Canary mode: every slot still holds its pattern after the call's work (synchronises s).
+lqt_status canary_check(const Work& w, hipStream_t s) {
+  if (!w.canary_armed) return LQT_OK;
+  hipLaunchKernelGGL(k_canary_check, dim3((unsigned)w.ncanary), dim3(64), 0, s, canary_list(w),
+                     w.canary_res);
+  int h = 0;
+  LQT_HIP(hipGetLastError());
+  LQT_HIP(hipMemcpyAsync(&h, w.canary_res, sizeof(int), hipMemcpyDeviceToHost, s));
+  LQT_HIP(hipStreamSynchronize(s));
+  if (h != 0x7fffffff)
+    return fail(LQT_EWORKSPACE,
+                "workspace canary %d of %d overwritten (a region was written past its end)", h,
+                w.ncanary);
+  return LQT_OK;
+}
+
 lqt_status finite_check(const lqt_dims* d, const Work& w, hipStream_t s,
                         std::initializer_list<Arr> arrays) {
+  LQT_TRY(canary_check(w, s));
   if (!finite_check_on()) return LQT_OK;
   if (!w.flag) return fail(LQT_EWORKSPACE, "no finite-check flag in the workspace layout");
   hipLaunchKernelGGL(k_flag_clear, dim3(1), dim3(64), 0, s, w.flag);
@@ -562,6 +664,10 @@ extern "C" {
 
 size_t lqt_element_count(int32_t nx) { return nx < 1 ? 0 : (size_t)ne_of(nx); }
 
+void lqt_debug_fail_launch(int32_t n) { g_fail_countdown.store(n > 0 ? n : 0); }
+
+void lqt_debug_canary(int32_t mode) { g_canary.store(mode >= 0 && mode <= 2 ? mode : 0); }
+
 size_t lqt_workspace_size(const lqt_dims* dims, lqt_call call) {
   if (check_dims_valid(dims) != LQT_OK) return 0;
   if (call < LQT_CALL_BUILD || call > LQT_CALL_TRAJ_METHOD2) return 0;
@@ -574,7 +680,7 @@ lqt_status lqt_build_elements(const lqt_dims* dims, const lqt_problem* prob, voi
   LQT_TRY(check_problem(dims, prob, true, false));
   LQT_TRY(check_ptr(elts, "elts", dsize(dims->dtype)));
   Work w;
-  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w));
+  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w, stream));
   KProb kp = make_kprob(dims, prob, w.consts);
   LQT_HIP(prep(dims, kp, w.consts, stream));
   if (use_wave(dims)) {
@@ -598,7 +704,7 @@ lqt_status lqt_build_elements_forward(const lqt_dims* dims, const lqt_problem* p
   LQT_TRY(check_problem(dims, prob, true, false));
   LQT_TRY(check_ptr(elts, "elts", dsize(dims->dtype)));
   Work w;
-  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w));
+  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w, stream));
   KProb kp = make_kprob(dims, prob, w.consts);
   LQT_HIP(prep(dims, kp, w.consts, stream));
   LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build_fwd(kp, elts, stream));
@@ -614,7 +720,7 @@ lqt_status lqt_build_elements_split(const lqt_dims* dims, const lqt_problem* pro
   LQT_TRY(check_problem(dims, prob, true, false));
   LQT_TRY(check_ptr(elts, "elts", dsize(dims->dtype)));
   Work w;
-  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w));
+  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w, stream));
   KProb kp = make_kprob(dims, prob, w.consts);
   LQT_HIP(prep(dims, kp, w.consts, stream));
   LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build_split(kp, elts, stream));
@@ -638,7 +744,7 @@ lqt_status lqt_forward_traj_method2(const lqt_dims* dims, const lqt_problem* pro
   LQT_TRY(check_ptr(x, "x", es));
   if (u) LQT_TRY(check_ptr(u, "u", es));
   Work w;
-  LQT_TRY(check_ws(dims, LQT_CALL_TRAJ_METHOD2, ws, ws_bytes, &w));
+  LQT_TRY(check_ws(dims, LQT_CALL_TRAJ_METHOD2, ws, ws_bytes, &w, stream));
   KProb kp = make_kprob(dims, prob, w.consts);
   const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
   const Tree t = tree_for(dims);
@@ -671,7 +777,7 @@ lqt_status lqt_dense_output(const lqt_dims* dims, const lqt_problem* prob, const
   LQT_TRY(check_ptr(xd, "xd", es));
   if (ud) LQT_TRY(check_ptr(ud, "ud", es));
   Work w;
-  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w));
+  LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w, stream));
   KProb kp = make_kprob(dims, prob, w.consts);
   const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
   LQT_HIP(o->prep(kp, w.consts, stream));
@@ -692,7 +798,7 @@ lqt_status lqt_scan_value(const lqt_dims* dims, const void* elts, const void* Qf
   LQT_TRY(check_ptr(S, "S", es));
   LQT_TRY(check_ptr(v, "v", es));
   Work w;
-  LQT_TRY(check_ws(dims, LQT_CALL_SCAN_VALUE, ws, ws_bytes, &w));
+  LQT_TRY(check_ws(dims, LQT_CALL_SCAN_VALUE, ws, ws_bytes, &w, stream));
   lqt_problem p;
   memset(&p, 0, sizeof(p));
   p.Qf = Qf;
@@ -724,7 +830,7 @@ lqt_status lqt_forward_traj(const lqt_dims* dims, const lqt_problem* prob, const
   LQT_TRY(check_ptr(x, "x", es));
   if (u) LQT_TRY(check_ptr(u, "u", es));
   Work w;
-  LQT_TRY(check_ws(dims, LQT_CALL_FORWARD_TRAJ, ws, ws_bytes, &w));
+  LQT_TRY(check_ws(dims, LQT_CALL_FORWARD_TRAJ, ws, ws_bytes, &w, stream));
   KProb kp = make_kprob(dims, prob, w.consts);
   LQT_HIP(prep(dims, kp, w.consts, stream));
   if (use_wave(dims)) {
@@ -802,7 +908,7 @@ lqt_status lqt_solve(const lqt_dims* dims, const lqt_problem* prob, void* elts, 
   LQT_TRY(check_ptr(x, "x", es));
   if (u) LQT_TRY(check_ptr(u, "u", es));
   Work w;
-  LQT_TRY(check_ws(dims, LQT_CALL_SOLVE, ws, ws_bytes, &w));
+  LQT_TRY(check_ws(dims, LQT_CALL_SOLVE, ws, ws_bytes, &w, stream));
   KProb kp = make_kprob(dims, prob, w.consts);
   void* e = elts ? elts : w.elts;
   SolveOpts o;
@@ -860,7 +966,7 @@ extern "C" {
 
 size_t lqt_noalloc_scratch_size(const lqt_dims* dims) {
   if (check_dims_valid(dims) != LQT_OK) return 0;
-  return layout(dims, LQT_CALL_SOLVE, nullptr, nullptr, kWaveChunk, dims->batch, false);
+  return layout(dims, LQT_CALL_SOLVE, nullptr, nullptr, kWaveChunk, dims->batch, false, false);
 }
 
 lqt_status lqt_solve_noalloc(const lqt_dims* dims, const lqt_problem* prob, void* elts, void* S,
@@ -873,7 +979,8 @@ lqt_status lqt_solve_noalloc(const lqt_dims* dims, const lqt_problem* prob, void
   LQT_TRY(check_ptr(v, "v", es));
   LQT_TRY(check_ptr(x, "x", es));
   if (u) LQT_TRY(check_ptr(u, "u", es));
-  const size_t need = layout(dims, LQT_CALL_SOLVE, nullptr, nullptr, kWaveChunk, dims->batch, false);
+  const size_t need =
+      layout(dims, LQT_CALL_SOLVE, nullptr, nullptr, kWaveChunk, dims->batch, false, false);
   if (need > kNoAllocScratchBytes)
     return fail(LQT_EWORKSPACE,
                 "this problem needs %zu bytes of scratch; the no-allocation entry point has %zu "
@@ -882,7 +989,7 @@ lqt_status lqt_solve_noalloc(const lqt_dims* dims, const lqt_problem* prob, void
   void* base = nullptr;
   LQT_TRY(noalloc_scratch(&base));
   Work w;
-  layout(dims, LQT_CALL_SOLVE, (char*)base, &w, kWaveChunk, dims->batch, false);
+  layout(dims, LQT_CALL_SOLVE, (char*)base, &w, kWaveChunk, dims->batch, false, false);
   KProb kp = make_kprob(dims, prob, w.consts);
   SolveOpts o;
   o.wave_chunk = kWaveChunk;
@@ -917,7 +1024,7 @@ lqt_status lqt_backward(const lqt_dims* dims, const lqt_problem* prob, const voi
   if (dQf) LQT_TRY(check_ptr(dQf, "dQf", es));
   if (drf) LQT_TRY(check_ptr(drf, "drf", es));
   Work w;
-  LQT_TRY(check_ws(dims, LQT_CALL_BACKWARD, ws, ws_bytes, &w));
+  LQT_TRY(check_ws(dims, LQT_CALL_BACKWARD, ws, ws_bytes, &w, stream));
   const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
   KProb kp = make_kprob(dims, prob, w.consts);
   const Tree t = tree_for(dims);

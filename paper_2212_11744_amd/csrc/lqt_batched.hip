@@ -9,6 +9,7 @@
 // in dependency order, so a plan is four launches per class (constants, elements, clearing of the
 // queue's status words, the queue launch), whatever the number of problems.
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -177,6 +178,80 @@ struct Choice {
 std::mutex g_tune_mu;
 std::map<std::string, Choice> g_tune_cache;
 
+// LQT_AUTOTUNE: "off" never tunes (the default configuration, whatever the flags), "on" (the
+// default) tunes plans created with LQT_PLAN_AUTOTUNE unless the cache holds their classes,
+// "force" tunes every plan afresh.
+enum class TuneMode { kOff, kOn, kForce };
+TuneMode tune_mode() {
+  const char* e = getenv("LQT_AUTOTUNE");
+  if (!e) return TuneMode::kOn;
+  if (!strcmp(e, "off") || !strcmp(e, "0")) return TuneMode::kOff;
+  if (!strcmp(e, "force")) return TuneMode::kForce;
+  return TuneMode::kOn;
+}
+
+// LQT_TUNE_CACHE=<file>: the cache persists there, one line per entry:
+//   <gfx arch> <class signature> <parallel 0|1> <n> (<wave_chunk> <queue_chunk>) x n |<text>
+// read when the first plan is created and rewritten after every tuning (under g_tune_mu).
+bool g_cache_loaded = false;
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "unknown";
+  std::string a = prop.gcnArchName;
+  return a.substr(0, a.find(':'));  // without the target features
+}
+
+void cache_load_locked() {
+  if (g_cache_loaded) return;
+  g_cache_loaded = true;
+  const char* path = getenv("LQT_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = fopen(path, "r");
+  if (!f) return;
+  char line[4096];
+  while (fgets(line, sizeof(line), f)) {
+    char arch[64], sig[2048];
+    int par = 0, n = 0, used = 0;
+    if (sscanf(line, "%63s %2047s %d %d%n", arch, sig, &par, &n, &used) != 4 || n < 1 || n > 64)
+      continue;
+    Choice c;
+    c.parallel = par != 0;
+    const char* q = line + used;
+    bool good = true;
+    for (int i = 0; i < n && good; ++i) {
+      SolveOpts o;
+      int k = 0;
+      good = sscanf(q, "%d %d%n", &o.wave_chunk, &o.queue_chunk, &k) == 2;
+      q += k;
+      c.opts.push_back(o);
+    }
+    const char* bar = strchr(q, '|');
+    if (!good || !bar) continue;
+    c.text = std::string(bar + 1);
+    while (!c.text.empty() && (c.text.back() == '\n' || c.text.back() == '\r')) c.text.pop_back();
+    g_tune_cache[std::string(arch) + " " + sig] = c;
+  }
+  fclose(f);
+}
+
+void cache_save_locked() {
+  const char* path = getenv("LQT_TUNE_CACHE");
+  if (!path) return;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (const auto& kv : g_tune_cache) {
+    fprintf(f, "%s %d %zu", kv.first.c_str(), kv.second.parallel ? 1 : 0, kv.second.opts.size());
+    for (const auto& o : kv.second.opts) fprintf(f, " %d %d", o.wave_chunk, o.queue_chunk);
+    fprintf(f, " |%s\n", kv.second.text.c_str());
+  }
+  const bool ok = fclose(f) == 0;
+  if (ok) rename(tmp.c_str(), path);
+}
+
 }  // namespace
 }  // namespace lqt
 
@@ -221,10 +296,11 @@ void release(lqt_plan_s* p) {
 
 #define PLAN_HIP(x)                                                        \
   do {                                                                     \
-    hipError_t _e = (x);                                                   \
+    hipError_t _e = debug_gate(x);                                         \
     if (_e != hipSuccess) {                                                \
       char _b[256];                                                        \
-      snprintf(_b, sizeof(_b), "%s failed: %s", #x, hipGetErrorString(_e)); \
+      snprintf(_b, sizeof(_b), "%s failed: %s%s", #x, hipGetErrorString(_e), \
+               debug_gate_note());                                         \
       return set_error(LQT_EHIP, _b);                                      \
     }                                                                      \
   } while (0)
@@ -413,23 +489,30 @@ lqt_status lqt_plan_create(const lqt_ragged* classes, int32_t nclasses, void* ws
       return fail_with(set_error(LQT_EHIP, "event creation failed"));
     p->join.push_back(e);
   }
-  const std::string key = signature(p->cls);
+  // class signatures contain no blanks (comma- and semicolon-separated numbers)
+  const std::string key = device_arch() + " " + signature(p->cls);
+  const TuneMode mode = tune_mode();
+  const bool want_tune =
+      mode == TuneMode::kForce || (mode == TuneMode::kOn && (flags & LQT_PLAN_AUTOTUNE));
   bool have = false;
-  if (flags & LQT_PLAN_AUTOTUNE) {
+  if (want_tune && mode != TuneMode::kForce) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    cache_load_locked();
     auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) {
+    if (it != g_tune_cache.end() && it->second.opts.size() == p->cls.size()) {
       p->choice = it->second;
       have = true;
     }
   }
   if (!have) {
-    if (flags & LQT_PLAN_AUTOTUNE) {
+    if (want_tune) {
       // Tuning runs are ordered after the caller's pending work on `stream`.
       st = tune(p, stream, &p->choice);
       if (st != LQT_OK) return fail_with(st);
       std::lock_guard<std::mutex> lk(g_tune_mu);
+      cache_load_locked();
       g_tune_cache[key] = p->choice;
+      cache_save_locked();
     } else {
       for (const auto& r : p->cls) p->choice.opts.push_back(default_opts(r));
       p->choice.parallel = true;

@@ -126,6 +126,13 @@ struct Work {
   unsigned* wq_done = nullptr;       // wave path: status words and counter of the queue solve
   long wq_words = 0;
   void* bmap = nullptr;              // wave path, solve: every block's map ([batch][T][nx^2 + nx])
+  // canary mode (lqt_debug_canary): a 256-byte slot after every region, filled by check_ws and
+  // checked at the end of the call; canary_res: the index of the first changed slot
+  static constexpr int kMaxCanaries = 160;
+  unsigned* canary[kMaxCanaries] = {};
+  int ncanary = 0;
+  int* canary_res = nullptr;
+  bool canary_armed = false;
   // adjoint
   void* lmap[kMaxLevels + 1] = {};   // lambda scan: maps, states, lane partials per level
   void* lst[kMaxLevels + 1] = {};
@@ -307,14 +314,19 @@ inline int queue_tchunk(int cv) { return cv < 4 ? cv : 4; }
 // Workspace layout of one call (lqt_api.hip); the layout for wave_chunk wc also serves any larger
 // chunk.  nconsts: problems whose per-problem constants are prepared.
 // ws_elts: a solve keeps its elements in the workspace (false when the caller provides them).
+// keep_maps: on the wave path, room for every block's closed-loop map (Work::bmap).
 size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, long nconsts,
-              bool ws_elts = true);
+              bool ws_elts = true, bool keep_maps = true);
 
 // Prep, element build, value scan and trajectory scan for validated arguments.
 lqt_status run_solve(const lqt_dims* d, const KProb& kp, const Work& w, void* elts, void* S,
                      void* v, void* x, void* u, const SolveOpts& o, hipStream_t stream);
 
 // Record / clear the calling thread's last error (lqt_last_error).
+// Simulated failures (lqt_debug_fail_launch): every checked HIP call's status passes through
+// debug_gate; debug_gate_note() names a failure the gate produced (and forgets it).
+hipError_t debug_gate(hipError_t e);
+const char* debug_gate_note();
 lqt_status set_error(lqt_status st, const char* msg);
 lqt_status clear_error();
 

@@ -71,6 +71,10 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER
         vp, sz, st = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p
+        L.lqt_debug_canary.argtypes = [ctypes.c_int32]
+        L.lqt_debug_canary.restype = None
+        L.lqt_debug_fail_launch.argtypes = [ctypes.c_int32]
+        L.lqt_debug_fail_launch.restype = None
         L.lqt_element_count.argtypes = [ctypes.c_int32]
         L.lqt_element_count.restype = sz
         L.lqt_workspace_size.argtypes = [P(Dims), ctypes.c_int]
@@ -356,6 +360,17 @@ def solve_noalloc(prob: DeviceProblem, out: Optional[dict] = None):
                                    _ptr(out["S"]), _ptr(out["v"]), _ptr(out["x"]),
                                    _ptr(out.get("u")), _stream()))
     return out
+
+
+def debug_canary(mode: int) -> None:
+    """Canary-padded workspaces (lqt_debug_canary): 1 on, 2 on with canary 0 spoilt by every call
+    (the check must report it), 0 off.  Workspaces must be sized after changing the mode."""
+    lib().lqt_debug_canary(int(mode))
+
+
+def debug_fail_launch(n: int) -> None:
+    """The n-th checked HIP call from now on reports a launch failure (lqt_debug_fail_launch)."""
+    lib().lqt_debug_fail_launch(int(n))
 
 
 def noalloc_scratch_size(prob: DeviceProblem) -> int:
