@@ -241,8 +241,10 @@ lqt_status lqt_solve_noalloc(const lqt_dims *dims, const lqt_problem *prob, void
  * workspace, not read.  Structure: a reverse affine scan for the state adjoint
  * lambda_k = dLdx_k + Psi_k^T lambda_{k+1}, a forward scan for the value adjoints (the linear
  * parts compose like the trajectory maps), per-block gradients of the combination rule
- * (Lemma 7) and the discrete adjoint of each block's RK4 steps.  FP64 only, nx <= 4, F and L
- * constant, c = 0 (LQT_EUNSUPPORTED otherwise). */
+ * (Lemma 7) and the discrete adjoint of each block's RK4 steps.  FP64 only, nx <= 4
+ * (LQT_EUNSUPPORTED otherwise); F and L constant or sampled, with or without a drift c (F, L, c
+ * are not differentiated; with sampled L, R enters through G(t) = L(t) R^{-1} L(t)^T at every
+ * sample, and the workspace holds G at every sample). */
 lqt_status lqt_backward(const lqt_dims *dims, const lqt_problem *prob, const void *S,
                         const void *v, const void *x, const void *dLdx, void *dQ, void *dR,
                         void *dr, void *dx0, void *dQf, void *drf, void *ws, size_t ws_bytes,

@@ -1,5 +1,6 @@
 // Adjoint of lqt_solve (1 <= nu <= nx <= 4): gradients of a loss L(x_0, ..., x_T) with
-// respect to Q, R, the reference samples r, x0, Qf and rf, for F, L constant and c = 0.
+// respect to Q, R, the reference samples r, x0, Qf and rf; F and L constant or sampled, with or
+// without a drift c (none of them differentiated).
 //
 // The forward scheme is: elements a_k from RK4 on Theorem 8 (Sec. IV-B); values
 // (S_k, v_k) = a_k (x) (S_{k+1}, v_{k+1}) from the terminal value (Qf, Qf rf) (Theorem 6,
@@ -701,12 +702,40 @@ LQT_DEV void stage_axpy(const Stage<N, R>& y, R c, const Stage<N, R>& k, Stage<N
   for (int i = 0; i < Sym<N>::size; ++i) o.J[i] = fma(c, k.J[i], y.J[i]);
 }
 
-// The (Ad, eta, J) part of the right-hand side.  F, G, Q: row-major N x N.
-template <int N, class R>
-LQT_DEV void rhs_aej(const Stage<N, R>& y, const R* F, const R* G,
-                     const R* Q, const R (&r)[N],
+// Coefficients of the right-hand side at one sample: F, G row-major N x N, the drift c
+// (nullptr: none).
+template <class R>
+struct Cf {
+  const R* F;
+  const R* G;
+  const R* c;
+};
+
+// Where the coefficients of sample j are.  SMP = false: constant F and G (one pointer each, the
+// same for the whole wave) and no drift.  SMP = true: F + j fs, G + j gs (fs, gs zero for a
+// constant one) and c + j N when c != nullptr.
+template <int N, class R, bool SMP>
+struct CoefSrc {
+  const R* F;
+  long fs;
+  const R* G;
+  long gs;
+  const R* c;
+  LQT_DEV Cf<R> at(long j) const {
+    if constexpr (SMP)
+      return {F + j * fs, G + j * gs, c ? c + j * N : nullptr};
+    else
+      return {F, G, nullptr};
+  }
+};
+
+// The (Ad, eta, J) part of the right-hand side (D: a drift may be present).  Q: row-major.
+template <int N, class R, bool D>
+LQT_DEV void rhs_aej(const Stage<N, R>& y, const Cf<R>& cf, const R* Q, const R (&r)[N],
                      Stage<N, R>& f) {
   using Y = Sym<N>;
+  const R* F = cf.F;
+  const R* G = cf.G;
   R K[N][N];
 #pragma unroll
   for (int i = 0; i < N; ++i)
@@ -734,6 +763,12 @@ LQT_DEV void rhs_aej(const Stage<N, R>& y, const R* F, const R* G,
       s = fma(K[l][i], y.e[l], s);
       s = fma(-Q[i * N + l], r[l], s);
     }
+    if constexpr (D) {
+      if (cf.c) {  // + J c
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(y.J[Y::at(i, l)], cf.c[l], s);
+      }
+    }
     f.e[i] = s;
   }
 #pragma unroll
@@ -755,11 +790,15 @@ LQT_DEV void rhs_aej(const Stage<N, R>& y, const R* F, const R* G,
 // Returns the adjoint of y's (Ad, eta, J) in `out`, accumulates the symmetric parts of the Q and
 // G adjoints (packed, per-lane LDS slots Qs, Gs) and the adjoint of this stage's reference
 // sample into rb.  The phases are ordered so that each temporary dies early (register pressure).
-template <int N, class R>
+// With a drift (D and cf.c): w = G eta + c in the b right-hand side, and the J c term of the
+// eta right-hand side adds g.eta c^T to the J adjoint.
+template <int N, class R, bool D>
 LQT_DEV void rhs_vjp(const Stage<N, R>& y, const Stage<N, R>& g, R c1, const R (&yb_b)[N],
-                     const R (&yb_C)[Sym<N>::size], const R* F, const R* G, const R* Q,
+                     const R (&yb_C)[Sym<N>::size], const Cf<R>& cf, const R* Q,
                      const R (&r)[N], Stage<N, R>& out, R* Qs, R* Gs, int lane, R (&rb)[N]) {
   using Y = Sym<N>;
+  const R* F = cf.F;
+  const R* G = cf.G;
   // Bs = Bc + Bc^T from the C adjoint (upper triangular Bc); Bj upper triangular from g.J.
   auto Bs = [&](int i, int l) -> R {
     return i == l ? R(2) * c1 * yb_C[Y::at(i, i)] : c1 * yb_C[Y::at(i, l)];
@@ -805,6 +844,9 @@ LQT_DEV void rhs_vjp(const Stage<N, R>& y, const Stage<N, R>& g, R c1, const R (
         s = fma(-F[i * N + l], Bj(l, q), s);
         s = fma(G[i * N + l], Kb[l][q], s);
       }
+      if constexpr (D) {
+        if (cf.c) s = fma(g.e[i], cf.c[q], s);
+      }
       out.J[Y::at(i, q)] += s;
     }
   // Qs: symmetric parts of -ge r^T and of -Bj (upper entries).
@@ -827,6 +869,9 @@ LQT_DEV void rhs_vjp(const Stage<N, R>& y, const Stage<N, R>& g, R c1, const R (
       t = fma(G[i * N + l], y.e[l], t);
     }
     wb[i] = -c1 * s;
+    if constexpr (D) {
+      if (cf.c) t += cf.c[i];
+    }
     w[i] = t;
   }
   // Gs: symmetric parts of Kb J and wb eta^T.
@@ -907,50 +952,79 @@ LQT_DEV void sample_r(const R* rp, long j, R (&r)[N]) {
 }
 
 // One classical RK4 step of -h (hp = -h) from the sample j1 (stage 1) to j1 - 2 (stage 4).
-template <int N, class R>
-LQT_DEV void rk4_forward(Stage<N, R>& y, long j1, R hp, const R* rp, const R* F,
-                         const R* G, const R* Q) {
+template <int N, class R, bool SMP>
+LQT_DEV void rk4_forward(Stage<N, R>& y, long j1, R hp, const R* rp,
+                         const CoefSrc<N, R, SMP>& cs, const R* Q) {
   R r[N];
   Stage<N, R> acc, s, k;
   const R w6 = hp / R(6), w3 = hp / R(3);
   sample_r<N, R>(rp, j1, r);
-  rhs_aej(y, F, G, Q, r, k);
+  rhs_aej<N, R, SMP>(y, cs.at(j1), Q, r, k);
   stage_axpy(y, w6, k, acc);
   stage_axpy(y, R(0.5) * hp, k, s);
   sample_r<N, R>(rp, j1 - 1, r);
   lds_fence();
-  rhs_aej(s, F, G, Q, r, k);
+  rhs_aej<N, R, SMP>(s, cs.at(j1 - 1), Q, r, k);
   stage_axpy(acc, w3, k, acc);
   stage_axpy(y, R(0.5) * hp, k, s);
   lds_fence();
-  rhs_aej(s, F, G, Q, r, k);
+  rhs_aej<N, R, SMP>(s, cs.at(j1 - 1), Q, r, k);
   stage_axpy(acc, w3, k, acc);
   stage_axpy(y, hp, k, s);
   sample_r<N, R>(rp, j1 - 2, r);
   lds_fence();
-  rhs_aej(s, F, G, Q, r, k);
+  rhs_aej<N, R, SMP>(s, cs.at(j1 - 2), Q, r, k);
   stage_axpy(acc, w6, k, y);
 }
 
 // Stage value `stage` (2, 3 or 4) of the RK4 step starting at y (samples j1, j1 - 1).
-template <int N, class R>
+template <int N, class R, bool SMP>
 LQT_DEV void stage_value(const Stage<N, R>& y, int stage, long j1, R hp, const R* rp,
-                         const R* F, const R* G, const R* Q,
-                         Stage<N, R>& s) {
+                         const CoefSrc<N, R, SMP>& cs, const R* Q, Stage<N, R>& s) {
   R r[N];
   Stage<N, R> k;
   sample_r<N, R>(rp, j1, r);
-  rhs_aej(y, F, G, Q, r, k);
+  rhs_aej<N, R, SMP>(y, cs.at(j1), Q, r, k);
   stage_axpy(y, R(0.5) * hp, k, s);
   if (stage == 2) return;
   sample_r<N, R>(rp, j1 - 1, r);
   lds_fence();
-  rhs_aej(s, F, G, Q, r, k);
+  rhs_aej<N, R, SMP>(s, cs.at(j1 - 1), Q, r, k);
   stage_axpy(y, R(0.5) * hp, k, s);
   if (stage == 3) return;
   lds_fence();
-  rhs_aej(s, F, G, Q, r, k);
+  rhs_aej<N, R, SMP>(s, cs.at(j1 - 1), Q, r, k);
   stage_axpy(y, hp, k, s);
+}
+
+// Sampled L: the G adjoint of one stage (packed symmetric, per-lane slots gL) becomes the adjoint
+// of W = R^{-1} through G = L W L^T at the stage's sample: Wbar += L^T Gbar L (packed symmetric,
+// slots wL); gL is cleared for the next stage.
+template <int N, int NU, class R>
+LQT_DEV void wbar_stage(R* gL, const R* L, R* wL, int lane) {
+  using Y = Sym<N>;
+  using U = Sym<NU>;
+  R GL[N][NU];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      R s = R(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(gL[Y::at(i, l) * kT + lane], L[l * NU + m], s);
+      GL[i][m] = s;
+    }
+#pragma unroll
+  for (int a = 0; a < NU; ++a)
+#pragma unroll
+    for (int b = a; b < NU; ++b) {
+      R s = R(0);
+#pragma unroll
+      for (int i = 0; i < N; ++i) s = fma(L[i * NU + a], GL[i][b], s);
+      wL[U::at(a, b) * kT + lane] += s;
+    }
+#pragma unroll
+  for (int i = 0; i < Y::size; ++i) gL[i * kT + lane] = R(0);
 }
 
 // g = c1 * yb + c2 * sn on the (Ad, eta, J) parts.
@@ -966,19 +1040,24 @@ LQT_DEV void stage_seed(R c1, const Tup<N, R>& yb, R c2, const Stage<N, R>& sn, 
   for (int i = 0; i < Sym<N>::size; ++i) g.J[i] = fma(c2, sn.J[i], c1 * yb.J[i]);
 }
 
-template <int N, int NU, class R>
+// SMP: sampled F or L, or a drift c (per-lane coefficients at every stage; gsamp holds G at every
+// sample when L is sampled).  Otherwise F, G are the problem's constants.
+template <int N, int NU, class R, bool SMP>
 __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restrict__ abar,
                                                R* __restrict__ dr, R* __restrict__ bnd,
                                                R* __restrict__ wsum, R* __restrict__ ckpt,
                                                int ckpt_ready, const R* __restrict__ cF,
                                                const R* __restrict__ cG,
-                                               const R* __restrict__ cQ) {
+                                               const R* __restrict__ cQ,
+                                               const R* __restrict__ gsamp) {
   using Y = Sym<N>;
-  constexpr int NS = Y::size, SL = StageLay<N>::size;
+  using U = Sym<NU>;
+  constexpr int NS = Y::size, SL = StageLay<N>::size, NW = SMP ? U::size : 1;
   // per-lane slots: step start value, running sum of stage adjoints, symmetric Q and G adjoints
   // (40 KB in FP64 at nx = 4, so four workgroups fit the 160 KB of LDS of a CU; F, G and Q are
-  // read through the scalar cache instead of being staged here)
-  __shared__ R yL[SL * kT], aL[SL * kT], qL[NS * kT], gL[NS * kT];
+  // read through the scalar cache instead of being staged here); with sampled L also the
+  // adjoint of R^{-1} (wL), the G adjoint then holding one stage's part at a time
+  __shared__ R yL[SL * kT], aL[SL * kT], qL[NS * kT], gL[NS * kT], wL[NW * kT];
   const int p = blockIdx.y;
   const long k = gidx();
   const long T = kp.T;
@@ -991,8 +1070,27 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
     qL[i * kT + lane] = R(0);
     gL[i * kT + lane] = R(0);
   }
-  const R* vF = cF;
-  const R* vG = cG + (long)p * CS<N, NU>::size;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) wL[i * kT + lane] = R(0);
+  CoefSrc<N, R, SMP> cs;
+  cs.F = cF;
+  cs.fs = 0;
+  cs.G = cG + (long)p * CS<N, NU>::size;
+  cs.gs = 0;
+  cs.c = nullptr;
+  const bool Lsmp = SMP && kp.L_sampled;
+  const R* Lp = Lsmp ? (const R*)kp.L + (long)p * nsamp * N * NU : nullptr;  // sampled L
+  if constexpr (SMP) {
+    if (kp.F_sampled) {
+      cs.F = (const R*)kp.F + (long)p * nsamp * N * N;
+      cs.fs = N * N;
+    }
+    if (kp.L_sampled) {
+      cs.G = gsamp + (long)p * nsamp * N * N;
+      cs.gs = N * N;
+    }
+    if (kp.has_c) cs.c = (const R*)kp.c + (long)p * nsamp * N;
+  }
   const R* vQ = cQ + (long)p * N * N;
   R* vq = qL;
   R* vg = gL;
@@ -1021,7 +1119,7 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
       stage_zero(y);
 #pragma unroll 1
       for (int mm = 0; mm < n - 1; ++mm) {
-        rk4_forward(y, 2L * n * k + 2L * (n - mm), hp, rp, vF, vG, vQ);
+        rk4_forward(y, 2L * n * k + 2L * (n - mm), hp, rp, cs, vQ);
         stage_to_global(y, ckp + (long)mm * SL * ck_stride, ck_stride, k);
       }
     }
@@ -1036,7 +1134,7 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
         } else if (!ckp) {
 #pragma unroll 1
           for (int mm = 0; mm < m; ++mm)
-            rk4_forward(y, 2L * n * k + 2L * (n - mm), hp, rp, vF, vG, vQ);
+            rk4_forward(y, 2L * n * k + 2L * (n - mm), hp, rp, cs, vQ);
         }
         stage_to_lds(y, yL, lane);
         Stage<N, R> z;
@@ -1054,13 +1152,14 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
         Stage<N, R> y, s, g;
         R r[N], rbs[N];
         stage_from_lds(y, yL, lane);
-        stage_value(y, 4, j1, hp, rp, vF, vG, vQ, s);
+        stage_value(y, 4, j1, hp, rp, cs, vQ, s);
         stage_zero(sn);
         stage_seed(w6, yb, R(0), sn, g);
         sample_r<N, R>(rp, j1 - 2, r);
 #pragma unroll
         for (int q = 0; q < N; ++q) rbs[q] = R(0);
-        rhs_vjp(s, g, w6, yb.b, yb.C, vF, vG, vQ, r, sn, vq, vg, lane, rbs);
+        rhs_vjp<N, R, SMP>(s, g, w6, yb.b, yb.C, cs.at(j1 - 2), vQ, r, sn, vq, vg, lane, rbs);
+        if (Lsmp) wbar_stage<N, NU, R>(gL, Lp + (j1 - 2) * N * NU, wL, lane);
         stage_add_lds(sn, aL, lane);
         if (m == n - 1) {
 #pragma unroll
@@ -1076,12 +1175,13 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
         Stage<N, R> y, s, g;
         R r[N], rbs[N];
         stage_from_lds(y, yL, lane);
-        stage_value(y, 3, j1, hp, rp, vF, vG, vQ, s);
+        stage_value(y, 3, j1, hp, rp, cs, vQ, s);
         stage_seed(w3, yb, hp, sn, g);
         sample_r<N, R>(rp, j1 - 1, r);
 #pragma unroll
         for (int q = 0; q < N; ++q) rbs[q] = R(0);
-        rhs_vjp(s, g, w3, yb.b, yb.C, vF, vG, vQ, r, sn, vq, vg, lane, rbs);
+        rhs_vjp<N, R, SMP>(s, g, w3, yb.b, yb.C, cs.at(j1 - 1), vQ, r, sn, vq, vg, lane, rbs);
+        if (Lsmp) wbar_stage<N, NU, R>(gL, Lp + (j1 - 1) * N * NU, wL, lane);
         stage_add_lds(sn, aL, lane);
 #pragma unroll
         for (int q = 0; q < N; ++q) drp[(j1 - 1) * N + q] = rbs[q];
@@ -1092,12 +1192,13 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
         Stage<N, R> y, s, g;
         R r[N], rbs[N];
         stage_from_lds(y, yL, lane);
-        stage_value(y, 2, j1, hp, rp, vF, vG, vQ, s);
+        stage_value(y, 2, j1, hp, rp, cs, vQ, s);
         stage_seed(w3, yb, R(0.5) * hp, sn, g);
         sample_r<N, R>(rp, j1 - 1, r);
 #pragma unroll
         for (int q = 0; q < N; ++q) rbs[q] = drp[(j1 - 1) * N + q];
-        rhs_vjp(s, g, w3, yb.b, yb.C, vF, vG, vQ, r, sn, vq, vg, lane, rbs);
+        rhs_vjp<N, R, SMP>(s, g, w3, yb.b, yb.C, cs.at(j1 - 1), vQ, r, sn, vq, vg, lane, rbs);
+        if (Lsmp) wbar_stage<N, NU, R>(gL, Lp + (j1 - 1) * N * NU, wL, lane);
         stage_add_lds(sn, aL, lane);
 #pragma unroll
         for (int q = 0; q < N; ++q) drp[(j1 - 1) * N + q] = rbs[q];
@@ -1112,7 +1213,8 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
         sample_r<N, R>(rp, j1, r);
 #pragma unroll
         for (int q = 0; q < N; ++q) carry[q] = R(0);
-        rhs_vjp(y, g, w6, yb.b, yb.C, vF, vG, vQ, r, sn, vq, vg, lane, carry);
+        rhs_vjp<N, R, SMP>(y, g, w6, yb.b, yb.C, cs.at(j1), vQ, r, sn, vq, vg, lane, carry);
+        if (Lsmp) wbar_stage<N, NU, R>(gL, Lp + j1 * N * NU, wL, lane);
         stage_add_lds(sn, aL, lane);
       }
       lds_fence();
@@ -1133,11 +1235,13 @@ __global__ __launch_bounds__(kT) void k_adj_rk4(const KProb kp, const R* __restr
 #pragma unroll
     for (int q = 0; q < N; ++q) bnd[((long)p * T + k) * 2 * N + N + q] = carry[q];
   }
-  // Wave sums of the symmetric Q and G adjoints (deterministic, one record per wave).
+  // Wave sums of the symmetric Q and G adjoints (deterministic, one record per wave); with sampled
+  // L the G part of the record holds the adjoint of R^{-1} instead (packed, nu (nu + 1) / 2).
   R Qs[NS], Gs[NS];
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    R a = qL[i * kT + lane], b = gL[i * kT + lane];
+    R a = qL[i * kT + lane];
+    R b = Lsmp ? (i < U::size ? wL[(i < NW ? i : 0) * kT + lane] : R(0)) : gL[i * kT + lane];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       a += __shfl_xor(a, off, 64);
@@ -1212,6 +1316,32 @@ __global__ __launch_bounds__(kT) void k_adj_sum(const KProb kp, const R* __restr
       Gs[i][q] = acc[NS + Y::at(i, q)];
     }
   const R* cs = (const R*)kp.consts + (long)p * CS<N, NU>::size;
+  if (kp.L_sampled) {
+    // G = L(t) W L(t)^T sample by sample: the record holds Wbar (W = R^{-1}, packed);
+    // Rbar = -W Wbar W
+    using U = Sym<NU>;
+    const R* Wi = cs + CS<N, NU>::Rinv;
+    R WB[NU][NU];
+#pragma unroll
+    for (int a = 0; a < NU; ++a)
+#pragma unroll
+      for (int m = 0; m < NU; ++m) {
+        R t = R(0);
+#pragma unroll
+        for (int q = 0; q < NU; ++q) t = fma(Wi[a * NU + q], acc[NS + U::at(q, m)], t);
+        WB[a][m] = t;
+      }
+#pragma unroll
+    for (int a = 0; a < NU; ++a)
+#pragma unroll
+      for (int m = 0; m < NU; ++m) {
+        R t = R(0);
+#pragma unroll
+        for (int q = 0; q < NU; ++q) t = fma(WB[a][q], Wi[q * NU + m], t);
+        dR[(long)p * NU * NU + a * NU + m] = -t;
+      }
+    return;
+  }
   R KG[NU][N];
 #pragma unroll
   for (int l = 0; l < NU; ++l)
@@ -1230,6 +1360,37 @@ __global__ __launch_bounds__(kT) void k_adj_sum(const KProb kp, const R* __restr
 #pragma unroll
       for (int q = 0; q < N; ++q) s = fma(KG[l][q], cs[CS<N, NU>::Kc + m * N + q], s);
       dR[(long)p * NU * NU + l * NU + m] = -s;
+    }
+}
+
+// G(t) = L(t) R^{-1} L(t)^T at every sample of a problem with sampled L (full N x N).
+template <int N, int NU, class R>
+__global__ __launch_bounds__(kT) void k_adj_gsamp(const KProb kp, R* __restrict__ gsamp) {
+  const int p = blockIdx.y;
+  const long j = gidx();
+  const long nsamp = 2L * kp.n * kp.T + 1;
+  if (j >= nsamp) return;
+  const R* L = (const R*)kp.L + ((long)p * nsamp + j) * N * NU;
+  const R* Wi = (const R*)kp.consts + (long)p * CS<N, NU>::size + CS<N, NU>::Rinv;
+  R LW[N][NU];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+      R t = R(0);
+#pragma unroll
+      for (int q = 0; q < NU; ++q) t = fma(L[i * NU + q], Wi[q * NU + m], t);
+      LW[i][m] = t;
+    }
+  R* g = gsamp + ((long)p * nsamp + j) * N * N;
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      R t = R(0);
+#pragma unroll
+      for (int m = 0; m < NU; ++m) t = fma(LW[i][m], L[q * NU + m], t);
+      g[i * N + q] = t;
     }
 }
 
@@ -1301,10 +1462,23 @@ struct A {
     return hipGetLastError();
   }
   static hipError_t rk4(const KProb& kp, const void* abar, void* dr, void* bnd, void* wsum,
-                        void* ckpt, bool ckpt_ready, hipStream_t s) {
-    hipLaunchKernelGGL((k_adj_rk4<N, NU, R>), lanes(kp.T, kp.batch), dim3(kT), 0, s, kp,
-                       (const R*)abar, (R*)dr, (R*)bnd, (R*)wsum, (R*)ckpt, (int)ckpt_ready,
-                       (const R*)kp.F, (const R*)kp.consts + CS<N, NU>::G, (const R*)kp.Q);
+                        void* ckpt, bool ckpt_ready, void* gsamp, hipStream_t s) {
+    if (kp.L_sampled) {
+      hipLaunchKernelGGL((k_adj_gsamp<N, NU, R>), lanes(2L * kp.n * kp.T + 1, kp.batch), dim3(kT),
+                         0, s, kp, (R*)gsamp);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+    if (kp.F_sampled || kp.L_sampled || kp.has_c)
+      hipLaunchKernelGGL((k_adj_rk4<N, NU, R, true>), lanes(kp.T, kp.batch), dim3(kT), 0, s, kp,
+                         (const R*)abar, (R*)dr, (R*)bnd, (R*)wsum, (R*)ckpt, (int)ckpt_ready,
+                         (const R*)kp.F, (const R*)kp.consts + CS<N, NU>::G, (const R*)kp.Q,
+                         (const R*)gsamp);
+    else
+      hipLaunchKernelGGL((k_adj_rk4<N, NU, R, false>), lanes(kp.T, kp.batch), dim3(kT), 0, s, kp,
+                         (const R*)abar, (R*)dr, (R*)bnd, (R*)wsum, (R*)ckpt, (int)ckpt_ready,
+                         (const R*)kp.F, (const R*)kp.consts + CS<N, NU>::G, (const R*)kp.Q,
+                         (const R*)nullptr);
     return hipGetLastError();
   }
   static hipError_t finish(const KProb& kp, const void* bnd, void* dr, const void* wsum, void* dQ,

@@ -359,6 +359,10 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
                           padt(d->T))
                    : nullptr;
     if (w) w->ckpt = ck;
+    // G(t) = L(t) R^{-1} L(t)^T at every sample, when L is sampled
+    void* gs = d->L_sampled ? take(es * B * (size_t)(2L * d->n_steps * d->T + 1) * nx * nx)
+                            : nullptr;
+    if (w) w->gsamp = gs;
     if (w) {
       w->lam = lam;
       w->bnd = bnd;
@@ -1006,8 +1010,6 @@ lqt_status lqt_backward(const lqt_dims* dims, const lqt_problem* prob, const voi
                         void* dr, void* dx0, void* dQf, void* drf, void* ws, size_t ws_bytes,
                         hipStream_t stream) {
   LQT_TRY(check_supported(dims));
-  if (dims->F_sampled || dims->L_sampled || dims->has_c)
-    return fail(LQT_EUNSUPPORTED, "lqt_backward needs constant F and L and c = 0");
   const AdjOps* ao = adj_ops(dims->nx, dims->nu, dims->dtype);
   if (!ao || use_wave(dims))
     return fail(LQT_EUNSUPPORTED, "lqt_backward is available in FP64 for nx <= 4");
@@ -1051,7 +1053,7 @@ lqt_status lqt_backward(const lqt_dims* dims, const lqt_problem* prob, const voi
     LQT_HIP(ao->cong_down(kp, w.cmap[l], t.n[l], w.cpart[l], w.cst[l + 1], t.n[l + 1], w.cst[l], s));
   // element gradients, then the RK4 adjoint of every block and the reductions
   LQT_HIP(ao->elem(kp, w.elts, S, v, x, w.lam, w.cst[1], t.n[1], dQf, drf, s));
-  LQT_HIP(ao->rk4(kp, w.elts, dr, w.bnd, w.wsum, w.ckpt, w.ckpt != nullptr, s));
+  LQT_HIP(ao->rk4(kp, w.elts, dr, w.bnd, w.wsum, w.ckpt, w.ckpt != nullptr, w.gsamp, s));
   LQT_HIP(ao->finish(kp, w.bnd, dr, w.wsum, dQ, dR, s));
   const long nb = dims->batch, nx = dims->nx, nu = dims->nu;
   const long ns = 2L * dims->n_steps * dims->T + 1;

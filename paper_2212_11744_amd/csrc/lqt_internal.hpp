@@ -123,6 +123,7 @@ struct Work {
   void* tx[kMaxLevels + 1] = {};     // trajectory tree: x at left ends of level-l nodes
   void* tpart[kMaxLevels + 1] = {};  // trajectory tree: lane partials above level l
   void* elts = nullptr;              // elements when the caller gives none (lqt_solve)
+  void* gsamp = nullptr;             // adjoint with sampled L: G(t) at every sample
   unsigned* wq_done = nullptr;       // wave path: status words and counter of the queue solve
   long wq_words = 0;
   void* bmap = nullptr;              // wave path, solve: every block's map ([batch][T][nx^2 + nx])
@@ -214,7 +215,7 @@ struct AdjOps {
                      hipStream_t);
   // ckpt_ready: the step start values are already in ckpt (written by Ops::build_ckpt)
   hipError_t (*rk4)(const KProb&, const void* abar, void* dr, void* bnd, void* wsum, void* ckpt,
-                    bool ckpt_ready, hipStream_t);
+                    bool ckpt_ready, void* gsamp, hipStream_t);
   hipError_t (*finish)(const KProb&, const void* bnd, void* dr, const void* wsum, void* dQ,
                        void* dR, hipStream_t);
 };

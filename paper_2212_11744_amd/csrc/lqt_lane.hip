@@ -854,7 +854,7 @@ __global__ __launch_bounds__(kThreads) void k_build(const KProb kp, R* __restric
 // Element build that also keeps the start values (A - I, eta, J) of steps 1 .. n - 1 of every
 // block for the RK4 adjoint: layout [problem][step - 1][value][padt(T)], values in the order
 // A - I (row-major), eta, J (packed upper), so a wave's stores of one value are coalesced.
-template <int N, int NU, class R>
+template <int N, int NU, class R, bool CONST_COEF>
 __global__ __launch_bounds__(kThreads) void k_build_ckpt(const KProb kp, R* __restrict__ elts,
                                                           R* __restrict__ ckpt) {
   constexpr int SL = N * N + N + Sym<N>::size;
@@ -876,8 +876,8 @@ __global__ __launch_bounds__(kThreads) void k_build_ckpt(const KProb kp, R* __re
     for (int i = 0; i < Sym<N>::size; ++i) c[(N * N + N + i) * st] = J[i];
   };
   Tup<N, R> out;
-  build_block_rs<N, NU, R, true>(kp, blk_plain(kp, p, k), RMem<N, R>{(const R*)kp.r}, out, kp.n,
-                                 keep);
+  build_block_rs<N, NU, R, CONST_COEF>(kp, blk_plain(kp, p, k), RMem<N, R>{(const R*)kp.r}, out,
+                                       kp.n, keep);
   tup_store(out, elts + (long)p * Lay<N>::NE * padt(kp.T), k);
 }
 
@@ -2103,8 +2103,12 @@ struct L {
     return hipGetLastError();
   }
   static hipError_t build_ckpt(const KProb& kp, void* elts, void* ckpt, hipStream_t s) {
-    hipLaunchKernelGGL((k_build_ckpt<N, NU, R>), grid_lanes(kp.T, kp.batch), dim3(kThreads), 0,
-                       s, kp, (R*)elts, (R*)ckpt);
+    if (!kp.F_sampled && !kp.L_sampled && !kp.has_c)
+      hipLaunchKernelGGL((k_build_ckpt<N, NU, R, true>), grid_lanes(kp.T, kp.batch),
+                         dim3(kThreads), 0, s, kp, (R*)elts, (R*)ckpt);
+    else
+      hipLaunchKernelGGL((k_build_ckpt<N, NU, R, false>), grid_lanes(kp.T, kp.batch),
+                         dim3(kThreads), 0, s, kp, (R*)elts, (R*)ckpt);
     return hipGetLastError();
   }
   static hipError_t lti_prep(const KProb& kp, void* tab, hipStream_t s) {

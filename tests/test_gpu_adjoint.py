@@ -1,5 +1,6 @@
 """GPU adjoint (lqt_backward) vs the oracle: its sequential adjoint (tape), its exact JVP (dual
-numbers) along random directions, and central differences of the GPU forward pass.
+numbers) along random directions, and central differences of the GPU forward pass; constant and
+sampled F(t), L(t), with and without a drift c(t).
 
 Gradients of Q, R, Qf are symmetric (derivative for symmetric perturbations), so the oracle's
 entrywise gradients are symmetrised before comparison.  Tolerance: 1e-9 normwise against the
@@ -132,8 +133,54 @@ def test_autograd_function_and_central_differences():
         assert abs(ad - fd) <= tol * max(1.0, abs(fd)), (name, ad, fd)
 
 
-def test_backward_rejects_sampled_dynamics():
-    p = W.random_stable(1, nx=2, nu=1, T=8, n=2, time_varying=True)
+def _sampled(kind, nx, nu, T, n, seed):
+    """F(t) sampled (random stable time-varying), L(t) sampled, a drift c(t), or all three."""
+    p = W.random_stable(seed, nx=nx, nu=nu, T=T, n=n, tf=0.02 * T + 0.5,
+                        time_varying=kind in ("F", "all"))
+    ts = W.half_step_times(p.t, p.n)
+    rng = np.random.default_rng(seed)
+    if kind in ("L", "all"):
+        p.L = np.asarray(p.L)[None] * (1.0 + 0.3 * np.sin(1.7 * ts))[:, None, None]
+    if kind in ("c", "all"):
+        p.c = 0.3 * np.cos(0.9 * ts)[:, None] * rng.standard_normal(nx)[None]
+    return p
+
+
+@pytest.mark.parametrize("kind", ["F", "L", "c", "all"])
+@pytest.mark.parametrize("nx,nu,T", [(4, 2, 37), (3, 3, 20), (2, 1, 65)])
+def test_adjoint_sampled_coefficients_against_tape(kind, nx, nu, T):
+    """Sampled F(t), sampled L(t) (R enters through G(t) = L(t) R^-1 L(t)^T sample by sample), a
+    drift c(t), and all three: every gradient against the oracle's sequential adjoint (tape),
+    entrywise, 1e-9 normwise."""
+    p = _sampled(kind, nx, nu, T, 3, 70 + T)
+    Wt = np.random.default_rng(T).standard_normal((T + 1, nx))
+    _, go = O.objective_grad(p, Wt)
+    g = _gpu_grads([p], [Wt])
+    for k, ref in (("Q", _sym(go["Q"])), ("R", _sym(go["R"])), ("Qf", _sym(go["Qf"])),
+                   ("rf", go["rf"]), ("x0", go["x0"]), ("r", go["r"])):
+        e = relerr(_np(g[k][0]), ref)
+        assert e < 1e-9, f"{kind} nx={nx} nu={nu} d{k}: {e:.3e}"
+
+
+def test_adjoint_sampled_all_batch_against_dual_jvp():
+    """All three time-varying inputs, two problems of T = 1500 in one batch: <grad, d> against the
+    oracle's exact directional derivative along random (symmetric) directions."""
+    probs = [_sampled("all", 4, 2, 1500, 4, 90 + i) for i in range(2)]
+    rng = np.random.default_rng(11)
+    Ws = [rng.standard_normal((1501, 4)) for _ in probs]
+    g = _gpu_grads(probs, Ws)
+    for b, p in enumerate(probs):
+        for name in ("Q", "R", "r", "x0", "Qf", "rf"):
+            d = rng.standard_normal(np.shape(getattr(p, name)))
+            if name in ("Q", "R", "Qf"):
+                d = d + d.T
+            _, df = O.objective_jvp(p, Ws[b], {name: d})
+            got = float(np.sum(_np(g[name][b]) * d))
+            assert abs(got - df) <= 1e-9 * max(1.0, abs(df)), (b, name, got, df)
+
+
+def test_backward_refuses_unsupported_sizes():
+    p = W.random_stable(1, nx=5, nu=2, T=8, n=2, time_varying=True)
     dp = lqt.DeviceProblem.from_problems([p])
     out = lqt.solve(dp)
     with pytest.raises(lqt.LQTError) as ei:
