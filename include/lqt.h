@@ -241,7 +241,7 @@ lqt_status lqt_solve_noalloc(const lqt_dims *dims, const lqt_problem *prob, void
  * workspace, not read.  Structure: a reverse affine scan for the state adjoint
  * lambda_k = dLdx_k + Psi_k^T lambda_{k+1}, a forward scan for the value adjoints (the linear
  * parts compose like the trajectory maps), per-block gradients of the combination rule
- * (Lemma 7) and the discrete adjoint of each block's RK4 steps.  FP64 only, nx <= 4
+ * (Lemma 7) and the discrete adjoint of each block's RK4 steps.  FP64 or FP32, nx <= 4
  * (LQT_EUNSUPPORTED otherwise); F and L constant or sampled, with or without a drift c (F, L, c
  * are not differentiated; with sampled L, R enters through G(t) = L(t) R^{-1} L(t)^T at every
  * sample, and the workspace holds G at every sample). */

@@ -1519,7 +1519,7 @@ const AdjOps* adj_for(int nx, int nu) {
 }  // namespace
 
 const AdjOps* adj_ops(int nx, int nu, int dtype) {
-  return dtype == 0 ? adj_for<double>(nx, nu) : nullptr;
+  return dtype == 0 ? adj_for<double>(nx, nu) : adj_for<float>(nx, nu);
 }
 
 }  // namespace lqt

@@ -1012,7 +1012,7 @@ lqt_status lqt_backward(const lqt_dims* dims, const lqt_problem* prob, const voi
   LQT_TRY(check_supported(dims));
   const AdjOps* ao = adj_ops(dims->nx, dims->nu, dims->dtype);
   if (!ao || use_wave(dims))
-    return fail(LQT_EUNSUPPORTED, "lqt_backward is available in FP64 for nx <= 4");
+    return fail(LQT_EUNSUPPORTED, "lqt_backward is available for nx <= 4");
   LQT_TRY(check_problem(dims, prob, true, true));
   const size_t es = dsize(dims->dtype);
   LQT_TRY(check_ptr(S, "S", es));

@@ -31,10 +31,10 @@ def _sym(a):
     return 0.5 * (a + np.swapaxes(a, -1, -2))
 
 
-def _gpu_grads(probs, W_list):
-    dp = lqt.DeviceProblem.from_problems(probs)
+def _gpu_grads(probs, W_list, dtype=torch.float64):
+    dp = lqt.DeviceProblem.from_problems(probs, dtype=dtype)
     out = lqt.solve(dp)
-    dLdx = torch.as_tensor(np.stack(W_list), device="cuda")
+    dLdx = torch.as_tensor(np.stack(W_list), device="cuda", dtype=dtype)
     return lqt.backward(dp, out["S"], out["v"], out["x"], dLdx)
 
 
@@ -177,6 +177,23 @@ def test_adjoint_sampled_all_batch_against_dual_jvp():
             _, df = O.objective_jvp(p, Ws[b], {name: d})
             got = float(np.sum(_np(g[name][b]) * d))
             assert abs(got - df) <= 1e-9 * max(1.0, abs(df)), (b, name, got, df)
+
+
+@pytest.mark.parametrize("kind", ["const", "all"])
+def test_adjoint_fp32(kind):
+    """FP32 adjoint (constant coefficients; sampled F, L with a drift) against the oracle's FP64
+    sequential adjoint, 1e-4 normwise."""
+    if kind == "const":
+        p = W.point_mass(31, 60, 4, tf=2.0)
+    else:
+        p = _sampled("all", 4, 2, 45, 3, 33)
+    Wt = np.random.default_rng(8).standard_normal((p.T + 1, p.nx))
+    _, go = O.objective_grad(p, Wt)
+    g = _gpu_grads([p], [Wt], dtype=torch.float32)
+    for k, ref in (("Q", _sym(go["Q"])), ("R", _sym(go["R"])), ("Qf", _sym(go["Qf"])),
+                   ("rf", go["rf"]), ("x0", go["x0"]), ("r", go["r"])):
+        e = relerr(_np(g[k][0]), ref)
+        assert e < 1e-4, f"{kind} d{k}: {e:.3e}"
 
 
 def test_backward_refuses_unsupported_sizes():
