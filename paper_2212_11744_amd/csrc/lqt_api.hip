@@ -89,15 +89,18 @@ Tree plan_tree(long T) {
   return t;
 }
 
-// Wave-path trees: n[0] = T, n[l + 1] = ceil(n[l] / wc) while n[l] > wc.
+// Wave-path trees: n[0] = T, n[l + 1] = ceil(n[l] / wcs[l]) while n[l] > wcs[l], with
+// wcs[0] = wc and kWaveUpperChunk above.
 WTree wave_tree(long T, int wc) {
   WTree t;
   t.wc = wc;
+  for (int l = 0; l <= kMaxLevels; ++l) t.wcs[l] = l == 0 ? wc : kWaveUpperChunk;
   t.n[0] = T;
   t.n[1] = (T + wc - 1) / wc;
   t.levels = 1;
-  while (t.n[t.levels] > wc && t.levels < kMaxLevels) {
-    t.n[t.levels + 1] = (t.n[t.levels] + wc - 1) / wc;
+  while (t.n[t.levels] > t.wcs[t.levels] && t.levels < kMaxLevels) {
+    const int b = t.wcs[t.levels];
+    t.n[t.levels + 1] = (t.n[t.levels] + b - 1) / b;
     ++t.levels;
   }
   return t;
@@ -133,7 +136,7 @@ bool wave_queue(const WTree& t, long batch, const Work& w, WQueue* q) {
   if (t.levels > kWqMaxLevels || !w.wq_done) return false;
   const int L = t.levels;
   q->levels = L;
-  q->wc = t.wc;
+  for (int l = 0; l <= L; ++l) q->wcs[l] = t.wcs[l];
   for (int l = 0; l <= L; ++l) q->n[l] = t.n[l];
   for (int l = 1; l <= L; ++l) {
     q->vtup[l] = w.vtup[l];

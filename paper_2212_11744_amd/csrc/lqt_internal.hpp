@@ -243,22 +243,27 @@ const Ops* lane_ops_shard(int nx, int nu, int dtype);
 const Ops* lane_ops(int nx, int nu, int dtype);
 
 // Wavefront-per-tuple path (lqt_wave.hip) for any nx <= 16: one wavefront per block or tree
-// node, matrices in LDS.  Its trees reduce `wc` nodes per wave at every level: n[0] = T,
-// n[l + 1] = ceil(n[l] / wc) while n[l] > wc.  Tree nodes are records ([batch][n[l]][record]):
+// node, matrices in LDS.  Its trees reduce wcs[l] nodes per wave at level l: n[0] = T,
+// n[l + 1] = ceil(n[l] / wcs[l]) while n[l] > wcs[l] (wcs[0] = wc, above kWaveUpperChunk).  Tree nodes are records ([batch][n[l]][record]):
 // tuples (NE values, element order), values (S full, v: nx^2 + nx), maps (P = Psi - I, q:
 // nx^2 + nx), states (nx).
 struct WTree {
   int levels = 0;
-  int wc = 8;
+  int wc = 8;                     // blocks per wave at the bottom (= wcs[0])
+  int wcs[kMaxLevels + 1] = {};   // wcs[l]: nodes of level l per node of level l + 1
   long n[kMaxLevels + 1] = {};
 };
+// Upper levels branch by kWaveUpperChunk whatever the bottom chunk: their node counts are small,
+// so the serial chain of a wave (wcs[l] combinations or folds) is what they cost.
+constexpr int kWaveUpperChunk = 4;
 WTree wave_tree(long T, int wc);
 // The wave path's solve after the element build in one launch over a work queue: the stages of
 // the two trees (4 levels + 1 of them) and where their items start; done: one status word per
 // item, then the item counter (total + 1 words, zero before the launch).
 constexpr int kWqMaxLevels = 16;
 struct WQueue {
-  int levels = 0, wc = 0, nst = 0;
+  int levels = 0, nst = 0;
+  int wcs[kWqMaxLevels + 1] = {};  // branching of every level (WTree::wcs)
   long total = 0;
   long n[kWqMaxLevels + 1] = {};      // nodes per problem at level l (n[0] = T)
   long start[4 * kWqMaxLevels + 1] = {};

@@ -6,8 +6,9 @@
 //
 // Elements use the tiled layout of the C ABI; tree nodes are records ([batch][n][NQ]) with the
 // element's value order: A - I (nx*nx, row-major), b, C (upper triangle, row by row), eta, J.
-// Scans: every wave reduces `wc` consecutive nodes serially (wc chosen at run time); level l + 1
-// has ceil(n_l / wc) nodes while n_l > wc; the top (<= wc nodes) is swept by one wave.
+// Scans: every wave reduces wcs[l] consecutive nodes of level l serially (the bottom chunk chosen at
+// run time, upper levels kWaveUpperChunk); level l + 1 has ceil(n_l / wcs[l]) nodes while
+// n_l > wcs[l]; the top (<= wcs[L] nodes) is swept by one wave.
 #include <cstring>
 
 #include "../../include/lqt.h"
@@ -2018,7 +2019,8 @@ __global__ __launch_bounds__(64) void kw_solve_queue(const KProb kp, const WQueu
   if (it >= q.total) return;
   int s = 0;
   while (s + 1 < q.nst && q.start[s + 1] <= it) ++s;
-  const long B = kp.batch, L = q.levels, wc = q.wc;
+  const long B = kp.batch, L = q.levels;
+  auto wcs = [&](long lv) { return (long)q.wcs[lv]; };  // nodes of level lv per node of lv + 1
   const int p = (int)((it - q.start[s]) % B);
   const long i = (it - q.start[s]) / B;
   // stage index of each kind (see the order above)
@@ -2042,11 +2044,13 @@ __global__ __launch_bounds__(64) void kw_solve_queue(const KProb kp, const WQueu
   const long l = q.level[s];
   const R* e = elts;
   switch (kind) {
-    case kWqVRed:
-      if (l > 1) wait(st_vred(l - 1), i * wc, min(i * wc + wc, q.n[l - 1]));
-      wb_vreduce<N, DevAcc>(sh, &piv, p, i, (int)wc, l == 1, l == 1 ? e : (const R*)q.vtup[l - 1],
+    case kWqVRed: {  // node i of level l from nodes i wcs(l - 1) .. of level l - 1
+      const long b = wcs(l - 1);
+      if (l > 1) wait(st_vred(l - 1), i * b, min(i * b + b, q.n[l - 1]));
+      wb_vreduce<N, DevAcc>(sh, &piv, p, i, (int)b, l == 1, l == 1 ? e : (const R*)q.vtup[l - 1],
                             q.n[l - 1], (R*)q.vtup[l], q.n[l]);
       break;
+    }
     case kWqVTop:
       wait(st_vred(L), 0, q.n[L]);
       wb_vtop<N, DevAcc>(sh, &piv, kp, p, (const R*)q.vtup[L], q.n[L], (R*)q.vval[L]);
@@ -2055,23 +2059,25 @@ __global__ __launch_bounds__(64) void kw_solve_queue(const KProb kp, const WQueu
       if (l + 1 == L)
         wait(st_vtop, 0, 1);
       else
-        wait(st_vdown(l + 1), i / wc, i / wc + 1);
-      wb_vdown<N, DevAcc>(sh, &piv, p, i, (int)wc, (const R*)q.vtup[l], q.n[l],
+        wait(st_vdown(l + 1), i / wcs(l + 1), i / wcs(l + 1) + 1);
+      wb_vdown<N, DevAcc>(sh, &piv, p, i, (int)wcs(l), (const R*)q.vtup[l], q.n[l],
                           (const R*)q.vval[l + 1], q.n[l + 1], (R*)q.vval[l]);
       break;
     case kWqVBot:
       if (L == 1)
         wait(st_vtop, 0, 1);
       else
-        wait(st_vdown(1), i / wc, i / wc + 1);
-      wb_vbottom<N, DevAcc>(sh, &piv, kp, p, i, (int)wc, e, (const R*)q.vval[1], q.n[1], S, v,
+        wait(st_vdown(1), i / wcs(1), i / wcs(1) + 1);
+      wb_vbottom<N, DevAcc>(sh, &piv, kp, p, i, (int)wcs(0), e, (const R*)q.vval[1], q.n[1], S, v,
                             (R*)q.tmap[1], (R*)q.bmap);
       break;
-    case kWqTRed:
-      wait(l == 2 ? st_vbot : st_tred(l - 1), i * wc, min(i * wc + wc, q.n[l - 1]));
-      wb_treduce<N, DevAcc>(sh, p, i, (int)wc, (const R*)q.tmap[l - 1], q.n[l - 1], (R*)q.tmap[l],
+    case kWqTRed: {
+      const long b = wcs(l - 1);
+      wait(l == 2 ? st_vbot : st_tred(l - 1), i * b, min(i * b + b, q.n[l - 1]));
+      wb_treduce<N, DevAcc>(sh, p, i, (int)b, (const R*)q.tmap[l - 1], q.n[l - 1], (R*)q.tmap[l],
                             q.n[l]);
       break;
+    }
     case kWqTTop:
       wait(L == 1 ? st_vbot : st_tred(L), 0, q.n[L]);
       wb_ttop<N, DevAcc>(sh, kp, p, (const R*)q.tmap[L], q.n[L], (R*)q.tx[L]);
@@ -2080,16 +2086,16 @@ __global__ __launch_bounds__(64) void kw_solve_queue(const KProb kp, const WQueu
       if (l + 1 == L)
         wait(st_ttop, 0, 1);
       else
-        wait(st_tdown(l + 1), i / wc, i / wc + 1);
-      wb_tdown<N, DevAcc>(sh, p, i, (int)wc, (const R*)q.tmap[l], q.n[l], (const R*)q.tx[l + 1],
-                          q.n[l + 1], (R*)q.tx[l]);
+        wait(st_tdown(l + 1), i / wcs(l + 1), i / wcs(l + 1) + 1);
+      wb_tdown<N, DevAcc>(sh, p, i, (int)wcs(l), (const R*)q.tmap[l], q.n[l],
+                          (const R*)q.tx[l + 1], q.n[l + 1], (R*)q.tx[l]);
       break;
     case kWqTBot:
       if (L == 1)
         wait(st_ttop, 0, 1);
       else
-        wait(st_tdown(1), i / wc, i / wc + 1);
-      wb_tbottom<N, DevAcc>(sh, &piv, kp, p, i, (int)wc, e, S, v, (const R*)q.tx[1], q.n[1], x, u,
+        wait(st_tdown(1), i / wcs(1), i / wcs(1) + 1);
+      wb_tbottom<N, DevAcc>(sh, &piv, kp, p, i, (int)wcs(0), e, S, v, (const R*)q.tx[1], q.n[1], x, u,
                             (const R*)q.bmap);
       break;
   }
@@ -2129,13 +2135,13 @@ hipError_t wave_value_t(const KProb& kp, const WTree& t, const Work& w, const vo
   hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, n, wc, 1,
                      (const R*)elts, t.n[0], (R*)w.vtup[1], t.n[1]);
   for (int l = 1; l < t.levels; ++l)
-    hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
-                       0, (const R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1], t.n[l + 1]);
+    hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n,
+                       t.wcs[l], 0, (const R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1], t.n[l + 1]);
   hipLaunchKernelGGL((kw_vtop<N, R>), dim3(1, kp.batch), b, 0, s, kp, (const R*)w.vtup[t.levels],
                      t.n[t.levels], (R*)w.vval[t.levels]);
   for (int l = t.levels - 1; l >= 1; --l)
-    hipLaunchKernelGGL((kw_vdown<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
-                       (const R*)w.vtup[l], t.n[l], (const R*)w.vval[l + 1], t.n[l + 1],
+    hipLaunchKernelGGL((kw_vdown<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n,
+                       t.wcs[l], (const R*)w.vtup[l], t.n[l], (const R*)w.vval[l + 1], t.n[l + 1],
                        (R*)w.vval[l]);
   hipLaunchKernelGGL((kw_vbottom<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
                      (const R*)elts, (const R*)w.vval[1], t.n[1], (R*)S, (R*)v, (R*)maps1,
@@ -2153,13 +2159,13 @@ hipError_t wave_traj_t(const KProb& kp, const WTree& t, const Work& w, const voi
     hipLaunchKernelGGL((kw_tbottom_reduce<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp,
                        wc, (const R*)elts, (const R*)S, (const R*)v, (R*)w.tmap[1], t.n[1]);
   for (int l = 1; l < t.levels; ++l)
-    hipLaunchKernelGGL((kw_treduce<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
-                       (const R*)w.tmap[l], t.n[l], (R*)w.tmap[l + 1], t.n[l + 1]);
+    hipLaunchKernelGGL((kw_treduce<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n,
+                       t.wcs[l], (const R*)w.tmap[l], t.n[l], (R*)w.tmap[l + 1], t.n[l + 1]);
   hipLaunchKernelGGL((kw_ttop<N, R>), dim3(1, kp.batch), b, 0, s, kp, (const R*)w.tmap[t.levels],
                      t.n[t.levels], (R*)w.tx[t.levels]);
   for (int l = t.levels - 1; l >= 1; --l)
-    hipLaunchKernelGGL((kw_tdown<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n, wc,
-                       (const R*)w.tmap[l], t.n[l], (const R*)w.tx[l + 1], t.n[l + 1],
+    hipLaunchKernelGGL((kw_tdown<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n,
+                       t.wcs[l], (const R*)w.tmap[l], t.n[l], (const R*)w.tx[l + 1], t.n[l + 1],
                        (R*)w.tx[l]);
   hipLaunchKernelGGL((kw_tbottom<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
                      (const R*)elts, (const R*)S, (const R*)v, (const R*)w.tx[1], t.n[1], (R*)x,

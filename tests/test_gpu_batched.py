@@ -181,11 +181,12 @@ def test_batched_mix_full_size():
 
 
 @pytest.mark.parametrize("Ts", [(1, 2), (20, 30), (100, 130), (300, 257, 500), (4000, 3000, 2500)],
-                         ids=["one-node", "one-level", "two-level", "three-level", "four-level"])
+                         ids=["L1", "L2", "L3", "L4", "L6"])
 def test_wave_class_queue_tree_depths(Ts):
-    """One wave-path class (nx = 6) in the single queue launch, with trees of 1 to 4 levels
-    (8 nodes per wave; rows = sum of T_i + 1: 5 and 52 give one level, 232 two, 1060 three, 9503
-    four): every member against the oracle and against lqt_solve alone."""
+    """One wave-path class (nx = 6) in the single queue launch, with trees of 1 to 6 levels
+    (8 blocks per wave at the bottom, 4 nodes per wave above; rows = sum of T_i + 1: 5 give one
+    level, 52 two, 232 three, 1060 four, 9503 six): every member against the oracle and against
+    lqt_solve alone."""
     probs = [W.random_stable(40 + i, 6, 3, T, 2, 0.0, 0.004 * T + 0.1, time_varying=False)
              for i, T in enumerate(Ts)]
     bs = lqt.BatchedSolve(probs, plan=False)
