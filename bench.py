@@ -339,8 +339,16 @@ def nx16_leg(torch, lqt, W, reps):
     out = lqt.solve(dp, ws=ws)
     torch.cuda.synchronize()
     ms = _events_time(lambda: lqt.solve(dp, out, ws), reps, torch)
+    wsb = lqt.workspace(dp, lqt.CALL_BUILD)
+    e = lqt.build_elements(dp, ws=wsb)
+    builds = {}
+    for name, f in (("theorem8", lqt.build_elements), ("theorem9", lqt.build_elements_forward),
+                    ("split", lqt.build_elements_split)):
+        f(dp, e, wsb)
+        torch.cuda.synchronize()
+        builds[name] = _events_time(lambda f=f: f(dp, e, wsb), reps, torch)
     return {"workload": f"random stable time-varying LQT nx=16 nu=4, T={T} x 4 RK4 steps, FP64",
-            "ms": ms, "sub_intervals_per_s": T / (ms * 1e-3)}
+            "ms": ms, "sub_intervals_per_s": T / (ms * 1e-3), "build_ms": builds}
 
 
 def batched_leg(torch, lqt, W, reps):

@@ -153,7 +153,8 @@ lqt_status lqt_build_elements(const lqt_dims *dims, const lqt_problem *prob, voi
  * + 1 (stages 2, 3), + 2 (stage 4).  Both theorems describe the same conditional value function,
  * so the two builds agree to the order of RK4 (O(h^4) per block), not to rounding.  Same
  * arguments and layout as lqt_build_elements (workspace LQT_CALL_BUILD; lqt_dims.lti ignored);
- * nx <= 4 (LQT_EUNSUPPORTED otherwise). */
+ * 1 <= nx <= 16 (per-lane kernels up to nx = 4, one wavefront per block above); a plain batch
+ * (no ragged members). */
 lqt_status lqt_build_elements_forward(const lqt_dims *dims, const lqt_problem *prob, void *elts,
                                       void *ws, size_t ws_bytes, hipStream_t stream);
 
@@ -161,11 +162,11 @@ lqt_status lqt_build_elements_forward(const lqt_dims *dims, const lqt_problem *p
  * forward ODEs of Theorem 9 over the first m RK4 steps give V(., t_k; ., tau), tau = t_k + m h_k
  * (the steps of lqt_build_elements_forward), the backward ODEs of Theorem 8 over the last
  * n_steps - m steps give V(., tau; ., t_{k+1}) (the steps of lqt_build_elements), and Lemma 7
- * joins them.  The two parts of a block are integrated at the same time by two wavefronts, so the
- * span of the build is about halved (useful when T is small).  Agrees with lqt_build_elements to
- * the order of RK4; equal up to rounding for n_steps = 1.  Same arguments and layout as
- * lqt_build_elements (workspace LQT_CALL_BUILD; lqt_dims.lti ignored); nx <= 4
- * (LQT_EUNSUPPORTED otherwise). */
+ * joins them.  For nx <= 4 the two parts of a block are integrated at the same time by two
+ * wavefronts, so the span of the build is about halved (useful when T is small); for nx 5 .. 16
+ * one wavefront per block integrates them one after the other.  Agrees with lqt_build_elements
+ * to the order of RK4; equal up to rounding for n_steps = 1.  Same arguments and layout as
+ * lqt_build_elements (workspace LQT_CALL_BUILD; lqt_dims.lti ignored); 1 <= nx <= 16. */
 lqt_status lqt_build_elements_split(const lqt_dims *dims, const lqt_problem *prob, void *elts,
                                     void *ws, size_t ws_bytes, hipStream_t stream);
 

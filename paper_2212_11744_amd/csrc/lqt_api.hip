@@ -180,6 +180,16 @@ hipError_t wave_build(const KProb& kp, int dtype, void* elts, hipStream_t s) {
   return f ? f->build(kp, elts, s) : hipErrorInvalidValue;
 }
 
+hipError_t wave_build_fwd(const KProb& kp, int dtype, void* elts, hipStream_t s) {
+  const WaveFns* f = wave_fns(kp.nx, dtype);
+  return f ? f->build_fwd(kp, elts, s) : hipErrorInvalidValue;
+}
+
+hipError_t wave_build_split(const KProb& kp, int dtype, void* elts, hipStream_t s) {
+  const WaveFns* f = wave_fns(kp.nx, dtype);
+  return f ? f->build_split(kp, elts, s) : hipErrorInvalidValue;
+}
+
 hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
                       void* S, void* v, void* maps1, hipStream_t s) {
   const WaveFns* f = wave_fns(kp.nx, dtype);
@@ -706,15 +716,16 @@ lqt_status lqt_build_elements(const lqt_dims* dims, const lqt_problem* prob, voi
 lqt_status lqt_build_elements_forward(const lqt_dims* dims, const lqt_problem* prob, void* elts,
                                       void* ws, size_t ws_bytes, hipStream_t stream) {
   LQT_TRY(check_supported(dims));
-  if (use_wave(dims))
-    return fail(LQT_EUNSUPPORTED, "the forward element build is available for nx <= 4");
   LQT_TRY(check_problem(dims, prob, true, false));
   LQT_TRY(check_ptr(elts, "elts", dsize(dims->dtype)));
   Work w;
   LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w, stream));
   KProb kp = make_kprob(dims, prob, w.consts);
   LQT_HIP(prep(dims, kp, w.consts, stream));
-  LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build_fwd(kp, elts, stream));
+  if (use_wave(dims))
+    LQT_HIP(wave_build_fwd(kp, dims->dtype, elts, stream));
+  else
+    LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build_fwd(kp, elts, stream));
   LQT_TRY(finite_check(dims, w, stream, {{elts, 0, true}}));
   return ok();
 }
@@ -722,15 +733,16 @@ lqt_status lqt_build_elements_forward(const lqt_dims* dims, const lqt_problem* p
 lqt_status lqt_build_elements_split(const lqt_dims* dims, const lqt_problem* prob, void* elts,
                                     void* ws, size_t ws_bytes, hipStream_t stream) {
   LQT_TRY(check_supported(dims));
-  if (use_wave(dims))
-    return fail(LQT_EUNSUPPORTED, "the split-block element build is available for nx <= 4");
   LQT_TRY(check_problem(dims, prob, true, false));
   LQT_TRY(check_ptr(elts, "elts", dsize(dims->dtype)));
   Work w;
   LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w, stream));
   KProb kp = make_kprob(dims, prob, w.consts);
   LQT_HIP(prep(dims, kp, w.consts, stream));
-  LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build_split(kp, elts, stream));
+  if (use_wave(dims))
+    LQT_HIP(wave_build_split(kp, dims->dtype, elts, stream));
+  else
+    LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->build_split(kp, elts, stream));
   LQT_TRY(finite_check(dims, w, stream, {{elts, 0, true}}));
   return ok();
 }

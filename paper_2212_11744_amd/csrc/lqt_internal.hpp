@@ -288,10 +288,14 @@ struct WaveFns {
   // both trees in one launch (q.done cleared)
   hipError_t (*solve_queue)(const KProb&, const WQueue& q, const void* elts, void* S, void* v,
                             void* x, void* u, hipStream_t);
+  hipError_t (*build_fwd)(const KProb&, void* elts, hipStream_t);    // Theorem 9
+  hipError_t (*build_split)(const KProb&, void* elts, hipStream_t);  // split blocks
 };
 template <int S>
 const WaveFns* wave_fns_shard(int nx, int dtype);
 hipError_t wave_build(const KProb& kp, int dtype, void* elts, hipStream_t s);
+hipError_t wave_build_fwd(const KProb& kp, int dtype, void* elts, hipStream_t s);
+hipError_t wave_build_split(const KProb& kp, int dtype, void* elts, hipStream_t s);
 hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
                       void* S, void* v, void* maps1, hipStream_t s);
 hipError_t wave_traj(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,

@@ -620,37 +620,40 @@ WDEV void w_separator(const KProb& kp, int i, WT<R> y, int n) {
   wsync();
 }
 
+// Where block k's data sits: problem p, sample offset s0 (sample j of the block at
+// s0 + 2 n k + j), left end t[tk], constant F of problem pf.
+struct WBlk {
+  int p;
+  long s0, tk, pf;
+};
+
+WDEV WBlk wblk_plain(const KProb& kp, int p, long k) {
+  return {p, (long)p * (2L * kp.n * kp.T + 1), (long)p * (kp.T + 1) + k, 0};
+}
+
+// Scratch of a one-wave element build beside its three tuples: 8 n^2 + 5 n values.
+template <int N>
+constexpr int kBuildScr = 8 * N * N + 5 * N;
+
+// The last `nsteps` RK4 steps of Theorem 8 on block k, backward from t_{k+1}: y holds the
+// element of [t_{k+1} - m h, t_{k+1}] after step m (start from the identity for a full build).
+// ac and st are tuple scratch, scr kBuildScr<N> values.
 template <int N, class R>
-__global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ elts) {
-  constexpr int NM = N, kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
-  __shared__ R sh[3 * kTupW + 8 * NM * NM + 4 * NM];
+WDEV void wb_bwd_steps(const KProb& kp, const WBlk& bk, long k, int nsteps, WT<R> y, WT<R> ac,
+                       WT<R> st, R* scr) {
+  constexpr int NM = N;
   constexpr int n = N;
   const int nu = kp.nu;
-  const long T = kp.T;
   const int nn = kp.n;
-  const long k = blockIdx.x;
-  // Problem p, sample offset s0 (sample j of the block at s0 + 2 n k + j), left end t[tk].
-  int p = blockIdx.y;
-  long s0 = (long)p * (2L * nn * T + 1), tk = (long)p * (T + 1) + k, pf = 0;
-  WT<R> y = wt_at(sh, n), ac = wt_at(sh + kTupW, n), st = wt_at(sh + 2 * kTupW, n);
-  if (kp.seg) {
-    p = seg_find(kp.seg, kp.nseg, k);
-    if (k == kp.seg[p + 1] - 1 || k == T - 1) {
-      w_separator(kp, p, y, n);
-      wt_store(y, elt_ref(elts, 0, k, T, ne_w(n)), n);
-      return;
-    }
-    s0 = (long)p * (1 - 2L * nn);
-    tk = k;
-    pf = p;
-  }
+  const int p = bk.p;
+  const long s0 = bk.s0, tk = bk.tk, pf = bk.pf;
   const R* t = (const R*)kp.t + tk;
   const R* r = (const R*)kp.r;
   const R* Fc = (const R*)kp.F + pf * n * n;  // constant F (per problem when ragged)
   const R* cb = kp.has_c ? (const R*)kp.c : nullptr;
   const R* Qp = (const R*)kp.Q + (long)p * n * n;
   const R* cs = (const R*)kp.consts + (long)p * consts_count(n, nu);
-  R* F = sh + 3 * kTupW;
+  R* F = scr;
   R* G = F + NM * NM;
   R* K = G + NM * NM;
   R* Lc = K + NM * NM;  // n x nu
@@ -662,9 +665,8 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
   R* ke = kb + NM;
   R* rv = ke + NM;
   R* cv = rv + NM;
-  wt_identity(y, n);
   const R h = (t[1] - t[0]) / R(nn);
-  for (int m = 0; m < nn; ++m) {
+  for (int m = 0; m < nsteps; ++m) {
     const long j1 = 2L * nn * k + 2L * (nn - m);
     w_copy(st.A, y.A, n * n);
     w_copy(st.e, y.e, n);
@@ -778,7 +780,206 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
     w_copy(y.e, ac.e, n);
     w_copy(y.J, ac.J, n * n);
   }
-  wt_store(y, elt_ref(elts, kp.seg ? 0 : p, k, T, ne_w(n)), n);
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ elts) {
+  constexpr int kTupW = 3 * N * N + 2 * N;
+  __shared__ R sh[3 * kTupW + kBuildScr<N>];
+  constexpr int n = N;
+  const long T = kp.T;
+  const long k = blockIdx.x;
+  WBlk bk = wblk_plain(kp, blockIdx.y, k);
+  WT<R> y = wt_at(sh, n), ac = wt_at(sh + kTupW, n), st = wt_at(sh + 2 * kTupW, n);
+  if (kp.seg) {
+    const int p = seg_find(kp.seg, kp.nseg, k);
+    if (k == kp.seg[p + 1] - 1 || k == T - 1) {
+      w_separator(kp, p, y, n);
+      wt_store(y, elt_ref(elts, 0, k, T, ne_w(n)), n);
+      return;
+    }
+    bk = {p, (long)p * (1 - 2L * kp.n), k, p};
+  }
+  wt_identity(y, n);
+  wb_bwd_steps<N, R>(kp, bk, k, kp.n, y, ac, st, sh + 3 * kTupW);
+  wt_store(y, elt_ref(elts, kp.seg ? 0 : bk.p, k, T, ne_w(n)), n);
+}
+
+// ------------------------------------------------------------------------------------------
+// Element build from the forward conditional ODEs (Theorem 9, Sec. IV-C), one wave per block:
+// with M = F - C Q and A = I + Ad, dAd/dtau = M + M Ad, db/dtau = M b + (F - M) r + c and
+// dC/dtau = G + M C + C F^T, integrated by RK4 forward in tau from t_k; eta and J enter no
+// right-hand side, so their increments w + Ad^T w (w = Q (r - b)) and P + Ad^T P
+// (P = Q (I + Ad)) are added to them directly.  Samples: stage 1 at 2 n k + 2 m, stages 2 and 3
+// at + 1, stage 4 at + 2.  Full matrices in LDS as in the Theorem 8 build; C and J take their
+// upper entries after every stage (the exact derivatives are symmetric).
+// ------------------------------------------------------------------------------------------
+// The first `nsteps` steps of block k: y holds the element of [t_k, t_k + m h] after step m
+// (start from the identity).  ac and st are tuple scratch (their e and J unused), scr
+// kBuildScr<N> values.
+template <int N, class R>
+WDEV void wb_fwd_steps(const KProb& kp, const WBlk& bk, long k, int nsteps, WT<R> y, WT<R> ac,
+                       WT<R> st, R* scr) {
+  constexpr int n = N;
+  const int nu = kp.nu;
+  const int nn = kp.n;
+  const int p = bk.p;
+  const long s0 = bk.s0;
+  const R* t = (const R*)kp.t + bk.tk;
+  const R* r = (const R*)kp.r;
+  const R* Fc = (const R*)kp.F + bk.pf * n * n;
+  const R* cb = kp.has_c ? (const R*)kp.c : nullptr;
+  const R* Qp = (const R*)kp.Q + (long)p * n * n;
+  const R* cs = (const R*)kp.consts + (long)p * consts_count(n, nu);
+  R* F = scr;
+  R* G = F + N * N;
+  R* Lc = G + N * N;  // n x nu
+  R* Qs = Lc + N * N;
+  R* M = Qs + N * N;
+  R* P = M + N * N;
+  R* kC = P + N * N;
+  R* X = kC + N * N;  // kJ, then kA
+  R* rv = X + N * N;
+  R* cv = rv + N;
+  R* wv = cv + N;
+  R* kb = wv + N;
+  R* ke = kb + N;
+  for (int e = lane_id(); e < n * n; e += 64) Qs[e] = Qp[e];
+  if (!kp.L_sampled) {
+    for (int e = lane_id(); e < n * n; e += 64) G[e] = cs[consts_off_G(n, nu) + e];
+  }
+  wsync();
+  const R h = (t[1] - t[0]) / R(nn);
+  for (int m = 0; m < nsteps; ++m) {
+    const long j0 = 2L * nn * k + 2L * m;
+    w_copy(st.A, y.A, n * n);
+    w_copy(st.b, y.b, n);
+    w_copy(st.C, y.C, n * n);
+    for (int s = 0; s < 4; ++s) {
+      const long j = s == 0 ? j0 : (s == 3 ? j0 + 2 : j0 + 1);
+      const R wk = (s == 0 || s == 3) ? h / R(6) : h / R(3);
+      const R cn = s == 2 ? h : h / R(2);
+      const R* Fj = kp.F_sampled ? (const R*)kp.F + (s0 + j) * n * n : Fc;
+      for (int e = lane_id(); e < n * n; e += 64) F[e] = Fj[e];
+      for (int i = lane_id(); i < n; i += 64) {
+        rv[i] = r[(s0 + j) * n + i];
+        cv[i] = cb ? cb[(s0 + j) * n + i] : R(0);
+      }
+      if (kp.L_sampled) {
+        const R* Lj = (const R*)kp.L + (s0 + j) * n * nu;
+        const R* W = cs + consts_off_W(n, nu);
+        for (int e = lane_id(); e < n * nu; e += 64) {
+          const int i = e / nu, l = e % nu;
+          R a = R(0);
+          for (int q2 = 0; q2 < nu; ++q2) a = fma(Lj[i * nu + q2], W[q2 * nu + l], a);
+          Lc[e] = a;
+        }
+        wsync();
+        w_gemm<kMfma<N, R>>(G, Lc, Lc, n, nu, n, false, true, R(1), R(0));
+      } else {
+        wsync();
+      }
+      // M = F - C Q
+      w_copy(M, F, n * n);
+      w_gemm<kMfma<N, R>>(M, st.C, Qs, n, n, n, false, false, R(-1), R(1));
+      // eta increment: w = Q (r - b), w + Ad^T w
+      for (int i = lane_id(); i < n; i += 64) {
+        R a = R(0);
+        for (int l = 0; l < n; ++l) a = fma(Qs[i * n + l], rv[l] - st.b[l], a);
+        wv[i] = a;
+      }
+      wsync();
+      for (int i = lane_id(); i < n; i += 64) {
+        R a = wv[i];
+        for (int l = 0; l < n; ++l) a = fma(st.A[l * n + i], wv[l], a);
+        ke[i] = a;
+      }
+      // J increment: P = Q + Q Ad, P + Ad^T P
+      w_copy(P, Qs, n * n);
+      w_gemm<kMfma<N, R>>(P, Qs, st.A, n, n, n, false, false, R(1), R(1));
+      w_copy(X, P, n * n);
+      w_gemm<kMfma<N, R>>(X, st.A, P, n, n, n, true, false, R(1), R(1));
+      for (int e = lane_id(); e < n * n; e += 64) {
+        const int i = e / n, q2 = e % n;
+        y.J[e] = fma(wk, X[(i < q2 ? i : q2) * n + (i < q2 ? q2 : i)], y.J[e]);
+      }
+      for (int i = lane_id(); i < n; i += 64) y.e[i] = fma(wk, ke[i], y.e[i]);
+      // kb = M b + (F - M) r + c
+      for (int i = lane_id(); i < n; i += 64) {
+        R a = cv[i];
+        for (int l = 0; l < n; ++l) {
+          a = fma(M[i * n + l], st.b[l], a);
+          a = fma(F[i * n + l] - M[i * n + l], rv[l], a);
+        }
+        kb[i] = a;
+      }
+      // kC = G + M C + C F^T
+      w_copy(kC, G, n * n);
+      w_gemm<kMfma<N, R>>(kC, M, st.C, n, n, n, false, false, R(1), R(1));
+      w_gemm<kMfma<N, R>>(kC, st.C, F, n, n, n, false, true, R(1), R(1));
+      // kA = M + M Ad
+      w_copy(X, M, n * n);
+      w_gemm<kMfma<N, R>>(X, M, st.A, n, n, n, false, false, R(1), R(1));
+      // accumulate and form the next stage input
+      for (int e = lane_id(); e < n * n; e += 64) {
+        const int i = e / n, q2 = e % n;
+        const R c = kC[(i < q2 ? i : q2) * n + (i < q2 ? q2 : i)];
+        ac.A[e] = s == 0 ? fma(wk, X[e], y.A[e]) : fma(wk, X[e], ac.A[e]);
+        ac.C[e] = s == 0 ? fma(wk, c, y.C[e]) : fma(wk, c, ac.C[e]);
+        if (s < 3) {
+          st.A[e] = fma(cn, X[e], y.A[e]);
+          st.C[e] = fma(cn, c, y.C[e]);
+        }
+      }
+      for (int i = lane_id(); i < n; i += 64) {
+        ac.b[i] = s == 0 ? fma(wk, kb[i], y.b[i]) : fma(wk, kb[i], ac.b[i]);
+        if (s < 3) st.b[i] = fma(cn, kb[i], y.b[i]);
+      }
+      wsync();
+    }
+    w_copy(y.A, ac.A, n * n);
+    w_copy(y.b, ac.b, n);
+    w_copy(y.C, ac.C, n * n);
+  }
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_build_fwd(const KProb kp, R* __restrict__ elts) {
+  constexpr int kTupW = 3 * N * N + 2 * N;
+  __shared__ R sh[3 * kTupW + kBuildScr<N>];
+  const long k = blockIdx.x;
+  const WBlk bk = wblk_plain(kp, blockIdx.y, k);
+  WT<R> y = wt_at(sh, N), ac = wt_at(sh + kTupW, N), st = wt_at(sh + 2 * kTupW, N);
+  wt_identity(y, N);
+  wb_fwd_steps<N, R>(kp, bk, k, kp.n, y, ac, st, sh + 3 * kTupW);
+  wt_store(y, elt_ref(elts, bk.p, k, kp.T, ne_w(N)), N);
+}
+
+// ------------------------------------------------------------------------------------------
+// Element build with every block split at tau = t_k + floor(n/2) h (Sec. IV-D): Theorem 9 gives
+// the element of [t_k, tau], Theorem 8 that of [tau, t_{k+1}], and Lemma 7 joins them.  One wave
+// per block does the two parts one after the other: with a wave per block the launch already
+// holds T waves, so the halved span of a block buys no occupancy here; the total work is that
+// of a full build plus one combination.
+// ------------------------------------------------------------------------------------------
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_build_split(const KProb kp, R* __restrict__ elts) {
+  constexpr int kTupW = 3 * N * N + 2 * N;
+  static_assert(4 * N * N + N * (2 * N + 1) + 2 * N <= kBuildScr<N>, "combination scratch");
+  __shared__ R sh[4 * kTupW + kBuildScr<N>];
+  __shared__ int piv[N];
+  const long k = blockIdx.x;
+  const int m = kp.n / 2;
+  const WBlk bk = wblk_plain(kp, blockIdx.y, k);
+  WT<R> f = wt_at(sh, N), y = wt_at(sh + kTupW, N), ac = wt_at(sh + 2 * kTupW, N),
+        st = wt_at(sh + 3 * kTupW, N);
+  R* scr = sh + 4 * kTupW;
+  wt_identity(f, N);
+  wt_identity(y, N);
+  wb_fwd_steps<N, R>(kp, bk, k, m, f, ac, st, scr);
+  wb_bwd_steps<N, R>(kp, bk, k, kp.n - m, y, ac, st, scr);
+  w_combine<N>(f, y, y, ws_at(scr, piv, N), N);
+  wt_store(y, elt_ref(elts, bk.p, k, kp.T, ne_w(N)), N);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2128,6 +2329,20 @@ hipError_t wave_build_t(const KProb& kp, void* elts, hipStream_t s) {
 }
 
 template <int N, class R>
+hipError_t wave_build_fwd_t(const KProb& kp, void* elts, hipStream_t s) {
+  hipLaunchKernelGGL((kw_build_fwd<N, R>), dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
+                     (R*)elts);
+  return hipGetLastError();
+}
+
+template <int N, class R>
+hipError_t wave_build_split_t(const KProb& kp, void* elts, hipStream_t s) {
+  hipLaunchKernelGGL((kw_build_split<N, R>), dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
+                     (R*)elts);
+  return hipGetLastError();
+}
+
+template <int N, class R>
 hipError_t wave_value_t(const KProb& kp, const WTree& t, const Work& w, const void* elts, void* S,
                         void* v, void* maps1, hipStream_t s) {
   const int n = N, wc = t.wc;
@@ -2190,8 +2405,9 @@ template <int N, class R>
 struct Fns {
   static const WaveFns* get() {
     if constexpr (wave_shard(N, sizeof(R) == 4) == LQT_SHARD) {
-      static const WaveFns f = {wave_build_t<N, R>, wave_value_t<N, R>, wave_traj_t<N, R>,
-                                wave_solve_queue_t<N, R>};
+      static const WaveFns f = {wave_build_t<N, R>,       wave_value_t<N, R>,
+                                wave_traj_t<N, R>,        wave_solve_queue_t<N, R>,
+                                wave_build_fwd_t<N, R>,   wave_build_split_t<N, R>};
       return &f;
     } else {
       return nullptr;
