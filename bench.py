@@ -347,8 +347,29 @@ def nx16_leg(torch, lqt, W, reps):
         f(dp, e, wsb)
         torch.cuda.synchronize()
         builds[name] = _events_time(lambda f=f: f(dp, e, wsb), reps, torch)
+    e = lqt.build_elements(dp, e, wsb)
+    ws2 = lqt.workspace(dp, lqt.CALL_TRAJ_METHOD2)
+    x2, u2 = lqt.forward_traj_method2(dp, e, out["S"], out["v"], ws=ws2)
+    m2 = lambda: lqt.forward_traj_method2(dp, e, out["S"], out["v"], x2, u2, ws=ws2)
+    torch.cuda.synchronize()
+    ms_m2 = _events_time(m2, reps, torch)
+    d = lqt.dense_output(dp, out["S"], out["v"], out["x"], ws=wsb)
+    dense = lambda: lqt.dense_output(dp, out["S"], out["v"], out["x"], out=d, ws=wsb)
+    torch.cuda.synchronize()
+    ms_dense = _events_time(dense, reps, torch)
+    # time-invariant variant (F = F0 constant): general build vs the tabulated one
+    pti = W.random_stable(3, nx=16, nu=4, T=T, n=4, time_varying=False)
+    lti_ms = {}
+    for name, flag in (("general", False), ("lti", True)):
+        dpt = lqt.DeviceProblem.from_problems([pti], lti=flag)
+        wst = lqt.workspace(dpt, lqt.CALL_BUILD)
+        et = lqt.build_elements(dpt, ws=wst)
+        torch.cuda.synchronize()
+        lti_ms[name] = _events_time(lambda: lqt.build_elements(dpt, et, wst), reps, torch)
     return {"workload": f"random stable time-varying LQT nx=16 nu=4, T={T} x 4 RK4 steps, FP64",
-            "ms": ms, "sub_intervals_per_s": T / (ms * 1e-3), "build_ms": builds}
+            "ms": ms, "sub_intervals_per_s": T / (ms * 1e-3), "build_ms": builds,
+            "method2_ms": ms_m2, "dense_output_ms": ms_dense,
+            "time_invariant_build_ms": lti_ms}
 
 
 def batched_leg(torch, lqt, W, reps):

@@ -102,8 +102,8 @@ typedef struct lqt_dims {
                         references to tabulate those linear maps, and forms each block's b, eta
                         as weighted sums of its samples (same results as the general build up to
                         rounding).  Requires F_sampled = L_sampled = has_c = 0 (LQT_EINVAL
-                        otherwise); used by lqt_build_elements and lqt_solve for nx <= 4 and
-                        ignored otherwise.  0: general path.                                    */
+                        otherwise); used by lqt_build_elements and lqt_solve (every nx; the
+                        batched solve uses the general build).  0: general path.                */
 } lqt_dims;
 
 typedef struct lqt_problem {
@@ -188,8 +188,8 @@ lqt_status lqt_forward_traj(const lqt_dims *dims, const lqt_problem *prob, const
  * conditional value function on [t_0, t_k] the prefix a_0 (x) ... (x) a_{k-1} (Lemma 7) and
  * V(., t_k) from S_k, v_k:  x_k = (I + C S_k)^{-1} (A x0 + b + C v_k) for the prefix's A, b, C,
  * computed by a forward parallel scan; u_k as in lqt_forward_traj.  Agrees with lqt_forward_traj
- * up to rounding.  Same arguments (workspace LQT_CALL_TRAJ_METHOD2); nx <= 4 (LQT_EUNSUPPORTED
- * otherwise). */
+ * up to rounding.  Same arguments (workspace LQT_CALL_TRAJ_METHOD2); 1 <= nx <= 16 (per-lane
+ * trees up to nx = 4, one wavefront per tree node above); a plain batch. */
 lqt_status lqt_forward_traj_method2(const lqt_dims *dims, const lqt_problem *prob,
                                     const void *elts, const void *S, const void *v, void *x,
                                     void *u, void *ws, size_t ws_bytes, hipStream_t stream);
@@ -205,7 +205,8 @@ lqt_status lqt_forward_traj_method2(const lqt_dims *dims, const lqt_problem *pro
  * x = (I + C S)^{-1} (A x_k + b + C v) (Sec. IV-E); u = -R^{-1} L^T (S x - v) with L at sample 2 x
  * node.  Outputs (device, caller-allocated): Sd [batch][n T + 1][nx*nx] (full symmetric),
  * vd and xd [batch][n T + 1][nx], ud [batch][n T + 1][nu] (may be NULL).  Reads prob->{t, F, L,
- * c, Q, R, r}.  ws: LQT_CALL_BUILD bytes.  nx <= 4 (LQT_EUNSUPPORTED otherwise). */
+ * c, Q, R, r}.  ws: LQT_CALL_BUILD bytes.  1 <= nx <= 16 (one lane per block up to nx = 4, one
+ * wavefront per block above); a plain batch. */
 lqt_status lqt_dense_output(const lqt_dims *dims, const lqt_problem *prob, const void *S,
                             const void *v, const void *x, void *Sd, void *vd, void *xd, void *ud,
                             void *ws, size_t ws_bytes, hipStream_t stream);

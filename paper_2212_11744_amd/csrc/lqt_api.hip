@@ -190,6 +190,26 @@ hipError_t wave_build_split(const KProb& kp, int dtype, void* elts, hipStream_t 
   return f ? f->build_split(kp, elts, s) : hipErrorInvalidValue;
 }
 
+hipError_t wave_method2(const KProb& kp, int dtype, const WTree& t, const Work& w,
+                        const void* elts, const void* S, const void* v, void* x, void* u,
+                        hipStream_t s) {
+  const WaveFns* f = wave_fns(kp.nx, dtype);
+  return f ? f->method2(kp, t, w, elts, S, v, x, u, s) : hipErrorInvalidValue;
+}
+
+hipError_t wave_lti(const KProb& kp, int dtype, void* tab, void* elts, hipStream_t s) {
+  const WaveFns* f = wave_fns(kp.nx, dtype);
+  if (!f) return hipErrorInvalidValue;
+  const hipError_t e = f->lti_prep(kp, tab, s);
+  return e != hipSuccess ? e : f->lti_build(kp, tab, elts, s);
+}
+
+hipError_t wave_dense(const KProb& kp, int dtype, const void* S, const void* v, const void* x,
+                      void* Sd, void* vd, void* xd, void* ud, hipStream_t s) {
+  const WaveFns* f = wave_fns(kp.nx, dtype);
+  return f ? f->dense(kp, S, v, x, Sd, vd, xd, ud, s) : hipErrorInvalidValue;
+}
+
 hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
                       void* S, void* v, void* maps1, hipStream_t s) {
   const WaveFns* f = wave_fns(kp.nx, dtype);
@@ -248,7 +268,7 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
   if (w) w->consts = consts;
   void* fl = take(256);  // finite-check flag (taken here: the wave branch below returns early)
   if (w) w->flag = (int*)fl;
-  if (d->lti && !use_wave(d) && (call == LQT_CALL_BUILD || call == LQT_CALL_SOLVE)) {
+  if (d->lti && (call == LQT_CALL_BUILD || call == LQT_CALL_SOLVE)) {
     void* t = take(es * nconsts * lti_count(d->nx, d->n_steps));
     if (w) w->lti = t;
   }
@@ -274,6 +294,10 @@ size_t layout(const lqt_dims* d, lqt_call call, char* base, Work* w, int wc, lon
           w->tmap[l] = a;
           w->tx[l] = b;
         }
+      }
+      if (call == LQT_CALL_TRAJ_METHOD2) {  // prefix records of the nodes
+        void* a = take(es * B * ne_of(d->nx) * t.n[l]);
+        if (w) w->vpart[l] = a;
       }
     }
     if (call == LQT_CALL_SOLVE && ws_elts) {
@@ -701,7 +725,10 @@ lqt_status lqt_build_elements(const lqt_dims* dims, const lqt_problem* prob, voi
   KProb kp = make_kprob(dims, prob, w.consts);
   LQT_HIP(prep(dims, kp, w.consts, stream));
   if (use_wave(dims)) {
-    LQT_HIP(wave_build(kp, dims->dtype, elts, stream));
+    if (dims->lti)
+      LQT_HIP(wave_lti(kp, dims->dtype, w.lti, elts, stream));
+    else
+      LQT_HIP(wave_build(kp, dims->dtype, elts, stream));
   } else if (dims->lti) {
     const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
     LQT_HIP(o->lti_prep(kp, w.lti, stream));
@@ -751,7 +778,6 @@ lqt_status lqt_forward_traj_method2(const lqt_dims* dims, const lqt_problem* pro
                                     const void* elts, const void* S, const void* v, void* x,
                                     void* u, void* ws, size_t ws_bytes, hipStream_t stream) {
   LQT_TRY(check_supported(dims));
-  if (use_wave(dims)) return fail(LQT_EUNSUPPORTED, "the Method 2 trajectory is available for nx <= 4");
   const size_t es = dsize(dims->dtype);
   if (!prob) return fail(LQT_EINVAL, "problem is NULL");
   LQT_TRY(check_ptr(prob->L, "L", es));
@@ -765,6 +791,14 @@ lqt_status lqt_forward_traj_method2(const lqt_dims* dims, const lqt_problem* pro
   Work w;
   LQT_TRY(check_ws(dims, LQT_CALL_TRAJ_METHOD2, ws, ws_bytes, &w, stream));
   KProb kp = make_kprob(dims, prob, w.consts);
+  const long nb = dims->batch, T1 = (long)dims->T + 1;
+  if (use_wave(dims)) {
+    LQT_HIP(prep(dims, kp, w.consts, stream));
+    LQT_HIP(wave_method2(kp, dims->dtype, wtree_for(dims), w, elts, S, v, x, u, stream));
+    LQT_TRY(finite_check(dims, w, stream,
+                         {{x, nb * T1 * dims->nx, false}, {u, nb * T1 * dims->nu, false}}));
+    return ok();
+  }
   const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
   const Tree t = tree_for(dims);
   LQT_HIP(o->prep(kp, w.consts, stream));
@@ -776,7 +810,6 @@ lqt_status lqt_forward_traj_method2(const lqt_dims* dims, const lqt_problem* pro
     LQT_HIP(o->m2_down(kp, w.vtup[l], t.n[l], w.vpart[l], w.vval[l + 1], t.n[l + 1], w.vval[l],
                        stream));
   LQT_HIP(o->m2_bottom(kp, elts, S, v, w.vval[1], t.n[1], x, u, stream));
-  const long nb = dims->batch, T1 = (long)dims->T + 1;
   LQT_TRY(finite_check(dims, w, stream, {{x, nb * T1 * dims->nx, false}, {u, nb * T1 * dims->nu, false}}));
   return ok();
 }
@@ -785,7 +818,6 @@ lqt_status lqt_dense_output(const lqt_dims* dims, const lqt_problem* prob, const
                             const void* v, const void* x, void* Sd, void* vd, void* xd, void* ud,
                             void* ws, size_t ws_bytes, hipStream_t stream) {
   LQT_TRY(check_supported(dims));
-  if (use_wave(dims)) return fail(LQT_EUNSUPPORTED, "values inside the blocks are available for nx <= 4");
   LQT_TRY(check_problem(dims, prob, true, false));
   const size_t es = dsize(dims->dtype);
   LQT_TRY(check_ptr(S, "S", es));
@@ -798,9 +830,11 @@ lqt_status lqt_dense_output(const lqt_dims* dims, const lqt_problem* prob, const
   Work w;
   LQT_TRY(check_ws(dims, LQT_CALL_BUILD, ws, ws_bytes, &w, stream));
   KProb kp = make_kprob(dims, prob, w.consts);
-  const Ops* o = lane_ops(dims->nx, dims->nu, dims->dtype);
-  LQT_HIP(o->prep(kp, w.consts, stream));
-  LQT_HIP(o->dense(kp, S, v, x, Sd, vd, xd, ud, stream));
+  LQT_HIP(prep(dims, kp, w.consts, stream));
+  if (use_wave(dims))
+    LQT_HIP(wave_dense(kp, dims->dtype, S, v, x, Sd, vd, xd, ud, stream));
+  else
+    LQT_HIP(lane_ops(dims->nx, dims->nu, dims->dtype)->dense(kp, S, v, x, Sd, vd, xd, ud, stream));
   const long nb = dims->batch, nodes = (long)dims->n_steps * dims->T + 1, nx = dims->nx;
   LQT_TRY(finite_check(dims, w, stream, {{Sd, nb * nodes * nx * nx, false}, {vd, nb * nodes * nx, false},
                                          {xd, nb * nodes * nx, false}, {ud, nb * nodes * dims->nu, false}}));
@@ -876,7 +910,10 @@ lqt_status run_solve(const lqt_dims* dims, const KProb& kp, const Work& w, void*
   LQT_HIP(prep(dims, kprep, w.consts, stream));
   if (use_wave(dims)) {
     const WTree wt = wave_tree(dims->T, o.wave_chunk);
-    LQT_HIP(wave_build(kp, dims->dtype, e, stream));
+    if (kp.lti && !kp.seg && w.lti)
+      LQT_HIP(wave_lti(kp, dims->dtype, w.lti, e, stream));
+    else
+      LQT_HIP(wave_build(kp, dims->dtype, e, stream));
     WQueue q;
     if (o.queue_chunk && wave_queue(wt, kp.batch, w, &q)) {
       hipLaunchKernelGGL(k_lb_clear, dim3((unsigned)min((w.wq_words + 255) / 256, 1024L)),

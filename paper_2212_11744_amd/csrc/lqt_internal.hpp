@@ -290,12 +290,26 @@ struct WaveFns {
                             void* x, void* u, hipStream_t);
   hipError_t (*build_fwd)(const KProb&, void* elts, hipStream_t);    // Theorem 9
   hipError_t (*build_split)(const KProb&, void* elts, hipStream_t);  // split blocks
+  // Method 2 trajectory (node products in w.vtup, prefix records in w.vpart)
+  hipError_t (*method2)(const KProb&, const WTree&, const Work&, const void* elts, const void* S,
+                        const void* v, void* x, void* u, hipStream_t);
+  hipError_t (*dense)(const KProb&, const void* S, const void* v, const void* x, void* Sd,
+                      void* vd, void* xd, void* ud, hipStream_t);  // values inside the blocks
+  // time-invariant path: the table of a problem (lti_count values), then the elements
+  hipError_t (*lti_prep)(const KProb&, void* tab, hipStream_t);
+  hipError_t (*lti_build)(const KProb&, const void* tab, void* elts, hipStream_t);
 };
 template <int S>
 const WaveFns* wave_fns_shard(int nx, int dtype);
 hipError_t wave_build(const KProb& kp, int dtype, void* elts, hipStream_t s);
 hipError_t wave_build_fwd(const KProb& kp, int dtype, void* elts, hipStream_t s);
 hipError_t wave_build_split(const KProb& kp, int dtype, void* elts, hipStream_t s);
+hipError_t wave_method2(const KProb& kp, int dtype, const WTree& t, const Work& w,
+                        const void* elts, const void* S, const void* v, void* x, void* u,
+                        hipStream_t s);
+hipError_t wave_lti(const KProb& kp, int dtype, void* tab, void* elts, hipStream_t s);
+hipError_t wave_dense(const KProb& kp, int dtype, const void* S, const void* v, const void* x,
+                      void* Sd, void* vd, void* xd, void* ud, hipStream_t s);
 hipError_t wave_value(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,
                       void* S, void* v, void* maps1, hipStream_t s);
 hipError_t wave_traj(const KProb& kp, int dtype, const WTree& t, const Work& w, const void* elts,

@@ -637,10 +637,12 @@ constexpr int kBuildScr = 8 * N * N + 5 * N;
 
 // The last `nsteps` RK4 steps of Theorem 8 on block k, backward from t_{k+1}: y holds the
 // element of [t_{k+1} - m h, t_{k+1}] after step m (start from the identity for a full build).
-// ac and st are tuple scratch, scr kBuildScr<N> values.
-template <int N, class R>
+// ac and st are tuple scratch, scr kBuildScr<N> values.  IMP: the reference is the unit impulse
+// at sample imp_j of the problem, component imp_i, instead of the problem's r (the
+// time-invariant path tabulates the response of b and eta to each sample this way).
+template <int N, class R, bool IMP = false>
 WDEV void wb_bwd_steps(const KProb& kp, const WBlk& bk, long k, int nsteps, WT<R> y, WT<R> ac,
-                       WT<R> st, R* scr) {
+                       WT<R> st, R* scr, long imp_j = -1, int imp_i = 0) {
   constexpr int NM = N;
   constexpr int n = N;
   const int nu = kp.nu;
@@ -678,7 +680,7 @@ WDEV void wb_bwd_steps(const KProb& kp, const WBlk& bk, long k, int nsteps, WT<R
       const R* Fj = kp.F_sampled ? (const R*)kp.F + (s0 + j) * n * n : Fc;
       for (int e = lane_id(); e < n * n; e += 64) F[e] = Fj[e];
       for (int i = lane_id(); i < n; i += 64) {
-        rv[i] = r[(s0 + j) * n + i];
+        rv[i] = IMP ? (j == imp_j && i == imp_i ? R(1) : R(0)) : r[(s0 + j) * n + i];
         cv[i] = cb ? cb[(s0 + j) * n + i] : R(0);
       }
       if (kp.L_sampled) {
@@ -806,6 +808,74 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
 }
 
 // ------------------------------------------------------------------------------------------
+// Time-invariant path (F, L constant, c = 0, uniform grid).  The RK4 recursion of Theorem 8 for
+// A, C, J does not involve r, so every block has the same A, C, J, and b, eta are linear in the
+// block's samples r_0 .. r_2n: b = sum_j V_j r_j, eta = sum_j W_j r_j.  kw_lti_prep integrates
+// block 0 once per unit impulse (sample j0, component i0; one wave each) to tabulate column i0 of
+// V_j0 and W_j0, and A, C, J; kw_build_lti forms every block's element from the table.
+// Table of a problem: A - I (n^2, full), C and J (packed upper, the element's order), then
+// V_0 .. V_2n and W_0 .. W_2n (n^2 each, row-major).
+// ------------------------------------------------------------------------------------------
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_lti_prep(const KProb kp, R* __restrict__ tab) {
+  constexpr int n = N, kTupW = 3 * N * N + 2 * N, ns = N * (N + 1) / 2;
+  __shared__ R sh[3 * kTupW + kBuildScr<N>];
+  const int p = blockIdx.y;
+  const long m = blockIdx.x;
+  const long j0 = m / n;
+  const int i0 = (int)(m % n);
+  WT<R> y = wt_at(sh, n), ac = wt_at(sh + kTupW, n), st = wt_at(sh + 2 * kTupW, n);
+  wt_identity(y, n);
+  wb_bwd_steps<N, R, true>(kp, wblk_plain(kp, p, 0), 0, kp.n, y, ac, st, sh + 3 * kTupW, j0, i0);
+  R* tp = tab + (long)p * lti_count(n, kp.n);
+  R* V = tp + lti_off_V(n) + j0 * n * n;
+  R* W = tp + lti_off_W(n, kp.n) + j0 * n * n;
+  for (int a = lane_id(); a < n; a += 64) {
+    V[a * n + i0] = y.b[a];
+    W[a * n + i0] = y.e[a];
+  }
+  if (m == 0) {
+    for (int e = lane_id(); e < n * n; e += 64) {
+      const int i = e / n, j = e % n;
+      tp[e] = y.A[e];
+      if (i <= j) {
+        tp[n * n + pk(i, j, n)] = y.C[e];
+        tp[n * n + ns + pk(i, j, n)] = y.J[e];
+      }
+    }
+  }
+}
+
+// One wave per block: A, C, J copied from the table, b and eta summed over the block's samples
+// (lane 2 a + w: row a of V (w = 0) or W (w = 1)).
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_build_lti(const KProb kp, const R* __restrict__ tab,
+                                                   R* __restrict__ elts) {
+  constexpr int n = N, ns = N * (N + 1) / 2;
+  const int p = blockIdx.y;
+  const long k = blockIdx.x;
+  const int nn = kp.n;
+  const long T = kp.T;
+  const R* tp = tab + (long)p * lti_count(n, nn);
+  const GRef<R> g = elt_ref(elts, p, k, T, ne_w(n));
+  const int oB = n * n, oC = oB + n, oE = oC + ns, oJ = oE + n;
+  for (int q = lane_id(); q < n * n + 2 * ns; q += 64) {
+    const int dst = q < n * n ? q : (q < n * n + ns ? oC + (q - n * n) : oJ + (q - n * n - ns));
+    g.g[dst * g.st] = tp[q];
+  }
+  const int l = lane_id();
+  if (l < 2 * n) {
+    const int a = l >> 1, w = l & 1;
+    const R* Mt = tp + (w ? lti_off_W(n, nn) : lti_off_V(n)) + a * n;
+    const R* rp = (const R*)kp.r + ((long)p * (2L * nn * T + 1) + 2L * nn * k) * n;
+    R acc = R(0);
+    for (int j = 0; j <= 2 * nn; ++j)
+      for (int i = 0; i < n; ++i) acc = fma(Mt[(long)j * n * n + i], rp[j * n + i], acc);
+    g.g[((w ? oE : oB) + a) * g.st] = acc;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
 // Element build from the forward conditional ODEs (Theorem 9, Sec. IV-C), one wave per block:
 // with M = F - C Q and A = I + Ad, dAd/dtau = M + M Ad, db/dtau = M b + (F - M) r + c and
 // dC/dtau = G + M C + C F^T, integrated by RK4 forward in tau from t_k; eta and J enter no
@@ -817,9 +887,15 @@ __global__ __launch_bounds__(64) void kw_build(const KProb kp, R* __restrict__ e
 // The first `nsteps` steps of block k: y holds the element of [t_k, t_k + m h] after step m
 // (start from the identity).  ac and st are tuple scratch (their e and J unused), scr
 // kBuildScr<N> values.
-template <int N, class R>
+// EJ = false leaves eta and J alone (the state formula of Method 2 needs A, b, C only); step(m)
+// runs after step m, with y holding the parts on [t_k, t_k + (m + 1) h].
+struct WNoStep {
+  WDEV void operator()(int) const {}
+};
+
+template <int N, class R, bool EJ = true, class STEP = WNoStep>
 WDEV void wb_fwd_steps(const KProb& kp, const WBlk& bk, long k, int nsteps, WT<R> y, WT<R> ac,
-                       WT<R> st, R* scr) {
+                       WT<R> st, R* scr, const STEP& step = STEP{}) {
   constexpr int n = N;
   const int nu = kp.nu;
   const int nn = kp.n;
@@ -882,28 +958,30 @@ WDEV void wb_fwd_steps(const KProb& kp, const WBlk& bk, long k, int nsteps, WT<R
       // M = F - C Q
       w_copy(M, F, n * n);
       w_gemm<kMfma<N, R>>(M, st.C, Qs, n, n, n, false, false, R(-1), R(1));
-      // eta increment: w = Q (r - b), w + Ad^T w
-      for (int i = lane_id(); i < n; i += 64) {
-        R a = R(0);
-        for (int l = 0; l < n; ++l) a = fma(Qs[i * n + l], rv[l] - st.b[l], a);
-        wv[i] = a;
+      if constexpr (EJ) {
+        // eta increment: w = Q (r - b), w + Ad^T w
+        for (int i = lane_id(); i < n; i += 64) {
+          R a = R(0);
+          for (int l = 0; l < n; ++l) a = fma(Qs[i * n + l], rv[l] - st.b[l], a);
+          wv[i] = a;
+        }
+        wsync();
+        for (int i = lane_id(); i < n; i += 64) {
+          R a = wv[i];
+          for (int l = 0; l < n; ++l) a = fma(st.A[l * n + i], wv[l], a);
+          ke[i] = a;
+        }
+        // J increment: P = Q + Q Ad, P + Ad^T P
+        w_copy(P, Qs, n * n);
+        w_gemm<kMfma<N, R>>(P, Qs, st.A, n, n, n, false, false, R(1), R(1));
+        w_copy(X, P, n * n);
+        w_gemm<kMfma<N, R>>(X, st.A, P, n, n, n, true, false, R(1), R(1));
+        for (int e = lane_id(); e < n * n; e += 64) {
+          const int i = e / n, q2 = e % n;
+          y.J[e] = fma(wk, X[(i < q2 ? i : q2) * n + (i < q2 ? q2 : i)], y.J[e]);
+        }
+        for (int i = lane_id(); i < n; i += 64) y.e[i] = fma(wk, ke[i], y.e[i]);
       }
-      wsync();
-      for (int i = lane_id(); i < n; i += 64) {
-        R a = wv[i];
-        for (int l = 0; l < n; ++l) a = fma(st.A[l * n + i], wv[l], a);
-        ke[i] = a;
-      }
-      // J increment: P = Q + Q Ad, P + Ad^T P
-      w_copy(P, Qs, n * n);
-      w_gemm<kMfma<N, R>>(P, Qs, st.A, n, n, n, false, false, R(1), R(1));
-      w_copy(X, P, n * n);
-      w_gemm<kMfma<N, R>>(X, st.A, P, n, n, n, true, false, R(1), R(1));
-      for (int e = lane_id(); e < n * n; e += 64) {
-        const int i = e / n, q2 = e % n;
-        y.J[e] = fma(wk, X[(i < q2 ? i : q2) * n + (i < q2 ? q2 : i)], y.J[e]);
-      }
-      for (int i = lane_id(); i < n; i += 64) y.e[i] = fma(wk, ke[i], y.e[i]);
       // kb = M b + (F - M) r + c
       for (int i = lane_id(); i < n; i += 64) {
         R a = cv[i];
@@ -940,6 +1018,7 @@ WDEV void wb_fwd_steps(const KProb& kp, const WBlk& bk, long k, int nsteps, WT<R
     w_copy(y.A, ac.A, n * n);
     w_copy(y.b, ac.b, n);
     w_copy(y.C, ac.C, n * n);
+    step(m);
   }
 }
 
@@ -1973,6 +2052,67 @@ __global__ __launch_bounds__(64) void kw_vbottom(const KProb kp, int wc, const R
 // Trajectory tree.
 // ------------------------------------------------------------------------------------------
 
+// Gain R^{-1} L^T (nu x n, row-major) of problem pk into Kc, L at global sample s when sampled.
+template <class R>
+WDEV void w_gain(const KProb& kp, int pk, long s, R* Kc, int n, int nu) {
+  const R* cs = (const R*)kp.consts + (long)pk * consts_count(n, nu);
+  if (kp.L_sampled) {
+    const R* Lk = (const R*)kp.L + s * n * nu;
+    const R* Ri = cs + consts_off_Rinv(n, nu);
+    for (int e = lane_id(); e < nu * n; e += 64) {
+      const int l = e / n, j = e % n;
+      R a = R(0);
+      for (int q = 0; q < nu; ++q) a = fma(Ri[l * nu + q], Lk[j * nu + q], a);
+      Kc[e] = a;
+    }
+  } else {
+    for (int e = lane_id(); e < nu * n; e += 64) Kc[e] = cs[consts_off_Kc(n, nu) + e];
+  }
+  wsync();
+}
+
+// u = -Kc (S x - v) with S (full), v, x, Kc in LDS; g: n values of scratch.
+template <class R>
+WDEV void w_control(const R* Kc, const R* S, const R* v, const R* x, R* g, R* u, int n, int nu) {
+  for (int r = lane_id(); r < n; r += 64) {
+    R a = -v[r];
+    for (int j = 0; j < n; ++j) a = fma(S[r * n + j], x[j], a);
+    g[r] = a;
+  }
+  wsync();
+  for (int l = lane_id(); l < nu; l += 64) {
+    R a = R(0);
+    for (int j = 0; j < n; ++j) a = fma(-Kc[l * n + j], g[j], a);
+    u[l] = a;
+  }
+  wsync();
+}
+
+// The Method 2 state x = (I + C S)^{-1} (xk + Ad xk + b + C v) (Sec. IV-E) for the parts Ad, b, C
+// of an interval that starts at xk, and S, v at its right end; M, B: n^2 and n values of scratch.
+template <int N, class R>
+WDEV void w_m2_state(const R* Ad, const R* b, const R* C, const R* xk, const R* S, const R* v,
+                     R* M, R* B, R* x, int n) {
+  for (int e = lane_id(); e < n * n; e += 64) {
+    const int i = e / n, j = e % n;
+    R a = i == j ? R(1) : R(0);
+    for (int l = 0; l < n; ++l) a = fma(C[i * n + l], S[l * n + j], a);
+    M[e] = a;
+  }
+  for (int i = lane_id(); i < n; i += 64) {
+    R a = xk[i] + b[i];
+    for (int l = 0; l < n; ++l) {
+      a = fma(Ad[i * n + l], xk[l], a);
+      a = fma(C[i * n + l], v[l], a);
+    }
+    B[i] = a;
+  }
+  wsync();
+  w_solve<N>(M, B, n, 1, (R*)nullptr, (int*)nullptr);
+  for (int i = lane_id(); i < n; i += 64) x[i] = B[i];
+  wsync();
+}
+
 // (S_{k+1}, v_{k+1}) into LDS; zeros for the last block in ragged mode (a separator, whose map
 // does not depend on them; row T does not exist there).
 template <class A = PlainAcc, class R>
@@ -2136,19 +2276,7 @@ WDEV void wb_tbottom(R* sh, int* piv, const KProb& kp, int p, long i, int wc, co
     // Gain of the problem owning boundary k (looked up in ragged mode).
     const int pk = kp.seg ? seg_find(kp.seg, kp.nseg, k) : p;
     const long s0 = kp.seg ? (long)pk * (1 - 2L * kp.n) : (long)p * (2L * kp.n * T + 1);
-    const R* cs = (const R*)kp.consts + (long)pk * consts_count(n, nu);
-    if (kp.L_sampled) {
-      const R* Lk = (const R*)kp.L + (s0 + 2L * kp.n * k) * n * nu;
-      const R* Ri = cs + consts_off_Rinv(n, nu);
-      for (int e = lane_id(); e < nu * n; e += 64) {
-        const int l = e / n, j = e % n;
-        R s = R(0);
-        for (int q = 0; q < nu; ++q) s = fma(Ri[l * nu + q], Lk[j * nu + q], s);
-        Kc[e] = s;
-      }
-    } else {
-      for (int e = lane_id(); e < nu * n; e += 64) Kc[e] = cs[consts_off_Kc(n, nu) + e];
-    }
+    w_gain(kp, pk, s0 + 2L * kp.n * k, Kc, n, nu);
     for (int r = lane_id(); r < n; r += 64) {
       R s = -A::ld(vp + k * n + r);
       for (int j = 0; j < n; ++j) s = fma(A::ld(Sp + k * n * n + r * n + j), x[j], s);
@@ -2191,6 +2319,317 @@ __global__ __launch_bounds__(64) void kw_tbottom(const KProb kp, int wc, const R
   if ((long)blockIdx.x >= n1) return;
   wb_tbottom<N, PlainAcc>(sh, &piv, kp, blockIdx.y, blockIdx.x, wc, elts, Sg, vg, x1, n1, xout,
                           uout, bmaps);
+}
+
+// ------------------------------------------------------------------------------------------
+// Method 2 (Sec. IV-E): x_k from the prefix a_0 (x) ... (x) a_{k-1} (Lemma 7) and S_k, v_k by the
+// state formula of w_m2_state with xk = x0.  The node products of the tree are those of the value
+// scan's reduce (kw_vreduce; a product does not depend on the direction it is read in); the
+// prefix of each node (the product of every block before it) goes down the tree as a tuple
+// record, and the bottom extends each leaf's prefix block by block.
+// ------------------------------------------------------------------------------------------
+template <int N>
+struct WM2Sh {
+  static constexpr int kTupW = 3 * N * N + 2 * N, kScr = 4 * N * N + N * (2 * N + 1) + 2 * N;
+  static constexpr int sweep = 2 * kTupW + kScr;
+  static constexpr int bottom = sweep + 3 * N * N + 6 * N;
+};
+
+// Prefix records of the children j0 .. j1 - 1 of a node whose own prefix is in run: each child's
+// prefix, then run (x) child (tup: the children's products, or nullptr for the identity start).
+template <int N, class R>
+WDEV void wb_m2_sweep(R* sh, int* piv, int p, long j0, long j1, const R* tup, long n_child,
+                      R* pre, WT<R> run) {
+  constexpr int n = N;
+  const int NE = ne_w(n);
+  WT<R> a = wt_at(sh + WM2Sh<N>::kTupW, n);
+  WS<R> scr = ws_at(sh + 2 * WM2Sh<N>::kTupW, piv, n);
+  for (long j = j0; j < j1; ++j) {
+    wt_store(run, rec_ref(pre, p, j, n_child, NE), n);
+    if (j + 1 == j1) break;
+    wt_load<PlainAcc>(a, rec_ref(tup, p, j, n_child, NE), n);
+    w_combine<N>(run, a, a, scr, n);
+    const WT<R> t = run;
+    run = a;
+    a = t;
+  }
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_m2_top(const R* __restrict__ tup, long n_top,
+                                                R* __restrict__ pre) {
+  __shared__ R sh[WM2Sh<N>::sweep];
+  __shared__ int piv;
+  WT<R> run = wt_at(sh, N);
+  wt_identity(run, N);
+  wb_m2_sweep<N, R>(sh, &piv, blockIdx.y, 0, n_top, tup, n_top, pre, run);
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_m2_down(int wc, const R* __restrict__ tup, long n_child,
+                                                 const R* __restrict__ pre_in, long n_par,
+                                                 R* __restrict__ pre_out) {
+  __shared__ R sh[WM2Sh<N>::sweep];
+  __shared__ int piv;
+  const long i = blockIdx.x;
+  if (i >= n_par) return;
+  WT<R> run = wt_at(sh, N);
+  wt_load<PlainAcc>(run, rec_ref(pre_in, blockIdx.y, i, n_par, ne_w(N)), N);
+  wb_m2_sweep<N, R>(sh, &piv, blockIdx.y, i * wc, min(i * wc + wc, n_child), tup, n_child,
+                    pre_out, run);
+}
+
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_m2_bottom(const KProb kp, int wc, const R* __restrict__ elts,
+                                                   const R* __restrict__ Sg,
+                                                   const R* __restrict__ vg,
+                                                   const R* __restrict__ pre1, long n1,
+                                                   R* __restrict__ xout, R* __restrict__ uout) {
+  constexpr int n = N, kTupW = WM2Sh<N>::kTupW;
+  __shared__ R sh[WM2Sh<N>::bottom];
+  __shared__ int piv;
+  const int p = blockIdx.y;
+  const long i = blockIdx.x;
+  if (i >= n1) return;
+  const int nu = kp.nu;
+  const long T = kp.T;
+  const int NE = ne_w(n);
+  WT<R> run = wt_at(sh, n), a = wt_at(sh + kTupW, n);
+  WS<R> scr = ws_at(sh + 2 * kTupW, &piv, n);
+  R* S = sh + WM2Sh<N>::sweep;
+  R* M = S + n * n;
+  R* Kc = M + n * n;
+  R* v = Kc + n * n;
+  R* x0 = v + n;
+  R* x = x0 + n;
+  R* B = x + n;
+  R* g = B + n;
+  R* u = g + n;
+  const R* Sp = Sg + (long)p * (T + 1) * n * n;
+  const R* vp = vg + (long)p * (T + 1) * n;
+  R* xp = xout + (long)p * (T + 1) * n;
+  R* up = uout ? uout + (long)p * (T + 1) * nu : nullptr;
+  const long s0 = (long)p * (2L * kp.n * T + 1);
+  for (int q = lane_id(); q < n; q += 64) x0[q] = ((const R*)kp.x0)[(long)p * n + q];
+  wt_load<PlainAcc>(run, rec_ref(pre1, p, i, n1, NE), n);
+  auto emit = [&](long k) {
+    for (int e = lane_id(); e < n * n; e += 64) S[e] = Sp[k * n * n + e];
+    for (int q = lane_id(); q < n; q += 64) v[q] = vp[k * n + q];
+    wsync();
+    w_m2_state<N>(run.A, run.b, run.C, x0, S, v, M, B, x, n);
+    for (int q = lane_id(); q < n; q += 64) xp[k * n + q] = x[q];
+    if (up) {
+      w_gain(kp, p, s0 + 2L * kp.n * k, Kc, n, nu);
+      w_control(Kc, S, v, x, g, u, n, nu);
+      for (int l = lane_id(); l < nu; l += 64) up[k * nu + l] = u[l];
+    }
+  };
+  const long j0 = i * wc, j1 = min(j0 + wc, T);
+  for (long k = j0; k < j1; ++k) {
+    emit(k);
+    if (k + 1 == j1 && j1 < T) break;
+    wt_load<PlainAcc>(a, elt_ref(elts, p, k, T, NE), n);
+    w_combine<N>(run, a, a, scr, n);
+    const WT<R> t = run;
+    run = a;
+    a = t;
+  }
+  if (j1 == T) emit(T);
+}
+
+// ------------------------------------------------------------------------------------------
+// Values inside the blocks (Sec. VI-A), one wave per block k.  At the nodes t_k + m h
+// (m = 1 .. n - 1):
+//   S, v by classical RK4 on their backward ODEs (Sec. II-B) from S_{k+1}, v_{k+1}:
+//     dS/dt = -F^T S - S F - Q + S G S,  dv/dt = -Q r - F^T v + S G v + S c;
+//   x by the Method 2 formula with the forward parts of Theorem 9 on [t_k, t_k + m h] (the steps
+//     of the forward build without eta, J), x_k at the left end;
+//   u by the control law at the node's sample.
+// Node n k carries the block-boundary values and node n T those at t_T.  The forward sweep reads
+// the interior S, v back from the outputs the same wave wrote (L2-resident by then).
+// ------------------------------------------------------------------------------------------
+template <int N>
+struct WDenseSh {
+  static constexpr int kTupW = 3 * N * N + 2 * N;
+  static constexpr int riccati = 9 * N * N + 6 * N;
+  static constexpr int fwd = 3 * kTupW + kBuildScr<N>;
+  static constexpr int extra = 3 * N * N + 5 * N;
+  static constexpr int all = (riccati > fwd ? riccati : fwd) + extra;
+};
+
+template <int N, class R>
+__global__ __launch_bounds__(64) void kw_dense(const KProb kp, const R* __restrict__ Sg,
+                                               const R* __restrict__ vg,
+                                               const R* __restrict__ xg, R* __restrict__ Sd,
+                                               R* __restrict__ vd, R* __restrict__ xd,
+                                               R* __restrict__ ud) {
+  constexpr int n = N, kTupW = WDenseSh<N>::kTupW;
+  __shared__ R sh[WDenseSh<N>::all];
+  const int p = blockIdx.y;
+  const long k = blockIdx.x;
+  const int nn = kp.n, nu = kp.nu;
+  const long T = kp.T;
+  const long nodes = (long)nn * T + 1;
+  const WBlk bk = wblk_plain(kp, p, k);
+  const R* Sp = Sg + (long)p * (T + 1) * n * n;
+  const R* vp = vg + (long)p * (T + 1) * n;
+  const R* xp = xg + (long)p * (T + 1) * n;
+  R* Sdp = Sd + (long)p * nodes * n * n;
+  R* vdp = vd + (long)p * nodes * n;
+  R* xdp = xd + (long)p * nodes * n;
+  R* udp = ud ? ud + (long)p * nodes * nu : nullptr;
+  const R* t = (const R*)kp.t + bk.tk;
+  const R h = (t[1] - t[0]) / R(nn);
+  // node-level scratch, beside both sweeps' areas
+  R* Sn = sh + (WDenseSh<N>::all - WDenseSh<N>::extra);
+  R* Mn = Sn + n * n;
+  R* Kc = Mn + n * n;
+  R* vn = Kc + n * n;
+  R* xk = vn + n;
+  R* xn = xk + n;
+  R* Bn = xn + n;
+  R* gn = Bn + n;
+  auto emit_u = [&](long node) {  // from Sn, vn, xn
+    if (!udp) return;
+    w_gain(kp, p, bk.s0 + 2 * node, Kc, n, nu);
+    w_control(Kc, Sn, vn, xn, gn, Bn, n, nu);
+    for (int l = lane_id(); l < nu; l += 64) udp[node * nu + l] = Bn[l];
+    wsync();
+  };
+
+  // ---- backward sweep: S, v at nodes n k + n - 1 down to n k + 1 ----
+  {
+    R* F = sh;
+    R* G = F + n * n;
+    R* Lc = G + n * n;
+    R* Qs = Lc + n * n;
+    R* P = Qs + n * n;
+    R* kS = P + n * n;
+    R* S = kS + n * n;
+    R* sS = S + n * n;
+    R* aS = sS + n * n;
+    R* rv = aS + n * n;
+    R* cv = rv + n;
+    R* v = cv + n;
+    R* sv = v + n;
+    R* av = sv + n;
+    R* kv = av + n;
+    const R* Fc = (const R*)kp.F;
+    const R* Qp = (const R*)kp.Q + (long)p * n * n;
+    const R* cs = (const R*)kp.consts + (long)p * consts_count(n, nu);
+    const R* cb = kp.has_c ? (const R*)kp.c : nullptr;
+    for (int e = lane_id(); e < n * n; e += 64) {
+      Qs[e] = Qp[e];
+      S[e] = Sp[(k + 1) * n * n + e];
+      if (!kp.L_sampled) G[e] = cs[consts_off_G(n, nu) + e];
+    }
+    for (int i = lane_id(); i < n; i += 64) v[i] = vp[(k + 1) * n + i];
+    wsync();
+    for (int mp = 0; mp < nn - 1; ++mp) {
+      const long j1 = 2L * nn * k + 2L * (nn - mp);  // sample at t = t_{k+1} - mp h
+      w_copy(sS, S, n * n);
+      w_copy(sv, v, n);
+      for (int st = 0; st < 4; ++st) {
+        const long j = st == 0 ? j1 : (st == 3 ? j1 - 2 : j1 - 1);
+        const R wk = (st == 0 || st == 3) ? h / R(6) : h / R(3);
+        const R cn = st == 2 ? h : h / R(2);
+        const R* Fj = kp.F_sampled ? (const R*)kp.F + (bk.s0 + j) * n * n : Fc;
+        for (int e = lane_id(); e < n * n; e += 64) F[e] = Fj[e];
+        for (int i = lane_id(); i < n; i += 64) {
+          rv[i] = ((const R*)kp.r)[(bk.s0 + j) * n + i];
+          cv[i] = cb ? cb[(bk.s0 + j) * n + i] : R(0);
+        }
+        if (kp.L_sampled) {
+          const R* Lj = (const R*)kp.L + (bk.s0 + j) * n * nu;
+          const R* W = cs + consts_off_W(n, nu);
+          for (int e = lane_id(); e < n * nu; e += 64) {
+            const int i = e / nu, l = e % nu;
+            R a = R(0);
+            for (int q2 = 0; q2 < nu; ++q2) a = fma(Lj[i * nu + q2], W[q2 * nu + l], a);
+            Lc[e] = a;
+          }
+          wsync();
+          w_gemm<kMfma<N, R>>(G, Lc, Lc, n, nu, n, false, true, R(1), R(0));
+        } else {
+          wsync();
+        }
+        // P = S G;  kS = -F^T S - S F - Q + P S (upper entries);  kv = -Q r - F^T v + P v + S c
+        w_gemm<kMfma<N, R>>(P, sS, G, n, n, n, false, false, R(1), R(0));
+        for (int e = lane_id(); e < n * n; e += 64) kS[e] = -Qs[e];
+        wsync();
+        w_gemm<kMfma<N, R>>(kS, F, sS, n, n, n, true, false, R(-1), R(1));
+        w_gemm<kMfma<N, R>>(kS, sS, F, n, n, n, false, false, R(-1), R(1));
+        w_gemm<kMfma<N, R>>(kS, P, sS, n, n, n, false, false, R(1), R(1));
+        for (int i = lane_id(); i < n; i += 64) {
+          R a = R(0);
+          for (int l = 0; l < n; ++l) {
+            a = fma(-Qs[i * n + l], rv[l], a);
+            a = fma(-F[l * n + i], sv[l], a);
+            a = fma(P[i * n + l], sv[l], a);
+            a = fma(sS[i * n + l], cv[l], a);
+          }
+          kv[i] = a;
+        }
+        wsync();
+        for (int e = lane_id(); e < n * n; e += 64) {
+          const int i = e / n, q2 = e % n;
+          const R ks = kS[(i < q2 ? i : q2) * n + (i < q2 ? q2 : i)];
+          aS[e] = st == 0 ? fma(-wk, ks, S[e]) : fma(-wk, ks, aS[e]);
+          if (st < 3) sS[e] = fma(-cn, ks, S[e]);
+        }
+        for (int i = lane_id(); i < n; i += 64) {
+          av[i] = st == 0 ? fma(-wk, kv[i], v[i]) : fma(-wk, kv[i], av[i]);
+          if (st < 3) sv[i] = fma(-cn, kv[i], v[i]);
+        }
+        wsync();
+      }
+      const long node = (long)nn * k + (nn - mp - 1);
+      for (int e = lane_id(); e < n * n; e += 64) {
+        S[e] = aS[e];
+        Sdp[node * n * n + e] = aS[e];
+      }
+      for (int i = lane_id(); i < n; i += 64) {
+        v[i] = av[i];
+        vdp[node * n + i] = av[i];
+      }
+      wsync();
+    }
+  }
+
+  // ---- block-boundary nodes ----
+  auto boundary = [&](long kb) {
+    const long node = (long)nn * kb;
+    for (int e = lane_id(); e < n * n; e += 64) {
+      Sn[e] = Sp[kb * n * n + e];
+      Sdp[node * n * n + e] = Sn[e];
+    }
+    for (int i = lane_id(); i < n; i += 64) {
+      vn[i] = vp[kb * n + i];
+      xn[i] = xp[kb * n + i];
+      vdp[node * n + i] = vn[i];
+      xdp[node * n + i] = xn[i];
+    }
+    wsync();
+    emit_u(node);
+  };
+  boundary(k);
+  for (int i = lane_id(); i < n; i += 64) xk[i] = xn[i];
+  if (k == T - 1) boundary(T);
+  wsync();
+
+  // ---- forward sweep: Theorem 9 parts, x and u at nodes n k + 1 .. n k + n - 1 ----
+  WT<R> y = wt_at(sh, n), ac = wt_at(sh + kTupW, n), st = wt_at(sh + 2 * kTupW, n);
+  wt_identity(y, n);
+  auto step = [&](int m) {
+    const long node = (long)nn * k + m + 1;
+    for (int e = lane_id(); e < n * n; e += 64) Sn[e] = Sdp[node * n * n + e];
+    for (int i = lane_id(); i < n; i += 64) vn[i] = vdp[node * n + i];
+    wsync();
+    w_m2_state<N>(y.A, y.b, y.C, xk, Sn, vn, Mn, Bn, xn, n);
+    for (int i = lane_id(); i < n; i += 64) xdp[node * n + i] = xn[i];
+    emit_u(node);
+  };
+  wb_fwd_steps<N, R, false>(kp, bk, k, nn - 1, y, ac, st, sh + 3 * kTupW, step);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2343,6 +2782,50 @@ hipError_t wave_build_split_t(const KProb& kp, void* elts, hipStream_t s) {
 }
 
 template <int N, class R>
+hipError_t wave_lti_prep_t(const KProb& kp, void* tab, hipStream_t s) {
+  hipLaunchKernelGGL((kw_lti_prep<N, R>), dim3((unsigned)((2 * kp.n + 1) * N), kp.batch), dim3(64),
+                     0, s, kp, (R*)tab);
+  return hipGetLastError();
+}
+
+template <int N, class R>
+hipError_t wave_lti_build_t(const KProb& kp, const void* tab, void* elts, hipStream_t s) {
+  hipLaunchKernelGGL((kw_build_lti<N, R>), dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
+                     (const R*)tab, (R*)elts);
+  return hipGetLastError();
+}
+
+template <int N, class R>
+hipError_t wave_method2_t(const KProb& kp, const WTree& t, const Work& w, const void* elts,
+                          const void* S, const void* v, void* x, void* u, hipStream_t s) {
+  const int n = N;
+  const dim3 b(64);
+  hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, n, t.wc, 1,
+                     (const R*)elts, t.n[0], (R*)w.vtup[1], t.n[1]);
+  for (int l = 1; l < t.levels; ++l)
+    hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n,
+                       t.wcs[l], 0, (const R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1], t.n[l + 1]);
+  hipLaunchKernelGGL((kw_m2_top<N, R>), dim3(1, kp.batch), b, 0, s, (const R*)w.vtup[t.levels],
+                     t.n[t.levels], (R*)w.vpart[t.levels]);
+  for (int l = t.levels - 1; l >= 1; --l)
+    hipLaunchKernelGGL((kw_m2_down<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s,
+                       t.wcs[l], (const R*)w.vtup[l], t.n[l], (const R*)w.vpart[l + 1],
+                       t.n[l + 1], (R*)w.vpart[l]);
+  hipLaunchKernelGGL((kw_m2_bottom<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, t.wc,
+                     (const R*)elts, (const R*)S, (const R*)v, (const R*)w.vpart[1], t.n[1],
+                     (R*)x, (R*)u);
+  return hipGetLastError();
+}
+
+template <int N, class R>
+hipError_t wave_dense_t(const KProb& kp, const void* S, const void* v, const void* x, void* Sd,
+                        void* vd, void* xd, void* ud, hipStream_t s) {
+  hipLaunchKernelGGL((kw_dense<N, R>), dim3((unsigned)kp.T, kp.batch), dim3(64), 0, s, kp,
+                     (const R*)S, (const R*)v, (const R*)x, (R*)Sd, (R*)vd, (R*)xd, (R*)ud);
+  return hipGetLastError();
+}
+
+template <int N, class R>
 hipError_t wave_value_t(const KProb& kp, const WTree& t, const Work& w, const void* elts, void* S,
                         void* v, void* maps1, hipStream_t s) {
   const int n = N, wc = t.wc;
@@ -2407,7 +2890,9 @@ struct Fns {
     if constexpr (wave_shard(N, sizeof(R) == 4) == LQT_SHARD) {
       static const WaveFns f = {wave_build_t<N, R>,       wave_value_t<N, R>,
                                 wave_traj_t<N, R>,        wave_solve_queue_t<N, R>,
-                                wave_build_fwd_t<N, R>,   wave_build_split_t<N, R>};
+                                wave_build_fwd_t<N, R>,   wave_build_split_t<N, R>,
+                                wave_method2_t<N, R>,     wave_dense_t<N, R>,
+                                wave_lti_prep_t<N, R>,    wave_lti_build_t<N, R>};
       return &f;
     } else {
       return nullptr;

@@ -2,8 +2,8 @@
 forward Theorem 9 parts and the Method 2 formula, u by the control law) on the GPU.
 
 Against the oracle's dense output of the oracle's solve (normwise 1e-9 in FP64, 1e-4 in FP32), for
-every (nx, nu) of the per-lane path, sampled F and L, a drift c, n = 1 (no interior nodes), T = 1,
-ragged tiles and batches.  At the full size (point mass, T = 2^20 blocks x 4 steps) the stored
+every (nx, nu) of the per-lane path, state sizes 5 .. 16 (one wavefront per block), sampled F and
+L, a drift c, n = 1 (no interior nodes), T = 1, ragged tiles and batches.  At the full size (point mass, T = 2^20 blocks x 4 steps) the stored
 oracle boundary values of tests/golden/fullsize_point_mass_T2p20.json give, for each sampled
 block whose two ends are both stored, the oracle's interior values of that block; every output is
 also checked for properties that hold at any size (boundary nodes copied unchanged, S symmetric,
@@ -123,12 +123,48 @@ def test_without_control_output():
     assert relerr(_np(d["x"][0]), ref["x"]) < 1e-9
 
 
-def test_wave_sizes_are_refused():
-    p = W.random_stable(1, nx=6, nu=2, T=8, n=2, tf=1.0)
+# ---- state sizes 5 .. 16 (one wavefront per block) ----
+
+@pytest.mark.parametrize("nx,nu,T,n", [(5, 2, 40, 3), (8, 4, 65, 4), (16, 4, 20, 3), (16, 16, 3, 2),
+                                       (6, 1, 1, 1), (7, 3, 1, 5), (9, 2, 9, 2)])
+def test_wave_sizes_time_varying_with_drift(nx, nu, T, n):
+    p = W.random_stable(19 * nx + T + n, nx=nx, nu=nu, T=T, n=n, tf=0.02 * T + 0.5,
+                        time_varying=True)
+    rng = np.random.default_rng(nx + 7 * nu)
+    p.c = 0.3 * np.sin(np.linspace(0, 3, p.r.shape[0]))[:, None] * rng.standard_normal(nx)[None, :]
+    out, d = _run([p])
+    _check(p, d, torch.float64, label=f"nx={nx} nu={nu} T={T} n={n}")
+    for k in ("S", "v", "x"):  # block boundaries: the solve's values unchanged
+        assert torch.equal(d[k][0, ::n], out[k][0]), k
+    assert relerr(_np(d["u"][0, ::n]), _np(out["u"][0])) < 1e-13
+
+
+def test_wave_sampled_L():
+    p = W.random_stable(6, nx=10, nu=3, T=50, n=4, tf=2.0)
+    ts = W.half_step_times(p.t, p.n)
+    p.L = p.L[None] * (1.0 + 0.2 * np.cos(ts))[:, None, None]
+    _, d = _run([p])
+    _check(p, d, torch.float64, label="sampled L nx=10")
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_wave_batch(dtype):
+    probs = [W.random_stable(90 + i, nx=8, nu=2, T=70, n=4, tf=1.5) for i in range(2)]
+    probs[1].L = probs[0].L  # a constant L is shared by a batch
+    _, d = _run(probs, dtype=dtype)
+    for b, p in enumerate(probs):
+        _check(p, d, dtype, b=b, label=f"member {b}")
+
+
+def test_wave_without_control_output():
+    p = W.random_stable(4, nx=6, nu=2, T=30, n=3, tf=1.0)
     dp = lqt.DeviceProblem.from_problems([p])
     out = lqt.solve(dp)
-    with pytest.raises(lqt.LQTError):
-        lqt.dense_output(dp, out["S"], out["v"], out["x"])
+    d = lqt.dense_output(dp, out["S"], out["v"], out["x"], want_u=False)
+    torch.cuda.synchronize()
+    assert "u" not in d
+    ref = O.dense(p, O.solve(p))
+    assert relerr(_np(d["x"][0]), ref["x"]) < 1e-9
 
 
 def test_full_size_blocks_against_oracle():

@@ -97,6 +97,37 @@ def test_full_size_against_oracle_samples():
         assert e < 1e-9, f"{k}: {e:.3e}"
 
 
+@pytest.mark.parametrize("nx,nu,T,n", [(5, 2, 1, 1), (8, 4, 300, 4), (11, 3, 65, 2), (16, 4, 129, 3),
+                                       (16, 16, 9, 5)])
+def test_wave_sizes_time_invariant(nx, nu, T, n):
+    """State sizes 5 .. 16 (one wavefront per impulse and per block): elements and the solve
+    against the oracle, and the solve against the general GPU build."""
+    p = W.random_stable(23 * nx + T, nx=nx, nu=nu, T=T, n=n, tf=0.01 * T + 0.3, time_varying=False)
+    out = lqt.solve(lqt.DeviceProblem.from_problems([p], lti=True), keep_elements=True)
+    _check(out, O.solve(p), torch.float64, label=f"nx={nx} T={T} n={n}")
+    el = soa_to_dense(_np(out["elts"][0]), nx, T)
+    ref = O.elements(p)
+    for k in ("A", "b", "C", "eta", "J"):
+        assert relerr(el[k], ref[k]) < 1e-9, k
+    gen = lqt.solve(lqt.DeviceProblem.from_problems([p]))
+    for k in ("S", "v", "x", "u"):
+        assert relerr(_np(out[k]), _np(gen[k])) < 1e-11, k
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_wave_batch_build(dtype):
+    probs = [W.random_stable(30 + i, nx=9, nu=3, T=200, n=4, tf=2.0, time_varying=False)
+             for i in range(2)]
+    probs[1].F, probs[1].L = probs[0].F, probs[0].L  # constant F, L are shared by a batch
+    dp = lqt.DeviceProblem.from_problems(probs, dtype=dtype, lti=True)
+    e = lqt.build_elements(dp, lqt.empty_elements(dp).zero_())  # tile padding zeroed
+    for b, p in enumerate(probs):
+        el = soa_to_dense(_np(e[b]), 9, 200)
+        ref = O.elements(p)
+        for k in ("A", "b", "C", "eta", "J"):
+            assert relerr(el[k], ref[k]) < TOL[dtype], (b, k)
+
+
 def test_host_checks_refuse_non_uniform_grids():
     p = W.point_mass(1, 16, 2, t_grid=np.sort(np.r_[0.0, np.random.default_rng(0).uniform(0, 10, 15), 10.0]))
     with pytest.raises(ValueError):

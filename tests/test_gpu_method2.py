@@ -4,7 +4,8 @@ the value function at t_k) on the GPU.
 Against the oracle's Method 2 solve (normwise 1e-9 FP64, 1e-4 FP32) and against the Method 1
 trajectory of the same elements and values (the two routes agree up to rounding).  Sizes span
 one to three levels of the scan tree with ragged last nodes, every (nx, nu) of the per-lane path,
-sampled F, L, a drift c, and batches.
+state sizes 5 .. 16 (one wavefront per tree node, one to five tree levels), sampled F, L, a drift
+c, and batches.
 """
 import json
 import os
@@ -85,13 +86,40 @@ def test_fp32():
     assert relerr(_np(x2[0]), ref["x"]) < 1e-4
 
 
-def test_large_state_is_unsupported():
-    p = W.random_stable(1, nx=6, nu=2, T=8, n=2)
-    dp = lqt.DeviceProblem.from_problems([p])
-    out = lqt.solve(dp, keep_elements=True)
-    with pytest.raises(lqt.LQTError) as ei:
-        lqt.forward_traj_method2(dp, out["elts"], out["S"], out["v"])
-    assert ei.value.status == lqt.LQT_EUNSUPPORTED
+# ---- state sizes 5 .. 16 (one wavefront per tree node) ----
+
+@pytest.mark.parametrize("nx,nu,T", [(5, 1, 1), (6, 3, 9), (8, 4, 33), (11, 5, 150), (16, 4, 600),
+                                     (16, 16, 7), (7, 2, 2049)])
+def test_wave_sizes_time_varying_with_drift(nx, nu, T):
+    """One to five tree levels (8 blocks per leaf, 4 nodes per upper node), ragged last nodes."""
+    p = W.random_stable(17 * nx + T, nx=nx, nu=nu, T=T, n=3, tf=0.01 * T + 0.5, time_varying=True)
+    rng = np.random.default_rng(nx + T)
+    p.c = 0.3 * np.sin(np.linspace(0, 3, p.r.shape[0]))[:, None] * rng.standard_normal(nx)[None, :]
+    ref = O.solve(p, method2=True)
+    out, x2, u2 = _run(p)
+    assert relerr(_np(x2[0]), ref["x"]) < 1e-9
+    assert relerr(_np(u2[0]), ref["u"]) < 1e-9
+    assert relerr(_np(x2[0]), _np(out["x"][0])) < 1e-10
+
+
+def test_wave_sampled_L_and_batch():
+    probs = [W.random_stable(80 + i, nx=9, nu=3, T=100, n=4, tf=2.0) for i in range(2)]
+    for p in probs:
+        ts = W.half_step_times(p.t, p.n)
+        p.L = probs[0].L[None] * (1.0 + 0.2 * np.cos(ts))[:, None, None] if np.ndim(probs[0].L) == 2 \
+            else probs[0].L
+    _, x2, u2 = _run(None, batch=probs)
+    for b, p in enumerate(probs):
+        ref = O.solve(p, method2=True)
+        assert relerr(_np(x2[b]), ref["x"]) < 1e-9, b
+        assert relerr(_np(u2[b]), ref["u"]) < 1e-9, b
+
+
+def test_wave_fp32():
+    p = W.random_stable(3, nx=16, nu=4, T=256, n=4, tf=10.0 * 256 / 2 ** 14)
+    ref = O.solve(p, method2=True)
+    _, x2, _ = _run(p, torch.float32)
+    assert relerr(_np(x2[0]), ref["x"]) < 1e-4
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
