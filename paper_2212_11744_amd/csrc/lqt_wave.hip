@@ -63,16 +63,21 @@ WDEV void w_gemm16(double* C, const double* A, const double* B, int kk, bool tA,
 template <int N, class R>
 constexpr bool kMfma = N == 16 && sizeof(R) == 8;
 
-// C = alpha * op(A) op(B) + beta * D for a 16 x 16 result with row strides ldc, lda, ldb, ldd
-// (op(A)(i, k) = tA ? A[k lda + i] : A[i lda + k], likewise B; D nullable, may be C).
+// C = alpha * op(A) (op(B) + addI I) + beta * D for a 16 x 16 result with row strides ldc, lda,
+// ldb, ldd (op(A)(i, k) = tA ? A[k lda + i] : A[i lda + k], likewise B; D nullable, may be C).
+// LDS banks: the 16 lanes of an operand read hold 16 rows i (A) or columns j (B) of one k, so A
+// with tA and B without tB are read from consecutive addresses; A without tA (a column of a
+// row-major matrix, stride 16 values) puts the 16 lanes on one bank pair.  Symmetric left
+// factors are therefore passed with tA, general ones transposed beforehand.
 WDEV void w_mm16(double* C, int ldc, const double* A, int lda, bool tA, const double* B, int ldb,
-                 bool tB, int kk, double alpha, const double* D, int ldd, double beta) {
+                 bool tB, int kk, double alpha, const double* D, int ldd, double beta,
+                 bool addI = false) {
   const int l = lane_id(), li = l & 15, lq = l >> 4;
   wd4 acc = {0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < kk; k0 += 4) {
     const int k = k0 + lq;
     const double a = tA ? A[k * lda + li] : A[li * lda + k];
-    const double b = tB ? B[li * ldb + k] : B[k * ldb + li];
+    const double b = (tB ? B[li * ldb + k] : B[k * ldb + li]) + (addI && k == li ? 1.0 : 0.0);
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
   wsync();  // C may be an operand
@@ -137,20 +142,61 @@ WDEV void w_fill(R* dst, R v, int n) {
   wsync();
 }
 
+// Lane exchange through DPP (a VALU operand modifier: no LDS round trip): CTRL is the DPP control
+// (0xB1 / 0x4E: xor 1 / xor 2 inside each quad; 0x141: mirror inside each half-row of 8 lanes;
+// 0x140: mirror inside each row of 16 lanes).
+template <int CTRL>
+WDEV int w_dpp(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+WDEV float w_dpp(float x) {
+  return __builtin_bit_cast(float, w_dpp<CTRL>(__builtin_bit_cast(int, x)));
+}
+template <int CTRL>
+WDEV double w_dpp(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = w_dpp<CTRL>((int)b), hi = w_dpp<CTRL>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// (v, ix) <- the largest v of the RP consecutive lanes of this lane's group (RP = 8 or 16, groups
+// aligned), the smallest ix among equal v; every lane of the group ends with the same pair.
+template <int CTRL, class R>
+WDEV void w_argmax_step(R& v, int& ix) {
+  const R vo = w_dpp<CTRL>(v);
+  const int io = w_dpp<CTRL>(ix);
+  if (vo > v || (vo == v && io < ix)) {
+    v = vo;
+    ix = io;
+  }
+}
+template <int RP, class R>
+WDEV void w_argmax(R& v, int& ix) {
+  w_argmax_step<0xB1>(v, ix);
+  w_argmax_step<0x4E>(v, ix);
+  w_argmax_step<0x141>(v, ix);
+  if constexpr (RP == 16) w_argmax_step<0x140>(v, ix);
+}
+
 // Solve M X = B in place (B <- M^{-1} B), M n x n (n = N), B n x nb with n + nb <= 3n + 1, by
-// Gauss-Jordan elimination with partial pivoting (first row of largest magnitude).  The system
-// lives in registers: row i of [M | B] belongs to LP = 64 / RP lanes (RP = 8 or 16 rows, padded),
-// lane phase c0 holding columns c0, c0 + LP, ...  Per pivot: an argmax butterfly across the rows,
-// a register swap when the pivot row moves, and one LDS broadcast of the pivot row and of column c
-// (M's own storage is reused for it), after which every lane updates its columns.  M is
-// destroyed; the arithmetic per entry is that of the textbook elimination (scale the pivot row by
-// 1 / pivot, subtract f_i times it from every other row).
+// Gauss-Jordan elimination with partial pivoting (the row of largest magnitude among those not yet
+// used as pivots, the first one on ties).  The system lives in registers: row i of [M | B]
+// belongs to the lanes i + RP c0 (RP = 8 or 16 rows, padded; phase c0 = 0 .. 64 / RP - 1 holds
+// columns c0, c0 + 64 / RP, ...), so the candidates of a column sit in RP consecutive lanes and
+// the pivot search is a DPP reduction.  Pivoting is implicit: rows stay in place and each
+// remembers the column it was the pivot of, which places its solution row at the end.  Per pivot
+// one LDS broadcast of the pivot row and of column c, alternating between two buffers (M's storage
+// and B's, whose values are in registers by then) so that one barrier per pivot suffices; then
+// every lane updates its columns (scale the pivot row by 1 / pivot, subtract f_i times it from
+// every other row, as in the textbook elimination).  M is destroyed.
 template <int N, class R>
 WDEV void w_solve(R* M, R* B, int n, int nb, R*, int*) {
   constexpr int RP = N <= 8 ? 8 : 16;
   constexpr int LP = 64 / RP;
   constexpr int NT = (3 * N + 1 + LP - 1) / LP;
-  const int l = lane_id(), i = l / LP, c0 = l % LP;
+  static_assert(N >= 5, "the broadcast buffers need N^2 >= 4 N + 2");
+  const int l = lane_id(), i = l % RP, c0 = l / RP;
   const int W = N + nb;
   R x[NT];
 #pragma unroll
@@ -158,30 +204,21 @@ WDEV void w_solve(R* M, R* B, int n, int nb, R*, int*) {
     const int j = c0 + LP * t;
     x[t] = i < N && j < W ? (j < N ? M[i * N + j] : B[i * nb + (j - N)]) : R(0);
   }
-  wsync();  // M's storage becomes the broadcast buffer
-  R* rowc = M;      // pivot row (W values)
-  R* fcol = M + W;  // column c of every row (N values)
+  wsync();  // M's and B's storage become the broadcast buffers (W + N values each)
+  R* const buf0 = M;
+  R* const buf1 = nb >= 3 ? B : M + (W + N);
+  int mycol = -1;  // the column this lane's row was the pivot of
 #pragma unroll
   for (int c = 0; c < N; ++c) {
     const int tc = c / LP, cc = c % LP;
-    R v = c0 == cc && i >= c && i < N ? fabs(x[tc]) : R(-1);
+    R* const rowc = (c & 1) ? buf1 : buf0;  // pivot row (W values)
+    R* const fcol = rowc + W;               // column c of every row (N values)
+    R v = c0 == cc && i < N && mycol < 0 ? fabs(x[tc]) : R(-1);
     int ix = i;
-#pragma unroll
-    for (int d = LP; d < 64; d <<= 1) {
-      const R vo = __shfl_xor(v, d);
-      const int io = __shfl_xor(ix, d);
-      if (vo > v || (vo == v && io < ix)) {
-        v = vo;
-        ix = io;
-      }
-    }
-    const int p = __shfl(ix, cc);  // lane cc (row 0, phase cc) saw every row's column c
-    if (p != c) {
-      const int src = i == c ? l + (p - c) * LP : (i == p ? l - (p - c) * LP : l);
-#pragma unroll
-      for (int t = 0; t < NT; ++t) x[t] = __shfl(x[t], src);
-    }
-    if (i == c) {
+    w_argmax<RP>(v, ix);
+    const int p = __builtin_amdgcn_readlane(ix, cc * RP);  // the group of phase cc holds column c
+    if (i == p) {
+      mycol = c;
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int j = c0 + LP * t;
@@ -197,15 +234,15 @@ WDEV void w_solve(R* M, R* B, int n, int nb, R*, int*) {
       const int j = c0 + LP * t;
       if (i < N && j < W && (j > c || j >= N)) {
         const R rj = rowc[j] * inv;
-        x[t] = i == c ? rj : fma(-f, rj, x[t]);
+        x[t] = i == p ? rj : fma(-f, rj, x[t]);
       }
     }
-    wsync();  // the next pivot overwrites the buffer
   }
+  wsync();  // the last broadcast may have used B's storage
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int j = c0 + LP * t;
-    if (i < N && j >= N && j < W) B[i * nb + (j - N)] = x[t];
+    if (i < N && mycol >= 0 && j >= N && j < W) B[mycol * nb + (j - N)] = x[t];
   }
   wsync();
 }
@@ -303,40 +340,45 @@ struct WS {
 template <int N, class R>
 WDEV void w_combine(WT<R> x1, WT<R> x2, WT<R> o, WS<R> s, int n) {
   const int nb = 2 * n + 1;
-  // M = I + C1 J2; B = [Ad1 - C1 J2 | C1 | b1 + C1 eta2]
-  w_gemm<kMfma<N, R>>(s.X, x1.C, x2.J, n, n, n, false, false, R(1), R(0));
+  // Ad2^T for the matrix-core products (after the n values of f, inside the scratch)
+  R* At = s.f + 2 * n;
+  // M = I + C1 J2; B = [Ad1 - C1 J2 | C1 | b1 + C1 eta2]  (C1 symmetric: read by columns)
+  w_gemm<kMfma<N, R>>(s.X, x1.C, x2.J, n, n, n, kMfma<N, R>, false, R(1), R(0));
   for (int e = lane_id(); e < n * n; e += 64) {
     const int i = e / n, j = e % n;
     s.M[e] = (i == j ? R(1) : R(0)) + s.X[e];
     s.B[i * nb + j] = x1.A[e] - s.X[e];
     s.B[i * nb + n + j] = x1.C[e];
+    if constexpr (kMfma<N, R>) At[j * n + i] = x2.A[e];
   }
   for (int i = lane_id(); i < n; i += 64) {
     R g = x1.b[i];
-    for (int k = 0; k < n; ++k) g = fma(x1.C[i * n + k], x2.e[k], g);
+    for (int k = 0; k < n; ++k) g = fma(x1.C[k * n + i], x2.e[k], g);
     s.B[i * nb + 2 * n] = g;
   }
   wsync();
   w_solve<N>(s.M, s.B, n, nb, s.f, s.piv);
   if constexpr (kMfma<N, R>) {
     // The same products on the matrix cores; every result goes to scratch first (o may be x2).
+    // W = (I + Ad2) D is formed transposed (W^T = D^T (I + Ad2^T)) so that both of its products
+    // read their left factor by columns.
     const int l = lane_id();
-    w_mm16(s.X, 16, x2.A, 16, false, s.B + n, nb, false, 16, 1.0, s.B + n, nb, 1.0);  // W
-    w_mm16(s.Y, 16, s.X, 16, false, x2.A, 16, true, 16, 1.0, s.X, 16, 1.0);  // W (I + Ad2)^T
-    w_symadd16(s.Y, x2.C);                                                   // C
+    w_mm16(s.X, 16, s.B + n, nb, true, At, 16, false, 16, 1.0, nullptr, 16, 0.0, true);  // W^T
+    w_mm16(s.Y, 16, s.X, 16, true, At, 16, false, 16, 1.0, nullptr, 16, 0.0, true);  // W (I + Ad2)^T
+    w_symadd16(s.Y, x2.C);                                                           // C
     R bn = R(0), en = R(0);
     if (l < n) {
       R t = R(0);
-      for (int k = 0; k < n; ++k) t = fma(x2.A[l * n + k], s.B[k * nb + 2 * n], t);
+      for (int k = 0; k < n; ++k) t = fma(At[k * n + l], s.B[k * nb + 2 * n], t);
       bn = x2.b[l] + s.B[l * nb + 2 * n] + t;
       R u = x2.e[l];
-      for (int k = 0; k < n; ++k) u = fma(-x2.J[l * n + k], x1.b[k], u);
+      for (int k = 0; k < n; ++k) u = fma(-x2.J[k * n + l], x1.b[k], u);
       s.f[l] = u;
     }
-    w_mm16(s.X, 16, x2.J, 16, false, x1.A, 16, false, 16, 1.0, x2.J, 16, 1.0);  // P
-    w_mm16(s.M, 16, s.B, nb, true, s.X, 16, false, 16, 1.0, s.X, 16, 1.0);     // (I + Yd)^T P
-    w_symadd16(s.M, x1.J);                                                      // J
-    w_mm16(s.X, 16, x2.A, 16, false, s.B, nb, false, 16, 1.0, s.B, nb, 1.0);   // Yd + Ad2 Yd
+    w_mm16(s.X, 16, x2.J, 16, true, x1.A, 16, false, 16, 1.0, x2.J, 16, 1.0);  // P
+    w_mm16(s.M, 16, s.B, nb, true, s.X, 16, false, 16, 1.0, s.X, 16, 1.0);    // (I + Yd)^T P
+    w_symadd16(s.M, x1.J);                                                     // J
+    w_mm16(s.X, 16, At, 16, true, s.B, nb, false, 16, 1.0, s.B, nb, 1.0);     // Yd + Ad2 Yd
     if (l < n) {
       R t = R(0);
       for (int k = 0; k < n; ++k) t = fma(s.B[k * nb + l], s.f[k], t);
@@ -432,7 +474,8 @@ WDEV void w_combine(WT<R> x1, WT<R> x2, WT<R> o, WS<R> s, int n) {
 template <int N, class R>
 WDEV void w_fold(WT<R> a, R* S, R* v, WS<R> s, int n, R* P, R* q) {
   const int nb = n + 1;
-  w_gemm<kMfma<N, R>>(s.X, a.C, S, n, n, n, false, false, R(1), R(0));  // C S
+  // C and S are symmetric: the left factors and the vector products read them by columns
+  w_gemm<kMfma<N, R>>(s.X, a.C, S, n, n, n, kMfma<N, R>, false, R(1), R(0));  // C S
   for (int e = lane_id(); e < n * n; e += 64) {
     const int i = e / n, j = e % n;
     s.M[e] = (i == j ? R(1) : R(0)) + s.X[e];
@@ -440,7 +483,7 @@ WDEV void w_fold(WT<R> a, R* S, R* v, WS<R> s, int n, R* P, R* q) {
   }
   for (int i = lane_id(); i < n; i += 64) {
     R g = a.b[i];
-    for (int k = 0; k < n; ++k) g = fma(a.C[i * n + k], v[k], g);
+    for (int k = 0; k < n; ++k) g = fma(a.C[k * n + i], v[k], g);
     s.B[i * nb + n] = g;
   }
   wsync();
@@ -452,11 +495,11 @@ WDEV void w_fold(WT<R> a, R* S, R* v, WS<R> s, int n, R* P, R* q) {
   // w = v - S b -> f;  X = S (I + Ad) -> X
   for (int i = lane_id(); i < n; i += 64) {
     R t = v[i];
-    for (int k = 0; k < n; ++k) t = fma(-S[i * n + k], a.b[k], t);
+    for (int k = 0; k < n; ++k) t = fma(-S[k * n + i], a.b[k], t);
     s.f[i] = t;
   }
   if constexpr (kMfma<N, R>) {
-    w_mm16(s.X, 16, S, 16, false, a.A, 16, false, 16, 1.0, S, 16, 1.0);     // S (I + Ad)
+    w_mm16(s.X, 16, S, 16, true, a.A, 16, false, 16, 1.0, S, 16, 1.0);      // S (I + Ad)
     w_mm16(s.M, 16, s.B, nb, true, s.X, 16, false, 16, 1.0, s.X, 16, 1.0);  // (I + Yd)^T X
     w_symadd16(s.M, a.J);
     const int i = lane_id();
@@ -505,7 +548,7 @@ WDEV void w_fold(WT<R> a, R* S, R* v, WS<R> s, int n, R* P, R* q) {
 template <int N, class R>
 WDEV void w_block_map(WT<R> a, const R* S, const R* v, WS<R> s, int n, R* P, R* q) {
   const int nb = n + 1;
-  w_gemm<kMfma<N, R>>(s.X, a.C, S, n, n, n, false, false, R(1), R(0));
+  w_gemm<kMfma<N, R>>(s.X, a.C, S, n, n, n, kMfma<N, R>, false, R(1), R(0));
   for (int e = lane_id(); e < n * n; e += 64) {
     const int i = e / n, j = e % n;
     s.M[e] = (i == j ? R(1) : R(0)) + s.X[e];
@@ -513,7 +556,7 @@ WDEV void w_block_map(WT<R> a, const R* S, const R* v, WS<R> s, int n, R* P, R* 
   }
   for (int i = lane_id(); i < n; i += 64) {
     R g = a.b[i];
-    for (int k = 0; k < n; ++k) g = fma(a.C[i * n + k], v[k], g);
+    for (int k = 0; k < n; ++k) g = fma(a.C[k * n + i], v[k], g);
     s.B[i * nb + n] = g;
   }
   wsync();
