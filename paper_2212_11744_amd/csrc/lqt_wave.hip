@@ -166,10 +166,9 @@ template <int CTRL, class R>
 WDEV void w_argmax_step(R& v, int& ix) {
   const R vo = w_dpp<CTRL>(v);
   const int io = w_dpp<CTRL>(ix);
-  if (vo > v || (vo == v && io < ix)) {
-    v = vo;
-    ix = io;
-  }
+  const bool take = (vo > v) | ((vo == v) & (io < ix));  // selects, no branch
+  v = take ? vo : v;
+  ix = take ? io : ix;
 }
 template <int RP, class R>
 WDEV void w_argmax(R& v, int& ix) {
@@ -179,63 +178,84 @@ WDEV void w_argmax(R& v, int& ix) {
   if constexpr (RP == 16) w_argmax_step<0x140>(v, ix);
 }
 
+WDEV double w_readlane(double x, int lane) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+WDEV float w_readlane(float x, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
+}
+
 // Solve M X = B in place (B <- M^{-1} B), M n x n (n = N), B n x nb with n + nb <= 3n + 1, by
 // Gauss-Jordan elimination with partial pivoting (the row of largest magnitude among those not yet
 // used as pivots, the first one on ties).  The system lives in registers: row i of [M | B]
-// belongs to the lanes i + RP c0 (RP = 8 or 16 rows, padded; phase c0 = 0 .. 64 / RP - 1 holds
-// columns c0, c0 + 64 / RP, ...), so the candidates of a column sit in RP consecutive lanes and
-// the pivot search is a DPP reduction.  Pivoting is implicit: rows stay in place and each
-// remembers the column it was the pivot of, which places its solution row at the end.  Per pivot
-// one LDS broadcast of the pivot row and of column c, alternating between two buffers (M's storage
-// and B's, whose values are in registers by then) so that one barrier per pivot suffices; then
-// every lane updates its columns (scale the pivot row by 1 / pivot, subtract f_i times it from
-// every other row, as in the textbook elimination).  M is destroyed.
+// belongs to the lanes i + RP c0 (RP = 8 or 16 rows, padded; phase c0 = 0 .. LP - 1 holds columns
+// c0, c0 + LP, ..., LP = 64 / RP), so the candidates of a column sit in RP consecutive lanes and
+// the pivot search is a DPP reduction; the pivot's index and value reach every lane by readlane.
+// Pivoting is implicit: rows stay in place and each remembers the column it was the pivot of,
+// which places its solution row at the end.  Per pivot one LDS broadcast of the pivot row and of
+// column c, alternating between two buffers of kSolveBuf values so that one barrier per pivot
+// suffices, then a branch-free update of every lane's columns (scale the pivot row by 1 / pivot,
+// subtract f_i times it from every other row, as in the textbook elimination).  Buffers: M's
+// storage, and B's when it holds kSolveBuf values, else M + kSolveBuf (then M must have room for
+// two buffers; both are no larger than n^2).  M is destroyed.
+template <int N>
+struct WSolveDims {
+  static constexpr int RP = N <= 8 ? 8 : 16;
+  static constexpr int LP = 64 / RP;
+  static constexpr int NT = (3 * N + 1 + LP - 1) / LP;
+  static constexpr int buf = LP * NT + N;  // pivot row (LP NT slots), then column c (N)
+  static_assert(buf <= N * N, "a broadcast buffer fits in M");
+};
+
 template <int N, class R>
 WDEV void w_solve(R* M, R* B, int n, int nb, R*, int*) {
-  constexpr int RP = N <= 8 ? 8 : 16;
-  constexpr int LP = 64 / RP;
-  constexpr int NT = (3 * N + 1 + LP - 1) / LP;
-  static_assert(N >= 5, "the broadcast buffers need N^2 >= 4 N + 2");
+  using D = WSolveDims<N>;
+  constexpr int RP = D::RP, LP = D::LP, NT = D::NT;
   const int l = lane_id(), i = l % RP, c0 = l / RP;
   const int W = N + nb;
   R x[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int j = c0 + LP * t;
-    x[t] = i < N && j < W ? (j < N ? M[i * N + j] : B[i * nb + (j - N)]) : R(0);
+    const bool in = i < N && j < W;
+    const R* src = !in ? M : (j < N ? M + i * N + j : B + i * nb + (j - N));
+    const R a = *src;
+    x[t] = in ? a : R(0);
   }
-  wsync();  // M's and B's storage become the broadcast buffers (W + N values each)
+  wsync();  // M's and B's storage become the broadcast buffers
   R* const buf0 = M;
-  R* const buf1 = nb >= 3 ? B : M + (W + N);
+  R* const buf1 = N * nb >= D::buf ? B : M + D::buf;
   int mycol = -1;  // the column this lane's row was the pivot of
 #pragma unroll
   for (int c = 0; c < N; ++c) {
     const int tc = c / LP, cc = c % LP;
-    R* const rowc = (c & 1) ? buf1 : buf0;  // pivot row (W values)
-    R* const fcol = rowc + W;               // column c of every row (N values)
+    R* const rowc = (c & 1) ? buf1 : buf0;
+    R* const fcol = rowc + LP * NT;
     R v = c0 == cc && i < N && mycol < 0 ? fabs(x[tc]) : R(-1);
     int ix = i;
     w_argmax<RP>(v, ix);
     const int p = __builtin_amdgcn_readlane(ix, cc * RP);  // the group of phase cc holds column c
+    const R inv = R(1) / w_readlane(x[tc], p + cc * RP);
     if (i == p) {
       mycol = c;
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int j = c0 + LP * t;
-        if (j < W) rowc[j] = x[t];
-      }
+      for (int t = 0; t < NT; ++t) rowc[c0 + LP * t] = x[t];  // slots j >= W hold zeros
     }
     if (c0 == cc && i < N) fcol[i] = x[tc];
     wsync();
-    const R inv = R(1) / rowc[c];
     const R f = fcol[i < N ? i : 0];
+    R r[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) r[t] = rowc[c0 + LP * t];
+    // Every slot is updated: columns <= c of M are not read again, slots j >= W stay zero (the
+    // pivot row's are zero) and padding rows are never pivots or written out.
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const int j = c0 + LP * t;
-      if (i < N && j < W && (j > c || j >= N)) {
-        const R rj = rowc[j] * inv;
-        x[t] = i == p ? rj : fma(-f, rj, x[t]);
-      }
+      const R rj = r[t] * inv;
+      x[t] = i == p ? rj : fma(-f, rj, x[t]);
     }
   }
   wsync();  // the last broadcast may have used B's storage
@@ -2132,7 +2152,8 @@ WDEV void w_control(const R* Kc, const R* S, const R* v, const R* x, R* g, R* u,
 }
 
 // The Method 2 state x = (I + C S)^{-1} (xk + Ad xk + b + C v) (Sec. IV-E) for the parts Ad, b, C
-// of an interval that starts at xk, and S, v at its right end; M, B: n^2 and n values of scratch.
+// of an interval that starts at xk, and S, v at its right end; M, B: 2 n^2 and n values of scratch
+// (the solve with one right-hand side keeps both of its broadcast buffers in M's).
 template <int N, class R>
 WDEV void w_m2_state(const R* Ad, const R* b, const R* C, const R* xk, const R* S, const R* v,
                      R* M, R* B, R* x, int n) {
