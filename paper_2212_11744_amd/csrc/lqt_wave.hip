@@ -188,7 +188,7 @@ WDEV float w_readlane(float x, int lane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), lane));
 }
 
-// Solve M X = B in place (B <- M^{-1} B), M n x n (n = N), B n x nb with n + nb <= 3n + 1, by
+// Solve M X = B in place (B <- M^{-1} B), M N x N, B N x NB with NB <= 2 N + 1, by
 // Gauss-Jordan elimination with partial pivoting (the row of largest magnitude among those not yet
 // used as pivots, the first one on ties).  The system lives in registers: row i of [M | B]
 // belongs to the lanes i + RP c0 (RP = 8 or 16 rows, padded; phase c0 = 0 .. LP - 1 holds columns
@@ -201,21 +201,23 @@ WDEV float w_readlane(float x, int lane) {
 // subtract f_i times it from every other row, as in the textbook elimination).  Buffers: M's
 // storage, and B's when it holds kSolveBuf values, else M + kSolveBuf (then M must have room for
 // two buffers; both are no larger than n^2).  M is destroyed.
-template <int N>
+template <int N, int NB>
 struct WSolveDims {
   static constexpr int RP = N <= 8 ? 8 : 16;
   static constexpr int LP = 64 / RP;
-  static constexpr int NT = (3 * N + 1 + LP - 1) / LP;
+  static constexpr int NT = (N + NB + LP - 1) / LP;  // column slots per lane
   static constexpr int buf = LP * NT + N;  // pivot row (LP NT slots), then column c (N)
   static_assert(buf <= N * N, "a broadcast buffer fits in M");
 };
 
-template <int N, class R>
-WDEV void w_solve(R* M, R* B, int n, int nb, R*, int*) {
-  using D = WSolveDims<N>;
+// NB: the number of right-hand columns (2 N + 1 for a combination, N + 1 for a fold, 1 for a
+// state), a compile-time constant so that each lane carries only the column slots in use.
+template <int N, int NB, class R>
+WDEV void w_solve(R* M, R* B) {
+  using D = WSolveDims<N, NB>;
   constexpr int RP = D::RP, LP = D::LP, NT = D::NT;
+  constexpr int nb = NB, W = N + NB;
   const int l = lane_id(), i = l % RP, c0 = l / RP;
-  const int W = N + nb;
   R x[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -377,7 +379,7 @@ WDEV void w_combine(WT<R> x1, WT<R> x2, WT<R> o, WS<R> s, int n) {
     s.B[i * nb + 2 * n] = g;
   }
   wsync();
-  w_solve<N>(s.M, s.B, n, nb, s.f, s.piv);
+  w_solve<N, 2 * N + 1>(s.M, s.B);
   if constexpr (kMfma<N, R>) {
     // The same products on the matrix cores; every result goes to scratch first (o may be x2).
     // W = (I + Ad2) D is formed transposed (W^T = D^T (I + Ad2^T)) so that both of its products
@@ -507,7 +509,7 @@ WDEV void w_fold(WT<R> a, R* S, R* v, WS<R> s, int n, R* P, R* q) {
     s.B[i * nb + n] = g;
   }
   wsync();
-  w_solve<N>(s.M, s.B, n, nb, s.f, s.piv);
+  w_solve<N, N + 1>(s.M, s.B);
   if (P) {
     for (int e = lane_id(); e < n * n; e += 64) P[e] = s.B[(e / n) * nb + e % n];
     for (int i = lane_id(); i < n; i += 64) q[i] = s.B[i * nb + n];
@@ -580,7 +582,7 @@ WDEV void w_block_map(WT<R> a, const R* S, const R* v, WS<R> s, int n, R* P, R* 
     s.B[i * nb + n] = g;
   }
   wsync();
-  w_solve<N>(s.M, s.B, n, nb, s.f, s.piv);
+  w_solve<N, N + 1>(s.M, s.B);
   for (int e = lane_id(); e < n * n; e += 64) P[e] = s.B[(e / n) * nb + e % n];
   for (int i = lane_id(); i < n; i += 64) q[i] = s.B[i * nb + n];
   wsync();
@@ -2172,7 +2174,7 @@ WDEV void w_m2_state(const R* Ad, const R* b, const R* C, const R* xk, const R* 
     B[i] = a;
   }
   wsync();
-  w_solve<N>(M, B, n, 1, (R*)nullptr, (int*)nullptr);
+  w_solve<N, 1>(M, B);
   for (int i = lane_id(); i < n; i += 64) x[i] = B[i];
   wsync();
 }
