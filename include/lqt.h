@@ -120,11 +120,11 @@ typedef struct lqt_problem {
 } lqt_problem;
 
 /* Number of values per element: NE = 2 nx^2 + 3 nx.  Element storage is a tiled structure of
- * arrays, elts[batch][ceil(T/256)][NE][256]: value q of block k of problem p is
- *     elts[((p * ceil(T/256) + k / 256) * NE + q) * 256 + 64 * (k % 4) + (k % 256) / 4]
- * (256 consecutive blocks share a tile; lane l of the wavefront owning a tile handles blocks
- * 4 l .. 4 l + 3, and "block j of every lane" is one contiguous 64-value row; the last tile is
- * padded).  Values q:
+ * arrays, elts[batch][ceil(T/512)][NE][512]: value q of block k of problem p is
+ *     elts[((p * ceil(T/512) + k / 512) * NE + q) * 512 + 64 * (k % 8) + (k % 512) / 8]
+ * (512 consecutive blocks share a tile; when lane l of a wavefront handles blocks 8 l .. 8 l + 7
+ * of a tile, "block j of every lane" is one contiguous 64-value row; the last tile is padded).
+ * Values q:
  *   [0, nx^2)                A - I, row-major (the deviation from the identity is stored so that
  *                            short blocks keep full relative precision in FP32)
  *   [nx^2, nx^2+nx)          b
@@ -140,7 +140,7 @@ size_t lqt_workspace_size(const lqt_dims *dims, lqt_call call);
  * dA/ds = A G J - A F, db/ds = -A G eta - A c, dC/ds = -A G A^T,
  * deta/ds = -Q r - F^T eta + J c + J G eta, dJ/ds = -Q - J F - F^T J + J G J  (G = L R^{-1} L^T)
  * in s from s = t_{k+1}, where (A, b, C, eta, J) = (I, 0, 0, 0, 0), down to s = t_k with n_steps
- * classical RK4 steps.  elts: [batch][ceil(T/256)][NE][256] output (layout above).  ws:
+ * classical RK4 steps.  elts: [batch][ceil(T/512)][NE][512] output (layout above).  ws:
  * LQT_CALL_BUILD bytes. */
 lqt_status lqt_build_elements(const lqt_dims *dims, const lqt_problem *prob, void *elts, void *ws,
                               size_t ws_bytes, hipStream_t stream);

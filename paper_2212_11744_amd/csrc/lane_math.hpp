@@ -15,6 +15,7 @@
 #define LQT_DEV __device__ __forceinline__
 
 #include "coherent.hpp"
+#include "lqt_internal.hpp"
 
 namespace lqt {
 
@@ -42,17 +43,17 @@ struct Lay {
 };
 
 // Tiled structure-of-arrays: records of NQ values for items k = 0..n-1 are stored in tiles of
-// kTile = 256 items.  Lane l of the wave that owns a tile handles the kChunk = 4 consecutive
-// items 4 l + j (j = 0..3), so inside a tile value q of item k sits at row q, column
-// 64 j + l:  index = (k / 256) * NQ * 256 + q * 256 + 64 (k % 4) + (k % 256) / 4.
-// A wave access to "item j of every lane" is then one contiguous 512-byte row (FP64), whether
-// lanes own one item each (build) or four (serial sweeps).
-constexpr int kTile = 256;
-constexpr int kChunk = 4;  // items per lane in every serial sweep (kTile = 64 * kChunk)
+// kTile = 512 items; inside a tile value q of item k sits at row q, column 64 (k % 8) + (k % 512) / 8:
+//   index = (k / 512) * NQ * 512 + q * 512 + 64 (k % 8) + (k % 512) / 8.
+// A wave access to "item j of every lane" is one contiguous 512-byte row (FP64) when each lane
+// owns 8 consecutive items (the value scan), two contiguous 256-byte half-rows when it owns 4 (the
+// serial sweeps), and eight 64-byte segments when it owns one (the builds).
+constexpr int kTile = kEltTile;
+constexpr int kChunk = 4;  // items per lane in every serial sweep
 
 template <int NQ>
 LQT_DEV long tix(int q, long k) {
-  return (k >> 8) * (NQ * (long)kTile) + (long)q * kTile + ((k & 3) << 6) + ((k & 255) >> 2);
+  return (k >> 9) * (NQ * (long)kTile) + (long)q * kTile + ((k & 7) << 6) + ((k & 511) >> 3);
 }
 
 

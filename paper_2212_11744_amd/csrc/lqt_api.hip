@@ -58,7 +58,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 long ne_of(int nx) { return 2L * nx * nx + 3L * nx; }
 long nv_of(int nx) { return (long)nx * (nx + 1) / 2 + nx; }
 long nm_of(int nx) { return (long)nx * nx + nx; }
-long padt(long n) { return (n + 255) / 256 * 256; }
+long padt(long n) { return (n + kEltTile - 1) / kEltTile * kEltTile; }
 
 }  // namespace
 
@@ -564,7 +564,7 @@ __global__ void k_nonfinite_elts(const R* __restrict__ e, int NE, long T, long p
   bool bad = false;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const long k = i % T, q = (i / T) % NE, p = i / ((long)NE * T);
-    const long idx = p * NE * pt + (k >> 8) * (NE * 256L) + q * 256L + ((k & 3) << 6) + ((k & 255) >> 2);
+    const long idx = p * NE * pt + (k >> 9) * (NE * 512L) + q * 512L + ((k & 7) << 6) + ((k & 511) >> 3);
     bad |= !isfinite(e[idx]);
   }
   if (bad) *flag = 1;

@@ -71,6 +71,8 @@ __host__ __device__ inline int consts_count(int nx, int nu) { return nx * nx + 2
 // Tree shape of the scans: n[0] = T blocks; level 1 has ceil(T / 4) nodes (4 blocks per lane);
 // level l + 1 has ceil(n[l] / 256) nodes (4 nodes per lane, 64 lanes per wave) while n[l] > 256;
 // level `levels` (<= 256 nodes) is swept by one wavefront.
+// Blocks per tile of the element layout (include/lqt.h) and of every tiled record array.
+constexpr int kEltTile = 512;
 constexpr int kLaneChunk = 4;
 constexpr int kWaveSpan = 256;
 constexpr int kLbGroupTiles = 64;  // tiles per group record of the single-pass scans
@@ -112,7 +114,7 @@ struct LbRecs {
 };
 
 // Workspace pointers of one call (all per-level arrays hold `batch` problems back to back, each in
-// tiles of 256 items).
+// tiles of 512 items).
 struct Work {
   void* consts = nullptr;
   LbRecs lbv, lbt;                   // single-pass value and trajectory scans (per-lane path)

@@ -1273,14 +1273,15 @@ struct TrajAlg {
 };
 
 // ------------------------------------------------------------------------------------------
-// Single-pass scans (lookback.hpp).  One wave per tile of 256 blocks (4 consecutive blocks per
-// lane, the tile of the element layout); the wave reduces its tile, resolves the state at the
+// Single-pass scans (lookback.hpp).  One wave per tile of 64 c blocks (c consecutive blocks per
+// lane: c = 8 covers one tile of the element layout with full 512-byte rows, c = 4 half a tile
+// with full 256-byte half-rows); the wave reduces its tile, resolves the state at the
 // tile's free end from the records of the tiles before it in the flow, carries that state to
 // every lane through the lane's exclusive product, and sweeps the lane's blocks.
 // ------------------------------------------------------------------------------------------
 // Value scan (Theorem 6, Lemma 7, terminal element of Sec. IV-D).  The flow is backward in time:
 // place i takes tile G - 1 - i, so the first place holds the end of the horizon.  Tiles are 512
-// blocks, 8 per lane (two tiles of the element layout): with four waves per CU at most (a lane
+// blocks, 8 per lane (one tile of the element layout): with four waves per CU at most (a lane
 // holds two tuples and a Lemma 7 combination), a horizon of 2^20 blocks then needs two rounds of
 // resident waves instead of four, and the per-tile costs that do not grow with the tile (the
 // lane scan of the wave and the look-back) are spread over twice the blocks.

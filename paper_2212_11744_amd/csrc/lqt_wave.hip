@@ -19,7 +19,7 @@ namespace lqt {
 namespace {
 
 constexpr int NM = 16;      // largest state size
-constexpr int kTile = 256;  // element tile (blocks per tile of the element layout)
+constexpr int kTile = kEltTile;  // element tile (blocks per tile of the element layout)
 #define WDEV __device__ __forceinline__
 
 WDEV int lane_id() { return threadIdx.x; }
@@ -296,11 +296,11 @@ struct GRef {
 };
 
 // Element k of problem p in the tiled element layout (tiles of kTile blocks, value-major inside a
-// tile, block k at column 64 (k % 4) + (k % 256) / 4).
+// tile, block k at column 64 (k % 8) + (k % 512) / 8).
 template <class R>
 WDEV GRef<R> elt_ref(R* elts, int p, long k, long T, int NE) {
   const long nt = (T + kTile - 1) / kTile;
-  return {elts + ((p * nt + k / kTile) * NE) * kTile + ((k & 3) << 6) + ((k & 255) >> 2), kTile};
+  return {elts + ((p * nt + k / kTile) * NE) * kTile + ((k & 7) << 6) + ((k & 511) >> 3), kTile};
 }
 template <class R>
 WDEV GRef<R> rec_ref(R* rec, int p, long k, long n, int NE) {

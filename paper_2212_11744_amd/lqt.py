@@ -224,16 +224,16 @@ def element_count(nx: int) -> int:
     return int(lib().lqt_element_count(nx))
 
 
-ELEMENT_TILE = 256
+ELEMENT_TILE = 512
 
 
 def element_tiles(T: int) -> int:
-    """Number of 256-block tiles of the element layout."""
+    """Number of 512-block tiles of the element layout."""
     return (T + ELEMENT_TILE - 1) // ELEMENT_TILE
 
 
 def empty_elements(prob: "DeviceProblem") -> torch.Tensor:
-    """Element array [batch][ceil(T/256)][NE][256] (tiled structure of arrays, include/lqt.h)."""
+    """Element array [batch][ceil(T/512)][NE][512] (tiled structure of arrays, include/lqt.h)."""
     return torch.empty(prob.batch, element_tiles(prob.T), element_count(prob.nx), ELEMENT_TILE,
                        dtype=prob.dtype, device=prob.t.device)
 
@@ -259,7 +259,7 @@ def _empty(prob, *shape):
 
 def build_elements(prob: DeviceProblem, elts: Optional[torch.Tensor] = None,
                    ws: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Elements [batch][ceil(T/256)][NE][256] (tiled structure of arrays, A stored as A - I)."""
+    """Elements [batch][ceil(T/512)][NE][512] (tiled structure of arrays, A stored as A - I)."""
     elts = empty_elements(prob) if elts is None else elts
     ws = workspace(prob, CALL_BUILD) if ws is None else ws
     d, p = prob.dims(), prob.ptrs()

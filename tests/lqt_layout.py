@@ -5,24 +5,24 @@ import numpy as np
 from paper_2212_11744_amd import lqt
 
 
-TILE = 256
+TILE = 512
 
 
 def tile_position(k):
-    """(tile, column) of item k: tiles of 256 items, column 64 (k % 4) + (k % 256) // 4."""
+    """(tile, column) of item k: tiles of 512 items, column 64 (k % 8) + (k % 512) // 8."""
     k = np.asarray(k)
-    return k // TILE, 64 * (k % 4) + (k % TILE) // 4
+    return k // TILE, 64 * (k % 8) + (k % TILE) // 8
 
 
 def untile(elts, T):
-    """[ntile][NE][256] -> [NE][T]."""
+    """[ntile][NE][512] -> [NE][T]."""
     e = np.asarray(elts, dtype=np.float64)
     g, c = tile_position(np.arange(T))
     return e[g, :, c].T
 
 
 def tile(e):
-    """[NE][T] -> [ntile][NE][256] (padding zero)."""
+    """[NE][T] -> [ntile][NE][512] (padding zero)."""
     NE, T = e.shape
     nt = (T + TILE - 1) // TILE
     out = np.zeros((nt, NE, TILE))
@@ -32,7 +32,7 @@ def tile(e):
 
 
 def soa_to_dense(elts, nx, T):
-    """[ntile][NE][256] array (one problem) -> dict of A, b, C, eta, J with A the full matrix."""
+    """[ntile][NE][512] array (one problem) -> dict of A, b, C, eta, J with A the full matrix."""
     e = untile(elts, T)
     sl = lqt.element_slices(nx)
     iu = np.triu_indices(nx)
@@ -48,7 +48,7 @@ def soa_to_dense(elts, nx, T):
 
 
 def dense_to_soa(el, nx, Ad=None):
-    """dict of A, b, C, eta, J (T leading) -> [ntile][NE][256] (A - I, packed upper triangles)."""
+    """dict of A, b, C, eta, J (T leading) -> [ntile][NE][512] (A - I, packed upper triangles)."""
     T = el["A"].shape[0]
     iu = np.triu_indices(nx)
     Ad = el["A"] - np.eye(nx)[None] if Ad is None else Ad

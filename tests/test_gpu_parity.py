@@ -64,12 +64,12 @@ def test_solve_config1(dtype):
     dp = lqt.DeviceProblem.from_problems([p], dtype=dtype)
     out = lqt.solve(dp)
     torch.cuda.synchronize()
-    _check_solution(p, out, ref, dtype, label="fused")
+    _check_solution(p, out, ref, dtype, label="lqt_solve")
     # Stage-split calls give the same results.
     elts = lqt.build_elements(dp)
     S, v = lqt.scan_value(dp, elts)
     x, u = lqt.forward_traj(dp, elts, S, v)
-    _check_solution(p, {"S": S, "v": v, "x": x, "u": u}, ref, dtype, label="split")
+    _check_solution(p, {"S": S, "v": v, "x": x, "u": u}, ref, dtype, label="stage calls")
     if dtype == torch.float64:
         for a, b in ((S, out["S"]), (x, out["x"]), (u, out["u"])):
             assert relerr(_np(a), _np(b)) < 1e-13
