@@ -690,7 +690,7 @@ lqt_status run_value(const Ops* o, const KProb& kp, const Work& w, const void* e
 // Trajectory scan (single pass; per-lane path): x_k, u_k of every boundary.
 lqt_status run_traj(const Ops* o, const KProb& kp, const Work& w, const void* elts,
                     const void* S, const void* v, void* x, void* u, hipStream_t s) {
-  const int c = scan_chunk(kp.T, kScanMaxTChunk);
+  const int c = traj_chunk(kp.T);
   LQT_HIP(lb_clear(w.lbt, s));
   LQT_HIP(o->tscan(kp, elts, S, v, x, u, lb_for(w.lbt, kp.T, c), c, s));
   return LQT_OK;

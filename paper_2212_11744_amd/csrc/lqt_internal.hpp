@@ -79,15 +79,19 @@ constexpr int kLbGroupTiles = 64;  // tiles per group record of the single-pass 
 // Blocks per lane of the single-pass scans (a tile is one wave: 64 lanes), chosen from the
 // horizon.  A longer chunk costs serial steps per lane; more tiles cost look-back depth (about
 // log2 of the tiles in flight, in Lemma 7 combinations) and, beyond the ~1024 waves resident at
-// once, another round of tiles.  Measured on the FP64 point mass (value scan): 4 blocks per lane
-// are best from 2^13 to 2^18 blocks (2^16: 73 us vs 89 us with 1), 8 from 2^19 on (2^20: 359 us
-// vs 395 us with 4); very short horizons do best with 1 (64 blocks: one tile, no serial steps).
+// once, another round of tiles.  Measured on the FP64 point mass (value scan, 512-block element
+// tiles): 1 block per lane is best up to 2^11 blocks, 2 up to 2^14, 4 up to 2^17 (2^16: 78 us vs
+// 84 with 2 and 87 with 8), 8 from 2^18 on (2^18: 110 us vs 122 with 4; 2^20: 315 us vs 407).
 // The trajectory scan keeps its lanes' block maps in registers and stops at 4.  The records are
 // laid out for one block per lane, so they hold any chunk's tiles.
 constexpr int kScanMaxVChunk = 8, kScanMaxTChunk = 4;
 inline int scan_chunk(long T, int cmax) {
-  const int c = T <= (1L << 11) ? 1 : T <= (1L << 13) ? 2 : T < (1L << 19) ? 4 : 8;
+  const int c = T <= (1L << 11) ? 1 : T <= (1L << 14) ? 2 : T <= (1L << 17) ? 4 : 8;
   return c < cmax ? c : cmax;
+}
+// Trajectory scan: 1 block per lane up to 2^11 blocks, 2 up to 2^13, 4 beyond (its maximum).
+inline int traj_chunk(long T) {
+  return T <= (1L << 11) ? 1 : T <= (1L << 13) ? 2 : kScanMaxTChunk;
 }
 
 struct Tree {
