@@ -46,6 +46,14 @@ struct CS {
 };
 
 __device__ inline long gid() { return (long)blockIdx.x * blockDim.x + threadIdx.x; }
+// The item of this lane in kernels that handle one independent item per lane and store tiled
+// records (64-thread workgroups, grid_tile_rows): wave r of the 8 waves of tile t takes the items
+// 512 t + 8 l + r (lane l), which share row r of the tile, so each store of one value is a whole
+// 512-byte row instead of eight 64-byte segments.
+__device__ inline long tile_row_item() {
+  const long g = gid();
+  return (g & ~511L) | ((g & 63) << 3) | ((g >> 6) & 7);
+}
 
 // ------------------------------------------------------------------------------------------
 // Element build (Theorem 8):
@@ -601,7 +609,7 @@ LQT_DEV void fwd_parts(const KProb& kp, const Blk& bk, int nsteps, Tup<N, R>& ou
 template <int N, int NU, class R, bool CONST_COEF>
 __global__ __launch_bounds__(kThreads) void k_build_fwd(const KProb kp, R* __restrict__ elts) {
   const int p = blockIdx.y;
-  const long k = gid();
+  const long k = tile_row_item();
   if (k >= kp.T) return;
   Tup<N, R> out;
   fwd_parts<N, NU, R, CONST_COEF, true>(kp, blk_plain(kp, p, k), kp.n, out, NoStep{});
@@ -844,7 +852,7 @@ LQT_DEV void element_at(const KProb& kp, int p, long k, Tup<N, R>& out) {
 template <int N, int NU, class R, bool CONST_COEF>
 __global__ __launch_bounds__(kThreads) void k_build(const KProb kp, R* __restrict__ elts) {
   const int p = blockIdx.y;
-  const long k = gid();
+  const long k = tile_row_item();
   if (k >= kp.T) return;
   Tup<N, R> out;
   element_at<N, NU, R, CONST_COEF>(kp, p, k, out);
@@ -1967,6 +1975,10 @@ __global__ __launch_bounds__(kThreads) void k_dense(const KProb kp, const R* __r
 inline dim3 grid_lanes(long n, int batch) {
   return dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)batch, 1);
 }
+// Whole tiles of kTile items (kTile / kThreads waves each), for kernels indexed by tile_row_item.
+inline dim3 grid_tile_rows(long n, int batch) {
+  return dim3((unsigned)((n + kTile - 1) / kTile * (kTile / kThreads)), (unsigned)batch, 1);
+}
 inline dim3 grid_waves(long waves, int batch) { return dim3((unsigned)waves, (unsigned)batch, 1); }
 
 template <int N, int NU, class R>
@@ -1974,10 +1986,10 @@ struct L {
   static hipError_t build(const KProb& kp, void* elts, hipStream_t s) {
     const bool cc = !kp.F_sampled && !kp.L_sampled && !kp.has_c;
     if (cc)
-      hipLaunchKernelGGL((k_build<N, NU, R, true>), grid_lanes(kp.T, kp.batch), dim3(kThreads),
+      hipLaunchKernelGGL((k_build<N, NU, R, true>), grid_tile_rows(kp.T, kp.batch), dim3(kThreads),
                          0, s, kp, (R*)elts);
     else
-      hipLaunchKernelGGL((k_build<N, NU, R, false>), grid_lanes(kp.T, kp.batch), dim3(kThreads),
+      hipLaunchKernelGGL((k_build<N, NU, R, false>), grid_tile_rows(kp.T, kp.batch), dim3(kThreads),
                          0, s, kp, (R*)elts);
     return hipGetLastError();
   }
@@ -2072,10 +2084,10 @@ struct L {
   static hipError_t build_fwd(const KProb& kp, void* elts, hipStream_t s) {
     const bool cc = !kp.F_sampled && !kp.L_sampled && !kp.has_c;
     if (cc)
-      hipLaunchKernelGGL((k_build_fwd<N, NU, R, true>), grid_lanes(kp.T, kp.batch),
+      hipLaunchKernelGGL((k_build_fwd<N, NU, R, true>), grid_tile_rows(kp.T, kp.batch),
                          dim3(kThreads), 0, s, kp, (R*)elts);
     else
-      hipLaunchKernelGGL((k_build_fwd<N, NU, R, false>), grid_lanes(kp.T, kp.batch),
+      hipLaunchKernelGGL((k_build_fwd<N, NU, R, false>), grid_tile_rows(kp.T, kp.batch),
                          dim3(kThreads), 0, s, kp, (R*)elts);
     return hipGetLastError();
   }
