@@ -47,13 +47,18 @@ struct CS {
 
 __device__ inline long gid() { return (long)blockIdx.x * blockDim.x + threadIdx.x; }
 // The item of this lane in kernels that handle one independent item per lane and store tiled
-// records (64-thread workgroups, grid_tile_rows): wave r of the 8 waves of tile t takes the items
+// records (64-thread workgroups, grid_tile_rows): the wave for row r of tile t takes the items
 // 512 t + 8 l + r (lane l), which share row r of the tile, so each store of one value is a whole
-// 512-byte row instead of eight 64-byte segments.
+// 512-byte row instead of eight 64-byte segments.  (Placing the 8 rows of a tile on one XCD, with
+// wave w taking tile 8 (w / 64) + w % 8, measured no faster at 2^20 blocks: 0.300 ms both.)
 __device__ inline long tile_row_item() {
   const long g = gid();
   return (g & ~511L) | ((g & 63) << 3) | ((g >> 6) & 7);
 }
+// Short horizons keep consecutive items per wave (neighbouring blocks share reference samples, and
+// a few waves are latency-bound): rows per wave from 8 tiles on.
+constexpr long kTileRowMin = 8L * kTile;
+__device__ inline long build_item(long n) { return n >= kTileRowMin ? tile_row_item() : gid(); }
 
 // ------------------------------------------------------------------------------------------
 // Element build (Theorem 8):
@@ -609,7 +614,7 @@ LQT_DEV void fwd_parts(const KProb& kp, const Blk& bk, int nsteps, Tup<N, R>& ou
 template <int N, int NU, class R, bool CONST_COEF>
 __global__ __launch_bounds__(kThreads) void k_build_fwd(const KProb kp, R* __restrict__ elts) {
   const int p = blockIdx.y;
-  const long k = tile_row_item();
+  const long k = build_item(kp.T);
   if (k >= kp.T) return;
   Tup<N, R> out;
   fwd_parts<N, NU, R, CONST_COEF, true>(kp, blk_plain(kp, p, k), kp.n, out, NoStep{});
@@ -852,7 +857,7 @@ LQT_DEV void element_at(const KProb& kp, int p, long k, Tup<N, R>& out) {
 template <int N, int NU, class R, bool CONST_COEF>
 __global__ __launch_bounds__(kThreads) void k_build(const KProb kp, R* __restrict__ elts) {
   const int p = blockIdx.y;
-  const long k = tile_row_item();
+  const long k = build_item(kp.T);
   if (k >= kp.T) return;
   Tup<N, R> out;
   element_at<N, NU, R, CONST_COEF>(kp, p, k, out);
@@ -1975,8 +1980,10 @@ __global__ __launch_bounds__(kThreads) void k_dense(const KProb kp, const R* __r
 inline dim3 grid_lanes(long n, int batch) {
   return dim3((unsigned)((n + kThreads - 1) / kThreads), (unsigned)batch, 1);
 }
-// Whole tiles of kTile items (kTile / kThreads waves each), for kernels indexed by tile_row_item.
+// The grid of kernels indexed by build_item: whole tiles of kTile items (kTile / kThreads waves
+// each) when n >= kTileRowMin, else one lane per item.
 inline dim3 grid_tile_rows(long n, int batch) {
+  if (n < kTileRowMin) return grid_lanes(n, batch);
   return dim3((unsigned)((n + kTile - 1) / kTile * (kTile / kThreads)), (unsigned)batch, 1);
 }
 inline dim3 grid_waves(long waves, int batch) { return dim3((unsigned)waves, (unsigned)batch, 1); }
