@@ -234,7 +234,8 @@ bool use_wave(const lqt_dims* d) { return lane_ops(d->nx, d->nu, d->dtype) == nu
 // Blocks per wave at the bottom level of the wave path's trees for single solves and stage calls
 // (upper levels: kWaveUpperChunk), also the chunk the workspace is laid out for.  Measured on
 // single solves: 4 vs 8 gives nx = 16 at T = 2^14 1.55 vs 1.61 ms and at 2^12 0.68 vs 0.74 ms,
-// nx = 8 and 12 within 1 %; 16 is slower for all three.  A solve must not use fewer blocks per
+// nx = 8 and 12 within 1 %; 16 is slower for all three, and so are binary trees (2 per wave at
+// every level: nx = 16 1.61 ms, nx = 8 at 2^16 1.30 vs 1.23 ms, nx = 12 2.02 vs 1.92 ms).  A solve must not use fewer blocks per
 // wave than its workspace was laid out for: the level-1 tree arrays hold ceil(T / chunk) records.
 constexpr int kWaveChunk = 4;
 
