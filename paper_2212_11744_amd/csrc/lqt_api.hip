@@ -685,19 +685,21 @@ LbRecs lb_for(const LbRecs& r, long T, int chunk) {
 }
 
 // Value scan over elements (single pass; per-lane path).
+// cleared: the records' status words were already cleared (the solve clears both scans' at once).
 lqt_status run_value(const Ops* o, const KProb& kp, const Work& w, const void* elts, void* S,
-                     void* v, hipStream_t s) {
+                     void* v, hipStream_t s, bool cleared = false) {
   const int c = scan_chunk(kp.T, kScanMaxVChunk);
-  LQT_HIP(lb_clear(w.lbv, s));
+  if (!cleared) LQT_HIP(lb_clear(w.lbv, s));
   LQT_HIP(o->vscan(kp, elts, S, v, lb_for(w.lbv, kp.T, c), c, s));
   return LQT_OK;
 }
 
 // Trajectory scan (single pass; per-lane path): x_k, u_k of every boundary.
 lqt_status run_traj(const Ops* o, const KProb& kp, const Work& w, const void* elts,
-                    const void* S, const void* v, void* x, void* u, hipStream_t s) {
+                    const void* S, const void* v, void* x, void* u, hipStream_t s,
+                    bool cleared = false) {
   const int c = traj_chunk(kp.T);
-  LQT_HIP(lb_clear(w.lbt, s));
+  if (!cleared) LQT_HIP(lb_clear(w.lbt, s));
   LQT_HIP(o->tscan(kp, elts, S, v, x, u, lb_for(w.lbt, kp.T, c), c, s));
   return LQT_OK;
 }
@@ -947,8 +949,9 @@ lqt_status run_solve(const lqt_dims* dims, const KProb& kp, const Work& w, void*
                              lb_for(w.lbt, kp.T, queue_tchunk(cv)), cv, stream));
     return LQT_OK;
   }
-  LQT_TRY(run_value(op, kp, w, e, S, v, stream));
-  LQT_TRY(run_traj(op, kp, w, e, S, v, x, u, stream));
+  LQT_HIP(lb_clear2(w.lbv, w.lbt, stream));  // both scans' status words in one launch
+  LQT_TRY(run_value(op, kp, w, e, S, v, stream, true));
+  LQT_TRY(run_traj(op, kp, w, e, S, v, x, u, stream, true));
   return LQT_OK;
 }
 
