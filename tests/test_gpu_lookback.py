@@ -1,8 +1,8 @@
 """Single-pass value and trajectory scans (decoupled look-back) vs the oracle, through the C ABI.
 
 The scans give every tile (one wave; 1, 2, 4 or 8 blocks per lane, chosen from the horizon: value
-scan 1 up to 2^11 blocks, 2 up to 2^14, 4 up to 2^17, then 8; trajectory scan 1 up to 2^11, 2 up
-to 2^13, then 4) a place in the flow order from a counter; a tile resolves the state at its free end from up
+scan 1 up to 2^11 blocks, 2 up to 2^14, 4 up to 2^17, then 8; trajectory scan 1 up to 2^14, 2 up
+to 2^15, then 4) a place in the flow order from a counter; a tile resolves the state at its free end from up
 to 63 preceding tile records and then from group records (64 tiles each), 64 groups per round.
 The horizons below use every chunk size, put the last tile just before, on and after group
 boundaries, and go past the first 64 groups (a second round of group records); batches check
