@@ -81,7 +81,8 @@ constexpr int kLbGroupTiles = 64;  // tiles per group record of the single-pass 
 // log2 of the tiles in flight, in Lemma 7 combinations) and, beyond the ~1024 waves resident at
 // once, another round of tiles.  Measured on the FP64 point mass (value scan, 512-block element
 // tiles): 1 block per lane is best up to 2^11 blocks, 2 up to 2^14, 4 up to 2^17 (2^16: 78 us vs
-// 84 with 2 and 87 with 8), 8 from 2^18 on (2^18: 110 us vs 122 with 4; 2^20: 315 us vs 407).
+// 84 with 2 and 87 with 8), 8 from 2^18 on (2^18: 110 us vs 122 with 4; 2^20: 315 us vs 407;
+// 16 per lane, one round of resident tiles at 2^20, is slower again: 402 us).
 // The trajectory scan keeps its lanes' block maps in registers and stops at 4.  The records are
 // laid out for one block per lane, so they hold any chunk's tiles.
 constexpr int kScanMaxVChunk = 8, kScanMaxTChunk = 4;
