@@ -2464,7 +2464,7 @@ __global__ __launch_bounds__(64) void kw_m2_bottom(const KProb kp, int wc, const
   WS<R> scr = ws_at(sh + 2 * kTupW, &piv, n);
   R* S = sh + WM2Sh<N>::sweep;
   R* M = S + n * n;
-  R* Kc = M + n * n;
+  R* Kc = M + n * n;  // right after M: the state solve takes M and Kc as its 2 n^2 values
   R* v = Kc + n * n;
   R* x0 = v + n;
   R* x = x0 + n;
@@ -2549,7 +2549,7 @@ __global__ __launch_bounds__(64) void kw_dense(const KProb kp, const R* __restri
   // node-level scratch, beside both sweeps' areas
   R* Sn = sh + (WDenseSh<N>::all - WDenseSh<N>::extra);
   R* Mn = Sn + n * n;
-  R* Kc = Mn + n * n;
+  R* Kc = Mn + n * n;  // right after Mn: the state solve takes Mn and Kc as its 2 n^2 values
   R* vn = Kc + n * n;
   R* xk = vn + n;
   R* xn = xk + n;
