@@ -527,23 +527,6 @@ hipError_t lb_clear(const LbRecs& r, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ void k_lb_clear2(unsigned* __restrict__ a, long na, unsigned* __restrict__ b, long nb) {
-  for (long k = (long)blockIdx.x * blockDim.x + threadIdx.x; k < na + nb;
-       k += (long)gridDim.x * blockDim.x) {
-    if (k < na)
-      a[k] = 0u;
-    else
-      b[k - na] = 0u;
-  }
-}
-
-hipError_t lb_clear2(const LbRecs& a, const LbRecs& b, hipStream_t s) {
-  const long blocks = min((a.nwords + b.nwords + 255) / 256, 1024L);
-  hipLaunchKernelGGL(k_lb_clear2, dim3((unsigned)blocks), dim3(256), 0, s, a.ctr, a.nwords, b.ctr,
-                     b.nwords);
-  return hipGetLastError();
-}
-
 namespace {
 
 // ------------------------------------------------------------------------------------------
@@ -915,8 +898,8 @@ lqt_status run_solve(const lqt_dims* dims, const KProb& kp, const Work& w, void*
                      void* v, void* x, void* u, const SolveOpts& o, hipStream_t stream) {
   KProb kprep = kp;
   if (kp.seg) kprep.batch = kp.nseg;
-  LQT_HIP(prep(dims, kprep, w.consts, stream));
   if (use_wave(dims)) {
+    LQT_HIP(prep(dims, kprep, w.consts, stream));
     const WTree wt = wave_tree(dims->T, o.wave_chunk);
     if (kp.lti && !kp.seg && w.lti)
       LQT_HIP(wave_lti(kp, dims->dtype, w.lti, e, stream));
@@ -935,6 +918,8 @@ lqt_status run_solve(const lqt_dims* dims, const KProb& kp, const Work& w, void*
     return LQT_OK;
   }
   const Ops* op = lane_ops(dims->nx, dims->nu, dims->dtype);
+  // the constants, and both scans' status words cleared in the same launch
+  LQT_HIP(op->prep_clear(kprep, w.consts, w.lbv, w.lbt, stream));
   const bool lti = kp.lti && !kp.seg && w.lti;
   if (lti) {
     LQT_HIP(op->lti_prep(kp, w.lti, stream));
@@ -944,12 +929,10 @@ lqt_status run_solve(const lqt_dims* dims, const KProb& kp, const Work& w, void*
   }
   if (o.queue_chunk) {
     const int cv = o.queue_chunk;
-    LQT_HIP(lb_clear2(w.lbv, w.lbt, stream));
     LQT_HIP(op->scan_queue(kp, e, S, v, x, u, lb_for(w.lbv, kp.T, cv),
                              lb_for(w.lbt, kp.T, queue_tchunk(cv)), cv, stream));
     return LQT_OK;
   }
-  LQT_HIP(lb_clear2(w.lbv, w.lbt, stream));  // both scans' status words in one launch
   LQT_TRY(run_value(op, kp, w, e, S, v, stream, true));
   LQT_TRY(run_traj(op, kp, w, e, S, v, x, u, stream, true));
   return LQT_OK;

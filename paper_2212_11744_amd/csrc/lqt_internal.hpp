@@ -197,6 +197,10 @@ struct Ops {
   hipError_t (*build_ckpt)(const KProb&, void* elts, void* ckpt, hipStream_t);
   // value and trajectory scans in one launch over a work queue (records lbv, lbt cleared; value chunk
   // cv = 1, 4 or 8 blocks per lane, trajectory chunk queue_tchunk(cv))
+  // the constants prep and, in the same launch, the zeroing of both single-pass scans' status
+  // words (the full solve: one launch less)
+  hipError_t (*prep_clear)(const KProb&, void* consts, const LbRecs& a, const LbRecs& b,
+                           hipStream_t);
   hipError_t (*scan_queue)(const KProb&, const void* elts, void* S, void* v, void* x, void* u,
                              const LbRecs& lbv, const LbRecs& lbt, int cv, hipStream_t);
 };
@@ -336,10 +340,9 @@ struct SolveOpts {
   int queue_chunk = 0;
 };
 
-// Zeroes the counter and status words of a single-pass scan (before every launch).
+// Zeroes the counter and status words of a single-pass scan (before every launch; the full solve
+// clears both of its scans' words in its constants launch, Ops::prep_clear).
 hipError_t lb_clear(const LbRecs& r, hipStream_t s);
-// The same for two record sets in one launch.
-hipError_t lb_clear2(const LbRecs& a, const LbRecs& b, hipStream_t s);
 
 // Trajectory chunk of the work-queue scans for value chunk cv.
 inline int queue_tchunk(int cv) { return cv < 4 ? cv : 4; }

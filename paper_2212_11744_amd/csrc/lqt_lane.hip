@@ -1085,8 +1085,23 @@ LQT_DEV void gain_at(const KProb& kp, int p, long k, R (&Kc)[NU][N]) {
 // Per-problem constants (see lqt_internal.hpp), fully unrolled for the sizes of this path:
 // R = Lr Lr^T (Cholesky), W = Lr^{-T}, Rinv = W W^T, Lc = L W, G = Lc Lc^T, Kc = Rinv L^T.
 // ------------------------------------------------------------------------------------------
+// Workgroups from prep_blocks on zero the na + nb status words za, zb instead (nullable).
 template <int N, int NU, class R>
-__global__ __launch_bounds__(kThreads) void k_prep_lane(const KProb kp, R* __restrict__ consts) {
+__global__ __launch_bounds__(kThreads) void k_prep_lane(const KProb kp, R* __restrict__ consts,
+                                                         int prep_blocks, unsigned* __restrict__ za,
+                                                         long na, unsigned* __restrict__ zb,
+                                                         long nb) {
+  if ((int)blockIdx.x >= prep_blocks) {
+    const long stride = (long)(gridDim.x - prep_blocks) * blockDim.x;
+    for (long k = (long)(blockIdx.x - prep_blocks) * blockDim.x + threadIdx.x; k < na + nb;
+         k += stride) {
+      if (k < na)
+        za[k] = 0u;
+      else
+        zb[k - na] = 0u;
+    }
+    return;
+  }
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= kp.batch) return;
   using C = CS<N, NU>;
@@ -2058,8 +2073,18 @@ struct L {
     return hipGetLastError();
   }
   static hipError_t prep(const KProb& kp, void* consts, hipStream_t s) {
-    hipLaunchKernelGGL((k_prep_lane<N, NU, R>), dim3((kp.batch + kThreads - 1) / kThreads),
-                       dim3(kThreads), 0, s, kp, (R*)consts);
+    const int pb = (kp.batch + kThreads - 1) / kThreads;
+    hipLaunchKernelGGL((k_prep_lane<N, NU, R>), dim3(pb), dim3(kThreads), 0, s, kp, (R*)consts, pb,
+                       (unsigned*)nullptr, 0L, (unsigned*)nullptr, 0L);
+    return hipGetLastError();
+  }
+  static hipError_t prep_clear(const KProb& kp, void* consts, const LbRecs& a, const LbRecs& b,
+                               hipStream_t s) {
+    const int pb = (kp.batch + kThreads - 1) / kThreads;
+    const long need = (a.nwords + b.nwords + kThreads - 1) / kThreads;
+    const long cb = need < 4096 ? need : 4096;
+    hipLaunchKernelGGL((k_prep_lane<N, NU, R>), dim3((unsigned)(pb + cb)), dim3(kThreads), 0, s, kp,
+                       (R*)consts, pb, a.ctr, a.nwords, b.ctr, b.nwords);
     return hipGetLastError();
   }
   // Method 2: forward prefix scan over the node products (the value tree's level 1 and up)
@@ -2145,7 +2170,8 @@ struct L {
     static const Ops o = {prep,    build,          vscan,        tscan,    vreduce0,
                           lti_prep,       lti_build,    build_fwd,
                           m2_up,   m2_top,         m2_down,      m2_bottom,
-                          dense,   build_split,    build_ckpt,   scan_queue};
+                          dense,   build_split,    build_ckpt,   prep_clear,
+                          scan_queue};
     return &o;
   }
 };
