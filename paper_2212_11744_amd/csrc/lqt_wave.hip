@@ -22,8 +22,10 @@ constexpr int NM = 16;      // largest state size
 constexpr int kTile = kEltTile;  // element tile (blocks per tile of the element layout)
 #define WDEV __device__ __forceinline__
 
-WDEV int lane_id() { return threadIdx.x; }
-WDEV void wsync() { __syncthreads(); }  // one wavefront per workgroup
+WDEV int lane_id() { return threadIdx.x & 63; }
+// A workgroup barrier.  Most kernels run one wavefront per workgroup; the two-wave tree kernels
+// (kw_vreduce2, kw_vdown2) have both of their waves pass the same number of these.
+WDEV void wsync() { __syncthreads(); }
 
 WDEV int pk(int i, int j, int n) {  // packed upper index
   if (i > j) {
@@ -2058,6 +2060,108 @@ __global__ __launch_bounds__(64) void kw_vdown(int, int wc, const R* __restrict_
                         val_out);
 }
 
+// Two-wave form of a value-tree level above the leaves, for levels of few nodes (each node's
+// chain of combinations, not the device's throughput, sets their time).  Node i of level l + 1
+// from its four children t0 .. t3 of level l: wave 0 forms t0 (x) t1 while wave 1 forms
+// t2 (x) t3, then wave 0 combines the two (the Lemma 7 combination is associative), two
+// combinations deep instead of three.  Wave 1 also writes t2 (x) t3 over t2's record, where the
+// down-sweep of the same level (kw_vdown2) reads it: that sweep needs the pair product and not
+// t2.  A node with fewer children (the last of a level) takes the sequential product on both
+// waves and wave 0 stores it.  Where one wave has a step the other lacks, the other repeats a
+// step of the same kind on its own LDS copy or takes the barrier alone, so both pass the same
+// barriers; the wave index is made wave-uniform (readfirstlane), so such branches are scalar.
+template <int N, class R>
+__global__ __launch_bounds__(128) void kw_vreduce2(int wc, R* __restrict__ src, long n_src,
+                                                   R* __restrict__ dst, long n_dst) {
+  constexpr int n = N, kTupW = WSh<N>::kTupW;
+  __shared__ R sh[2][WSh<N>::vreduce];
+  __shared__ int piv[2];
+  if ((long)blockIdx.x >= n_dst) return;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int p = blockIdx.y, NE = ne_w(n);
+  const long i = blockIdx.x;
+  WT<R> acc = wt_at(sh[w], n), x = wt_at(sh[w] + kTupW, n);
+  WS<R> scr = ws_at(sh[w] + 2 * kTupW, &piv[w], n);
+  const R* in = src;
+  const long j0 = i * wc, j1 = min(j0 + wc, n_src);
+  if (j1 - j0 == 4) {
+    const long ja = j0 + 2 * w;
+    wt_load<PlainAcc>(x, rec_ref(in, p, ja, n_src, NE), n);
+    wt_load<PlainAcc>(acc, rec_ref(in, p, ja + 1, n_src, NE), n);
+    w_combine<N>(x, acc, acc, scr, n);  // wave w: t_2w (x) t_2w+1
+    if (w == 1)
+      wt_store<PlainAcc>(acc, rec_ref(src, p, j0 + 2, n_src, NE), n);
+    else
+      wsync();
+    // wave 0: (t0 t1) (x) (t2 t3) from wave 1's LDS; wave 1: a combination of its own copy of t2
+    // with itself, discarded (it leaves wave 1's product, which wave 0 reads, untouched)
+    const WT<R> right = wt_at(sh[1], n);
+    w_combine<N>(w == 0 ? acc : x, w == 0 ? right : x, w == 0 ? acc : x, scr, n);
+  } else {
+    wt_load<PlainAcc>(acc, rec_ref(in, p, j1 - 1, n_src, NE), n);
+    for (long j = j1 - 2; j >= j0; --j) {
+      wt_load<PlainAcc>(x, rec_ref(in, p, j, n_src, NE), n);
+      w_combine<N>(x, acc, acc, scr, n);
+    }
+  }
+  if (w == 0)
+    wt_store<PlainAcc>(acc, rec_ref(dst, p, i, n_dst, NE), n);
+  else
+    wsync();
+}
+
+// Down-sweep of a level reduced by kw_vreduce2: the values at the right ends of node i's children
+// from the node's own.  With four children, wave 0 stores the node's value as child 3's and folds
+// t3 into it (child 2) while wave 1 folds the pair product t2 (x) t3 (child 1) and then t1 (child
+// 0): two folds deep instead of three.  Fewer children: the sequential sweep on both waves, wave 0
+// storing.  Barriers as in kw_vreduce2.
+template <int N, class R>
+__global__ __launch_bounds__(128) void kw_vdown2(int wc, const R* __restrict__ tup, long n_child,
+                                                 const R* __restrict__ val_in, long n_par,
+                                                 R* __restrict__ val_out) {
+  constexpr int n = N, kTupW = WSh<N>::kTupW, kScr = WSh<N>::kScr;
+  __shared__ R sh[2][WSh<N>::vfold];
+  __shared__ int piv[2];
+  if ((long)blockIdx.x >= n_par) return;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int p = blockIdx.y, NE = ne_w(n), VR = n * n + n;
+  const long i = blockIdx.x;
+  WT<R> a = wt_at(sh[w], n);
+  WS<R> scr = ws_at(sh[w] + kTupW, &piv[w], n);
+  R* S = sh[w] + kTupW + kScr;
+  R* v = S + n * n;
+  R* out = val_out + (long)p * n_child * VR;
+  val_ld<PlainAcc>(S, v, val_in + ((long)p * n_par + i) * VR, n);
+  const long j0 = i * wc, j1 = min(j0 + wc, n_child);
+  if (j1 - j0 == 4) {
+    if (w == 0)
+      val_st<PlainAcc>(S, v, out + (j0 + 3) * VR, n);
+    else
+      wsync();
+    // wave 0: t3 (child 2); wave 1: the pair product t2 (x) t3 in t2's slot (child 1)
+    wt_load<PlainAcc>(a, rec_ref(tup, p, w == 0 ? j0 + 3 : j0 + 2, n_child, NE), n);
+    w_fold<N>(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
+    val_st<PlainAcc>(S, v, out + (w == 0 ? j0 + 2 : j0 + 1) * VR, n);
+    // wave 1: t1 (child 0); wave 0 folds the same record into its own copy, discarded
+    wt_load<PlainAcc>(a, rec_ref(tup, p, j0 + 1, n_child, NE), n);
+    w_fold<N>(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
+    if (w == 1)
+      val_st<PlainAcc>(S, v, out + j0 * VR, n);
+    else
+      wsync();
+  } else {
+    for (long j = j1 - 1; j >= j0; --j) {
+      if (w == 0)
+        val_st<PlainAcc>(S, v, out + j * VR, n);
+      else
+        wsync();
+      if (j == j0) break;
+      wt_load<PlainAcc>(a, rec_ref(tup, p, j, n_child, NE), n);
+      w_fold<N>(a, S, v, scr, n, (R*)nullptr, (R*)nullptr);
+    }
+  }
+}
+
 // Values of every block from the value at the right end of each chunk; level 1 of the
 // trajectory tree (composition of the chunk's block maps) when maps1 != nullptr, and every
 // block's closed-loop map ([batch][T] records P = Psi - I, q = alpha; the fold computes it on the
@@ -2891,6 +2995,11 @@ hipError_t wave_dense_t(const KProb& kp, const void* S, const void* v, const voi
   return hipGetLastError();
 }
 
+// Largest level (nodes x problems) that the value tree runs on two waves per node: its
+// workgroups hold two bodies' LDS each (51 KB at nx = 16 in FP64, three per CU), so wider levels,
+// whose time is throughput rather than chain latency, keep one wave per node.
+constexpr long kTwoWaveNodes = 512;
+
 template <int N, class R>
 hipError_t wave_value_t(const KProb& kp, const WTree& t, const Work& w, const void* elts, void* S,
                         void* v, void* maps1, hipStream_t s) {
@@ -2898,15 +3007,30 @@ hipError_t wave_value_t(const KProb& kp, const WTree& t, const Work& w, const vo
   const dim3 b(64);
   hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, n, wc, 1,
                      (const R*)elts, t.n[0], (R*)w.vtup[1], t.n[1]);
-  for (int l = 1; l < t.levels; ++l)
-    hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n,
-                       t.wcs[l], 0, (const R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1], t.n[l + 1]);
+  // Levels of few nodes run on two waves per node (kw_vreduce2 / kw_vdown2); a level's
+  // reduce and down-sweep take the same form (the two-wave reduce leaves pair products in the
+  // records its down-sweep reads).
+  auto two_wave = [&](int l) { return t.wcs[l] == 4 && t.n[l + 1] * kp.batch <= kTwoWaveNodes; };
+  for (int l = 1; l < t.levels; ++l) {
+    if (two_wave(l))
+      hipLaunchKernelGGL((kw_vreduce2<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), dim3(128), 0,
+                         s, t.wcs[l], (R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1], t.n[l + 1]);
+    else
+      hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n,
+                         t.wcs[l], 0, (const R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1], t.n[l + 1]);
+  }
   hipLaunchKernelGGL((kw_vtop<N, R>), dim3(1, kp.batch), b, 0, s, kp, (const R*)w.vtup[t.levels],
                      t.n[t.levels], (R*)w.vval[t.levels]);
-  for (int l = t.levels - 1; l >= 1; --l)
-    hipLaunchKernelGGL((kw_vdown<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n,
-                       t.wcs[l], (const R*)w.vtup[l], t.n[l], (const R*)w.vval[l + 1], t.n[l + 1],
-                       (R*)w.vval[l]);
+  for (int l = t.levels - 1; l >= 1; --l) {
+    if (two_wave(l))
+      hipLaunchKernelGGL((kw_vdown2<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), dim3(128), 0,
+                         s, t.wcs[l], (const R*)w.vtup[l], t.n[l], (const R*)w.vval[l + 1],
+                         t.n[l + 1], (R*)w.vval[l]);
+    else
+      hipLaunchKernelGGL((kw_vdown<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n,
+                         t.wcs[l], (const R*)w.vtup[l], t.n[l], (const R*)w.vval[l + 1],
+                         t.n[l + 1], (R*)w.vval[l]);
+  }
   hipLaunchKernelGGL((kw_vbottom<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, wc,
                      (const R*)elts, (const R*)w.vval[1], t.n[1], (R*)S, (R*)v, (R*)maps1,
                      (R*)(maps1 ? w.bmap : nullptr));

@@ -2,9 +2,11 @@
 
 Same tolerances as the per-lane path: normwise 1e-9 in FP64 and 1e-4 in FP32 against the FP64
 oracle, for elements, value matrices, trajectories and controls.  The scan trees of this path
-reduce 4 blocks per wave at the bottom level and 4 nodes per wave above it (single solves), so
-horizons around multiples and powers of 4 and 8 exercise ragged last nodes and one to six tree
-levels.  The random time-varying nx = 16 workload
+reduce 4 blocks per wave at the bottom level and 4 children per node above it (single solves), so
+horizons around multiples and powers of 4 and 8 exercise ragged last nodes (of 1, 2 and 3
+children) and one to six tree levels.  Levels of at most 512 nodes run on two waves per node
+(pair products, the last node sequential); 8193 blocks give a level of 513 nodes on one wave
+below levels on two.  The random time-varying nx = 16 workload
 (T = 2^14, F(t) sampled) is compared at full size.
 """
 import numpy as np
@@ -58,9 +60,10 @@ def test_sizes_with_time_varying_F_and_drift(nx, nu):
         assert relerr(el[k], el_ref[k]) < 1e-9, f"element {k}"
 
 
-@pytest.mark.parametrize("T", [1, 2, 3, 4, 5, 7, 8, 9, 17, 63, 64, 65, 257, 513, 4097])
+@pytest.mark.parametrize("T", [1, 2, 3, 4, 5, 7, 8, 9, 17, 22, 26, 32, 63, 64, 65, 257, 513, 4097,
+                               8193])
 def test_tree_shapes(T):
-    """One to six tree levels with 4 nodes per wave, ragged last nodes."""
+    """One to six tree levels with 4 children per node, ragged last nodes."""
     p = W.random_stable(200 + T, nx=6, nu=3, T=T, n=2, tf=0.004 * T + 0.3, time_varying=False)
     ref = O.solve(p)
     out = lqt.solve(lqt.DeviceProblem.from_problems([p]))
