@@ -117,6 +117,17 @@ def test_batch(dtype):
         _check(out, O.solve(p), dtype, b=b, label=f"member {b}")
 
 
+def test_batch_one_and_two_wave_levels():
+    """8 problems of 1100 blocks: a level of 69 nodes per problem (552 in the launch) on one wave
+    per node under levels of 18, 5 and 2 nodes on two (ragged last nodes of 2 and 1 children)."""
+    probs = [W.random_stable(90 + i, nx=6, nu=3, T=1100, n=2, tf=4.7) for i in range(8)]
+    for p in probs[1:]:
+        p.L = probs[0].L
+    out = lqt.solve(lqt.DeviceProblem.from_problems(probs))
+    for b, p in enumerate(probs):
+        _check(out, O.solve(p), torch.float64, b=b, label=f"member {b}")
+
+
 def test_fp32_nx16():
     p = W.random_stable(3, nx=16, nu=4, T=512, n=4, tf=10.0 * 512 / 2 ** 14)
     out = lqt.solve(lqt.DeviceProblem.from_problems([p], dtype=torch.float32))
