@@ -2070,7 +2070,9 @@ __global__ __launch_bounds__(64) void kw_vdown(int, int wc, const R* __restrict_
 // waves and wave 0 stores it.  Where one wave has a step the other lacks, the other repeats a
 // step of the same kind on its own LDS copy or takes the barrier alone, so both pass the same
 // barriers; the wave index is made wave-uniform (readfirstlane), so such branches are scalar.
-template <int N, class R>
+// LEFT: keep t0 (x) t1 over t1's record instead, for Method 2's down-sweep (kw_m2_down2), which
+// builds prefixes from the left and needs t0, the left pair and t2.
+template <int N, class R, bool LEFT = false>
 __global__ __launch_bounds__(128) void kw_vreduce2(int wc, R* __restrict__ src, long n_src,
                                                    R* __restrict__ dst, long n_dst) {
   constexpr int n = N, kTupW = WSh<N>::kTupW;
@@ -2089,8 +2091,8 @@ __global__ __launch_bounds__(128) void kw_vreduce2(int wc, R* __restrict__ src, 
     wt_load<PlainAcc>(x, rec_ref(in, p, ja, n_src, NE), n);
     wt_load<PlainAcc>(acc, rec_ref(in, p, ja + 1, n_src, NE), n);
     w_combine<N>(x, acc, acc, scr, n);  // wave w: t_2w (x) t_2w+1
-    if (w == 1)
-      wt_store<PlainAcc>(acc, rec_ref(src, p, j0 + 2, n_src, NE), n);
+    if (w == (LEFT ? 0 : 1))
+      wt_store<PlainAcc>(acc, rec_ref(src, p, LEFT ? j0 + 1 : j0 + 2, n_src, NE), n);
     else
       wsync();
     // wave 0: (t0 t1) (x) (t2 t3) from wave 1's LDS; wave 1: a combination of its own copy of t2
@@ -2549,6 +2551,58 @@ __global__ __launch_bounds__(64) void kw_m2_down(int wc, const R* __restrict__ t
                     pre_out, run);
 }
 
+// Down-sweep of a level reduced by kw_vreduce2<N, R, true> (left pair products t0 (x) t1 in t1's
+// records): with four children, wave 0 stores the node's prefix as child 0's and forms
+// prefix (x) t0 (child 1) while wave 1 forms prefix (x) (t0 t1) (child 2) and then (x) t2
+// (child 3): two combinations deep instead of three.  Fewer children: the sequential sweep on
+// both waves, wave 0 storing.  Barriers as in kw_vreduce2.
+template <int N, class R>
+__global__ __launch_bounds__(128) void kw_m2_down2(int wc, const R* __restrict__ tup, long n_child,
+                                                   const R* __restrict__ pre_in, long n_par,
+                                                   R* __restrict__ pre_out) {
+  constexpr int n = N, kTupW = WM2Sh<N>::kTupW;
+  __shared__ R sh[2][WM2Sh<N>::sweep];
+  __shared__ int piv[2];
+  if ((long)blockIdx.x >= n_par) return;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int p = blockIdx.y, NE = ne_w(n);
+  const long i = blockIdx.x;
+  WT<R> run = wt_at(sh[w], n), a = wt_at(sh[w] + kTupW, n);
+  WS<R> scr = ws_at(sh[w] + 2 * kTupW, &piv[w], n);
+  wt_load<PlainAcc>(run, rec_ref(pre_in, p, i, n_par, NE), n);
+  const long j0 = i * wc, j1 = min(j0 + wc, n_child);
+  if (j1 - j0 == 4) {
+    if (w == 0)
+      wt_store<PlainAcc>(run, rec_ref(pre_out, p, j0, n_child, NE), n);
+    else
+      wsync();
+    // wave 0: t0 (child 1); wave 1: the left pair product in t1's slot (child 2)
+    wt_load<PlainAcc>(a, rec_ref(tup, p, j0 + w, n_child, NE), n);
+    w_combine<N>(run, a, a, scr, n);
+    wt_store<PlainAcc>(a, rec_ref(pre_out, p, j0 + 1 + w, n_child, NE), n);
+    // wave 1: (x) t2 (child 3); wave 0 forms the same kind of product on its copy, discarded
+    wt_load<PlainAcc>(run, rec_ref(tup, p, j0 + 2, n_child, NE), n);
+    w_combine<N>(a, run, run, scr, n);
+    if (w == 1)
+      wt_store<PlainAcc>(run, rec_ref(pre_out, p, j0 + 3, n_child, NE), n);
+    else
+      wsync();
+  } else {
+    for (long j = j0; j < j1; ++j) {
+      if (w == 0)
+        wt_store<PlainAcc>(run, rec_ref(pre_out, p, j, n_child, NE), n);
+      else
+        wsync();
+      if (j + 1 == j1) break;
+      wt_load<PlainAcc>(a, rec_ref(tup, p, j, n_child, NE), n);
+      w_combine<N>(run, a, a, scr, n);
+      const WT<R> t = run;
+      run = a;
+      a = t;
+    }
+  }
+}
+
 template <int N, class R>
 __global__ __launch_bounds__(64) void kw_m2_bottom(const KProb kp, int wc, const R* __restrict__ elts,
                                                    const R* __restrict__ Sg,
@@ -2965,6 +3019,11 @@ hipError_t wave_lti_build_t(const KProb& kp, const void* tab, void* elts, hipStr
   return hipGetLastError();
 }
 
+// Largest level (nodes x problems) that the value and Method 2 trees run on two waves per node:
+// its workgroups hold two bodies' LDS each (51 KB at nx = 16 in FP64, three per CU), so wider
+// levels, whose time is throughput rather than chain latency, keep one wave per node.
+constexpr long kTwoWaveNodes = 512;
+
 template <int N, class R>
 hipError_t wave_method2_t(const KProb& kp, const WTree& t, const Work& w, const void* elts,
                           const void* S, const void* v, void* x, void* u, hipStream_t s) {
@@ -2972,15 +3031,30 @@ hipError_t wave_method2_t(const KProb& kp, const WTree& t, const Work& w, const 
   const dim3 b(64);
   hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, n, t.wc, 1,
                      (const R*)elts, t.n[0], (R*)w.vtup[1], t.n[1]);
-  for (int l = 1; l < t.levels; ++l)
-    hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n,
-                       t.wcs[l], 0, (const R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1], t.n[l + 1]);
+  // Levels of few nodes on two waves per node, reduce and down-sweep alike (the reduce leaves
+  // left pair products in the records the down-sweep reads).
+  auto two_wave = [&](int l) { return t.wcs[l] == 4 && t.n[l + 1] * kp.batch <= kTwoWaveNodes; };
+  for (int l = 1; l < t.levels; ++l) {
+    if (two_wave(l))
+      hipLaunchKernelGGL((kw_vreduce2<N, R, true>), dim3((unsigned)t.n[l + 1], kp.batch),
+                         dim3(128), 0, s, t.wcs[l], (R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1],
+                         t.n[l + 1]);
+    else
+      hipLaunchKernelGGL((kw_vreduce<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s, n,
+                         t.wcs[l], 0, (const R*)w.vtup[l], t.n[l], (R*)w.vtup[l + 1], t.n[l + 1]);
+  }
   hipLaunchKernelGGL((kw_m2_top<N, R>), dim3(1, kp.batch), b, 0, s, (const R*)w.vtup[t.levels],
                      t.n[t.levels], (R*)w.vpart[t.levels]);
-  for (int l = t.levels - 1; l >= 1; --l)
-    hipLaunchKernelGGL((kw_m2_down<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s,
-                       t.wcs[l], (const R*)w.vtup[l], t.n[l], (const R*)w.vpart[l + 1],
-                       t.n[l + 1], (R*)w.vpart[l]);
+  for (int l = t.levels - 1; l >= 1; --l) {
+    if (two_wave(l))
+      hipLaunchKernelGGL((kw_m2_down2<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), dim3(128), 0,
+                         s, t.wcs[l], (const R*)w.vtup[l], t.n[l], (const R*)w.vpart[l + 1],
+                         t.n[l + 1], (R*)w.vpart[l]);
+    else
+      hipLaunchKernelGGL((kw_m2_down<N, R>), dim3((unsigned)t.n[l + 1], kp.batch), b, 0, s,
+                         t.wcs[l], (const R*)w.vtup[l], t.n[l], (const R*)w.vpart[l + 1],
+                         t.n[l + 1], (R*)w.vpart[l]);
+  }
   hipLaunchKernelGGL((kw_m2_bottom<N, R>), dim3((unsigned)t.n[1], kp.batch), b, 0, s, kp, t.wc,
                      (const R*)elts, (const R*)S, (const R*)v, (const R*)w.vpart[1], t.n[1],
                      (R*)x, (R*)u);
@@ -2994,11 +3068,6 @@ hipError_t wave_dense_t(const KProb& kp, const void* S, const void* v, const voi
                      (const R*)S, (const R*)v, (const R*)x, (R*)Sd, (R*)vd, (R*)xd, (R*)ud);
   return hipGetLastError();
 }
-
-// Largest level (nodes x problems) that the value tree runs on two waves per node: its
-// workgroups hold two bodies' LDS each (51 KB at nx = 16 in FP64, three per CU), so wider levels,
-// whose time is throughput rather than chain latency, keep one wave per node.
-constexpr long kTwoWaveNodes = 512;
 
 template <int N, class R>
 hipError_t wave_value_t(const KProb& kp, const WTree& t, const Work& w, const void* elts, void* S,

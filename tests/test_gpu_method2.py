@@ -88,10 +88,12 @@ def test_fp32():
 
 # ---- state sizes 5 .. 16 (one wavefront per tree node) ----
 
-@pytest.mark.parametrize("nx,nu,T", [(5, 1, 1), (6, 3, 9), (8, 4, 33), (11, 5, 150), (16, 4, 600),
-                                     (16, 16, 7), (7, 2, 2049)])
+@pytest.mark.parametrize("nx,nu,T", [(5, 1, 1), (6, 3, 9), (6, 2, 27), (8, 4, 33), (11, 5, 150),
+                                     (16, 4, 600), (16, 16, 7), (7, 2, 2049), (5, 2, 8193)])
 def test_wave_sizes_time_varying_with_drift(nx, nu, T):
-    """One to five tree levels (8 blocks per leaf, 4 nodes per upper node), ragged last nodes."""
+    """One to six tree levels (4 blocks per leaf, 4 children per upper node), ragged last nodes of
+    1, 2 and 3 children; levels of at most 512 nodes run on two waves per node (left pair
+    products), and 8193 blocks give a 513-node level on one wave below levels on two."""
     p = W.random_stable(17 * nx + T, nx=nx, nu=nu, T=T, n=3, tf=0.01 * T + 0.5, time_varying=True)
     rng = np.random.default_rng(nx + T)
     p.c = 0.3 * np.sin(np.linspace(0, 3, p.r.shape[0]))[:, None] * rng.standard_normal(nx)[None, :]
