@@ -1718,7 +1718,11 @@ constexpr int kDenseSlots = 4;
 //     [t_k, t_k + m h]:  x = (I + C S)^{-1} (A x_k + b + C v),
 //   u by the control law at the node's sample.  Node n k carries the block-boundary values and
 //   node n T those at t_T.  One lane per block; the forward sweep reads back the S, v that the
-//   same lane stored in the backward sweep.
+//   same lane stored in the backward sweep.  A lane's nodes are consecutive in the outputs, so
+//   its v, x and u (32 + 32 + 16 bytes a node) share cache lines: they are written together at
+//   the end (from LDS and registers) rather than node by node in the two sweeps, so that no line
+//   is evicted half written and fetched back for the rest.  S (one line a node) is written as it
+//   is formed.
 // ------------------------------------------------------------------------------------------
 template <int N, int NU, class R, bool CONST_COEF>
 __global__ __launch_bounds__(kThreads) void k_dense(const KProb kp, const R* __restrict__ Sg,
@@ -1730,8 +1734,11 @@ __global__ __launch_bounds__(kThreads) void k_dense(const KProb kp, const R* __r
   constexpr int NS = Y::size;
   // S (upper) and v at the interior nodes of the lane's block, kept from the backward sweep for
   // the forward sweep when the block has at most kDenseSlots of them (else read back from the
-  // outputs, by then mostly evicted from the L2).
-  __shared__ R sSv[kDenseSlots][NS + N][kThreads];
+  // outputs, by then mostly evicted from the L2).  Once the forward sweep has read a node's S, its
+  // first N + NU words take the node's x and u until the final writes (v at word XU; the S
+  // words are widened to N + NU where they are fewer, at nx = 1 and at nx = nu = 2).
+  constexpr int XU = NS > N + NU ? NS : N + NU;
+  __shared__ R sSv[kDenseSlots][XU + N][kThreads];
   const int p = blockIdx.y;
   const long k = gid();
   if (k >= kp.T) return;
@@ -1899,36 +1906,43 @@ __global__ __launch_bounds__(kThreads) void k_dense(const KProb kp, const R* __r
 #pragma unroll
       for (int i = 0; i < N; ++i) {
         v[i] = av[i];
-        vdp[node * N + i] = v[i];
+        if (!keep) vdp[node * N + i] = v[i];
       }
       if (keep) {
         const int slot = n - mp - 2;  // interior node m = n - mp - 1 in slot m - 1
 #pragma unroll
         for (int i = 0; i < NS; ++i) sSv[slot][i][lane] = S[i];
 #pragma unroll
-        for (int i = 0; i < N; ++i) sSv[slot][NS + i][lane] = v[i];
+        for (int i = 0; i < N; ++i) sSv[slot][XU + i][lane] = v[i];
       }
     }
   }
 
   // ---- block-boundary nodes ----
-  R xk[N];
+  R xk[N], vb[N], ub[NU];  // node n k: x, v, u (vb, ub held for the final writes when keep)
   {
-    R S[NS], v[N];
+    R S[NS];
     S_load_upper<N, R>(S, Sp + k * N * N);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      v[i] = vp[k * N + i];
+      vb[i] = vp[k * N + i];
       xk[i] = xp[k * N + i];
     }
     const long node = (long)n * k;
     S_store_full<N, R>(S, Sdp + node * N * N);
+    if (keep) {
+      if (udp) {
+        if (kp.L_sampled) gain_sample<N, NU, R>(kp, p, bk.s0 + 2 * node, Kc);
+        control<N, NU, R>(Kc, S, vb, xk, ub);
+      }
+    } else {
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      vdp[node * N + i] = v[i];
-      xdp[node * N + i] = xk[i];
+      for (int i = 0; i < N; ++i) {
+        vdp[node * N + i] = vb[i];
+        xdp[node * N + i] = xk[i];
+      }
+      emit_u(node, S, vb, xk);
     }
-    emit_u(node, S, v, xk);
   }
   if (k == T - 1) {
     R S[NS], v[N], x[N];
@@ -1956,7 +1970,7 @@ __global__ __launch_bounds__(kThreads) void k_dense(const KProb kp, const R* __r
 #pragma unroll
       for (int i = 0; i < NS; ++i) S[i] = sSv[m][i][lane];
 #pragma unroll
-      for (int i = 0; i < N; ++i) v[i] = sSv[m][NS + i][lane];
+      for (int i = 0; i < N; ++i) v[i] = sSv[m][XU + i][lane];
     } else {
       S_load_upper<N, R>(S, Sdp + node * N * N);
 #pragma unroll
@@ -1979,14 +1993,47 @@ __global__ __launch_bounds__(kThreads) void k_dense(const KProb kp, const R* __r
     gj_solve<N, 1>(M, B);
     R x[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
-      x[i] = B[i][0];
-      xdp[node * N + i] = x[i];
+    for (int i = 0; i < N; ++i) x[i] = B[i][0];
+    if (keep) {
+      // the node's S words have been read: they hold its x and u until the final writes
+#pragma unroll
+      for (int i = 0; i < N; ++i) sSv[m][i][lane] = x[i];
+      if (udp) {
+        R uu[NU];
+        if (kp.L_sampled) gain_sample<N, NU, R>(kp, p, bk.s0 + 2 * node, Kc);
+        control<N, NU, R>(Kc, S, v, x, uu);
+#pragma unroll
+        for (int l = 0; l < NU; ++l) sSv[m][N + l][lane] = uu[l];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < N; ++i) xdp[node * N + i] = x[i];
+      emit_u(node, S, v, x);
     }
-    emit_u(node, S, v, x);
   };
   Tup<N, R> parts;
   fwd_parts<N, NU, R, CONST_COEF, false>(kp, bk, n - 1, parts, step);
+  if (!keep) return;
+  // v, x and u of nodes n k .. n k + n - 1 (interior node m in slot m - 1), each array's lines
+  // of this block written in one burst
+  const long node0 = (long)n * k;
+#pragma unroll
+  for (int i = 0; i < N; ++i) vdp[node0 * N + i] = vb[i];
+  for (int m = 1; m < n; ++m)
+#pragma unroll
+    for (int i = 0; i < N; ++i) vdp[(node0 + m) * N + i] = sSv[m - 1][XU + i][lane];
+#pragma unroll
+  for (int i = 0; i < N; ++i) xdp[node0 * N + i] = xk[i];
+  for (int m = 1; m < n; ++m)
+#pragma unroll
+    for (int i = 0; i < N; ++i) xdp[(node0 + m) * N + i] = sSv[m - 1][i][lane];
+  if (udp) {
+#pragma unroll
+    for (int l = 0; l < NU; ++l) udp[node0 * NU + l] = ub[l];
+    for (int m = 1; m < n; ++m)
+#pragma unroll
+      for (int l = 0; l < NU; ++l) udp[(node0 + m) * NU + l] = sSv[m - 1][N + l][lane];
+  }
 }
 
 // ------------------------------------------------------------------------------------------
