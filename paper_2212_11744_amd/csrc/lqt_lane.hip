@@ -1644,7 +1644,9 @@ struct PreAlg {
 };
 
 // x_k = (I + C S_k)^{-1} (z + C v_k) and u_k for the 4 blocks of lane i, from the prefix state at
-// the left end of its level-1 node; the last lane also gives x_T, u_T.
+// the left end of its level-1 node; the last lane also gives x_T, u_T.  The lane's x and u share
+// cache lines across its blocks, so they wait in LDS and are written together after the sweep
+// (written block by block, lines would leave the L2 half written and be fetched back).
 template <int N, int NU, class R>
 __global__ __launch_bounds__(kThreads) void k_m2_bottom(const KProb kp, const R* __restrict__ elts,
                                                          const R* __restrict__ Sg,
@@ -1653,7 +1655,10 @@ __global__ __launch_bounds__(kThreads) void k_m2_bottom(const KProb kp, const R*
                                                          R* __restrict__ xout,
                                                          R* __restrict__ uout) {
   using Y = Sym<N>;
+  __shared__ R sx[kChunk][N][kThreads];
+  __shared__ R su[kChunk][NU][kThreads];
   const int p = blockIdx.y;
+  const int lane = threadIdx.x;
   const long i = gid();
   if (i >= n1) return;
   const long T = kp.T;
@@ -1668,6 +1673,7 @@ __global__ __launch_bounds__(kThreads) void k_m2_bottom(const KProb kp, const R*
   const long j1 = min(j0 + kChunk, T);
   R Kc[NU][N];
   if (!kp.L_sampled) gain_at<N, NU, R>(kp, p, 0, Kc);
+  // k < j1: the lane's own blocks, staged in LDS; k = T: the final row, written directly
   auto emit = [&](long k) {
     R S[Y::size], v[N], M[N][N], B[N][1];
     S_load_upper<N, R>(S, Sp + k * N * N);
@@ -1687,15 +1693,28 @@ __global__ __launch_bounds__(kThreads) void k_m2_bottom(const KProb kp, const R*
       B[a][0] = g;
     }
     gj_solve<N, 1>(M, B);
-    R x[N];
+    R x[N], u[NU];
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-      x[q] = B[q][0];
-      xp[k * N + q] = x[q];
-    }
+    for (int q = 0; q < N; ++q) x[q] = B[q][0];
     if (up) {
       if (kp.L_sampled) gain_at<N, NU, R>(kp, p, k, Kc);
-      control<N, NU, R>(Kc, S, v, x, up + k * NU);
+      control<N, NU, R>(Kc, S, v, x, u);
+    }
+    if (k < j1) {
+      const int r = (int)(k - j0);
+#pragma unroll
+      for (int q = 0; q < N; ++q) sx[r][q][lane] = x[q];
+      if (up) {
+#pragma unroll
+        for (int l = 0; l < NU; ++l) su[r][l][lane] = u[l];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < N; ++q) xp[k * N + q] = x[q];
+      if (up) {
+#pragma unroll
+        for (int l = 0; l < NU; ++l) up[k * NU + l] = u[l];
+      }
     }
   };
   for (long k = j0; k < j1; ++k) {
@@ -1703,6 +1722,15 @@ __global__ __launch_bounds__(kThreads) void k_m2_bottom(const KProb kp, const R*
     Tup<N, R> a;
     tup_load(a, ep, k);
     fwd_fold(a, C, z);
+  }
+  const int cnt = (int)(j1 - j0);
+  for (int r = 0; r < cnt; ++r)
+#pragma unroll
+    for (int q = 0; q < N; ++q) xp[(j0 + r) * N + q] = sx[r][q][lane];
+  if (up) {
+    for (int r = 0; r < cnt; ++r)
+#pragma unroll
+      for (int l = 0; l < NU; ++l) up[(j0 + r) * NU + l] = su[r][l][lane];
   }
   if (j1 == T) emit(T);
 }
