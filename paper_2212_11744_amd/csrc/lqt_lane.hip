@@ -1351,6 +1351,10 @@ LQT_DEV void vscan_tile(const KProb& kp, int p, long i, const R* __restrict__ el
 #pragma unroll
     for (int q = 0; q < N; ++q) vp[T * N + q] = st.v[q];
   }
+  // The lane's v rows share cache lines (S rows are a line each): where the lane's LDS column
+  // (free once E is back in registers) holds them, they are written together after the sweep,
+  // so that no line leaves the L2 half written.
+  constexpr bool kStageV = CH * N <= Lay<N>::NE;
   Tup<N, R> nxt;
   tup_load(nxt, ep, j1 - 1);
   for (long k = j1 - 1; k >= j0; --k) {
@@ -1360,7 +1364,17 @@ LQT_DEV void vscan_tile(const KProb& kp, int p, long i, const R* __restrict__ el
     fold(a, st.S, st.v, m);
     S_store_full<N, R>(st.S, Sp + k * N * N);
 #pragma unroll
-    for (int q = 0; q < N; ++q) vp[k * N + q] = st.v[q];
+    for (int q = 0; q < N; ++q) {
+      if (kStageV)
+        sE[(k - j0) * N + q][lane] = st.v[q];
+      else
+        vp[k * N + q] = st.v[q];
+    }
+  }
+  if (kStageV) {
+    for (long k = j0; k < j1; ++k)
+#pragma unroll
+      for (int q = 0; q < N; ++q) vp[k * N + q] = sE[(k - j0) * N + q][lane];
   }
 }
 
